@@ -1,0 +1,111 @@
+"""Oracle for the variational objective and its optimisation.
+
+TEST INFRASTRUCTURE ONLY.
+
+  Etilde(s) = E_1(s) - logZ_R(s) / beta                         (Eq. 4)
+  F_q = E_{s~q}[Etilde(s) + ln q(s) / beta]                      (Eq. 9)
+  grad F_q = E_{s~q}[(Etilde + ln q / beta) grad ln q(s)]        (Eq. 10)
+
+The batch estimator uses f_b = Etilde(s_b) + ln q(s_b) / beta, F_q = mean f,
+and subtracts the batch mean as a baseline (it leaves the expectation of the
+estimator unchanged because E_q[grad ln q] = 0): the per-sample REINFORCE
+weight is w_b = (f_b - mean f) / B.  The update is Adam (Kingma & Ba 2015)
+with beta1 = 0.9, beta2 = 0.999, eps = 1e-8 (the paper says gradient
+descent, Algorithm 1 step (d)).
+
+Functions and what pins them (tests/test_oracle_objective.py):
+  free_energy_terms   Eq. 9 written out; pinned by the variational bound
+                      F_q >= F (exact enumeration, Eq. 5)
+  exact_fq_and_grad   enumeration of all 2^|W| width-set states; the exact
+                      gradient pinned by central finite differences of the
+                      exact F_q, and the sampled REINFORCE estimator is
+                      checked against it statistically
+  adam_step           pinned by the closed form of the first step
+                      (update = lr * g / (|g| + eps)) and a hand-computed
+                      second step
+  train               Algorithm 1 (sample -> contract -> loss/grad -> update)
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from . import ising, made, philox
+
+
+def free_energy_terms(inst, spins, logq, logz_r):
+    """Per-sample f_b and the batch statistics (F_q, stderr, <Etilde>,
+    <ln q>/beta)."""
+    beta = float(inst.beta)
+    e1 = ising.e1_energy(inst, spins)
+    et = e1 - np.asarray(logz_r, np.float64) / beta
+    f = et + np.asarray(logq, np.float64) / beta
+    B = f.shape[0]
+    Fq = float(np.mean(f))
+    se = float(np.std(f, ddof=1) / np.sqrt(B)) if B > 1 else 0.0
+    return f, np.array([Fq, se, float(np.mean(et)),
+                        float(np.mean(np.asarray(logq, np.float64) / beta))])
+
+
+def reinforce_weights(f: np.ndarray) -> np.ndarray:
+    f = np.asarray(f, np.float64)
+    return (f - f.mean()) / f.shape[0]
+
+
+def adam_step(theta, grad, m, v, t: int, lr: float, b1=0.9, b2=0.999,
+              eps=1e-8):
+    """One Adam update; t is the 1-based step number.  Returns new
+    (theta, m, v)."""
+    g = np.asarray(grad, np.float64)
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    mh = m / (1 - b1 ** t)
+    vh = v / (1 - b2 ** t)
+    return theta - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def all_width_states(nw: int) -> np.ndarray:
+    k = np.arange(2 ** nw, dtype=np.int64)[:, None]
+    return (1 - 2 * ((k >> np.arange(nw)[None, :]) & 1)).astype(np.int8)
+
+
+def exact_free_energy(inst) -> float:
+    """F = -ln Z / beta by enumerating all 2^n states (Eq. 1)."""
+    return -ising.logz_full_bruteforce(inst) / float(inst.beta)
+
+
+def exact_fq_and_grad(inst, theta, H: int, logz_fn=None):
+    """Exact F_q = sum_s q(s) [Etilde(s) + ln q(s)/beta] over all 2^|W|
+    states and its exact gradient, sum_s q(s) f(s) grad ln q(s)."""
+    nw = int(inst.width_set.shape[0])
+    s = all_width_states(nw)
+    lz = (logz_fn or ising.logz_r_elimination)(inst, s)
+    lq = made.logq(theta, s, nw, H)
+    q = np.exp(lq)
+    f = ising.e1_energy(inst, s) - lz / inst.beta + lq / inst.beta
+    Fq = float(np.sum(q * f))
+    grad = made.logq_backward(theta, s, q * f, nw, H)
+    return Fq, grad
+
+
+def train(inst, theta0, H: int, steps: int, B: int, lr: float, seed: int,
+          inst_index: int = 0, logz_fn=None, record=False):
+    """Algorithm 1: per epoch sample with Philox uniforms, contract, form
+    F_q and the REINFORCE gradient, apply Adam.  Returns the final theta
+    and the per-step statistics [steps, 4]."""
+    nw = int(inst.width_set.shape[0])
+    theta = np.asarray(theta0, np.float64).copy()
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    stats = []
+    lzf = logz_fn or ising.logz_r_elimination
+    for t in range(steps):
+        u = philox.sampler_uniforms(seed, t, inst_index, B, nw)
+        s, lq, _ = made.sample(theta, u, nw, H)
+        lz = lzf(inst, s)
+        f, st = free_energy_terms(inst, s, lq, lz)
+        w = reinforce_weights(f)
+        g = made.logq_backward(theta, s, w, nw, H)
+        theta, m, v = adam_step(theta, g, m, v, t + 1, lr)
+        stats.append(st)
+    return theta, np.asarray(stats)
