@@ -1,0 +1,184 @@
+/* tnvan.h - C ABI of the TNVAN hot path on MI355X (gfx950).
+ *
+ * Tensor-network-based variational autoregressive networks (arXiv 2504.12037):
+ * a spin system E(s) = -sum_<ij> J_ij s_i s_j - sum_i h_i s_i (Sec. 2, Eq. 1;
+ * the field term is this library's extension) is split into a width set W and
+ * a remainder R.  For every width-set configuration s_W drawn from a masked
+ * autoregressive network q (Sec. 3, Eqs. 6-8) the library contracts
+ *
+ *     logZ_R(s_W) = ln sum_r exp(-beta E_2(s_W, r))          (Eqs. 3-4)
+ *
+ * exactly along a fixed elimination order of R, differentiates it with a
+ * hand-written adjoint, and trains q by the REINFORCE gradient of the
+ * variational free energy (Eqs. 9-10, Algorithm 1).
+ *
+ * Conventions for every entry point
+ *  - Host arrays are read during the call and copied; the caller keeps
+ *    ownership.  Device pointers ("dev") are caller-owned device memory that
+ *    must stay valid until the work queued on `stream` has completed.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work of a call is queued on it; calls return without waiting
+ *    unless stated otherwise.
+ *  - Several instances (disorder realisations) can live in one net.  Their
+ *    sample batches are concatenated in instance order ("instance-major"):
+ *    instance i owns n_samples[i] consecutive samples.
+ *  - Spins are int8 holding +1 or -1.  The spins of a sample are its width-set
+ *    spins in the order of `width_set`.
+ *  - Every function returns a tnvan_status and never aborts or throws.  On
+ *    failure tnvan_last_error() returns a message (thread-local).  HIP errors
+ *    map to TNVAN_E_HIP; an asynchronous device fault surfaces at the next
+ *    synchronising call.
+ *  - One net must not be used from two host threads or two streams at once:
+ *    it owns workspaces that every call reuses.
+ */
+#ifndef TNVAN_H
+#define TNVAN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tnvan_net tnvan_net;   /* opaque, library-owned */
+
+typedef enum {
+  TNVAN_OK = 0,
+  TNVAN_E_INVALID = 1,    /* malformed instance or argument */
+  TNVAN_E_WIDTH = 2,      /* a message scope exceeds the width limit */
+  TNVAN_E_NOMEM = 3,      /* device or host allocation failed */
+  TNVAN_E_HIP = 4,        /* a HIP runtime call failed */
+  TNVAN_E_STATE = 5,      /* call out of order (e.g. missing build) */
+  TNVAN_E_NONFINITE = 6   /* non-finite value detected */
+} tnvan_status;
+
+typedef enum {
+  TNVAN_FP64 = 0,         /* plain FP64 path */
+  TNVAN_FP32 = 1,         /* FP32 contraction, FP64 log-norm and reductions */
+  TNVAN_BF16 = 2          /* as FP32 with BF16 inputs to the dense products */
+} tnvan_precision;
+
+/* One disorder instance (Sec. 2): couplings, fields, inverse temperature,
+ * width set W and the elimination order of R = V \ W (Alg. 1, step 1). */
+typedef struct {
+  int32_t n_spins;
+  int32_t n_edges;
+  const int32_t *edge_i;      /* [n_edges], 0-based, edge_i < edge_j */
+  const int32_t *edge_j;      /* [n_edges], no duplicate edges */
+  const double *J;            /* [n_edges] couplings J_ij */
+  const double *h;            /* [n_spins] fields, or NULL for h = 0 */
+  double beta;                /* inverse temperature, >= 0 */
+  int32_t n_width;
+  const int32_t *width_set;   /* [n_width]; also the sampling order of q */
+  int32_t n_order;
+  const int32_t *order;       /* [n_order], a permutation of V \ W */
+  int32_t n_groups;           /* 0 => one vertex per elimination step */
+  const int32_t *group_ptr;   /* [n_groups+1] CSR over `order`, or NULL */
+  int32_t hidden;             /* hidden width H of q (0: Eq. 7 exactly) */
+} tnvan_instance;
+
+typedef struct {
+  int32_t precision;          /* tnvan_precision */
+  int32_t max_width;          /* largest message scope allowed (<= 14) */
+  int32_t deterministic;      /* reserved: every reduction is ordered */
+  int32_t reserved;
+  uint64_t seed;              /* key of the Philox4x32-10 stream of q */
+} tnvan_options;
+
+/* Compile n_inst instances into one net (host work plus device uploads,
+ * synchronous).  Validates every instance: W and order disjoint and covering
+ * all spins, edges unique with i < j, finite J, h and beta >= 0, group sizes
+ * <= 8 and a grouped step whose input message is not exactly its group
+ * (TNVAN_E_INVALID); a message scope above max_width (TNVAN_E_WIDTH).
+ * The initial parameters of q are zero; set them with tnvan_set_params.
+ * On success *out owns all device state; free it with tnvan_free_network. */
+tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
+                                 const tnvan_options *opt, tnvan_net **out);
+
+void tnvan_free_network(tnvan_net *net);
+
+const char *tnvan_last_error(void);
+
+/* Number of float32 parameters of q for instance i (flat layout
+ * W1 [H,n], b1 [H], W2 [n,H], b2 [n], W0 [n,n], n = |W|, row-major). */
+tnvan_status tnvan_param_count(const tnvan_net *net, int32_t inst, int64_t *count);
+
+/* Copy the parameters of instance i from / to device memory (float32 in
+ * every precision; stream-ordered).  set_params also clears the optimiser
+ * state and the step counter of that instance. */
+tnvan_status tnvan_set_params(tnvan_net *net, int32_t inst, const float *src_dev,
+                              void *stream);
+tnvan_status tnvan_get_params(tnvan_net *net, int32_t inst, float *dst_dev,
+                              void *stream);
+
+/* Copy one state vector of instance i into device memory (float32,
+ * param_count entries, stream-ordered): which = 0 parameters, 1 gradient of
+ * the last free_energy_step, 2 Adam first moment, 3 Adam second moment.
+ * Used for checkpoints and for checking the REINFORCE gradient. */
+tnvan_status tnvan_get_state(tnvan_net *net, int32_t inst, int32_t which,
+                             float *dst_dev, void *stream);
+
+/* Ancestral sampling from q (Sec. 3, Eq. 8): for each position i in the
+ * order of width_set, p_i = sigmoid(logit_i(s_<i)) and s_i = +1 iff
+ * u_i < p_i; logq accumulates ln q(s) = sum_i log sigmoid(s_i logit_i).
+ *   n_samples [n_inst] host: samples per instance
+ *   uniforms  dev float32 [sum_i n_samples[i] * |W_i|], instance-major,
+ *             sample-major inside; NULL => the net's Philox stream at the
+ *             current step counter (the counter is not advanced)
+ *   spins     dev int8 out, same layout as uniforms
+ *   logq      dev out, [sum n_samples]: double for TNVAN_FP64, else float */
+tnvan_status tnvan_sample(tnvan_net *net, const int64_t *n_samples,
+                          const float *uniforms, int8_t *spins, void *logq,
+                          void *stream);
+
+/* Batched conditional log-partition function (Eqs. 3-4): for every sample,
+ * logz[b] = ln sum_r exp(-beta E_2(s_W(b), r)), by exact contraction along
+ * the compiled order with per-step power-of-two rescaling; the log-norm and
+ * the result are FP64 in every precision.
+ *   spins  dev int8 [sum n_samples * |W|] (layout as tnvan_sample)
+ *   logz   dev double out [sum n_samples] */
+tnvan_status tnvan_logz_batch(tnvan_net *net, const int64_t *n_samples,
+                              const int8_t *spins, double *logz, void *stream);
+
+/* Adjoint of tnvan_logz_batch: writes the vector-Jacobian product
+ *   dh[i]    = sum_b g_b dlogZ_R(b)/dh_i     = beta sum_b g_b <r_i>_b
+ *   dJ[e]    = sum_b g_b dlogZ_R(b)/dJ_e     = beta sum_b g_b <x_i x_j>_b
+ *   dbeta[k] = sum_b g_b dlogZ_R(b)/dbeta    = -sum_b g_b <E_2>_b
+ * (magnetisations, edge correlations and internal energy of the remainder;
+ * zero on W vertices and W-W edges).  The forward is recomputed inside.
+ *   grad_logz dev double [sum n_samples] (g_b)
+ *   dh        dev double out [sum_i n_spins_i], instance-major
+ *   dJ        dev double out [sum_i n_edges_i]
+ *   dbeta     dev double out [n_inst] */
+tnvan_status tnvan_logz_backward(tnvan_net *net, const int64_t *n_samples,
+                                 const int8_t *spins, const double *grad_logz,
+                                 double *dh, double *dJ, double *dbeta,
+                                 void *stream);
+
+/* One training iteration of Algorithm 1 for every instance: sample with the
+ * Philox stream at the current step counter, contract, form
+ * f_b = E_1 - logZ_R/beta + ln q/beta, F_q = mean f (Eq. 9), REINFORCE
+ * weights (f_b - F_q)/B (Eq. 10, batch-mean baseline, FP64), the gradient of
+ * q and one Adam step (lr; beta1 0.9, beta2 0.999, eps 1e-8); then the step
+ * counter advances.  Needs beta > 0 (TNVAN_E_INVALID otherwise).
+ *   stats     dev double out [n_inst, 4]: F_q, its standard error,
+ *             mean Etilde, mean ln q / beta
+ *   spins_out dev int8 out (optional, may be NULL): the sampled spins */
+tnvan_status tnvan_free_energy_step(tnvan_net *net, const int64_t *n_samples,
+                                    float lr, double *stats, int8_t *spins_out,
+                                    void *stream);
+
+/* Per-instance program statistics of the compiled order (host values):
+ *   info[0] steps, [1] largest message scope, [2] arena entries per sample,
+ *   [3] flops per sample of the forward contraction (2 per multiply-add,
+ *   counting the dense step form as executed), [4] |W|, [5] |R| */
+tnvan_status tnvan_program_info(const tnvan_net *net, int32_t inst, int64_t info[6]);
+
+/* Host-only planning: validate and compile one instance without touching a
+ * device and report the same statistics as tnvan_program_info. */
+tnvan_status tnvan_plan(const tnvan_instance *inst, int32_t max_width, int64_t info[6]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TNVAN_H */

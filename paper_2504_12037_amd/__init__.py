@@ -1,0 +1,169 @@
+"""TNVAN hot path on MI355X: Python face of libtnvan.so.
+
+    net = Net(instances, precision="fp32")
+    logz = net.logz(spins, n_samples)              # Eqs. 3-4, per sample
+    dh, dJ, dbeta = net.backward(spins, g, n_samples)
+    spins, logq = net.sample(n_samples, uniforms)  # Eq. 8
+    stats, spins = net.free_energy_step(n_samples, lr)   # Algorithm 1
+
+Tensors are torch tensors on the current HIP device; the current torch
+stream is handed to the library.  ``LogZ`` wraps logz/backward as a
+torch.autograd.Function returning gradients for (J, h, beta).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from typing import Sequence
+
+import torch
+
+from . import _lib
+from ._lib import TnvanError, plan  # noqa: F401
+
+__all__ = ["Net", "LogZ", "plan", "TnvanError"]
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Net:
+    """One or more compiled instances sharing a device program."""
+
+    def __init__(self, instances: Sequence, precision: str = "fp32",
+                 max_width: int = 14, seed: int = 0):
+        L = _lib.lib()
+        self.instances = list(instances)
+        self.precision = precision
+        keep = []
+        arr = (_lib.CInstance * len(self.instances))()
+        for k, inst in enumerate(self.instances):
+            arr[k] = _lib.make_cinstance(inst, keep)
+        opt = _lib.COptions(_lib._PREC[precision], int(max_width), 1, 0, int(seed))
+        h = C.c_void_p()
+        _lib.check(L.tnvan_build_network(arr, len(self.instances), C.byref(opt),
+                                         C.byref(h)))
+        self._h = h
+        self.nw = [int(len(i.width_set)) for i in self.instances]
+        self.n = [int(i.n) for i in self.instances]
+        self.ne = [int(len(i.edges)) for i in self.instances]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.lib().tnvan_free_network(h)
+            self._h = None
+
+    # ---------------------------------------------------------------- helpers
+    def _counts(self, n_samples):
+        if isinstance(n_samples, int):
+            n_samples = [n_samples] * len(self.instances)
+        arr = (C.c_int64 * len(self.instances))(*[int(b) for b in n_samples])
+        return arr, [int(b) for b in n_samples]
+
+    @property
+    def logq_dtype(self):
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    def info(self, inst: int = 0):
+        out = (C.c_int64 * 6)()
+        _lib.check(_lib.lib().tnvan_program_info(self._h, inst, out))
+        return tuple(int(x) for x in out)
+
+    def param_count(self, inst: int = 0) -> int:
+        n = C.c_int64()
+        _lib.check(_lib.lib().tnvan_param_count(self._h, inst, C.byref(n)))
+        return n.value
+
+    def set_params(self, inst: int, theta: torch.Tensor):
+        t = theta.to(device="cuda", dtype=torch.float32).contiguous()
+        assert t.numel() == self.param_count(inst)
+        _lib.check(_lib.lib().tnvan_set_params(self._h, inst, _ptr(t), _stream()))
+        torch.cuda.current_stream().synchronize()
+
+    def get_params(self, inst: int = 0) -> torch.Tensor:
+        t = torch.empty(self.param_count(inst), device="cuda", dtype=torch.float32)
+        _lib.check(_lib.lib().tnvan_get_params(self._h, inst, _ptr(t), _stream()))
+        return t
+
+    def get_state(self, inst: int, which: int) -> torch.Tensor:
+        """0 params, 1 last gradient, 2 Adam m, 3 Adam v (float32)."""
+        t = torch.empty(self.param_count(inst), device="cuda", dtype=torch.float32)
+        _lib.check(_lib.lib().tnvan_get_state(self._h, inst, which, _ptr(t), _stream()))
+        return t
+
+    # ----------------------------------------------------------- entry points
+    def sample(self, n_samples, uniforms: torch.Tensor = None):
+        arr, counts = self._counts(n_samples)
+        tot = sum(b * w for b, w in zip(counts, self.nw))
+        spins = torch.empty(max(tot, 1), device="cuda", dtype=torch.int8)
+        logq = torch.empty(max(sum(counts), 1), device="cuda", dtype=self.logq_dtype)
+        if uniforms is not None:
+            uniforms = uniforms.contiguous()
+            assert uniforms.dtype == torch.float32 and uniforms.numel() == tot
+        _lib.check(_lib.lib().tnvan_sample(self._h, arr, _ptr(uniforms), _ptr(spins),
+                                           _ptr(logq), _stream()))
+        return spins[:tot], logq[:sum(counts)]
+
+    def logz(self, spins: torch.Tensor, n_samples, out: torch.Tensor = None):
+        arr, counts = self._counts(n_samples)
+        spins = spins.contiguous()
+        assert spins.dtype == torch.int8
+        assert spins.numel() == sum(b * w for b, w in zip(counts, self.nw))
+        if out is None:
+            out = torch.empty(max(sum(counts), 1), device="cuda", dtype=torch.float64)
+        _lib.check(_lib.lib().tnvan_logz_batch(self._h, arr, _ptr(spins), _ptr(out),
+                                               _stream()))
+        return out[:sum(counts)]
+
+    def backward(self, spins: torch.Tensor, grad: torch.Tensor, n_samples, out=None):
+        arr, counts = self._counts(n_samples)
+        spins = spins.contiguous()
+        grad = grad.to(torch.float64).contiguous()
+        assert grad.numel() == sum(counts)
+        if out is None:
+            dh = torch.empty(sum(self.n), device="cuda", dtype=torch.float64)
+            dJ = torch.empty(max(sum(self.ne), 1), device="cuda", dtype=torch.float64)
+            db = torch.empty(len(self.instances), device="cuda", dtype=torch.float64)
+        else:
+            dh, dJ, db = out
+        _lib.check(_lib.lib().tnvan_logz_backward(self._h, arr, _ptr(spins), _ptr(grad),
+                                                  _ptr(dh), _ptr(dJ), _ptr(db),
+                                                  _stream()))
+        return dh, dJ[:sum(self.ne)], db
+
+    def free_energy_step(self, n_samples, lr: float, stats: torch.Tensor = None,
+                         spins_out: torch.Tensor = None):
+        arr, counts = self._counts(n_samples)
+        if stats is None:
+            stats = torch.empty(len(self.instances), 4, device="cuda", dtype=torch.float64)
+        _lib.check(_lib.lib().tnvan_free_energy_step(self._h, arr, float(lr), _ptr(stats),
+                                                     _ptr(spins_out), _stream()))
+        return stats, spins_out
+
+
+class LogZ(torch.autograd.Function):
+    """logZ_R(s_W) per sample as a differentiable function of (J, h, beta).
+
+    ``net`` must have been built from the same couplings, fields and beta as
+    the tensors passed in (they are used for their gradients only); the
+    backward runs the library's adjoint.
+    """
+
+    @staticmethod
+    def forward(ctx, J, h, beta, spins, net: Net, n_samples):
+        ctx.net = net
+        ctx.n_samples = n_samples
+        ctx.save_for_backward(spins)
+        return net.logz(spins, n_samples).clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        (spins,) = ctx.saved_tensors
+        dh, dJ, db = ctx.net.backward(spins, g.contiguous(), ctx.n_samples)
+        return dJ, dh, db, None, None, None

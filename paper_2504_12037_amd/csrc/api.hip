@@ -1,0 +1,643 @@
+// C ABI of the TNVAN hot path: build, sample, logz_batch, logz_backward,
+// free_energy_step (Algorithm 1) and accessors.  Host orchestration only;
+// every step of the path runs in the kernels of contract.hip and made.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tnvan.h"
+#include "compile.h"
+#include "launch.h"
+
+namespace tnvan {
+hipError_t zero_doubles(double *p, int64_t n, hipStream_t st);
+}
+
+using namespace tnvan;
+
+namespace {
+
+thread_local std::string g_err;
+
+tnvan_status set_err(tnvan_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPCHK(expr)                                                          \
+  do {                                                                        \
+    hipError_t e_ = (expr);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      return set_err(TNVAN_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));    \
+  } while (0)
+
+// Device buffer that grows on demand (contents are not preserved).
+struct DBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t need) {
+    if (need <= bytes) return hipSuccess;
+    if (p) { hipFree(p); p = nullptr; bytes = 0; }
+    hipError_t e = hipMalloc(&p, need);
+    if (e == hipSuccess) bytes = need;
+    return e;
+  }
+  void release() { if (p) hipFree(p); p = nullptr; bytes = 0; }
+  template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+template <typename T>
+hipError_t upload(DBuf &b, const std::vector<T> &v) {
+  size_t n = std::max<size_t>(1, v.size()) * sizeof(T);
+  hipError_t e = b.ensure(n);
+  if (e != hipSuccess) return e;
+  if (!v.empty()) e = hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+struct TileCache {
+  std::vector<int64_t> key;       // n_samples it was built for
+  int S = 0;
+  int n_tiles = 0;
+  DBuf tile_inst, tile_start, first_tile, n_tiles_i, partial_off;
+  std::vector<int32_t> h_first, h_count;
+  int64_t partial_total = 0;
+};
+
+}  // namespace
+
+struct tnvan_net {
+  int precision = TNVAN_FP32;
+  uint64_t seed = 0;
+  HostProgram P;
+  int n_inst = 0;
+  // program on the device
+  DBuf inst, steps, inputs, edges, T, fld_ptr, fld_w, fld_J, hR, wr_pos, wr_w;
+  DBuf rr_edge, rr_J, wr_edge, wr_J, hR64, vr, ww_a, ww_b, ww_J, hW;
+  // network
+  std::vector<MadeInst> mi;
+  std::vector<int64_t> param_count;
+  int64_t param_total = 0;
+  DBuf d_mi, params, adam_m, adam_v, grad, step_ctr;
+  // per-call tables
+  std::vector<int64_t> nkey;
+  std::vector<int64_t> sample_off, spin_off;
+  int64_t B_total = 0, spin_total = 0;
+  DBuf d_sample_off, d_B, d_spin_off, d_spin_base, d_edge_base;
+  TileCache tc_fwd, tc_bwd;
+  int S_fwd = 1, S_bwd = 1;
+  bool glob_fwd = false, glob_bwd = false;
+  size_t lds_fwd = 0, lds_bwd = 0;
+  std::vector<int32_t> h_blk_inst, h_blk_start;
+  DBuf blk_inst, blk_start;
+  int n_sblocks = 0;
+  std::vector<int64_t> skey;
+  // workspaces
+  DBuf garena, partial, w_logz, w_logq, w_spins, w_f, w_wts, w_hid, w_da, w_dlogit, w_sf,
+      w_part;
+  int rs() const { return precision == TNVAN_FP64 ? 8 : 4; }
+};
+
+namespace {
+
+int ilog2(int x) { int r = 0; while ((1 << r) < x) ++r; return r; }
+
+// Largest S (power of two <= 64) whose tile fits the LDS budget.
+void choose_tiles(tnvan_net *net, bool bwd) {
+  int dev = 0;
+  hipGetDevice(&dev);
+  int maxlds = 65536;
+  hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  const size_t budget = std::min<size_t>((size_t)maxlds, 80 * 1024);
+  int S = 64;
+  bool glob = false;
+  for (; S >= 1; S >>= 1) {
+    size_t worst = 0;
+    for (auto &D : net->P.insts)
+      worst = std::max(worst, contract_lds_bytes(D, S, bwd, false, net->rs()));
+    if (worst <= budget) break;
+  }
+  if (S < 4) {
+    glob = true;
+    for (S = 64; S >= 1; S >>= 1) {
+      size_t worst = 0;
+      for (auto &D : net->P.insts)
+        worst = std::max(worst, contract_lds_bytes(D, S, bwd, true, net->rs()));
+      if (worst <= budget && S <= 16) break;
+    }
+    if (S < 1) S = 1;
+  }
+  size_t worst = 0;
+  for (auto &D : net->P.insts)
+    worst = std::max(worst, contract_lds_bytes(D, S, bwd, glob, net->rs()));
+  if (bwd) { net->S_bwd = S; net->glob_bwd = glob; net->lds_bwd = worst; }
+  else { net->S_fwd = S; net->glob_fwd = glob; net->lds_fwd = worst; }
+}
+
+tnvan_status set_batch(tnvan_net *net, const int64_t *n_samples) {
+  if (!n_samples) return set_err(TNVAN_E_INVALID, "n_samples is NULL");
+  std::vector<int64_t> key(n_samples, n_samples + net->n_inst);
+  for (auto b : key)
+    if (b < 0 || b > ((int64_t)1 << 31)) return set_err(TNVAN_E_INVALID, "bad sample count");
+  if (key == net->nkey) return TNVAN_OK;
+  net->sample_off.assign(net->n_inst, 0);
+  net->spin_off.assign(net->n_inst, 0);
+  int64_t so = 0, sp = 0;
+  for (int q = 0; q < net->n_inst; ++q) {
+    net->sample_off[q] = so;
+    net->spin_off[q] = sp;
+    so += key[q];
+    sp += key[q] * net->P.insts[q].nw;
+  }
+  net->B_total = so;
+  net->spin_total = sp;
+  HIPCHK(upload(net->d_sample_off, net->sample_off));
+  HIPCHK(upload(net->d_B, key));
+  HIPCHK(upload(net->d_spin_off, net->spin_off));
+  for (int q = 0; q < net->n_inst; ++q) {
+    net->mi[q].sample_off = net->sample_off[q];
+    net->mi[q].B = key[q];
+    net->mi[q].spin_off = net->spin_off[q];
+  }
+  HIPCHK(upload(net->d_mi, net->mi));
+  net->nkey = key;
+  net->tc_fwd.key.clear();
+  net->tc_bwd.key.clear();
+  net->skey.clear();
+  return TNVAN_OK;
+}
+
+tnvan_status ensure_tiles(tnvan_net *net, TileCache &tc, int S, bool bwd) {
+  if (tc.key == net->nkey && tc.S == S) return TNVAN_OK;
+  std::vector<int32_t> ti, ts, first(net->n_inst), cnt(net->n_inst);
+  std::vector<int64_t> poff(net->n_inst);
+  int64_t ptot = 0;
+  for (int q = 0; q < net->n_inst; ++q) {
+    first[q] = (int32_t)ti.size();
+    const int64_t B = net->nkey[q];
+    for (int64_t b = 0; b < B; b += S) { ti.push_back(q); ts.push_back((int32_t)b); }
+    cnt[q] = (int32_t)ti.size() - first[q];
+    poff[q] = ptot;
+    if (bwd) ptot += (int64_t)cnt[q] * net->P.insts[q].n_partial;
+  }
+  HIPCHK(upload(tc.tile_inst, ti));
+  HIPCHK(upload(tc.tile_start, ts));
+  HIPCHK(upload(tc.first_tile, first));
+  HIPCHK(upload(tc.n_tiles_i, cnt));
+  HIPCHK(upload(tc.partial_off, poff));
+  tc.h_first = first;
+  tc.h_count = cnt;
+  tc.n_tiles = (int)ti.size();
+  tc.partial_total = ptot;
+  tc.S = S;
+  tc.key = net->nkey;
+  return TNVAN_OK;
+}
+
+template <typename real>
+ContractArgs<real> contract_args(tnvan_net *net, TileCache &tc, int S) {
+  ContractArgs<real> a{};
+  a.inst = net->inst.as<InstDesc>();
+  a.steps = net->steps.as<StepDesc>();
+  a.inputs = net->inputs.as<InputDesc>();
+  a.edges = net->edges.as<EdgeDesc>();
+  a.T = net->T.as<real>();
+  a.fld_ptr = net->fld_ptr.as<int32_t>();
+  a.fld_w = net->fld_w.as<int32_t>();
+  a.fld_J = net->fld_J.as<real>();
+  a.hR = net->hR.as<real>();
+  a.wr_pos = net->wr_pos.as<int32_t>();
+  a.wr_w = net->wr_w.as<int32_t>();
+  a.tile_inst = tc.tile_inst.as<int32_t>();
+  a.tile_start = tc.tile_start.as<int32_t>();
+  a.inst_first_tile = tc.first_tile.as<int32_t>();
+  a.inst_sample_off = net->d_sample_off.as<int64_t>();
+  a.inst_B = net->d_B.as<int64_t>();
+  a.inst_spin_off = net->d_spin_off.as<int64_t>();
+  a.inst_partial_off = tc.partial_off.as<int64_t>();
+  a.S = S;
+  a.logS = ilog2(S);
+  return a;
+}
+
+template <typename real>
+tnvan_status run_logz(tnvan_net *net, const int8_t *spins, double *logz, hipStream_t st) {
+  tnvan_status s = ensure_tiles(net, net->tc_fwd, net->S_fwd, false);
+  if (s) return s;
+  auto a = contract_args<real>(net, net->tc_fwd, net->S_fwd);
+  a.spins = spins;
+  a.logz = logz;
+  if (net->glob_fwd) {
+    int64_t per = 0;
+    for (auto &D : net->P.insts) per = std::max(per, contract_garena_entries(D, net->S_fwd, false));
+    HIPCHK(net->garena.ensure((size_t)per * net->tc_fwd.n_tiles * sizeof(real)));
+    a.garena = net->garena.as<real>();
+    a.garena_stride = per;
+  }
+  HIPCHK(launch_contract<real>(a, net->tc_fwd.n_tiles, net->lds_fwd, false, net->glob_fwd, st));
+  return TNVAN_OK;
+}
+
+template <typename real>
+tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *grad,
+                          double *dh, double *dJ, double *dbeta, hipStream_t st) {
+  tnvan_status s = ensure_tiles(net, net->tc_bwd, net->S_bwd, true);
+  if (s) return s;
+  TileCache &tc = net->tc_bwd;
+  auto a = contract_args<real>(net, tc, net->S_bwd);
+  a.spins = spins;
+  a.grad = grad;
+  HIPCHK(net->partial.ensure(std::max<int64_t>(1, tc.partial_total) * sizeof(real)));
+  a.partial = net->partial.as<real>();
+  if (net->glob_bwd) {
+    int64_t per = 0;
+    for (auto &D : net->P.insts) per = std::max(per, contract_garena_entries(D, net->S_bwd, true));
+    HIPCHK(net->garena.ensure((size_t)per * tc.n_tiles * sizeof(real)));
+    a.garena = net->garena.as<real>();
+    a.garena_stride = per;
+  }
+  HIPCHK(launch_contract<real>(a, tc.n_tiles, net->lds_bwd, true, net->glob_bwd, st));
+  int64_t nh = 0, ne = 0;
+  for (auto &D : net->P.insts) { nh += D.n; ne += D.n_edges; }
+  HIPCHK(zero_doubles(dh, nh, st));
+  HIPCHK(zero_doubles(dJ, ne, st));
+  VjpArgs v{};
+  v.inst = net->inst.as<InstDesc>();
+  v.rr_edge = net->rr_edge.as<int32_t>();
+  v.rr_J = net->rr_J.as<double>();
+  v.wr_edge = net->wr_edge.as<int32_t>();
+  v.wr_J = net->wr_J.as<double>();
+  v.hR = net->hR64.as<double>();
+  v.vr = net->vr.as<int32_t>();
+  v.inst_first_tile = tc.first_tile.as<int32_t>();
+  v.inst_n_tiles = tc.n_tiles_i.as<int32_t>();
+  v.inst_partial_off = tc.partial_off.as<int64_t>();
+  v.inst_spin_base = net->d_spin_base.as<int64_t>();
+  v.inst_edge_base = net->d_edge_base.as<int64_t>();
+  v.dh = dh;
+  v.dJ = dJ;
+  v.dbeta = dbeta;
+  HIPCHK(launch_vjp_reduce<real>(v, net->partial.as<real>(), net->n_inst, st));
+  return TNVAN_OK;
+}
+
+tnvan_status ensure_sample_blocks(tnvan_net *net) {
+  if (net->skey == net->nkey) return TNVAN_OK;
+  net->h_blk_inst.clear();
+  net->h_blk_start.clear();
+  for (int q = 0; q < net->n_inst; ++q) {
+    const int spb = 256 / net->mi[q].L;
+    for (int64_t b = 0; b < net->nkey[q]; b += spb) {
+      net->h_blk_inst.push_back(q);
+      net->h_blk_start.push_back((int32_t)b);
+    }
+  }
+  HIPCHK(upload(net->blk_inst, net->h_blk_inst));
+  HIPCHK(upload(net->blk_start, net->h_blk_start));
+  net->n_sblocks = (int)net->h_blk_inst.size();
+  net->skey = net->nkey;
+  return TNVAN_OK;
+}
+
+template <typename real>
+tnvan_status run_sample(tnvan_net *net, const float *uniforms, int8_t *spins, void *logq,
+                        hipStream_t st) {
+  tnvan_status s = ensure_sample_blocks(net);
+  if (s) return s;
+  // all instances share the launch; samples per block follow the smallest L
+  // (each instance's own lane count is used inside its blocks)
+  SampleArgs<real> a{};
+  a.mi = net->d_mi.as<MadeInst>();
+  a.params = net->params.as<float>();
+  a.uniforms = uniforms;
+  a.blk_inst = net->blk_inst.as<int32_t>();
+  a.blk_start = net->blk_start.as<int32_t>();
+  a.spins = spins;
+  a.logq = static_cast<real *>(logq);
+  a.seed = net->seed;
+  a.step_ctr = net->step_ctr.as<int32_t>();
+  a.spb = 0;
+  // spb differs per instance: launch per group of equal L
+  int minL = 64;
+  for (auto &m : net->mi) minL = std::min(minL, (int)m.L);
+  bool uniformL = true;
+  for (auto &m : net->mi) uniformL &= (m.L == net->mi[0].L);
+  if (!uniformL) return set_err(TNVAN_E_INVALID, "instances need equal sampler lane counts");
+  a.spb = 256 / net->mi[0].L;
+  HIPCHK(launch_sample<real>(a, net->n_sblocks, st));
+  return TNVAN_OK;
+}
+
+template <typename real>
+tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out,
+                      hipStream_t st) {
+  const int64_t B = net->B_total;
+  HIPCHK(net->w_spins.ensure(std::max<int64_t>(1, net->spin_total)));
+  HIPCHK(net->w_logz.ensure(std::max<int64_t>(1, B) * 8));
+  HIPCHK(net->w_logq.ensure(std::max<int64_t>(1, B) * sizeof(real)));
+  HIPCHK(net->w_f.ensure(std::max<int64_t>(1, B) * 8));
+  HIPCHK(net->w_wts.ensure(std::max<int64_t>(1, B) * sizeof(real)));
+  int8_t *spins = spins_out ? spins_out : net->w_spins.as<int8_t>();
+  tnvan_status s = run_sample<real>(net, nullptr, spins, net->w_logq.p, st);
+  if (s) return s;
+  s = run_logz<real>(net, spins, net->w_logz.as<double>(), st);
+  if (s) return s;
+  for (int q = 0; q < net->n_inst; ++q) {
+    const MadeInst &m = net->mi[q];
+    const InstDesc &D = net->P.insts[q];
+    if (m.B <= 0) continue;
+    FreeArgs<real> f{};
+    f.spins = spins + m.spin_off;
+    f.logz = net->w_logz.as<double>() + m.sample_off;
+    f.logq = net->w_logq.as<real>() + m.sample_off;
+    f.ww_a = net->ww_a.as<int32_t>() + D.ww_off;
+    f.ww_b = net->ww_b.as<int32_t>() + D.ww_off;
+    f.ww_J = net->ww_J.as<double>() + D.ww_off;
+    f.hW = net->hW.as<double>() + net->P.hw_off[q];
+    f.n_ww = D.n_ww;
+    f.nw = D.nw;
+    f.B = m.B;
+    f.beta = D.beta;
+    f.f = net->w_f.as<double>() + m.sample_off;
+    f.wts = net->w_wts.as<real>() + m.sample_off;
+    f.stats = stats + 4 * q;
+    HIPCHK(launch_free<real>(f, st));
+    // REINFORCE backward through q
+    const int n = m.n, H = m.H;
+    HIPCHK(net->w_hid.ensure(std::max<int64_t>(1, m.B * H) * sizeof(real)));
+    HIPCHK(net->w_da.ensure(std::max<int64_t>(1, m.B * H) * sizeof(real)));
+    HIPCHK(net->w_dlogit.ensure(std::max<int64_t>(1, m.B * n) * sizeof(real)));
+    HIPCHK(net->w_sf.ensure(std::max<int64_t>(1, m.B * n) * sizeof(real)));
+    RowArgs<real> r{};
+    r.mi = m;
+    r.mi.spin_off = 0;
+    r.params = net->params.as<float>();
+    r.spins = spins + m.spin_off;
+    r.wts = net->w_wts.as<real>();
+    r.hid = net->w_hid.as<real>();
+    r.da = net->w_da.as<real>();
+    r.dlogit = net->w_dlogit.as<real>();
+    r.sf = net->w_sf.as<real>();
+    HIPCHK(launch_rows<real>(r, st));
+    const int ks = (int)std::max<int64_t>(1, std::min<int64_t>(64, m.B / 256));
+    const int64_t maxmn = std::max<int64_t>({(int64_t)n * H, (int64_t)n * n, (int64_t)H});
+    HIPCHK(net->w_part.ensure(std::max<int64_t>(1, maxmn * ks) * sizeof(real)));
+    float *g = net->grad.as<float>() + m.param_off;
+    float *gW1 = g, *gb1 = g + (int64_t)H * n, *gW2 = gb1 + H, *gb2 = gW2 + (int64_t)n * H,
+          *gW0 = gb2 + n;
+    real *part = net->w_part.as<real>();
+    if (H > 0) {
+      HIPCHK(launch_atb<real>(r.dlogit, n, r.hid, H, m.B, n, H, part, ks, gW2, H, 1, n, st));
+      HIPCHK(launch_atb<real>(r.da, H, r.sf, n, m.B, H, n, part, ks, gW1, n, 3, n, st));
+      HIPCHK(launch_colsum<real>(r.da, H, m.B, H, part, ks, gb1, st));
+    }
+    HIPCHK(launch_atb<real>(r.dlogit, n, r.sf, n, m.B, n, n, part, ks, gW0, n, 2, n, st));
+    HIPCHK(launch_colsum<real>(r.dlogit, n, m.B, n, part, ks, gb2, st));
+    HIPCHK(launch_adam(net->params.as<float>() + m.param_off, g,
+                       net->adam_m.as<float>() + m.param_off,
+                       net->adam_v.as<float>() + m.param_off, net->param_count[q], lr,
+                       net->step_ctr.as<int32_t>() + q, st));
+  }
+  HIPCHK(launch_bump(net->step_ctr.as<int32_t>(), net->n_inst, st));
+  return TNVAN_OK;
+}
+
+tnvan_status check_net(const tnvan_net *net) {
+  if (!net) return set_err(TNVAN_E_INVALID, "net is NULL");
+  return TNVAN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tnvan_last_error(void) { return g_err.c_str(); }
+
+tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
+                                 const tnvan_options *opt, tnvan_net **out) {
+  if (!out) return set_err(TNVAN_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!inst || n_inst <= 0 || n_inst > 65536) return set_err(TNVAN_E_INVALID, "bad instance list");
+  if (!opt) return set_err(TNVAN_E_INVALID, "options are NULL");
+  if (opt->precision < TNVAN_FP64 || opt->precision > TNVAN_BF16)
+    return set_err(TNVAN_E_INVALID, "unknown precision %d", opt->precision);
+  tnvan_net *net = new (std::nothrow) tnvan_net();
+  if (!net) return set_err(TNVAN_E_NOMEM, "host allocation failed");
+  net->precision = opt->precision;
+  net->seed = opt->seed;
+  net->n_inst = n_inst;
+  for (int q = 0; q < n_inst; ++q) {
+    std::string msg;
+    tnvan_status s = compile_instance(inst[q], opt->max_width, net->P, msg);
+    if (s != TNVAN_OK) {
+      delete net;
+      return set_err(s, "instance %d: %s", q, msg.c_str());
+    }
+    const InstDesc &D = net->P.insts[q];
+    if (D.nw > 2048) { delete net; return set_err(TNVAN_E_INVALID, "instance %d: |W| above 2048", q); }
+  }
+  // network layout
+  int64_t poff = 0;
+  for (int q = 0; q < n_inst; ++q) {
+    MadeInst m{};
+    m.n = net->P.insts[q].nw;
+    m.H = net->P.hidden[q];
+    int L = 8;
+    while (L < 64 && (m.H > 16 * L || m.n > 32 * L)) L <<= 1;
+    if (m.H > 16 * L || m.n > 32 * L) { delete net; return set_err(TNVAN_E_INVALID, "instance %d: network too wide", q); }
+    m.L = L;
+    m.param_off = poff;
+    const int64_t pc = (int64_t)m.H * m.n + m.H + (int64_t)m.n * m.H + m.n + (int64_t)m.n * m.n;
+    net->param_count.push_back(pc);
+    poff += pc;
+    net->mi.push_back(m);
+  }
+  // one lane count for every instance keeps the sampler a single launch
+  int Lmax = 8;
+  for (auto &m : net->mi) Lmax = std::max(Lmax, (int)m.L);
+  for (auto &m : net->mi) m.L = Lmax;
+  net->param_total = poff;
+  auto fail = [&](hipError_t e, const char *what) {
+    tnvan_free_network(net);
+    return set_err(e == hipErrorOutOfMemory ? TNVAN_E_NOMEM : TNVAN_E_HIP, "%s: %s", what,
+                   hipGetErrorString(e));
+  };
+  hipError_t e;
+  HostProgram &P = net->P;
+#define UP(buf, vec) if ((e = upload(net->buf, vec)) != hipSuccess) return fail(e, #buf);
+  UP(inst, P.insts) UP(steps, P.steps) UP(inputs, P.inputs) UP(edges, P.edges)
+  UP(fld_ptr, P.fld_ptr) UP(fld_w, P.fld_w) UP(wr_pos, P.wr_pos) UP(wr_w, P.wr_w)
+  UP(rr_edge, P.rr_edge) UP(rr_J, P.rr_J) UP(wr_edge, P.wr_edge) UP(wr_J, P.wr_J)
+  UP(hR64, P.hR) UP(vr, P.vr) UP(ww_a, P.ww_a) UP(ww_b, P.ww_b) UP(ww_J, P.ww_J)
+  UP(hW, P.hW)
+  if (net->precision == TNVAN_FP64) {
+    UP(T, P.T) UP(fld_J, P.fld_J) UP(hR, P.hR)
+  } else {
+    std::vector<float> t(P.T.begin(), P.T.end()), fj(P.fld_J.begin(), P.fld_J.end()),
+        hr(P.hR.begin(), P.hR.end());
+    UP(T, t) UP(fld_J, fj) UP(hR, hr)
+  }
+  {
+    std::vector<int64_t> sb(n_inst), eb(n_inst);
+    int64_t a = 0, b = 0;
+    for (int q = 0; q < n_inst; ++q) { sb[q] = a; eb[q] = b; a += P.insts[q].n; b += P.insts[q].n_edges; }
+    UP(d_spin_base, sb) UP(d_edge_base, eb)
+  }
+  UP(d_mi, net->mi)
+#undef UP
+  const size_t pb = std::max<int64_t>(1, net->param_total) * sizeof(float);
+  if ((e = net->params.ensure(pb)) || (e = net->adam_m.ensure(pb)) || (e = net->adam_v.ensure(pb)) ||
+      (e = net->grad.ensure(pb)) || (e = net->step_ctr.ensure(sizeof(int32_t) * n_inst)))
+    return fail(e, "parameter buffers");
+  if ((e = hipMemset(net->params.p, 0, pb)) || (e = hipMemset(net->adam_m.p, 0, pb)) ||
+      (e = hipMemset(net->adam_v.p, 0, pb)) || (e = hipMemset(net->grad.p, 0, pb)) ||
+      (e = hipMemset(net->step_ctr.p, 0, sizeof(int32_t) * n_inst)))
+    return fail(e, "parameter init");
+  choose_tiles(net, false);
+  choose_tiles(net, true);
+  *out = net;
+  return TNVAN_OK;
+}
+
+void tnvan_free_network(tnvan_net *net) {
+  if (!net) return;
+  DBuf *all[] = {&net->inst, &net->steps, &net->inputs, &net->edges, &net->T, &net->fld_ptr,
+                 &net->fld_w, &net->fld_J, &net->hR, &net->wr_pos, &net->wr_w, &net->rr_edge,
+                 &net->rr_J, &net->wr_edge, &net->wr_J, &net->hR64, &net->vr, &net->ww_a,
+                 &net->ww_b, &net->ww_J, &net->hW, &net->d_mi, &net->params, &net->adam_m,
+                 &net->adam_v, &net->grad, &net->step_ctr, &net->d_sample_off, &net->d_B,
+                 &net->d_spin_off, &net->d_spin_base, &net->d_edge_base, &net->blk_inst,
+                 &net->blk_start, &net->garena, &net->partial, &net->w_logz, &net->w_logq,
+                 &net->w_spins, &net->w_f, &net->w_wts, &net->w_hid, &net->w_da,
+                 &net->w_dlogit, &net->w_sf, &net->w_part};
+  for (DBuf *b : all) b->release();
+  TileCache *tcs[] = {&net->tc_fwd, &net->tc_bwd};
+  for (TileCache *tc : tcs) {
+    tc->tile_inst.release(); tc->tile_start.release(); tc->first_tile.release();
+    tc->n_tiles_i.release(); tc->partial_off.release();
+  }
+  delete net;
+}
+
+tnvan_status tnvan_param_count(const tnvan_net *net, int32_t inst, int64_t *count) {
+  if (tnvan_status s = check_net(net)) return s;
+  if (inst < 0 || inst >= net->n_inst || !count) return set_err(TNVAN_E_INVALID, "bad instance index");
+  *count = net->param_count[inst];
+  return TNVAN_OK;
+}
+
+tnvan_status tnvan_set_params(tnvan_net *net, int32_t inst, const float *src, void *stream) {
+  if (tnvan_status s = check_net(net)) return s;
+  if (inst < 0 || inst >= net->n_inst || !src) return set_err(TNVAN_E_INVALID, "bad instance or source");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t bytes = net->param_count[inst] * sizeof(float);
+  const int64_t off = net->mi[inst].param_off;
+  HIPCHK(hipMemcpyAsync(net->params.as<float>() + off, src, bytes, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemsetAsync(net->adam_m.as<float>() + off, 0, bytes, st));
+  HIPCHK(hipMemsetAsync(net->adam_v.as<float>() + off, 0, bytes, st));
+  HIPCHK(hipMemsetAsync(net->step_ctr.as<int32_t>() + inst, 0, sizeof(int32_t), st));
+  return TNVAN_OK;
+}
+
+tnvan_status tnvan_get_params(tnvan_net *net, int32_t inst, float *dst, void *stream) {
+  if (tnvan_status s = check_net(net)) return s;
+  if (inst < 0 || inst >= net->n_inst || !dst) return set_err(TNVAN_E_INVALID, "bad instance or destination");
+  HIPCHK(hipMemcpyAsync(dst, net->params.as<float>() + net->mi[inst].param_off,
+                        net->param_count[inst] * sizeof(float), hipMemcpyDeviceToDevice,
+                        static_cast<hipStream_t>(stream)));
+  return TNVAN_OK;
+}
+
+tnvan_status tnvan_get_state(tnvan_net *net, int32_t inst, int32_t which, float *dst,
+                             void *stream) {
+  if (tnvan_status s = check_net(net)) return s;
+  if (inst < 0 || inst >= net->n_inst || !dst) return set_err(TNVAN_E_INVALID, "bad instance or destination");
+  const DBuf *src = which == 0 ? &net->params : which == 1 ? &net->grad
+                  : which == 2 ? &net->adam_m : which == 3 ? &net->adam_v : nullptr;
+  if (!src) return set_err(TNVAN_E_INVALID, "unknown state %d", which);
+  HIPCHK(hipMemcpyAsync(dst, src->as<float>() + net->mi[inst].param_off,
+                        net->param_count[inst] * sizeof(float), hipMemcpyDeviceToDevice,
+                        static_cast<hipStream_t>(stream)));
+  return TNVAN_OK;
+}
+
+tnvan_status tnvan_sample(tnvan_net *net, const int64_t *n_samples, const float *uniforms,
+                          int8_t *spins, void *logq, void *stream) {
+  if (tnvan_status s = check_net(net)) return s;
+  if (tnvan_status s = set_batch(net, n_samples)) return s;
+  if (net->B_total == 0) return TNVAN_OK;
+  if (!spins || !logq) return set_err(TNVAN_E_INVALID, "spins and logq are required");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (net->precision == TNVAN_FP64) return run_sample<double>(net, uniforms, spins, logq, st);
+  return run_sample<float>(net, uniforms, spins, logq, st);
+}
+
+tnvan_status tnvan_logz_batch(tnvan_net *net, const int64_t *n_samples, const int8_t *spins,
+                              double *logz, void *stream) {
+  if (tnvan_status s = check_net(net)) return s;
+  if (tnvan_status s = set_batch(net, n_samples)) return s;
+  if (net->B_total == 0) return TNVAN_OK;
+  if (!logz || (!spins && net->spin_total > 0)) return set_err(TNVAN_E_INVALID, "spins and logz are required");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (net->precision == TNVAN_FP64) return run_logz<double>(net, spins, logz, st);
+  return run_logz<float>(net, spins, logz, st);
+}
+
+tnvan_status tnvan_logz_backward(tnvan_net *net, const int64_t *n_samples, const int8_t *spins,
+                                 const double *grad, double *dh, double *dJ, double *dbeta,
+                                 void *stream) {
+  if (tnvan_status s = check_net(net)) return s;
+  if (tnvan_status s = set_batch(net, n_samples)) return s;
+  if (!dh || !dJ || !dbeta) return set_err(TNVAN_E_INVALID, "dh, dJ and dbeta are required");
+  if (net->B_total > 0 && (!grad || (!spins && net->spin_total > 0)))
+    return set_err(TNVAN_E_INVALID, "spins and grad_logz are required");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (net->precision == TNVAN_FP64) return run_backward<double>(net, spins, grad, dh, dJ, dbeta, st);
+  return run_backward<float>(net, spins, grad, dh, dJ, dbeta, st);
+}
+
+tnvan_status tnvan_free_energy_step(tnvan_net *net, const int64_t *n_samples, float lr,
+                                    double *stats, int8_t *spins_out, void *stream) {
+  if (tnvan_status s = check_net(net)) return s;
+  if (!stats) return set_err(TNVAN_E_INVALID, "stats is required");
+  for (auto &D : net->P.insts)
+    if (!(D.beta > 0)) return set_err(TNVAN_E_INVALID, "free_energy_step needs beta > 0");
+  if (tnvan_status s = set_batch(net, n_samples)) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (net->precision == TNVAN_FP64) return run_step<double>(net, lr, stats, spins_out, st);
+  return run_step<float>(net, lr, stats, spins_out, st);
+}
+
+tnvan_status tnvan_program_info(const tnvan_net *net, int32_t inst, int64_t info[6]) {
+  if (tnvan_status s = check_net(net)) return s;
+  if (inst < 0 || inst >= net->n_inst || !info) return set_err(TNVAN_E_INVALID, "bad instance index");
+  const InstDesc &D = net->P.insts[inst];
+  info[0] = D.n_steps; info[1] = D.max_w; info[2] = D.arena_all;
+  info[3] = net->P.flops_fwd[inst]; info[4] = D.nw; info[5] = D.nr;
+  return TNVAN_OK;
+}
+
+tnvan_status tnvan_plan(const tnvan_instance *inst, int32_t max_width, int64_t info[6]) {
+  if (!inst || !info) return set_err(TNVAN_E_INVALID, "instance and info are required");
+  HostProgram P;
+  std::string msg;
+  tnvan_status s = compile_instance(*inst, max_width, P, msg);
+  if (s != TNVAN_OK) return set_err(s, "%s", msg.c_str());
+  const InstDesc &D = P.insts[0];
+  info[0] = D.n_steps; info[1] = D.max_w; info[2] = D.arena_all;
+  info[3] = P.flops_fwd[0]; info[4] = D.nw; info[5] = D.nr;
+  return TNVAN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,40 @@
+// Host-side instance compiler: validates a tnvan_instance and turns its
+// width set and elimination order into the step program of program.h.
+// Pure C++ (no HIP), so it is also built and tested on machines without a GPU.
+#pragma once
+#include <string>
+#include <vector>
+
+#include "../../include/tnvan.h"
+#include "program.h"
+
+namespace tnvan {
+
+struct HostProgram {
+  std::vector<InstDesc> insts;
+  std::vector<StepDesc> steps;
+  std::vector<InputDesc> inputs;
+  std::vector<EdgeDesc> edges;
+  std::vector<double> T;          // all step tables, FP64
+  std::vector<int32_t> fld_ptr;   // per instance: nr + 1 entries (local)
+  std::vector<int32_t> fld_w;     // W index of each W-neighbour
+  std::vector<double> fld_J;      // its coupling
+  std::vector<double> hR;         // h on R positions
+  std::vector<int32_t> wr_pos, wr_w, wr_edge;   // W-R edges
+  std::vector<double> wr_J;
+  std::vector<int32_t> rr_edge;   // R-R edges (global edge id per instance)
+  std::vector<double> rr_J;
+  std::vector<int32_t> ww_a, ww_b;  // W-W edges as W indices
+  std::vector<double> ww_J;
+  std::vector<double> hW;           // h on W indices (for E_1)
+  std::vector<int32_t> vr, wv;      // R position -> vertex, W index -> vertex
+  std::vector<int32_t> hidden;      // per instance
+  std::vector<int64_t> flops_fwd;   // per instance, per sample
+  std::vector<int32_t> hw_off;      // per instance offset into hW
+};
+
+// Appends one instance to P.  Returns TNVAN_OK or an error code with msg.
+tnvan_status compile_instance(const tnvan_instance &in, int max_width,
+                              HostProgram &P, std::string &msg);
+
+}  // namespace tnvan

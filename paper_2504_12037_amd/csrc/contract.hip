@@ -1,0 +1,540 @@
+// Batched conditional log-partition function of the remainder and its
+// adjoint (Sec. 2, Eqs. 2-4).
+//
+// One workgroup (256 threads) contracts a tile of S samples of one instance
+// through every elimination step of the compiled program.  Work items of a
+// step are (sample, output entry) pairs with the sample index fastest, so a
+// thread always serves the same sample and the per-sample state sits in LDS
+// as [entry][S] (conflict-free, broadcast reads of the static tables).
+//
+// Rescaling: a message is stored as computed ("raw"); its per-sample scale
+// 2^-e, with e the binary exponent of the largest entry, is kept as the max
+// bit pattern of that step (LDS atomic max over positive floats) and applied
+// whenever the message is read.  Scaling by a power of two is exact, so the
+// contraction result is independent of it; the exponents are summed in FP64
+// into log Z.
+//
+// Adjoint: with mu_t the marginal of message t's scope and m~_t the scaled
+// message, rho_t = mu_t / m~_t is written over message t by the step that
+// consumed it.  Walking the steps backwards, step t forms for every sample the
+// joint weight c(o, x) = rho_t[o] 2^-e_t T[x, o] d[x] prod_k m~_k (a
+// probability: it sums to one over (o, x)), from which the marginals of the
+// eliminated spins, the correlations of the R-R edges the step consumed and
+// the rho of its inputs follow.  Batch sums weighted by the upstream gradient
+// are reduced in a fixed order into one partial row per tile.
+#include <hip/hip_runtime.h>
+
+#include "launch.h"
+
+namespace tnvan {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kRed = 4;         // values per column reduction pass
+
+template <typename real> struct FBits;
+template <> struct FBits<float> {
+  using U = uint32_t;
+  __device__ static U bits(float x) { return __float_as_uint(x); }
+  // e with max * 2^-e in [0.5, 1)
+  __device__ static int expo(U b) {
+    int E = (int)((b >> 23) & 0xffu);
+    int e = E - 126;
+    return e > 126 ? 126 : e;
+  }
+  __device__ static float scale(int e) { return __uint_as_float((uint32_t)(127 - e) << 23); }
+};
+template <> struct FBits<double> {
+  using U = unsigned long long;
+  __device__ static U bits(double x) { return (U)__double_as_longlong(x); }
+  __device__ static int expo(U b) {
+    int E = (int)((b >> 52) & 0x7ffull);
+    int e = E - 1022;
+    return e > 1022 ? 1022 : e;
+  }
+  __device__ static double scale(int e) {
+    return __longlong_as_double((long long)((unsigned long long)(1023 - e) << 52));
+  }
+};
+
+struct Layout {
+  size_t mx, phi, fab, gs, M, C, red, res, arena, scr, end;
+};
+
+__host__ __device__ inline size_t al8(size_t x) { return (x + 7) & ~(size_t)7; }
+
+__host__ __device__ inline Layout make_layout(const InstDesc &D, int S, bool bwd,
+                                              bool global_arena, int rs) {
+  Layout L{};
+  size_t o = 0;
+  const int us = rs == 4 ? 4 : 8;
+  L.mx = o;  o = al8(o + (size_t)D.n_steps * S * us);
+  L.phi = o; o = al8(o + (size_t)D.nr * 2 * S * rs);
+  L.fab = o; o = al8(o + (size_t)D.nr * S * rs);
+  if (bwd) {
+    L.gs = o;  o = al8(o + (size_t)S * rs);
+    L.M = o;   o = al8(o + (size_t)D.nr * S * rs);
+    L.C = o;   o = al8(o + (size_t)D.n_rr * rs);
+    L.red = o; o = al8(o + (size_t)kWaves * kRed * S * rs);
+    L.res = o; o = al8(o + (size_t)kRed * S * rs);
+  }
+  if (!global_arena) {
+    L.arena = o; o = al8(o + (size_t)(bwd ? D.arena_all : D.arena_fwd) * S * rs);
+    L.scr = o;   o = al8(o + (size_t)(bwd ? D.scr_bwd : D.scr_fwd) * S * rs);
+  }
+  L.end = o;
+  return L;
+}
+
+template <typename real>
+__device__ inline real rexp(real x);
+template <> __device__ inline float rexp<float>(float x) { return expf(x); }
+template <> __device__ inline double rexp<double>(double x) { return exp(x); }
+
+// index of the input message entry for output entry o and group state x
+__device__ inline int gather_index(const InputDesc &id, int o, int x) {
+  int idx = 0;
+  for (int b = 0; b < id.nbits; ++b) {
+    int sb = id.src[b];
+    int bit = sb < 0 ? x : ((o >> sb) & 1);
+    idx |= bit << b;
+  }
+  return idx;
+}
+
+template <typename real, bool kGlobal, bool kBwd>
+__global__ __launch_bounds__(kThreads) void contract_kernel(ContractArgs<real> a) {
+  using FB = FBits<real>;
+  using U = typename FB::U;
+  extern __shared__ __align__(16) char smem[];
+  const int tid = threadIdx.x;
+  const int tile = blockIdx.x;
+  const int q = a.tile_inst[tile];
+  const InstDesc D = a.inst[q];
+  const int S = a.S, logS = a.logS;
+  const int64_t b0 = a.tile_start[tile];
+  const int64_t Bq = a.inst_B[q];
+  const int nb = (int)((Bq - b0) < S ? (Bq - b0) : S);
+  const int sme = tid & (S - 1);
+  const Layout Lo = make_layout(D, S, kBwd, kGlobal, (int)sizeof(real));
+  U *mx = reinterpret_cast<U *>(smem + Lo.mx);
+  real *phi = reinterpret_cast<real *>(smem + Lo.phi);
+  real *fab = reinterpret_cast<real *>(smem + Lo.fab);
+  real *arena;
+  real *scr;
+  if (kGlobal) {
+    arena = a.garena + (int64_t)tile * a.garena_stride;
+    scr = arena + (int64_t)(kBwd ? D.arena_all : D.arena_fwd) * S;
+  } else {
+    arena = reinterpret_cast<real *>(smem + Lo.arena);
+    scr = reinterpret_cast<real *>(smem + Lo.scr);
+  }
+  const StepDesc *steps = a.steps + D.step_off;
+  const int8_t *spq = a.spins + a.inst_spin_off[q];
+  const real beta = (real)D.beta;
+
+  for (int i = tid; i < D.n_steps * S; i += kThreads) mx[i] = 0;
+  // unary factors of R (fields from h and the fixed width-set spins),
+  // normalised so that the larger of the two equals one
+  for (int i = tid; i < D.nr * S; i += kThreads) {
+    const int p = i >> logS, s = i & (S - 1);
+    real f = a.hR[D.hr_off + p];
+    if (s < nb) {
+      const int8_t *sp = spq + (b0 + s) * D.nw;
+      const int k0 = a.fld_ptr[D.fld_off + p], k1 = a.fld_ptr[D.fld_off + p + 1];
+      for (int k = k0; k < k1; ++k)
+        f += a.fld_J[D.fld_nnz_off + k] * (real)sp[a.fld_w[D.fld_nnz_off + k]];
+    }
+    const real af = beta * (f < 0 ? -f : f);
+    const real small = rexp<real>(-2 * af);
+    phi[(2 * p) * S + s] = f >= 0 ? (real)1 : small;       // spin +1
+    phi[(2 * p + 1) * S + s] = f >= 0 ? small : (real)1;   // spin -1
+    fab[p * S + s] = af;
+  }
+  __syncthreads();
+
+  // ------------------------------------------------------------ forward
+  for (int t = 0; t < D.n_steps; ++t) {
+    const StepDesc sd = steps[t];
+    const int w = sd.w, g = sd.g;
+    const int off = kBwd ? sd.off_all : sd.off_fwd;
+    const real *Tt = a.T + sd.t_off;
+    real lmax = 0;
+    if (sd.kind == STEP_DENSE) {
+      int inoff = 0;
+      real insc = 1;
+      if (sd.n_in) {
+        const InputDesc id = a.inputs[sd.in_off];
+        const StepDesc ps = steps[id.step];
+        inoff = kBwd ? ps.off_all : ps.off_fwd;
+        insc = FB::scale(FB::expo(mx[id.step * S + sme]));
+      }
+      for (int i = tid; i < (S << g); i += kThreads) {
+        const int x = i >> logS;
+        real A = 1;
+        for (int j = 0; j < g; ++j) A *= phi[(2 * (sd.gpos + j) + ((x >> j) & 1)) * S + sme];
+        if (sd.n_in) A *= arena[(inoff + x) * S + sme] * insc;
+        scr[x * S + sme] = A;
+      }
+      __syncthreads();
+      const int nx = 1 << g;
+      for (int i = tid; i < (S << w); i += kThreads) {
+        const int o = i >> logS;
+        real acc = 0;
+        for (int x = 0; x < nx; ++x) acc += Tt[(x << w) | o] * scr[x * S + sme];
+        arena[(off + o) * S + sme] = acc;
+        lmax = acc > lmax ? acc : lmax;
+      }
+    } else {
+      for (int i = tid; i < (S << w); i += kThreads) {
+        const int o = i >> logS;
+        real acc = 0;
+        for (int x = 0; x < 2; ++x) {
+          real p = Tt[(x << w) | o] * phi[(2 * sd.gpos + x) * S + sme];
+          for (int k = 0; k < sd.n_in; ++k) {
+            const InputDesc id = a.inputs[sd.in_off + k];
+            const StepDesc ps = steps[id.step];
+            const int ioff = kBwd ? ps.off_all : ps.off_fwd;
+            const real sc = FB::scale(FB::expo(mx[id.step * S + sme]));
+            p *= arena[(ioff + gather_index(id, o, x)) * S + sme] * sc;
+          }
+          acc += p;
+        }
+        arena[(off + o) * S + sme] = acc;
+        lmax = acc > lmax ? acc : lmax;
+      }
+    }
+    if (tid < (S << w)) atomicMax(&mx[t * S + sme], FB::bits(lmax));
+    __syncthreads();
+  }
+
+  if (!kBwd) {
+    for (int s = tid; s < nb; s += kThreads) {
+      double acc = D.log_const;
+      for (int p = 0; p < D.nr; ++p) acc += (double)fab[p * S + s];
+      int64_t esum = 0;
+      for (int t = 0; t < D.n_steps; ++t) {
+        const StepDesc sd = steps[t];
+        if (sd.w == 0) acc += log((double)arena[sd.off_fwd * S + s]);
+        else esum += FB::expo(mx[t * S + s]);
+      }
+      acc += (double)esum * 0.69314718055994530942;
+      a.logz[a.inst_sample_off[q] + b0 + s] = acc;
+    }
+    return;
+  }
+
+  // ------------------------------------------------------------ reverse
+  real *gs = reinterpret_cast<real *>(smem + Lo.gs);
+  real *Mg = reinterpret_cast<real *>(smem + Lo.M);
+  real *Cw = reinterpret_cast<real *>(smem + Lo.C);
+  real *red = reinterpret_cast<real *>(smem + Lo.red);
+  real *res = reinterpret_cast<real *>(smem + Lo.res);
+  for (int s = tid; s < S; s += kThreads)
+    gs[s] = s < nb ? (real)a.grad[a.inst_sample_off[q] + b0 + s] : (real)0;
+  for (int k = tid; k < D.n_rr; k += kThreads) Cw[k] = 0;
+  __syncthreads();
+  const int lane = tid & 63, wave = tid >> 6;
+
+  for (int t = D.n_steps - 1; t >= 0; --t) {
+    const StepDesc sd = steps[t];
+    const int w = sd.w, g = sd.g;
+    const int off = sd.off_all;
+    const real *Tt = a.T + sd.t_off;
+    const real sct = FB::scale(FB::expo(mx[t * S + sme]));
+    // adjoint factor of the output entry o for sample sme
+    auto rfac = [&](int o) -> real {
+      const real v = arena[(off + o) * S + sme];
+      if (w == 0) return v > 0 ? (real)1 / v : (real)0;
+      return v * sct;
+    };
+    if (sd.kind == STEP_DENSE) {
+      const int nx = 1 << g;
+      int inoff = 0;
+      real insc = 1;
+      if (sd.n_in) {
+        const InputDesc id = a.inputs[sd.in_off];
+        inoff = steps[id.step].off_all;
+        insc = FB::scale(FB::expo(mx[id.step * S + sme]));
+      }
+      real *sA = scr;                 // [x][S]
+      real *sL = scr + nx * S;        // [x][w+1][S], slot w = Lambda
+      for (int i = tid; i < (S << g); i += kThreads) {
+        const int x = i >> logS;
+        real A = 1;
+        for (int j = 0; j < g; ++j) A *= phi[(2 * (sd.gpos + j) + ((x >> j) & 1)) * S + sme];
+        if (sd.n_in) A *= arena[(inoff + x) * S + sme] * insc;
+        real lam = 0;
+        real lj[kMaxW];
+#pragma unroll
+        for (int j = 0; j < kMaxW; ++j) lj[j] = 0;
+        const int no = 1 << w;
+        for (int o = 0; o < no; ++o) {
+          const real tr = Tt[(x << w) | o] * rfac(o);
+          lam += tr;
+#pragma unroll
+          for (int j = 0; j < kMaxW; ++j)
+            if (j < w) lj[j] += ((o >> j) & 1) ? -tr : tr;
+        }
+        sA[x * S + sme] = A;
+#pragma unroll
+        for (int j = 0; j < kMaxW; ++j)
+          if (j < w) sL[(x * (w + 1) + j) * S + sme] = lj[j];
+        sL[(x * (w + 1) + w) * S + sme] = lam;
+      }
+      __syncthreads();
+      // rho of the input message: d[x] * Lambda[x]
+      if (sd.n_in) {
+        for (int i = tid; i < (S << g); i += kThreads) {
+          const int x = i >> logS;
+          real d = 1;
+          for (int j = 0; j < g; ++j) d *= phi[(2 * (sd.gpos + j) + ((x >> j) & 1)) * S + sme];
+          arena[(inoff + x) * S + sme] = d * sL[(x * (w + 1) + w) * S + sme];
+        }
+      }
+      // per-sample magnetisation of the eliminated spins
+      for (int i = tid; i < S * g; i += kThreads) {
+        const int s = i & (S - 1), j = i >> logS;
+        real m = 0;
+        for (int x = 0; x < nx; ++x) {
+          const real c = sA[x * S + s] * sL[(x * (w + 1) + w) * S + s];
+          m += ((x >> j) & 1) ? -c : c;
+        }
+        Mg[(sd.gpos + j) * S + s] = m;
+      }
+      // gradient-weighted correlations of the R-R edges folded into T
+      for (int k = tid; k < sd.n_edge; k += kThreads) {
+        const EdgeDesc ed = a.edges[sd.edge_off + k];
+        const int ju = ed.bu - w;
+        const bool vin = ed.bv >= w;
+        const int jv = vin ? ed.bv - w : ed.bv;
+        real acc = 0;
+        for (int s = 0; s < S; ++s) {
+          real cs = 0;
+          for (int x = 0; x < nx; ++x) {
+            const real l = vin ? (((x >> jv) & 1) ? -sL[(x * (w + 1) + w) * S + s]
+                                                  : sL[(x * (w + 1) + w) * S + s])
+                               : sL[(x * (w + 1) + jv) * S + s];
+            const real c = sA[x * S + s] * l;
+            cs += ((x >> ju) & 1) ? -c : c;
+          }
+          acc += gs[s] * cs;
+        }
+        Cw[ed.rr] = acc;
+      }
+      __syncthreads();
+    } else {
+      // SINGLE: joint weights c(o, x) into scratch [(o*2 + x)][S]
+      for (int i = tid; i < (S << w); i += kThreads) {
+        const int o = i >> logS;
+        const real r = rfac(o);
+        for (int x = 0; x < 2; ++x) {
+          real p = r * Tt[(x << w) | o] * phi[(2 * sd.gpos + x) * S + sme];
+          for (int k = 0; k < sd.n_in; ++k) {
+            const InputDesc id = a.inputs[sd.in_off + k];
+            const StepDesc ps = steps[id.step];
+            const real sc = FB::scale(FB::expo(mx[id.step * S + sme]));
+            p *= arena[(ps.off_all + gather_index(id, o, x)) * S + sme] * sc;
+          }
+          scr[(o * 2 + x) * S + sme] = p;
+        }
+      }
+      __syncthreads();
+      // rho of every input: marginal of its scope over its scaled value
+      for (int k = 0; k < sd.n_in; ++k) {
+        const InputDesc id = a.inputs[sd.in_off + k];
+        const StepDesc ps = steps[id.step];
+        const real sc = FB::scale(FB::expo(mx[id.step * S + sme]));
+        int omask = 0;
+        for (int b = 0; b < id.nbits; ++b)
+          if (id.src[b] >= 0) omask |= 1 << id.src[b];
+        const int freem = ((1 << w) - 1) & ~omask;
+        for (int i = tid; i < (S << id.nbits); i += kThreads) {
+          const int j = i >> logS;
+          int ofix = 0, x = 0;
+          for (int b = 0; b < id.nbits; ++b) {
+            const int bit = (j >> b) & 1;
+            if (id.src[b] < 0) x = bit;
+            else ofix |= bit << id.src[b];
+          }
+          real mu = 0;
+          int z = 0;
+          do {
+            mu += scr[(((ofix | z) * 2) + x) * S + sme];
+            z = (z - freem) & freem;
+          } while (z != 0);
+          real *slot = &arena[(ps.off_all + j) * S + sme];
+          const real m = *slot * sc;
+          *slot = m > 0 ? mu / m : (real)0;
+        }
+      }
+      // per-sample sums over o: magnetisation of v and its edge correlations
+      const int K = 1 + sd.n_edge;
+      for (int c0 = 0; c0 < K; c0 += kRed) {
+        real v[kRed];
+        int ob[kRed];
+#pragma unroll
+        for (int r = 0; r < kRed; ++r) {
+          v[r] = 0;
+          const int k = c0 + r;
+          ob[r] = (k == 0 || k >= K) ? -1 : a.edges[sd.edge_off + k - 1].bv;
+        }
+        for (int i = tid; i < (S << w); i += kThreads) {
+          const int o = i >> logS;
+          const real dlt = scr[(o * 2) * S + sme] - scr[(o * 2 + 1) * S + sme];
+#pragma unroll
+          for (int r = 0; r < kRed; ++r)
+            v[r] += (ob[r] >= 0 && ((o >> ob[r]) & 1)) ? -dlt : dlt;
+        }
+#pragma unroll
+        for (int r = 0; r < kRed; ++r)
+          for (int sh = S; sh < 64; sh <<= 1) v[r] += __shfl_xor(v[r], sh, 64);
+        if (lane < S) {
+#pragma unroll
+          for (int r = 0; r < kRed; ++r) red[(wave * kRed + r) * S + lane] = v[r];
+        }
+        __syncthreads();
+        for (int i = tid; i < kRed * S; i += kThreads) {
+          real sum = 0;
+          for (int wv = 0; wv < kWaves; ++wv) sum += red[(wv * kRed) * S + i];
+          res[i] = sum;
+        }
+        __syncthreads();
+        for (int r = tid; r < kRed; r += kThreads) {
+          const int k = c0 + r;
+          if (k == 0) {
+            // handled below (per sample)
+          } else if (k < K) {
+            real acc = 0;
+            for (int s = 0; s < S; ++s) acc += gs[s] * res[r * S + s];
+            Cw[a.edges[sd.edge_off + k - 1].rr] = acc;
+          }
+        }
+        if (c0 == 0)
+          for (int s = tid; s < S; s += kThreads) Mg[sd.gpos * S + s] = res[s];
+        __syncthreads();
+      }
+    }
+  }
+
+  // ------------------------------------------------- per-tile partial row
+  const int64_t prow = a.inst_partial_off[q] +
+                       (int64_t)(tile - a.inst_first_tile[q]) * D.n_partial;
+  for (int p = tid; p < D.nr; p += kThreads) {
+    real acc = 0;
+    for (int s = 0; s < S; ++s) acc += gs[s] * Mg[p * S + s];
+    a.partial[prow + p] = acc;
+  }
+  for (int k = tid; k < D.n_wr; k += kThreads) {
+    const int p = a.wr_pos[D.wr_off + k], wi = a.wr_w[D.wr_off + k];
+    real acc = 0;
+    for (int s = 0; s < nb; ++s)
+      acc += gs[s] * (real)spq[(b0 + s) * D.nw + wi] * Mg[p * S + s];
+    a.partial[prow + D.nr + k] = acc;
+  }
+  for (int k = tid; k < D.n_rr; k += kThreads) a.partial[prow + D.nr + D.n_wr + k] = Cw[k];
+}
+
+template <typename real>
+__global__ void vjp_sum_kernel(VjpArgs a, const real *partial, int n_inst) {
+  const int q = blockIdx.y;
+  if (q >= n_inst) return;
+  const InstDesc D = a.inst[q];
+  const int nt = a.inst_n_tiles[q];
+  const int64_t pb = a.inst_partial_off[q];
+  double *dh = a.dh + a.inst_spin_base[q];
+  double *dJ = a.dJ + a.inst_edge_base[q];
+  const double beta = D.beta;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < D.n_partial;
+       k += gridDim.x * blockDim.x) {
+    double acc = 0;
+    for (int t = 0; t < nt; ++t) acc += (double)partial[pb + (int64_t)t * D.n_partial + k];
+    if (k < D.nr) dh[a.vr[D.vr_off + k]] = beta * acc;
+    else if (k < D.nr + D.n_wr) dJ[a.wr_edge[D.wr_off + k - D.nr]] = beta * acc;
+    else dJ[a.rr_edge[D.rr_off + k - D.nr - D.n_wr]] = beta * acc;
+  }
+}
+
+template <typename real>
+__global__ void vjp_beta_kernel(VjpArgs a, const real *partial, int n_inst) {
+  // dbeta = sum_RR J C + sum_R h U + sum_WR J UW, from the reduced entries
+  __shared__ double sh[256];
+  const int q = blockIdx.x;
+  const InstDesc D = a.inst[q];
+  const int nt = a.inst_n_tiles[q];
+  const int64_t pb = a.inst_partial_off[q];
+  double acc = 0;
+  for (int k = threadIdx.x; k < D.n_partial; k += blockDim.x) {
+    double s = 0;
+    for (int t = 0; t < nt; ++t) s += (double)partial[pb + (int64_t)t * D.n_partial + k];
+    double coef;
+    if (k < D.nr) coef = a.hR[D.hr_off + k];
+    else if (k < D.nr + D.n_wr) coef = a.wr_J[D.wr_off + k - D.nr];
+    else coef = a.rr_J[D.rr_off + k - D.nr - D.n_wr];
+    acc += coef * s;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.dbeta[q] = sh[0];
+}
+
+__global__ void zero_kernel(double *p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+}  // namespace
+
+size_t contract_lds_bytes(const InstDesc &D, int S, bool bwd, bool global_arena,
+                          int real_size) {
+  return make_layout(D, S, bwd, global_arena, real_size).end;
+}
+
+int64_t contract_garena_entries(const InstDesc &D, int S, bool bwd) {
+  return (int64_t)((bwd ? D.arena_all : D.arena_fwd) + (bwd ? D.scr_bwd : D.scr_fwd)) * S;
+}
+
+template <typename real>
+hipError_t launch_contract(const ContractArgs<real> &a, int n_tiles, size_t lds,
+                           bool bwd, bool global_arena, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  void (*k)(ContractArgs<real>);
+  if (bwd) k = global_arena ? contract_kernel<real, true, true> : contract_kernel<real, false, true>;
+  else k = global_arena ? contract_kernel<real, true, false> : contract_kernel<real, false, false>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(n_tiles), dim3(kThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_vjp_reduce(const VjpArgs &a, const real *partial, int n_inst,
+                             hipStream_t st) {
+  (void)zero_kernel;
+  hipLaunchKernelGGL(vjp_sum_kernel<real>, dim3(8, n_inst), dim3(256), 0, st, a, partial, n_inst);
+  hipLaunchKernelGGL(vjp_beta_kernel<real>, dim3(n_inst), dim3(256), 0, st, a, partial, n_inst);
+  return hipGetLastError();
+}
+
+hipError_t zero_doubles(double *p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+template hipError_t launch_contract<float>(const ContractArgs<float> &, int, size_t, bool, bool, hipStream_t);
+template hipError_t launch_contract<double>(const ContractArgs<double> &, int, size_t, bool, bool, hipStream_t);
+template hipError_t launch_vjp_reduce<float>(const VjpArgs &, const float *, int, hipStream_t);
+template hipError_t launch_vjp_reduce<double>(const VjpArgs &, const double *, int, hipStream_t);
+
+}  // namespace tnvan

@@ -1,0 +1,150 @@
+// Internal launch interface between the C ABI (api.hip) and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "program.h"
+
+namespace tnvan {
+
+// Device copies of the compiled program (one set per precision of T).
+template <typename real>
+struct ContractArgs {
+  const InstDesc *inst;
+  const StepDesc *steps;
+  const InputDesc *inputs;
+  const EdgeDesc *edges;
+  const real *T;
+  const int32_t *fld_ptr;
+  const int32_t *fld_w;
+  const real *fld_J;
+  const real *hR;
+  const int32_t *wr_pos;
+  const int32_t *wr_w;
+  // tiles of samples: tile -> instance and first local sample
+  const int32_t *tile_inst;
+  const int32_t *tile_start;
+  const int32_t *inst_first_tile;
+  const int64_t *inst_sample_off;   // first global sample of each instance
+  const int64_t *inst_B;            // samples of each instance
+  const int64_t *inst_spin_off;     // first spin of each instance
+  const int64_t *inst_partial_off;  // first partial entry of each instance
+  const int8_t *spins;
+  double *logz;                     // forward output
+  const double *grad;               // backward input (upstream gradient)
+  real *partial;                    // backward per-tile partial sums
+  real *garena;                     // arena in global memory (or null)
+  int64_t garena_stride;            // entries per tile
+  int32_t S, logS;                  // samples per tile (power of two <= 64)
+};
+
+struct LdsPlan {
+  size_t bytes;          // dynamic LDS per workgroup
+  bool global_arena;     // arena and scratch live in global memory
+};
+
+// Bytes of LDS one tile of S samples of instance D needs.
+size_t contract_lds_bytes(const InstDesc &D, int S, bool bwd, bool global_arena,
+                          int real_size);
+// Global arena entries per tile (per sample entries times S).
+int64_t contract_garena_entries(const InstDesc &D, int S, bool bwd);
+
+template <typename real>
+hipError_t launch_contract(const ContractArgs<real> &a, int n_tiles, size_t lds,
+                           bool bwd, bool global_arena, hipStream_t st);
+
+// Sum per-tile partials and scatter dh, dJ, dbeta (FP64).
+struct VjpArgs {
+  const InstDesc *inst;
+  const int32_t *rr_edge;
+  const double *rr_J;
+  const int32_t *wr_edge;
+  const double *wr_J;
+  const double *hR;
+  const int32_t *vr;
+  const int32_t *inst_first_tile;
+  const int32_t *inst_n_tiles;
+  const int64_t *inst_partial_off;
+  const int64_t *inst_spin_base;   // offset of instance i in dh (sum of n)
+  const int64_t *inst_edge_base;   // offset of instance i in dJ
+  double *dh, *dJ, *dbeta;
+};
+template <typename real>
+hipError_t launch_vjp_reduce(const VjpArgs &a, const real *partial, int n_inst,
+                             hipStream_t st);
+
+// ---------------------------------------------------------------- network
+struct MadeInst {
+  int32_t n, H;             // |W|, hidden width
+  int32_t L;                // lanes per sample in the sampler
+  int32_t pad;
+  int64_t param_off;        // offset of the instance's parameters
+  int64_t sample_off;       // first global sample
+  int64_t B;                // samples
+  int64_t spin_off;         // first spin
+};
+
+template <typename real>
+struct SampleArgs {
+  const MadeInst *mi;
+  const float *params;
+  const float *uniforms;        // null => Philox
+  const int32_t *blk_inst;      // block -> instance
+  const int32_t *blk_start;     // block -> first local sample
+  int8_t *spins;
+  real *logq;
+  uint64_t seed;
+  const int32_t *step_ctr;      // per instance (device), Philox counter word 2
+  int32_t spb;                  // samples per block (256 / L)
+};
+template <typename real>
+hipError_t launch_sample(const SampleArgs<real> &a, int n_blocks, hipStream_t st);
+
+// Per-sample rows of the log-prob pass and the REINFORCE backward.
+template <typename real>
+struct RowArgs {
+  MadeInst mi;
+  const float *params;
+  const int8_t *spins;
+  const real *wts;         // REINFORCE weight per sample (global index)
+  real *hid;               // [B, H]
+  real *da;                // [B, H]
+  real *dlogit;            // [B, n]
+  real *sf;                // [B, n] spins as real
+};
+template <typename real>
+hipError_t launch_rows(const RowArgs<real> &a, hipStream_t st);
+
+// C[M, N] (+)= X^T Y over the batch; X [B, ldx] column offset, Y likewise.
+template <typename real>
+hipError_t launch_atb(const real *X, int ldx, const real *Y, int ldy, int64_t B,
+                      int M, int N, real *part, int ksplit, float *out,
+                      int ldo, int mask_kind, int nW, hipStream_t st);
+template <typename real>
+hipError_t launch_colsum(const real *X, int ldx, int64_t B, int M, real *part,
+                         int ksplit, float *out, hipStream_t st);
+
+// Free energy statistics and REINFORCE weights for one instance.
+template <typename real>
+struct FreeArgs {
+  const int8_t *spins;       // instance base
+  const double *logz;        // instance base
+  const real *logq;          // instance base
+  const int32_t *ww_a, *ww_b;
+  const double *ww_J;
+  const double *hW;
+  int32_t n_ww, nw;
+  int64_t B;
+  double beta;
+  double *f;                 // scratch [B]
+  real *wts;                 // out [B]
+  double *stats;             // out [4]
+};
+template <typename real>
+hipError_t launch_free(const FreeArgs<real> &a, hipStream_t st);
+
+hipError_t launch_adam(float *params, const float *grad, float *m, float *v,
+                       int64_t n, float lr, int32_t *step_ctr, hipStream_t st);
+hipError_t launch_bump(int32_t *step_ctr, int n, hipStream_t st);
+
+}  // namespace tnvan

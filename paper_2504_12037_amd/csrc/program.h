@@ -1,0 +1,91 @@
+// Compiled contraction program of one or more disorder instances.
+//
+// The conditional partition function of the remainder R (Sec. 2, Eqs. 3-4)
+// is contracted by eliminating R group by group along the given order.  A
+// step eliminates a group G of consecutive order positions and produces a
+// message over the scope S_out (the not-yet-eliminated R vertices it still
+// touches).  Per sample s_W the step computes
+//
+//   out[o] = sum_x T[x, o] * d[x] * prod_k m_k[idx_k(o, x)]
+//
+// where x runs over the 2^g states of G, o over the 2^w states of S_out,
+// T is the static product of the Boltzmann matrices (Eq. 2) of the R-R
+// edges the step consumes (normalised so that every factor is <= 1), d is
+// the product of the per-sample unary factors of G (the W-R couplings act on
+// R as fields, the "extra interaction" of Sec. 2) and m_k are the messages of
+// earlier steps whose scope meets G.
+//
+// Bit conventions: a message entry index has bit b set when the b-th vertex
+// of its scope has spin -1; the combined step index is (x << w) | o.
+//
+// This header is shared by the host compiler and the device kernels only.
+#pragma once
+#include <stdint.h>
+
+namespace tnvan {
+
+enum StepKind : int32_t {
+  // at most one input message and its scope is exactly G (same bit order);
+  // out = A . T with A[x] = d[x] m[x]: a dense batched product
+  STEP_DENSE = 0,
+  // g == 1 with any inputs: gather-product per output entry
+  STEP_SINGLE = 1,
+};
+
+constexpr int kMaxScope = 16;   // bits of any message / input scope
+constexpr int kMaxW = 14;       // output scope bits
+constexpr int kMaxG = 8;        // group size
+constexpr int kMaxInputs = 24;
+
+struct StepDesc {
+  int32_t kind;
+  int32_t g;          // group size
+  int32_t gpos;       // first order position of the group
+  int32_t w;          // output scope size (0: the step closes a component)
+  int32_t n_in;       // number of input messages
+  int32_t in_off;     // index of the first InputDesc
+  int64_t t_off;      // offset of T (2^(g+w) entries, index (x << w) | o)
+  int32_t off_all;    // arena offset of the output (every message kept)
+  int32_t off_fwd;    // arena offset of the output (liveness reuse)
+  int32_t n_edge;     // R-R edges folded into T
+  int32_t edge_off;   // index of the first EdgeDesc
+};
+
+struct InputDesc {
+  int32_t step;       // producing step (local index within the instance)
+  int32_t nbits;      // scope size of the message
+  int32_t xbit;       // SINGLE: bit of the eliminated vertex in this scope
+  int32_t pad;
+  int8_t src[kMaxScope];  // scope bit b -> o-bit index, or -1 for x (SINGLE)
+};
+
+struct EdgeDesc {
+  int32_t rr;         // local index of the edge among the instance's R-R edges
+  int32_t bu;         // combined-index bit of one endpoint (x bits at w..)
+  int32_t bv;         // combined-index bit of the other endpoint
+  int32_t pad;
+};
+
+// Per-instance view, everything as offsets into the flat device arrays.
+struct InstDesc {
+  int32_t n, n_edges, nw, nr;
+  int32_t n_steps, step_off;     // StepDesc range
+  int32_t fld_off;               // CSR of W-neighbours of R positions
+  int32_t fld_nnz_off;           // offset into fld_w / fld_J
+  int32_t hr_off;                // h on R positions
+  int32_t n_rr, n_wr;            // R-R and W-R edge counts
+  int32_t wr_off;                // WR edge tables (position, w index, edge id)
+  int32_t rr_off;                // RR edge tables (edge id, J)
+  int32_t ww_off, n_ww;          // WW edge tables for E_1
+  int32_t arena_all, arena_fwd;  // arena entries per sample
+  int32_t scr_fwd, scr_bwd;      // scratch entries per sample
+  int32_t max_w;
+  int32_t n_partial;             // nr + n_wr + n_rr
+  int32_t vr_off;                // R position -> vertex id
+  int32_t wv_off;                // W index -> vertex id
+  int32_t pad0;
+  double beta;
+  double log_const;              // sum of beta |J| over R-R edges
+};
+
+}  // namespace tnvan

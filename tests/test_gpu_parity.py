@@ -1,0 +1,171 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances: |logZ_R^gpu - logZ_R^oracle| / N <= 1e-10 (FP64 path) and
+<= 1e-5 (FP32 path) per sample.  The adjoint is a batch sum of marginals
+times beta; its entries are compared with an absolute bound proportional to
+sum_b |g_b| (per-sample marginal error times the number of samples)."""
+
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import ising as OI
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5}
+GTOL = {"fp64": 1e-9, "fp32": 5e-5}
+
+
+def _net(insts, prec, **kw):
+    from paper_2504_12037_amd import Net
+    return Net(insts, precision=prec, **kw)
+
+
+def _oracle_logz(inst, spins):
+    if len(inst.order) <= 16:
+        return OI.logz_r_bruteforce(inst, spins)
+    return OI.logz_r_elimination(inst, spins)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda().reshape(-1)
+
+
+CASES = {
+    "c1": lambda: S.c1_small_lattice(),
+    "c1_single": lambda: S.lattice_column_split(S.lattice_2d(4, seed=1), [2],
+                                                row_groups=False),
+    "c2_b05": lambda: S.c2_lattice(0.5),
+    "c2_b2": lambda: S.c2_lattice(2.0),
+    "c2_single": lambda: S.lattice_column_split(S.lattice_2d(16, seed=2, beta=1.0),
+                                                [6, 11], row_groups=False),
+    "c3_b1": lambda: S.c3_sk(1.0),
+    "c4": lambda: S.c4_rrg(),
+    "rrg20": lambda: S.c4_small_copies()[0],
+    "lat8_field": lambda: S.lattice_column_split(S.lattice_2d(8, seed=9, h_var=0.2),
+                                                 [5]),
+}
+SIZES = {"c1": 1024, "c1_single": 333, "c2_b05": 1037, "c2_b2": 517,
+         "c2_single": 301, "c3_b1": 600, "c4": 300, "rrg20": 257, "lat8_field": 1000}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_logz_parity(case, prec):
+    inst = CASES[case]()
+    B = SIZES[case]
+    print(f"\n[logz] case={case} prec={prec} B={B}", flush=True)
+    spins = S.uniform_spins(B, inst.n_width, 100 + B)
+    net = _net([inst], prec)
+    got = net.logz(_dev(spins), B).cpu().numpy()
+    want = _oracle_logz(inst, spins)
+    err = np.abs(got - want) / inst.n
+    assert err.max() <= TOL[prec], (err.max(), np.argmax(err))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", ["c1", "c1_single", "c2_b2", "c2_single", "c3_b1",
+                                  "rrg20", "c4", "lat8_field"])
+def test_backward_parity(case, prec):
+    inst = CASES[case]()
+    B = {"c4": 48, "c2_b2": 200, "c2_single": 120, "c3_b1": 300}.get(case, 257)
+    print(f"\n[backward] case={case} prec={prec} B={B}", flush=True)
+    spins = S.uniform_spins(B, inst.n_width, 7 + B)
+    g = np.random.default_rng(B).standard_normal(B)
+    net = _net([inst], prec)
+    dh, dJ, db = net.backward(_dev(spins), _dev(g), B)
+    if len(inst.order) <= 16:
+        mag, corr, e2 = OI.marginals_bruteforce(inst, spins)
+        wdh, wdJ, wdb = OI.logz_r_vjp(inst, spins, g, marg=(mag, corr, e2))
+    else:
+        wdh, wdJ, wdb = OI.logz_r_vjp(inst, spins, g)
+    scale = np.abs(g).sum() * max(inst.beta, 1.0)
+    tol = GTOL[prec] * scale
+    np.testing.assert_allclose(dh.cpu().numpy(), wdh, atol=tol, rtol=0)
+    np.testing.assert_allclose(dJ.cpu().numpy(), wdJ, atol=tol, rtol=0)
+    jscale = np.abs(inst.J).sum() + np.abs(inst.h).sum() + 1
+    assert abs(db.cpu().item() - wdb) <= GTOL[prec] * np.abs(g).sum() * jscale
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_logz_full_size_sampled(prec):
+    # the benchmark workload at full batch, in the launch configuration the
+    # benchmark times; 256 sampled outputs checked against the oracle
+    inst = S.c2_lattice(1.0)
+    B = 8192
+    spins = S.uniform_spins(B, inst.n_width, 102)
+    net = _net([inst], prec)
+    got = net.logz(_dev(spins), B).cpu().numpy()
+    idx = np.random.default_rng(0).choice(B, 256, replace=False)
+    want = OI.logz_r_elimination(inst, spins[idx])
+    assert np.abs(got[idx] - want).max() / inst.n <= TOL[prec]
+    # every output: global spin flip symmetry (h = 0) holds at any size
+    got2 = net.logz(_dev(-spins), B).cpu().numpy()
+    assert np.abs(got2 - got).max() / inst.n <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_multi_instance_uneven_batch(prec):
+    insts = [S.c1_small_lattice(), S.c4_small_copies()[1], S.c3_sk(0.5),
+             S.lattice_column_split(S.lattice_2d(8, seed=3), [5])]
+    Bs = [37, 0, 130, 65]
+    spins = [S.uniform_spins(b, i.n_width, 5 + k) for k, (b, i) in enumerate(zip(Bs, insts))]
+    flat = np.concatenate([s.reshape(-1) for s in spins])
+    net = _net(insts, prec)
+    got = net.logz(_dev(flat), Bs).cpu().numpy()
+    off = 0
+    for inst, b, s in zip(insts, Bs, spins):
+        if b:
+            want = _oracle_logz(inst, s)
+            assert np.abs(got[off:off + b] - want).max() / inst.n <= TOL[prec]
+        off += b
+    g = np.random.default_rng(3).standard_normal(sum(Bs))
+    dh, dJ, db = net.backward(_dev(flat), _dev(g), Bs)
+    dh, dJ, db = dh.cpu().numpy(), dJ.cpu().numpy(), db.cpu().numpy()
+    off = hoff = eoff = 0
+    for k, (inst, b, s) in enumerate(zip(insts, Bs, spins)):
+        gk = g[off:off + b]
+        if b:
+            wdh, wdJ, wdb = OI.logz_r_vjp(inst, s, gk)
+        else:
+            wdh, wdJ, wdb = np.zeros(inst.n), np.zeros(inst.n_edges), 0.0
+        tol = GTOL[prec] * (np.abs(gk).sum() + 1) * max(1, inst.beta)
+        np.testing.assert_allclose(dh[hoff:hoff + inst.n], wdh, atol=tol, rtol=0)
+        np.testing.assert_allclose(dJ[eoff:eoff + inst.n_edges], wdJ, atol=tol, rtol=0)
+        off += b
+        hoff += inst.n
+        eoff += inst.n_edges
+
+
+def test_edge_cases():
+    # beta = 0: log Z_R = |R| ln 2 exactly and the adjoint vanishes
+    inst = S.c1_small_lattice().with_beta(0.0)
+    spins = S.uniform_spins(70, 4, 1)
+    net = _net([inst], "fp64")
+    got = net.logz(_dev(spins), 70).cpu().numpy()
+    assert np.abs(got - 12 * np.log(2)).max() < 1e-12
+    dh, dJ, db = net.backward(_dev(spins), _dev(np.ones(70)), 70)
+    assert torch.abs(dh).max().item() < 1e-12 and torch.abs(dJ).max().item() < 1e-12
+    # empty width set: one sample carries the whole partition function
+    base = S.lattice_2d(4, seed=5)
+    full = S.Instance(16, base.edges, base.J, base.h, 0.7, np.zeros(0, np.int32),
+                      np.arange(16, dtype=np.int32))
+    net = _net([full], "fp64")
+    got = net.logz(torch.zeros(0, dtype=torch.int8, device="cuda"), 1).cpu().numpy()
+    assert abs(got[0] - OI.logz_full_bruteforce(full)) < 1e-10
+    # empty remainder: log Z_R = 0
+    allw = S.Instance(16, base.edges, base.J, base.h, 0.7, np.arange(16, dtype=np.int32),
+                      np.zeros(0, np.int32))
+    net = _net([allw], "fp32")
+    got = net.logz(_dev(S.uniform_spins(5, 16, 0)), 5).cpu().numpy()
+    assert np.all(got == 0)
+    # batch of one sample and an empty batch
+    inst = S.c2_lattice(1.0)
+    net = _net([inst], "fp32")
+    sp = S.uniform_spins(1, 32, 3)
+    assert abs(net.logz(_dev(sp), 1).cpu().numpy()[0]
+               - OI.logz_r_elimination(inst, sp)[0]) / 256 < 1e-5
+    out = net.logz(torch.zeros(0, dtype=torch.int8, device="cuda"), 0)
+    assert out.numel() == 0
