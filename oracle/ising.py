@@ -192,18 +192,24 @@ def marginals_bruteforce(inst, spins: np.ndarray):
     pair = np.einsum("ci,ij,cj->c", r, Jrr, r)
     expo = sp.beta * (pair[None, :] + f @ r.T)
     lz = _logsumexp(expo, axis=1)
-    p = np.exp(expo - lz[:, None])                        # [B, C]
-    full = np.zeros((B, r.shape[0], sp.n))
-    for k, v in enumerate(sp.W):
-        full[:, :, v] = s[:, k][:, None]
-    for k, v in enumerate(sp.R):
-        full[:, :, v] = r[None, :, k]
-    mag = np.einsum("bc,bcn->bn", p, full)
-    for v in sp.W:
-        mag[:, v] = 0.0
-    ea, eb = sp.edges[:, 0], sp.edges[:, 1]
-    corr = np.einsum("bc,bce->be", p, full[:, :, ea] * full[:, :, eb])
-    e2 = -np.einsum("bc,bc->b", p, pair[None, :] + f @ r.T)
+    p = np.exp(expo - lz[:, None])                        # [B, C] Boltzmann weights
+    # <r_v> = sum_c p_c r_v(c); <r_a r_b> = sum_c p_c r_a(c) r_b(c); a W spin
+    # is fixed, so its factor comes out of the sum
+    magR = p @ r                                          # [B, nr]
+    mag = np.zeros((B, sp.n))
+    mag[:, sp.R] = magR
+    corr = np.zeros((B, len(sp.edges)))
+    for e in sp.rr:
+        a, b = (pos[int(x)] for x in sp.edges[e])
+        corr[:, e] = p @ (r[:, a] * r[:, b])
+    for e in sp.wr:
+        a, b = (int(x) for x in sp.edges[e])
+        w, v = (a, b) if a in sp.widx else (b, a)
+        corr[:, e] = s[:, sp.widx[w]] * magR[:, pos[v]]
+    for e in sp.ww:
+        a, b = (int(x) for x in sp.edges[e])
+        corr[:, e] = s[:, sp.widx[a]] * s[:, sp.widx[b]]
+    e2 = -(p @ pair) - np.sum(f * magR, axis=1)
     return mag, corr, e2
 
 
