@@ -1,0 +1,209 @@
+"""Benchmark of the TNVAN hot path on one MI355X.
+
+Workload: 16x16 open-boundary Gaussian spin glass (J ~ N(0,1), seed 2, h = 0)
+at beta in {0.5, 1.0, 2.0} (three instances in one net), width set = columns
+6 and 11 (32 spins), remainder = strips 16x5 / 16x4 / 16x5 contracted row by
+row, masked network of hidden width 256, 8192 samples per instance.
+
+One step is one pass of the whole hot path over one batch: ancestral
+sampling (Philox uniforms), the batched conditional log Z, E_1 / F_q / the
+REINFORCE weights in FP64, the log-prob pass and the REINFORCE gradient, the
+Adam update (all inside tnvan_free_energy_step), and the adjoint
+(tnvan_logz_backward with g_b = 1/B, giving magnetisations, correlations and
+internal energy) on the step's samples.  `value` is samples per second of
+that step (3 x 8192 samples per step), inputs resident in HBM.
+
+Also reported: the forward + adjoint alone for the FP32 and the plain FP64
+paths, the error of logZ against the oracle on sampled outputs, a roofline
+line for the dominant kernel and the oracle timed on the host cores.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("conditional logZ samples/s (fwd+adjoint) at |dlogZ|/N<=1e-5 vs plain FP64 path")
+BETAS = (0.5, 1.0, 2.0)
+B = 8192
+HIDDEN = 256
+# algorithmic flops per sample of the 16x16 workload's remainder contraction
+# (pairwise form: per row, one 2x2 mix per vertical bond over the row's 2^w
+# states plus the diagonal horizontal bonds and fields):
+#   forward = 2*(15*(4*5*32 + 32*2) + 32) + (15*(4*4*16 + 16*2) + 16) = 25520
+# and the adjoint twice that, so forward + adjoint = 76560 flops per sample
+FWD_FLOPS = 25520
+FWD_ADJ_FLOPS = 3 * FWD_FLOPS
+PEAK_FP32 = 157.3e12       # MI355X vector FP32 (published)
+PEAK_FP64 = 78.6e12
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-samples", type=int, default=8192)
+    return p.parse_args()
+
+
+def event_time(fn, iters, stream):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(iters):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / iters
+
+
+def cpu_baseline(insts, n_samples):
+    """The oracle (numpy FP64 log-domain elimination and its reverse pass)
+    on a bounded sample of the same workload, on this host's cores."""
+    import synthetic as S
+    from oracle import ising as OI
+    t0 = time.perf_counter()
+    for k, inst in enumerate(insts):
+        spins = S.uniform_spins(n_samples, inst.n_width, 4242 + k)
+        OI.marginals_elimination(inst, spins, chunk=n_samples)
+    dt = time.perf_counter() - t0
+    n_samples *= len(insts)
+    cores = len(os.sched_getaffinity(0))
+    threads = os.environ.get("OMP_NUM_THREADS", "unset")
+    return {"value": n_samples / dt, "unit": "samples/s", "cores": cores,
+            "kind": "oracle",
+            "sample": (f"{n_samples} samples (every beta of the workload), forward + "
+                       f"reverse pass (numpy FP64, BLAS threads OMP_NUM_THREADS="
+                       f"{threads}; elementwise numpy is single-threaded), "
+                       f"{dt:.1f} s")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the batch of samples is independent and would shard by sample, "
+              "but no multi-GPU path is built.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import synthetic as S
+    from oracle import ising as OI
+    from paper_2504_12037_amd import Net
+
+    torch.cuda.set_device(0)
+    st = torch.cuda.current_stream()
+    insts = [S.c2_lattice(b, HIDDEN) for b in BETAS]
+    nI = len(insts)
+    counts = [B] * nI
+    nw = insts[0].n_width
+    net = Net(insts, precision=args.precision, seed=2024)
+    for k in range(nI):
+        net.set_params(k, torch.from_numpy(S.made_init(nw, HIDDEN, 7 + k)))
+    spins = torch.empty(nI * B * nw, dtype=torch.int8, device="cuda")
+    stats = torch.empty(nI, 4, dtype=torch.float64, device="cuda")
+    g = torch.full((nI * B,), 1.0 / B, dtype=torch.float64, device="cuda")
+    dh = torch.empty(sum(i.n for i in insts), dtype=torch.float64, device="cuda")
+    dJ = torch.empty(sum(i.n_edges for i in insts), dtype=torch.float64, device="cuda")
+    db = torch.empty(nI, dtype=torch.float64, device="cuda")
+
+    def step():
+        net.free_energy_step(counts, 1e-3, stats=stats, spins_out=spins)
+        net.backward(spins, g, counts, out=(dh, dJ, db))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(args.steps):
+        step()
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    value = nI * B / (ms / 1e3)
+
+    # forward + adjoint alone, FP32 (or the chosen) path and plain FP64 path
+    sp_fix = torch.from_numpy(S.uniform_spins(nI * B, nw, 102)).cuda().reshape(-1)
+    logz = torch.empty(nI * B, dtype=torch.float64, device="cuda")
+    out = (dh, dJ, db)
+    fa = lambda: (net.logz(sp_fix, counts, out=logz), net.backward(sp_fix, g, counts, out=out))
+    for _ in range(3):
+        fa()
+    t_fa = event_time(fa, max(5, args.steps), st)
+    t_bwd = event_time(lambda: net.backward(sp_fix, g, counts, out=out), max(5, args.steps), st)
+    t_fwd = event_time(lambda: net.logz(sp_fix, counts, out=logz), max(5, args.steps), st)
+    net64 = Net(insts, precision="fp64")
+    logz64 = torch.empty_like(logz)
+    fa64 = lambda: (net64.logz(sp_fix, counts, out=logz64),
+                    net64.backward(sp_fix, g, counts, out=out))
+    for _ in range(3):
+        fa64()
+    t_fa64 = event_time(fa64, max(5, args.steps), st)
+    # error of logZ on sampled outputs against the oracle, and vs FP64 path
+    lz = net.logz(sp_fix, counts).cpu().numpy()
+    lz64 = net64.logz(sp_fix, counts).cpu().numpy()
+    spn = sp_fix.cpu().numpy().reshape(nI * B, nw)
+    idx = np.random.default_rng(1).choice(B, 64, replace=False)
+    err = 0.0
+    for k, inst in enumerate(insts):
+        want = OI.logz_r_elimination(inst, spn[k * B + idx])
+        err = max(err, float(np.abs(lz[k * B + idx] - want).max() / inst.n))
+    err64 = float(np.abs(lz - lz64).max() / insts[0].n)
+
+    # dominant kernel: the fused recompute + adjoint contraction launch
+    achieved = FWD_ADJ_FLOPS * nI * B / t_bwd
+    peak = PEAK_FP64 if args.precision == "fp64" else PEAK_FP32
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "16x16 OBC Gaussian spin glass, W = columns 6,11, "
+                               "beta in {0.5,1,2}, 8192 samples each, MADE H=256",
+                   "global_batch": nI * B, "instances": nI, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "kernel": "contract_kernel (recompute + adjoint)",
+                     "kernel_avg_s": t_bwd},
+        "breakdown": {
+            "fwd_adj_samples_per_s": nI * B / t_fa,
+            "fwd_adj_fp64_path_samples_per_s": nI * B / t_fa64,
+            "speedup_vs_fp64_path": t_fa64 / t_fa,
+            "logz_fwd_s": t_fwd, "logz_bwd_s": t_bwd, "fwd_adj_s": t_fa,
+            "fwd_adj_fp64_s": t_fa64,
+            "max_abs_dlogZ_per_N_vs_oracle": err,
+            "max_abs_dlogZ_per_N_vs_fp64_path": err64,
+            "wall_s_timed_region": wall,
+        },
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(insts, args.cpu_samples)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()
