@@ -176,7 +176,7 @@ tnvan_status compile_instance(const tnvan_instance &in, int max_width,
   std::vector<int32_t> consumer;          // consuming step per local step (-1 root)
   double log_const = 0.0;
   int64_t flops = 0;
-  int max_w = 0, scr_fwd = 0, scr_bwd = 0;
+  int max_w = 0, scr_fwd = 0, scr_bwd = 0, pbuf = 0;
   const int ngroups = (int)gp.size() - 1;
   for (int k = 0; k < ngroups; ++k) {
     const int gs = gp[k], ge = gp[k + 1], g = ge - gs;
@@ -271,6 +271,7 @@ tnvan_status compile_instance(const tnvan_instance &in, int max_width,
     if (sd.kind == STEP_DENSE) {
       scr_fwd = std::max(scr_fwd, 1 << g);
       scr_bwd = std::max(scr_bwd, (1 << g) * (w + 2));
+      pbuf = std::max(pbuf, (1 << g) * (w + 1));
       flops += 2 * nT + (int64_t)(g + (sd.n_in ? 1 : 0)) * (1 << g);
     } else {
       scr_bwd = std::max(scr_bwd, 2 << w);
@@ -283,6 +284,7 @@ tnvan_status compile_instance(const tnvan_instance &in, int max_width,
   D.max_w = max_w;
   D.scr_fwd = scr_fwd;
   D.scr_bwd = scr_bwd;
+  D.pbuf = pbuf;
   // arenas
   {
     int32_t off = 0;

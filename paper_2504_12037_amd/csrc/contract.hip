@@ -60,7 +60,7 @@ template <> struct FBits<double> {
 };
 
 struct Layout {
-  size_t mx, phi, fab, gs, M, C, red, res, arena, scr, end;
+  size_t mx, phi, fab, gs, M, C, red, res, pb, arena, scr, end;
 };
 
 __host__ __device__ inline size_t al8(size_t x) { return (x + 7) & ~(size_t)7; }
@@ -79,6 +79,7 @@ __host__ __device__ inline Layout make_layout(const InstDesc &D, int S, bool bwd
     L.C = o;   o = al8(o + (size_t)D.n_rr * rs);
     L.red = o; o = al8(o + (size_t)kWaves * kRed * S * rs);
     L.res = o; o = al8(o + (size_t)kRed * S * rs);
+    L.pb = o;  o = al8(o + (size_t)D.pbuf * rs);
   }
   if (!global_arena) {
     L.arena = o; o = al8(o + (size_t)(bwd ? D.arena_all : D.arena_fwd) * S * rs);
@@ -183,6 +184,7 @@ __global__ __launch_bounds__(kThreads) void contract_kernel(ContractArgs<real> a
       for (int i = tid; i < (S << w); i += kThreads) {
         const int o = i >> logS;
         real acc = 0;
+#pragma unroll 8
         for (int x = 0; x < nx; ++x) acc += Tt[(x << w) | o] * scr[x * S + sme];
         arena[(off + o) * S + sme] = acc;
         lmax = acc > lmax ? acc : lmax;
@@ -232,6 +234,7 @@ __global__ __launch_bounds__(kThreads) void contract_kernel(ContractArgs<real> a
   real *Cw = reinterpret_cast<real *>(smem + Lo.C);
   real *red = reinterpret_cast<real *>(smem + Lo.red);
   real *res = reinterpret_cast<real *>(smem + Lo.res);
+  real *pb = reinterpret_cast<real *>(smem + Lo.pb);
   for (int s = tid; s < S; s += kThreads)
     gs[s] = s < nb ? (real)a.grad[a.inst_sample_off[q] + b0 + s] : (real)0;
   for (int k = tid; k < D.n_rr; k += kThreads) Cw[k] = 0;
@@ -271,6 +274,7 @@ __global__ __launch_bounds__(kThreads) void contract_kernel(ContractArgs<real> a
 #pragma unroll
         for (int j = 0; j < kMaxW; ++j) lj[j] = 0;
         const int no = 1 << w;
+#pragma unroll 4
         for (int o = 0; o < no; ++o) {
           const real tr = Tt[(x << w) | o] * rfac(o);
           lam += tr;
@@ -304,23 +308,25 @@ __global__ __launch_bounds__(kThreads) void contract_kernel(ContractArgs<real> a
         }
         Mg[(sd.gpos + j) * S + s] = m;
       }
-      // gradient-weighted correlations of the R-R edges folded into T
+      // gradient-weighted correlations of the R-R edges folded into T:
+      // per group state x, P[x][j] = sum_s g_s A_s[x] Lambda_{s,j}[x]
+      for (int i = tid; i < nx * (w + 1); i += kThreads) {
+        const int x = i / (w + 1), j = i - x * (w + 1);
+        real acc = 0;
+        for (int s = 0; s < S; ++s) acc += gs[s] * sA[x * S + s] * sL[(x * (w + 1) + j) * S + s];
+        pb[i] = acc;
+      }
+      __syncthreads();
       for (int k = tid; k < sd.n_edge; k += kThreads) {
         const EdgeDesc ed = a.edges[sd.edge_off + k];
         const int ju = ed.bu - w;
         const bool vin = ed.bv >= w;
         const int jv = vin ? ed.bv - w : ed.bv;
         real acc = 0;
-        for (int s = 0; s < S; ++s) {
-          real cs = 0;
-          for (int x = 0; x < nx; ++x) {
-            const real l = vin ? (((x >> jv) & 1) ? -sL[(x * (w + 1) + w) * S + s]
-                                                  : sL[(x * (w + 1) + w) * S + s])
-                               : sL[(x * (w + 1) + jv) * S + s];
-            const real c = sA[x * S + s] * l;
-            cs += ((x >> ju) & 1) ? -c : c;
-          }
-          acc += gs[s] * cs;
+        for (int x = 0; x < nx; ++x) {
+          real c = vin ? (((x >> jv) & 1) ? -pb[x * (w + 1) + w] : pb[x * (w + 1) + w])
+                       : pb[x * (w + 1) + jv];
+          acc += ((x >> ju) & 1) ? -c : c;
         }
         Cw[ed.rr] = acc;
       }

@@ -83,7 +83,7 @@ struct InstDesc {
   int32_t n_partial;             // nr + n_wr + n_rr
   int32_t vr_off;                // R position -> vertex id
   int32_t wv_off;                // W index -> vertex id
-  int32_t pad0;
+  int32_t pbuf;                  // adjoint: per-state edge partial sums
   double beta;
   double log_const;              // sum of beta |J| over R-R edges
 };
