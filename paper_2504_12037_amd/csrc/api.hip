@@ -106,6 +106,14 @@ struct tnvan_net {
   // workspaces
   DBuf garena, partial, w_logz, w_logq, w_spins, w_f, w_wts, w_hid, w_da, w_dlogit, w_sf,
       w_part;
+  // transfer-matrix form (chain kernels, FP32 / BF16 precisions)
+  std::vector<int32_t> use_chain;
+  DBuf cinst, chains, csteps, Tp, Tt, Tb, fld_wr, fld_J32, hR32;
+  int kseg = 1;
+  int32_t wlds_fwd = 0, wlds_bwd = 0;
+  DBuf task_inst, task_chain, task_start, cpart_off, chain_list, cpart;
+  int n_tasks = 0, n_chain_insts = 0;
+  std::vector<int64_t> ckey;
   int rs() const { return precision == TNVAN_FP64 ? 8 : 4; }
 };
 
@@ -120,27 +128,25 @@ void choose_tiles(tnvan_net *net, bool bwd) {
   int maxlds = 65536;
   hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   const size_t budget = std::min<size_t>((size_t)maxlds, 80 * 1024);
+  // instances in transfer-matrix form run in the chain kernels instead
+  auto worst_of = [&](int S, bool glob) {
+    size_t worst = 0;
+    for (size_t q = 0; q < net->P.insts.size(); ++q)
+      if (!net->use_chain[q])
+        worst = std::max(worst, contract_lds_bytes(net->P.insts[q], S, bwd, glob, net->rs()));
+    return worst;
+  };
   int S = 64;
   bool glob = false;
-  for (; S >= 1; S >>= 1) {
-    size_t worst = 0;
-    for (auto &D : net->P.insts)
-      worst = std::max(worst, contract_lds_bytes(D, S, bwd, false, net->rs()));
-    if (worst <= budget) break;
-  }
+  for (; S >= 1; S >>= 1)
+    if (worst_of(S, false) <= budget) break;
   if (S < 4) {
     glob = true;
-    for (S = 64; S >= 1; S >>= 1) {
-      size_t worst = 0;
-      for (auto &D : net->P.insts)
-        worst = std::max(worst, contract_lds_bytes(D, S, bwd, true, net->rs()));
-      if (worst <= budget && S <= 16) break;
-    }
+    for (S = 64; S >= 1; S >>= 1)
+      if (worst_of(S, true) <= budget && S <= 16) break;
     if (S < 1) S = 1;
   }
-  size_t worst = 0;
-  for (auto &D : net->P.insts)
-    worst = std::max(worst, contract_lds_bytes(D, S, bwd, glob, net->rs()));
+  const size_t worst = worst_of(S, glob);
   if (bwd) { net->S_bwd = S; net->glob_bwd = glob; net->lds_bwd = worst; }
   else { net->S_fwd = S; net->glob_fwd = glob; net->lds_fwd = worst; }
 }
@@ -175,6 +181,7 @@ tnvan_status set_batch(tnvan_net *net, const int64_t *n_samples) {
   net->tc_fwd.key.clear();
   net->tc_bwd.key.clear();
   net->skey.clear();
+  net->ckey.clear();
   return TNVAN_OK;
 }
 
@@ -186,8 +193,12 @@ tnvan_status ensure_tiles(tnvan_net *net, TileCache &tc, int S, bool bwd) {
   for (int q = 0; q < net->n_inst; ++q) {
     first[q] = (int32_t)ti.size();
     const int64_t B = net->nkey[q];
-    for (int64_t b = 0; b < B; b += S) { ti.push_back(q); ts.push_back((int32_t)b); }
-    cnt[q] = (int32_t)ti.size() - first[q];
+    if (net->use_chain[q]) {
+      cnt[q] = (int32_t)((B + 15) / 16);        // one partial row per 16 samples
+    } else {
+      for (int64_t b = 0; b < B; b += S) { ti.push_back(q); ts.push_back((int32_t)b); }
+      cnt[q] = (int32_t)ti.size() - first[q];
+    }
     poff[q] = ptot;
     if (bwd) ptot += (int64_t)cnt[q] * net->P.insts[q].n_partial;
   }
@@ -203,6 +214,66 @@ tnvan_status ensure_tiles(tnvan_net *net, TileCache &tc, int S, bool bwd) {
   tc.S = S;
   tc.key = net->nkey;
   return TNVAN_OK;
+}
+
+tnvan_status ensure_chain_tasks(tnvan_net *net) {
+  if (net->ckey == net->nkey) return TNVAN_OK;
+  std::vector<int32_t> ti, tc, ts, clist;
+  std::vector<int64_t> coff(net->n_inst, 0);
+  int64_t ctot = 0;
+  for (int q = 0; q < net->n_inst; ++q) {
+    if (!net->use_chain[q]) continue;
+    clist.push_back(q);
+    coff[q] = ctot;
+    const int nc = net->P.cinst[q].n_chains;
+    const int64_t B = net->nkey[q];
+    ctot += (int64_t)nc * B;
+    for (int64_t b = 0; b < B; b += 16)
+      for (int c = 0; c < nc; ++c) { ti.push_back(q); tc.push_back(c); ts.push_back((int32_t)b); }
+  }
+  HIPCHK(upload(net->task_inst, ti));
+  HIPCHK(upload(net->task_chain, tc));
+  HIPCHK(upload(net->task_start, ts));
+  HIPCHK(upload(net->cpart_off, coff));
+  HIPCHK(upload(net->chain_list, clist));
+  HIPCHK(net->cpart.ensure(std::max<int64_t>(1, ctot) * sizeof(double)));
+  net->n_tasks = (int)ti.size();
+  net->n_chain_insts = (int)clist.size();
+  net->ckey = net->nkey;
+  return TNVAN_OK;
+}
+
+ChainArgs chain_args(tnvan_net *net) {
+  ChainArgs a{};
+  a.inst = net->inst.as<InstDesc>();
+  a.cinst = net->cinst.as<ChainInst>();
+  a.chains = net->chains.as<ChainDesc>();
+  a.csteps = net->csteps.as<ChainStep>();
+  a.edges = net->edges.as<EdgeDesc>();
+  a.Tp = net->Tp.as<float>();
+  a.Tt = net->Tt.as<float>();
+  a.Tb = net->Tb.as<uint16_t>();
+  a.fld_ptr = net->fld_ptr.as<int32_t>();
+  a.fld_w = net->fld_w.as<int32_t>();
+  a.fld_wr = net->fld_wr.as<int32_t>();
+  a.fld_J = net->fld_J32.as<float>();
+  a.hR = net->hR32.as<float>();
+  a.task_inst = net->task_inst.as<int32_t>();
+  a.task_chain = net->task_chain.as<int32_t>();
+  a.task_start = net->task_start.as<int32_t>();
+  a.n_tasks = net->n_tasks;
+  a.kseg = net->kseg;
+  a.inst_B = net->d_B.as<int64_t>();
+  a.inst_sample_off = net->d_sample_off.as<int64_t>();
+  a.inst_spin_off = net->d_spin_off.as<int64_t>();
+  a.cpart_off = net->cpart_off.as<int64_t>();
+  a.cpart = net->cpart.as<double>();
+  a.bf16 = net->precision == TNVAN_BF16 ? 1 : 0;
+  int kb = 16;
+  for (int q = 0; q < net->n_inst; ++q)
+    if (net->use_chain[q]) kb = std::max(kb, (int)net->P.cinst[q].kbuf);
+  a.ntm = kb / 16;
+  return a;
 }
 
 template <typename real>
@@ -246,6 +317,18 @@ tnvan_status run_logz(tnvan_net *net, const int8_t *spins, double *logz, hipStre
     a.garena_stride = per;
   }
   HIPCHK(launch_contract<real>(a, net->tc_fwd.n_tiles, net->lds_fwd, false, net->glob_fwd, st));
+  if (std::count(net->use_chain.begin(), net->use_chain.end(), 1)) {
+    s = ensure_chain_tasks(net);
+    if (s) return s;
+    ChainArgs c = chain_args(net);
+    c.spins = spins;
+    c.wave_lds = net->wlds_fwd;
+    HIPCHK(launch_chain(c, false, st));
+    HIPCHK(launch_chain_sum(net->inst.as<InstDesc>(), net->cinst.as<ChainInst>(),
+                            net->chain_list.as<int32_t>(), net->n_chain_insts,
+                            net->d_B.as<int64_t>(), net->d_sample_off.as<int64_t>(),
+                            net->cpart_off.as<int64_t>(), net->cpart.as<double>(), logz, st));
+  }
   return TNVAN_OK;
 }
 
@@ -268,6 +351,17 @@ tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *gra
     a.garena_stride = per;
   }
   HIPCHK(launch_contract<real>(a, tc.n_tiles, net->lds_bwd, true, net->glob_bwd, st));
+  if (std::count(net->use_chain.begin(), net->use_chain.end(), 1)) {
+    s = ensure_chain_tasks(net);
+    if (s) return s;
+    ChainArgs c = chain_args(net);
+    c.spins = spins;
+    c.grad = grad;
+    c.partial = reinterpret_cast<float *>(net->partial.p);
+    c.inst_partial_off = tc.partial_off.as<int64_t>();
+    c.wave_lds = net->wlds_bwd;
+    HIPCHK(launch_chain(c, true, st));
+  }
   int64_t nh = 0, ne = 0;
   for (auto &D : net->P.insts) { nh += D.n; ne += D.n_edges; }
   HIPCHK(zero_doubles(dh, nh, st));
@@ -476,6 +570,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   hipError_t e;
   HostProgram &P = net->P;
 #define UP(buf, vec) if ((e = upload(net->buf, vec)) != hipSuccess) return fail(e, #buf);
+#define UP2(buf, vec) if ((e = upload(net->buf, vec)) != hipSuccess) return fail(e, #buf);
   UP(inst, P.insts) UP(steps, P.steps) UP(inputs, P.inputs) UP(edges, P.edges)
   UP(fld_ptr, P.fld_ptr) UP(fld_w, P.fld_w) UP(wr_pos, P.wr_pos) UP(wr_w, P.wr_w)
   UP(rr_edge, P.rr_edge) UP(rr_J, P.rr_J) UP(wr_edge, P.wr_edge) UP(wr_J, P.wr_J)
@@ -495,7 +590,6 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
     UP(d_spin_base, sb) UP(d_edge_base, eb)
   }
   UP(d_mi, net->mi)
-#undef UP
   const size_t pb = std::max<int64_t>(1, net->param_total) * sizeof(float);
   if ((e = net->params.ensure(pb)) || (e = net->adam_m.ensure(pb)) || (e = net->adam_v.ensure(pb)) ||
       (e = net->grad.ensure(pb)) || (e = net->step_ctr.ensure(sizeof(int32_t) * n_inst)))
@@ -504,8 +598,31 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
       (e = hipMemset(net->adam_v.p, 0, pb)) || (e = hipMemset(net->grad.p, 0, pb)) ||
       (e = hipMemset(net->step_ctr.p, 0, sizeof(int32_t) * n_inst)))
     return fail(e, "parameter init");
+  {
+    std::vector<float> fj(P.fld_J.begin(), P.fld_J.end()), hr(P.hR.begin(), P.hR.end());
+    UP2(fld_J32, fj) UP2(hR32, hr) UP2(fld_wr, P.fld_wr) UP2(cinst, P.cinst)
+    UP2(chains, P.chains) UP2(csteps, P.csteps) UP2(Tp, P.Tp) UP2(Tt, P.Tt) UP2(Tb, P.Tb)
+  }
+  net->use_chain.assign(n_inst, 0);
+  {
+    int kseg = 1;
+    for (int q = 0; q < n_inst; ++q)
+      if (P.cinst[q].ok) kseg = std::max(kseg, chain_kseg(P.cinst[q]));
+    net->kseg = kseg;
+    for (int q = 0; q < n_inst; ++q) {
+      const ChainInst &C = P.cinst[q];
+      if (net->precision == TNVAN_FP64 || !C.ok) continue;
+      const size_t wf = chain_wave_lds(C, false, kseg), wb = chain_wave_lds(C, true, kseg);
+      if (wb > 160 * 1024) continue;
+      net->use_chain[q] = 1;
+      net->wlds_fwd = std::max<int32_t>(net->wlds_fwd, (int32_t)wf);
+      net->wlds_bwd = std::max<int32_t>(net->wlds_bwd, (int32_t)wb);
+    }
+  }
   choose_tiles(net, false);
   choose_tiles(net, true);
+#undef UP
+#undef UP2
   *out = net;
   return TNVAN_OK;
 }
@@ -520,7 +637,10 @@ void tnvan_free_network(tnvan_net *net) {
                  &net->d_spin_off, &net->d_spin_base, &net->d_edge_base, &net->blk_inst,
                  &net->blk_start, &net->garena, &net->partial, &net->w_logz, &net->w_logq,
                  &net->w_spins, &net->w_f, &net->w_wts, &net->w_hid, &net->w_da,
-                 &net->w_dlogit, &net->w_sf, &net->w_part};
+                 &net->w_dlogit, &net->w_sf, &net->w_part, &net->cinst, &net->chains,
+                 &net->csteps, &net->Tp, &net->Tt, &net->Tb, &net->fld_wr, &net->fld_J32,
+                 &net->hR32, &net->task_inst, &net->task_chain, &net->task_start,
+                 &net->cpart_off, &net->chain_list, &net->cpart};
   for (DBuf *b : all) b->release();
   TileCache *tcs[] = {&net->tc_fwd, &net->tc_bwd};
   for (TileCache *tc : tcs) {

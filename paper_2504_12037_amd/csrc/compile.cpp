@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <map>
 #include <set>
 #include <utility>
@@ -59,6 +60,110 @@ bool fail(std::string &msg, const char *fmt, long a = 0, long b = 0) {
   snprintf(buf, sizeof buf, fmt, a, b);
   msg = buf;
   return false;
+}
+
+// Round-to-nearest-even float -> bfloat16 bits.
+uint16_t to_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// Recognise the transfer-matrix form (see program.h) and emit padded tables.
+void build_chains(const InstDesc &D, const std::vector<int32_t> &consumer, HostProgram &P) {
+  ChainInst ci{};
+  ci.chain_off = (int32_t)P.chains.size();
+  const StepDesc *st = P.steps.data() + D.step_off;
+  bool ok = D.n_steps > 0;
+  for (int t = 0; t < D.n_steps && ok; ++t) {
+    if (st[t].kind != STEP_DENSE || st[t].g > 8 || st[t].w > 8) ok = false;
+    if (st[t].w > 0 && consumer[t] < 0) ok = false;
+  }
+  std::vector<std::vector<int32_t>> chains;
+  if (ok) {
+    std::vector<int32_t> seen(D.n_steps, 0);
+    for (int t0 = 0; t0 < D.n_steps && ok; ++t0) {
+      if (st[t0].n_in != 0) continue;
+      std::vector<int32_t> ch;
+      int t = t0;
+      while (true) {
+        if (seen[t]) { ok = false; break; }
+        seen[t] = 1;
+        ch.push_back(t);
+        if (st[t].w == 0) break;
+        const int nx = consumer[t];
+        const InputDesc &id = P.inputs[st[nx].in_off];
+        if (st[nx].n_in != 1 || id.step != t || st[nx].g != st[t].w) { ok = false; break; }
+        t = nx;
+      }
+      if (!ok) break;
+      // the chain's positions must be one contiguous range
+      int lo = st[ch[0]].gpos, hi = lo;
+      for (int u : ch) {
+        if (st[u].gpos != hi) ok = false;
+        hi = st[u].gpos + st[u].g;
+      }
+      chains.push_back(ch);
+    }
+    for (int t = 0; t < D.n_steps; ++t) if (!seen[t]) ok = false;
+  }
+  if (!ok) {
+    ci.ok = 0;
+    P.cinst.push_back(ci);
+    return;
+  }
+  ci.ok = 1;
+  ci.n_chains = (int32_t)chains.size();
+  for (auto &ch : chains) {
+    ChainDesc cd{};
+    cd.n_steps = (int32_t)ch.size();
+    cd.cs_off = (int32_t)P.csteps.size();
+    cd.pos_lo = st[ch.front()].gpos;
+    cd.pos_hi = st[ch.back()].gpos + st[ch.back()].g;
+    ci.npos_max = std::max(ci.npos_max, cd.pos_hi - cd.pos_lo);
+    ci.max_steps = std::max(ci.max_steps, cd.n_steps);
+    for (int t : ch) {
+      const StepDesc &sd = st[t];
+      ChainStep cs{};
+      cs.step = t;
+      cs.g = sd.g; cs.w = sd.w; cs.gpos = sd.gpos;
+      const int K = 1 << sd.g, N = 1 << sd.w;
+      cs.kp = std::max(16, K);
+      cs.kb = std::max(32, K);
+      cs.np = sd.w == 0 ? 1 : std::max(16, N);
+      cs.n_edge = sd.n_edge;
+      cs.edge_off = sd.edge_off;
+      ci.kbuf = std::max({ci.kbuf, cs.kb, cs.np});
+      ci.gmax = std::max(ci.gmax, sd.g);
+      ci.pmax = std::max(ci.pmax, cs.kp * (sd.w + 1));
+      const double *T = P.T.data() + sd.t_off;
+      cs.tp_off = (int64_t)P.Tp.size();
+      for (int x = 0; x < cs.kp; ++x)
+        for (int o = 0; o < cs.np; ++o)
+          P.Tp.push_back((x < K && o < N) ? (float)T[((int64_t)x << sd.w) | o] : 0.0f);
+      cs.tt_off = (int64_t)P.Tt.size();
+      for (int o = 0; o < cs.np; ++o)
+        for (int x = 0; x < cs.kp; ++x)
+          P.Tt.push_back((x < K && o < N) ? (float)T[((int64_t)x << sd.w) | o] : 0.0f);
+      cs.tb_off = (int64_t)P.Tb.size();
+      if (sd.w > 0) {
+        const int KC = cs.kb / 32, NT = cs.np / 16;
+        for (int nt = 0; nt < NT; ++nt)
+          for (int kc = 0; kc < KC; ++kc)
+            for (int l = 0; l < 64; ++l)
+              for (int i = 0; i < 8; ++i) {
+                const int x = 32 * kc + 8 * (l / 16) + i, o = 16 * nt + l % 16;
+                const float v = (x < K && o < N) ? (float)T[((int64_t)x << sd.w) | o] : 0.0f;
+                P.Tb.push_back(to_bf16(v));
+              }
+      }
+      P.csteps.push_back(cs);
+    }
+    P.chains.push_back(cd);
+  }
+  P.cinst.push_back(ci);
 }
 
 }  // namespace
@@ -121,6 +226,7 @@ tnvan_status compile_instance(const tnvan_instance &in, int max_width,
   std::set<std::pair<int, int>> seen;
   std::vector<std::vector<std::pair<int32_t, int32_t>>> radj(nr);   // (nbr pos, rr idx)
   std::vector<std::vector<std::pair<int32_t, double>>> fld(nr);     // (w idx, J)
+  std::vector<std::vector<int32_t>> fldk(nr);                        // W-R edge index
   D.ww_off = (int32_t)P.ww_a.size();
   D.wr_off = (int32_t)P.wr_pos.size();
   D.rr_off = (int32_t)P.rr_edge.size();
@@ -140,6 +246,7 @@ tnvan_status compile_instance(const tnvan_instance &in, int max_width,
       P.wr_pos.push_back(pos[r]); P.wr_w.push_back(widx[w]);
       P.wr_edge.push_back(e); P.wr_J.push_back(J);
       fld[pos[r]].push_back({widx[w], J});
+      fldk[pos[r]].push_back((int32_t)P.wr_pos.size() - 1 - D.wr_off);
     } else {
       P.rr_edge.push_back(e); P.rr_J.push_back(J); rrJ.push_back(J);
       radj[pos[a]].push_back({pos[b], n_rr});
@@ -158,7 +265,10 @@ tnvan_status compile_instance(const tnvan_instance &in, int max_width,
     int32_t c = 0;
     for (int p = 0; p < nr; ++p) {
       P.fld_ptr.push_back(c);
-      for (auto &pr : fld[p]) { P.fld_w.push_back(pr.first); P.fld_J.push_back(pr.second); ++c; }
+      for (size_t k = 0; k < fld[p].size(); ++k) {
+        P.fld_w.push_back(fld[p][k].first); P.fld_J.push_back(fld[p][k].second);
+        P.fld_wr.push_back(fldk[p][k]); ++c;
+      }
     }
     P.fld_ptr.push_back(c);
   }
@@ -305,6 +415,7 @@ tnvan_status compile_instance(const tnvan_instance &in, int max_width,
     D.arena_all = off;
     D.arena_fwd = ar.top;
   }
+  build_chains(D, consumer, P);
   P.insts.push_back(D);
   P.hidden.push_back(in.hidden);
   P.flops_fwd.push_back(flops);

@@ -31,6 +31,13 @@ struct HostProgram {
   std::vector<int32_t> hidden;      // per instance
   std::vector<int64_t> flops_fwd;   // per instance, per sample
   std::vector<int32_t> hw_off;      // per instance offset into hW
+  std::vector<int32_t> fld_wr;      // W-R edge (local index) of each fld entry
+  // transfer-matrix form
+  std::vector<ChainInst> cinst;     // per instance
+  std::vector<ChainDesc> chains;
+  std::vector<ChainStep> csteps;
+  std::vector<float> Tp, Tt;        // padded FP32 tables
+  std::vector<uint16_t> Tb;         // padded BF16 tables (operand order)
 };
 
 // Appends one instance to P.  Returns TNVAN_OK or an error code with msg.

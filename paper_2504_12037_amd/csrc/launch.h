@@ -148,3 +148,42 @@ hipError_t launch_adam(float *params, const float *grad, float *m, float *v,
 hipError_t launch_bump(int32_t *step_ctr, int n, hipStream_t st);
 
 }  // namespace tnvan
+
+namespace tnvan {
+
+// Transfer-matrix (chain) kernels: one wave per (instance, chain, 16 samples).
+struct ChainArgs {
+  const InstDesc *inst;
+  const ChainInst *cinst;
+  const ChainDesc *chains;
+  const ChainStep *csteps;
+  const EdgeDesc *edges;
+  const float *Tp, *Tt;
+  const uint16_t *Tb;
+  const int32_t *fld_ptr, *fld_w, *fld_wr;
+  const float *fld_J, *hR;
+  const int32_t *task_inst, *task_chain, *task_start;
+  int32_t n_tasks;
+  int32_t kseg;                     // checkpoint interval of the adjoint
+  const int64_t *inst_B, *inst_sample_off, *inst_spin_off;
+  const int64_t *cpart_off;         // per instance: chain-partial logZ offset
+  const int8_t *spins;
+  double *cpart;                    // [chain][B] per instance
+  const double *grad;
+  float *partial;                   // adjoint partial rows
+  const int64_t *inst_partial_off;
+  int32_t wave_lds;                 // bytes of LDS per wave
+  int32_t bf16;
+  int32_t ntm;                      // largest K or N of the launch in 16-wide tiles
+};
+size_t chain_wave_lds(const ChainInst &C, bool bwd, int kseg);
+int chain_kseg(const ChainInst &C);
+hipError_t launch_chain(const ChainArgs &a, bool bwd, hipStream_t st);
+// logz[b] = log_const + sum over chains of the per-chain partials
+hipError_t launch_chain_sum(const InstDesc *inst, const ChainInst *cinst,
+                            const int32_t *chain_insts, int n_chain_insts,
+                            const int64_t *inst_B, const int64_t *inst_sample_off,
+                            const int64_t *cpart_off, const double *cpart, double *logz,
+                            hipStream_t st);
+
+}  // namespace tnvan

@@ -88,4 +88,40 @@ struct InstDesc {
   double log_const;              // sum of beta |J| over R-R edges
 };
 
+// ---------------------------------------------------------------------------
+// Transfer-matrix form: when every step is dense and the steps form chains
+// (each step consumes exactly the message of the previous step of its chain,
+// the first one none, the last one closes the chain), a chain is a sequence
+// of batched products [samples x K] . [K x N] with a per-sample diagonal in
+// between.  Lattice strips eliminated row by row and the two-block SK
+// remainder have this form.  The tables are zero-padded to the matrix-core
+// tile sizes.
+struct ChainStep {
+  int32_t step;       // local step index
+  int32_t g, w, gpos;
+  int32_t kp;         // padded K for FP32 16x16x4 products (>= 16)
+  int32_t kb;         // padded K for BF16 16x16x32 products (>= 32)
+  int32_t np;         // padded N (>= 16), or 1 when the step closes the chain
+  int32_t n_edge, edge_off;
+  int32_t pad;
+  int64_t tp_off;     // FP32 [kp][np]
+  int64_t tt_off;     // FP32 [np][kp] (transposed, for the adjoint)
+  int64_t tb_off;     // BF16 packed in the 16x16x32 operand order
+};
+
+struct ChainDesc {
+  int32_t n_steps, cs_off;   // ChainStep range
+  int32_t pos_lo, pos_hi;    // R positions the chain eliminates
+};
+
+struct ChainInst {
+  int32_t ok;                // instance runs in transfer-matrix form
+  int32_t n_chains, chain_off;
+  int32_t kbuf;              // widest padded K or N of any step
+  int32_t npos_max;          // most positions of one chain
+  int32_t max_steps;         // longest chain
+  int32_t gmax;              // largest group
+  int32_t pmax;              // largest (kp/16... ) edge partial table
+};
+
 }  // namespace tnvan
