@@ -104,15 +104,19 @@ struct tnvan_net {
   int n_sblocks = 0;
   std::vector<int64_t> skey;
   // workspaces
-  DBuf garena, partial, w_logz, w_logq, w_spins, w_f, w_wts, w_hid, w_da, w_dlogit, w_sf,
-      w_part;
+  DBuf garena, partial, w_logz, w_logq, w_spins, w_f, w_fpart, w_hid, w_da, w_dlogit, w_sf,
+      w_part, d_hw_off, d_sum_off, sumP;
+  int64_t sum_total = 0;
+  int max_partial = 0;
+  int sample_reps = 1;
   // transfer-matrix form (chain kernels, FP32 / BF16 precisions)
   std::vector<int32_t> use_chain;
   DBuf cinst, chains, csteps, Tp, Tt, Tb, fld_wr, fld_J32, hR32;
-  int kseg = 1;
-  int32_t wlds_fwd = 0, wlds_bwd = 0;
-  DBuf task_inst, task_chain, task_start, cpart_off, chain_list, cpart;
-  int n_tasks = 0, n_chain_insts = 0;
+  ChainLim lim_fwd{}, lim_bwd{};
+  DBuf Tl, Tbl, cedges, ckpt;
+  DBuf task_inst, task_chain, task_start, btask_inst, btask_chain, btask_start, cpart_off,
+      chain_list, cpart;
+  int n_tasks = 0, n_btasks = 0, n_chain_insts = 0;
   std::vector<int64_t> ckey;
   int rs() const { return precision == TNVAN_FP64 ? 8 : 4; }
 };
@@ -216,63 +220,91 @@ tnvan_status ensure_tiles(tnvan_net *net, TileCache &tc, int S, bool bwd) {
   return TNVAN_OK;
 }
 
+// Workgroup tasks of the chain kernels: (instance, chain, first sample) with
+// 16 samples per wave; the forward and the adjoint use different waves per
+// workgroup, hence two lists.
 tnvan_status ensure_chain_tasks(tnvan_net *net) {
   if (net->ckey == net->nkey) return TNVAN_OK;
-  std::vector<int32_t> ti, tc, ts, clist;
+  std::vector<int32_t> clist;
   std::vector<int64_t> coff(net->n_inst, 0);
   int64_t ctot = 0;
-  for (int q = 0; q < net->n_inst; ++q) {
-    if (!net->use_chain[q]) continue;
-    clist.push_back(q);
-    coff[q] = ctot;
-    const int nc = net->P.cinst[q].n_chains;
-    const int64_t B = net->nkey[q];
-    ctot += (int64_t)nc * B;
-    for (int64_t b = 0; b < B; b += 16)
-      for (int c = 0; c < nc; ++c) { ti.push_back(q); tc.push_back(c); ts.push_back((int32_t)b); }
+  for (int pass = 0; pass < 2; ++pass) {
+    const int per = 16 * (pass ? net->lim_bwd.wpb : net->lim_fwd.wpb);
+    std::vector<int32_t> ti, tc, ts;
+    for (int q = 0; q < net->n_inst; ++q) {
+      if (!net->use_chain[q]) continue;
+      const int nc = net->P.cinst[q].n_chains;
+      const int64_t B = net->nkey[q];
+      if (pass == 0) {
+        clist.push_back(q);
+        coff[q] = ctot;
+        ctot += (int64_t)nc * B;
+      }
+      for (int64_t b = 0; b < B; b += per)
+        for (int c = 0; c < nc; ++c) { ti.push_back(q); tc.push_back(c); ts.push_back((int32_t)b); }
+    }
+    if (pass == 0) {
+      HIPCHK(upload(net->task_inst, ti));
+      HIPCHK(upload(net->task_chain, tc));
+      HIPCHK(upload(net->task_start, ts));
+      net->n_tasks = (int)ti.size();
+    } else {
+      HIPCHK(upload(net->btask_inst, ti));
+      HIPCHK(upload(net->btask_chain, tc));
+      HIPCHK(upload(net->btask_start, ts));
+      net->n_btasks = (int)ti.size();
+    }
   }
-  HIPCHK(upload(net->task_inst, ti));
-  HIPCHK(upload(net->task_chain, tc));
-  HIPCHK(upload(net->task_start, ts));
   HIPCHK(upload(net->cpart_off, coff));
   HIPCHK(upload(net->chain_list, clist));
   HIPCHK(net->cpart.ensure(std::max<int64_t>(1, ctot) * sizeof(double)));
-  net->n_tasks = (int)ti.size();
+  const ChainLim &L = net->lim_bwd;
+  const int64_t ncp = (L.max_steps + L.kseg - 1) / std::max(1, L.kseg);
+  HIPCHK(net->ckpt.ensure(std::max<int64_t>(1, (int64_t)net->n_btasks * L.wpb * ncp * 16 * L.kbuf) *
+                          sizeof(float)));
   net->n_chain_insts = (int)clist.size();
   net->ckey = net->nkey;
   return TNVAN_OK;
 }
 
-ChainArgs chain_args(tnvan_net *net) {
+ChainArgs chain_args(tnvan_net *net, bool bwd) {
   ChainArgs a{};
   a.inst = net->inst.as<InstDesc>();
   a.cinst = net->cinst.as<ChainInst>();
   a.chains = net->chains.as<ChainDesc>();
   a.csteps = net->csteps.as<ChainStep>();
-  a.edges = net->edges.as<EdgeDesc>();
   a.Tp = net->Tp.as<float>();
   a.Tt = net->Tt.as<float>();
   a.Tb = net->Tb.as<uint16_t>();
+  a.Tl = net->Tl.as<float>();
+  a.Tbl = net->Tbl.as<uint16_t>();
+  a.cedges = net->cedges.as<EdgeDesc>();
   a.fld_ptr = net->fld_ptr.as<int32_t>();
   a.fld_w = net->fld_w.as<int32_t>();
   a.fld_wr = net->fld_wr.as<int32_t>();
   a.fld_J = net->fld_J32.as<float>();
   a.hR = net->hR32.as<float>();
-  a.task_inst = net->task_inst.as<int32_t>();
-  a.task_chain = net->task_chain.as<int32_t>();
-  a.task_start = net->task_start.as<int32_t>();
-  a.n_tasks = net->n_tasks;
-  a.kseg = net->kseg;
+  if (bwd) {
+    a.task_inst = net->btask_inst.as<int32_t>();
+    a.task_chain = net->btask_chain.as<int32_t>();
+    a.task_start = net->btask_start.as<int32_t>();
+    a.n_tasks = net->n_btasks;
+    a.lim = net->lim_bwd;
+  } else {
+    a.task_inst = net->task_inst.as<int32_t>();
+    a.task_chain = net->task_chain.as<int32_t>();
+    a.task_start = net->task_start.as<int32_t>();
+    a.n_tasks = net->n_tasks;
+    a.lim = net->lim_fwd;
+  }
   a.inst_B = net->d_B.as<int64_t>();
   a.inst_sample_off = net->d_sample_off.as<int64_t>();
   a.inst_spin_off = net->d_spin_off.as<int64_t>();
   a.cpart_off = net->cpart_off.as<int64_t>();
   a.cpart = net->cpart.as<double>();
-  a.bf16 = net->precision == TNVAN_BF16 ? 1 : 0;
-  int kb = 16;
-  for (int q = 0; q < net->n_inst; ++q)
-    if (net->use_chain[q]) kb = std::max(kb, (int)net->P.cinst[q].kbuf);
-  a.ntm = kb / 16;
+  a.ckpt = net->ckpt.as<float>();
+  a.bf16 = (!bwd && net->precision == TNVAN_BF16) ? 1 : 0;
+  a.ntm = std::max(16, (int)a.lim.kbuf) / 16;
   return a;
 }
 
@@ -320,9 +352,8 @@ tnvan_status run_logz(tnvan_net *net, const int8_t *spins, double *logz, hipStre
   if (std::count(net->use_chain.begin(), net->use_chain.end(), 1)) {
     s = ensure_chain_tasks(net);
     if (s) return s;
-    ChainArgs c = chain_args(net);
+    ChainArgs c = chain_args(net, false);
     c.spins = spins;
-    c.wave_lds = net->wlds_fwd;
     HIPCHK(launch_chain(c, false, st));
     HIPCHK(launch_chain_sum(net->inst.as<InstDesc>(), net->cinst.as<ChainInst>(),
                             net->chain_list.as<int32_t>(), net->n_chain_insts,
@@ -354,12 +385,11 @@ tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *gra
   if (std::count(net->use_chain.begin(), net->use_chain.end(), 1)) {
     s = ensure_chain_tasks(net);
     if (s) return s;
-    ChainArgs c = chain_args(net);
+    ChainArgs c = chain_args(net, true);
     c.spins = spins;
     c.grad = grad;
     c.partial = reinterpret_cast<float *>(net->partial.p);
     c.inst_partial_off = tc.partial_off.as<int64_t>();
-    c.wave_lds = net->wlds_bwd;
     HIPCHK(launch_chain(c, true, st));
   }
   int64_t nh = 0, ne = 0;
@@ -382,7 +412,10 @@ tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *gra
   v.dh = dh;
   v.dJ = dJ;
   v.dbeta = dbeta;
-  HIPCHK(launch_vjp_reduce<real>(v, net->partial.as<real>(), net->n_inst, st));
+  v.inst_sum_off = net->d_sum_off.as<int64_t>();
+  HIPCHK(net->sumP.ensure(std::max<int64_t>(1, net->sum_total) * sizeof(double)));
+  v.sumP = net->sumP.as<double>();
+  HIPCHK(launch_vjp_reduce<real>(v, net->partial.as<real>(), net->n_inst, net->max_partial, st));
   return TNVAN_OK;
 }
 
@@ -390,9 +423,14 @@ tnvan_status ensure_sample_blocks(tnvan_net *net) {
   if (net->skey == net->nkey) return TNVAN_OK;
   net->h_blk_inst.clear();
   net->h_blk_start.clear();
+  const int spb = 256 / net->mi[0].L;
+  int64_t groups = 0;
+  for (int q = 0; q < net->n_inst; ++q) groups += (net->nkey[q] + spb - 1) / spb;
+  // a few rounds per block so that each block stages its parameters once
+  net->sample_reps = (int)std::max<int64_t>(1, (groups + 511) / 512);
+  const int64_t per_block = (int64_t)spb * net->sample_reps;
   for (int q = 0; q < net->n_inst; ++q) {
-    const int spb = 256 / net->mi[q].L;
-    for (int64_t b = 0; b < net->nkey[q]; b += spb) {
+    for (int64_t b = 0; b < net->nkey[q]; b += per_block) {
       net->h_blk_inst.push_back(q);
       net->h_blk_start.push_back((int32_t)b);
     }
@@ -409,8 +447,6 @@ tnvan_status run_sample(tnvan_net *net, const float *uniforms, int8_t *spins, vo
                         hipStream_t st) {
   tnvan_status s = ensure_sample_blocks(net);
   if (s) return s;
-  // all instances share the launch; samples per block follow the smallest L
-  // (each instance's own lane count is used inside its blocks)
   SampleArgs<real> a{};
   a.mi = net->d_mi.as<MadeInst>();
   a.params = net->params.as<float>();
@@ -421,15 +457,11 @@ tnvan_status run_sample(tnvan_net *net, const float *uniforms, int8_t *spins, vo
   a.logq = static_cast<real *>(logq);
   a.seed = net->seed;
   a.step_ctr = net->step_ctr.as<int32_t>();
-  a.spb = 0;
-  // spb differs per instance: launch per group of equal L
-  int minL = 64;
-  for (auto &m : net->mi) minL = std::min(minL, (int)m.L);
-  bool uniformL = true;
-  for (auto &m : net->mi) uniformL &= (m.L == net->mi[0].L);
-  if (!uniformL) return set_err(TNVAN_E_INVALID, "instances need equal sampler lane counts");
-  a.spb = 256 / net->mi[0].L;
-  HIPCHK(launch_sample<real>(a, net->n_sblocks, st));
+  a.spb = 256 / net->mi[0].L;      // every instance uses the same lane count
+  a.reps = net->sample_reps;
+  size_t stage = 0;
+  for (auto &m : net->mi) stage = std::max(stage, made_param_bytes(m.n, m.H));
+  HIPCHK(launch_sample<real>(a, net->n_sblocks, stage, st));
   return TNVAN_OK;
 }
 
@@ -441,33 +473,35 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
   HIPCHK(net->w_logz.ensure(std::max<int64_t>(1, B) * 8));
   HIPCHK(net->w_logq.ensure(std::max<int64_t>(1, B) * sizeof(real)));
   HIPCHK(net->w_f.ensure(std::max<int64_t>(1, B) * 8));
-  HIPCHK(net->w_wts.ensure(std::max<int64_t>(1, B) * sizeof(real)));
   int8_t *spins = spins_out ? spins_out : net->w_spins.as<int8_t>();
   tnvan_status s = run_sample<real>(net, nullptr, spins, net->w_logq.p, st);
   if (s) return s;
   s = run_logz<real>(net, spins, net->w_logz.as<double>(), st);
   if (s) return s;
+  // f_b and the batch statistics of every instance (Eq. 9)
+  int64_t Bmax = 1;
+  for (int q = 0; q < net->n_inst; ++q) Bmax = std::max(Bmax, net->nkey[q]);
+  FreeArgs<real> f{};
+  f.inst = net->inst.as<InstDesc>();
+  f.mi = net->d_mi.as<MadeInst>();
+  f.hw_off = net->d_hw_off.as<int32_t>();
+  f.spins = spins;
+  f.logz = net->w_logz.as<double>();
+  f.logq = net->w_logq.as<real>();
+  f.ww_a = net->ww_a.as<int32_t>();
+  f.ww_b = net->ww_b.as<int32_t>();
+  f.ww_J = net->ww_J.as<double>();
+  f.hW = net->hW.as<double>();
+  f.f = net->w_f.as<double>();
+  f.nblk = (int)std::min<int64_t>(64, (Bmax + 255) / 256);
+  HIPCHK(net->w_fpart.ensure((size_t)net->n_inst * f.nblk * 4 * sizeof(double)));
+  f.part = net->w_fpart.as<double>();
+  f.stats = stats;
+  HIPCHK(launch_free<real>(f, net->n_inst, st));
   for (int q = 0; q < net->n_inst; ++q) {
     const MadeInst &m = net->mi[q];
-    const InstDesc &D = net->P.insts[q];
     if (m.B <= 0) continue;
-    FreeArgs<real> f{};
-    f.spins = spins + m.spin_off;
-    f.logz = net->w_logz.as<double>() + m.sample_off;
-    f.logq = net->w_logq.as<real>() + m.sample_off;
-    f.ww_a = net->ww_a.as<int32_t>() + D.ww_off;
-    f.ww_b = net->ww_b.as<int32_t>() + D.ww_off;
-    f.ww_J = net->ww_J.as<double>() + D.ww_off;
-    f.hW = net->hW.as<double>() + net->P.hw_off[q];
-    f.n_ww = D.n_ww;
-    f.nw = D.nw;
-    f.B = m.B;
-    f.beta = D.beta;
-    f.f = net->w_f.as<double>() + m.sample_off;
-    f.wts = net->w_wts.as<real>() + m.sample_off;
-    f.stats = stats + 4 * q;
-    HIPCHK(launch_free<real>(f, st));
-    // REINFORCE backward through q
+    // REINFORCE backward through q (Eq. 10): per-sample rows, then batch sums
     const int n = m.n, H = m.H;
     HIPCHK(net->w_hid.ensure(std::max<int64_t>(1, m.B * H) * sizeof(real)));
     HIPCHK(net->w_da.ensure(std::max<int64_t>(1, m.B * H) * sizeof(real)));
@@ -475,10 +509,11 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     HIPCHK(net->w_sf.ensure(std::max<int64_t>(1, m.B * n) * sizeof(real)));
     RowArgs<real> r{};
     r.mi = m;
-    r.mi.spin_off = 0;
     r.params = net->params.as<float>();
     r.spins = spins + m.spin_off;
-    r.wts = net->w_wts.as<real>();
+    r.f = net->w_f.as<double>();
+    r.stats = stats + 4 * q;
+    r.chunk = std::max<int64_t>(16, ((m.B + 255) / 256 + 15) / 16 * 16);
     r.hid = net->w_hid.as<real>();
     r.da = net->w_da.as<real>();
     r.dlogit = net->w_dlogit.as<real>();
@@ -575,7 +610,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   UP(fld_ptr, P.fld_ptr) UP(fld_w, P.fld_w) UP(wr_pos, P.wr_pos) UP(wr_w, P.wr_w)
   UP(rr_edge, P.rr_edge) UP(rr_J, P.rr_J) UP(wr_edge, P.wr_edge) UP(wr_J, P.wr_J)
   UP(hR64, P.hR) UP(vr, P.vr) UP(ww_a, P.ww_a) UP(ww_b, P.ww_b) UP(ww_J, P.ww_J)
-  UP(hW, P.hW)
+  UP(hW, P.hW) UP(d_hw_off, P.hw_off)
   if (net->precision == TNVAN_FP64) {
     UP(T, P.T) UP(fld_J, P.fld_J) UP(hR, P.hR)
   } else {
@@ -588,6 +623,15 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
     int64_t a = 0, b = 0;
     for (int q = 0; q < n_inst; ++q) { sb[q] = a; eb[q] = b; a += P.insts[q].n; b += P.insts[q].n_edges; }
     UP(d_spin_base, sb) UP(d_edge_base, eb)
+    std::vector<int64_t> so(n_inst);
+    int64_t tot = 0;
+    for (int q = 0; q < n_inst; ++q) {
+      so[q] = tot;
+      tot += P.insts[q].n_partial;
+      net->max_partial = std::max(net->max_partial, (int)P.insts[q].n_partial);
+    }
+    net->sum_total = tot;
+    UP(d_sum_off, so)
   }
   UP(d_mi, net->mi)
   const size_t pb = std::max<int64_t>(1, net->param_total) * sizeof(float);
@@ -603,21 +647,48 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
     UP2(fld_J32, fj) UP2(hR32, hr) UP2(fld_wr, P.fld_wr) UP2(cinst, P.cinst)
     UP2(chains, P.chains) UP2(csteps, P.csteps) UP2(Tp, P.Tp) UP2(Tt, P.Tt) UP2(Tb, P.Tb)
   }
+  UP2(Tl, P.Tl) UP2(Tbl, P.Tbl) UP2(cedges, P.cedges)
+  // transfer-matrix form: instances whose program is a set of dense chains
+  // (FP32 / BF16 only); the launch-wide maxima size the LDS layout
   net->use_chain.assign(n_inst, 0);
   {
-    int kseg = 1;
-    for (int q = 0; q < n_inst; ++q)
-      if (P.cinst[q].ok) kseg = std::max(kseg, chain_kseg(P.cinst[q]));
-    net->kseg = kseg;
+    int dev = 0, maxlds = 65536;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    ChainLim lim{};
+    lim.kbuf = 16;
+    lim.kseg = 1;
     for (int q = 0; q < n_inst; ++q) {
       const ChainInst &C = P.cinst[q];
       if (net->precision == TNVAN_FP64 || !C.ok) continue;
-      const size_t wf = chain_wave_lds(C, false, kseg), wb = chain_wave_lds(C, true, kseg);
-      if (wb > 160 * 1024) continue;
       net->use_chain[q] = 1;
-      net->wlds_fwd = std::max<int32_t>(net->wlds_fwd, (int32_t)wf);
-      net->wlds_bwd = std::max<int32_t>(net->wlds_bwd, (int32_t)wb);
+      lim.kbuf = std::max(lim.kbuf, C.kbuf);
+      lim.npos_max = std::max(lim.npos_max, C.npos_max);
+      lim.max_steps = std::max(lim.max_steps, C.max_steps);
+      lim.pmax = std::max(lim.pmax, C.pmax);
+      lim.nw = std::max(lim.nw, C.nw);
+      lim.tl_max = std::max(lim.tl_max, C.tl_max);
+      lim.tbl_max = std::max(lim.tbl_max, C.tbl_max);
+      lim.ne_max = std::max(lim.ne_max, C.ne_max);
+      lim.nf_max = std::max(lim.nf_max, C.nf_max);
+      lim.kseg = std::max(lim.kseg, chain_kseg(C));
     }
+    const bool bf = net->precision == TNVAN_BF16;
+    bool ok = true;
+    for (int pass = 0; pass < 2 && std::count(net->use_chain.begin(), net->use_chain.end(), 1); ++pass) {
+      const bool bwd = pass == 1;
+      ChainLim L = lim;
+      L.tlds = 1;
+      size_t sh = chain_shared_lds(L, bwd, bf && !bwd), per = chain_wave_lds(L, bwd);
+      if (sh + per > (size_t)maxlds) {   // tables too large: read them from HBM
+        L.tlds = 0;
+        sh = chain_shared_lds(L, bwd, bf && !bwd);
+      }
+      if (sh + per > (size_t)maxlds) { ok = false; break; }
+      L.wpb = (int)std::min<size_t>(4, ((size_t)maxlds - sh) / per);
+      (bwd ? net->lim_bwd : net->lim_fwd) = L;
+    }
+    if (!ok) net->use_chain.assign(n_inst, 0);
   }
   choose_tiles(net, false);
   choose_tiles(net, true);
@@ -636,10 +707,13 @@ void tnvan_free_network(tnvan_net *net) {
                  &net->adam_v, &net->grad, &net->step_ctr, &net->d_sample_off, &net->d_B,
                  &net->d_spin_off, &net->d_spin_base, &net->d_edge_base, &net->blk_inst,
                  &net->blk_start, &net->garena, &net->partial, &net->w_logz, &net->w_logq,
-                 &net->w_spins, &net->w_f, &net->w_wts, &net->w_hid, &net->w_da,
+                 &net->w_spins, &net->w_f, &net->w_fpart, &net->w_hid, &net->w_da, &net->d_hw_off,
+                 &net->d_sum_off, &net->sumP,
                  &net->w_dlogit, &net->w_sf, &net->w_part, &net->cinst, &net->chains,
                  &net->csteps, &net->Tp, &net->Tt, &net->Tb, &net->fld_wr, &net->fld_J32,
                  &net->hR32, &net->task_inst, &net->task_chain, &net->task_start,
+                 &net->btask_inst, &net->btask_chain, &net->btask_start, &net->Tl, &net->Tbl,
+                 &net->cedges, &net->ckpt,
                  &net->cpart_off, &net->chain_list, &net->cpart};
   for (DBuf *b : all) b->release();
   TileCache *tcs[] = {&net->tc_fwd, &net->tc_bwd};

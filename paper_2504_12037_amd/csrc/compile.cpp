@@ -115,6 +115,7 @@ void build_chains(const InstDesc &D, const std::vector<int32_t> &consumer, HostP
     return;
   }
   ci.ok = 1;
+  ci.nw = D.nw;
   ci.n_chains = (int32_t)chains.size();
   for (auto &ch : chains) {
     ChainDesc cd{};
@@ -122,6 +123,11 @@ void build_chains(const InstDesc &D, const std::vector<int32_t> &consumer, HostP
     cd.cs_off = (int32_t)P.csteps.size();
     cd.pos_lo = st[ch.front()].gpos;
     cd.pos_hi = st[ch.back()].gpos + st[ch.back()].g;
+    cd.tl_src = (int64_t)P.Tl.size();
+    cd.tbl_src = (int64_t)P.Tbl.size();
+    cd.e_src = (int32_t)P.cedges.size();
+    cd.f_lo = P.fld_ptr[D.fld_off + cd.pos_lo];
+    cd.f_hi = P.fld_ptr[D.fld_off + cd.pos_hi];
     ci.npos_max = std::max(ci.npos_max, cd.pos_hi - cd.pos_lo);
     ci.max_steps = std::max(ci.max_steps, cd.n_steps);
     for (int t : ch) {
@@ -148,6 +154,7 @@ void build_chains(const InstDesc &D, const std::vector<int32_t> &consumer, HostP
         for (int x = 0; x < cs.kp; ++x)
           P.Tt.push_back((x < K && o < N) ? (float)T[((int64_t)x << sd.w) | o] : 0.0f);
       cs.tb_off = (int64_t)P.Tb.size();
+      cs.tbl_off = (int32_t)(P.Tbl.size() - cd.tbl_src);
       if (sd.w > 0) {
         const int KC = cs.kb / 32, NT = cs.np / 16;
         for (int nt = 0; nt < NT; ++nt)
@@ -157,10 +164,27 @@ void build_chains(const InstDesc &D, const std::vector<int32_t> &consumer, HostP
                 const int x = 32 * kc + 8 * (l / 16) + i, o = 16 * nt + l % 16;
                 const float v = (x < K && o < N) ? (float)T[((int64_t)x << sd.w) | o] : 0.0f;
                 P.Tb.push_back(to_bf16(v));
+                P.Tbl.push_back(to_bf16(v));
               }
       }
+      // rows padded by one word: lanes walking down a column hit distinct banks
+      cs.tl_off = (int32_t)(P.Tl.size() - cd.tl_src);
+      for (int x = 0; x < cs.kp; ++x) {
+        for (int o = 0; o < cs.np; ++o)
+          P.Tl.push_back((x < K && o < N) ? (float)T[((int64_t)x << sd.w) | o] : 0.0f);
+        P.Tl.push_back(0.0f);
+      }
+      cs.ce_off = (int32_t)P.cedges.size() - cd.e_src;
+      for (int k = 0; k < sd.n_edge; ++k) P.cedges.push_back(P.edges[sd.edge_off + k]);
       P.csteps.push_back(cs);
     }
+    cd.tl_size = (int32_t)(P.Tl.size() - cd.tl_src);
+    cd.tbl_size = (int32_t)(P.Tbl.size() - cd.tbl_src);
+    cd.n_e = (int32_t)P.cedges.size() - cd.e_src;
+    ci.tl_max = std::max(ci.tl_max, cd.tl_size);
+    ci.tbl_max = std::max(ci.tbl_max, cd.tbl_size);
+    ci.ne_max = std::max(ci.ne_max, cd.n_e);
+    ci.nf_max = std::max(ci.nf_max, cd.f_hi - cd.f_lo);
     P.chains.push_back(cd);
   }
   P.cinst.push_back(ci);

@@ -38,6 +38,9 @@ struct HostProgram {
   std::vector<ChainStep> csteps;
   std::vector<float> Tp, Tt;        // padded FP32 tables
   std::vector<uint16_t> Tb;         // padded BF16 tables (operand order)
+  std::vector<float> Tl;            // per chain: FP32 tables with rows padded by one
+  std::vector<uint16_t> Tbl;        // per chain: BF16 operand-order tables
+  std::vector<EdgeDesc> cedges;     // per chain: the edges of its steps
 };
 
 // Appends one instance to P.  Returns TNVAN_OK or an error code with msg.

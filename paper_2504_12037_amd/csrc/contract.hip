@@ -443,43 +443,56 @@ __global__ __launch_bounds__(kThreads) void contract_kernel(ContractArgs<real> a
   for (int k = tid; k < D.n_rr; k += kThreads) a.partial[prow + D.nr + D.n_wr + k] = Cw[k];
 }
 
+// Column sums of the per-tile partial rows of every instance (rows in a
+// fixed order, FP64): 16 columns x 16 row groups per block.
 template <typename real>
-__global__ void vjp_sum_kernel(VjpArgs a, const real *partial, int n_inst) {
+__global__ __launch_bounds__(256) void vjp_colsum_kernel(VjpArgs a, const real *partial) {
+  __shared__ double sh[16][17];
   const int q = blockIdx.y;
-  if (q >= n_inst) return;
   const InstDesc D = a.inst[q];
+  const int c = threadIdx.x & 15, rg = threadIdx.x >> 4;
+  const int k = blockIdx.x * 16 + c;
   const int nt = a.inst_n_tiles[q];
   const int64_t pb = a.inst_partial_off[q];
-  double *dh = a.dh + a.inst_spin_base[q];
-  double *dJ = a.dJ + a.inst_edge_base[q];
-  const double beta = D.beta;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < D.n_partial;
-       k += gridDim.x * blockDim.x) {
-    double acc = 0;
-    for (int t = 0; t < nt; ++t) acc += (double)partial[pb + (int64_t)t * D.n_partial + k];
-    if (k < D.nr) dh[a.vr[D.vr_off + k]] = beta * acc;
-    else if (k < D.nr + D.n_wr) dJ[a.wr_edge[D.wr_off + k - D.nr]] = beta * acc;
-    else dJ[a.rr_edge[D.rr_off + k - D.nr - D.n_wr]] = beta * acc;
+  double acc = 0.0;
+  if (k < D.n_partial)
+    for (int t = rg; t < nt; t += 16) acc += (double)partial[pb + (int64_t)t * D.n_partial + k];
+  sh[rg][c] = acc;
+  __syncthreads();
+  if (rg == 0 && k < D.n_partial) {
+    double s = 0.0;
+    for (int r = 0; r < 16; ++r) s += sh[r][c];
+    a.sumP[a.inst_sum_off[q] + k] = s;
   }
 }
 
-template <typename real>
-__global__ void vjp_beta_kernel(VjpArgs a, const real *partial, int n_inst) {
-  // dbeta = sum_RR J C + sum_R h U + sum_WR J UW, from the reduced entries
+// dh, dJ from the column sums (times beta); W vertices and W-W edges stay 0
+__global__ void vjp_scatter_kernel(VjpArgs a) {
+  const int q = blockIdx.y;
+  const InstDesc D = a.inst[q];
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= D.n_partial) return;
+  double *dh = a.dh + a.inst_spin_base[q];
+  double *dJ = a.dJ + a.inst_edge_base[q];
+  const double v = D.beta * a.sumP[a.inst_sum_off[q] + k];
+  if (k < D.nr) dh[a.vr[D.vr_off + k]] = v;
+  else if (k < D.nr + D.n_wr) dJ[a.wr_edge[D.wr_off + k - D.nr]] = v;
+  else dJ[a.rr_edge[D.rr_off + k - D.nr - D.n_wr]] = v;
+}
+
+// dbeta = -<E_2> weighted = sum_RR J C + sum_R h U + sum_WR J UW
+__global__ __launch_bounds__(256) void vjp_beta_kernel(VjpArgs a) {
   __shared__ double sh[256];
   const int q = blockIdx.x;
   const InstDesc D = a.inst[q];
-  const int nt = a.inst_n_tiles[q];
-  const int64_t pb = a.inst_partial_off[q];
-  double acc = 0;
+  const double *sp = a.sumP + a.inst_sum_off[q];
+  double acc = 0.0;
   for (int k = threadIdx.x; k < D.n_partial; k += blockDim.x) {
-    double s = 0;
-    for (int t = 0; t < nt; ++t) s += (double)partial[pb + (int64_t)t * D.n_partial + k];
     double coef;
     if (k < D.nr) coef = a.hR[D.hr_off + k];
     else if (k < D.nr + D.n_wr) coef = a.wr_J[D.wr_off + k - D.nr];
     else coef = a.rr_J[D.rr_off + k - D.nr - D.n_wr];
-    acc += coef * s;
+    acc += coef * sp[k];
   }
   sh[threadIdx.x] = acc;
   __syncthreads();
@@ -522,11 +535,14 @@ hipError_t launch_contract(const ContractArgs<real> &a, int n_tiles, size_t lds,
 }
 
 template <typename real>
-hipError_t launch_vjp_reduce(const VjpArgs &a, const real *partial, int n_inst,
+hipError_t launch_vjp_reduce(const VjpArgs &a, const real *partial, int n_inst, int max_partial,
                              hipStream_t st) {
-  (void)zero_kernel;
-  hipLaunchKernelGGL(vjp_sum_kernel<real>, dim3(8, n_inst), dim3(256), 0, st, a, partial, n_inst);
-  hipLaunchKernelGGL(vjp_beta_kernel<real>, dim3(n_inst), dim3(256), 0, st, a, partial, n_inst);
+  if (n_inst <= 0 || max_partial <= 0) return hipSuccess;
+  hipLaunchKernelGGL(vjp_colsum_kernel<real>, dim3((max_partial + 15) / 16, n_inst), dim3(256), 0,
+                     st, a, partial);
+  hipLaunchKernelGGL(vjp_scatter_kernel, dim3((max_partial + 255) / 256, n_inst), dim3(256), 0,
+                     st, a);
+  hipLaunchKernelGGL(vjp_beta_kernel, dim3(n_inst), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
@@ -540,7 +556,7 @@ hipError_t zero_doubles(double *p, int64_t n, hipStream_t st) {
 
 template hipError_t launch_contract<float>(const ContractArgs<float> &, int, size_t, bool, bool, hipStream_t);
 template hipError_t launch_contract<double>(const ContractArgs<double> &, int, size_t, bool, bool, hipStream_t);
-template hipError_t launch_vjp_reduce<float>(const VjpArgs &, const float *, int, hipStream_t);
-template hipError_t launch_vjp_reduce<double>(const VjpArgs &, const double *, int, hipStream_t);
+template hipError_t launch_vjp_reduce<float>(const VjpArgs &, const float *, int, int, hipStream_t);
+template hipError_t launch_vjp_reduce<double>(const VjpArgs &, const double *, int, int, hipStream_t);
 
 }  // namespace tnvan

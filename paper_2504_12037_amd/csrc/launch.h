@@ -67,10 +67,12 @@ struct VjpArgs {
   const int64_t *inst_partial_off;
   const int64_t *inst_spin_base;   // offset of instance i in dh (sum of n)
   const int64_t *inst_edge_base;   // offset of instance i in dJ
+  const int64_t *inst_sum_off;     // offset of instance i in sumP
+  double *sumP;                    // column sums of the partial rows
   double *dh, *dJ, *dbeta;
 };
 template <typename real>
-hipError_t launch_vjp_reduce(const VjpArgs &a, const real *partial, int n_inst,
+hipError_t launch_vjp_reduce(const VjpArgs &a, const real *partial, int n_inst, int max_partial,
                              hipStream_t st);
 
 // ---------------------------------------------------------------- network
@@ -95,18 +97,24 @@ struct SampleArgs {
   real *logq;
   uint64_t seed;
   const int32_t *step_ctr;      // per instance (device), Philox counter word 2
-  int32_t spb;                  // samples per block (256 / L)
+  int32_t spb;                  // samples per round of a block (256 / L)
+  int32_t reps;                 // rounds per block
 };
+// stage_bytes: LDS for the parameters (0 or too large: read them from HBM)
 template <typename real>
-hipError_t launch_sample(const SampleArgs<real> &a, int n_blocks, hipStream_t st);
+hipError_t launch_sample(const SampleArgs<real> &a, int n_blocks, size_t stage_bytes,
+                         hipStream_t st);
+size_t made_param_bytes(int n, int H);
 
 // Per-sample rows of the log-prob pass and the REINFORCE backward.
 template <typename real>
 struct RowArgs {
   MadeInst mi;
   const float *params;
-  const int8_t *spins;
-  const real *wts;         // REINFORCE weight per sample (global index)
+  const int8_t *spins;     // the instance's spins [B, n]
+  const double *f;         // f_b per sample (global index)
+  const double *stats;     // the instance's F_q (stats[0])
+  int64_t chunk;           // samples per block
   real *hid;               // [B, H]
   real *da;                // [B, H]
   real *dlogit;            // [B, n]
@@ -124,24 +132,25 @@ template <typename real>
 hipError_t launch_colsum(const real *X, int ldx, int64_t B, int M, real *part,
                          int ksplit, float *out, hipStream_t st);
 
-// Free energy statistics and REINFORCE weights for one instance.
+// Free energy statistics of every instance of the batch.
 template <typename real>
 struct FreeArgs {
-  const int8_t *spins;       // instance base
-  const double *logz;        // instance base
-  const real *logq;          // instance base
+  const InstDesc *inst;
+  const MadeInst *mi;
+  const int32_t *hw_off;     // per instance offset into hW
+  const int8_t *spins;
+  const double *logz;
+  const real *logq;
   const int32_t *ww_a, *ww_b;
   const double *ww_J;
   const double *hW;
-  int32_t n_ww, nw;
-  int64_t B;
-  double beta;
-  double *f;                 // scratch [B]
-  real *wts;                 // out [B]
-  double *stats;             // out [4]
+  double *f;                 // out [sum B]
+  double *part;              // scratch [n_inst][nblk][4]
+  int32_t nblk;
+  double *stats;             // out [n_inst][4]
 };
 template <typename real>
-hipError_t launch_free(const FreeArgs<real> &a, hipStream_t st);
+hipError_t launch_free(const FreeArgs<real> &a, int n_inst, hipStream_t st);
 
 hipError_t launch_adam(float *params, const float *grad, float *m, float *v,
                        int64_t n, float lr, int32_t *step_ctr, hipStream_t st);
@@ -151,20 +160,30 @@ hipError_t launch_bump(int32_t *step_ctr, int n, hipStream_t st);
 
 namespace tnvan {
 
-// Transfer-matrix (chain) kernels: one wave per (instance, chain, 16 samples).
+// Transfer-matrix (chain) kernels: a workgroup takes one chain of one
+// instance and wpb groups of 16 samples (one per wave).
+struct ChainLim {             // launch-wide maxima that size the LDS layout
+  int32_t kbuf, npos_max, max_steps, pmax, nw;
+  int32_t tl_max, tbl_max, ne_max, nf_max;
+  int32_t kseg;               // checkpoint interval of the adjoint
+  int32_t wpb;                // waves per workgroup
+  int32_t tlds;               // transfer tables staged in LDS
+};
 struct ChainArgs {
   const InstDesc *inst;
   const ChainInst *cinst;
   const ChainDesc *chains;
   const ChainStep *csteps;
-  const EdgeDesc *edges;
-  const float *Tp, *Tt;
+  const float *Tp, *Tt;       // per-step padded tables (HBM)
   const uint16_t *Tb;
+  const float *Tl;            // per-chain staged blocks (HBM source)
+  const uint16_t *Tbl;
+  const EdgeDesc *cedges;
   const int32_t *fld_ptr, *fld_w, *fld_wr;
   const float *fld_J, *hR;
-  const int32_t *task_inst, *task_chain, *task_start;
+  const int32_t *task_inst, *task_chain, *task_start;   // per workgroup
   int32_t n_tasks;
-  int32_t kseg;                     // checkpoint interval of the adjoint
+  ChainLim lim;
   const int64_t *inst_B, *inst_sample_off, *inst_spin_off;
   const int64_t *cpart_off;         // per instance: chain-partial logZ offset
   const int8_t *spins;
@@ -172,11 +191,13 @@ struct ChainArgs {
   const double *grad;
   float *partial;                   // adjoint partial rows
   const int64_t *inst_partial_off;
-  int32_t wave_lds;                 // bytes of LDS per wave
+  float *ckpt;                      // adjoint checkpoints, per wave
   int32_t bf16;
   int32_t ntm;                      // largest K or N of the launch in 16-wide tiles
 };
-size_t chain_wave_lds(const ChainInst &C, bool bwd, int kseg);
+// LDS bytes: shared part of a workgroup and per-wave part
+size_t chain_shared_lds(const ChainLim &L, bool bwd, bool bf16);
+size_t chain_wave_lds(const ChainLim &L, bool bwd);
 int chain_kseg(const ChainInst &C);
 hipError_t launch_chain(const ChainArgs &a, bool bwd, hipStream_t st);
 // logz[b] = log_const + sum over chains of the per-chain partials

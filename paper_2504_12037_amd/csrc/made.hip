@@ -54,149 +54,224 @@ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
 constexpr int KH = 16;    // hidden units per lane
 constexpr int KN = 32;    // width-set positions per lane
 
+// Parameter views with row strides.  With kLDS a block first copies the
+// parameters of its instance into LDS: for the sampler W1 is stored
+// transposed ([n][H], lanes owning consecutive hidden units read consecutive
+// words); for the row kernel every matrix keeps its orientation with its rows
+// padded by one word so that lanes walking down a column hit distinct banks.
+struct MadeView {
+  const float *W1;   // [H][ld1] (or transposed [n][ld1])
+  const float *b1, *W2, *b2, *W0;
+  int ld1, ld2, ld0;
+};
+
+// LDS bytes of the staged parameters (padded layout, the larger of the two)
+__host__ __device__ inline size_t made_stage_bytes(int n, int H) {
+  return (size_t)(H * (n + 1) + n * (H + 1) + n * (n + 1) + H + n) * 4;
+}
+
+__device__ inline MadeView made_view(const float *p, int n, int H) {
+  MadeView v;
+  v.W1 = p;
+  v.b1 = p + (int64_t)H * n;
+  v.W2 = v.b1 + H;
+  v.b2 = v.W2 + (int64_t)n * H;
+  v.W0 = v.b2 + n;
+  v.ld1 = n; v.ld2 = H; v.ld0 = n;
+  return v;
+}
+
+__device__ inline MadeView made_stage(const MadeView g, int n, int H, float *s, bool transpose_w1) {
+  MadeView v;
+  v.ld1 = transpose_w1 ? H : n + 1;
+  v.ld2 = transpose_w1 ? H : H + 1;
+  v.ld0 = transpose_w1 ? n : n + 1;
+  const int rows1 = transpose_w1 ? n : H;
+  float *W1 = s, *W2 = W1 + (size_t)rows1 * v.ld1, *W0 = W2 + (size_t)n * v.ld2,
+        *b1 = W0 + (size_t)n * v.ld0, *b2 = b1 + H;
+  for (int i = threadIdx.x; i < n * H; i += blockDim.x) {
+    if (transpose_w1) {
+      const int j = i / H, k = i - j * H;     // W1t[j][k] = W1[k][j]
+      W1[(size_t)j * v.ld1 + k] = g.W1[(int64_t)k * n + j];
+    } else {
+      const int k = i / n, j = i - k * n;
+      W1[(size_t)k * v.ld1 + j] = g.W1[i];
+    }
+    const int ii = i / H, k = i - ii * H;
+    W2[(size_t)ii * v.ld2 + k] = g.W2[i];
+  }
+  for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
+    const int ii = i / n, j = i - ii * n;
+    W0[(size_t)ii * v.ld0 + j] = g.W0[i];
+  }
+  for (int i = threadIdx.x; i < H; i += blockDim.x) b1[i] = g.b1[i];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) b2[i] = g.b2[i];
+  __syncthreads();
+  v.W1 = W1; v.b1 = b1; v.W2 = W2; v.b2 = b2; v.W0 = W0;
+  return v;
+}
+
 // One group of L lanes per sample; lane l owns hidden units k = l + L*kk and
 // positions j = l + L*jj.  Spins are drawn one position after the other.
-template <typename real>
+// A block runs `reps` rounds of 256/L samples of one instance.
+template <typename real, bool kLDS>
 __global__ __launch_bounds__(256) void sample_kernel(SampleArgs<real> a) {
+  extern __shared__ __align__(16) char smem[];
   const int q = a.blk_inst[blockIdx.x];
   const MadeInst mi = a.mi[q];
   const int L = mi.L;
   const int grp = threadIdx.x / L, l = threadIdx.x % L;
-  const int64_t b = a.blk_start[blockIdx.x] + grp;
-  const bool live = grp < a.spb && b < mi.B;
-  const int n = mi.n, H = (n >= 2) ? mi.H : 0;
-  const float *W1 = a.params + mi.param_off;
-  const float *b1 = W1 + (int64_t)mi.H * n;
-  const float *W2 = b1 + mi.H;
-  const float *b2 = W2 + (int64_t)n * mi.H;
-  const float *W0 = b2 + n;
-  real av[KH], hv[KH], sv[KN];
+  const int n = mi.n, Hs = mi.H, H = (n >= 2) ? mi.H : 0;
+  MadeView w = made_view(a.params + mi.param_off, n, Hs);
+  if (kLDS) w = made_stage(w, n, Hs, reinterpret_cast<float *>(smem), true);
+  const uint32_t step = a.step_ctr ? (uint32_t)a.step_ctr[q] : 0u;
+  int dg[KH];
 #pragma unroll
   for (int kk = 0; kk < KH; ++kk) {
     const int k = l + L * kk;
-    av[kk] = (k < H) ? (real)b1[k] : (real)0;
-    hv[kk] = 0;
+    dg[kk] = k < H ? degree(k, n) : 0;
   }
-#pragma unroll
-  for (int jj = 0; jj < KN; ++jj) sv[jj] = 0;
-  real lq = 0;
-  const int64_t gs = mi.sample_off + (live ? b : 0);
-  const float *u = a.uniforms ? a.uniforms + mi.spin_off + (live ? b : 0) * n : nullptr;
-  int8_t *so = a.spins + mi.spin_off + (live ? b : 0) * n;
-  uint32_t pw[4] = {0, 0, 0, 0};
-  const uint32_t step = a.step_ctr ? (uint32_t)a.step_ctr[q] : 0u;
-  for (int i = 0; i < n; ++i) {
-    real part = 0;
+  for (int rep = 0; rep < a.reps; ++rep) {
+    const int64_t b = a.blk_start[blockIdx.x] + (int64_t)rep * a.spb + grp;
+    const bool live = grp < a.spb && b < mi.B;
+    real av[KH], hv[KH], sv[KN];
 #pragma unroll
     for (int kk = 0; kk < KH; ++kk) {
       const int k = l + L * kk;
-      if (k < H && degree(k, n) <= i) part += (real)W2[(int64_t)i * mi.H + k] * hv[kk];
+      av[kk] = (k < H) ? (real)w.b1[k] : (real)0;
+      hv[kk] = 0;
     }
 #pragma unroll
-    for (int jj = 0; jj < KN; ++jj) {
-      const int j = l + L * jj;
-      if (j < i) part += (real)W0[(int64_t)i * n + j] * sv[jj];
-    }
-    for (int off = L >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
-    const real logit = part + (real)b2[i];
-    float ui;
-    if (u) {
-      ui = live ? u[i] : 0.5f;
-    } else {
-      if ((i & 3) == 0) {
-        pw[0] = (uint32_t)(i >> 2); pw[1] = (uint32_t)b; pw[2] = step; pw[3] = (uint32_t)q;
-        philox4x32_10(pw, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+    for (int jj = 0; jj < KN; ++jj) sv[jj] = 0;
+    real lq = 0;
+    const int64_t bs = live ? b : 0;
+    const float *u = a.uniforms ? a.uniforms + mi.spin_off + bs * n : nullptr;
+    int8_t *so = a.spins + mi.spin_off + bs * n;
+    uint32_t pw[4] = {0, 0, 0, 0};
+    for (int i = 0; i < n; ++i) {
+      real part = 0;
+#pragma unroll
+      for (int kk = 0; kk < KH; ++kk) {
+        const int k = l + L * kk;
+        if (k < H && dg[kk] <= i) part += (real)w.W2[(int64_t)i * w.ld2 + k] * hv[kk];
       }
-      ui = (float)(pw[i & 3] >> 8) * 5.9604644775390625e-08f;
-    }
-    const real p = sigmoid<real>(logit);
-    const real si = ((real)ui < p) ? (real)1 : (real)-1;
-    lq += log_sigmoid<real>(si * logit);
-    if (l == (i % L)) {
-      const int jw = i / L;
 #pragma unroll
-      for (int jj = 0; jj < KN; ++jj)
-        if (jj == jw) sv[jj] = si;
-      if (live) so[i] = (int8_t)(si > 0 ? 1 : -1);
-    }
+      for (int jj = 0; jj < KN; ++jj) {
+        const int j = l + L * jj;
+        if (j < i) part += (real)w.W0[(int64_t)i * w.ld0 + j] * sv[jj];
+      }
+      for (int off = L >> 1; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+      const real logit = part + (real)w.b2[i];
+      float ui;
+      if (u) {
+        ui = live ? u[i] : 0.5f;
+      } else {
+        if ((i & 3) == 0) {
+          pw[0] = (uint32_t)(i >> 2); pw[1] = (uint32_t)b; pw[2] = step; pw[3] = (uint32_t)q;
+          philox4x32_10(pw, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+        }
+        ui = (float)(pw[i & 3] >> 8) * 5.9604644775390625e-08f;
+      }
+      const real p = sigmoid<real>(logit);
+      const real si = ((real)ui < p) ? (real)1 : (real)-1;
+      lq += log_sigmoid<real>(si * logit);
+      if (l == (i % L)) {
+        const int jw = i / L;
 #pragma unroll
-    for (int kk = 0; kk < KH; ++kk) {
-      const int k = l + L * kk;
-      if (k < H) {
-        const int m = degree(k, n);
-        if (m >= i + 1) {
-          av[kk] += (real)W1[(int64_t)k * n + i] * si;
-          if (m == i + 1) hv[kk] = rtanh<real>(av[kk]);
+        for (int jj = 0; jj < KN; ++jj)
+          if (jj == jw) sv[jj] = si;
+        if (live) so[i] = (int8_t)(si > 0 ? 1 : -1);
+      }
+#pragma unroll
+      for (int kk = 0; kk < KH; ++kk) {
+        const int k = l + L * kk;
+        if (k < H) {
+          const int m = dg[kk];
+          if (m >= i + 1) {
+            const float wk = kLDS ? w.W1[(int64_t)i * w.ld1 + k] : w.W1[(int64_t)k * n + i];
+            av[kk] += (real)wk * si;
+            if (m == i + 1) hv[kk] = rtanh<real>(av[kk]);
+          }
         }
       }
     }
+    if (live && l == 0) a.logq[mi.sample_off + b] = lq;
   }
-  if (live && l == 0) a.logq[gs] = lq;
 }
 
-// Per-sample rows: a, tanh(a), logits, dlogit = w ((1+s)/2 - sigmoid(logit)),
-// da = (dlogit . W2m) (1 - tanh^2).  One block of 256 threads per 16 samples.
+// Per-sample rows of the log-prob pass and the REINFORCE backward:
+// a, tanh(a), logits, dlogit = w ((1+s)/2 - sigmoid(logit)) with the weight
+// w_b = (f_b - F_q) / B, and da = (dlogit . W2m) (1 - tanh^2).  A block walks
+// a chunk of samples in rounds of RB, with the parameters staged in LDS.
 constexpr int RB = 16;
-template <typename real>
+template <typename real, bool kLDS>
 __global__ __launch_bounds__(256) void rows_kernel(RowArgs<real> a) {
   extern __shared__ __align__(16) char smem[];
   const MadeInst mi = a.mi;
   const int n = mi.n, H = (n >= 2) ? mi.H : 0, Hs = mi.H;
-  real *ss = reinterpret_cast<real *>(smem);         // [RB][n]
+  MadeView w = made_view(a.params + mi.param_off, n, Hs);
+  size_t woff = 0;
+  if (kLDS) {
+    w = made_stage(w, n, Hs, reinterpret_cast<float *>(smem), false);
+    woff = (made_stage_bytes(n, Hs) + 15) & ~(size_t)15;
+  }
+  real *ss = reinterpret_cast<real *>(smem + woff);  // [RB][n]
   real *hh = ss + RB * n;                            // [RB][H]
   real *dl = hh + RB * Hs;                           // [RB][n]
-  const int64_t r0 = (int64_t)blockIdx.x * RB;
-  const int nr = (int)((mi.B - r0) < RB ? (mi.B - r0) : RB);
-  const float *W1 = a.params + mi.param_off;
-  const float *b1 = W1 + (int64_t)Hs * n;
-  const float *W2 = b1 + Hs;
-  const float *b2 = W2 + (int64_t)n * Hs;
-  const float *W0 = b2 + n;
-  const int8_t *sp = a.spins + mi.spin_off + r0 * n;
-  for (int i = threadIdx.x; i < RB * n; i += blockDim.x) {
-    const int r = i / n;
-    ss[i] = r < nr ? (real)sp[i] : (real)0;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < RB * Hs; i += blockDim.x) {
-    const int r = i / Hs, k = i % Hs;
-    real acc = 0;
-    if (k < H) {
-      acc = (real)b1[k];
-      const int m = degree(k, n);
-      for (int j = 0; j < m; ++j) acc += (real)W1[(int64_t)k * n + j] * ss[r * n + j];
-      acc = rtanh<real>(acc);
+  const double Fq = a.stats[0];
+  const double invB = 1.0 / (double)mi.B;
+  const int64_t c0 = (int64_t)blockIdx.x * a.chunk;
+  const int64_t c1 = (c0 + a.chunk) < mi.B ? (c0 + a.chunk) : mi.B;
+  for (int64_t r0 = c0; r0 < c1; r0 += RB) {
+    const int nr = (int)((c1 - r0) < RB ? (c1 - r0) : RB);
+    const int8_t *sp = a.spins + r0 * n;
+    for (int i = threadIdx.x; i < RB * n; i += blockDim.x) {
+      const int r = i / n;
+      ss[i] = r < nr ? (real)sp[i] : (real)0;
     }
-    hh[i] = acc;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < RB * n; i += blockDim.x) {
-    const int r = i / n, ii = i % n;
-    real z = (real)b2[ii];
-    for (int k = 0; k < H; ++k)
-      if (degree(k, n) <= ii) z += (real)W2[(int64_t)ii * Hs + k] * hh[r * Hs + k];
-    for (int j = 0; j < ii; ++j) z += (real)W0[(int64_t)ii * n + j] * ss[r * n + j];
-    const real s = ss[i];
-    const real wt = r < nr ? a.wts[mi.sample_off + r0 + r] : (real)0;
-    const real d = wt * (((real)1 + s) * (real)0.5 - sigmoid<real>(z));
-    dl[i] = d;
-    if (r < nr) {
-      a.dlogit[(r0 + r) * n + ii] = d;
-      a.sf[(r0 + r) * n + ii] = s;
+    __syncthreads();
+    for (int i = threadIdx.x; i < RB * Hs; i += blockDim.x) {
+      const int r = i / Hs, k = i % Hs;
+      real acc = 0;
+      if (k < H) {
+        acc = (real)w.b1[k];
+        const int m = degree(k, n);
+        for (int j = 0; j < m; ++j) acc += (real)w.W1[(int64_t)k * w.ld1 + j] * ss[r * n + j];
+        acc = rtanh<real>(acc);
+      }
+      hh[i] = acc;
     }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < RB * Hs; i += blockDim.x) {
-    const int r = i / Hs, k = i % Hs;
-    if (r >= nr) continue;
-    real acc = 0;
-    const real hk = hh[i];
-    if (k < H) {
-      const int m = degree(k, n);
-      for (int ii = m; ii < n; ++ii) acc += dl[r * n + ii] * (real)W2[(int64_t)ii * Hs + k];
+    __syncthreads();
+    for (int i = threadIdx.x; i < RB * n; i += blockDim.x) {
+      const int r = i / n, ii = i % n;
+      real z = (real)w.b2[ii];
+      for (int k = 0; k < H; ++k)
+        if (degree(k, n) <= ii) z += (real)w.W2[(int64_t)ii * w.ld2 + k] * hh[r * Hs + k];
+      for (int j = 0; j < ii; ++j) z += (real)w.W0[(int64_t)ii * w.ld0 + j] * ss[r * n + j];
+      const real s = ss[i];
+      const real wt = r < nr ? (real)((a.f[mi.sample_off + r0 + r] - Fq) * invB) : (real)0;
+      const real d = wt * (((real)1 + s) * (real)0.5 - sigmoid<real>(z));
+      dl[i] = d;
+      if (r < nr) {
+        a.dlogit[(r0 + r) * n + ii] = d;
+        a.sf[(r0 + r) * n + ii] = s;
+      }
     }
-    a.hid[(r0 + r) * Hs + k] = hk;
-    a.da[(r0 + r) * Hs + k] = acc * ((real)1 - hk * hk);
+    __syncthreads();
+    for (int i = threadIdx.x; i < RB * Hs; i += blockDim.x) {
+      const int r = i / Hs, k = i % Hs;
+      if (r < nr) {
+        real acc = 0;
+        const real hk = hh[i];
+        if (k < H) {
+          const int m = degree(k, n);
+          for (int ii = m; ii < n; ++ii) acc += dl[r * n + ii] * (real)w.W2[(int64_t)ii * w.ld2 + k];
+        }
+        a.hid[(r0 + r) * Hs + k] = hk;
+        a.da[(r0 + r) * Hs + k] = acc * ((real)1 - hk * hk);
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -281,52 +356,60 @@ __global__ void colsum_finish(const real *part, int ksplit, int M, float *out) {
   out[m] = (float)acc;
 }
 
-// f_b = E_1 - logZ_R / beta + ln q / beta (FP64), F_q, its standard error,
-// <Etilde>, <ln q>/beta and REINFORCE weights (f_b - F_q) / B.
+// f_b = E_1 - logZ_R / beta + ln q / beta (FP64, Eqs. 4 and 9) per sample and
+// per-block sums of f, f^2, Etilde and ln q / beta; every instance of the
+// batch in one launch (grid.y = instance).
 template <typename real>
-__global__ __launch_bounds__(1024) void free_kernel(FreeArgs<real> a) {
-  __shared__ double sh[3][1024];
-  const int tid = threadIdx.x;
-  double s_f = 0, s_e = 0, s_q = 0;
-  for (int64_t b = tid; b < a.B; b += blockDim.x) {
-    const int8_t *s = a.spins + b * a.nw;
-    double e1 = 0;
-    for (int k = 0; k < a.n_ww; ++k) e1 -= a.ww_J[k] * (double)s[a.ww_a[k]] * (double)s[a.ww_b[k]];
-    for (int k = 0; k < a.nw; ++k) e1 -= a.hW[k] * (double)s[k];
-    const double et = e1 - a.logz[b] / a.beta;
-    const double lqb = (double)a.logq[b] / a.beta;
+__global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
+  __shared__ double sh[4][256];
+  const int q = blockIdx.y, tid = threadIdx.x;
+  const InstDesc D = a.inst[q];
+  const MadeInst mi = a.mi[q];
+  const double beta = D.beta;
+  const int32_t *wa = a.ww_a + D.ww_off, *wb = a.ww_b + D.ww_off;
+  const double *wJ = a.ww_J + D.ww_off, *hW = a.hW + a.hw_off[q];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + tid; b < mi.B;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int8_t *s = a.spins + mi.spin_off + b * mi.n;
+    double e1 = 0.0;
+    for (int k = 0; k < D.n_ww; ++k) e1 -= wJ[k] * (double)s[wa[k]] * (double)s[wb[k]];
+    for (int k = 0; k < mi.n; ++k) e1 -= hW[k] * (double)s[k];
+    const int64_t g = mi.sample_off + b;
+    const double et = e1 - a.logz[g] / beta;
+    const double lqb = (double)a.logq[g] / beta;
     const double f = et + lqb;
-    a.f[b] = f;
-    s_f += f; s_e += et; s_q += lqb;
+    a.f[g] = f;
+    acc[0] += f; acc[1] += f * f; acc[2] += et; acc[3] += lqb;
   }
-  sh[0][tid] = s_f; sh[1][tid] = s_e; sh[2][tid] = s_q;
+  for (int c = 0; c < 4; ++c) sh[c][tid] = acc[c];
   __syncthreads();
   for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-    if (tid < st) for (int c = 0; c < 3; ++c) sh[c][tid] += sh[c][tid + st];
+    if (tid < st)
+      for (int c = 0; c < 4; ++c) sh[c][tid] += sh[c][tid + st];
     __syncthreads();
   }
-  const double Fq = sh[0][0] / (double)a.B;
-  const double me = sh[1][0] / (double)a.B, mq = sh[2][0] / (double)a.B;
-  __syncthreads();
-  double v = 0;
-  for (int64_t b = tid; b < a.B; b += blockDim.x) {
-    const double d = a.f[b] - Fq;
-    v += d * d;
-    a.wts[b] = (real)(d / (double)a.B);
-  }
-  sh[0][tid] = v;
-  __syncthreads();
-  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
-    if (tid < st) sh[0][tid] += sh[0][tid + st];
-    __syncthreads();
-  }
-  if (tid == 0) {
-    const double var = a.B > 1 ? sh[0][0] / (double)(a.B - 1) : 0.0;
-    a.stats[0] = Fq;
-    a.stats[1] = sqrt(var / (double)a.B);
-    a.stats[2] = me;
-    a.stats[3] = mq;
-  }
+  if (tid < 4) a.part[((int64_t)q * gridDim.x + blockIdx.x) * 4 + tid] = sh[tid][0];
+}
+
+// F_q = mean f, its standard error, <Etilde>, <ln q>/beta from the block sums
+// (summed in a fixed order).
+template <typename real>
+__global__ void free_stats_kernel(FreeArgs<real> a) {
+  const int q = blockIdx.x;
+  const MadeInst mi = a.mi[q];
+  if (threadIdx.x != 0 || mi.B <= 0) return;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < a.nblk; ++k)
+    for (int c = 0; c < 4; ++c) s[c] += a.part[((int64_t)q * a.nblk + k) * 4 + c];
+  const double B = (double)mi.B;
+  const double Fq = s[0] / B;
+  double var = mi.B > 1 ? (s[1] - B * Fq * Fq) / (B - 1.0) : 0.0;
+  if (var < 0.0) var = 0.0;
+  a.stats[4 * q + 0] = Fq;
+  a.stats[4 * q + 1] = sqrt(var / B);
+  a.stats[4 * q + 2] = s[2] / B;
+  a.stats[4 * q + 3] = s[3] / B;
 }
 
 __global__ void adam_kernel(float *p, const float *g, float *m, float *v, int64_t n,
@@ -352,19 +435,41 @@ __global__ void bump_kernel(int32_t *c, int n) {
 
 }  // namespace
 
+constexpr size_t kStageMax = 96 * 1024;
+
+size_t made_param_bytes(int n, int H) { return made_stage_bytes(n, H); }
+
 template <typename real>
-hipError_t launch_sample(const SampleArgs<real> &a, int n_blocks, hipStream_t st) {
+hipError_t launch_sample(const SampleArgs<real> &a, int n_blocks, size_t stage_bytes,
+                         hipStream_t st) {
   if (n_blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sample_kernel<real>, dim3(n_blocks), dim3(256), 0, st, a);
+  if (stage_bytes > 0 && stage_bytes <= kStageMax) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(sample_kernel<real, true>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)stage_bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((sample_kernel<real, true>), dim3(n_blocks), dim3(256), stage_bytes, st, a);
+  } else {
+    hipLaunchKernelGGL((sample_kernel<real, false>), dim3(n_blocks), dim3(256), 0, st, a);
+  }
   return hipGetLastError();
 }
 
 template <typename real>
 hipError_t launch_rows(const RowArgs<real> &a, hipStream_t st) {
   if (a.mi.B <= 0) return hipSuccess;
-  const int blocks = (int)((a.mi.B + RB - 1) / RB);
-  const size_t lds = sizeof(real) * (size_t)RB * (2 * a.mi.n + a.mi.H);
-  hipLaunchKernelGGL(rows_kernel<real>, dim3(blocks), dim3(256), lds, st, a);
+  const int64_t blocks = (a.mi.B + a.chunk - 1) / a.chunk;
+  const size_t rows = sizeof(real) * (size_t)RB * (2 * a.mi.n + a.mi.H);
+  const size_t wb = (made_param_bytes(a.mi.n, a.mi.H) + 15) & ~(size_t)15;
+  if (wb + rows <= kStageMax) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(rows_kernel<real, true>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(wb + rows));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((rows_kernel<real, true>), dim3(blocks), dim3(256), wb + rows, st, a);
+  } else {
+    hipLaunchKernelGGL((rows_kernel<real, false>), dim3(blocks), dim3(256), rows, st, a);
+  }
   return hipGetLastError();
 }
 
@@ -396,8 +501,10 @@ hipError_t launch_colsum(const real *X, int ldx, int64_t B, int M, real *part, i
 }
 
 template <typename real>
-hipError_t launch_free(const FreeArgs<real> &a, hipStream_t st) {
-  hipLaunchKernelGGL(free_kernel<real>, dim3(1), dim3(1024), 0, st, a);
+hipError_t launch_free(const FreeArgs<real> &a, int n_inst, hipStream_t st) {
+  if (n_inst <= 0) return hipSuccess;
+  hipLaunchKernelGGL(free_f_kernel<real>, dim3(a.nblk, n_inst), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(free_stats_kernel<real>, dim3(n_inst), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 
@@ -416,15 +523,15 @@ hipError_t launch_bump(int32_t *step_ctr, int n, hipStream_t st) {
   return hipGetLastError();
 }
 
-template hipError_t launch_sample<float>(const SampleArgs<float> &, int, hipStream_t);
-template hipError_t launch_sample<double>(const SampleArgs<double> &, int, hipStream_t);
+template hipError_t launch_sample<float>(const SampleArgs<float> &, int, size_t, hipStream_t);
+template hipError_t launch_sample<double>(const SampleArgs<double> &, int, size_t, hipStream_t);
 template hipError_t launch_rows<float>(const RowArgs<float> &, hipStream_t);
 template hipError_t launch_rows<double>(const RowArgs<double> &, hipStream_t);
 template hipError_t launch_atb<float>(const float *, int, const float *, int, int64_t, int, int, float *, int, float *, int, int, int, hipStream_t);
 template hipError_t launch_atb<double>(const double *, int, const double *, int, int64_t, int, int, double *, int, float *, int, int, int, hipStream_t);
 template hipError_t launch_colsum<float>(const float *, int, int64_t, int, float *, int, float *, hipStream_t);
 template hipError_t launch_colsum<double>(const double *, int, int64_t, int, double *, int, float *, hipStream_t);
-template hipError_t launch_free<float>(const FreeArgs<float> &, hipStream_t);
-template hipError_t launch_free<double>(const FreeArgs<double> &, hipStream_t);
+template hipError_t launch_free<float>(const FreeArgs<float> &, int, hipStream_t);
+template hipError_t launch_free<double>(const FreeArgs<double> &, int, hipStream_t);
 
 }  // namespace tnvan

@@ -103,7 +103,9 @@ struct ChainStep {
   int32_t kb;         // padded K for BF16 16x16x32 products (>= 32)
   int32_t np;         // padded N (>= 16), or 1 when the step closes the chain
   int32_t n_edge, edge_off;
-  int32_t pad;
+  int32_t tl_off;     // FP32 [kp][np + 1] table inside the chain's staged block
+  int32_t tbl_off;    // BF16 operand-order table inside the chain's staged block
+  int32_t ce_off;     // first edge inside the chain's edge list
   int64_t tp_off;     // FP32 [kp][np]
   int64_t tt_off;     // FP32 [np][kp] (transposed, for the adjoint)
   int64_t tb_off;     // BF16 packed in the 16x16x32 operand order
@@ -112,6 +114,13 @@ struct ChainStep {
 struct ChainDesc {
   int32_t n_steps, cs_off;   // ChainStep range
   int32_t pos_lo, pos_hi;    // R positions the chain eliminates
+  // data a workgroup stages into LDS once for all its waves
+  int32_t tl_size;           // floats of the padded FP32 tables of every step
+  int32_t tbl_size;          // BF16 entries of the operand-order tables
+  int64_t tl_src;            // offset of that block in the FP32 block array
+  int64_t tbl_src;           // offset in the BF16 block array
+  int32_t e_src, n_e;        // the chain's edges in the chain edge array
+  int32_t f_lo, f_hi;        // W-neighbour entries of the chain's positions
 };
 
 struct ChainInst {
@@ -121,7 +130,13 @@ struct ChainInst {
   int32_t npos_max;          // most positions of one chain
   int32_t max_steps;         // longest chain
   int32_t gmax;              // largest group
-  int32_t pmax;              // largest (kp/16... ) edge partial table
+  int32_t pmax;              // largest per-state edge partial table (kp * (w+1))
+  int32_t nw;                // width-set size (spins staged per sample)
+  int32_t tl_max;            // largest tl_size of the instance's chains
+  int32_t tbl_max;           // largest tbl_size
+  int32_t ne_max;            // most edges of one chain
+  int32_t nf_max;            // most W-neighbour entries of one chain
+  int32_t pad;
 };
 
 }  // namespace tnvan
