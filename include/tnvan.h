@@ -81,9 +81,14 @@ typedef struct {
   int32_t precision;          /* tnvan_precision */
   int32_t max_width;          /* largest message scope allowed (<= 14) */
   int32_t deterministic;      /* reserved: every reduction is ordered */
-  int32_t reserved;
+  int32_t flags;              /* TNVAN_FLAG_* bits, 0 for the defaults */
   uint64_t seed;              /* key of the Philox4x32-10 stream of q */
 } tnvan_options;
+
+/* Run chains of narrow dense steps in the LDS-staged transfer-matrix kernels
+ * instead of the register-resident ones (same results up to rounding; for
+ * comparisons and timing). */
+#define TNVAN_FLAG_LDS_CHAIN 1
 
 /* Compile n_inst instances into one net (host work plus device uploads,
  * synchronous).  Validates every instance: W and order disjoint and covering

@@ -48,7 +48,7 @@ class CInstance(C.Structure):
 
 class COptions(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_width", C.c_int32),
-                ("deterministic", C.c_int32), ("reserved", C.c_int32),
+                ("deterministic", C.c_int32), ("flags", C.c_int32),
                 ("seed", C.c_uint64)]
 
 

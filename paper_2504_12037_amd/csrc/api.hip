@@ -114,6 +114,10 @@ struct tnvan_net {
   DBuf cinst, chains, csteps, Tp, Tt, Tb, fld_wr, fld_J32, hR32;
   ChainLim lim_fwd{}, lim_bwd{};
   DBuf Tl, Tbl, cedges, ckpt;
+  // register-resident chain kernels (per-wave tasks)
+  DBuf Tr, Tq, Trb, xcol;
+  bool rfwd = false, rbwd = false;
+  int rtiles = 1, sg = 2;
   DBuf task_inst, task_chain, task_start, btask_inst, btask_chain, btask_start, cpart_off,
       chain_list, cpart;
   int n_tasks = 0, n_btasks = 0, n_chain_insts = 0;
@@ -229,7 +233,10 @@ tnvan_status ensure_chain_tasks(tnvan_net *net) {
   std::vector<int64_t> coff(net->n_inst, 0);
   int64_t ctot = 0;
   for (int pass = 0; pass < 2; ++pass) {
-    const int per = 16 * (pass ? net->lim_bwd.wpb : net->lim_fwd.wpb);
+    // samples per task: a workgroup of the LDS kernels, a wave of the
+    // register-resident ones
+    const int per = pass ? (net->rbwd ? 16 : 16 * net->lim_bwd.wpb)
+                         : (net->rfwd ? 16 * net->sg : 16 * net->lim_fwd.wpb);
     std::vector<int32_t> ti, tc, ts;
     for (int q = 0; q < net->n_inst; ++q) {
       if (!net->use_chain[q]) continue;
@@ -259,9 +266,14 @@ tnvan_status ensure_chain_tasks(tnvan_net *net) {
   HIPCHK(upload(net->chain_list, clist));
   HIPCHK(net->cpart.ensure(std::max<int64_t>(1, ctot) * sizeof(double)));
   const ChainLim &L = net->lim_bwd;
-  const int64_t ncp = (L.max_steps + L.kseg - 1) / std::max(1, L.kseg);
-  HIPCHK(net->ckpt.ensure(std::max<int64_t>(1, (int64_t)net->n_btasks * L.wpb * ncp * 16 * L.kbuf) *
-                          sizeof(float)));
+  int64_t ckf = 0;
+  if (net->rbwd) {
+    ckf = (int64_t)net->n_btasks * rchain_ckpt_floats(L);
+  } else {
+    const int64_t ncp = (L.max_steps + L.kseg - 1) / std::max(1, L.kseg);
+    ckf = (int64_t)net->n_btasks * L.wpb * ncp * 16 * L.kbuf;
+  }
+  HIPCHK(net->ckpt.ensure(std::max<int64_t>(1, ckf) * sizeof(float)));
   net->n_chain_insts = (int)clist.size();
   net->ckey = net->nkey;
   return TNVAN_OK;
@@ -305,6 +317,12 @@ ChainArgs chain_args(tnvan_net *net, bool bwd) {
   a.ckpt = net->ckpt.as<float>();
   a.bf16 = (!bwd && net->precision == TNVAN_BF16) ? 1 : 0;
   a.ntm = std::max(16, (int)a.lim.kbuf) / 16;
+  a.Tr = net->Tr.as<float>();
+  a.Tq = net->Tq.as<float>();
+  a.Trb = net->Trb.as<uint16_t>();
+  a.xcol = net->xcol.as<int32_t>();
+  a.sg = net->sg;
+  if (bwd ? net->rbwd : net->rfwd) a.ntm = net->rtiles;
   return a;
 }
 
@@ -354,7 +372,7 @@ tnvan_status run_logz(tnvan_net *net, const int8_t *spins, double *logz, hipStre
     if (s) return s;
     ChainArgs c = chain_args(net, false);
     c.spins = spins;
-    HIPCHK(launch_chain(c, false, st));
+    HIPCHK(net->rfwd ? launch_rchain(c, false, st) : launch_chain(c, false, st));
     HIPCHK(launch_chain_sum(net->inst.as<InstDesc>(), net->cinst.as<ChainInst>(),
                             net->chain_list.as<int32_t>(), net->n_chain_insts,
                             net->d_B.as<int64_t>(), net->d_sample_off.as<int64_t>(),
@@ -390,7 +408,7 @@ tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *gra
     c.grad = grad;
     c.partial = reinterpret_cast<float *>(net->partial.p);
     c.inst_partial_off = tc.partial_off.as<int64_t>();
-    HIPCHK(launch_chain(c, true, st));
+    HIPCHK(net->rbwd ? launch_rchain(c, true, st) : launch_chain(c, true, st));
   }
   int64_t nh = 0, ne = 0;
   for (auto &D : net->P.insts) { nh += D.n; ne += D.n_edges; }
@@ -648,6 +666,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
     UP2(chains, P.chains) UP2(csteps, P.csteps) UP2(Tp, P.Tp) UP2(Tt, P.Tt) UP2(Tb, P.Tb)
   }
   UP2(Tl, P.Tl) UP2(Tbl, P.Tbl) UP2(cedges, P.cedges)
+  UP2(Tr, P.Tr) UP2(Tq, P.Tq) UP2(Trb, P.Trb) UP2(xcol, P.xcol)
   // transfer-matrix form: instances whose program is a set of dense chains
   // (FP32 / BF16 only); the launch-wide maxima size the LDS layout
   net->use_chain.assign(n_inst, 0);
@@ -656,6 +675,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
     hipGetDevice(&dev);
     hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     ChainLim lim{};
+    bool rq = true;
     lim.kbuf = 16;
     lim.kseg = 1;
     for (int q = 0; q < n_inst; ++q) {
@@ -672,12 +692,26 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
       lim.ne_max = std::max(lim.ne_max, C.ne_max);
       lim.nf_max = std::max(lim.nf_max, C.nf_max);
       lim.kseg = std::max(lim.kseg, chain_kseg(C));
+      net->rtiles = std::max(net->rtiles, C.rtiles);
+      rq = rq && C.rq_ok;
     }
+    const bool any = std::count(net->use_chain.begin(), net->use_chain.end(), 1) > 0;
+    // register-resident kernels when every chain step is narrow enough
+    const bool reg = any && !(opt->flags & TNVAN_FLAG_LDS_CHAIN);
+    net->rfwd = reg && net->rtiles <= kRegFwdTiles &&
+                4 * rchain_wave_lds(lim, false, net->sg) <= (size_t)maxlds;
+    net->rbwd = reg && rq && net->rtiles <= kRegBwdTiles &&
+                4 * rchain_wave_lds(lim, true, 1) <= (size_t)maxlds;
     const bool bf = net->precision == TNVAN_BF16;
     bool ok = true;
-    for (int pass = 0; pass < 2 && std::count(net->use_chain.begin(), net->use_chain.end(), 1); ++pass) {
+    for (int pass = 0; pass < 2 && any; ++pass) {
       const bool bwd = pass == 1;
       ChainLim L = lim;
+      L.wpb = 1;
+      if (bwd ? net->rbwd : net->rfwd) {
+        (bwd ? net->lim_bwd : net->lim_fwd) = L;
+        continue;
+      }
       L.tlds = 1;
       size_t sh = chain_shared_lds(L, bwd, bf && !bwd), per = chain_wave_lds(L, bwd);
       if (sh + per > (size_t)maxlds) {   // tables too large: read them from HBM
@@ -688,7 +722,10 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
       L.wpb = (int)std::min<size_t>(4, ((size_t)maxlds - sh) / per);
       (bwd ? net->lim_bwd : net->lim_fwd) = L;
     }
-    if (!ok) net->use_chain.assign(n_inst, 0);
+    if (!ok) {
+      net->use_chain.assign(n_inst, 0);
+      net->rfwd = net->rbwd = false;
+    }
   }
   choose_tiles(net, false);
   choose_tiles(net, true);
@@ -713,7 +750,7 @@ void tnvan_free_network(tnvan_net *net) {
                  &net->csteps, &net->Tp, &net->Tt, &net->Tb, &net->fld_wr, &net->fld_J32,
                  &net->hR32, &net->task_inst, &net->task_chain, &net->task_start,
                  &net->btask_inst, &net->btask_chain, &net->btask_start, &net->Tl, &net->Tbl,
-                 &net->cedges, &net->ckpt,
+                 &net->cedges, &net->ckpt, &net->Tr, &net->Tq, &net->Trb, &net->xcol,
                  &net->cpart_off, &net->chain_list, &net->cpart};
   for (DBuf *b : all) b->release();
   TileCache *tcs[] = {&net->tc_fwd, &net->tc_bwd};

@@ -116,6 +116,7 @@ void build_chains(const InstDesc &D, const std::vector<int32_t> &consumer, HostP
   }
   ci.ok = 1;
   ci.nw = D.nw;
+  bool ok_rq = true;
   ci.n_chains = (int32_t)chains.size();
   for (auto &ch : chains) {
     ChainDesc cd{};
@@ -175,7 +176,50 @@ void build_chains(const InstDesc &D, const std::vector<int32_t> &consumer, HostP
         P.Tl.push_back(0.0f);
       }
       cs.ce_off = (int32_t)P.cedges.size() - cd.e_src;
-      for (int k = 0; k < sd.n_edge; ++k) P.cedges.push_back(P.edges[sd.edge_off + k]);
+      // register-resident operand tables (program.h: R-layout)
+      auto tv = [&](int x, int o) {
+        return (x < K && o < N) ? (float)T[((int64_t)x << sd.w) | o] : 0.0f;
+      };
+      const int KT = cs.kp / 16, NT16 = sd.w == 0 ? 1 : cs.np / 16, KC2 = (KT + 1) / 2;
+      cs.nt16 = NT16;
+      ci.rtiles = std::max({ci.rtiles, KT, NT16});
+      cs.tr_off = (int64_t)P.Tr.size();
+      for (int nt = 0; nt < NT16; ++nt)
+        for (int xt = 0; xt < KT; ++xt)
+          for (int l = 0; l < 64; ++l)
+            for (int r = 0; r < 4; ++r) P.Tr.push_back(tv(16 * xt + 4 * (l >> 4) + r, 16 * nt + (l & 15)));
+      cs.tq_off = (int64_t)P.Tq.size();
+      for (int xt = 0; xt < KT; ++xt)
+        for (int nt = 0; nt < NT16; ++nt)
+          for (int l = 0; l < 64; ++l)
+            for (int r = 0; r < 4; ++r) P.Tq.push_back(tv(16 * xt + (l & 15), 16 * nt + 4 * (l >> 4) + r));
+      cs.trb_off = (int64_t)P.Trb.size();
+      for (int nt = 0; nt < NT16; ++nt)
+        for (int c = 0; c < KC2; ++c)
+          for (int l = 0; l < 64; ++l)
+            for (int i = 0; i < 8; ++i)
+              P.Trb.push_back(to_bf16(tv(16 * (2 * c + (i >> 2)) + 4 * (l >> 4) + (i & 3), 16 * nt + (l & 15))));
+      // adjoint columns: the group's spins, then the edges inside the group
+      cs.xc_off = (int32_t)P.xcol.size();
+      int32_t xc[16];
+      for (int c = 0; c < 16; ++c) xc[c] = c < sd.g ? (c | (31 << 8)) : -1;
+      int nxx = 0;
+      for (int k = 0; k < sd.n_edge; ++k) {
+        EdgeDesc e = P.edges[sd.edge_off + k];
+        if (e.bu < sd.w) std::swap(e.bu, e.bv);
+        if (e.bu < sd.w) { ok_rq = false; e.pad = 0; }
+        else if (e.bv >= sd.w) {
+          const int col = sd.g + nxx++;
+          if (col < 16 && sd.w < 16) xc[col] = (e.bu - sd.w) | ((e.bv - sd.w) << 8);
+          else ok_rq = false;
+          e.pad = col * 16 + sd.w;
+        } else {
+          e.pad = (e.bu - sd.w) * 16 + e.bv;
+        }
+        P.cedges.push_back(e);
+      }
+      if (sd.w >= 16) ok_rq = false;
+      for (int c = 0; c < 16; ++c) P.xcol.push_back(xc[c]);
       P.csteps.push_back(cs);
     }
     cd.tl_size = (int32_t)(P.Tl.size() - cd.tl_src);
@@ -187,6 +231,7 @@ void build_chains(const InstDesc &D, const std::vector<int32_t> &consumer, HostP
     ci.nf_max = std::max(ci.nf_max, cd.f_hi - cd.f_lo);
     P.chains.push_back(cd);
   }
+  ci.rq_ok = ok_rq ? 1 : 0;
   P.cinst.push_back(ci);
 }
 

@@ -41,6 +41,9 @@ struct HostProgram {
   std::vector<float> Tl;            // per chain: FP32 tables with rows padded by one
   std::vector<uint16_t> Tbl;        // per chain: BF16 operand-order tables
   std::vector<EdgeDesc> cedges;     // per chain: the edges of its steps
+  std::vector<float> Tr, Tq;        // register-resident operand tables
+  std::vector<uint16_t> Trb;
+  std::vector<int32_t> xcol;        // 16 adjoint column codes per chain step
 };
 
 // Appends one instance to P.  Returns TNVAN_OK or an error code with msg.

@@ -194,12 +194,26 @@ struct ChainArgs {
   float *ckpt;                      // adjoint checkpoints, per wave
   int32_t bf16;
   int32_t ntm;                      // largest K or N of the launch in 16-wide tiles
+  // register-resident kernels: per-wave tasks, permuted tables
+  const float *Tr, *Tq;
+  const uint16_t *Trb;
+  const int32_t *xcol;
+  int32_t sg;                       // 16-sample groups per wave (forward)
 };
 // LDS bytes: shared part of a workgroup and per-wave part
 size_t chain_shared_lds(const ChainLim &L, bool bwd, bool bf16);
 size_t chain_wave_lds(const ChainLim &L, bool bwd);
 int chain_kseg(const ChainInst &C);
 hipError_t launch_chain(const ChainArgs &a, bool bwd, hipStream_t st);
+// Register-resident chain kernels: one task (instance, chain, 16 * sg
+// samples; sg = 1 for the adjoint) per wave, four waves per workgroup.
+// Forward: steps of at most 4 tiles (K, N <= 64); adjoint: at most 2 tiles.
+constexpr int kRegFwdTiles = 4;
+constexpr int kRegBwdTiles = 2;
+constexpr int kRegSeg = 4;            // adjoint checkpoint interval
+size_t rchain_wave_lds(const ChainLim &L, bool bwd, int sg);
+int64_t rchain_ckpt_floats(const ChainLim &L);   // per adjoint task
+hipError_t launch_rchain(const ChainArgs &a, bool bwd, hipStream_t st);
 // logz[b] = log_const + sum over chains of the per-chain partials
 hipError_t launch_chain_sum(const InstDesc *inst, const ChainInst *cinst,
                             const int32_t *chain_insts, int n_chain_insts,

@@ -109,7 +109,29 @@ struct ChainStep {
   int64_t tp_off;     // FP32 [kp][np]
   int64_t tt_off;     // FP32 [np][kp] (transposed, for the adjoint)
   int64_t tb_off;     // BF16 packed in the 16x16x32 operand order
+  // register-resident form (see the comment below)
+  int64_t tr_off;     // FP32 [nt][xt][lane][4]: T[16xt + 4(lane>>4) + r][16nt + (lane&15)]
+  int64_t tq_off;     // FP32 [xt][nt][lane][4]: T[16xt + (lane&15)][16nt + 4(lane>>4) + r]
+  int64_t trb_off;    // BF16 [nt][c][lane][8]: T[16(2c + i/4) + 4(lane>>4) + i%4][16nt + (lane&15)]
+  int32_t nt16;       // output tiles of 16 (1 for the closing step)
+  int32_t xc_off;     // 16 column codes of the adjoint's spin-product matrix
 };
+
+// Register-resident layout ("R-layout") of a per-sample vector over 16*KT
+// states on one 64-lane wave: lane l holds, for sample l & 15, the states
+// 16 t + 4 (l >> 4) + r in register [t][r].  This is the output layout of a
+// 16x16x4 FP32 matrix-core product D = T^T A^T (rows = states, columns =
+// samples), and the operand layout the next such product reads, so a chain
+// runs from register to register; the tables above are the transfer
+// matrices permuted into that operand order.
+//
+// Adjoint column codes (xc): column c of S_x is the spin product
+// sigma_u(x) sigma_v(x) with u = code & 0xff, v = (code >> 8) & 0xff
+// (v = 31 means a single spin), or a zero column when code < 0.  Columns
+// 0..g-1 are the group's spins, then one column per edge with both ends in
+// the group.  Every edge of the step stores in EdgeDesc::pad the cell
+// (column * 16 + output-spin row) of S_x^T G S_o that holds its correlation
+// (row w = the all-ones column of S_o).
 
 struct ChainDesc {
   int32_t n_steps, cs_off;   // ChainStep range
@@ -136,6 +158,8 @@ struct ChainInst {
   int32_t tbl_max;           // largest tbl_size
   int32_t ne_max;            // most edges of one chain
   int32_t nf_max;            // most W-neighbour entries of one chain
+  int32_t rtiles;            // widest step in 16-state tiles (register-resident form)
+  int32_t rq_ok;             // every step fits the 16-column adjoint products
   int32_t pad;
 };
 

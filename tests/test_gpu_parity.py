@@ -169,3 +169,24 @@ def test_edge_cases():
                - OI.logz_r_elimination(inst, sp)[0]) / 256 < 1e-5
     out = net.logz(torch.zeros(0, dtype=torch.int8, device="cuda"), 0)
     assert out.numel() == 0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("case", ["c1", "c2_b2", "lat8_field"])
+def test_lds_chain_kernels(case, prec):
+    # the LDS-staged transfer-matrix kernels, kept for steps wider than the
+    # register-resident kernels take, forced on narrow chains
+    inst = CASES[case]()
+    B = 333
+    print(f"\n[lds-chain] case={case} prec={prec} B={B}", flush=True)
+    spins = S.uniform_spins(B, inst.n_width, 11 + B)
+    net = _net([inst], prec, flags=1)
+    got = net.logz(_dev(spins), B).cpu().numpy()
+    want = _oracle_logz(inst, spins)
+    assert (np.abs(got - want) / inst.n).max() <= TOL[prec]
+    g = np.random.default_rng(B).standard_normal(B)
+    dh, dJ, db = net.backward(_dev(spins), _dev(g), B)
+    wdh, wdJ, wdb = OI.logz_r_vjp(inst, spins, g)
+    tol = GTOL[prec] * np.abs(g).sum() * max(inst.beta, 1.0)
+    np.testing.assert_allclose(dh.cpu().numpy(), wdh, atol=tol, rtol=0)
+    np.testing.assert_allclose(dJ.cpu().numpy(), wdJ, atol=tol, rtol=0)
