@@ -118,6 +118,12 @@ struct tnvan_net {
   DBuf Tr, Tq, Trb, xcol;
   bool rfwd = false, rbwd = false;
   int rtiles = 1, sg = 2;
+  // matrix-core sampler
+  bool msample = false;
+  int mpt = 1;
+  int64_t mpack_total = 0, mpack_max = 0;
+  DBuf mpack, mtask_inst, mtask_start;
+  int n_mtasks = 0;
   DBuf task_inst, task_chain, task_start, btask_inst, btask_chain, btask_start, cpart_off,
       chain_list, cpart;
   int n_tasks = 0, n_btasks = 0, n_chain_insts = 0;
@@ -439,6 +445,15 @@ tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *gra
 
 tnvan_status ensure_sample_blocks(tnvan_net *net) {
   if (net->skey == net->nkey) return TNVAN_OK;
+  {
+    // matrix-core sampler: one wave per 16 samples
+    std::vector<int32_t> ti, ts;
+    for (int q = 0; q < net->n_inst; ++q)
+      for (int64_t b = 0; b < net->nkey[q]; b += 16) { ti.push_back(q); ts.push_back((int32_t)b); }
+    HIPCHK(upload(net->mtask_inst, ti));
+    HIPCHK(upload(net->mtask_start, ts));
+    net->n_mtasks = (int)ti.size();
+  }
   net->h_blk_inst.clear();
   net->h_blk_start.clear();
   const int spb = 256 / net->mi[0].L;
@@ -465,6 +480,24 @@ tnvan_status run_sample(tnvan_net *net, const float *uniforms, int8_t *spins, vo
                         hipStream_t st) {
   tnvan_status s = ensure_sample_blocks(net);
   if (s) return s;
+  if (net->msample && sizeof(real) == 4) {
+    HIPCHK(net->mpack.ensure(std::max<int64_t>(1, net->mpack_total) * sizeof(float)));
+    HIPCHK(launch_made_pack(net->d_mi.as<MadeInst>(), net->n_inst, net->mpack_max,
+                            net->params.as<float>(), net->mpack.as<float>(), net->mpt, st));
+    MSampleArgs m{};
+    m.mi = net->d_mi.as<MadeInst>();
+    m.pack = net->mpack.as<float>();
+    m.task_inst = net->mtask_inst.as<int32_t>();
+    m.task_start = net->mtask_start.as<int32_t>();
+    m.n_tasks = net->n_mtasks;
+    m.uniforms = uniforms;
+    m.spins = spins;
+    m.logq = reinterpret_cast<float *>(logq);
+    m.seed = net->seed;
+    m.step_ctr = net->step_ctr.as<int32_t>();
+    HIPCHK(launch_msample(m, net->mpt, st));
+    return TNVAN_OK;
+  }
   SampleArgs<real> a{};
   a.mi = net->d_mi.as<MadeInst>();
   a.params = net->params.as<float>();
@@ -615,6 +648,25 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   for (auto &m : net->mi) Lmax = std::max(Lmax, (int)m.L);
   for (auto &m : net->mi) m.L = Lmax;
   net->param_total = poff;
+  // matrix-core sampler: every instance with n <= 64 and at most 15 hidden
+  // units per degree (FP32 / BF16 precisions)
+  {
+    int nmax = 1;
+    bool fits = net->precision != TNVAN_FP64;
+    for (auto &m : net->mi) {
+      nmax = std::max(nmax, (int)m.n);
+      if (m.n > 64 || (m.n >= 2 && m.H > 15 * (m.n - 1))) fits = false;
+    }
+    net->mpt = nmax <= 16 ? 1 : nmax <= 32 ? 2 : 4;
+    net->msample = fits;
+    int64_t po = 0;
+    for (auto &m : net->mi) {
+      m.pack_off = po;
+      po += made_pack_floats(m.n, net->mpt);
+      net->mpack_max = std::max(net->mpack_max, made_pack_floats(m.n, net->mpt));
+    }
+    net->mpack_total = po;
+  }
   auto fail = [&](hipError_t e, const char *what) {
     tnvan_free_network(net);
     return set_err(e == hipErrorOutOfMemory ? TNVAN_E_NOMEM : TNVAN_E_HIP, "%s: %s", what,
@@ -751,6 +803,7 @@ void tnvan_free_network(tnvan_net *net) {
                  &net->hR32, &net->task_inst, &net->task_chain, &net->task_start,
                  &net->btask_inst, &net->btask_chain, &net->btask_start, &net->Tl, &net->Tbl,
                  &net->cedges, &net->ckpt, &net->Tr, &net->Tq, &net->Trb, &net->xcol,
+                 &net->mpack, &net->mtask_inst, &net->mtask_start,
                  &net->cpart_off, &net->chain_list, &net->cpart};
   for (DBuf *b : all) b->release();
   TileCache *tcs[] = {&net->tc_fwd, &net->tc_bwd};

@@ -81,6 +81,7 @@ struct MadeInst {
   int32_t L;                // lanes per sample in the sampler
   int32_t pad;
   int64_t param_off;        // offset of the instance's parameters
+  int64_t pack_off;         // offset of its matrix-core sampler tables
   int64_t sample_off;       // first global sample
   int64_t B;                // samples
   int64_t spin_off;         // first spin
@@ -105,6 +106,25 @@ template <typename real>
 hipError_t launch_sample(const SampleArgs<real> &a, int n_blocks, size_t stage_bytes,
                          hipStream_t st);
 size_t made_param_bytes(int n, int H);
+
+// Matrix-core sampler (FP32): one wave per 16 samples of one instance.
+// Needs n <= 64 and at most 15 hidden units per degree (H <= 15 (n - 1)).
+struct MSampleArgs {
+  const MadeInst *mi;
+  const float *pack;            // repacked parameters (made_pack_kernel)
+  const int32_t *task_inst;     // per wave
+  const int32_t *task_start;    // first local sample of the wave
+  int32_t n_tasks;
+  const float *uniforms;        // null => Philox
+  int8_t *spins;
+  float *logq;
+  uint64_t seed;
+  const int32_t *step_ctr;
+};
+int64_t made_pack_floats(int n, int npt);
+hipError_t launch_made_pack(const MadeInst *mi, int n_inst, int64_t max_floats, const float *params,
+                            float *pack, int npt, hipStream_t st);
+hipError_t launch_msample(const MSampleArgs &a, int npt, hipStream_t st);
 
 // Per-sample rows of the log-prob pass and the REINFORCE backward.
 template <typename real>

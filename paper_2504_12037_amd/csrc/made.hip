@@ -9,6 +9,8 @@
 // W1 [H,n], b1 [H], W2 [n,H], b2 [n], W0 [n,n].
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "launch.h"
 
 namespace tnvan {
@@ -433,11 +435,210 @@ __global__ void bump_kernel(int32_t *c, int n) {
   if (i < n) c[i] += 1;
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-core sampler (FP32).  A wave draws 16 samples.  Logits z and spins
+// of the wave's samples live in the R-layout of the chain kernels (lane l
+// holds positions 16 t + 4 (l >> 4) + r of sample l & 15).  After position i
+// is drawn, the hidden units of degree i + 1 are complete: their
+// activations are one 16x16x4 product over the spins drawn so far, and
+// their tanh values (plus the direct W0 term of s_i in slot 15) are folded
+// into every later logit by a second product.  Both products read
+// parameters repacked into operand order by made_pack_kernel.
+//
+// Packed layout per instance (floats, NPT position tiles):
+//   PA  [n][NPT][64][4]  W1[k(i, l & 15)][16 t + 4 (l >> 4) + r], j <= i
+//   PZ  [n][NPT][64][4]  slot u = 4 (l >> 4) + r:  W2[16 t + (l & 15)][k(i, u)]
+//                        for u < 15, W0[16 t + (l & 15)][i] for u = 15
+//                        (zero unless the output position is > i)
+//   PB1 [n][64][4]       b1[k(i, 4 (l >> 4) + r)]
+//   PB2 [NPT][64][4]     b2[16 t + 4 (l >> 4) + r]
+// with k(i, u) = i + (n - 1) u the u-th hidden unit of degree i + 1.
+
+__host__ __device__ inline int64_t mpack_floats(int n, int npt) {
+  return (int64_t)n * npt * 512 + (int64_t)n * 256 + (int64_t)npt * 256;
+}
+
+__global__ void made_pack_kernel(const MadeInst *mi, const float *params, float *pack, int npt) {
+  const MadeInst m = mi[blockIdx.y];
+  const int n = m.n, Hs = m.H, H = n >= 2 ? m.H : 0;
+  const float *W1 = params + m.param_off, *b1 = W1 + (int64_t)Hs * n, *W2 = b1 + Hs,
+              *b2 = W2 + (int64_t)n * Hs, *W0 = b2 + n;
+  const int64_t sa = (int64_t)n * npt * 256, sb = (int64_t)n * 256;
+  const int64_t total = mpack_floats(n, npt);
+  float *P = pack + m.pack_off;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    float v = 0.f;
+    if (idx < 2 * sa) {
+      const int64_t e = idx < sa ? idx : idx - sa;
+      const int r = (int)(e & 3), lane = (int)((e >> 2) & 63);
+      const int t = (int)((e >> 8) % npt), i = (int)((e >> 8) / npt);
+      const int ls = lane & 15, lg = lane >> 4;
+      if (idx < sa) {
+        const int k = i + (n - 1) * ls, j = 16 * t + 4 * lg + r;
+        if (i < n - 1 && ls < 15 && k < H && j <= i) v = W1[(int64_t)k * n + j];
+      } else {
+        const int u = 4 * lg + r, ip = 16 * t + ls;
+        if (ip < n && ip > i) {
+          if (u == 15) {
+            v = W0[(int64_t)ip * n + i];
+          } else {
+            const int k = i + (n - 1) * u;
+            if (i < n - 1 && k < H) v = W2[(int64_t)ip * Hs + k];
+          }
+        }
+      }
+    } else if (idx < 2 * sa + sb) {
+      const int64_t e = idx - 2 * sa;
+      const int r = (int)(e & 3), lane = (int)((e >> 2) & 63), i = (int)(e >> 8);
+      const int u = 4 * (lane >> 4) + r, k = i + (n - 1) * u;
+      if (i < n - 1 && u < 15 && k < H) v = b1[k];
+    } else {
+      const int64_t e = idx - 2 * sa - sb;
+      const int r = (int)(e & 3), lane = (int)((e >> 2) & 63), t = (int)(e >> 8);
+      const int pos = 16 * t + 4 * (lane >> 4) + r;
+      if (pos < n) v = b2[pos];
+    }
+    P[idx] = v;
+  }
+}
+
+template <int NPT>
+__global__ __launch_bounds__(256) void msample_kernel(MSampleArgs a) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63, ls = lane & 15, lg = lane >> 4;
+  const int task = blockIdx.x * 4 + wave;
+  if (task >= a.n_tasks) return;
+  const int q = a.task_inst[task];
+  const MadeInst mi = a.mi[q];
+  const int n = mi.n;
+  const int64_t b = a.task_start[task] + ls;
+  const bool live = b < mi.B;
+  const int64_t sa = (int64_t)n * NPT * 64;   // in f4 units
+  const f4 *PA = reinterpret_cast<const f4 *>(a.pack + mi.pack_off) + lane;
+  const f4 *PZ = PA + sa;
+  const f4 *PB1 = PZ + sa;
+  const f4 *PB2 = PB1 + (int64_t)n * 64;
+  const uint32_t step = a.step_ctr ? (uint32_t)a.step_ctr[q] : 0u;
+  f4 z[NPT];
+  float sp[NPT][4];
+#pragma unroll
+  for (int t = 0; t < NPT; ++t) {
+    z[t] = PB2[t * 64];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sp[t][r] = 0.f;
+  }
+  float lq = 0.f;
+  uint32_t pw[4] = {0u, 0u, 0u, 0u};
+  const float *u = a.uniforms ? a.uniforms + mi.spin_off + (live ? b : 0) * n : nullptr;
+  f4 pa[NPT], pz[NPT], pb;
+#pragma unroll
+  for (int t = 0; t < NPT; ++t) {
+    pa[t] = PA[t * 64];
+    pz[t] = PZ[t * 64];
+  }
+  pb = PB1[0];
+  for (int i = 0; i < n; ++i) {
+    f4 cpa[NPT], cpz[NPT];
+#pragma unroll
+    for (int t = 0; t < NPT; ++t) { cpa[t] = pa[t]; cpz[t] = pz[t]; }
+    const f4 cpb = pb;
+    if (i + 1 < n) {
+#pragma unroll
+      for (int t = 0; t < NPT; ++t) {
+        pa[t] = PA[((int64_t)(i + 1) * NPT + t) * 64];
+        pz[t] = PZ[((int64_t)(i + 1) * NPT + t) * 64];
+      }
+      pb = PB1[(int64_t)(i + 1) * 64];
+    }
+    // logit of position i, held by the lanes of row (i >> 2) & 3
+    const int ti = i >> 4, ri = i & 3, gi = (i >> 2) & 3;
+    float own = 0.f;
+#pragma unroll
+    for (int t = 0; t < NPT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (t == ti && r == ri) own = z[t][r];
+    const float zi = __shfl(own, 16 * gi + ls, 64);
+    float ui;
+    if (u) {
+      ui = live ? u[i] : 0.5f;
+    } else {
+      if ((i & 3) == 0) {
+        pw[0] = (uint32_t)(i >> 2); pw[1] = (uint32_t)b; pw[2] = step; pw[3] = (uint32_t)q;
+        philox4x32_10(pw, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+      }
+      const uint32_t wd = (i & 3) == 0 ? pw[0] : (i & 3) == 1 ? pw[1] : (i & 3) == 2 ? pw[2] : pw[3];
+      ui = (float)(wd >> 8) * 5.9604644775390625e-08f;
+    }
+    const float p = sigmoid<float>(zi);
+    const float si = ui < p ? 1.f : -1.f;
+    lq += log_sigmoid<float>(si * zi);
+    if (lg == gi) {
+#pragma unroll
+      for (int t = 0; t < NPT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (t == ti && r == ri) sp[t][r] = si;
+    }
+    // hidden units of degree i + 1, then every later logit
+    f4 acc = cpb;
+#pragma unroll
+    for (int t = 0; t < NPT; ++t)
+      if (t <= ti)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(cpa[t][r], sp[t][r], acc, 0, 0, 0);
+    float h[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h[r] = tanhf(acc[r]);
+    if (lg == 3) h[3] = si;
+#pragma unroll
+    for (int t = 0; t < NPT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        z[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(cpz[t][r], h[r], z[t], 0, 0, 0);
+  }
+  if (live) {
+    int8_t *so = a.spins + mi.spin_off + b * n;
+#pragma unroll
+    for (int t = 0; t < NPT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int pos = 16 * t + 4 * lg + r;
+        if (pos < n) so[pos] = (int8_t)(sp[t][r] > 0.f ? 1 : -1);
+      }
+    if (lg == 0) a.logq[mi.sample_off + b] = lq;
+  }
+}
+
 }  // namespace
 
 constexpr size_t kStageMax = 96 * 1024;
 
 size_t made_param_bytes(int n, int H) { return made_stage_bytes(n, H); }
+
+int64_t made_pack_floats(int n, int npt) { return mpack_floats(n, npt); }
+
+hipError_t launch_made_pack(const MadeInst *mi, int n_inst, int64_t max_floats, const float *params,
+                            float *pack, int npt, hipStream_t st) {
+  if (n_inst <= 0) return hipSuccess;
+  const int bx = (int)std::min<int64_t>(256, (max_floats + 255) / 256);
+  hipLaunchKernelGGL(made_pack_kernel, dim3(std::max(1, bx), n_inst), dim3(256), 0, st, mi, params,
+                     pack, npt);
+  return hipGetLastError();
+}
+
+hipError_t launch_msample(const MSampleArgs &a, int npt, hipStream_t st) {
+  if (a.n_tasks <= 0) return hipSuccess;
+  const dim3 grid((a.n_tasks + 3) / 4);
+  if (npt <= 1) hipLaunchKernelGGL(msample_kernel<1>, grid, dim3(256), 0, st, a);
+  else if (npt <= 2) hipLaunchKernelGGL(msample_kernel<2>, grid, dim3(256), 0, st, a);
+  else if (npt <= 4) hipLaunchKernelGGL(msample_kernel<4>, grid, dim3(256), 0, st, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
 
 template <typename real>
 hipError_t launch_sample(const SampleArgs<real> &a, int n_blocks, size_t stage_bytes,
