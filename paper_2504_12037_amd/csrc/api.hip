@@ -124,6 +124,12 @@ struct tnvan_net {
   int64_t mpack_total = 0, mpack_max = 0;
   DBuf mpack, mtask_inst, mtask_start;
   int n_mtasks = 0;
+  // fused REINFORCE backward
+  bool mgrad = false;
+  int mg_hmax = 0;
+  int64_t mg_pstride = 0;
+  DBuf mg_task_inst, mg_task_start, mg_first, mg_count;
+  int n_mgtasks = 0;
   DBuf task_inst, task_chain, task_start, btask_inst, btask_chain, btask_start, cpart_off,
       chain_list, cpart;
   int n_tasks = 0, n_btasks = 0, n_chain_insts = 0;
@@ -453,6 +459,18 @@ tnvan_status ensure_sample_blocks(tnvan_net *net) {
     HIPCHK(upload(net->mtask_inst, ti));
     HIPCHK(upload(net->mtask_start, ts));
     net->n_mtasks = (int)ti.size();
+    // fused REINFORCE backward: one workgroup per 64 samples
+    std::vector<int32_t> gi, gs, gf(net->n_inst), gc(net->n_inst);
+    for (int q = 0; q < net->n_inst; ++q) {
+      gf[q] = (int32_t)gi.size();
+      for (int64_t b = 0; b < net->nkey[q]; b += 64) { gi.push_back(q); gs.push_back((int32_t)b); }
+      gc[q] = (int32_t)gi.size() - gf[q];
+    }
+    HIPCHK(upload(net->mg_task_inst, gi));
+    HIPCHK(upload(net->mg_task_start, gs));
+    HIPCHK(upload(net->mg_first, gf));
+    HIPCHK(upload(net->mg_count, gc));
+    net->n_mgtasks = (int)gi.size();
   }
   net->h_blk_inst.clear();
   net->h_blk_start.clear();
@@ -549,9 +567,39 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
   f.part = net->w_fpart.as<double>();
   f.stats = stats;
   HIPCHK(launch_free<real>(f, net->n_inst, st));
+  if (net->mgrad && sizeof(real) == 4) {
+    // fused REINFORCE backward of every instance (Eq. 10)
+    HIPCHK(net->w_part.ensure(std::max<int64_t>(1, (int64_t)net->n_mgtasks * net->mg_pstride) *
+                              sizeof(float)));
+    MGradArgs g{};
+    g.mi = net->d_mi.as<MadeInst>();
+    g.n_inst = net->n_inst;
+    g.hmax = net->mg_hmax;
+    g.params = net->params.as<float>();
+    g.spins = spins;
+    g.f = net->w_f.as<double>();
+    g.stats = stats;
+    g.task_inst = net->mg_task_inst.as<int32_t>();
+    g.task_start = net->mg_task_start.as<int32_t>();
+    g.n_tasks = net->n_mgtasks;
+    g.part = net->w_part.as<float>();
+    g.pstride = net->mg_pstride;
+    g.first_row = net->mg_first.as<int32_t>();
+    g.n_rows = net->mg_count.as<int32_t>();
+    g.grad = net->grad.as<float>();
+    HIPCHK(launch_mgrad(g, net->mpt, st));
+  }
   for (int q = 0; q < net->n_inst; ++q) {
     const MadeInst &m = net->mi[q];
     if (m.B <= 0) continue;
+    float *g = net->grad.as<float>() + m.param_off;
+    if (net->mgrad && sizeof(real) == 4) {
+      HIPCHK(launch_adam(net->params.as<float>() + m.param_off, g,
+                         net->adam_m.as<float>() + m.param_off,
+                         net->adam_v.as<float>() + m.param_off, net->param_count[q], lr,
+                         net->step_ctr.as<int32_t>() + q, st));
+      continue;
+    }
     // REINFORCE backward through q (Eq. 10): per-sample rows, then batch sums
     const int n = m.n, H = m.H;
     HIPCHK(net->w_hid.ensure(std::max<int64_t>(1, m.B * H) * sizeof(real)));
@@ -573,7 +621,6 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     const int ks = (int)std::max<int64_t>(1, std::min<int64_t>(64, m.B / 256));
     const int64_t maxmn = std::max<int64_t>({(int64_t)n * H, (int64_t)n * n, (int64_t)H});
     HIPCHK(net->w_part.ensure(std::max<int64_t>(1, maxmn * ks) * sizeof(real)));
-    float *g = net->grad.as<float>() + m.param_off;
     float *gW1 = g, *gb1 = g + (int64_t)H * n, *gW2 = gb1 + H, *gb2 = gW2 + (int64_t)n * H,
           *gW0 = gb2 + n;
     real *part = net->w_part.as<real>();
@@ -666,6 +713,18 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
       net->mpack_max = std::max(net->mpack_max, made_pack_floats(m.n, net->mpt));
     }
     net->mpack_total = po;
+    // fused REINFORCE backward: n <= 64, H <= 256, rows of 64 samples in LDS
+    int dev = 0, maxlds = 65536;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    bool gfit = net->precision != TNVAN_FP64;
+    for (auto &m : net->mi) {
+      net->mg_hmax = std::max(net->mg_hmax, (int)m.H);
+      if (m.n > 64 || m.H > 256) gfit = false;
+    }
+    for (auto pc : net->param_count) net->mg_pstride = std::max(net->mg_pstride, pc);
+    net->mg_pstride = (net->mg_pstride + 63) / 64 * 64;
+    net->mgrad = gfit && mgrad_lds_bytes(net->mg_hmax, net->mpt) <= (size_t)maxlds;
   }
   auto fail = [&](hipError_t e, const char *what) {
     tnvan_free_network(net);
@@ -803,7 +862,8 @@ void tnvan_free_network(tnvan_net *net) {
                  &net->hR32, &net->task_inst, &net->task_chain, &net->task_start,
                  &net->btask_inst, &net->btask_chain, &net->btask_start, &net->Tl, &net->Tbl,
                  &net->cedges, &net->ckpt, &net->Tr, &net->Tq, &net->Trb, &net->xcol,
-                 &net->mpack, &net->mtask_inst, &net->mtask_start,
+                 &net->mpack, &net->mtask_inst, &net->mtask_start, &net->mg_task_inst,
+                 &net->mg_task_start, &net->mg_first, &net->mg_count,
                  &net->cpart_off, &net->chain_list, &net->cpart};
   for (DBuf *b : all) b->release();
   TileCache *tcs[] = {&net->tc_fwd, &net->tc_bwd};

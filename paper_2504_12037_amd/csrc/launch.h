@@ -121,6 +121,26 @@ struct MSampleArgs {
   uint64_t seed;
   const int32_t *step_ctr;
 };
+// Fused REINFORCE backward (FP32): one workgroup per 64 samples of one
+// instance writes a masked partial gradient row; rows are then summed per
+// instance in a fixed order into grad.  Needs n <= 64 and H <= 256.
+struct MGradArgs {
+  const MadeInst *mi;
+  int32_t n_inst, hmax;
+  const float *params;
+  const int8_t *spins;          // all instances
+  const double *f;              // f_b per global sample
+  const double *stats;          // [n_inst][4], F_q first
+  const int32_t *task_inst;     // per workgroup
+  const int32_t *task_start;    // first local sample (multiple of 64)
+  int32_t n_tasks;
+  float *part;                  // [n_tasks][pstride]
+  int64_t pstride;
+  const int32_t *first_row, *n_rows;   // per instance: its workgroup rows
+  float *grad;                  // flat parameter gradient
+};
+size_t mgrad_lds_bytes(int H, int npt);
+hipError_t launch_mgrad(const MGradArgs &a, int npt, hipStream_t st);
 int64_t made_pack_floats(int n, int npt);
 hipError_t launch_made_pack(const MadeInst *mi, int n_inst, int64_t max_floats, const float *params,
                             float *pack, int npt, hipStream_t st);

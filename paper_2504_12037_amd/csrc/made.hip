@@ -613,6 +613,237 @@ __global__ __launch_bounds__(256) void msample_kernel(MSampleArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fused REINFORCE backward through q (Eq. 10), FP32 on the matrix cores.
+// A workgroup of 4 waves takes 64 samples of one instance.  Each wave first
+// computes the rows of its 16 samples in R-layout: a = b1 + W1m s, h = tanh a,
+// logits z = b2 + W2m h + W0m s, dlogit = w ((1 + s)/2 - sigmoid z) with
+// w = (f_b - F_q) / B, dh = W2m^T dlogit and da = dh (1 - h^2), and writes
+// h, da, dlogit and s sample-major into LDS.  After one barrier the
+// gradient blocks are products over the 64 samples, each wave owning a
+// share of the 16x16 output tiles:  gW2 = dlogit^T h,  gW0 = dlogit^T s,
+// gW1 = da^T s;  the bias gradients are column sums.  The workgroup writes
+// its masked partial gradient as one row; mgrad_reduce sums the rows of an
+// instance in a fixed order.
+constexpr int kMgTiles = 16;    // hidden tiles (H <= 256)
+
+struct MgLayout {
+  int ldh, ldn;
+  size_t hid, da, dl, sf, end;
+};
+__host__ __device__ inline MgLayout mg_layout(int H, int npt) {
+  MgLayout L;
+  const int ht = (H + 15) / 16 > 0 ? (H + 15) / 16 : 1;
+  L.ldh = 16 * ht + 4;
+  L.ldn = 16 * npt + 4;
+  L.hid = 0;
+  L.da = L.hid + (size_t)64 * L.ldh * 4;
+  L.dl = L.da + (size_t)64 * L.ldh * 4;
+  L.sf = L.dl + (size_t)64 * L.ldn * 4;
+  L.end = L.sf + (size_t)64 * L.ldn * 4;
+  return L;
+}
+
+template <int NPT>
+__global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  extern __shared__ __align__(16) char smem[];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63, ls = lane & 15, lg = lane >> 4;
+  const int q = a.task_inst[blockIdx.x];
+  const MadeInst mi = a.mi[q];
+  const int n = mi.n, Hs = mi.H, H = n >= 2 ? mi.H : 0;
+  const int HT = (Hs + 15) / 16;   // tiles cover every stored unit; masks use H
+  const int64_t bw = a.task_start[blockIdx.x];
+  const MgLayout Lm = mg_layout(Hs, NPT);
+  float *hid = reinterpret_cast<float *>(smem + Lm.hid);
+  float *dab = reinterpret_cast<float *>(smem + Lm.da);
+  float *dlb = reinterpret_cast<float *>(smem + Lm.dl);
+  float *sfb = reinterpret_cast<float *>(smem + Lm.sf);
+  const float *W1 = a.params + mi.param_off, *b1 = W1 + (int64_t)Hs * n, *W2 = b1 + Hs,
+              *b2 = W2 + (int64_t)n * Hs, *W0 = b2 + n;
+  const int nm1 = n > 1 ? n - 1 : 1;
+  {
+    // rows of the wave's 16 samples
+    const int64_t sb = bw + 16 * wave + ls;
+    const bool valid = sb < mi.B;
+    const int8_t *spn = a.spins + mi.spin_off + (valid ? sb : 0) * n;
+    float sp[NPT][4];
+#pragma unroll
+    for (int t = 0; t < NPT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int pos = 16 * t + 4 * lg + r;
+        sp[t][r] = (valid && pos < n) ? (float)spn[pos] : 0.f;
+      }
+    const float wt = valid ? (float)((a.f[mi.sample_off + sb] - a.stats[4 * q]) / (double)mi.B) : 0.f;
+    float h[kMgTiles][4];
+#pragma unroll
+    for (int ht = 0; ht < kMgTiles; ++ht) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h[ht][r] = 0.f;
+      if (ht < HT) {
+        f4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int k = 16 * ht + 4 * lg + r;
+          acc[r] = k < H ? b1[k] : 0.f;
+        }
+        const int ka = 16 * ht + ls, dga = 1 + ka % nm1;
+#pragma unroll
+        for (int t = 0; t < NPT; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int j = 16 * t + 4 * lg + r;
+            const float wv = (ka < H && j < dga && j < n) ? W1[(int64_t)ka * n + j] : 0.f;
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, sp[t][r], acc, 0, 0, 0);
+          }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h[ht][r] = (16 * ht + 4 * lg + r < H) ? tanhf(acc[r]) : 0.f;
+      }
+    }
+    float dl[NPT][4];
+#pragma unroll
+    for (int pt = 0; pt < NPT; ++pt) {
+      f4 z;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int pos = 16 * pt + 4 * lg + r;
+        z[r] = pos < n ? b2[pos] : 0.f;
+      }
+      const int pa = 16 * pt + ls;
+#pragma unroll
+      for (int ht = 0; ht < kMgTiles; ++ht)
+        if (ht < HT)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int k = 16 * ht + 4 * lg + r;
+            const float wv = (pa < n && k < H && 1 + k % nm1 <= pa) ? W2[(int64_t)pa * Hs + k] : 0.f;
+            z = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, h[ht][r], z, 0, 0, 0);
+          }
+#pragma unroll
+      for (int t = 0; t < NPT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = 16 * t + 4 * lg + r;
+          const float wv = (pa < n && j < pa) ? W0[(int64_t)pa * n + j] : 0.f;
+          z = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, sp[t][r], z, 0, 0, 0);
+        }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int pos = 16 * pt + 4 * lg + r;
+        const float s1 = sp[pt][r];
+        dl[pt][r] = pos < n ? wt * ((1.f + s1) * 0.5f - sigmoid<float>(z[r])) : 0.f;
+      }
+    }
+    const int srow = 16 * wave + ls;
+#pragma unroll
+    for (int pt = 0; pt < NPT; ++pt) {
+      *reinterpret_cast<f4 *>(dlb + srow * Lm.ldn + 16 * pt + 4 * lg) =
+          f4{dl[pt][0], dl[pt][1], dl[pt][2], dl[pt][3]};
+      *reinterpret_cast<f4 *>(sfb + srow * Lm.ldn + 16 * pt + 4 * lg) =
+          f4{sp[pt][0], sp[pt][1], sp[pt][2], sp[pt][3]};
+    }
+#pragma unroll
+    for (int ht = 0; ht < kMgTiles; ++ht)
+      if (ht < HT) {
+        f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+        const int ka = 16 * ht + ls, dga = 1 + ka % nm1;
+#pragma unroll
+        for (int pt = 0; pt < NPT; ++pt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int pos = 16 * pt + 4 * lg + r;
+            const float wv = (ka < H && pos < n && dga <= pos) ? W2[(int64_t)pos * Hs + ka] : 0.f;
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, dl[pt][r], acc, 0, 0, 0);
+          }
+        *reinterpret_cast<f4 *>(hid + srow * Lm.ldh + 16 * ht + 4 * lg) =
+            f4{h[ht][0], h[ht][1], h[ht][2], h[ht][3]};
+        f4 dv;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dv[r] = acc[r] * (1.f - h[ht][r] * h[ht][r]);
+        *reinterpret_cast<f4 *>(dab + srow * Lm.ldh + 16 * ht + 4 * lg) = dv;
+      }
+  }
+  __syncthreads();
+  // gradient tiles: [0, NPT*HT) gW2 (pt, ht); then NPT*NPT gW0 (pt, jt);
+  // then HT*NPT gW1 (ht, jt); wave w takes tiles w, w + 4, ...
+  float *prow = a.part + (int64_t)blockIdx.x * a.pstride;
+  const int n2 = NPT * HT, n0 = NPT * NPT, n1 = HT * NPT;
+  const int ntile = n2 + n0 + n1;
+  const int64_t o_b1 = (int64_t)Hs * n, o_W2 = o_b1 + Hs, o_b2 = o_W2 + (int64_t)n * Hs,
+                o_W0 = o_b2 + n;
+  for (int tile = wave; tile < ntile; tile += 4) {
+    const float *Ab, *Bb;
+    int lda, ldb, ai, bj;
+    int kind;
+    if (tile < n2) {
+      kind = 2;
+      const int pt = tile / HT, ht = tile % HT;
+      Ab = dlb; lda = Lm.ldn; ai = 16 * pt;
+      Bb = hid; ldb = Lm.ldh; bj = 16 * ht;
+    } else if (tile < n2 + n0) {
+      kind = 0;
+      const int e = tile - n2, pt = e / NPT, jt = e % NPT;
+      Ab = dlb; lda = Lm.ldn; ai = 16 * pt;
+      Bb = sfb; ldb = Lm.ldn; bj = 16 * jt;
+    } else {
+      kind = 1;
+      const int e = tile - n2 - n0, ht = e / NPT, jt = e % NPT;
+      Ab = dab; lda = Lm.ldh; ai = 16 * ht;
+      Bb = sfb; ldb = Lm.ldn; bj = 16 * jt;
+    }
+    f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < 16; ++kc) {
+      const int s = 4 * kc + lg;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Ab[s * lda + ai + ls], Bb[s * ldb + bj + ls], acc,
+                                                 0, 0, 0);
+    }
+    // lane holds rows ai + 4 lg + r, column bj + ls
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = ai + 4 * lg + r, col = bj + ls;
+      if (kind == 2) {         // gW2[pos][k]: deg(k) <= pos
+        if (row < n && col < Hs)
+          prow[o_W2 + (int64_t)row * Hs + col] = (col < H && 1 + col % nm1 <= row) ? acc[r] : 0.f;
+      } else if (kind == 0) {  // gW0[pos][j]: j < pos
+        if (row < n && col < n) prow[o_W0 + (int64_t)row * n + col] = col < row ? acc[r] : 0.f;
+      } else {                 // gW1[k][j]: j < deg(k)
+        if (row < Hs && col < n)
+          prow[(int64_t)row * n + col] = (row < H && col < 1 + row % nm1) ? acc[r] : 0.f;
+      }
+    }
+  }
+  // bias gradients: column sums over the 64 samples
+  for (int k = threadIdx.x; k < Hs; k += blockDim.x) {
+    float acc = 0.f;
+    if (k < H)
+      for (int s = 0; s < 64; ++s) acc += dab[s * Lm.ldh + k];
+    prow[o_b1 + k] = acc;
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    float acc = 0.f;
+    for (int s = 0; s < 64; ++s) acc += dlb[s * Lm.ldn + i];
+    prow[o_b2 + i] = acc;
+  }
+}
+
+// grad[param_off + p] = sum over the instance's workgroup rows (fixed order)
+__global__ void mgrad_reduce(const MadeInst *mi, const int32_t *first_row, const int32_t *n_rows,
+                             const float *part, int64_t pstride, float *grad) {
+  const int q = blockIdx.y;
+  const MadeInst m = mi[q];
+  const int64_t pc = (int64_t)m.H * m.n + m.H + (int64_t)m.n * m.H + m.n + (int64_t)m.n * m.n;
+  const int r0 = first_row[q], nr = n_rows[q];
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < pc;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int r = 0; r < nr; ++r) acc += (double)part[(int64_t)(r0 + r) * pstride + p];
+    grad[m.param_off + p] = (float)acc;
+  }
+}
+
 }  // namespace
 
 constexpr size_t kStageMax = 96 * 1024;
@@ -620,6 +851,24 @@ constexpr size_t kStageMax = 96 * 1024;
 size_t made_param_bytes(int n, int H) { return made_stage_bytes(n, H); }
 
 int64_t made_pack_floats(int n, int npt) { return mpack_floats(n, npt); }
+
+size_t mgrad_lds_bytes(int H, int npt) { return mg_layout(H, npt).end; }
+
+hipError_t launch_mgrad(const MGradArgs &a, int npt, hipStream_t st) {
+  if (a.n_tasks <= 0) return hipSuccess;
+  size_t lds = 0;
+  for (int q = 0; q < a.n_inst; ++q) lds = std::max(lds, mg_layout(a.hmax, npt).end);
+  void (*k)(MGradArgs) = npt <= 1 ? mgrad_kernel<1> : npt <= 2 ? mgrad_kernel<2> : mgrad_kernel<4>;
+  if (npt > 4) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k, dim3(a.n_tasks), dim3(256), lds, st, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(mgrad_reduce, dim3(64, a.n_inst), dim3(256), 0, st, a.mi, a.first_row,
+                     a.n_rows, a.part, a.pstride, a.grad);
+  return hipGetLastError();
+}
 
 hipError_t launch_made_pack(const MadeInst *mi, int n_inst, int64_t max_floats, const float *params,
                             float *pack, int npt, hipStream_t st) {
