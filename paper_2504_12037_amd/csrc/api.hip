@@ -115,9 +115,14 @@ struct tnvan_net {
   ChainLim lim_fwd{}, lim_bwd{};
   DBuf Tl, Tbl, cedges, ckpt;
   // register-resident chain kernels (per-wave tasks)
-  DBuf Tr, Tq, Trb, xcol;
+  DBuf Tr, Tq, Trb, xcol, cf_w, cf_r, cf_J;
+  DBuf Ubuf, fabp, u_off, f_off;
+  int u_chunks = 0;
+  int64_t u_maxB = 0;
   bool rfwd = false, rbwd = false;
   int rtiles = 1, sg = 2;
+  int rg_lo[3] = {0, 0, 0}, rg_n[3] = {0, 0, 0}, brg_lo[3] = {0, 0, 0}, brg_n[3] = {0, 0, 0};
+  int sg_of(int rt) const { return rt >= 4 ? 1 : sg; }
   // matrix-core sampler
   bool msample = false;
   int mpt = 1;
@@ -128,7 +133,7 @@ struct tnvan_net {
   bool mgrad = false;
   int mg_hmax = 0;
   int64_t mg_pstride = 0;
-  DBuf mg_task_inst, mg_task_start, mg_first, mg_count;
+  DBuf mg_task_inst, mg_task_start, mg_first, mg_count, w_part2;
   int n_mgtasks = 0;
   DBuf task_inst, task_chain, task_start, btask_inst, btask_chain, btask_start, cpart_off,
       chain_list, cpart;
@@ -245,22 +250,37 @@ tnvan_status ensure_chain_tasks(tnvan_net *net) {
   std::vector<int64_t> coff(net->n_inst, 0);
   int64_t ctot = 0;
   for (int pass = 0; pass < 2; ++pass) {
-    // samples per task: a workgroup of the LDS kernels, a wave of the
-    // register-resident ones
-    const int per = pass ? (net->rbwd ? 16 : 16 * net->lim_bwd.wpb)
-                         : (net->rfwd ? 16 * net->sg : 16 * net->lim_fwd.wpb);
+    const bool reg = pass ? net->rbwd : net->rfwd;
     std::vector<int32_t> ti, tc, ts;
     for (int q = 0; q < net->n_inst; ++q) {
       if (!net->use_chain[q]) continue;
-      const int nc = net->P.cinst[q].n_chains;
       const int64_t B = net->nkey[q];
       if (pass == 0) {
         clist.push_back(q);
         coff[q] = ctot;
-        ctot += (int64_t)nc * B;
+        ctot += (int64_t)net->P.cinst[q].n_chains * B;
       }
-      for (int64_t b = 0; b < B; b += per)
-        for (int c = 0; c < nc; ++c) { ti.push_back(q); tc.push_back(c); ts.push_back((int32_t)b); }
+    }
+    // register-resident kernels: one task per wave, grouped by chain width
+    // (one launch per width); LDS kernels: one task per workgroup
+    for (int gi = 0; gi < (reg ? 3 : 1); ++gi) {
+      const int rt = 1 << gi;
+      int *lo = pass ? net->brg_lo : net->rg_lo, *cnt = pass ? net->brg_n : net->rg_n;
+      lo[gi] = (int)ti.size();
+      const int per = reg ? 16 * (pass ? 1 : net->sg_of(rt))
+                          : 16 * (pass ? net->lim_bwd.wpb : net->lim_fwd.wpb);
+      for (int q = 0; q < net->n_inst; ++q) {
+        if (!net->use_chain[q]) continue;
+        const ChainInst &C = net->P.cinst[q];
+        const int64_t B = net->nkey[q];
+        for (int64_t b = 0; b < B; b += per)
+          for (int c = 0; c < C.n_chains; ++c) {
+            const int crt = net->P.chains[C.chain_off + c].rt;
+            if (reg && (crt > 4 ? 4 : crt) != rt) continue;
+            ti.push_back(q); tc.push_back(c); ts.push_back((int32_t)b);
+          }
+      }
+      cnt[gi] = (int)ti.size() - lo[gi];
     }
     if (pass == 0) {
       HIPCHK(upload(net->task_inst, ti));
@@ -276,6 +296,30 @@ tnvan_status ensure_chain_tasks(tnvan_net *net) {
   }
   HIPCHK(upload(net->cpart_off, coff));
   HIPCHK(upload(net->chain_list, clist));
+  {
+    // unary factors of the register-resident kernels: [nr][B] floats and
+    // [ceil(nr / kUnaryChunk)][B] partial sums per chain instance
+    std::vector<int64_t> uo(net->n_inst, 0), fo(net->n_inst, 0);
+    int64_t ut = 0, ft = 0;
+    net->u_chunks = 0;
+    net->u_maxB = 0;
+    for (int q : clist) {
+      const int64_t B = net->nkey[q];
+      const int nr = net->P.insts[q].nr, nch = (nr + kUnaryChunk - 1) / kUnaryChunk;
+      uo[q] = ut;
+      fo[q] = ft;
+      ut += (int64_t)nr * B;
+      ft += (int64_t)nch * B;
+      net->u_chunks = std::max(net->u_chunks, nch);
+      net->u_maxB = std::max(net->u_maxB, B);
+    }
+    HIPCHK(upload(net->u_off, uo));
+    HIPCHK(upload(net->f_off, fo));
+    if (net->rfwd || net->rbwd) {
+      HIPCHK(net->Ubuf.ensure(std::max<int64_t>(1, ut) * sizeof(float)));
+      HIPCHK(net->fabp.ensure(std::max<int64_t>(1, ft) * sizeof(double)));
+    }
+  }
   HIPCHK(net->cpart.ensure(std::max<int64_t>(1, ctot) * sizeof(double)));
   const ChainLim &L = net->lim_bwd;
   int64_t ckf = 0;
@@ -333,6 +377,11 @@ ChainArgs chain_args(tnvan_net *net, bool bwd) {
   a.Tq = net->Tq.as<float>();
   a.Trb = net->Trb.as<uint16_t>();
   a.xcol = net->xcol.as<int32_t>();
+  a.cf_w = net->cf_w.as<int32_t>();
+  a.cf_r = net->cf_r.as<int32_t>();
+  a.cf_J = net->cf_J.as<float>();
+  a.U = net->Ubuf.as<float>();
+  a.u_off = net->u_off.as<int64_t>();
   a.sg = net->sg;
   if (bwd ? net->rbwd : net->rfwd) a.ntm = net->rtiles;
   return a;
@@ -384,11 +433,26 @@ tnvan_status run_logz(tnvan_net *net, const int8_t *spins, double *logz, hipStre
     if (s) return s;
     ChainArgs c = chain_args(net, false);
     c.spins = spins;
-    HIPCHK(net->rfwd ? launch_rchain(c, false, st) : launch_chain(c, false, st));
+    if (net->rfwd) {
+      HIPCHK(launch_unary(c, net->chain_list.as<int32_t>(), net->n_chain_insts, net->u_chunks,
+                          net->u_maxB, net->f_off.as<int64_t>(), net->Ubuf.as<float>(),
+                          net->fabp.as<double>(), st));
+      for (int gi = 0; gi < 3; ++gi) {
+        c.task_base = net->rg_lo[gi];
+        c.n_tasks = net->rg_n[gi];
+        c.ntm = 1 << gi;
+        c.sg = net->sg_of(1 << gi);
+        HIPCHK(launch_rchain(c, false, st));
+      }
+    } else {
+      HIPCHK(launch_chain(c, false, st));
+    }
     HIPCHK(launch_chain_sum(net->inst.as<InstDesc>(), net->cinst.as<ChainInst>(),
                             net->chain_list.as<int32_t>(), net->n_chain_insts,
                             net->d_B.as<int64_t>(), net->d_sample_off.as<int64_t>(),
-                            net->cpart_off.as<int64_t>(), net->cpart.as<double>(), logz, st));
+                            net->cpart_off.as<int64_t>(), net->cpart.as<double>(),
+                            net->f_off.as<int64_t>(),
+                            net->rfwd ? net->fabp.as<double>() : nullptr, logz, st));
   }
   return TNVAN_OK;
 }
@@ -420,7 +484,19 @@ tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *gra
     c.grad = grad;
     c.partial = reinterpret_cast<float *>(net->partial.p);
     c.inst_partial_off = tc.partial_off.as<int64_t>();
-    HIPCHK(net->rbwd ? launch_rchain(c, true, st) : launch_chain(c, true, st));
+    if (net->rbwd) {
+      HIPCHK(launch_unary(c, net->chain_list.as<int32_t>(), net->n_chain_insts, net->u_chunks,
+                          net->u_maxB, net->f_off.as<int64_t>(), net->Ubuf.as<float>(),
+                          net->fabp.as<double>(), st));
+      for (int gi = 0; gi < 2; ++gi) {
+        c.task_base = net->brg_lo[gi];
+        c.n_tasks = net->brg_n[gi];
+        c.ntm = 1 << gi;
+        HIPCHK(launch_rchain(c, true, st));
+      }
+    } else {
+      HIPCHK(launch_chain(c, true, st));
+    }
   }
   int64_t nh = 0, ne = 0;
   for (auto &D : net->P.insts) { nh += D.n; ne += D.n_edges; }
@@ -498,10 +574,13 @@ tnvan_status run_sample(tnvan_net *net, const float *uniforms, int8_t *spins, vo
                         hipStream_t st) {
   tnvan_status s = ensure_sample_blocks(net);
   if (s) return s;
-  if (net->msample && sizeof(real) == 4) {
+  if ((net->msample || net->mgrad) && sizeof(real) == 4) {
+    // parameters repacked for the matrix-core sampler and backward
     HIPCHK(net->mpack.ensure(std::max<int64_t>(1, net->mpack_total) * sizeof(float)));
     HIPCHK(launch_made_pack(net->d_mi.as<MadeInst>(), net->n_inst, net->mpack_max,
                             net->params.as<float>(), net->mpack.as<float>(), net->mpt, st));
+  }
+  if (net->msample && sizeof(real) == 4) {
     MSampleArgs m{};
     m.mi = net->d_mi.as<MadeInst>();
     m.pack = net->mpack.as<float>();
@@ -586,6 +665,9 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     g.pstride = net->mg_pstride;
     g.first_row = net->mg_first.as<int32_t>();
     g.n_rows = net->mg_count.as<int32_t>();
+    HIPCHK(net->w_part2.ensure((size_t)net->n_inst * mgrad_split() * net->mg_pstride * sizeof(float)));
+    g.part2 = net->w_part2.as<float>();
+    g.pack = net->mpack.as<float>();
     g.grad = net->grad.as<float>();
     HIPCHK(launch_mgrad(g, net->mpt, st));
   }
@@ -709,8 +791,8 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
     int64_t po = 0;
     for (auto &m : net->mi) {
       m.pack_off = po;
-      po += made_pack_floats(m.n, net->mpt);
-      net->mpack_max = std::max(net->mpack_max, made_pack_floats(m.n, net->mpt));
+      po += made_pack_floats(m.n, net->mpt, m.H);
+      net->mpack_max = std::max(net->mpack_max, made_pack_floats(m.n, net->mpt, m.H));
     }
     net->mpack_total = po;
     // fused REINFORCE backward: n <= 64, H <= 256, rows of 64 samples in LDS
@@ -720,7 +802,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
     bool gfit = net->precision != TNVAN_FP64;
     for (auto &m : net->mi) {
       net->mg_hmax = std::max(net->mg_hmax, (int)m.H);
-      if (m.n > 64 || m.H > 256) gfit = false;
+      if (m.n > 64 || m.H > 256 || m.n % 4 || m.H % 4) gfit = false;
     }
     for (auto pc : net->param_count) net->mg_pstride = std::max(net->mg_pstride, pc);
     net->mg_pstride = (net->mg_pstride + 63) / 64 * 64;
@@ -778,6 +860,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   }
   UP2(Tl, P.Tl) UP2(Tbl, P.Tbl) UP2(cedges, P.cedges)
   UP2(Tr, P.Tr) UP2(Tq, P.Tq) UP2(Trb, P.Trb) UP2(xcol, P.xcol)
+  UP2(cf_w, P.cf_w) UP2(cf_r, P.cf_r) UP2(cf_J, P.cf_J)
   // transfer-matrix form: instances whose program is a set of dense chains
   // (FP32 / BF16 only); the launch-wide maxima size the LDS layout
   net->use_chain.assign(n_inst, 0);
@@ -808,8 +891,8 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
     }
     const bool any = std::count(net->use_chain.begin(), net->use_chain.end(), 1) > 0;
     // register-resident kernels when every chain step is narrow enough
-    const bool reg = any && !(opt->flags & TNVAN_FLAG_LDS_CHAIN);
-    net->rfwd = reg && net->rtiles <= kRegFwdTiles &&
+    const bool reg = any && !(opt->flags & TNVAN_FLAG_LDS_CHAIN) && lim.nw <= 128;
+    net->rfwd = reg && rq && net->rtiles <= kRegFwdTiles &&
                 4 * rchain_wave_lds(lim, false, net->sg) <= (size_t)maxlds;
     net->rbwd = reg && rq && net->rtiles <= kRegBwdTiles &&
                 4 * rchain_wave_lds(lim, true, 1) <= (size_t)maxlds;
@@ -862,8 +945,10 @@ void tnvan_free_network(tnvan_net *net) {
                  &net->hR32, &net->task_inst, &net->task_chain, &net->task_start,
                  &net->btask_inst, &net->btask_chain, &net->btask_start, &net->Tl, &net->Tbl,
                  &net->cedges, &net->ckpt, &net->Tr, &net->Tq, &net->Trb, &net->xcol,
+                 &net->cf_w, &net->cf_r, &net->cf_J, &net->Ubuf, &net->fabp, &net->u_off,
+                 &net->f_off,
                  &net->mpack, &net->mtask_inst, &net->mtask_start, &net->mg_task_inst,
-                 &net->mg_task_start, &net->mg_first, &net->mg_count,
+                 &net->mg_task_start, &net->mg_first, &net->mg_count, &net->w_part2,
                  &net->cpart_off, &net->chain_list, &net->cpart};
   for (DBuf *b : all) b->release();
   TileCache *tcs[] = {&net->tc_fwd, &net->tc_bwd};

@@ -650,17 +650,50 @@ __global__ __launch_bounds__(256) void chain_bwd_kernel(ChainArgs a) {
 __global__ void chain_sum_kernel(const InstDesc *inst, const ChainInst *cinst,
                                  const int32_t *cis, int n, const int64_t *inst_B,
                                  const int64_t *inst_sample_off, const int64_t *cpart_off,
-                                 const double *cpart, double *logz) {
+                                 const double *cpart, const int64_t *f_off, const double *fabp,
+                                 double *logz) {
   const int q = cis[blockIdx.y];
   const int64_t B = inst_B[q];
   const int nc = cinst[q].n_chains;
+  const int nf = (inst[q].nr + kUnaryChunk - 1) / kUnaryChunk;
   const double lc = inst[q].log_const;
   for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < B;
        b += (int64_t)gridDim.x * blockDim.x) {
     double acc = lc;
     for (int c = 0; c < nc; ++c) acc += cpart[cpart_off[q] + (int64_t)c * B + b];
+    if (fabp)
+      for (int c = 0; c < nf; ++c) acc += fabp[f_off[q] + (int64_t)c * B + b];
     logz[inst_sample_off[q] + b] = acc;
   }
+}
+
+// One thread per (sample, run of kUnaryChunk positions); grid.z picks the
+// instance.  The field on R position p of sample s_W is h_p plus the W-R
+// couplings times the neighbouring width-set spins (Sec. 2).
+__global__ __launch_bounds__(256) void unary_kernel(ChainArgs a, const int32_t *cis,
+                                                    const int64_t *f_off, float *U,
+                                                    double *fabp) {
+  const int q = cis[blockIdx.z];
+  const InstDesc D = a.inst[q];
+  const int64_t B = a.inst_B[q];
+  const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int p0 = blockIdx.y * kUnaryChunk;
+  if (p0 >= D.nr || b >= B) return;
+  const int p1 = p0 + kUnaryChunk < D.nr ? p0 + kUnaryChunk : D.nr;
+  const int8_t *s = a.spins + a.inst_spin_off[q] + b * D.nw;
+  const float beta = (float)D.beta;
+  float *Uq = U + a.u_off[q];
+  double fab = 0.0;
+  for (int p = p0; p < p1; ++p) {
+    float f = a.hR[D.hr_off + p];
+    const int k0 = a.fld_ptr[D.fld_off + p], k1 = a.fld_ptr[D.fld_off + p + 1];
+    for (int k = k0; k < k1; ++k) f += a.fld_J[D.fld_nnz_off + k] * (float)s[a.fld_w[D.fld_nnz_off + k]];
+    const float af = beta * fabsf(f);
+    const float sm = __expf(-2.f * af);
+    Uq[(int64_t)p * B + b] = f >= 0.f ? sm : -sm;
+    fab += (double)af;
+  }
+  fabp[f_off[q] + (int64_t)blockIdx.y * B + b] = fab;
 }
 
 template <int NTM>
@@ -704,12 +737,21 @@ hipError_t launch_chain(const ChainArgs &a, bool bwd, hipStream_t st) {
 hipError_t launch_chain_sum(const InstDesc *inst, const ChainInst *cinst,
                             const int32_t *chain_insts, int n_chain_insts,
                             const int64_t *inst_B, const int64_t *inst_sample_off,
-                            const int64_t *cpart_off, const double *cpart, double *logz,
-                            hipStream_t st) {
+                            const int64_t *cpart_off, const double *cpart, const int64_t *f_off,
+                            const double *fabp, double *logz, hipStream_t st) {
   if (n_chain_insts <= 0) return hipSuccess;
   hipLaunchKernelGGL(chain_sum_kernel, dim3(32, n_chain_insts), dim3(256), 0, st, inst, cinst,
-                     chain_insts, n_chain_insts, inst_B, inst_sample_off, cpart_off, cpart,
-                     logz);
+                     chain_insts, n_chain_insts, inst_B, inst_sample_off, cpart_off, cpart, f_off,
+                     fabp, logz);
+  return hipGetLastError();
+}
+
+hipError_t launch_unary(const ChainArgs &a, const int32_t *cis, int n_cis, int max_chunks,
+                        int64_t max_B, const int64_t *f_off, float *U, double *fabp,
+                        hipStream_t st) {
+  if (n_cis <= 0 || max_B <= 0 || max_chunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(unary_kernel, dim3((unsigned)((max_B + 255) / 256), max_chunks, n_cis),
+                     dim3(256), 0, st, a, cis, f_off, U, fabp);
   return hipGetLastError();
 }
 

@@ -41,7 +41,6 @@ typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 
 constexpr int CW = 16;       // samples per 16-sample group
 constexpr int kWaves = 4;    // waves per workgroup
-constexpr int kGr = 6;       // largest group (4 tiles of 16 states)
 
 __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~(size_t)15; }
 
@@ -55,7 +54,8 @@ struct RL {
 __host__ __device__ inline RL rlayout(const ChainLim &L, bool bwd, int sg) {
   RL r{};
   size_t o = 0;
-  r.sp = o; o = al16(o + (size_t)CW * sg * L.nw);
+  r.sp = o;
+  (void)sg;
   if (bwd) {
     const int ldt = ldt_of(kRegBwdTiles);
     r.ex = o; o = al16(o + (size_t)L.max_steps * CW * 4);
@@ -67,111 +67,139 @@ __host__ __device__ inline RL rlayout(const ChainLim &L, bool bwd, int sg) {
   return r;
 }
 
-// spins of 16 * sg samples into the wave's LDS (zero rows past the batch)
-__device__ inline void stage_spins(const int8_t *src, int8_t *dst, int nw, int nvalid, int n,
-                                   int lane) {
-  for (int i = lane; i < n * nw; i += 64) dst[i] = i < nvalid * nw ? src[i] : (int8_t)0;
-  wsync();
-}
-
-// Unary factors (normalised to max 1) of the group of g positions starting at
-// order position gpos, for the sample whose spins are sp; adds sum beta |f|.
-__device__ inline void group_unary(const ChainArgs &a, const InstDesc &D, int gpos, int g,
-                                   const int8_t *sp, float beta, float (&p0)[kGr],
-                                   float (&p1)[kGr], double &fab) {
-#pragma unroll
-  for (int j = 0; j < kGr; ++j) {
-    p0[j] = 1.f;
-    p1[j] = 1.f;
-    if (j < g) {
-      const int pos = gpos + j;
-      float f = a.hR[D.hr_off + pos];
-      const int k0 = a.fld_ptr[D.fld_off + pos], k1 = a.fld_ptr[D.fld_off + pos + 1];
-      for (int k = k0; k < k1; ++k)
-        f += a.fld_J[D.fld_nnz_off + k] * (float)sp[a.fld_w[D.fld_nnz_off + k]];
-      const float af = beta * fabsf(f);
-      const float sm = __expf(-2.f * af);
-      p0[j] = f >= 0.f ? 1.f : sm;
-      p1[j] = f >= 0.f ? sm : 1.f;
-      fab += (double)af;
-    }
+// Width-set spins of one sample as a bit mask (bit w set: s_w = -1), up to
+// 128 spins; the chain kernels read a spin with a uniform index w.
+struct SpinBits {
+  uint32_t m[4];
+  __device__ float sigma(int w) const {
+    const uint32_t word = w < 32 ? m[0] : w < 64 ? m[1] : w < 96 ? m[2] : m[3];
+    return ((word >> (w & 31)) & 1u) ? -1.f : 1.f;
   }
+};
+
+// spins s[0..nw) (+-1 bytes); a sample past the batch reads as all +1
+__device__ inline SpinBits load_bits(const int8_t *s, int nw, bool valid) {
+  SpinBits b;
+  b.m[0] = b.m[1] = b.m[2] = b.m[3] = 0u;
+  if (!valid) return b;
+  for (int w0 = 0; w0 < nw; w0 += 4) {
+    uint32_t v = 0u;
+    if ((nw & 3) == 0) {
+      v = *reinterpret_cast<const uint32_t *>(s + w0);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (w0 + k < nw) v |= (uint32_t)(uint8_t)s[w0 + k] << (8 * k);
+    }
+    // sign bit of each byte
+    const uint32_t nib = ((v >> 7) & 1u) | ((v >> 14) & 2u) | ((v >> 21) & 4u) | ((v >> 28) & 8u);
+    const uint32_t sh = nib << (w0 & 31);
+    const int wd = w0 >> 5;
+    b.m[0] |= wd == 0 ? sh : 0u;
+    b.m[1] |= wd == 1 ? sh : 0u;
+    b.m[2] |= wd == 2 ? sh : 0u;
+    b.m[3] |= wd == 3 ? sh : 0u;
+  }
+  return b;
 }
 
 // d[t][r] = prod_j phi_j(bit j of x) for x = 16 t + 4 lg + r < K, else 0
-template <int NTM>
-__device__ inline void make_diag(const float (&p0)[kGr], const float (&p1)[kGr], int K, int lg,
-                                 float (&d)[NTM][4]) {
-  const float fl = ((lg & 1) ? p1[2] : p0[2]) * ((lg & 2) ? p1[3] : p0[3]);
+template <int CT, int GR>
+__device__ inline void make_diag(const float (&p0)[GR], const float (&p1)[GR], int K, int lg,
+                                 float (&d)[CT][4]) {
+  auto ph = [&](int j, bool bit) { return j < GR ? (bit ? p1[j < GR ? j : 0] : p0[j < GR ? j : 0]) : 1.f; };
+  const float fl = ph(2, lg & 1) * ph(3, lg & 2);
   float fr[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) fr[r] = ((r & 1) ? p1[0] : p0[0]) * ((r & 2) ? p1[1] : p0[1]) * fl;
+  for (int r = 0; r < 4; ++r) fr[r] = ph(0, r & 1) * ph(1, r & 2) * fl;
 #pragma unroll
-  for (int t = 0; t < NTM; ++t) {
-    const float ft = ((t & 1) ? p1[4] : p0[4]) * ((t & 2) ? p1[5] : p0[5]);
+  for (int t = 0; t < CT; ++t) {
+    const float ft = ph(4, t & 1) * ph(5, t & 2);
 #pragma unroll
     for (int r = 0; r < 4; ++r) d[t][r] = (16 * t + 4 * lg + r < K) ? fr[r] * ft : 0.f;
   }
 }
 
-template <int NTM>
-__device__ inline void load_t(const float *tab, int n_out, int n_in, int lane, f4 (&tc)[NTM][NTM]) {
-  const f4 *p = reinterpret_cast<const f4 *>(tab) + lane;
+// Unary factors of the group of g <= GR positions starting at order
+// position gpos for sample b (clamped into the batch), as stored by
+// unary_kernel: +-exp(-2 beta |f|), the sign that of f.
+template <int GR>
+__device__ inline void load_phi(const ChainArgs &a, int q, int64_t Bq, int gpos, int g, int64_t b,
+                                float (&u)[GR]) {
+  const float *Uq = a.U + a.u_off[q];
+  const int64_t bs = b < Bq ? b : Bq - 1;
 #pragma unroll
-  for (int i = 0; i < NTM; ++i)
-#pragma unroll
-    for (int j = 0; j < NTM; ++j)
-      tc[i][j] = (i < n_out && j < n_in) ? p[(i * n_in + j) * 64] : f4{0.f, 0.f, 0.f, 0.f};
+  for (int j = 0; j < GR; ++j) u[j] = Uq[(int64_t)(gpos + (j < g ? j : 0)) * Bq + bs];
 }
 
-template <int NTM>
-__device__ inline void load_tb(const uint16_t *tab, int n_out, int n_c, int lane,
-                               u4v (&tb)[NTM][(NTM + 1) / 2]) {
+// phi(+1) = 1, phi(-1) = exp(-2 beta f) for f >= 0 and the mirror image for
+// f < 0 (normalised to max 1); then the diagonal over the group's states
+template <int CT, int GR>
+__device__ inline void diag_from_phi(const float (&u)[GR], int g, int lg, float (&d)[CT][4]) {
+  float p0[GR], p1[GR];
+#pragma unroll
+  for (int j = 0; j < GR; ++j) {
+    const bool in = j < g, neg = __builtin_signbit(u[j]);
+    const float m = fabsf(u[j]);
+    p0[j] = in && neg ? m : 1.f;
+    p1[j] = in && !neg ? m : 1.f;
+  }
+  make_diag<CT, GR>(p0, p1, 1 << g, lg, d);
+}
+
+// the chain's group sizes are at most 4 + log2(tiles)
+template <int CT> struct GroupMax { static constexpr int v = CT == 1 ? 4 : CT == 2 ? 5 : 6; };
+
+template <int CT>
+__device__ inline void load_t(const float *tab, int lane, f4 (&tc)[CT][CT]) {
+  const f4 *p = reinterpret_cast<const f4 *>(tab) + lane;
+#pragma unroll
+  for (int i = 0; i < CT; ++i)
+#pragma unroll
+    for (int j = 0; j < CT; ++j) tc[i][j] = p[(i * CT + j) * 64];
+}
+
+template <int CT>
+__device__ inline void load_tb(const uint16_t *tab, int lane, u4v (&tb)[CT][(CT + 1) / 2]) {
   const u4v *p = reinterpret_cast<const u4v *>(tab) + lane;
 #pragma unroll
-  for (int i = 0; i < NTM; ++i)
+  for (int i = 0; i < CT; ++i)
 #pragma unroll
-    for (int c = 0; c < (NTM + 1) / 2; ++c)
-      tb[i][c] = (i < n_out && c < n_c) ? p[(i * n_c + c) * 64] : u4v{0u, 0u, 0u, 0u};
+    for (int c = 0; c < (CT + 1) / 2; ++c) tb[i][c] = p[(i * ((CT + 1) / 2) + c) * 64];
 }
 
 // out^T = T^T A^T: tc[nt][xt] from the Tr table, x in R-layout
-template <int NTM>
-__device__ inline void mm_fwd(const f4 (&tc)[NTM][NTM], const float (&x)[NTM][4], int KT, int NT,
-                              f4 (&acc)[NTM]) {
+template <int CT>
+__device__ inline void mm_fwd(const f4 (&tc)[CT][CT], const float (&x)[CT][4], f4 (&acc)[CT]) {
 #pragma unroll
-  for (int nt = 0; nt < NTM; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int nt = 0; nt < CT; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int xt = 0; xt < NTM; ++xt)
-    if (xt < KT)
+  for (int xt = 0; xt < CT; ++xt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int nt = 0; nt < NTM; ++nt)
-          if (nt < NT)
-            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(tc[nt][xt][r], x[xt][r], acc[nt], 0, 0, 0);
+      for (int nt = 0; nt < CT; ++nt)
+        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(tc[nt][xt][r], x[xt][r], acc[nt], 0, 0, 0);
 }
 
-template <int NTM>
-__device__ inline void mm_fwd_bf(const u4v (&tb)[NTM][(NTM + 1) / 2], const float (&x)[NTM][4],
-                                 int KC, int NT, f4 (&acc)[NTM]) {
+template <int CT>
+__device__ inline void mm_fwd_bf(const u4v (&tb)[CT][(CT + 1) / 2], const float (&x)[CT][4],
+                                 f4 (&acc)[CT]) {
 #pragma unroll
-  for (int nt = 0; nt < NTM; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int nt = 0; nt < CT; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int c = 0; c < (NTM + 1) / 2; ++c)
-    if (c < KC) {
-      bf8 bv;
+  for (int c = 0; c < (CT + 1) / 2; ++c) {
+    bf8 bv;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int t = 2 * c + (i >> 2);
-        bv[i] = (__bf16)(t < NTM ? x[t < NTM ? t : 0][i & 3] : 0.f);
-      }
-#pragma unroll
-      for (int nt = 0; nt < NTM; ++nt)
-        if (nt < NT)
-          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, tb[nt][c]), bv,
-                                                            acc[nt], 0, 0, 0);
+    for (int i = 0; i < 8; ++i) {
+      const int t = 2 * c + (i >> 2);
+      bv[i] = (__bf16)(t < CT ? x[t < CT ? t : 0][i & 3] : 0.f);
     }
+#pragma unroll
+    for (int nt = 0; nt < CT; ++nt)
+      acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, tb[nt][c]), bv,
+                                                        acc[nt], 0, 0, 0);
+  }
 }
 
 __device__ inline float xlane_max(float v) {
@@ -187,21 +215,19 @@ __device__ inline float xlane_sum(float v) {
 
 // power-of-two rescale of the step output and the next diagonal:
 // x = out * 2^-e * d; returns e of the lane's sample
-template <int NTM>
-__device__ inline int rescale_next(const f4 (&acc)[NTM], int NT, const float (&d)[NTM][4],
-                                   float (&x)[NTM][4]) {
+template <int CT>
+__device__ inline int rescale_next(const f4 (&acc)[CT], const float (&d)[CT][4], float (&x)[CT][4]) {
   float m = 0.f;
 #pragma unroll
-  for (int nt = 0; nt < NTM; ++nt)
-    if (nt < NT)
+  for (int nt = 0; nt < CT; ++nt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) m = fmaxf(m, acc[nt][r]);
+    for (int r = 0; r < 4; ++r) m = fmaxf(m, acc[nt][r]);
   const int e = expo32(xlane_max(m));
   const float sc = pow2neg(e);
 #pragma unroll
-  for (int t = 0; t < NTM; ++t)
+  for (int t = 0; t < CT; ++t)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) x[t][r] = t < NT ? acc[t][r] * sc * d[t][r] : 0.f;
+    for (int r = 0; r < 4; ++r) x[t][r] = acc[t][r] * sc * d[t][r];
   return e;
 }
 
@@ -212,9 +238,9 @@ struct Task {
 
 __device__ inline Task wave_task(const ChainArgs &a, int wave) {
   Task k;
-  const int i = blockIdx.x * kWaves + wave;
+  const int i = a.task_base + blockIdx.x * kWaves + wave;
   k.q = -1;
-  if (i >= a.n_tasks) return k;
+  if (i >= a.task_base + a.n_tasks) return k;
   k.q = a.task_inst[i];
   k.c = a.task_chain[i];
   k.b0 = a.task_start[i];
@@ -222,70 +248,48 @@ __device__ inline Task wave_task(const ChainArgs &a, int wave) {
   return k;
 }
 
-template <bool kBF, int NTM, int SG>
-__global__ __launch_bounds__(256) void rchain_fwd_kernel(ChainArgs a) {
-  extern __shared__ __align__(16) char smem[];
-  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int lane = threadIdx.x & 63, ls = lane & 15, lg = lane >> 4;
-  const Task tk = wave_task(a, wave);
-  if (tk.q < 0) return;
-  const InstDesc D = a.inst[tk.q];
-  const ChainInst C = a.cinst[tk.q];
-  const ChainDesc cd = a.chains[C.chain_off + tk.c];
+// forward of one chain for SG groups of 16 samples: per sample the sum of
+// the step exponents (ln 2) and ln of the root value; the unary
+// normalisations are added from unary_kernel's sums
+template <bool kBF, int CT, int SG>
+__device__ inline void fwd_chain(const ChainArgs &a, const Task &tk, const ChainDesc &cd, int lane) {
+  constexpr int GR = GroupMax<CT>::v;
+  constexpr int NC2 = (CT + 1) / 2;
+  const int ls = lane & 15, lg = lane >> 4;
   const ChainStep *cs = a.csteps + cd.cs_off;
-  const RL L = rlayout(a.lim, false, SG);
-  int8_t *spl = reinterpret_cast<int8_t *>(smem + (size_t)wave * L.end + L.sp);
-  const int64_t left = tk.Bq - tk.b0;
-  const int nvalid = (int)(left < CW * SG ? left : CW * SG);
-  stage_spins(a.spins + a.inst_spin_off[tk.q] + tk.b0 * D.nw, spl, D.nw, nvalid, CW * SG, lane);
-  const float beta = (float)D.beta;
-
-  double fab[SG];
+  const int T = cd.n_steps;
   int esum[SG];
-  float x[SG][NTM][4], raw[SG];
+  float x[SG][CT][4], raw[SG];
   {
     const ChainStep s0 = cs[0];
 #pragma unroll
     for (int gi = 0; gi < SG; ++gi) {
-      fab[gi] = 0.0;
+      float u[GR];
+      load_phi<GR>(a, tk.q, tk.Bq, s0.gpos, s0.g, tk.b0 + gi * CW + ls, u);
+      diag_from_phi<CT, GR>(u, s0.g, lg, x[gi]);
       esum[gi] = 0;
-      float p0[kGr], p1[kGr];
-      group_unary(a, D, s0.gpos, s0.g, spl + (gi * CW + ls) * D.nw, beta, p0, p1, fab[gi]);
-      make_diag<NTM>(p0, p1, 1 << s0.g, lg, x[gi]);
     }
   }
-  constexpr int NC2 = (NTM + 1) / 2;
-  f4 tc[NTM][NTM], tn[NTM][NTM];
-  u4v bc[NTM][NC2], bn[NTM][NC2];
-  {
-    const ChainStep s0 = cs[0];
-    if (kBF) load_tb<NTM>(a.Trb + s0.trb_off, s0.nt16, ((s0.kp >> 4) + 1) >> 1, lane, bc);
-    else load_t<NTM>(a.Tr + s0.tr_off, s0.nt16, s0.kp >> 4, lane, tc);
-  }
+  f4 tc[CT][CT];
+  u4v bc[CT][NC2];
+  if (kBF) load_tb<CT>(a.Trb + cs[0].trb_off, lane, bc);
+  else load_t<CT>(a.Tr + cs[0].tr_off, lane, tc);
   for (int t = 0;; ++t) {
-    const ChainStep st = cs[t];
-    const int KT = st.kp >> 4, NT = st.nt16;
-    const bool last = st.w == 0;
-    ChainStep nx = st;
-    if (!last) {
-      nx = cs[t + 1];
-      if (kBF) load_tb<NTM>(a.Trb + nx.trb_off, nx.nt16, ((nx.kp >> 4) + 1) >> 1, lane, bn);
-      else load_t<NTM>(a.Tr + nx.tr_off, nx.nt16, nx.kp >> 4, lane, tn);
-    }
-    float d[SG][NTM][4];
-    if (!last) {
+    const bool last = t == T - 1;
+    const ChainStep nx = cs[last ? t : t + 1];
+    // next step's tables and unary factors (the closing step reloads its own)
+    f4 tn[CT][CT];
+    u4v bn[CT][NC2];
+    if (kBF) load_tb<CT>(a.Trb + nx.trb_off, lane, bn);
+    else load_t<CT>(a.Tr + nx.tr_off, lane, tn);
+    float un[SG][GR];
 #pragma unroll
-      for (int gi = 0; gi < SG; ++gi) {
-        float p0[kGr], p1[kGr];
-        group_unary(a, D, nx.gpos, nx.g, spl + (gi * CW + ls) * D.nw, beta, p0, p1, fab[gi]);
-        make_diag<NTM>(p0, p1, 1 << nx.g, lg, d[gi]);
-      }
-    }
-    f4 acc[SG][NTM];
+    for (int gi = 0; gi < SG; ++gi) load_phi<GR>(a, tk.q, tk.Bq, nx.gpos, nx.g, tk.b0 + gi * CW + ls, un[gi]);
+    f4 acc[SG][CT];
 #pragma unroll
     for (int gi = 0; gi < SG; ++gi) {
-      if (kBF) mm_fwd_bf<NTM>(bc, x[gi], (KT + 1) >> 1, NT, acc[gi]);
-      else mm_fwd<NTM>(tc, x[gi], KT, NT, acc[gi]);
+      if (kBF) mm_fwd_bf<CT>(bc, x[gi], acc[gi]);
+      else mm_fwd<CT>(tc, x[gi], acc[gi]);
     }
     if (last) {
 #pragma unroll
@@ -293,11 +297,15 @@ __global__ __launch_bounds__(256) void rchain_fwd_kernel(ChainArgs a) {
       break;
     }
 #pragma unroll
-    for (int gi = 0; gi < SG; ++gi) esum[gi] += rescale_next<NTM>(acc[gi], NT, d[gi], x[gi]);
+    for (int gi = 0; gi < SG; ++gi) {
+      float d[CT][4];
+      diag_from_phi<CT, GR>(un[gi], nx.g, lg, d);
+      esum[gi] += rescale_next<CT>(acc[gi], d, x[gi]);
+    }
 #pragma unroll
-    for (int i = 0; i < NTM; ++i) {
+    for (int i = 0; i < CT; ++i) {
 #pragma unroll
-      for (int j = 0; j < NTM; ++j) tc[i][j] = tn[i][j];
+      for (int j = 0; j < CT; ++j) tc[i][j] = tn[i][j];
 #pragma unroll
       for (int c = 0; c < NC2; ++c) bc[i][c] = bn[i][c];
     }
@@ -308,229 +316,227 @@ __global__ __launch_bounds__(256) void rchain_fwd_kernel(ChainArgs a) {
       const int64_t b = tk.b0 + gi * CW + ls;
       if (b < tk.Bq)
         a.cpart[a.cpart_off[tk.q] + (int64_t)tk.c * tk.Bq + b] =
-            fab[gi] + (double)esum[gi] * 0.69314718055994530942 + log((double)raw[gi]);
+            (double)esum[gi] * 0.69314718055994530942 + log((double)raw[gi]);
     }
   }
 }
 
-// spin sign of bit j of the state index x
-__device__ inline float sgn(int x, int j) { return ((x >> j) & 1) ? -1.f : 1.f; }
-
-template <int NTM>
-__global__ __launch_bounds__(256) void rchain_bwd_kernel(ChainArgs a) {
+template <bool kBF, int CT, int SG>
+__global__ __launch_bounds__(256) void rchain_fwd_kernel(ChainArgs a) {
   extern __shared__ __align__(16) char smem[];
-  constexpr int KS = kRegSeg;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int lane = threadIdx.x & 63, ls = lane & 15, lg = lane >> 4;
+  const int lane = threadIdx.x & 63;
   const Task tk = wave_task(a, wave);
   if (tk.q < 0) return;
   const InstDesc D = a.inst[tk.q];
   const ChainInst C = a.cinst[tk.q];
   const ChainDesc cd = a.chains[C.chain_off + tk.c];
+  (void)smem;
+  (void)D;
+  fwd_chain<kBF, CT, SG>(a, tk, cd, lane);
+}
+
+// spin sign of bit j of the state index x
+__device__ inline float sgn(int x, int j) { return ((x >> j) & 1) ? -1.f : 1.f; }
+
+template <int CT>
+__device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstDesc &D,
+                                 const ChainDesc &cd, char *base, const RL &L, int lane) {
+  constexpr int KS = kRegSeg;
+  constexpr int GR = GroupMax<CT>::v;
+  constexpr int LDT = ldt_of(CT);
+  const int ls = lane & 15, lg = lane >> 4;
   const ChainStep *cs = a.csteps + cd.cs_off;
-  const RL L = rlayout(a.lim, true, 1);
-  char *base = smem + (size_t)wave * L.end;
-  int8_t *spl = reinterpret_cast<int8_t *>(base + L.sp);
   int *ex = reinterpret_cast<int *>(base + L.ex);
   float *ga = reinterpret_cast<float *>(base + L.ga);
   float *rs = reinterpret_cast<float *>(base + L.rs);
   float *qs = reinterpret_cast<float *>(base + L.qs);
-  constexpr int LDT = ldt_of(NTM);
   const int64_t left = tk.Bq - tk.b0;
   const int nvalid = (int)(left < CW ? left : CW);
-  stage_spins(a.spins + a.inst_spin_off[tk.q] + tk.b0 * D.nw, spl, D.nw, nvalid, CW, lane);
-  const int8_t *sp = spl + ls * D.nw;
-  const float beta = (float)D.beta;
+  const SpinBits sp = load_bits(a.spins + a.inst_spin_off[tk.q] + (tk.b0 + (ls < nvalid ? ls : 0)) * D.nw,
+                                D.nw, ls < nvalid);
   const float gs = ls < nvalid ? (float)a.grad[a.inst_sample_off[tk.q] + tk.b0 + ls] : 0.f;
   float *prow = a.partial + a.inst_partial_off[tk.q] + (tk.b0 / CW) * (int64_t)D.n_partial;
   const int T = cd.n_steps;
   const int ncmax = (a.lim.max_steps + KS - 1) / KS;
-  f4 *ck = reinterpret_cast<f4 *>(a.ckpt) + (int64_t)(blockIdx.x * kWaves + wave) * ncmax * NTM * 64 + lane;
+  f4 *ck = reinterpret_cast<f4 *>(a.ckpt) +
+           (int64_t)(a.task_base + blockIdx.x * kWaves + (threadIdx.x >> 6)) * ncmax * kRegBwdTiles * 64 +
+           lane;
   const EdgeDesc *ce = a.cedges + cd.e_src;
 
   // forward: checkpoints every KS steps, exponents in LDS, root value
-  float x[NTM][4];
-  double fab = 0.0;
+  const int64_t bme = tk.b0 + ls;
+  float x[CT][4];
   {
-    const ChainStep s0 = cs[0];
-    float p0[kGr], p1[kGr];
-    group_unary(a, D, s0.gpos, s0.g, sp, beta, p0, p1, fab);
-    make_diag<NTM>(p0, p1, 1 << s0.g, lg, x);
+    float u[GR];
+    load_phi<GR>(a, tk.q, tk.Bq, cs[0].gpos, cs[0].g, bme, u);
+    diag_from_phi<CT, GR>(u, cs[0].g, lg, x);
   }
   float raw = 1.f;
   {
-    f4 tc[NTM][NTM], tn[NTM][NTM];
-    load_t<NTM>(a.Tr + cs[0].tr_off, cs[0].nt16, cs[0].kp >> 4, lane, tc);
+    f4 tc[CT][CT];
+    load_t<CT>(a.Tr + cs[0].tr_off, lane, tc);
     for (int t = 0;; ++t) {
-      const ChainStep st = cs[t];
       if (t % KS == 0) {
 #pragma unroll
-        for (int i = 0; i < NTM; ++i)
-          ck[((t / KS) * NTM + i) * 64] = f4{x[i][0], x[i][1], x[i][2], x[i][3]};
+        for (int i = 0; i < CT; ++i)
+          ck[((t / KS) * kRegBwdTiles + i) * 64] = f4{x[i][0], x[i][1], x[i][2], x[i][3]};
       }
-      const bool last = st.w == 0;
-      ChainStep nx = st;
-      float d[NTM][4];
-      if (!last) {
-        nx = cs[t + 1];
-        load_t<NTM>(a.Tr + nx.tr_off, nx.nt16, nx.kp >> 4, lane, tn);
-        float p0[kGr], p1[kGr];
-        double dummy = 0.0;
-        group_unary(a, D, nx.gpos, nx.g, sp, beta, p0, p1, dummy);
-        make_diag<NTM>(p0, p1, 1 << nx.g, lg, d);
-      }
-      f4 acc[NTM];
-      mm_fwd<NTM>(tc, x, st.kp >> 4, st.nt16, acc);
+      const bool last = t == T - 1;
+      const ChainStep nx = cs[last ? t : t + 1];
+      f4 tn[CT][CT];
+      load_t<CT>(a.Tr + nx.tr_off, lane, tn);
+      float u[GR], d[CT][4];
+      load_phi<GR>(a, tk.q, tk.Bq, nx.gpos, nx.g, bme, u);
+      f4 acc[CT];
+      mm_fwd<CT>(tc, x, acc);
+      diag_from_phi<CT, GR>(u, nx.g, lg, d);
       if (last) {
         raw = __shfl(acc[0][0], ls, 64);
         break;
       }
-      const int e = rescale_next<NTM>(acc, st.nt16, d, x);
+      const int e = rescale_next<CT>(acc, d, x);
       if (lg == 0) ex[t * CW + ls] = e;
 #pragma unroll
-      for (int i = 0; i < NTM; ++i)
+      for (int i = 0; i < CT; ++i)
 #pragma unroll
-        for (int j = 0; j < NTM; ++j) tc[i][j] = tn[i][j];
+        for (int j = 0; j < CT; ++j) tc[i][j] = tn[i][j];
     }
   }
   wsync();
 
   // R of the closing step: d ln(raw) / d out = 1 / raw on its single entry
-  float R[NTM][4];
+  float R[CT][4];
 #pragma unroll
-  for (int i = 0; i < NTM; ++i)
+  for (int i = 0; i < CT; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) R[i][r] = 0.f;
   if (lg == 0) R[0][0] = raw > 0.f ? 1.f / raw : 0.f;
 
   const int NC = (T + KS - 1) / KS;
+  f4 ckn[CT];   // checkpoint of the next segment, loaded one segment ahead
+#pragma unroll
+  for (int i = 0; i < CT; ++i) ckn[i] = ck[((NC - 1) * kRegBwdTiles + i) * 64];
   for (int seg = NC - 1; seg >= 0; --seg) {
     const int t0 = seg * KS;
-    float As[KS][NTM][4];
+    float As[KS][CT][4];
 #pragma unroll
-    for (int i = 0; i < NTM; ++i) {
-      const f4 v = ck[(seg * NTM + i) * 64];
+    for (int i = 0; i < CT; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) As[0][i][r] = v[r];
-    }
-    // replay the segment
+      for (int r = 0; r < 4; ++r) As[0][i][r] = ckn[i][r];
+#pragma unroll
+    for (int i = 0; i < CT; ++i) ckn[i] = ck[((seg > 0 ? seg - 1 : 0) * kRegBwdTiles + i) * 64];
+    // replay the segment (steps past the chain recompute the last one)
 #pragma unroll
     for (int u = 1; u < KS; ++u) {
-      if (t0 + u < T) {
-        const ChainStep st = cs[t0 + u - 1], nx = cs[t0 + u];
-        f4 tc[NTM][NTM];
-        load_t<NTM>(a.Tr + st.tr_off, st.nt16, st.kp >> 4, lane, tc);
-        float p0[kGr], p1[kGr], d[NTM][4];
-        double dummy = 0.0;
-        group_unary(a, D, nx.gpos, nx.g, sp, beta, p0, p1, dummy);
-        make_diag<NTM>(p0, p1, 1 << nx.g, lg, d);
-        f4 acc[NTM];
-        mm_fwd<NTM>(tc, As[u - 1], st.kp >> 4, st.nt16, acc);
-        rescale_next<NTM>(acc, st.nt16, d, As[u]);
-      }
+      const int tp = t0 + u - 1 < T - 1 ? t0 + u - 1 : T - 1;
+      const ChainStep st = cs[tp], nx = cs[tp + 1 < T ? tp + 1 : tp];
+      f4 tc[CT][CT];
+      load_t<CT>(a.Tr + st.tr_off, lane, tc);
+      float uu[GR], d[CT][4];
+      load_phi<GR>(a, tk.q, tk.Bq, nx.gpos, nx.g, bme, uu);
+      f4 acc[CT];
+      mm_fwd<CT>(tc, As[u - 1], acc);
+      diag_from_phi<CT, GR>(uu, nx.g, lg, d);
+      rescale_next<CT>(acc, d, As[u]);
     }
     // walk the segment backwards
 #pragma unroll
     for (int u = KS - 1; u >= 0; --u) {
       const int t = t0 + u;
-      if (t >= T) continue;
-      const ChainStep st = cs[t];
-      const int KT = st.kp >> 4, OT = st.nt16, g = st.g, w = st.w;
-      f4 tq[NTM][NTM], tr[NTM][NTM];
-      load_t<NTM>(a.Tq + st.tq_off, KT, OT, lane, tq);
-      load_t<NTM>(a.Tr + st.tr_off, OT, KT, lane, tr);
-      // Lambda = T R (R-layout over the group states)
-      f4 lam[NTM];
+      if (t < T) {
+        const ChainStep st = cs[t];
+        const int g = st.g, w = st.w;
+        f4 tq[CT][CT], tr[CT][CT];
+        load_t<CT>(a.Tq + st.tq_off, lane, tq);
+        load_t<CT>(a.Tr + st.tr_off, lane, tr);
+        // Lambda = T R (R-layout over the group states)
+        f4 lam[CT];
 #pragma unroll
-      for (int xt = 0; xt < NTM; ++xt) lam[xt] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int xt = 0; xt < CT; ++xt) lam[xt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int ot = 0; ot < NTM; ++ot)
-        if (ot < OT)
+        for (int ot = 0; ot < CT; ++ot)
 #pragma unroll
           for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int xt = 0; xt < NTM; ++xt)
-              if (xt < KT)
-                lam[xt] = __builtin_amdgcn_mfma_f32_16x16x4f32(tq[xt][ot][r], R[ot][r], lam[xt], 0, 0, 0);
-      // W-R correlations: per-sample magnetisation of a group spin times the
-      // neighbouring width-set spin, weighted and summed over the samples
-      for (int j = 0; j < g; ++j) {
-        const int pos = st.gpos + j;
-        const int k0 = a.fld_ptr[D.fld_off + pos], k1 = a.fld_ptr[D.fld_off + pos + 1];
-        if (k1 <= k0) continue;
-        float m = 0.f;
+            for (int xt = 0; xt < CT; ++xt)
+              lam[xt] = __builtin_amdgcn_mfma_f32_16x16x4f32(tq[xt][ot][r], R[ot][r], lam[xt], 0, 0, 0);
+        // W-R correlations: per-sample magnetisation of a group spin times the
+        // neighbouring width-set spin, weighted and summed over the samples
+        for (int j = 0; j < g; ++j) {
+          typedef int i4v __attribute__((ext_vector_type(4)));
+          const int64_t pos = D.hr_off + st.gpos + j;
+          const i4v wr = *reinterpret_cast<const i4v *>(a.cf_r + 4 * pos);
+          if (wr[0] < 0) continue;
+          const i4v wi = *reinterpret_cast<const i4v *>(a.cf_w + 4 * pos);
+          float m = 0.f;
 #pragma unroll
-        for (int xt = 0; xt < NTM; ++xt)
+          for (int xt = 0; xt < CT; ++xt)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) m += sgn(16 * xt + 4 * lg + r, j) * As[u][xt][r] * lam[xt][r];
-        m = xlane_sum(m) * gs;
-        for (int k = k0; k < k1; ++k) {
-          const float v = row16_sum(m * (float)sp[a.fld_w[D.fld_nnz_off + k]]);
-          if (lane == 0) prow[D.nr + a.fld_wr[D.fld_nnz_off + k]] = v;
+            for (int r = 0; r < 4; ++r) m += sgn(16 * xt + 4 * lg + r, j) * As[u][xt][r] * lam[xt][r];
+          m = xlane_sum(m) * gs;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (wr[k] >= 0) {
+              const float v = row16_sum(m * sp.sigma(wi[k]));
+              if (lane == 0) prow[D.nr + wr[k]] = v;
+            }
         }
-      }
-      // R of the previous step
-      float Rn[NTM][4];
-      if (t > 0) {
-        float p0[kGr], p1[kGr], d[NTM][4];
-        double dummy = 0.0;
-        group_unary(a, D, st.gpos, g, sp, beta, p0, p1, dummy);
-        make_diag<NTM>(p0, p1, 1 << g, lg, d);
-        const float sc = pow2neg(ex[(t - 1) * CW + ls]);
+        // R of the previous step (unused after the first step)
+        float Rn[CT][4];
+        {
+          float uu[GR], d[CT][4];
+          load_phi<GR>(a, tk.q, tk.Bq, st.gpos, g, bme, uu);
+          diag_from_phi<CT, GR>(uu, g, lg, d);
+          const float sc = pow2neg(ex[(t > 0 ? t - 1 : 0) * CW + ls]);
 #pragma unroll
-        for (int xt = 0; xt < NTM; ++xt)
+          for (int xt = 0; xt < CT; ++xt)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) Rn[xt][r] = xt < KT ? d[xt][r] * lam[xt][r] * sc : 0.f;
-      }
-      // H = sum_s (g A)[s] R[s]^T through an LDS transpose
+            for (int r = 0; r < 4; ++r) Rn[xt][r] = d[xt][r] * lam[xt][r] * sc;
+        }
+        // H = sum_s (g A)[s] R[s]^T through an LDS transpose
 #pragma unroll
-      for (int xt = 0; xt < NTM; ++xt)
-        if (xt < KT)
+        for (int xt = 0; xt < CT; ++xt)
           *reinterpret_cast<f4 *>(ga + ls * LDT + 16 * xt + 4 * lg) =
               f4{gs * As[u][xt][0], gs * As[u][xt][1], gs * As[u][xt][2], gs * As[u][xt][3]};
 #pragma unroll
-      for (int ot = 0; ot < NTM; ++ot)
-        if (ot < OT)
+        for (int ot = 0; ot < CT; ++ot)
           *reinterpret_cast<f4 *>(rs + ls * LDT + 16 * ot + 4 * lg) =
               f4{R[ot][0], R[ot][1], R[ot][2], R[ot][3]};
-      wsync();
-      f4 hg[NTM][NTM];
+        wsync();
+        f4 hg[CT][CT];
 #pragma unroll
-      for (int xt = 0; xt < NTM; ++xt)
+        for (int xt = 0; xt < CT; ++xt)
 #pragma unroll
-        for (int ot = 0; ot < NTM; ++ot) {
-          hg[xt][ot] = f4{0.f, 0.f, 0.f, 0.f};
-          if (xt < KT && ot < OT)
+          for (int ot = 0; ot < CT; ++ot) {
+            hg[xt][ot] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kc = 0; kc < 4; ++kc)
               hg[xt][ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(
                   ga[(4 * kc + lg) * LDT + 16 * xt + ls], rs[(4 * kc + lg) * LDT + 16 * ot + ls],
                   hg[xt][ot], 0, 0, 0);
+          }
+        wsync();
+        // G = H o T, then Q'^T = G^T S_x and Q = S_o^T Q'^T
+        const int code = a.xcol[st.xc_off + ls];
+        const int cu = code & 0xff, cv = (code >> 8) & 0xff;
+        f4 qt[CT];
+#pragma unroll
+        for (int ot = 0; ot < CT; ++ot) {
+          qt[ot] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int xt = 0; xt < CT; ++xt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int xs = 16 * xt + 4 * lg + r;
+              const float sx = code < 0 ? 0.f : ((((xs >> cu) ^ (xs >> cv)) & 1) ? -1.f : 1.f);
+              qt[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(hg[xt][ot][r] * tr[ot][xt][r], sx,
+                                                            qt[ot], 0, 0, 0);
+            }
         }
-      wsync();
-      // G = H o T, then Q'^T = G^T S_x and Q = S_o^T Q'^T
-      const int code = a.xcol[st.xc_off + ls];
-      const int cu = code & 0xff, cv = (code >> 8) & 0xff;
-      f4 qt[NTM];
+        f4 qq = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int ot = 0; ot < NTM; ++ot) {
-        qt[ot] = f4{0.f, 0.f, 0.f, 0.f};
-        if (ot < OT)
-#pragma unroll
-          for (int xt = 0; xt < NTM; ++xt)
-            if (xt < KT)
-#pragma unroll
-              for (int r = 0; r < 4; ++r) {
-                const int xs = 16 * xt + 4 * lg + r;
-                const float sx = code < 0 ? 0.f : ((((xs >> cu) ^ (xs >> cv)) & 1) ? -1.f : 1.f);
-                qt[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(hg[xt][ot][r] * tr[ot][xt][r], sx,
-                                                              qt[ot], 0, 0, 0);
-              }
-      }
-      f4 qq = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ot = 0; ot < NTM; ++ot)
-        if (ot < OT)
+        for (int ot = 0; ot < CT; ++ot)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int o = 16 * ot + 4 * lg + r;
@@ -538,30 +544,36 @@ __global__ __launch_bounds__(256) void rchain_bwd_kernel(ChainArgs a) {
             qq = __builtin_amdgcn_mfma_f32_16x16x4f32(so, qt[ot][r], qq, 0, 0, 0);
           }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) qs[ls * 17 + 4 * lg + r] = qq[r];
-      wsync();
-      for (int k = lane; k < st.n_edge; k += 64) {
-        const EdgeDesc ed = ce[st.ce_off + k];
-        prow[D.nr + D.n_wr + ed.rr] = qs[(ed.pad >> 4) * 17 + (ed.pad & 15)];
+        for (int r = 0; r < 4; ++r) qs[ls * 17 + 4 * lg + r] = qq[r];
+        wsync();
+        for (int k = lane; k < st.n_edge; k += 64) {
+          const EdgeDesc ed = ce[st.ce_off + k];
+          prow[D.nr + D.n_wr + ed.rr] = qs[(ed.pad >> 4) * 17 + (ed.pad & 15)];
+        }
+        if (lane < g) prow[st.gpos + lane] = qs[lane * 17 + w];
+        wsync();
+#pragma unroll
+        for (int i = 0; i < CT; ++i)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) R[i][r] = Rn[i][r];
       }
-      if (lane < g) prow[st.gpos + lane] = qs[lane * 17 + w];
-      wsync();
-#pragma unroll
-      for (int i = 0; i < NTM; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) R[i][r] = Rn[i][r];
     }
   }
 }
 
-template <int NTM>
-void pick_rchain(bool bwd, bool bf, int sg, void (**k)(ChainArgs)) {
-  if (bwd) {
-    if constexpr (NTM <= kRegBwdTiles) *k = rchain_bwd_kernel<NTM>;
-    return;
-  }
-  if (bf) *k = sg >= 2 ? rchain_fwd_kernel<true, NTM, 2> : rchain_fwd_kernel<true, NTM, 1>;
-  else *k = sg >= 2 ? rchain_fwd_kernel<false, NTM, 2> : rchain_fwd_kernel<false, NTM, 1>;
+template <int CT>
+__global__ __launch_bounds__(256, 3) void rchain_bwd_kernel(ChainArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const Task tk = wave_task(a, wave);
+  if (tk.q < 0) return;
+  const InstDesc D = a.inst[tk.q];
+  const ChainInst C = a.cinst[tk.q];
+  const ChainDesc cd = a.chains[C.chain_off + tk.c];
+  const RL L = rlayout(a.lim, true, 1);
+  char *base = smem + (size_t)wave * L.end;
+  bwd_chain<CT>(a, tk, D, cd, base, L, lane);
 }
 
 }  // namespace
@@ -572,14 +584,28 @@ int64_t rchain_ckpt_floats(const ChainLim &L) {
   return (int64_t)((L.max_steps + kRegSeg - 1) / kRegSeg) * kRegBwdTiles * 64 * 4;
 }
 
+// one launch per chain width: tasks [task_base, task_base + n_tasks) all
+// belong to chains of a.ntm tiles
 hipError_t launch_rchain(const ChainArgs &a, bool bwd, hipStream_t st) {
   if (a.n_tasks <= 0) return hipSuccess;
   const int sg = bwd ? 1 : (a.sg >= 2 ? 2 : 1);
   void (*k)(ChainArgs) = nullptr;
-  if (bwd) pick_rchain<kRegBwdTiles>(true, false, 1, &k);
-  else if (a.ntm <= 2) pick_rchain<2>(false, a.bf16 != 0, sg, &k);
-  else if (a.ntm <= 4) pick_rchain<4>(false, a.bf16 != 0, sg, &k);
-  if (!k || (bwd && a.ntm > kRegBwdTiles)) return hipErrorInvalidValue;
+  const int ct = a.ntm;
+  if (bwd) {
+    if (ct == 1) k = rchain_bwd_kernel<1>;
+    else if (ct == 2) k = rchain_bwd_kernel<2>;
+  } else if (a.bf16) {
+    if (ct == 1) k = sg >= 2 ? rchain_fwd_kernel<true, 1, 2> : rchain_fwd_kernel<true, 1, 1>;
+    else if (ct == 2) k = sg >= 2 ? rchain_fwd_kernel<true, 2, 2> : rchain_fwd_kernel<true, 2, 1>;
+    else if (ct == 4) k = rchain_fwd_kernel<true, 4, 1>;
+  } else {
+    if (ct == 1) k = sg >= 2 ? rchain_fwd_kernel<false, 1, 2> : rchain_fwd_kernel<false, 1, 1>;
+    else if (ct == 2) k = sg >= 2 ? rchain_fwd_kernel<false, 2, 2> : rchain_fwd_kernel<false, 2, 1>;
+    else if (ct == 4) k = rchain_fwd_kernel<false, 4, 1>;
+  }
+  if (!k) return hipErrorInvalidValue;
+  const int sgl = (!bwd && ct == 4) ? 1 : sg;
+  if (sgl != sg) return hipErrorInvalidValue;   // the task list was cut for sg samples
   const size_t lds = (size_t)kWaves * rlayout(a.lim, bwd, sg).end;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),

@@ -117,6 +117,8 @@ void build_chains(const InstDesc &D, const std::vector<int32_t> &consumer, HostP
   ci.ok = 1;
   ci.nw = D.nw;
   bool ok_rq = true;
+  for (int p = 0; p < D.nr; ++p)
+    if (P.fld_ptr[D.fld_off + p + 1] - P.fld_ptr[D.fld_off + p] > 4) ok_rq = false;
   ci.n_chains = (int32_t)chains.size();
   for (auto &ch : chains) {
     ChainDesc cd{};
@@ -131,6 +133,14 @@ void build_chains(const InstDesc &D, const std::vector<int32_t> &consumer, HostP
     cd.f_hi = P.fld_ptr[D.fld_off + cd.pos_hi];
     ci.npos_max = std::max(ci.npos_max, cd.pos_hi - cd.pos_lo);
     ci.max_steps = std::max(ci.max_steps, cd.n_steps);
+    // register-resident form: one tile count for every step of the chain
+    int rt = 1;
+    for (int t : ch) {
+      const int K = 1 << st[t].g, N = st[t].w == 0 ? 1 : 1 << st[t].w;
+      while (16 * rt < K || 16 * rt < N) rt <<= 1;
+    }
+    cd.rt = rt;
+    ci.rtiles = std::max(ci.rtiles, rt);
     for (int t : ch) {
       const StepDesc &sd = st[t];
       ChainStep cs{};
@@ -180,21 +190,20 @@ void build_chains(const InstDesc &D, const std::vector<int32_t> &consumer, HostP
       auto tv = [&](int x, int o) {
         return (x < K && o < N) ? (float)T[((int64_t)x << sd.w) | o] : 0.0f;
       };
-      const int KT = cs.kp / 16, NT16 = sd.w == 0 ? 1 : cs.np / 16, KC2 = (KT + 1) / 2;
-      cs.nt16 = NT16;
-      ci.rtiles = std::max({ci.rtiles, KT, NT16});
+      const int CT = rt, KC2 = (CT + 1) / 2;
+      cs.nt16 = sd.w == 0 ? 1 : cs.np / 16;
       cs.tr_off = (int64_t)P.Tr.size();
-      for (int nt = 0; nt < NT16; ++nt)
-        for (int xt = 0; xt < KT; ++xt)
+      for (int nt = 0; nt < CT; ++nt)
+        for (int xt = 0; xt < CT; ++xt)
           for (int l = 0; l < 64; ++l)
             for (int r = 0; r < 4; ++r) P.Tr.push_back(tv(16 * xt + 4 * (l >> 4) + r, 16 * nt + (l & 15)));
       cs.tq_off = (int64_t)P.Tq.size();
-      for (int xt = 0; xt < KT; ++xt)
-        for (int nt = 0; nt < NT16; ++nt)
+      for (int xt = 0; xt < CT; ++xt)
+        for (int nt = 0; nt < CT; ++nt)
           for (int l = 0; l < 64; ++l)
             for (int r = 0; r < 4; ++r) P.Tq.push_back(tv(16 * xt + (l & 15), 16 * nt + 4 * (l >> 4) + r));
       cs.trb_off = (int64_t)P.Trb.size();
-      for (int nt = 0; nt < NT16; ++nt)
+      for (int nt = 0; nt < CT; ++nt)
         for (int c = 0; c < KC2; ++c)
           for (int l = 0; l < 64; ++l)
             for (int i = 0; i < 8; ++i)
@@ -340,6 +349,15 @@ tnvan_status compile_instance(const tnvan_instance &in, int max_width,
       }
     }
     P.fld_ptr.push_back(c);
+    // dense form: four (W index, J, W-R edge) slots per R position, unused
+    // slots (0, 0, -1); positions with more W-neighbours keep only the CSR
+    for (int p = 0; p < nr; ++p)
+      for (int k = 0; k < 4; ++k) {
+        const bool u = k < (int)fld[p].size();
+        P.cf_w.push_back(u ? fld[p][k].first : 0);
+        P.cf_J.push_back(u ? (float)fld[p][k].second : 0.0f);
+        P.cf_r.push_back(u ? fldk[p][k] : -1);
+      }
   }
   D.hr_off = (int32_t)P.hR.size();
   D.vr_off = (int32_t)P.vr.size();

@@ -137,11 +137,14 @@ struct MGradArgs {
   float *part;                  // [n_tasks][pstride]
   int64_t pstride;
   const int32_t *first_row, *n_rows;   // per instance: its workgroup rows
+  float *part2;                 // [n_inst][mgrad_split()][pstride]
+  const float *pack;            // made_pack_kernel output (holds the masked W2^T)
   float *grad;                  // flat parameter gradient
 };
 size_t mgrad_lds_bytes(int H, int npt);
+int mgrad_split();
 hipError_t launch_mgrad(const MGradArgs &a, int npt, hipStream_t st);
-int64_t made_pack_floats(int n, int npt);
+int64_t made_pack_floats(int n, int npt, int H);
 hipError_t launch_made_pack(const MadeInst *mi, int n_inst, int64_t max_floats, const float *params,
                             float *pack, int npt, hipStream_t st);
 hipError_t launch_msample(const MSampleArgs &a, int npt, hipStream_t st);
@@ -239,7 +242,21 @@ struct ChainArgs {
   const uint16_t *Trb;
   const int32_t *xcol;
   int32_t sg;                       // 16-sample groups per wave (forward)
+  int32_t task_base;                // first task of the launch
+  // dense W-neighbour slots of every R position (index hr_off + position)
+  const int32_t *cf_w, *cf_r;       // [4] per position: W index, W-R edge (-1: unused)
+  const float *cf_J;                // [4] per position
+  // unary factors of every (R position, sample), position-major per
+  // instance: +-exp(-2 beta |f|), negative when f < 0 (unary_kernel)
+  const float *U;
+  const int64_t *u_off;             // per instance
 };
+// U and the per-sample sums of beta |f| over each run of kUnaryChunk
+// positions (fabp[f_off[q] + chunk * B + b]) of the instances in cis.
+constexpr int kUnaryChunk = 16;
+hipError_t launch_unary(const ChainArgs &a, const int32_t *cis, int n_cis, int max_chunks,
+                        int64_t max_B, const int64_t *f_off, float *U, double *fabp,
+                        hipStream_t st);
 // LDS bytes: shared part of a workgroup and per-wave part
 size_t chain_shared_lds(const ChainLim &L, bool bwd, bool bf16);
 size_t chain_wave_lds(const ChainLim &L, bool bwd);
@@ -255,10 +272,11 @@ size_t rchain_wave_lds(const ChainLim &L, bool bwd, int sg);
 int64_t rchain_ckpt_floats(const ChainLim &L);   // per adjoint task
 hipError_t launch_rchain(const ChainArgs &a, bool bwd, hipStream_t st);
 // logz[b] = log_const + sum over chains of the per-chain partials
+// (plus the unary sums fabp of launch_unary when fabp is not null)
 hipError_t launch_chain_sum(const InstDesc *inst, const ChainInst *cinst,
                             const int32_t *chain_insts, int n_chain_insts,
                             const int64_t *inst_B, const int64_t *inst_sample_off,
-                            const int64_t *cpart_off, const double *cpart, double *logz,
-                            hipStream_t st);
+                            const int64_t *cpart_off, const double *cpart, const int64_t *f_off,
+                            const double *fabp, double *logz, hipStream_t st);
 
 }  // namespace tnvan

@@ -454,8 +454,13 @@ __global__ void bump_kernel(int32_t *c, int n) {
 //   PB2 [NPT][64][4]     b2[16 t + 4 (l >> 4) + r]
 // with k(i, u) = i + (n - 1) u the u-th hidden unit of degree i + 1.
 
-__host__ __device__ inline int64_t mpack_floats(int n, int npt) {
+__host__ __device__ inline int64_t msample_floats(int n, int npt) {
   return (int64_t)n * npt * 512 + (int64_t)n * 256 + (int64_t)npt * 256;
+}
+// sampler tables, then W2T [H][n]: W2[pos][k] where deg(k) <= pos, else 0
+// (the transposed masked W2 of the fused backward), padded to 64 floats
+__host__ __device__ inline int64_t mpack_floats(int n, int npt, int H) {
+  return msample_floats(n, npt) + ((int64_t)H * n + 63) / 64 * 64;
 }
 
 __global__ void made_pack_kernel(const MadeInst *mi, const float *params, float *pack, int npt) {
@@ -464,12 +469,17 @@ __global__ void made_pack_kernel(const MadeInst *mi, const float *params, float 
   const float *W1 = params + m.param_off, *b1 = W1 + (int64_t)Hs * n, *W2 = b1 + Hs,
               *b2 = W2 + (int64_t)n * Hs, *W0 = b2 + n;
   const int64_t sa = (int64_t)n * npt * 256, sb = (int64_t)n * 256;
-  const int64_t total = mpack_floats(n, npt);
+  const int64_t tsamp = msample_floats(n, npt);
+  const int64_t total = tsamp + (int64_t)Hs * n;
   float *P = pack + m.pack_off;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     float v = 0.f;
-    if (idx < 2 * sa) {
+    if (idx >= tsamp) {
+      const int64_t e = idx - tsamp;
+      const int k = (int)(e / n), pos = (int)(e % n);
+      if (k < H && 1 + k % (n - 1) <= pos) v = W2[(int64_t)pos * Hs + k];
+    } else if (idx < 2 * sa) {
       const int64_t e = idx < sa ? idx : idx - sa;
       const int r = (int)(e & 3), lane = (int)((e >> 2) & 63);
       const int t = (int)((e >> 8) % npt), i = (int)((e >> 8) / npt);
@@ -662,7 +672,12 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
   float *sfb = reinterpret_cast<float *>(smem + Lm.sf);
   const float *W1 = a.params + mi.param_off, *b1 = W1 + (int64_t)Hs * n, *W2 = b1 + Hs,
               *b2 = W2 + (int64_t)n * Hs, *W0 = b2 + n;
+  const float *W2T = a.pack + mi.pack_off + msample_floats(n, NPT);
   const int nm1 = n > 1 ? n - 1 : 1;
+  // four consecutive parameters p[0..3] (rows are multiples of 4 floats long)
+  auto ld4 = [](const float *p, bool ok) {
+    return ok ? *reinterpret_cast<const f4 *>(p) : f4{0.f, 0.f, 0.f, 0.f};
+  };
   {
     // rows of the wave's 16 samples
     const int64_t sb = bw + 16 * wave + ls;
@@ -690,12 +705,16 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
           acc[r] = k < H ? b1[k] : 0.f;
         }
         const int ka = 16 * ht + ls, dga = 1 + ka % nm1;
+        f4 wl[NPT];
+#pragma unroll
+        for (int t = 0; t < NPT; ++t)
+          wl[t] = ld4(W1 + (int64_t)ka * n + 16 * t + 4 * lg, ka < H && 16 * t + 4 * lg < n);
 #pragma unroll
         for (int t = 0; t < NPT; ++t)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int j = 16 * t + 4 * lg + r;
-            const float wv = (ka < H && j < dga && j < n) ? W1[(int64_t)ka * n + j] : 0.f;
+            const float wv = j < dga ? wl[t][r] : 0.f;
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, sp[t][r], acc, 0, 0, 0);
           }
 #pragma unroll
@@ -714,21 +733,25 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
       const int pa = 16 * pt + ls;
 #pragma unroll
       for (int ht = 0; ht < kMgTiles; ++ht)
-        if (ht < HT)
+        if (ht < HT) {
+          const f4 wz = ld4(W2 + (int64_t)pa * Hs + 16 * ht + 4 * lg, pa < n && 16 * ht + 4 * lg < H);
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int k = 16 * ht + 4 * lg + r;
-            const float wv = (pa < n && k < H && 1 + k % nm1 <= pa) ? W2[(int64_t)pa * Hs + k] : 0.f;
+            const float wv = 1 + k % nm1 <= pa ? wz[r] : 0.f;
             z = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, h[ht][r], z, 0, 0, 0);
           }
+        }
 #pragma unroll
-      for (int t = 0; t < NPT; ++t)
+      for (int t = 0; t < NPT; ++t) {
+        const f4 w0 = ld4(W0 + (int64_t)pa * n + 16 * t + 4 * lg, pa < n && 16 * t + 4 * lg < n);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int j = 16 * t + 4 * lg + r;
-          const float wv = (pa < n && j < pa) ? W0[(int64_t)pa * n + j] : 0.f;
+          const float wv = j < pa ? w0[r] : 0.f;
           z = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, sp[t][r], z, 0, 0, 0);
         }
+      }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int pos = 16 * pt + 4 * lg + r;
@@ -748,15 +771,14 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
     for (int ht = 0; ht < kMgTiles; ++ht)
       if (ht < HT) {
         f4 acc = f4{0.f, 0.f, 0.f, 0.f};
-        const int ka = 16 * ht + ls, dga = 1 + ka % nm1;
+        const int ka = 16 * ht + ls;
 #pragma unroll
-        for (int pt = 0; pt < NPT; ++pt)
+        for (int pt = 0; pt < NPT; ++pt) {
+          const f4 wt2 = ld4(W2T + (int64_t)ka * n + 16 * pt + 4 * lg, ka < H && 16 * pt + 4 * lg < n);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int pos = 16 * pt + 4 * lg + r;
-            const float wv = (ka < H && pos < n && dga <= pos) ? W2[(int64_t)pos * Hs + ka] : 0.f;
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, dl[pt][r], acc, 0, 0, 0);
-          }
+          for (int r = 0; r < 4; ++r)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wt2[r], dl[pt][r], acc, 0, 0, 0);
+        }
         *reinterpret_cast<f4 *>(hid + srow * Lm.ldh + 16 * ht + 4 * lg) =
             f4{h[ht][0], h[ht][1], h[ht][2], h[ht][3]};
         f4 dv;
@@ -829,19 +851,37 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
   }
 }
 
-// grad[param_off + p] = sum over the instance's workgroup rows (fixed order)
-__global__ void mgrad_reduce(const MadeInst *mi, const int32_t *first_row, const int32_t *n_rows,
-                             const float *part, int64_t pstride, float *grad) {
+// Sum of the instance's workgroup rows in a fixed order, in two passes:
+// slice z of the rows (rows r0 + z, r0 + z + kRedSplit, ...) into part2[q][z],
+// then the kRedSplit slices into grad.  Four parameters per thread.
+constexpr int kRedSplit = 16;
+__device__ inline int64_t made_pc(const MadeInst &m) {
+  return (int64_t)m.H * m.n + m.H + (int64_t)m.n * m.H + m.n + (int64_t)m.n * m.n;
+}
+__global__ void mgrad_reduce1(const MadeInst *mi, const int32_t *first_row, const int32_t *n_rows,
+                              const float *part, int64_t pstride, float *part2) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const int q = blockIdx.y, z = blockIdx.z;
+  const int64_t pc = made_pc(mi[q]);
+  const int r0 = first_row[q], nr = n_rows[q];
+  const int64_t p = 4 * (blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+  if (p >= pc) return;
+  f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+  for (int r = z; r < nr; r += kRedSplit)
+    acc += *reinterpret_cast<const f4 *>(part + (int64_t)(r0 + r) * pstride + p);
+  *reinterpret_cast<f4 *>(part2 + ((int64_t)q * kRedSplit + z) * pstride + p) = acc;
+}
+__global__ void mgrad_reduce2(const MadeInst *mi, const float *part2, int64_t pstride,
+                              float *grad) {
   const int q = blockIdx.y;
   const MadeInst m = mi[q];
-  const int64_t pc = (int64_t)m.H * m.n + m.H + (int64_t)m.n * m.H + m.n + (int64_t)m.n * m.n;
-  const int r0 = first_row[q], nr = n_rows[q];
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < pc;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    for (int r = 0; r < nr; ++r) acc += (double)part[(int64_t)(r0 + r) * pstride + p];
-    grad[m.param_off + p] = (float)acc;
-  }
+  const int64_t pc = made_pc(m);
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= pc) return;
+  double acc = 0.0;
+#pragma unroll
+  for (int z = 0; z < kRedSplit; ++z) acc += (double)part2[((int64_t)q * kRedSplit + z) * pstride + p];
+  grad[m.param_off + p] = (float)acc;
 }
 
 }  // namespace
@@ -850,9 +890,11 @@ constexpr size_t kStageMax = 96 * 1024;
 
 size_t made_param_bytes(int n, int H) { return made_stage_bytes(n, H); }
 
-int64_t made_pack_floats(int n, int npt) { return mpack_floats(n, npt); }
+int64_t made_pack_floats(int n, int npt, int H) { return mpack_floats(n, npt, H); }
+int64_t made_w2t_offset(int n, int npt) { return msample_floats(n, npt); }
 
 size_t mgrad_lds_bytes(int H, int npt) { return mg_layout(H, npt).end; }
+int mgrad_split() { return kRedSplit; }
 
 hipError_t launch_mgrad(const MGradArgs &a, int npt, hipStream_t st) {
   if (a.n_tasks <= 0) return hipSuccess;
@@ -865,8 +907,12 @@ hipError_t launch_mgrad(const MGradArgs &a, int npt, hipStream_t st) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(a.n_tasks), dim3(256), lds, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(mgrad_reduce, dim3(64, a.n_inst), dim3(256), 0, st, a.mi, a.first_row,
-                     a.n_rows, a.part, a.pstride, a.grad);
+  const unsigned bx1 = (unsigned)((a.pstride / 4 + 255) / 256), bx2 = (unsigned)((a.pstride + 255) / 256);
+  hipLaunchKernelGGL(mgrad_reduce1, dim3(bx1, a.n_inst, kRedSplit), dim3(256), 0, st, a.mi,
+                     a.first_row, a.n_rows, a.part, a.pstride, a.part2);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(mgrad_reduce2, dim3(bx2, a.n_inst), dim3(256), 0, st, a.mi, a.part2,
+                     a.pstride, a.grad);
   return hipGetLastError();
 }
 

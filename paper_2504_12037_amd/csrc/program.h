@@ -110,6 +110,7 @@ struct ChainStep {
   int64_t tt_off;     // FP32 [np][kp] (transposed, for the adjoint)
   int64_t tb_off;     // BF16 packed in the 16x16x32 operand order
   // register-resident form (see the comment below)
+  // (every step of a chain padded with zeros to the chain's rt x rt tiles)
   int64_t tr_off;     // FP32 [nt][xt][lane][4]: T[16xt + 4(lane>>4) + r][16nt + (lane&15)]
   int64_t tq_off;     // FP32 [xt][nt][lane][4]: T[16xt + (lane&15)][16nt + 4(lane>>4) + r]
   int64_t trb_off;    // BF16 [nt][c][lane][8]: T[16(2c + i/4) + 4(lane>>4) + i%4][16nt + (lane&15)]
@@ -143,6 +144,8 @@ struct ChainDesc {
   int64_t tbl_src;           // offset in the BF16 block array
   int32_t e_src, n_e;        // the chain's edges in the chain edge array
   int32_t f_lo, f_hi;        // W-neighbour entries of the chain's positions
+  int32_t rt;                // register-resident form: tiles of every step (1, 2, 4, ...)
+  int32_t pad;
 };
 
 struct ChainInst {
@@ -159,7 +162,8 @@ struct ChainInst {
   int32_t ne_max;            // most edges of one chain
   int32_t nf_max;            // most W-neighbour entries of one chain
   int32_t rtiles;            // widest step in 16-state tiles (register-resident form)
-  int32_t rq_ok;             // every step fits the 16-column adjoint products
+  int32_t rq_ok;             // every step fits the 16-column adjoint products and
+                             // every R position has at most 4 W-neighbours
   int32_t pad;
 };
 
