@@ -35,15 +35,38 @@ METRIC = ("conditional logZ samples/s (fwd+adjoint) at |dlogZ|/N<=1e-5 vs plain 
 BETAS = (0.5, 1.0, 2.0)
 B = 8192
 HIDDEN = 256
-# algorithmic flops per sample of the 16x16 workload's remainder contraction
-# (pairwise form: per row, one 2x2 mix per vertical bond over the row's 2^w
-# states plus the diagonal horizontal bonds and fields):
-#   forward = 2*(15*(4*5*32 + 32*2) + 32) + (15*(4*4*16 + 16*2) + 16) = 25520
-# and the adjoint twice that, so forward + adjoint = 76560 flops per sample
-FWD_FLOPS = 25520
-FWD_ADJ_FLOPS = 3 * FWD_FLOPS
-PEAK_FP32 = 157.3e12       # MI355X vector FP32 (published)
+NW = 32
+# Algorithmic flops per sample (one multiply-add = 2).  Remainder
+# contraction in the pairwise form: per row transition, one 2x2 mix per
+# vertical bond over the 2^w row states plus the diagonal horizontal bonds
+# and fields; 15 transitions and a closing sum per 16-row strip:
+#   two 16x5 strips: 2 * (15 * (4*5*32 + 32*2) + 32) = 21184
+#   one 16x4 strip:       15 * (4*4*16 + 16*2) + 16  =  4336
+# forward 25520; the adjoint is twice the forward (reverse sweep plus the
+# per-step correlation sums), so forward + adjoint = 76560.
+FWD_STRIP5 = 21184
+FWD_STRIP4 = 4336
+FWD_FLOPS = FWD_STRIP5 + FWD_STRIP4
+# masked network (|W| = 32, H = 256): forward 2 * 2 * 32 * 256 = 32768 flops
+# (the two masked products, dense count), backward about twice that
+MADE_FWD = 2 * 2 * NW * HIDDEN
+MADE_GRAD = 3 * MADE_FWD
+SAMPLE_FLOPS = 2 * HIDDEN * NW + NW * NW
+# per-kernel algorithmic flops per sample of the batch (every launch covers
+# all three instances)
+KERNEL_FLOPS = {
+    "chain_fwd_2": FWD_STRIP5, "chain_fwd_1": FWD_STRIP4,
+    "chain_bwd_2": 2 * FWD_STRIP5, "chain_bwd_1": 2 * FWD_STRIP4,
+    "made_grad": MADE_GRAD, "sample": SAMPLE_FLOPS,
+}
+KERNEL_NAMES = {
+    "chain_fwd_2": "rchain_fwd_kernel<false, 2, 2>", "chain_fwd_1": "rchain_fwd_kernel<false, 1, 2>",
+    "chain_bwd_2": "rchain_bwd_kernel<2>", "chain_bwd_1": "rchain_bwd_kernel<1>",
+    "made_grad": "mgrad_kernel<2>", "sample": "msample_kernel<2>",
+}
+PEAK_FP32 = 157.3e12       # MI355X FP32 (vector and 16x16x4 matrix), published
 PEAK_FP64 = 78.6e12
+PEAK_BF16 = 2.5e15
 
 
 def parse():
@@ -53,7 +76,10 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-samples", type=int, default=8192)
+    p.add_argument("--cpu-samples", type=int, default=24576,
+                   help="oracle samples per instance for cpu_baseline")
+    p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                   help="run one plain device copy of MIB MiB first (counter calibration)")
     return p.parse_args()
 
 
@@ -77,7 +103,7 @@ def cpu_baseline(insts, n_samples):
     t0 = time.perf_counter()
     for k, inst in enumerate(insts):
         spins = S.uniform_spins(n_samples, inst.n_width, 4242 + k)
-        OI.marginals_elimination(inst, spins, chunk=n_samples)
+        OI.marginals_elimination(inst, spins, chunk=8192)
     dt = time.perf_counter() - t0
     n_samples *= len(insts)
     cores = len(os.sched_getaffinity(0))
@@ -88,6 +114,31 @@ def cpu_baseline(insts, n_samples):
                        f"reverse pass (numpy FP64, BLAS threads OMP_NUM_THREADS="
                        f"{threads}; elementwise numpy is single-threaded), "
                        f"{dt:.1f} s")}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy calibration), or None when
+    there is none or the kernel sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_c2_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for src in fields.get("sources", "").split():
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if not fields.get("sources") or h.hexdigest() != fields.get("sources_sha256"):
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def main():
@@ -109,7 +160,16 @@ def main():
     nI = len(insts)
     counts = [B] * nI
     nw = insts[0].n_width
-    net = Net(insts, precision=args.precision, seed=2024)
+    if args.calibrate_copy > 0:
+        # a plain copy of known size: the HBM traffic counters of every kernel
+        # are scaled by what they read for it
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    net = Net(insts, precision=args.precision, seed=2024, flags=Net.FLAG_PROFILE)
     for k in range(nI):
         net.set_params(k, torch.from_numpy(S.made_init(nw, HIDDEN, 7 + k)))
     spins = torch.empty(nI * B * nw, dtype=torch.int8, device="cuda")
@@ -126,6 +186,8 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    for k in Net.KERNELS:
+        net.kernel_time(k)          # drop the warm-up launches
     t0 = time.perf_counter()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -137,6 +199,13 @@ def main():
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1) / args.steps
     value = nI * B / (ms / 1e3)
+    # per-kernel device time over the timed region (HIP events recorded by the
+    # library on the launch stream around each launch)
+    ktime = {}
+    for k in Net.KERNELS:
+        tot, n = net.kernel_time(k)
+        if n:
+            ktime[k] = (tot, n)
 
     # forward + adjoint alone, FP32 (or the chosen) path and plain FP64 path
     sp_fix = torch.from_numpy(S.uniform_spins(nI * B, nw, 102)).cuda().reshape(-1)
@@ -166,9 +235,14 @@ def main():
         err = max(err, float(np.abs(lz[k * B + idx] - want).max() / inst.n))
     err64 = float(np.abs(lz - lz64).max() / insts[0].n)
 
-    # dominant kernel: the fused recompute + adjoint contraction launch
-    achieved = FWD_ADJ_FLOPS * nI * B / t_bwd
-    peak = PEAK_FP64 if args.precision == "fp64" else PEAK_FP32
+    # dominant kernel of the step: the largest device time in the timed region
+    dom = max((k for k in ktime if k in KERNEL_FLOPS), key=lambda k: ktime[k][0])
+    dom_avg = ktime[dom][0] / ktime[dom][1]
+    achieved = KERNEL_FLOPS[dom] * nI * B / dom_avg
+    peak = {"fp64": PEAK_FP64, "fp32": PEAK_FP32, "bf16": PEAK_BF16}[args.precision]
+    if dom.startswith("chain_bwd") or dom == "made_grad":
+        peak = PEAK_FP32 if args.precision != "fp64" else PEAK_FP64   # FP32 products
+    traffic = measured_traffic(dom)
     res = {
         "metric": METRIC,
         "value": value,
@@ -185,10 +259,10 @@ def main():
         "config": {"workload": "16x16 OBC Gaussian spin glass, W = columns 6,11, "
                                "beta in {0.5,1,2}, 8192 samples each, MADE H=256",
                    "global_batch": nI * B, "instances": nI, "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                     "kernel": "contract_kernel (recompute + adjoint)",
-                     "kernel_avg_s": t_bwd},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+                     "kernel": KERNEL_NAMES[dom], "kernel_avg_s": dom_avg,
+                     "flops_per_launch": KERNEL_FLOPS[dom] * nI * B},
         "breakdown": {
             "fwd_adj_samples_per_s": nI * B / t_fa,
             "fwd_adj_fp64_path_samples_per_s": nI * B / t_fa64,
@@ -198,6 +272,7 @@ def main():
             "max_abs_dlogZ_per_N_vs_oracle": err,
             "max_abs_dlogZ_per_N_vs_fp64_path": err64,
             "wall_s_timed_region": wall,
+            "kernel_avg_us": {KERNEL_NAMES.get(k, k): 1e6 * t / n for k, (t, n) in ktime.items()},
         },
     }
     if not args.no_cpu_baseline:

@@ -89,6 +89,21 @@ typedef struct {
  * instead of the register-resident ones (same results up to rounding; for
  * comparisons and timing). */
 #define TNVAN_FLAG_LDS_CHAIN 1
+/* Record HIP events on the launch stream around the kernels listed below;
+ * tnvan_kernel_time reads them back. */
+#define TNVAN_FLAG_PROFILE 2
+
+/* Kernels timed under TNVAN_FLAG_PROFILE. */
+typedef enum {
+  TNVAN_KERNEL_CHAIN_FWD_1 = 0,   /* register-resident forward, chains of 1 tile (K, N <= 16) */
+  TNVAN_KERNEL_CHAIN_FWD_2 = 1,   /* ... 2 tiles (K, N <= 32) */
+  TNVAN_KERNEL_CHAIN_FWD_4 = 2,   /* ... 4 tiles (K, N <= 64) */
+  TNVAN_KERNEL_CHAIN_BWD_1 = 3,   /* register-resident adjoint, chains of 1 tile */
+  TNVAN_KERNEL_CHAIN_BWD_2 = 4,   /* ... 2 tiles */
+  TNVAN_KERNEL_SAMPLE = 5,        /* matrix-core sampler */
+  TNVAN_KERNEL_MADE_GRAD = 6,     /* fused REINFORCE backward (without its row reduction) */
+  TNVAN_KERNEL_COUNT = 7
+} tnvan_kernel;
 
 /* Compile n_inst instances into one net (host work plus device uploads,
  * synchronous).  Validates every instance: W and order disjoint and covering
@@ -178,6 +193,13 @@ tnvan_status tnvan_free_energy_step(tnvan_net *net, const int64_t *n_samples,
  *   [3] flops per sample of the forward contraction (2 per multiply-add,
  *   counting the dense step form as executed), [4] |W|, [5] |R| */
 tnvan_status tnvan_program_info(const tnvan_net *net, int32_t inst, int64_t info[6]);
+
+/* Total device time (milliseconds, from the recorded HIP events) and number
+ * of launches of one kernel since the previous call for that kernel (waits
+ * for the recorded launches to finish).  Needs TNVAN_FLAG_PROFILE at build,
+ * else TNVAN_E_STATE. */
+tnvan_status tnvan_kernel_time(tnvan_net *net, int32_t kernel, double *total_ms,
+                               int64_t *launches);
 
 /* Host-only planning: validate and compile one instance without touching a
  * device and report the same statistics as tnvan_program_info. */

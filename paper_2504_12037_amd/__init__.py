@@ -55,8 +55,9 @@ class Net:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            _lib.lib().tnvan_free_network(h)
+        lib = getattr(_lib, "_lib", None)
+        if h is not None and h.value and lib is not None:
+            lib.tnvan_free_network(h)
             self._h = None
 
     # ---------------------------------------------------------------- helpers
@@ -74,6 +75,20 @@ class Net:
         out = (C.c_int64 * 6)()
         _lib.check(_lib.lib().tnvan_program_info(self._h, inst, out))
         return tuple(int(x) for x in out)
+
+    # kernel ids of tnvan_kernel_time (built with flags=FLAG_PROFILE)
+    KERNELS = {"chain_fwd_1": 0, "chain_fwd_2": 1, "chain_fwd_4": 2, "chain_bwd_1": 3,
+               "chain_bwd_2": 4, "sample": 5, "made_grad": 6}
+    FLAG_LDS_CHAIN = 1
+    FLAG_PROFILE = 2
+
+    def kernel_time(self, kernel):
+        """(total seconds, launches) of one kernel since the previous read."""
+        k = self.KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+        ms = C.c_double()
+        n = C.c_int64()
+        _lib.check(_lib.lib().tnvan_kernel_time(self._h, k, C.byref(ms), C.byref(n)))
+        return ms.value / 1e3, int(n.value)
 
     def param_count(self, inst: int = 0) -> int:
         n = C.c_int64()

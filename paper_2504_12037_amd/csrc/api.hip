@@ -117,6 +117,9 @@ struct tnvan_net {
   // register-resident chain kernels (per-wave tasks)
   DBuf Tr, Tq, Trb, xcol, cf_w, cf_r, cf_J;
   DBuf Ubuf, fabp, u_off, f_off;
+  // kernel timing (TNVAN_FLAG_PROFILE): event pairs recorded since the last read
+  bool profile = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_used[TNVAN_KERNEL_COUNT], prof_pool;
   int u_chunks = 0;
   int64_t u_maxB = 0;
   bool rfwd = false, rbwd = false;
@@ -145,6 +148,30 @@ struct tnvan_net {
 namespace {
 
 int ilog2(int x) { int r = 0; while ((1 << r) < x) ++r; return r; }
+
+// Events around one launch of a profiled kernel (no-op unless profiling).
+struct ProfScope {
+  tnvan_net *net;
+  int kind;
+  hipStream_t st;
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  ProfScope(tnvan_net *n, int k, hipStream_t s) : net(n), kind(k), st(s) {
+    if (!net->profile || kind < 0 || kind >= TNVAN_KERNEL_COUNT) return;
+    if (!net->prof_pool.empty()) {
+      ev = net->prof_pool.back();
+      net->prof_pool.pop_back();
+    } else if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess) {
+      ev = {nullptr, nullptr};
+      return;
+    }
+    hipEventRecord(ev.first, st);
+  }
+  ~ProfScope() {
+    if (!ev.first) return;
+    hipEventRecord(ev.second, st);
+    net->prof_used[kind].push_back(ev);
+  }
+};
 
 // Largest S (power of two <= 64) whose tile fits the LDS budget.
 void choose_tiles(tnvan_net *net, bool bwd) {
@@ -442,6 +469,8 @@ tnvan_status run_logz(tnvan_net *net, const int8_t *spins, double *logz, hipStre
         c.n_tasks = net->rg_n[gi];
         c.ntm = 1 << gi;
         c.sg = net->sg_of(1 << gi);
+        if (c.n_tasks <= 0) continue;
+        ProfScope ps(net, TNVAN_KERNEL_CHAIN_FWD_1 + gi, st);
         HIPCHK(launch_rchain(c, false, st));
       }
     } else {
@@ -492,6 +521,8 @@ tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *gra
         c.task_base = net->brg_lo[gi];
         c.n_tasks = net->brg_n[gi];
         c.ntm = 1 << gi;
+        if (c.n_tasks <= 0) continue;
+        ProfScope ps(net, TNVAN_KERNEL_CHAIN_BWD_1 + gi, st);
         HIPCHK(launch_rchain(c, true, st));
       }
     } else {
@@ -592,7 +623,10 @@ tnvan_status run_sample(tnvan_net *net, const float *uniforms, int8_t *spins, vo
     m.logq = reinterpret_cast<float *>(logq);
     m.seed = net->seed;
     m.step_ctr = net->step_ctr.as<int32_t>();
-    HIPCHK(launch_msample(m, net->mpt, st));
+    {
+      ProfScope ps(net, TNVAN_KERNEL_SAMPLE, st);
+      HIPCHK(launch_msample(m, net->mpt, st));
+    }
     return TNVAN_OK;
   }
   SampleArgs<real> a{};
@@ -669,7 +703,11 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     g.part2 = net->w_part2.as<float>();
     g.pack = net->mpack.as<float>();
     g.grad = net->grad.as<float>();
-    HIPCHK(launch_mgrad(g, net->mpt, st));
+    {
+      ProfScope ps(net, TNVAN_KERNEL_MADE_GRAD, st);
+      HIPCHK(launch_mgrad(g, net->mpt, st));
+    }
+    HIPCHK(launch_mgrad_reduce(g, st));
   }
   for (int q = 0; q < net->n_inst; ++q) {
     const MadeInst &m = net->mi[q];
@@ -745,6 +783,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   if (!net) return set_err(TNVAN_E_NOMEM, "host allocation failed");
   net->precision = opt->precision;
   net->seed = opt->seed;
+  net->profile = (opt->flags & TNVAN_FLAG_PROFILE) != 0;
   net->n_inst = n_inst;
   for (int q = 0; q < n_inst; ++q) {
     std::string msg;
@@ -931,6 +970,13 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
 
 void tnvan_free_network(tnvan_net *net) {
   if (!net) return;
+  for (auto &v : net->prof_used)
+    for (auto &e : v) net->prof_pool.push_back(e);
+  for (auto &e : net->prof_pool) {
+    hipEventDestroy(e.first);
+    hipEventDestroy(e.second);
+  }
+  net->prof_pool.clear();
   DBuf *all[] = {&net->inst, &net->steps, &net->inputs, &net->edges, &net->T, &net->fld_ptr,
                  &net->fld_w, &net->fld_J, &net->hR, &net->wr_pos, &net->wr_w, &net->rr_edge,
                  &net->rr_J, &net->wr_edge, &net->wr_J, &net->hR64, &net->vr, &net->ww_a,
@@ -1054,6 +1100,30 @@ tnvan_status tnvan_program_info(const tnvan_net *net, int32_t inst, int64_t info
   const InstDesc &D = net->P.insts[inst];
   info[0] = D.n_steps; info[1] = D.max_w; info[2] = D.arena_all;
   info[3] = net->P.flops_fwd[inst]; info[4] = D.nw; info[5] = D.nr;
+  return TNVAN_OK;
+}
+
+tnvan_status tnvan_kernel_time(tnvan_net *net, int32_t kernel, double *total_ms,
+                               int64_t *launches) {
+  if (tnvan_status s = check_net(net)) return s;
+  if (kernel < 0 || kernel >= TNVAN_KERNEL_COUNT || !total_ms || !launches)
+    return set_err(TNVAN_E_INVALID, "bad kernel id or output pointer");
+  if (!net->profile) return set_err(TNVAN_E_STATE, "net built without TNVAN_FLAG_PROFILE");
+  double tot = 0.0;
+  int64_t n = 0;
+  auto &used = net->prof_used[kernel];
+  for (auto &e : used) {
+    hipError_t r = hipEventSynchronize(e.second);
+    float ms = 0.f;
+    if (r == hipSuccess) r = hipEventElapsedTime(&ms, e.first, e.second);
+    if (r != hipSuccess) return set_err(TNVAN_E_HIP, "event timing: %s", hipGetErrorString(r));
+    tot += ms;
+    ++n;
+    net->prof_pool.push_back(e);
+  }
+  used.clear();
+  *total_ms = tot;
+  *launches = n;
   return TNVAN_OK;
 }
 

@@ -144,6 +144,7 @@ struct MGradArgs {
 size_t mgrad_lds_bytes(int H, int npt);
 int mgrad_split();
 hipError_t launch_mgrad(const MGradArgs &a, int npt, hipStream_t st);
+hipError_t launch_mgrad_reduce(const MGradArgs &a, hipStream_t st);
 int64_t made_pack_floats(int n, int npt, int H);
 hipError_t launch_made_pack(const MadeInst *mi, int n_inst, int64_t max_floats, const float *params,
                             float *pack, int npt, hipStream_t st);

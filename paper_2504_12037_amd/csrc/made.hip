@@ -906,7 +906,12 @@ hipError_t launch_mgrad(const MGradArgs &a, int npt, hipStream_t st) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k, dim3(a.n_tasks), dim3(256), lds, st, a);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_mgrad_reduce(const MGradArgs &a, hipStream_t st) {
+  if (a.n_tasks <= 0) return hipSuccess;
+  hipError_t e;
   const unsigned bx1 = (unsigned)((a.pstride / 4 + 255) / 256), bx2 = (unsigned)((a.pstride + 255) / 256);
   hipLaunchKernelGGL(mgrad_reduce1, dim3(bx1, a.n_inst, kRedSplit), dim3(256), 0, st, a.mi,
                      a.first_row, a.n_rows, a.part, a.pstride, a.part2);
