@@ -92,6 +92,12 @@ typedef struct {
 /* Record HIP events on the launch stream around the kernels listed below;
  * tnvan_kernel_time reads them back. */
 #define TNVAN_FLAG_PROFILE 2
+/* tnvan_free_energy_step replays the whole training step from a captured HIP
+ * graph.  A call whose batch shape, stats / spins_out pointers or lr differ
+ * from the recorded ones, or that follows a change of the net's device
+ * buffers or tables (another batch shape in any call), runs eagerly and
+ * records a new graph for the next calls. */
+#define TNVAN_FLAG_GRAPH 4
 
 /* Kernels timed under TNVAN_FLAG_PROFILE. */
 typedef enum {

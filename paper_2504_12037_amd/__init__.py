@@ -81,6 +81,7 @@ class Net:
                "chain_bwd_2": 4, "sample": 5, "made_grad": 6}
     FLAG_LDS_CHAIN = 1
     FLAG_PROFILE = 2
+    FLAG_GRAPH = 4
 
     def kernel_time(self, kernel):
         """(total seconds, launches) of one kernel since the previous read."""

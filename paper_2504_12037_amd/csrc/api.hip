@@ -3,6 +3,8 @@
 // every step of the path runs in the kernels of contract.hip and made.hip.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
@@ -42,6 +44,12 @@ tnvan_status set_err(tnvan_status s, const char *fmt, ...) {
       return set_err(TNVAN_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));    \
   } while (0)
 
+// Generation of every device buffer's address and of every uploaded table:
+// bumped on each reallocation and upload, so that a captured graph (whose
+// kernel arguments hold addresses and whose task tables hold one batch
+// shape) is known to be stale.
+std::atomic<uint64_t> g_buf_gen{1};
+
 // Device buffer that grows on demand (contents are not preserved).
 struct DBuf {
   void *p = nullptr;
@@ -49,6 +57,7 @@ struct DBuf {
   hipError_t ensure(size_t need) {
     if (need <= bytes) return hipSuccess;
     if (p) { hipFree(p); p = nullptr; bytes = 0; }
+    g_buf_gen.fetch_add(1);
     hipError_t e = hipMalloc(&p, need);
     if (e == hipSuccess) bytes = need;
     return e;
@@ -62,6 +71,7 @@ hipError_t upload(DBuf &b, const std::vector<T> &v) {
   size_t n = std::max<size_t>(1, v.size()) * sizeof(T);
   hipError_t e = b.ensure(n);
   if (e != hipSuccess) return e;
+  g_buf_gen.fetch_add(1);
   if (!v.empty()) e = hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
   return e;
 }
@@ -117,6 +127,17 @@ struct tnvan_net {
   // register-resident chain kernels (per-wave tasks)
   DBuf Tr, Tq, Trb, xcol, cf_w, cf_r, cf_J;
   DBuf Ubuf, fabp, u_off, f_off;
+  // training step replayed from a captured graph (TNVAN_FLAG_GRAPH)
+  bool use_graph = false, capturing = false;
+  hipStream_t cap_stream = nullptr;
+  struct StepGraph {
+    hipGraphExec_t exec = nullptr;
+    std::vector<int64_t> key;
+    double *stats = nullptr;
+    int8_t *spins = nullptr;
+    float lr = 0.f;
+    uint64_t gen = 0;
+  } step_graph;
   // kernel timing (TNVAN_FLAG_PROFILE): event pairs recorded since the last read
   bool profile = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_used[TNVAN_KERNEL_COUNT], prof_pool;
@@ -156,7 +177,7 @@ struct ProfScope {
   hipStream_t st;
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
   ProfScope(tnvan_net *n, int k, hipStream_t s) : net(n), kind(k), st(s) {
-    if (!net->profile || kind < 0 || kind >= TNVAN_KERNEL_COUNT) return;
+    if (!net->profile || net->capturing || kind < 0 || kind >= TNVAN_KERNEL_COUNT) return;
     if (!net->prof_pool.empty()) {
       ev = net->prof_pool.back();
       net->prof_pool.pop_back();
@@ -784,6 +805,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   net->precision = opt->precision;
   net->seed = opt->seed;
   net->profile = (opt->flags & TNVAN_FLAG_PROFILE) != 0;
+  net->use_graph = (opt->flags & TNVAN_FLAG_GRAPH) != 0;
   net->n_inst = n_inst;
   for (int q = 0; q < n_inst; ++q) {
     std::string msg;
@@ -970,6 +992,8 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
 
 void tnvan_free_network(tnvan_net *net) {
   if (!net) return;
+  if (net->step_graph.exec) hipGraphExecDestroy(net->step_graph.exec);
+  if (net->cap_stream) hipStreamDestroy(net->cap_stream);
   for (auto &v : net->prof_used)
     for (auto &e : v) net->prof_pool.push_back(e);
   for (auto &e : net->prof_pool) {
@@ -1090,8 +1114,50 @@ tnvan_status tnvan_free_energy_step(tnvan_net *net, const int64_t *n_samples, fl
     if (!(D.beta > 0)) return set_err(TNVAN_E_INVALID, "free_energy_step needs beta > 0");
   if (tnvan_status s = set_batch(net, n_samples)) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (net->precision == TNVAN_FP64) return run_step<double>(net, lr, stats, spins_out, st);
-  return run_step<float>(net, lr, stats, spins_out, st);
+  auto eager = [&](hipStream_t s2) {
+    return net->precision == TNVAN_FP64 ? run_step<double>(net, lr, stats, spins_out, s2)
+                                        : run_step<float>(net, lr, stats, spins_out, s2);
+  };
+  if (!net->use_graph) return eager(st);
+  auto &G = net->step_graph;
+  if (G.exec && G.key == net->nkey && G.stats == stats && G.spins == spins_out && G.lr == lr &&
+      G.gen == g_buf_gen.load()) {
+    HIPCHK(hipGraphLaunch(G.exec, st));
+    return TNVAN_OK;
+  }
+  // run this step eagerly (allocating and uploading what it needs), then
+  // record the same step on a private stream for the next calls
+  if (tnvan_status s = eager(st)) return s;
+  if (G.exec) {
+    hipGraphExecDestroy(G.exec);
+    G.exec = nullptr;
+  }
+  if (!net->cap_stream) HIPCHK(hipStreamCreateWithFlags(&net->cap_stream, hipStreamNonBlocking));
+  const uint64_t gen = g_buf_gen.load();
+  HIPCHK(hipStreamBeginCapture(net->cap_stream, hipStreamCaptureModeThreadLocal));
+  net->capturing = true;
+  tnvan_status s = eager(net->cap_stream);
+  net->capturing = false;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(net->cap_stream, &graph);
+  if (s != TNVAN_OK || e != hipSuccess || g_buf_gen.load() != gen) {
+    if (graph) hipGraphDestroy(graph);
+    if (s != TNVAN_OK) return s;
+    if (e != hipSuccess) return set_err(TNVAN_E_HIP, "graph capture: %s", hipGetErrorString(e));
+    return TNVAN_OK;   // buffers moved while recording: stay eager this call
+  }
+  e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    G.exec = nullptr;
+    return set_err(TNVAN_E_HIP, "graph instantiate: %s", hipGetErrorString(e));
+  }
+  G.key = net->nkey;
+  G.stats = stats;
+  G.spins = spins_out;
+  G.lr = lr;
+  G.gen = gen;
+  return TNVAN_OK;
 }
 
 tnvan_status tnvan_program_info(const tnvan_net *net, int32_t inst, int64_t info[6]) {

@@ -149,3 +149,37 @@ def test_free_energy_step_multi_instance_and_training():
     Fq1, _ = OO.exact_fq_and_grad(inst, th1, 16)
     F = OO.exact_free_energy(inst)
     assert F - 1e-9 <= Fq1 < Fq0
+
+
+def test_free_energy_step_graph_replay():
+    # the training step recorded once and replayed: every replay must equal
+    # the eager step of an identical net; eager work on other batch shapes
+    # (which moves the net's tables) runs between the replays
+    from paper_2504_12037_amd import Net
+    insts = [S.c1_small_lattice(16), S.lattice_column_split(S.lattice_2d(8, seed=2), [5], hidden=32),
+             S.c2_lattice(1.0, 64)]
+    Bs = [256, 384, 512]
+    nets = [_net(insts, "fp32", seed=21), _net(insts, "fp32", seed=21, flags=Net.FLAG_GRAPH)]
+    for net in nets:
+        for k, inst in enumerate(insts):
+            net.set_params(k, torch.from_numpy(_theta(inst.n_width, inst.hidden, 30 + k, 0.2)))
+    stats = [torch.empty(len(insts), 4, dtype=torch.float64, device="cuda") for _ in nets]
+    spins = [torch.empty(sum(b * i.n_width for b, i in zip(Bs, insts)), dtype=torch.int8,
+                         device="cuda") for _ in nets]
+    other = S.uniform_spins(100, insts[2].n_width, 5)
+    for it in range(8):
+        print(f"\n[graph] iteration {it}", flush=True)
+        for net, st, sp in zip(nets, stats, spins):
+            net.free_energy_step(Bs, 1e-2, stats=st, spins_out=sp)
+        torch.cuda.synchronize()
+        assert torch.equal(stats[0], stats[1]), (it, stats[0], stats[1])
+        assert torch.equal(spins[0], spins[1])
+        if it % 3 == 1:
+            # eager work on another batch shape between replays
+            lz = nets[1].logz(_dev(np.concatenate([S.uniform_spins(7, insts[0].n_width, 1).reshape(-1),
+                                                   S.uniform_spins(9, insts[1].n_width, 2).reshape(-1),
+                                                   other.reshape(-1)])), [7, 9, 100])
+            torch.cuda.synchronize()
+            assert torch.isfinite(lz).all()
+    for k in range(len(insts)):
+        assert torch.equal(nets[0].get_params(k), nets[1].get_params(k))
