@@ -38,6 +38,18 @@ template <typename real> __device__ inline real sigmoid(real z) {
                 : rexp<real>(z) / ((real)1 + rexp<real>(z));
 }
 
+// Short FP32 forms for the matrix-core kernels (hardware exp2/log2 and a
+// fast reciprocal; a few ulp, far inside the sampling tie band and the
+// gradient tolerance): tanh from exp(-2|x|), sigmoid, and log sigmoid.
+__device__ inline float ftanh(float x) {
+  const float t = __expf(-2.f * fabsf(x));
+  return copysignf(__fdividef(1.f - t, 1.f + t), x);
+}
+__device__ inline float fsigmoid(float z) { return __fdividef(1.f, 1.f + __expf(-z)); }
+__device__ inline float flogsigmoid(float x) {
+  return fminf(x, 0.f) - __logf(1.f + __expf(-fabsf(x)));
+}
+
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32->64-bit
 // multiplies with word swaps and key xors; Weyl key schedule.
 __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
@@ -582,9 +594,9 @@ __global__ __launch_bounds__(256) void msample_kernel(MSampleArgs a) {
       const uint32_t wd = (i & 3) == 0 ? pw[0] : (i & 3) == 1 ? pw[1] : (i & 3) == 2 ? pw[2] : pw[3];
       ui = (float)(wd >> 8) * 5.9604644775390625e-08f;
     }
-    const float p = sigmoid<float>(zi);
+    const float p = fsigmoid(zi);
     const float si = ui < p ? 1.f : -1.f;
-    lq += log_sigmoid<float>(si * zi);
+    lq += flogsigmoid(si * zi);
     if (lg == gi) {
 #pragma unroll
       for (int t = 0; t < NPT; ++t)
@@ -602,7 +614,7 @@ __global__ __launch_bounds__(256) void msample_kernel(MSampleArgs a) {
           acc = __builtin_amdgcn_mfma_f32_16x16x4f32(cpa[t][r], sp[t][r], acc, 0, 0, 0);
     float h[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) h[r] = tanhf(acc[r]);
+    for (int r = 0; r < 4; ++r) h[r] = ftanh(acc[r]);
     if (lg == 3) h[3] = si;
 #pragma unroll
     for (int t = 0; t < NPT; ++t)
@@ -654,7 +666,7 @@ __host__ __device__ inline MgLayout mg_layout(int H, int npt) {
   return L;
 }
 
-template <int NPT>
+template <int NPT, int HT>
 __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
   typedef float f4 __attribute__((ext_vector_type(4)));
   extern __shared__ __align__(16) char smem[];
@@ -663,9 +675,10 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
   const int q = a.task_inst[blockIdx.x];
   const MadeInst mi = a.mi[q];
   const int n = mi.n, Hs = mi.H, H = n >= 2 ? mi.H : 0;
-  const int HT = (Hs + 15) / 16;   // tiles cover every stored unit; masks use H
+  // HT tiles of 16 hidden units cover the widest instance of the launch;
+  // units past an instance's H read as zero
   const int64_t bw = a.task_start[blockIdx.x];
-  const MgLayout Lm = mg_layout(Hs, NPT);
+  const MgLayout Lm = mg_layout(16 * HT, NPT);
   float *hid = reinterpret_cast<float *>(smem + Lm.hid);
   float *dab = reinterpret_cast<float *>(smem + Lm.da);
   float *dlb = reinterpret_cast<float *>(smem + Lm.dl);
@@ -692,12 +705,10 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
         sp[t][r] = (valid && pos < n) ? (float)spn[pos] : 0.f;
       }
     const float wt = valid ? (float)((a.f[mi.sample_off + sb] - a.stats[4 * q]) / (double)mi.B) : 0.f;
-    float h[kMgTiles][4];
+    float h[HT][4];
 #pragma unroll
-    for (int ht = 0; ht < kMgTiles; ++ht) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) h[ht][r] = 0.f;
-      if (ht < HT) {
+    for (int ht = 0; ht < HT; ++ht) {
+      {
         f4 acc;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -718,7 +729,7 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
             acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, sp[t][r], acc, 0, 0, 0);
           }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) h[ht][r] = (16 * ht + 4 * lg + r < H) ? tanhf(acc[r]) : 0.f;
+        for (int r = 0; r < 4; ++r) h[ht][r] = (16 * ht + 4 * lg + r < H) ? ftanh(acc[r]) : 0.f;
       }
     }
     float dl[NPT][4];
@@ -732,8 +743,7 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
       }
       const int pa = 16 * pt + ls;
 #pragma unroll
-      for (int ht = 0; ht < kMgTiles; ++ht)
-        if (ht < HT) {
+      for (int ht = 0; ht < HT; ++ht) {
           const f4 wz = ld4(W2 + (int64_t)pa * Hs + 16 * ht + 4 * lg, pa < n && 16 * ht + 4 * lg < H);
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
@@ -756,7 +766,7 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
       for (int r = 0; r < 4; ++r) {
         const int pos = 16 * pt + 4 * lg + r;
         const float s1 = sp[pt][r];
-        dl[pt][r] = pos < n ? wt * ((1.f + s1) * 0.5f - sigmoid<float>(z[r])) : 0.f;
+        dl[pt][r] = pos < n ? wt * ((1.f + s1) * 0.5f - fsigmoid(z[r])) : 0.f;
       }
     }
     const int srow = 16 * wave + ls;
@@ -768,8 +778,7 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
           f4{sp[pt][0], sp[pt][1], sp[pt][2], sp[pt][3]};
     }
 #pragma unroll
-    for (int ht = 0; ht < kMgTiles; ++ht)
-      if (ht < HT) {
+    for (int ht = 0; ht < HT; ++ht) {
         f4 acc = f4{0.f, 0.f, 0.f, 0.f};
         const int ka = 16 * ht + ls;
 #pragma unroll
@@ -884,6 +893,17 @@ __global__ void mgrad_reduce2(const MadeInst *mi, const float *part2, int64_t ps
   grad[m.param_off + p] = (float)acc;
 }
 
+template <int NPT>
+void (*pick_mgrad(int ht))(MGradArgs) {
+  switch (ht) {
+    case 1: return mgrad_kernel<NPT, 1>;
+    case 2: return mgrad_kernel<NPT, 2>;
+    case 4: return mgrad_kernel<NPT, 4>;
+    case 8: return mgrad_kernel<NPT, 8>;
+    default: return mgrad_kernel<NPT, 16>;
+  }
+}
+
 }  // namespace
 
 constexpr size_t kStageMax = 96 * 1024;
@@ -893,15 +913,25 @@ size_t made_param_bytes(int n, int H) { return made_stage_bytes(n, H); }
 int64_t made_pack_floats(int n, int npt, int H) { return mpack_floats(n, npt, H); }
 int64_t made_w2t_offset(int n, int npt) { return msample_floats(n, npt); }
 
-size_t mgrad_lds_bytes(int H, int npt) { return mg_layout(H, npt).end; }
+size_t mgrad_lds_bytes(int H, int npt) {
+  int hpad = 16;
+  while (hpad < H) hpad <<= 1;
+  return mg_layout(hpad, npt).end;
+}
 int mgrad_split() { return kRedSplit; }
 
 hipError_t launch_mgrad(const MGradArgs &a, int npt, hipStream_t st) {
   if (a.n_tasks <= 0) return hipSuccess;
-  size_t lds = 0;
-  for (int q = 0; q < a.n_inst; ++q) lds = std::max(lds, mg_layout(a.hmax, npt).end);
-  void (*k)(MGradArgs) = npt <= 1 ? mgrad_kernel<1> : npt <= 2 ? mgrad_kernel<2> : mgrad_kernel<4>;
-  if (npt > 4) return hipErrorInvalidValue;
+  int hpad = 16;
+  while (hpad < a.hmax) hpad <<= 1;
+  const size_t lds = mg_layout(hpad, npt).end;
+    int ht = 1;
+  while (16 * ht < a.hmax) ht <<= 1;
+  if (npt > 4 || ht > 16) return hipErrorInvalidValue;
+  void (*k)(MGradArgs) = nullptr;
+  if (npt <= 1) k = pick_mgrad<1>(ht);
+  else if (npt <= 2) k = pick_mgrad<2>(ht);
+  else k = pick_mgrad<4>(ht);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
