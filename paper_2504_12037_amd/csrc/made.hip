@@ -469,10 +469,13 @@ __global__ void bump_kernel(int32_t *c, int n) {
 __host__ __device__ inline int64_t msample_floats(int n, int npt) {
   return (int64_t)n * npt * 512 + (int64_t)n * 256 + (int64_t)npt * 256;
 }
-// sampler tables, then W2T [H][n]: W2[pos][k] where deg(k) <= pos, else 0
-// (the transposed masked W2 of the fused backward), padded to 64 floats
+// sampler tables, then the masked matrices of the fused backward:
+//   W2T [H][n]  W2[pos][k] where deg(k) <= pos, else 0 (transposed)
+//   W1m [H][n]  W1[k][j] where j < deg(k), else 0
+//   W2m [n][H]  W2[pos][k] where deg(k) <= pos, else 0
+// (padded to 64 floats)
 __host__ __device__ inline int64_t mpack_floats(int n, int npt, int H) {
-  return msample_floats(n, npt) + ((int64_t)H * n + 63) / 64 * 64;
+  return msample_floats(n, npt) + (3 * (int64_t)H * n + 63) / 64 * 64;
 }
 
 __global__ void made_pack_kernel(const MadeInst *mi, const float *params, float *pack, int npt) {
@@ -482,15 +485,24 @@ __global__ void made_pack_kernel(const MadeInst *mi, const float *params, float 
               *b2 = W2 + (int64_t)n * Hs, *W0 = b2 + n;
   const int64_t sa = (int64_t)n * npt * 256, sb = (int64_t)n * 256;
   const int64_t tsamp = msample_floats(n, npt);
-  const int64_t total = tsamp + (int64_t)Hs * n;
+  const int64_t hn = (int64_t)Hs * n;
+  const int64_t total = tsamp + 3 * hn;
   float *P = pack + m.pack_off;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     float v = 0.f;
     if (idx >= tsamp) {
-      const int64_t e = idx - tsamp;
-      const int k = (int)(e / n), pos = (int)(e % n);
-      if (k < H && 1 + k % (n - 1) <= pos) v = W2[(int64_t)pos * Hs + k];
+      const int64_t e = idx - tsamp, part = e / (hn > 0 ? hn : 1), f = e - part * hn;
+      if (part == 0) {          // W2T
+        const int k = (int)(f / n), pos = (int)(f % n);
+        if (k < H && 1 + k % (n - 1) <= pos) v = W2[(int64_t)pos * Hs + k];
+      } else if (part == 1) {   // W1m
+        const int k = (int)(f / n), j = (int)(f % n);
+        if (k < H && j < 1 + k % (n - 1)) v = W1[f];
+      } else {                  // W2m
+        const int pos = (int)(f / Hs), k = (int)(f % Hs);
+        if (k < H && 1 + k % (n - 1) <= pos) v = W2[f];
+      }
     } else if (idx < 2 * sa) {
       const int64_t e = idx < sa ? idx : idx - sa;
       const int r = (int)(e & 3), lane = (int)((e >> 2) & 63);
@@ -665,6 +677,11 @@ __host__ __device__ inline MgLayout mg_layout(int H, int npt) {
   L.end = L.sf + (size_t)64 * L.ldn * 4;
   return L;
 }
+// bytes: rows plus the degree table (16 * tiles ints)
+__host__ __device__ inline size_t mg_bytes(int H, int npt) {
+  const int ht = (H + 15) / 16 > 0 ? (H + 15) / 16 : 1;
+  return mg_layout(H, npt).end + (size_t)16 * ht * 4;
+}
 
 template <int NPT, int HT>
 __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
@@ -686,6 +703,7 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
   const float *W1 = a.params + mi.param_off, *b1 = W1 + (int64_t)Hs * n, *W2 = b1 + Hs,
               *b2 = W2 + (int64_t)n * Hs, *W0 = b2 + n;
   const float *W2T = a.pack + mi.pack_off + msample_floats(n, NPT);
+  const float *W1m = W2T + (int64_t)Hs * n, *W2m = W1m + (int64_t)Hs * n;
   const int nm1 = n > 1 ? n - 1 : 1;
   // four consecutive parameters p[0..3] (rows are multiples of 4 floats long)
   auto ld4 = [](const float *p, bool ok) {
@@ -715,19 +733,16 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
           const int k = 16 * ht + 4 * lg + r;
           acc[r] = k < H ? b1[k] : 0.f;
         }
-        const int ka = 16 * ht + ls, dga = 1 + ka % nm1;
+        const int ka = 16 * ht + ls;
         f4 wl[NPT];
 #pragma unroll
         for (int t = 0; t < NPT; ++t)
-          wl[t] = ld4(W1 + (int64_t)ka * n + 16 * t + 4 * lg, ka < H && 16 * t + 4 * lg < n);
+          wl[t] = ld4(W1m + (int64_t)ka * n + 16 * t + 4 * lg, ka < H && 16 * t + 4 * lg < n);
 #pragma unroll
         for (int t = 0; t < NPT; ++t)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int j = 16 * t + 4 * lg + r;
-            const float wv = j < dga ? wl[t][r] : 0.f;
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, sp[t][r], acc, 0, 0, 0);
-          }
+          for (int r = 0; r < 4; ++r)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wl[t][r], sp[t][r], acc, 0, 0, 0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) h[ht][r] = (16 * ht + 4 * lg + r < H) ? ftanh(acc[r]) : 0.f;
       }
@@ -744,13 +759,10 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
       const int pa = 16 * pt + ls;
 #pragma unroll
       for (int ht = 0; ht < HT; ++ht) {
-          const f4 wz = ld4(W2 + (int64_t)pa * Hs + 16 * ht + 4 * lg, pa < n && 16 * ht + 4 * lg < H);
+          const f4 wz = ld4(W2m + (int64_t)pa * Hs + 16 * ht + 4 * lg, pa < n && 16 * ht + 4 * lg < H);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int k = 16 * ht + 4 * lg + r;
-            const float wv = 1 + k % nm1 <= pa ? wz[r] : 0.f;
-            z = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, h[ht][r], z, 0, 0, 0);
-          }
+          for (int r = 0; r < 4; ++r)
+            z = __builtin_amdgcn_mfma_f32_16x16x4f32(wz[r], h[ht][r], z, 0, 0, 0);
         }
 #pragma unroll
       for (int t = 0; t < NPT; ++t) {
@@ -796,6 +808,9 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
         *reinterpret_cast<f4 *>(dab + srow * Lm.ldh + 16 * ht + 4 * lg) = dv;
       }
   }
+  // hidden-unit degrees for the output masks
+  int32_t *deg = reinterpret_cast<int32_t *>(smem + Lm.end);
+  for (int k = threadIdx.x; k < 16 * HT; k += blockDim.x) deg[k] = k < H ? 1 + k % nm1 : 1 << 30;
   __syncthreads();
   // gradient tiles: [0, NPT*HT) gW2 (pt, ht); then NPT*NPT gW0 (pt, jt);
   // then HT*NPT gW1 (ht, jt); wave w takes tiles w, w + 4, ...
@@ -837,12 +852,12 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
       const int row = ai + 4 * lg + r, col = bj + ls;
       if (kind == 2) {         // gW2[pos][k]: deg(k) <= pos
         if (row < n && col < Hs)
-          prow[o_W2 + (int64_t)row * Hs + col] = (col < H && 1 + col % nm1 <= row) ? acc[r] : 0.f;
+          prow[o_W2 + (int64_t)row * Hs + col] = deg[col] <= row ? acc[r] : 0.f;
       } else if (kind == 0) {  // gW0[pos][j]: j < pos
         if (row < n && col < n) prow[o_W0 + (int64_t)row * n + col] = col < row ? acc[r] : 0.f;
       } else {                 // gW1[k][j]: j < deg(k)
         if (row < Hs && col < n)
-          prow[(int64_t)row * n + col] = (row < H && col < 1 + row % nm1) ? acc[r] : 0.f;
+          prow[(int64_t)row * n + col] = col < deg[row] ? acc[r] : 0.f;
       }
     }
   }
@@ -916,7 +931,7 @@ int64_t made_w2t_offset(int n, int npt) { return msample_floats(n, npt); }
 size_t mgrad_lds_bytes(int H, int npt) {
   int hpad = 16;
   while (hpad < H) hpad <<= 1;
-  return mg_layout(hpad, npt).end;
+  return mg_bytes(hpad, npt);
 }
 int mgrad_split() { return kRedSplit; }
 
@@ -924,7 +939,7 @@ hipError_t launch_mgrad(const MGradArgs &a, int npt, hipStream_t st) {
   if (a.n_tasks <= 0) return hipSuccess;
   int hpad = 16;
   while (hpad < a.hmax) hpad <<= 1;
-  const size_t lds = mg_layout(hpad, npt).end;
+  const size_t lds = mg_bytes(hpad, npt);
     int ht = 1;
   while (16 * ht < a.hmax) ht <<= 1;
   if (npt > 4 || ht > 16) return hipErrorInvalidValue;
