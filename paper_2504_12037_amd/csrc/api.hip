@@ -125,7 +125,7 @@ struct tnvan_net {
   ChainLim lim_fwd{}, lim_bwd{};
   DBuf Tl, Tbl, cedges, ckpt;
   // register-resident chain kernels (per-wave tasks)
-  DBuf Tr, Tq, Trb, xcol, cf_w, cf_r, cf_J;
+  DBuf Tr, Tq, Trb, xcol, cf_w, cf_r, cf_J, Tsx;
   DBuf Ubuf, fabp, u_off, f_off;
   // training step replayed from a captured graph (TNVAN_FLAG_GRAPH)
   bool use_graph = false, capturing = false;
@@ -425,6 +425,7 @@ ChainArgs chain_args(tnvan_net *net, bool bwd) {
   a.Tq = net->Tq.as<float>();
   a.Trb = net->Trb.as<uint16_t>();
   a.xcol = net->xcol.as<int32_t>();
+  a.Tsx = net->Tsx.as<float>();
   a.cf_w = net->cf_w.as<int32_t>();
   a.cf_r = net->cf_r.as<int32_t>();
   a.cf_J = net->cf_J.as<float>();
@@ -921,7 +922,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   }
   UP2(Tl, P.Tl) UP2(Tbl, P.Tbl) UP2(cedges, P.cedges)
   UP2(Tr, P.Tr) UP2(Tq, P.Tq) UP2(Trb, P.Trb) UP2(xcol, P.xcol)
-  UP2(cf_w, P.cf_w) UP2(cf_r, P.cf_r) UP2(cf_J, P.cf_J)
+  UP2(cf_w, P.cf_w) UP2(cf_r, P.cf_r) UP2(cf_J, P.cf_J) UP2(Tsx, P.Tsx)
   // transfer-matrix form: instances whose program is a set of dense chains
   // (FP32 / BF16 only); the launch-wide maxima size the LDS layout
   net->use_chain.assign(n_inst, 0);
@@ -1015,7 +1016,7 @@ void tnvan_free_network(tnvan_net *net) {
                  &net->hR32, &net->task_inst, &net->task_chain, &net->task_start,
                  &net->btask_inst, &net->btask_chain, &net->btask_start, &net->Tl, &net->Tbl,
                  &net->cedges, &net->ckpt, &net->Tr, &net->Tq, &net->Trb, &net->xcol,
-                 &net->cf_w, &net->cf_r, &net->cf_J, &net->Ubuf, &net->fabp, &net->u_off,
+                 &net->cf_w, &net->cf_r, &net->cf_J, &net->Tsx, &net->Ubuf, &net->fabp, &net->u_off,
                  &net->f_off,
                  &net->mpack, &net->mtask_inst, &net->mtask_start, &net->mg_task_inst,
                  &net->mg_task_start, &net->mg_first, &net->mg_count, &net->w_part2,

@@ -417,6 +417,10 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
   f4 ckn[CT];   // checkpoint of the next segment, loaded one segment ahead
 #pragma unroll
   for (int i = 0; i < CT; ++i) ckn[i] = ck[((NC - 1) * kRegBwdTiles + i) * 64];
+  // the Lambda operands of the next step walked, loaded one step ahead
+  ChainStep sn = cs[T - 1];
+  f4 tqn[CT][CT];
+  load_t<CT>(a.Tq + sn.tq_off, lane, tqn);
   for (int seg = NC - 1; seg >= 0; --seg) {
     const int t0 = seg * KS;
     float As[KS][CT][4];
@@ -445,11 +449,30 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
     for (int u = KS - 1; u >= 0; --u) {
       const int t = t0 + u;
       if (t < T) {
-        const ChainStep st = cs[t];
+        const ChainStep st = sn;
         const int g = st.g, w = st.w;
-        f4 tq[CT][CT], tr[CT][CT];
-        load_t<CT>(a.Tq + st.tq_off, lane, tq);
+        f4 tq[CT][CT];
+#pragma unroll
+        for (int i = 0; i < CT; ++i)
+#pragma unroll
+          for (int j = 0; j < CT; ++j) tq[i][j] = tqn[i][j];
+        // operands used later in this step, issued now
+        f4 tr[CT][CT], sx[CT], so[CT];
         load_t<CT>(a.Tr + st.tr_off, lane, tr);
+        {
+          const f4 *sxo = reinterpret_cast<const f4 *>(a.Tsx + st.sx_off) + lane;
+#pragma unroll
+          for (int i = 0; i < CT; ++i) {
+            sx[i] = sxo[i * 64];
+            so[i] = sxo[(CT + i) * 64];
+          }
+        }
+        float uu[GR];
+        load_phi<GR>(a, tk.q, tk.Bq, st.gpos, g, bme, uu);
+        const EdgeDesc myed = lane < st.n_edge ? ce[st.ce_off + lane] : EdgeDesc{0, 0, 0, 0};
+        // the next step's descriptor and Lambda operands
+        sn = cs[t > 0 ? t - 1 : 0];
+        load_t<CT>(a.Tq + sn.tq_off, lane, tqn);
         // Lambda = T R (R-layout over the group states)
         f4 lam[CT];
 #pragma unroll
@@ -463,30 +486,23 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
               lam[xt] = __builtin_amdgcn_mfma_f32_16x16x4f32(tq[xt][ot][r], R[ot][r], lam[xt], 0, 0, 0);
         // W-R correlations: per-sample magnetisation of a group spin times the
         // neighbouring width-set spin, weighted and summed over the samples
-        for (int j = 0; j < g; ++j) {
-          typedef int i4v __attribute__((ext_vector_type(4)));
-          const int64_t pos = D.hr_off + st.gpos + j;
-          const i4v wr = *reinterpret_cast<const i4v *>(a.cf_r + 4 * pos);
-          if (wr[0] < 0) continue;
-          const i4v wi = *reinterpret_cast<const i4v *>(a.cf_w + 4 * pos);
-          float m = 0.f;
 #pragma unroll
-          for (int xt = 0; xt < CT; ++xt)
+        for (int k = 0; k < 4; ++k)
+          if (k < st.n_wri) {
+            const int j = st.wri[k] & 0xff, wi = st.wri[k] >> 8;
+            float m = 0.f;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) m += sgn(16 * xt + 4 * lg + r, j) * As[u][xt][r] * lam[xt][r];
-          m = xlane_sum(m) * gs;
+            for (int xt = 0; xt < CT; ++xt)
 #pragma unroll
-          for (int k = 0; k < 4; ++k)
-            if (wr[k] >= 0) {
-              const float v = row16_sum(m * sp.sigma(wi[k]));
-              if (lane == 0) prow[D.nr + wr[k]] = v;
-            }
-        }
+              for (int r = 0; r < 4; ++r) m += sgn(16 * xt + 4 * lg + r, j) * As[u][xt][r] * lam[xt][r];
+            m = xlane_sum(m) * gs;
+            const float v = row16_sum(m * sp.sigma(wi));
+            if (lane == 0) prow[D.nr + st.wre[k]] = v;
+          }
         // R of the previous step (unused after the first step)
         float Rn[CT][4];
         {
-          float uu[GR], d[CT][4];
-          load_phi<GR>(a, tk.q, tk.Bq, st.gpos, g, bme, uu);
+          float d[CT][4];
           diag_from_phi<CT, GR>(uu, g, lg, d);
           const float sc = pow2neg(ex[(t > 0 ? t - 1 : 0) * CW + ls]);
 #pragma unroll
@@ -504,49 +520,41 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
           *reinterpret_cast<f4 *>(rs + ls * LDT + 16 * ot + 4 * lg) =
               f4{R[ot][0], R[ot][1], R[ot][2], R[ot][3]};
         wsync();
-        f4 hg[CT][CT];
-#pragma unroll
-        for (int xt = 0; xt < CT; ++xt)
-#pragma unroll
-          for (int ot = 0; ot < CT; ++ot) {
-            hg[xt][ot] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kc = 0; kc < 4; ++kc)
-              hg[xt][ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                  ga[(4 * kc + lg) * LDT + 16 * xt + ls], rs[(4 * kc + lg) * LDT + 16 * ot + ls],
-                  hg[xt][ot], 0, 0, 0);
-          }
-        wsync();
-        // G = H o T, then Q'^T = G^T S_x and Q = S_o^T Q'^T
-        const int code = a.xcol[st.xc_off + ls];
-        const int cu = code & 0xff, cv = (code >> 8) & 0xff;
+        // per output tile: H (samples contracted), G = H o T, Q'^T = G^T S_x
         f4 qt[CT];
 #pragma unroll
         for (int ot = 0; ot < CT; ++ot) {
+          f4 hg[CT];
+#pragma unroll
+          for (int xt = 0; xt < CT; ++xt) {
+            hg[xt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc)
+              hg[xt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                  ga[(4 * kc + lg) * LDT + 16 * xt + ls], rs[(4 * kc + lg) * LDT + 16 * ot + ls],
+                  hg[xt], 0, 0, 0);
+          }
           qt[ot] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int xt = 0; xt < CT; ++xt)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int xs = 16 * xt + 4 * lg + r;
-              const float sx = code < 0 ? 0.f : ((((xs >> cu) ^ (xs >> cv)) & 1) ? -1.f : 1.f);
-              qt[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(hg[xt][ot][r] * tr[ot][xt][r], sx,
+            for (int r = 0; r < 4; ++r)
+              qt[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(hg[xt][r] * tr[ot][xt][r], sx[xt][r],
                                                             qt[ot], 0, 0, 0);
-            }
         }
+        wsync();
+        // Q = S_o^T Q'^T (operand tables)
         f4 qq = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int ot = 0; ot < CT; ++ot)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int o = 16 * ot + 4 * lg + r;
-            const float so = ls < w ? sgn(o, ls) : (ls == w ? 1.f : 0.f);
-            qq = __builtin_amdgcn_mfma_f32_16x16x4f32(so, qt[ot][r], qq, 0, 0, 0);
-          }
+          for (int r = 0; r < 4; ++r)
+            qq = __builtin_amdgcn_mfma_f32_16x16x4f32(so[ot][r], qt[ot][r], qq, 0, 0, 0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) qs[ls * 17 + 4 * lg + r] = qq[r];
         wsync();
-        for (int k = lane; k < st.n_edge; k += 64) {
+        if (lane < st.n_edge) prow[D.nr + D.n_wr + myed.rr] = qs[(myed.pad >> 4) * 17 + (myed.pad & 15)];
+        for (int k = lane + 64; k < st.n_edge; k += 64) {
           const EdgeDesc ed = ce[st.ce_off + k];
           prow[D.nr + D.n_wr + ed.rr] = qs[(ed.pad >> 4) * 17 + (ed.pad & 15)];
         }

@@ -229,6 +229,40 @@ void build_chains(const InstDesc &D, const std::vector<int32_t> &consumer, HostP
       }
       if (sd.w >= 16) ok_rq = false;
       for (int c = 0; c < 16; ++c) P.xcol.push_back(xc[c]);
+      // S_x operand of lane l: column l & 15 at state x = 16 xt + 4 (l >> 4) + r;
+      // S_o operand: row j = l & 15 (output spin j < w, all-ones j = w) at
+      // output state o = 16 ot + 4 (l >> 4) + r
+      // W-R couplings of the group, in the step descriptor
+      cs.n_wri = 0;
+      for (int j = 0; j < sd.g; ++j) {
+        const int pos = sd.gpos + j;
+        for (int k = P.fld_ptr[D.fld_off + pos]; k < P.fld_ptr[D.fld_off + pos + 1]; ++k) {
+          if (cs.n_wri >= 4) { ok_rq = false; break; }
+          cs.wri[cs.n_wri] = j | (P.fld_w[D.fld_nnz_off + k] << 8);
+          cs.wre[cs.n_wri] = P.fld_wr[D.fld_nnz_off + k];
+          ++cs.n_wri;
+        }
+      }
+      cs.sx_off = (int64_t)P.Tsx.size();
+      auto par = [](int v) { return __builtin_popcount((unsigned)v) & 1; };
+      for (int xt = 0; xt < CT; ++xt)
+        for (int l = 0; l < 64; ++l)
+          for (int r = 0; r < 4; ++r) {
+            const int code = xc[l & 15], x = 16 * xt + 4 * (l >> 4) + r;
+            float v = 0.f;
+            if (code >= 0) {
+              const int cu = code & 0xff, cv = (code >> 8) & 0xff;
+              const int m = (1 << cu) | (cv < 31 ? (1 << cv) : 0);
+              v = par(x & m) ? -1.f : 1.f;
+            }
+            P.Tsx.push_back(v);
+          }
+      for (int ot = 0; ot < CT; ++ot)
+        for (int l = 0; l < 64; ++l)
+          for (int r = 0; r < 4; ++r) {
+            const int j = l & 15, o = 16 * ot + 4 * (l >> 4) + r;
+            P.Tsx.push_back(j < sd.w ? (((o >> j) & 1) ? -1.f : 1.f) : (j == sd.w ? 1.f : 0.f));
+          }
       P.csteps.push_back(cs);
     }
     cd.tl_size = (int32_t)(P.Tl.size() - cd.tl_src);

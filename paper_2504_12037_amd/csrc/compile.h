@@ -44,6 +44,7 @@ struct HostProgram {
   std::vector<float> Tr, Tq;        // register-resident operand tables
   std::vector<uint16_t> Trb;
   std::vector<int32_t> xcol;        // 16 adjoint column codes per chain step
+  std::vector<float> Tsx;           // per chain step: S_x and S_o operand tables
   std::vector<int32_t> cf_w, cf_r;  // 4 W-neighbour slots per R position (index, W-R edge)
   std::vector<float> cf_J;          // their couplings
 };

@@ -242,6 +242,7 @@ struct ChainArgs {
   const float *Tr, *Tq;
   const uint16_t *Trb;
   const int32_t *xcol;
+  const float *Tsx;                 // adjoint S_x / S_o operand tables
   int32_t sg;                       // 16-sample groups per wave (forward)
   int32_t task_base;                // first task of the launch
   // dense W-neighbour slots of every R position (index hr_off + position)
@@ -268,7 +269,7 @@ hipError_t launch_chain(const ChainArgs &a, bool bwd, hipStream_t st);
 // Forward: steps of at most 4 tiles (K, N <= 64); adjoint: at most 2 tiles.
 constexpr int kRegFwdTiles = 4;
 constexpr int kRegBwdTiles = 2;
-constexpr int kRegSeg = 4;            // adjoint checkpoint interval
+constexpr int kRegSeg = 2;            // adjoint checkpoint interval
 size_t rchain_wave_lds(const ChainLim &L, bool bwd, int sg);
 int64_t rchain_ckpt_floats(const ChainLim &L);   // per adjoint task
 hipError_t launch_rchain(const ChainArgs &a, bool bwd, hipStream_t st);

@@ -116,6 +116,13 @@ struct ChainStep {
   int64_t trb_off;    // BF16 [nt][c][lane][8]: T[16(2c + i/4) + 4(lane>>4) + i%4][16nt + (lane&15)]
   int32_t nt16;       // output tiles of 16 (1 for the closing step)
   int32_t xc_off;     // 16 column codes of the adjoint's spin-product matrix
+  int64_t sx_off;     // FP32 [xt][lane][4] S_x operands, then [ot][lane][4] S_o operands
+  // W-R couplings of the group (at most 4): group spin j and W index in
+  // wri = j | (w << 8), the W-R edge in wre
+  int32_t n_wri;
+  int32_t wri[4];
+  int32_t wre[4];
+  int32_t pad2;
 };
 
 // Register-resident layout ("R-layout") of a per-sample vector over 16*KT
