@@ -231,6 +231,22 @@ __device__ inline int rescale_next(const f4 (&acc)[CT], const float (&d)[CT][4],
   return e;
 }
 
+// the wave-uniform step descriptor t (scalar loads, not vector loads whose
+// wait would also wait for every operand load issued before it)
+// (the descriptors are never written on the device, so they are read
+// through the constant address space, which the compiler loads with scalar
+// instructions even where the kernel stores to global memory)
+typedef const __attribute__((address_space(4))) int32_t *const_i32_ptr;
+__device__ inline ChainStep step_at(const ChainStep *cs, int t) {
+  static_assert(sizeof(ChainStep) % 4 == 0, "descriptor of whole words");
+  const_i32_ptr src = (const_i32_ptr)(cs + __builtin_amdgcn_readfirstlane(t));
+  ChainStep r;
+  int32_t *dst = reinterpret_cast<int32_t *>(&r);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(ChainStep) / 4); ++i) dst[i] = src[i];
+  return r;
+}
+
 struct Task {
   int q, c;
   int64_t b0, Bq;
@@ -276,7 +292,7 @@ __device__ inline void fwd_chain(const ChainArgs &a, const Task &tk, const Chain
   else load_t<CT>(a.Tr + cs[0].tr_off, lane, tc);
   for (int t = 0;; ++t) {
     const bool last = t == T - 1;
-    const ChainStep nx = cs[last ? t : t + 1];
+    const ChainStep nx = step_at(cs, last ? t : t + 1);
     // next step's tables and unary factors (the closing step reloads its own)
     f4 tn[CT][CT];
     u4v bn[CT][NC2];
@@ -383,7 +399,7 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
           ck[((t / KS) * kRegBwdTiles + i) * 64] = f4{x[i][0], x[i][1], x[i][2], x[i][3]};
       }
       const bool last = t == T - 1;
-      const ChainStep nx = cs[last ? t : t + 1];
+      const ChainStep nx = step_at(cs, last ? t : t + 1);
       f4 tn[CT][CT];
       load_t<CT>(a.Tr + nx.tr_off, lane, tn);
       float u[GR], d[CT][4];
@@ -418,7 +434,7 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
 #pragma unroll
   for (int i = 0; i < CT; ++i) ckn[i] = ck[((NC - 1) * kRegBwdTiles + i) * 64];
   // the Lambda operands of the next step walked, loaded one step ahead
-  ChainStep sn = cs[T - 1];
+  ChainStep sn = step_at(cs, T - 1);
   f4 tqn[CT][CT];
   load_t<CT>(a.Tq + sn.tq_off, lane, tqn);
   for (int seg = NC - 1; seg >= 0; --seg) {
@@ -434,7 +450,7 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
 #pragma unroll
     for (int u = 1; u < KS; ++u) {
       const int tp = t0 + u - 1 < T - 1 ? t0 + u - 1 : T - 1;
-      const ChainStep st = cs[tp], nx = cs[tp + 1 < T ? tp + 1 : tp];
+      const ChainStep st = step_at(cs, tp), nx = step_at(cs, tp + 1 < T ? tp + 1 : tp);
       f4 tc[CT][CT];
       load_t<CT>(a.Tr + st.tr_off, lane, tc);
       float uu[GR], d[CT][4];
@@ -471,7 +487,7 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
         load_phi<GR>(a, tk.q, tk.Bq, st.gpos, g, bme, uu);
         const EdgeDesc myed = lane < st.n_edge ? ce[st.ce_off + lane] : EdgeDesc{0, 0, 0, 0};
         // the next step's descriptor and Lambda operands
-        sn = cs[t > 0 ? t - 1 : 0];
+        sn = step_at(cs, t > 0 ? t - 1 : 0);
         load_t<CT>(a.Tq + sn.tq_off, lane, tqn);
         // Lambda = T R (R-layout over the group states)
         f4 lam[CT];
