@@ -126,7 +126,8 @@ struct tnvan_net {
   DBuf Tl, Tbl, cedges, ckpt;
   // register-resident chain kernels (per-wave tasks)
   DBuf Tr, Tq, Trb, xcol, cf_w, cf_r, cf_J, Tsx;
-  DBuf Ubuf, fabp, u_off, f_off;
+  DBuf Ubuf, fabp, u_off, f_off, vjp_part, tickets, inv_v, inv_e, pcoef, vjp_bpart;
+  int max_out = 1;
   // training step replayed from a captured graph (TNVAN_FLAG_GRAPH)
   bool use_graph = false, capturing = false;
   hipStream_t cap_stream = nullptr;
@@ -551,10 +552,6 @@ tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *gra
       HIPCHK(launch_chain(c, true, st));
     }
   }
-  int64_t nh = 0, ne = 0;
-  for (auto &D : net->P.insts) { nh += D.n; ne += D.n_edges; }
-  HIPCHK(zero_doubles(dh, nh, st));
-  HIPCHK(zero_doubles(dJ, ne, st));
   VjpArgs v{};
   v.inst = net->inst.as<InstDesc>();
   v.rr_edge = net->rr_edge.as<int32_t>();
@@ -574,6 +571,17 @@ tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *gra
   v.inst_sum_off = net->d_sum_off.as<int64_t>();
   HIPCHK(net->sumP.ensure(std::max<int64_t>(1, net->sum_total) * sizeof(double)));
   v.sumP = net->sumP.as<double>();
+  HIPCHK(net->vjp_part.ensure((size_t)std::max(1, net->n_inst * vjp_split() * net->max_partial) *
+                              sizeof(double)));
+  v.part2 = net->vjp_part.as<double>();
+  v.maxp = net->max_partial;
+  v.max_out = net->max_out;
+  v.inv_v = net->inv_v.as<int32_t>();
+  v.inv_e = net->inv_e.as<int32_t>();
+  v.pcoef = net->pcoef.as<double>();
+  HIPCHK(net->vjp_bpart.ensure((size_t)net->n_inst * vjp_finish_blocks(net->max_out) * sizeof(double)));
+  v.bpart = net->vjp_bpart.as<double>();
+  v.done = net->tickets.as<int32_t>() + 2 * net->n_inst;
   HIPCHK(launch_vjp_reduce<real>(v, net->partial.as<real>(), net->n_inst, net->max_partial, st));
   return TNVAN_OK;
 }
@@ -701,6 +709,7 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
   HIPCHK(net->w_fpart.ensure((size_t)net->n_inst * f.nblk * 4 * sizeof(double)));
   f.part = net->w_fpart.as<double>();
   f.stats = stats;
+  f.done = net->tickets.as<int32_t>();
   HIPCHK(launch_free<real>(f, net->n_inst, st));
   if (net->mgrad && sizeof(real) == 4) {
     // fused REINFORCE backward of every instance (Eq. 10)
@@ -731,17 +740,11 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     }
     HIPCHK(launch_mgrad_reduce(g, st));
   }
-  for (int q = 0; q < net->n_inst; ++q) {
+  const bool fused = net->mgrad && sizeof(real) == 4;
+  for (int q = 0; q < net->n_inst && !fused; ++q) {
     const MadeInst &m = net->mi[q];
     if (m.B <= 0) continue;
     float *g = net->grad.as<float>() + m.param_off;
-    if (net->mgrad && sizeof(real) == 4) {
-      HIPCHK(launch_adam(net->params.as<float>() + m.param_off, g,
-                         net->adam_m.as<float>() + m.param_off,
-                         net->adam_v.as<float>() + m.param_off, net->param_count[q], lr,
-                         net->step_ctr.as<int32_t>() + q, st));
-      continue;
-    }
     // REINFORCE backward through q (Eq. 10): per-sample rows, then batch sums
     const int n = m.n, H = m.H;
     HIPCHK(net->w_hid.ensure(std::max<int64_t>(1, m.B * H) * sizeof(real)));
@@ -773,12 +776,23 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     }
     HIPCHK(launch_atb<real>(r.dlogit, n, r.sf, n, m.B, n, n, part, ks, gW0, n, 2, n, st));
     HIPCHK(launch_colsum<real>(r.dlogit, n, m.B, n, part, ks, gb2, st));
-    HIPCHK(launch_adam(net->params.as<float>() + m.param_off, g,
-                       net->adam_m.as<float>() + m.param_off,
-                       net->adam_v.as<float>() + m.param_off, net->param_count[q], lr,
-                       net->step_ctr.as<int32_t>() + q, st));
   }
-  HIPCHK(launch_bump(net->step_ctr.as<int32_t>(), net->n_inst, st));
+  // Adam on every instance and the step counters, one launch
+  OptArgs o{};
+  o.mi = net->d_mi.as<MadeInst>();
+  o.params = net->params.as<float>();
+  o.grad = net->grad.as<float>();
+  o.m = net->adam_m.as<float>();
+  o.v = net->adam_v.as<float>();
+  o.part2 = fused ? net->w_part2.as<float>() : nullptr;
+  o.pstride = net->mg_pstride;
+  o.nsplit = mgrad_split();
+  o.lr = lr;
+  o.step_ctr = net->step_ctr.as<int32_t>();
+  o.done = net->tickets.as<int32_t>() + net->n_inst;
+  int64_t max_pc = 1;
+  for (auto pc : net->param_count) max_pc = std::max(max_pc, pc);
+  HIPCHK(launch_adam_step(o, net->n_inst, max_pc, st));
   return TNVAN_OK;
 }
 
@@ -915,6 +929,11 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
       (e = hipMemset(net->adam_v.p, 0, pb)) || (e = hipMemset(net->grad.p, 0, pb)) ||
       (e = hipMemset(net->step_ctr.p, 0, sizeof(int32_t) * n_inst)))
     return fail(e, "parameter init");
+  // completion tickets of the last-block reductions (free energy, optimiser,
+  // adjoint): zero between launches, each launch resets what it used
+  if ((e = net->tickets.ensure(sizeof(int32_t) * 3 * n_inst)) ||
+      (e = hipMemset(net->tickets.p, 0, sizeof(int32_t) * 3 * n_inst)))
+    return fail(e, "tickets");
   {
     std::vector<float> fj(P.fld_J.begin(), P.fld_J.end()), hr(P.hR.begin(), P.hR.end());
     UP2(fld_J32, fj) UP2(hR32, hr) UP2(fld_wr, P.fld_wr) UP2(cinst, P.cinst)
@@ -922,6 +941,8 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   }
   UP2(Tl, P.Tl) UP2(Tbl, P.Tbl) UP2(cedges, P.cedges)
   UP2(Tr, P.Tr) UP2(Tq, P.Tq) UP2(Trb, P.Trb) UP2(xcol, P.xcol)
+  UP2(inv_v, P.inv_v) UP2(inv_e, P.inv_e) UP2(pcoef, P.pcoef)
+  for (auto &D : P.insts) net->max_out = std::max(net->max_out, (int)(D.n + D.n_edges));
   UP2(cf_w, P.cf_w) UP2(cf_r, P.cf_r) UP2(cf_J, P.cf_J) UP2(Tsx, P.Tsx)
   // transfer-matrix form: instances whose program is a set of dense chains
   // (FP32 / BF16 only); the launch-wide maxima size the LDS layout
@@ -1016,7 +1037,8 @@ void tnvan_free_network(tnvan_net *net) {
                  &net->hR32, &net->task_inst, &net->task_chain, &net->task_start,
                  &net->btask_inst, &net->btask_chain, &net->btask_start, &net->Tl, &net->Tbl,
                  &net->cedges, &net->ckpt, &net->Tr, &net->Tq, &net->Trb, &net->xcol,
-                 &net->cf_w, &net->cf_r, &net->cf_J, &net->Tsx, &net->Ubuf, &net->fabp, &net->u_off,
+                 &net->cf_w, &net->cf_r, &net->cf_J, &net->Tsx, &net->Ubuf, &net->vjp_part,
+                 &net->tickets, &net->inv_v, &net->inv_e, &net->pcoef, &net->vjp_bpart, &net->fabp, &net->u_off,
                  &net->f_off,
                  &net->mpack, &net->mtask_inst, &net->mtask_start, &net->mg_task_inst,
                  &net->mg_task_start, &net->mg_first, &net->mg_count, &net->w_part2,

@@ -669,10 +669,14 @@ __global__ void chain_sum_kernel(const InstDesc *inst, const ChainInst *cinst,
 
 // One thread per (sample, run of kUnaryChunk positions); grid.z picks the
 // instance.  The field on R position p of sample s_W is h_p plus the W-R
-// couplings times the neighbouring width-set spins (Sec. 2).
+// couplings times the neighbouring width-set spins (Sec. 2).  Positions
+// with at most four W-neighbours read the dense slots (all loads of a
+// position at once); others walk the neighbour list.
 __global__ __launch_bounds__(256) void unary_kernel(ChainArgs a, const int32_t *cis,
                                                     const int64_t *f_off, float *U,
                                                     double *fabp) {
+  typedef const __attribute__((address_space(4))) int32_t *ci32;
+  typedef const __attribute__((address_space(4))) float *cf32;
   const int q = cis[blockIdx.z];
   const InstDesc D = a.inst[q];
   const int64_t B = a.inst_B[q];
@@ -683,11 +687,22 @@ __global__ __launch_bounds__(256) void unary_kernel(ChainArgs a, const int32_t *
   const int8_t *s = a.spins + a.inst_spin_off[q] + b * D.nw;
   const float beta = (float)D.beta;
   float *Uq = U + a.u_off[q];
+  const ci32 fptr = (ci32)(a.fld_ptr + D.fld_off);
+  const ci32 cw = (ci32)(a.cf_w + 4 * (int64_t)D.hr_off), cr = (ci32)(a.cf_r + 4 * (int64_t)D.hr_off);
+  const cf32 cj = (cf32)(a.cf_J + 4 * (int64_t)D.hr_off), hr = (cf32)(a.hR + D.hr_off);
   double fab = 0.0;
   for (int p = p0; p < p1; ++p) {
-    float f = a.hR[D.hr_off + p];
-    const int k0 = a.fld_ptr[D.fld_off + p], k1 = a.fld_ptr[D.fld_off + p + 1];
-    for (int k = k0; k < k1; ++k) f += a.fld_J[D.fld_nnz_off + k] * (float)s[a.fld_w[D.fld_nnz_off + k]];
+    float f = hr[p];
+    const int nn = fptr[p + 1] - fptr[p];
+    if (nn <= 4) {
+      float t[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) t[k] = cr[4 * p + k] >= 0 ? cj[4 * p + k] * (float)s[cw[4 * p + k]] : 0.f;
+      f += (t[0] + t[1]) + (t[2] + t[3]);
+    } else {
+      for (int k = fptr[p]; k < fptr[p + 1]; ++k)
+        f += a.fld_J[D.fld_nnz_off + k] * (float)s[a.fld_w[D.fld_nnz_off + k]];
+    }
     const float af = beta * fabsf(f);
     const float sm = __expf(-2.f * af);
     Uq[(int64_t)p * B + b] = f >= 0.f ? sm : -sm;

@@ -537,6 +537,17 @@ tnvan_status compile_instance(const tnvan_instance &in, int max_width,
     D.arena_fwd = ar.top;
   }
   build_chains(D, consumer, P);
+  {
+    const size_t v0 = P.inv_v.size(), e0 = P.inv_e.size();
+    P.inv_v.resize(v0 + n, -1);
+    P.inv_e.resize(e0 + in.n_edges, -1);
+    for (int k = 0; k < nr; ++k) P.inv_v[v0 + P.vr[D.vr_off + k]] = k;
+    for (int j = 0; j < D.n_wr; ++j) P.inv_e[e0 + P.wr_edge[D.wr_off + j]] = nr + j;
+    for (int j = 0; j < D.n_rr; ++j) P.inv_e[e0 + P.rr_edge[D.rr_off + j]] = nr + D.n_wr + j;
+    for (int k = 0; k < nr; ++k) P.pcoef.push_back(P.hR[D.hr_off + k]);
+    for (int j = 0; j < D.n_wr; ++j) P.pcoef.push_back(P.wr_J[D.wr_off + j]);
+    for (int j = 0; j < D.n_rr; ++j) P.pcoef.push_back(P.rr_J[D.rr_off + j]);
+  }
   P.insts.push_back(D);
   P.hidden.push_back(in.hidden);
   P.flops_fwd.push_back(flops);

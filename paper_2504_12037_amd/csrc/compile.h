@@ -45,6 +45,10 @@ struct HostProgram {
   std::vector<uint16_t> Trb;
   std::vector<int32_t> xcol;        // 16 adjoint column codes per chain step
   std::vector<float> Tsx;           // per chain step: S_x and S_o operand tables
+  // adjoint output maps: vertex -> R position (-1 on W), edge -> partial
+  // column (-1 on W-W edges), and the dbeta coefficient of every column
+  std::vector<int32_t> inv_v, inv_e;
+  std::vector<double> pcoef;
   std::vector<int32_t> cf_w, cf_r;  // 4 W-neighbour slots per R position (index, W-R edge)
   std::vector<float> cf_J;          // their couplings
 };

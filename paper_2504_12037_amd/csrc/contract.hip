@@ -445,25 +445,85 @@ __global__ __launch_bounds__(kThreads) void contract_kernel(ContractArgs<real> a
 
 // Column sums of the per-tile partial rows of every instance (rows in a
 // fixed order, FP64): 16 columns x 16 row groups per block.
+// Column sums of the partial rows in two passes with a fixed order: block
+// (column group, row split, instance) sums its rows for 64 columns (four
+// row lanes, then through LDS), then one thread per column adds the splits.
+constexpr int kColSplit = 32;
 template <typename real>
 __global__ __launch_bounds__(256) void vjp_colsum_kernel(VjpArgs a, const real *partial) {
-  __shared__ double sh[16][17];
-  const int q = blockIdx.y;
+  __shared__ double sh[4][64];
+  const int q = blockIdx.z, sp = blockIdx.y;
   const InstDesc D = a.inst[q];
-  const int c = threadIdx.x & 15, rg = threadIdx.x >> 4;
-  const int k = blockIdx.x * 16 + c;
+  const int c = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  const int k = blockIdx.x * 64 + c;
   const int nt = a.inst_n_tiles[q];
+  const int per = (nt + kColSplit - 1) / kColSplit;
+  const int r0 = sp * per, r1 = r0 + per < nt ? r0 + per : nt;
   const int64_t pb = a.inst_partial_off[q];
   double acc = 0.0;
-  if (k < D.n_partial)
-    for (int t = rg; t < nt; t += 16) acc += (double)partial[pb + (int64_t)t * D.n_partial + k];
-  sh[rg][c] = acc;
-  __syncthreads();
-  if (rg == 0 && k < D.n_partial) {
-    double s = 0.0;
-    for (int r = 0; r < 16; ++r) s += sh[r][c];
-    a.sumP[a.inst_sum_off[q] + k] = s;
+  if (k < D.n_partial) {
+#pragma unroll 4
+    for (int t = r0 + rl; t < r1; t += 4) acc += (double)partial[pb + (int64_t)t * D.n_partial + k];
   }
+  sh[rl][c] = acc;
+  __syncthreads();
+  if (rl == 0 && blockIdx.x * 64 + c < a.maxp)
+    a.part2[((int64_t)q * kColSplit + sp) * a.maxp + k] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
+}
+
+__global__ void vjp_colsum_finish(VjpArgs a) {
+  const int q = blockIdx.y;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.inst[q].n_partial) return;
+  double s = 0.0;
+#pragma unroll 8
+  for (int sp = 0; sp < kColSplit; ++sp) s += a.part2[((int64_t)q * kColSplit + sp) * a.maxp + k];
+  a.sumP[a.inst_sum_off[q] + k] = s;
+}
+
+// Every output of the adjoint in one launch: dh over the instance's
+// vertices and dJ over its edges, each the fixed-order sum of the split
+// column sums of its partial column times beta (0 on W vertices and W-W
+// edges), and dbeta = sum over columns of coefficient x column sum (block
+// sums, then the last block of the instance in block order).
+__global__ __launch_bounds__(256) void vjp_finish_kernel(VjpArgs a) {
+  __shared__ double sh[256];
+  __shared__ int last;
+  const int q = blockIdx.y;
+  const InstDesc D = a.inst[q];
+  const int64_t vb = a.inst_spin_base[q], eb = a.inst_edge_base[q];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  double contrib = 0.0;
+  if (idx < D.n + D.n_edges) {
+    const int k = idx < D.n ? a.inv_v[vb + idx] : a.inv_e[eb + idx - D.n];
+    double S = 0.0;
+    if (k >= 0) {
+      for (int sp = 0; sp < kColSplit; ++sp) S += a.part2[((int64_t)q * kColSplit + sp) * a.maxp + k];
+      contrib = a.pcoef[a.inst_sum_off[q] + k] * S;
+    }
+    if (idx < D.n) a.dh[vb + idx] = D.beta * S;
+    else a.dJ[eb + idx - D.n] = D.beta * S;
+  }
+  sh[threadIdx.x] = contrib;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.bpart[(int64_t)q * gridDim.x + blockIdx.x] = sh[0];
+    __threadfence();
+    last = atomicAdd(a.done + q, 1) == (int)gridDim.x - 1;
+    if (last) atomicExch(a.done + q, 0);
+  }
+  __syncthreads();
+  if (!last || threadIdx.x != 0) return;
+  __threadfence();
+  double db = 0.0;
+  for (int b = 0; b < (int)gridDim.x; ++b)
+    db += __hip_atomic_load(a.bpart + (int64_t)q * gridDim.x + b, __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT);
+  a.dbeta[q] = db;
 }
 
 // dh, dJ from the column sums (times beta); W vertices and W-W edges stay 0
@@ -538,13 +598,14 @@ template <typename real>
 hipError_t launch_vjp_reduce(const VjpArgs &a, const real *partial, int n_inst, int max_partial,
                              hipStream_t st) {
   if (n_inst <= 0 || max_partial <= 0) return hipSuccess;
-  hipLaunchKernelGGL(vjp_colsum_kernel<real>, dim3((max_partial + 15) / 16, n_inst), dim3(256), 0,
-                     st, a, partial);
-  hipLaunchKernelGGL(vjp_scatter_kernel, dim3((max_partial + 255) / 256, n_inst), dim3(256), 0,
-                     st, a);
-  hipLaunchKernelGGL(vjp_beta_kernel, dim3(n_inst), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(vjp_colsum_kernel<real>, dim3((max_partial + 63) / 64, kColSplit, n_inst),
+                     dim3(256), 0, st, a, partial);
+  hipLaunchKernelGGL(vjp_finish_kernel, dim3((a.max_out + 255) / 256, n_inst), dim3(256), 0, st, a);
   return hipGetLastError();
 }
+
+int vjp_split() { return kColSplit; }
+int vjp_finish_blocks(int max_out) { return (max_out + 255) / 256; }
 
 hipError_t zero_doubles(double *p, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;

@@ -70,7 +70,16 @@ struct VjpArgs {
   const int64_t *inst_sum_off;     // offset of instance i in sumP
   double *sumP;                    // column sums of the partial rows
   double *dh, *dJ, *dbeta;
+  double *part2;                   // [n_inst][vjp_split()][maxp] split sums
+  int32_t maxp;                    // largest n_partial
+  int32_t max_out;                 // largest n_spins + n_edges
+  const int32_t *inv_v, *inv_e;    // vertex / edge -> partial column (-1: none)
+  const double *pcoef;             // dbeta coefficient of every partial column
+  double *bpart;                   // [n_inst][vjp_finish_blocks()] block sums
+  int32_t *done;                   // [n_inst] completion tickets
 };
+int vjp_split();
+int vjp_finish_blocks(int max_out);
 template <typename real>
 hipError_t launch_vjp_reduce(const VjpArgs &a, const real *partial, int n_inst, int max_partial,
                              hipStream_t st);
@@ -192,6 +201,7 @@ struct FreeArgs {
   double *part;              // scratch [n_inst][nblk][4]
   int32_t nblk;
   double *stats;             // out [n_inst][4]
+  int32_t *done;             // [n_inst] completion tickets, zero between launches
 };
 template <typename real>
 hipError_t launch_free(const FreeArgs<real> &a, int n_inst, hipStream_t st);
@@ -199,6 +209,19 @@ hipError_t launch_free(const FreeArgs<real> &a, int n_inst, hipStream_t st);
 hipError_t launch_adam(float *params, const float *grad, float *m, float *v,
                        int64_t n, float lr, int32_t *step_ctr, hipStream_t st);
 hipError_t launch_bump(int32_t *step_ctr, int n, hipStream_t st);
+
+// One optimiser step of every instance (see adam_step_kernel).
+struct OptArgs {
+  const MadeInst *mi;
+  float *params, *grad, *m, *v;
+  const float *part2;        // split gradient rows [n_inst][nsplit][pstride], or null
+  int64_t pstride;
+  int32_t nsplit;
+  float lr;
+  int32_t *step_ctr;
+  int32_t *done;             // [n_inst] completion tickets, zero between launches
+};
+hipError_t launch_adam_step(const OptArgs &a, int n_inst, int64_t max_pc, hipStream_t st);
 
 }  // namespace tnvan
 

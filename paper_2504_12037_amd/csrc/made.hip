@@ -65,6 +65,7 @@ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
   }
 }
 
+constexpr int kRedSplit = 16;   // row splits of the REINFORCE gradient reduction
 constexpr int KH = 16;    // hidden units per lane
 constexpr int KN = 32;    // width-set positions per lane
 
@@ -403,27 +404,84 @@ __global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
       for (int c = 0; c < 4; ++c) sh[c][tid] += sh[c][tid + st];
     __syncthreads();
   }
-  if (tid < 4) a.part[((int64_t)q * gridDim.x + blockIdx.x) * 4 + tid] = sh[tid][0];
-}
-
-// F_q = mean f, its standard error, <Etilde>, <ln q>/beta from the block sums
-// (summed in a fixed order).
-template <typename real>
-__global__ void free_stats_kernel(FreeArgs<real> a) {
-  const int q = blockIdx.x;
-  const MadeInst mi = a.mi[q];
-  if (threadIdx.x != 0 || mi.B <= 0) return;
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k = 0; k < a.nblk; ++k)
-    for (int c = 0; c < 4; ++c) s[c] += a.part[((int64_t)q * a.nblk + k) * 4 + c];
-  const double B = (double)mi.B;
-  const double Fq = s[0] / B;
-  double var = mi.B > 1 ? (s[1] - B * Fq * Fq) / (B - 1.0) : 0.0;
+  // the last block of the instance (completion ticket) forms the statistics
+  // from the block sums, in block order
+  __shared__ int last;
+  if (tid == 0) {
+    for (int c = 0; c < 4; ++c) a.part[((int64_t)q * gridDim.x + blockIdx.x) * 4 + c] = sh[c][0];
+    __threadfence();
+    const int prev = atomicAdd(a.done + q, 1);
+    last = prev == (int)gridDim.x - 1;
+    if (last) atomicExch(a.done + q, 0);
+  }
+  __syncthreads();
+  if (!last || mi.B <= 0) return;
+  __threadfence();
+  // block sums of the instance: thread k holds block k, then a fixed tree
+  for (int c = 0; c < 4; ++c)
+    sh[c][tid] = tid < (int)gridDim.x
+                     ? __hip_atomic_load(a.part + ((int64_t)q * gridDim.x + tid) * 4 + c,
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                     : 0.0;
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if (tid < st)
+      for (int c = 0; c < 4; ++c) sh[c][tid] += sh[c][tid + st];
+    __syncthreads();
+  }
+  if (tid != 0) return;
+  const double sm[4] = {sh[0][0], sh[1][0], sh[2][0], sh[3][0]};
+  const double Bd = (double)mi.B;
+  const double Fq = sm[0] / Bd;
+  double var = mi.B > 1 ? (sm[1] - Bd * Fq * Fq) / (Bd - 1.0) : 0.0;
   if (var < 0.0) var = 0.0;
   a.stats[4 * q + 0] = Fq;
-  a.stats[4 * q + 1] = sqrt(var / B);
-  a.stats[4 * q + 2] = s[2] / B;
-  a.stats[4 * q + 3] = s[3] / B;
+  a.stats[4 * q + 1] = sqrt(var / Bd);
+  a.stats[4 * q + 2] = sm[2] / Bd;
+  a.stats[4 * q + 3] = sm[3] / Bd;
+}
+
+// Adam for every instance in one launch (grid.y = instance).  The gradient
+// is either the flat gradient buffer or, after the fused REINFORCE backward,
+// the fixed-order sum of its split rows (then also stored as the gradient).
+// The last block of an instance (completion ticket) advances its step
+// counter, after every block has read it.
+__global__ __launch_bounds__(256) void adam_step_kernel(OptArgs a) {
+  const int q = blockIdx.y;
+  const MadeInst mi = a.mi[q];
+  const int64_t pc = (int64_t)mi.H * mi.n + mi.H + (int64_t)mi.n * mi.H + mi.n + (int64_t)mi.n * mi.n;
+  const double t = (double)(a.step_ctr[q] + 1);
+  const double c1 = 1.0 - pow(0.9, t), c2 = 1.0 - pow(0.999, t);
+  float *P = a.params + mi.param_off, *G = a.grad + mi.param_off, *M = a.m + mi.param_off,
+        *V = a.v + mi.param_off;
+  // an instance without samples this step keeps its parameters and moments
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; mi.B > 0 && i < pc;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    float gi;
+    if (a.part2) {
+      double acc = 0.0;
+#pragma unroll
+      for (int z = 0; z < kRedSplit; ++z) acc += (double)a.part2[((int64_t)q * kRedSplit + z) * a.pstride + i];
+      gi = (float)acc;
+      G[i] = gi;
+    } else {
+      gi = G[i];
+    }
+    const float mv = 0.9f * M[i] + 0.1f * gi;
+    const float vv = 0.999f * V[i] + 0.001f * gi * gi;
+    M[i] = mv;
+    V[i] = vv;
+    const double mh = (double)mv / c1, vh = (double)vv / c2;
+    P[i] = (float)((double)P[i] - (double)a.lr * mh / (sqrt(vh) + 1e-8));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(a.done + q, 1) == (int)gridDim.x - 1) {
+      atomicAdd(a.step_ctr + q, 1);
+      atomicExch(a.done + q, 0);
+    }
+  }
 }
 
 __global__ void adam_kernel(float *p, const float *g, float *m, float *v, int64_t n,
@@ -878,7 +936,6 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
 // Sum of the instance's workgroup rows in a fixed order, in two passes:
 // slice z of the rows (rows r0 + z, r0 + z + kRedSplit, ...) into part2[q][z],
 // then the kRedSplit slices into grad.  Four parameters per thread.
-constexpr int kRedSplit = 16;
 __device__ inline int64_t made_pc(const MadeInst &m) {
   return (int64_t)m.H * m.n + m.H + (int64_t)m.n * m.H + m.n + (int64_t)m.n * m.n;
 }
@@ -956,13 +1013,9 @@ hipError_t launch_mgrad(const MGradArgs &a, int npt, hipStream_t st) {
 
 hipError_t launch_mgrad_reduce(const MGradArgs &a, hipStream_t st) {
   if (a.n_tasks <= 0) return hipSuccess;
-  hipError_t e;
-  const unsigned bx1 = (unsigned)((a.pstride / 4 + 255) / 256), bx2 = (unsigned)((a.pstride + 255) / 256);
+  const unsigned bx1 = (unsigned)((a.pstride / 4 + 255) / 256);
   hipLaunchKernelGGL(mgrad_reduce1, dim3(bx1, a.n_inst, kRedSplit), dim3(256), 0, st, a.mi,
                      a.first_row, a.n_rows, a.part, a.pstride, a.part2);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(mgrad_reduce2, dim3(bx2, a.n_inst), dim3(256), 0, st, a.mi, a.part2,
-                     a.pstride, a.grad);
   return hipGetLastError();
 }
 
@@ -1050,7 +1103,6 @@ template <typename real>
 hipError_t launch_free(const FreeArgs<real> &a, int n_inst, hipStream_t st) {
   if (n_inst <= 0) return hipSuccess;
   hipLaunchKernelGGL(free_f_kernel<real>, dim3(a.nblk, n_inst), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(free_stats_kernel<real>, dim3(n_inst), dim3(64), 0, st, a);
   return hipGetLastError();
 }
 
@@ -1061,6 +1113,14 @@ hipError_t launch_adam(float *params, const float *grad, float *m, float *v, int
   if (blocks > 1024) blocks = 1024;
   hipLaunchKernelGGL(adam_kernel, dim3(blocks), dim3(256), 0, st, params, grad, m, v, n, lr,
                      step_ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam_step(const OptArgs &a, int n_inst, int64_t max_pc, hipStream_t st) {
+  if (n_inst <= 0) return hipSuccess;
+  if (a.part2 && a.nsplit != kRedSplit) return hipErrorInvalidValue;
+  const int bx = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (max_pc + 255) / 256));
+  hipLaunchKernelGGL(adam_step_kernel, dim3(bx, n_inst), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
