@@ -62,7 +62,7 @@ KERNEL_FLOPS = {
 KERNEL_NAMES = {
     "chain_fwd_2": "rchain_fwd_kernel<false, 2, 2>", "chain_fwd_1": "rchain_fwd_kernel<false, 1, 2>",
     "chain_bwd_2": "rchain_bwd_kernel<2>", "chain_bwd_1": "rchain_bwd_kernel<1>",
-    "made_grad": "mgrad_kernel<2>", "sample": "msample_kernel<2>",
+    "made_grad": "mgrad_kernel<2, 16>", "sample": "msample_kernel<2>",
 }
 PEAK_FP32 = 157.3e12       # MI355X FP32 (vector and 16x16x4 matrix), published
 PEAK_FP64 = 78.6e12
