@@ -3,7 +3,9 @@
     python -m paper_2504_12037_amd.build
 
 Compiles every source under csrc/ with hipcc (packed-FP32 instructions
-disabled) and links them into paper_2504_12037_amd/libtnvan.so.
+disabled; matrix-core operands and results kept in ordinary VGPRs, which
+saves the accumulator-register moves around each product) and links them
+into paper_2504_12037_amd/libtnvan.so.
 """
 
 from __future__ import annotations
@@ -20,6 +22,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]
+DEVICE_FLAGS = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def build(verbose: bool = False) -> str:
@@ -29,7 +32,7 @@ def build(verbose: bool = False) -> str:
     procs = []
     for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")
-        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        lang = ["-x", "hip", *DEVICE_FLAGS] if src.endswith(".hip") else []
         cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

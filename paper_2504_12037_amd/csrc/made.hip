@@ -8,6 +8,7 @@
 // never stored.  Parameters are float32 in the flat layout
 // W1 [H,n], b1 [H], W2 [n,H], b2 [n], W0 [n,n].
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include <algorithm>
 
@@ -43,16 +44,18 @@ template <typename real> __device__ inline real sigmoid(real z) {
 // gradient tolerance): tanh from exp(-2|x|), sigmoid, and log sigmoid.
 __device__ inline float ftanh(float x) {
   const float t = __expf(-2.f * fabsf(x));
-  return copysignf(__fdividef(1.f - t, 1.f + t), x);
+  return copysignf((1.f - t) * __builtin_amdgcn_rcpf(1.f + t), x);
 }
-__device__ inline float fsigmoid(float z) { return __fdividef(1.f, 1.f + __expf(-z)); }
+__device__ inline float fsigmoid(float z) { return __builtin_amdgcn_rcpf(1.f + __expf(-z)); }
+// 1 + e^-|x| lies in (1, 2]: the hardware log2 needs no range handling
 __device__ inline float flogsigmoid(float x) {
-  return fminf(x, 0.f) - __logf(1.f + __expf(-fabsf(x)));
+  return fminf(x, 0.f) - 0.69314718055994531f * __builtin_amdgcn_logf(1.f + __expf(-fabsf(x)));
 }
 
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32->64-bit
 // multiplies with word swaps and key xors; Weyl key schedule.
 __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
@@ -595,7 +598,7 @@ __global__ void made_pack_kernel(const MadeInst *mi, const float *params, float 
   }
 }
 
-template <int NPT>
+template <int NPT, bool kU>
 __global__ __launch_bounds__(256) void msample_kernel(MSampleArgs a) {
   typedef float f4 __attribute__((ext_vector_type(4)));
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -623,7 +626,9 @@ __global__ __launch_bounds__(256) void msample_kernel(MSampleArgs a) {
   }
   float lq = 0.f;
   uint32_t pw[4] = {0u, 0u, 0u, 0u};
-  const float *u = a.uniforms ? a.uniforms + mi.spin_off + (live ? b : 0) * n : nullptr;
+  const float *u = kU ? a.uniforms + mi.spin_off + (live ? b : 0) * n : nullptr;
+  // lanes past the batch end read row 0 (in bounds) and ignore it
+  float pu = kU ? u[0] : 0.5f, qu = 0.5f;
   f4 pa[NPT], pz[NPT], pb;
 #pragma unroll
   for (int t = 0; t < NPT; ++t) {
@@ -631,57 +636,54 @@ __global__ __launch_bounds__(256) void msample_kernel(MSampleArgs a) {
     pz[t] = PZ[t * 64];
   }
   pb = PB1[0];
-  for (int i = 0; i < n; ++i) {
-    f4 cpa[NPT], cpz[NPT];
+  f4 qa[NPT], qz[NPT], qb;
+  // one autoregressive position: logit z_i from the lanes that hold it,
+  // spin, log q, then the hidden units of degree i + 1 and every later
+  // logit; the operands of position i + 1 are loaded meanwhile into the
+  // other register set (R = i mod 4 is static after the unroll by four)
+  auto position = [&](const int i, auto RC, const f4 (&ca)[NPT], const f4 (&cz)[NPT], const f4 &cb,
+                      const float cu, f4 (&na)[NPT], f4 (&nz)[NPT], f4 &nb, float &nu) {
+    constexpr int ri = decltype(RC)::value;
+    // unconditional (the last position reloads itself), so that the wait
+    // for this position's operands can leave the new loads in flight
+    const int nx = i + 1 < n ? i + 1 : i;
 #pragma unroll
-    for (int t = 0; t < NPT; ++t) { cpa[t] = pa[t]; cpz[t] = pz[t]; }
-    const f4 cpb = pb;
-    if (i + 1 < n) {
-#pragma unroll
-      for (int t = 0; t < NPT; ++t) {
-        pa[t] = PA[((int64_t)(i + 1) * NPT + t) * 64];
-        pz[t] = PZ[((int64_t)(i + 1) * NPT + t) * 64];
-      }
-      pb = PB1[(int64_t)(i + 1) * 64];
+    for (int t = 0; t < NPT; ++t) {
+      na[t] = PA[((int64_t)nx * NPT + t) * 64];
+      nz[t] = PZ[((int64_t)nx * NPT + t) * 64];
     }
-    // logit of position i, held by the lanes of row (i >> 2) & 3
-    const int ti = i >> 4, ri = i & 3, gi = (i >> 2) & 3;
-    float own = 0.f;
+    nb = PB1[(int64_t)nx * 64];
+    if (kU) nu = u[nx];
+    const int ti = i >> 4, gi = (i >> 2) & 3;
+    float own = z[0][ri];
 #pragma unroll
-    for (int t = 0; t < NPT; ++t)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (t == ti && r == ri) own = z[t][r];
+    for (int t = 1; t < NPT; ++t)
+      if (t == ti) own = z[t][ri];
     const float zi = __shfl(own, 16 * gi + ls, 64);
     float ui;
-    if (u) {
-      ui = live ? u[i] : 0.5f;
+    if (kU) {
+      ui = live ? cu : 0.5f;
     } else {
-      if ((i & 3) == 0) {
+      if (ri == 0) {
         pw[0] = (uint32_t)(i >> 2); pw[1] = (uint32_t)b; pw[2] = step; pw[3] = (uint32_t)q;
         philox4x32_10(pw, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
       }
-      const uint32_t wd = (i & 3) == 0 ? pw[0] : (i & 3) == 1 ? pw[1] : (i & 3) == 2 ? pw[2] : pw[3];
-      ui = (float)(wd >> 8) * 5.9604644775390625e-08f;
+      ui = (float)(pw[ri] >> 8) * 5.9604644775390625e-08f;
     }
     const float p = fsigmoid(zi);
     const float si = ui < p ? 1.f : -1.f;
     lq += flogsigmoid(si * zi);
-    if (lg == gi) {
+    const bool mine = lg == gi;
 #pragma unroll
-      for (int t = 0; t < NPT; ++t)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (t == ti && r == ri) sp[t][r] = si;
-    }
-    // hidden units of degree i + 1, then every later logit
-    f4 acc = cpb;
+    for (int t = 0; t < NPT; ++t)
+      if (t == ti) sp[t][ri] = mine ? si : sp[t][ri];
+    f4 acc = cb;
 #pragma unroll
     for (int t = 0; t < NPT; ++t)
       if (t <= ti)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(cpa[t][r], sp[t][r], acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[t][r], sp[t][r], acc, 0, 0, 0);
     float h[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) h[r] = ftanh(acc[r]);
@@ -690,7 +692,13 @@ __global__ __launch_bounds__(256) void msample_kernel(MSampleArgs a) {
     for (int t = 0; t < NPT; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        z[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(cpz[t][r], h[r], z[t], 0, 0, 0);
+        z[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(cz[t][r], h[r], z[t], 0, 0, 0);
+  };
+  for (int i = 0; i < n; i += 4) {
+    position(i, std::integral_constant<int, 0>{}, pa, pz, pb, pu, qa, qz, qb, qu);
+    if (i + 1 < n) position(i + 1, std::integral_constant<int, 1>{}, qa, qz, qb, qu, pa, pz, pb, pu);
+    if (i + 2 < n) position(i + 2, std::integral_constant<int, 2>{}, pa, pz, pb, pu, qa, qz, qb, qu);
+    if (i + 3 < n) position(i + 3, std::integral_constant<int, 3>{}, qa, qz, qb, qu, pa, pz, pb, pu);
   }
   if (live) {
     int8_t *so = a.spins + mi.spin_off + b * n;
@@ -742,7 +750,7 @@ __host__ __device__ inline size_t mg_bytes(int H, int npt) {
 }
 
 template <int NPT, int HT>
-__global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
+__global__ __launch_bounds__(256, 1) void mgrad_kernel(MGradArgs a) {
   typedef float f4 __attribute__((ext_vector_type(4)));
   extern __shared__ __align__(16) char smem[];
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -781,7 +789,17 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
         sp[t][r] = (valid && pos < n) ? (float)spn[pos] : 0.f;
       }
     const float wt = valid ? (float)((a.f[mi.sample_off + sb] - a.stats[4 * q]) / (double)mi.B) : 0.f;
+    // one workgroup per CU (LDS), so every stage issues all of its weight
+    // loads before its products
     float h[HT][4];
+    f4 wl[HT][NPT];
+#pragma unroll
+    for (int ht = 0; ht < HT; ++ht) {
+      const int ka = 16 * ht + ls;
+#pragma unroll
+      for (int t = 0; t < NPT; ++t)
+        wl[ht][t] = ld4(W1m + (int64_t)ka * n + 16 * t + 4 * lg, ka < H && 16 * t + 4 * lg < n);
+    }
 #pragma unroll
     for (int ht = 0; ht < HT; ++ht) {
       {
@@ -791,16 +809,11 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
           const int k = 16 * ht + 4 * lg + r;
           acc[r] = k < H ? b1[k] : 0.f;
         }
-        const int ka = 16 * ht + ls;
-        f4 wl[NPT];
-#pragma unroll
-        for (int t = 0; t < NPT; ++t)
-          wl[t] = ld4(W1m + (int64_t)ka * n + 16 * t + 4 * lg, ka < H && 16 * t + 4 * lg < n);
 #pragma unroll
         for (int t = 0; t < NPT; ++t)
 #pragma unroll
           for (int r = 0; r < 4; ++r)
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wl[t][r], sp[t][r], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wl[ht][t][r], sp[t][r], acc, 0, 0, 0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) h[ht][r] = (16 * ht + 4 * lg + r < H) ? ftanh(acc[r]) : 0.f;
       }
@@ -815,12 +828,15 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
         z[r] = pos < n ? b2[pos] : 0.f;
       }
       const int pa = 16 * pt + ls;
+      f4 wz[HT];
+#pragma unroll
+      for (int ht = 0; ht < HT; ++ht)
+        wz[ht] = ld4(W2m + (int64_t)pa * Hs + 16 * ht + 4 * lg, pa < n && 16 * ht + 4 * lg < H);
 #pragma unroll
       for (int ht = 0; ht < HT; ++ht) {
-          const f4 wz = ld4(W2m + (int64_t)pa * Hs + 16 * ht + 4 * lg, pa < n && 16 * ht + 4 * lg < H);
 #pragma unroll
           for (int r = 0; r < 4; ++r)
-            z = __builtin_amdgcn_mfma_f32_16x16x4f32(wz[r], h[ht][r], z, 0, 0, 0);
+            z = __builtin_amdgcn_mfma_f32_16x16x4f32(wz[ht][r], h[ht][r], z, 0, 0, 0);
         }
 #pragma unroll
       for (int t = 0; t < NPT; ++t) {
@@ -847,16 +863,22 @@ __global__ __launch_bounds__(256) void mgrad_kernel(MGradArgs a) {
       *reinterpret_cast<f4 *>(sfb + srow * Lm.ldn + 16 * pt + 4 * lg) =
           f4{sp[pt][0], sp[pt][1], sp[pt][2], sp[pt][3]};
     }
+    f4 wt2[HT][NPT];
+#pragma unroll
+    for (int ht = 0; ht < HT; ++ht) {
+      const int ka = 16 * ht + ls;
+#pragma unroll
+      for (int pt = 0; pt < NPT; ++pt)
+        wt2[ht][pt] = ld4(W2T + (int64_t)ka * n + 16 * pt + 4 * lg, ka < H && 16 * pt + 4 * lg < n);
+    }
 #pragma unroll
     for (int ht = 0; ht < HT; ++ht) {
         f4 acc = f4{0.f, 0.f, 0.f, 0.f};
-        const int ka = 16 * ht + ls;
 #pragma unroll
         for (int pt = 0; pt < NPT; ++pt) {
-          const f4 wt2 = ld4(W2T + (int64_t)ka * n + 16 * pt + 4 * lg, ka < H && 16 * pt + 4 * lg < n);
 #pragma unroll
           for (int r = 0; r < 4; ++r)
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wt2[r], dl[pt][r], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wt2[ht][pt][r], dl[pt][r], acc, 0, 0, 0);
         }
         *reinterpret_cast<f4 *>(hid + srow * Lm.ldh + 16 * ht + 4 * lg) =
             f4{h[ht][0], h[ht][1], h[ht][2], h[ht][3]};
@@ -1031,10 +1053,13 @@ hipError_t launch_made_pack(const MadeInst *mi, int n_inst, int64_t max_floats, 
 hipError_t launch_msample(const MSampleArgs &a, int npt, hipStream_t st) {
   if (a.n_tasks <= 0) return hipSuccess;
   const dim3 grid((a.n_tasks + 3) / 4);
-  if (npt <= 1) hipLaunchKernelGGL(msample_kernel<1>, grid, dim3(256), 0, st, a);
-  else if (npt <= 2) hipLaunchKernelGGL(msample_kernel<2>, grid, dim3(256), 0, st, a);
-  else if (npt <= 4) hipLaunchKernelGGL(msample_kernel<4>, grid, dim3(256), 0, st, a);
+  const bool given = a.uniforms != nullptr;
+  void (*k)(MSampleArgs);
+  if (npt <= 1) k = given ? msample_kernel<1, true> : msample_kernel<1, false>;
+  else if (npt <= 2) k = given ? msample_kernel<2, true> : msample_kernel<2, false>;
+  else if (npt <= 4) k = given ? msample_kernel<4, true> : msample_kernel<4, false>;
   else return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k, grid, dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
