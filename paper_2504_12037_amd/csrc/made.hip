@@ -717,41 +717,46 @@ __global__ __launch_bounds__(256) void msample_kernel(MSampleArgs a) {
 // Fused REINFORCE backward through q (Eq. 10), FP32 on the matrix cores.
 // A workgroup of 4 waves takes 64 samples of one instance.  Each wave first
 // computes the rows of its 16 samples in R-layout: a = b1 + W1m s, h = tanh a,
-// logits z = b2 + W2m h + W0m s, dlogit = w ((1 + s)/2 - sigmoid z) with
-// w = (f_b - F_q) / B, dh = W2m^T dlogit and da = dh (1 - h^2), and writes
-// h, da, dlogit and s sample-major into LDS.  After one barrier the
-// gradient blocks are products over the 64 samples, each wave owning a
-// share of the 16x16 output tiles:  gW2 = dlogit^T h,  gW0 = dlogit^T s,
-// gW1 = da^T s;  the bias gradients are column sums.  The workgroup writes
-// its masked partial gradient as one row; mgrad_reduce sums the rows of an
-// instance in a fixed order.
+// logits z = b2 + W2m h + W0m s and dlogit = w ((1 + s)/2 - sigmoid z) with
+// w = (f_b - F_q) / B, keeping h in registers and writing dlogit and s
+// sample-major into LDS.  The hidden units are then taken in passes of
+// kMgPass tiles: each wave forms dh = W2m^T dlogit and da = dh (1 - h^2) for
+// the pass's tiles and stages h and da sample-major; after a barrier the
+// gradient blocks of the pass are products over the 64 samples, each wave
+// owning a share of the 16x16 output tiles:  gW2 = dlogit^T h,  gW1 = da^T s
+// (and once gW0 = dlogit^T s); the bias gradients are column sums.  Staging a
+// pass at a time keeps the LDS of a workgroup small enough for two per CU.
+// The workgroup writes its masked partial gradient as one row; mgrad_reduce
+// sums the rows of an instance in a fixed order.
 constexpr int kMgTiles = 16;    // hidden tiles (H <= 256)
+constexpr int kMgPass = 4;      // hidden tiles staged per pass
 
 struct MgLayout {
-  int ldh, ldn;
+  int ldq, ldn;
   size_t hid, da, dl, sf, end;
 };
-__host__ __device__ inline MgLayout mg_layout(int H, int npt) {
+__host__ __device__ inline MgLayout mg_layout(int npt) {
   MgLayout L;
-  const int ht = (H + 15) / 16 > 0 ? (H + 15) / 16 : 1;
-  L.ldh = 16 * ht + 4;
+  L.ldq = 16 * kMgPass + 4;
   L.ldn = 16 * npt + 4;
   L.hid = 0;
-  L.da = L.hid + (size_t)64 * L.ldh * 4;
-  L.dl = L.da + (size_t)64 * L.ldh * 4;
+  L.da = L.hid + (size_t)64 * L.ldq * 4;
+  L.dl = L.da + (size_t)64 * L.ldq * 4;
   L.sf = L.dl + (size_t)64 * L.ldn * 4;
   L.end = L.sf + (size_t)64 * L.ldn * 4;
   return L;
 }
-// bytes: rows plus the degree table (16 * tiles ints)
+// bytes: staged rows plus the degree table (16 * tiles ints)
 __host__ __device__ inline size_t mg_bytes(int H, int npt) {
   const int ht = (H + 15) / 16 > 0 ? (H + 15) / 16 : 1;
-  return mg_layout(H, npt).end + (size_t)16 * ht * 4;
+  return mg_layout(npt).end + (size_t)16 * ht * 4;
 }
 
 template <int NPT, int HT>
-__global__ __launch_bounds__(256, 1) void mgrad_kernel(MGradArgs a) {
+__global__ __launch_bounds__(256, 2) void mgrad_kernel(MGradArgs a) {
   typedef float f4 __attribute__((ext_vector_type(4)));
+  constexpr int QT = HT < kMgPass ? HT : kMgPass;   // hidden tiles per pass
+  constexpr int B1 = HT < 8 ? HT : 8;               // tiles per batch of weight loads
   extern __shared__ __align__(16) char smem[];
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63, ls = lane & 15, lg = lane >> 4;
@@ -761,11 +766,12 @@ __global__ __launch_bounds__(256, 1) void mgrad_kernel(MGradArgs a) {
   // HT tiles of 16 hidden units cover the widest instance of the launch;
   // units past an instance's H read as zero
   const int64_t bw = a.task_start[blockIdx.x];
-  const MgLayout Lm = mg_layout(16 * HT, NPT);
+  const MgLayout Lm = mg_layout(NPT);
   float *hid = reinterpret_cast<float *>(smem + Lm.hid);
   float *dab = reinterpret_cast<float *>(smem + Lm.da);
   float *dlb = reinterpret_cast<float *>(smem + Lm.dl);
   float *sfb = reinterpret_cast<float *>(smem + Lm.sf);
+  int32_t *deg = reinterpret_cast<int32_t *>(smem + Lm.end);
   const float *W1 = a.params + mi.param_off, *b1 = W1 + (int64_t)Hs * n, *W2 = b1 + Hs,
               *b2 = W2 + (int64_t)n * Hs, *W0 = b2 + n;
   const float *W2T = a.pack + mi.pack_off + msample_floats(n, NPT);
@@ -775,183 +781,188 @@ __global__ __launch_bounds__(256, 1) void mgrad_kernel(MGradArgs a) {
   auto ld4 = [](const float *p, bool ok) {
     return ok ? *reinterpret_cast<const f4 *>(p) : f4{0.f, 0.f, 0.f, 0.f};
   };
-  {
-    // rows of the wave's 16 samples
-    const int64_t sb = bw + 16 * wave + ls;
-    const bool valid = sb < mi.B;
-    const int8_t *spn = a.spins + mi.spin_off + (valid ? sb : 0) * n;
-    float sp[NPT][4];
+  // rows of the wave's 16 samples
+  const int64_t sb = bw + 16 * wave + ls;
+  const bool valid = sb < mi.B;
+  const int8_t *spn = a.spins + mi.spin_off + (valid ? sb : 0) * n;
+  float sp[NPT][4];
 #pragma unroll
-    for (int t = 0; t < NPT; ++t)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int pos = 16 * t + 4 * lg + r;
-        sp[t][r] = (valid && pos < n) ? (float)spn[pos] : 0.f;
-      }
-    const float wt = valid ? (float)((a.f[mi.sample_off + sb] - a.stats[4 * q]) / (double)mi.B) : 0.f;
-    // one workgroup per CU (LDS), so every stage issues all of its weight
-    // loads before its products
-    float h[HT][4];
-    f4 wl[HT][NPT];
-#pragma unroll
-    for (int ht = 0; ht < HT; ++ht) {
-      const int ka = 16 * ht + ls;
-#pragma unroll
-      for (int t = 0; t < NPT; ++t)
-        wl[ht][t] = ld4(W1m + (int64_t)ka * n + 16 * t + 4 * lg, ka < H && 16 * t + 4 * lg < n);
-    }
-#pragma unroll
-    for (int ht = 0; ht < HT; ++ht) {
-      {
-        f4 acc;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int k = 16 * ht + 4 * lg + r;
-          acc[r] = k < H ? b1[k] : 0.f;
-        }
-#pragma unroll
-        for (int t = 0; t < NPT; ++t)
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wl[ht][t][r], sp[t][r], acc, 0, 0, 0);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) h[ht][r] = (16 * ht + 4 * lg + r < H) ? ftanh(acc[r]) : 0.f;
-      }
-    }
-    float dl[NPT][4];
-#pragma unroll
-    for (int pt = 0; pt < NPT; ++pt) {
-      f4 z;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int pos = 16 * pt + 4 * lg + r;
-        z[r] = pos < n ? b2[pos] : 0.f;
-      }
-      const int pa = 16 * pt + ls;
-      f4 wz[HT];
-#pragma unroll
-      for (int ht = 0; ht < HT; ++ht)
-        wz[ht] = ld4(W2m + (int64_t)pa * Hs + 16 * ht + 4 * lg, pa < n && 16 * ht + 4 * lg < H);
-#pragma unroll
-      for (int ht = 0; ht < HT; ++ht) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            z = __builtin_amdgcn_mfma_f32_16x16x4f32(wz[ht][r], h[ht][r], z, 0, 0, 0);
-        }
-#pragma unroll
-      for (int t = 0; t < NPT; ++t) {
-        const f4 w0 = ld4(W0 + (int64_t)pa * n + 16 * t + 4 * lg, pa < n && 16 * t + 4 * lg < n);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int j = 16 * t + 4 * lg + r;
-          const float wv = j < pa ? w0[r] : 0.f;
-          z = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, sp[t][r], z, 0, 0, 0);
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int pos = 16 * pt + 4 * lg + r;
-        const float s1 = sp[pt][r];
-        dl[pt][r] = pos < n ? wt * ((1.f + s1) * 0.5f - fsigmoid(z[r])) : 0.f;
-      }
-    }
-    const int srow = 16 * wave + ls;
-#pragma unroll
-    for (int pt = 0; pt < NPT; ++pt) {
-      *reinterpret_cast<f4 *>(dlb + srow * Lm.ldn + 16 * pt + 4 * lg) =
-          f4{dl[pt][0], dl[pt][1], dl[pt][2], dl[pt][3]};
-      *reinterpret_cast<f4 *>(sfb + srow * Lm.ldn + 16 * pt + 4 * lg) =
-          f4{sp[pt][0], sp[pt][1], sp[pt][2], sp[pt][3]};
-    }
-    f4 wt2[HT][NPT];
-#pragma unroll
-    for (int ht = 0; ht < HT; ++ht) {
-      const int ka = 16 * ht + ls;
-#pragma unroll
-      for (int pt = 0; pt < NPT; ++pt)
-        wt2[ht][pt] = ld4(W2T + (int64_t)ka * n + 16 * pt + 4 * lg, ka < H && 16 * pt + 4 * lg < n);
-    }
-#pragma unroll
-    for (int ht = 0; ht < HT; ++ht) {
-        f4 acc = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int pt = 0; pt < NPT; ++pt) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wt2[ht][pt][r], dl[pt][r], acc, 0, 0, 0);
-        }
-        *reinterpret_cast<f4 *>(hid + srow * Lm.ldh + 16 * ht + 4 * lg) =
-            f4{h[ht][0], h[ht][1], h[ht][2], h[ht][3]};
-        f4 dv;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) dv[r] = acc[r] * (1.f - h[ht][r] * h[ht][r]);
-        *reinterpret_cast<f4 *>(dab + srow * Lm.ldh + 16 * ht + 4 * lg) = dv;
-      }
-  }
-  // hidden-unit degrees for the output masks
-  int32_t *deg = reinterpret_cast<int32_t *>(smem + Lm.end);
-  for (int k = threadIdx.x; k < 16 * HT; k += blockDim.x) deg[k] = k < H ? 1 + k % nm1 : 1 << 30;
-  __syncthreads();
-  // gradient tiles: [0, NPT*HT) gW2 (pt, ht); then NPT*NPT gW0 (pt, jt);
-  // then HT*NPT gW1 (ht, jt); wave w takes tiles w, w + 4, ...
-  float *prow = a.part + (int64_t)blockIdx.x * a.pstride;
-  const int n2 = NPT * HT, n0 = NPT * NPT, n1 = HT * NPT;
-  const int ntile = n2 + n0 + n1;
-  const int64_t o_b1 = (int64_t)Hs * n, o_W2 = o_b1 + Hs, o_b2 = o_W2 + (int64_t)n * Hs,
-                o_W0 = o_b2 + n;
-  for (int tile = wave; tile < ntile; tile += 4) {
-    const float *Ab, *Bb;
-    int lda, ldb, ai, bj;
-    int kind;
-    if (tile < n2) {
-      kind = 2;
-      const int pt = tile / HT, ht = tile % HT;
-      Ab = dlb; lda = Lm.ldn; ai = 16 * pt;
-      Bb = hid; ldb = Lm.ldh; bj = 16 * ht;
-    } else if (tile < n2 + n0) {
-      kind = 0;
-      const int e = tile - n2, pt = e / NPT, jt = e % NPT;
-      Ab = dlb; lda = Lm.ldn; ai = 16 * pt;
-      Bb = sfb; ldb = Lm.ldn; bj = 16 * jt;
-    } else {
-      kind = 1;
-      const int e = tile - n2 - n0, ht = e / NPT, jt = e % NPT;
-      Ab = dab; lda = Lm.ldh; ai = 16 * ht;
-      Bb = sfb; ldb = Lm.ldn; bj = 16 * jt;
-    }
-    f4 acc = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kc = 0; kc < 16; ++kc) {
-      const int s = 4 * kc + lg;
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Ab[s * lda + ai + ls], Bb[s * ldb + bj + ls], acc,
-                                                 0, 0, 0);
-    }
-    // lane holds rows ai + 4 lg + r, column bj + ls
+  for (int t = 0; t < NPT; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = ai + 4 * lg + r, col = bj + ls;
-      if (kind == 2) {         // gW2[pos][k]: deg(k) <= pos
-        if (row < n && col < Hs)
-          prow[o_W2 + (int64_t)row * Hs + col] = deg[col] <= row ? acc[r] : 0.f;
-      } else if (kind == 0) {  // gW0[pos][j]: j < pos
-        if (row < n && col < n) prow[o_W0 + (int64_t)row * n + col] = col < row ? acc[r] : 0.f;
-      } else {                 // gW1[k][j]: j < deg(k)
-        if (row < Hs && col < n)
-          prow[(int64_t)row * n + col] = col < deg[row] ? acc[r] : 0.f;
+      const int pos = 16 * t + 4 * lg + r;
+      sp[t][r] = (valid && pos < n) ? (float)spn[pos] : 0.f;
+    }
+  const float wt = valid ? (float)((a.f[mi.sample_off + sb] - a.stats[4 * q]) / (double)mi.B) : 0.f;
+  float h[HT][4];
+#pragma unroll
+  for (int h0 = 0; h0 < HT; h0 += B1) {
+    f4 wl[B1][NPT];
+#pragma unroll
+    for (int j = 0; j < B1; ++j) {
+      const int ka = 16 * (h0 + j) + ls;
+#pragma unroll
+      for (int t = 0; t < NPT; ++t)
+        wl[j][t] = ld4(W1m + (int64_t)ka * n + 16 * t + 4 * lg, ka < H && 16 * t + 4 * lg < n);
+    }
+#pragma unroll
+    for (int j = 0; j < B1; ++j) {
+      const int ht = h0 + j;
+      f4 acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = 16 * ht + 4 * lg + r;
+        acc[r] = k < H ? b1[k] : 0.f;
       }
+#pragma unroll
+      for (int t = 0; t < NPT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wl[j][t][r], sp[t][r], acc, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h[ht][r] = (16 * ht + 4 * lg + r < H) ? ftanh(acc[r]) : 0.f;
     }
   }
-  // bias gradients: column sums over the 64 samples
-  for (int k = threadIdx.x; k < Hs; k += blockDim.x) {
-    float acc = 0.f;
-    if (k < H)
-      for (int s = 0; s < 64; ++s) acc += dab[s * Lm.ldh + k];
-    prow[o_b1 + k] = acc;
+  float dl[NPT][4];
+#pragma unroll
+  for (int pt = 0; pt < NPT; ++pt) {
+    f4 z;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int pos = 16 * pt + 4 * lg + r;
+      z[r] = pos < n ? b2[pos] : 0.f;
+    }
+    const int pa = 16 * pt + ls;
+    f4 wz[HT];
+#pragma unroll
+    for (int ht = 0; ht < HT; ++ht)
+      wz[ht] = ld4(W2m + (int64_t)pa * Hs + 16 * ht + 4 * lg, pa < n && 16 * ht + 4 * lg < H);
+#pragma unroll
+    for (int ht = 0; ht < HT; ++ht)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        z = __builtin_amdgcn_mfma_f32_16x16x4f32(wz[ht][r], h[ht][r], z, 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < NPT; ++t) {
+      const f4 w0 = ld4(W0 + (int64_t)pa * n + 16 * t + 4 * lg, pa < n && 16 * t + 4 * lg < n);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = 16 * t + 4 * lg + r;
+        const float wv = j < pa ? w0[r] : 0.f;
+        z = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, sp[t][r], z, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int pos = 16 * pt + 4 * lg + r;
+      const float s1 = sp[pt][r];
+      dl[pt][r] = pos < n ? wt * ((1.f + s1) * 0.5f - fsigmoid(z[r])) : 0.f;
+    }
   }
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    float acc = 0.f;
-    for (int s = 0; s < 64; ++s) acc += dlb[s * Lm.ldn + i];
-    prow[o_b2 + i] = acc;
+  const int srow = 16 * wave + ls;
+#pragma unroll
+  for (int pt = 0; pt < NPT; ++pt) {
+    *reinterpret_cast<f4 *>(dlb + srow * Lm.ldn + 16 * pt + 4 * lg) =
+        f4{dl[pt][0], dl[pt][1], dl[pt][2], dl[pt][3]};
+    *reinterpret_cast<f4 *>(sfb + srow * Lm.ldn + 16 * pt + 4 * lg) =
+        f4{sp[pt][0], sp[pt][1], sp[pt][2], sp[pt][3]};
+  }
+  // hidden-unit degrees for the output masks
+  for (int k = threadIdx.x; k < 16 * HT; k += blockDim.x) deg[k] = k < H ? 1 + k % nm1 : 1 << 30;
+  float *prow = a.part + (int64_t)blockIdx.x * a.pstride;
+  const int64_t o_b1 = (int64_t)Hs * n, o_W2 = o_b1 + Hs, o_b2 = o_W2 + (int64_t)n * Hs,
+                o_W0 = o_b2 + n;
+#pragma unroll
+  for (int pass = 0; pass < HT / QT; ++pass) {
+    const int hbase = 16 * QT * pass;   // first hidden unit of the pass
+    {
+      f4 wt2[QT][NPT];
+#pragma unroll
+      for (int j = 0; j < QT; ++j) {
+        const int ka = hbase + 16 * j + ls;
+#pragma unroll
+        for (int pt = 0; pt < NPT; ++pt)
+          wt2[j][pt] = ld4(W2T + (int64_t)ka * n + 16 * pt + 4 * lg, ka < H && 16 * pt + 4 * lg < n);
+      }
+      if (pass > 0) __syncthreads();   // the previous pass's products are done
+#pragma unroll
+      for (int j = 0; j < QT; ++j) {
+        f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int pt = 0; pt < NPT; ++pt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wt2[j][pt][r], dl[pt][r], acc, 0, 0, 0);
+        const float *hv = h[QT * pass + j];
+        *reinterpret_cast<f4 *>(hid + srow * Lm.ldq + 16 * j + 4 * lg) = f4{hv[0], hv[1], hv[2], hv[3]};
+        f4 dv;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dv[r] = acc[r] * (1.f - hv[r] * hv[r]);
+        *reinterpret_cast<f4 *>(dab + srow * Lm.ldq + 16 * j + 4 * lg) = dv;
+      }
+    }
+    __syncthreads();
+    // tiles of the pass: NPT*QT of gW2 (pt, j), QT*NPT of gW1 (j, jt), and
+    // in the first pass NPT*NPT of gW0 (pt, jt); wave w takes w, w + 4, ...
+    constexpr int n2 = NPT * QT, n1 = QT * NPT;
+    const int ntile = n2 + n1 + (pass == 0 ? NPT * NPT : 0);
+    for (int tile = wave; tile < ntile; tile += 4) {
+      const float *Ab, *Bb;
+      int lda, ldb, ai, bj, kind;
+      if (tile < n2) {
+        kind = 2;
+        const int pt = tile / QT, j = tile % QT;
+        Ab = dlb; lda = Lm.ldn; ai = 16 * pt;
+        Bb = hid; ldb = Lm.ldq; bj = 16 * j;
+      } else if (tile < n2 + n1) {
+        kind = 1;
+        const int e = tile - n2, j = e / NPT, jt = e % NPT;
+        Ab = dab; lda = Lm.ldq; ai = 16 * j;
+        Bb = sfb; ldb = Lm.ldn; bj = 16 * jt;
+      } else {
+        kind = 0;
+        const int e = tile - n2 - n1, pt = e / NPT, jt = e % NPT;
+        Ab = dlb; lda = Lm.ldn; ai = 16 * pt;
+        Bb = sfb; ldb = Lm.ldn; bj = 16 * jt;
+      }
+      f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kc = 0; kc < 16; ++kc) {
+        const int s = 4 * kc + lg;
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Ab[s * lda + ai + ls], Bb[s * ldb + bj + ls], acc,
+                                                   0, 0, 0);
+      }
+      // lane holds rows ai + 4 lg + r, column bj + ls of the staged blocks
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = ai + 4 * lg + r, col = bj + ls;
+        if (kind == 2) {         // gW2[pos][k]: deg(k) <= pos
+          const int k = hbase + col;
+          if (row < n && k < Hs)
+            prow[o_W2 + (int64_t)row * Hs + k] = deg[k] <= row ? acc[r] : 0.f;
+        } else if (kind == 1) {  // gW1[k][j]: j < deg(k)
+          const int k = hbase + row;
+          if (k < Hs && col < n) prow[(int64_t)k * n + col] = col < deg[k] ? acc[r] : 0.f;
+        } else {                 // gW0[pos][j]: j < pos
+          if (row < n && col < n) prow[o_W0 + (int64_t)row * n + col] = col < row ? acc[r] : 0.f;
+        }
+      }
+    }
+    // bias gradients of the pass: column sums over the 64 samples
+    for (int k = threadIdx.x; k < 16 * QT; k += blockDim.x) {
+      const int kk = hbase + k;
+      if (kk >= Hs) continue;
+      float acc = 0.f;
+      if (kk < H)
+        for (int s = 0; s < 64; ++s) acc += dab[s * Lm.ldq + k];
+      prow[o_b1 + kk] = acc;
+    }
+    if (pass == 0)
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        float acc = 0.f;
+        for (int s = 0; s < 64; ++s) acc += dlb[s * Lm.ldn + i];
+        prow[o_b2 + i] = acc;
+      }
   }
 }
 
