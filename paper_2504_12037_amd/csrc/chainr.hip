@@ -13,7 +13,8 @@
 // width-set spins (staged once per wave in LDS) and the W-neighbour lists.
 //
 // The adjoint walks the chain backwards from checkpoints of A (every
-// kRegSeg steps, in HBM), replaying each segment in registers.  With
+// kRegSeg steps, in HBM; one step apart by default, so nothing is replayed,
+// else each segment is replayed in registers).  With
 // R_t = d(ln Z)/d(out_t) in R-layout:
 //   Lambda_t = T_t R_t                 (matrix core, R-layout over x)
 //   p_t      = A_t * Lambda_t          (marginal of the group's states)
@@ -437,6 +438,8 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
   ChainStep sn = step_at(cs, T - 1);
   f4 tqn[CT][CT];
   load_t<CT>(a.Tq + sn.tq_off, lane, tqn);
+  float uun[GR];   // and its unary factors (HBM, the longest wait of a step)
+  load_phi<GR>(a, tk.q, tk.Bq, sn.gpos, sn.g, bme, uun);
   for (int seg = NC - 1; seg >= 0; --seg) {
     const int t0 = seg * KS;
     float As[KS][CT][4];
@@ -484,11 +487,13 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
           }
         }
         float uu[GR];
-        load_phi<GR>(a, tk.q, tk.Bq, st.gpos, g, bme, uu);
+#pragma unroll
+        for (int j = 0; j < GR; ++j) uu[j] = uun[j];
         const EdgeDesc myed = lane < st.n_edge ? ce[st.ce_off + lane] : EdgeDesc{0, 0, 0, 0};
-        // the next step's descriptor and Lambda operands
+        // the next step's descriptor, Lambda operands and unary factors
         sn = step_at(cs, t > 0 ? t - 1 : 0);
         load_t<CT>(a.Tq + sn.tq_off, lane, tqn);
+        load_phi<GR>(a, tk.q, tk.Bq, sn.gpos, sn.g, bme, uun);
         // Lambda = T R (R-layout over the group states)
         f4 lam[CT];
 #pragma unroll
