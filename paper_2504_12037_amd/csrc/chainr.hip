@@ -12,9 +12,8 @@
 // unary factors of a group are computed on the fly from the sample's
 // width-set spins (staged once per wave in LDS) and the W-neighbour lists.
 //
-// The adjoint walks the chain backwards from checkpoints of A (every
-// kRegSeg steps, in HBM; one step apart by default, so nothing is replayed,
-// else each segment is replayed in registers).  With
+// The adjoint walks the chain backwards from checkpoints of A (every step,
+// in HBM; nothing is recomputed).  With
 // R_t = d(ln Z)/d(out_t) in R-layout:
 //   Lambda_t = T_t R_t                 (matrix core, R-layout over x)
 //   p_t      = A_t * Lambda_t          (marginal of the group's states)
@@ -122,15 +121,15 @@ __device__ inline void make_diag(const float (&p0)[GR], const float (&p1)[GR], i
 }
 
 // Unary factors of the group of g <= GR positions starting at order
-// position gpos for sample b (clamped into the batch), as stored by
-// unary_kernel: +-exp(-2 beta |f|), the sign that of f.
+// position gpos, as stored by unary_kernel: +-exp(-2 beta |f|), the sign
+// that of f.  ub = phi_base(...) of the sample (computed once per chain).
+__device__ inline const float *phi_base(const ChainArgs &a, int q, int64_t Bq, int64_t b) {
+  return a.U + a.u_off[q] + (b < Bq ? b : Bq - 1);   // past the batch: clamped
+}
 template <int GR>
-__device__ inline void load_phi(const ChainArgs &a, int q, int64_t Bq, int gpos, int g, int64_t b,
-                                float (&u)[GR]) {
-  const float *Uq = a.U + a.u_off[q];
-  const int64_t bs = b < Bq ? b : Bq - 1;
+__device__ inline void load_phi(const float *ub, int64_t Bq, int gpos, int g, float (&u)[GR]) {
 #pragma unroll
-  for (int j = 0; j < GR; ++j) u[j] = Uq[(int64_t)(gpos + (j < g ? j : 0)) * Bq + bs];
+  for (int j = 0; j < GR; ++j) u[j] = ub[(int64_t)(gpos + (j < g ? j : 0)) * Bq];
 }
 
 // phi(+1) = 1, phi(-1) = exp(-2 beta f) for f >= 0 and the mirror image for
@@ -277,31 +276,32 @@ __device__ inline void fwd_chain(const ChainArgs &a, const Task &tk, const Chain
   const int T = cd.n_steps;
   int esum[SG];
   float x[SG][CT][4], raw[SG];
+  const float *ub[SG];
+#pragma unroll
+  for (int gi = 0; gi < SG; ++gi) ub[gi] = phi_base(a, tk.q, tk.Bq, tk.b0 + gi * CW + ls);
   {
     const ChainStep s0 = cs[0];
 #pragma unroll
     for (int gi = 0; gi < SG; ++gi) {
       float u[GR];
-      load_phi<GR>(a, tk.q, tk.Bq, s0.gpos, s0.g, tk.b0 + gi * CW + ls, u);
+      load_phi<GR>(ub[gi], tk.Bq, s0.gpos, s0.g, u);
       diag_from_phi<CT, GR>(u, s0.g, lg, x[gi]);
       esum[gi] = 0;
     }
   }
-  f4 tc[CT][CT];
-  u4v bc[CT][NC2];
-  if (kBF) load_tb<CT>(a.Trb + cs[0].trb_off, lane, bc);
-  else load_t<CT>(a.Tr + cs[0].tr_off, lane, tc);
-  for (int t = 0;; ++t) {
+  // step t with the descriptor nx of step t + 1, the table of step t and
+  // the unary factors uc of step t + 1's group; loads step t + 1's table and
+  // step t + 2's unary factors into the other register set (two sets used in
+  // turn: a loaded value is never copied, which would wait for the load)
+  auto fstep = [&](int t, const ChainStep &nx, const f4 (&tc)[CT][CT], const u4v (&bc)[CT][NC2],
+                   const float (&uc)[SG][GR], ChainStep &nn, f4 (&tn)[CT][CT], u4v (&bn)[CT][NC2],
+                   float (&un)[SG][GR]) -> bool {
     const bool last = t == T - 1;
-    const ChainStep nx = step_at(cs, last ? t : t + 1);
-    // next step's tables and unary factors (the closing step reloads its own)
-    f4 tn[CT][CT];
-    u4v bn[CT][NC2];
+    nn = step_at(cs, t + 2 < T ? t + 2 : T - 1);
     if (kBF) load_tb<CT>(a.Trb + nx.trb_off, lane, bn);
     else load_t<CT>(a.Tr + nx.tr_off, lane, tn);
-    float un[SG][GR];
 #pragma unroll
-    for (int gi = 0; gi < SG; ++gi) load_phi<GR>(a, tk.q, tk.Bq, nx.gpos, nx.g, tk.b0 + gi * CW + ls, un[gi]);
+    for (int gi = 0; gi < SG; ++gi) load_phi<GR>(ub[gi], tk.Bq, nn.gpos, nn.g, un[gi]);
     f4 acc[SG][CT];
 #pragma unroll
     for (int gi = 0; gi < SG; ++gi) {
@@ -311,21 +311,27 @@ __device__ inline void fwd_chain(const ChainArgs &a, const Task &tk, const Chain
     if (last) {
 #pragma unroll
       for (int gi = 0; gi < SG; ++gi) raw[gi] = __shfl(acc[gi][0][0], ls, 64);
-      break;
+      return true;
     }
 #pragma unroll
     for (int gi = 0; gi < SG; ++gi) {
       float d[CT][4];
-      diag_from_phi<CT, GR>(un[gi], nx.g, lg, d);
+      diag_from_phi<CT, GR>(uc[gi], nx.g, lg, d);
       esum[gi] += rescale_next<CT>(acc[gi], d, x[gi]);
     }
+    return false;
+  };
+  ChainStep nA = step_at(cs, T > 1 ? 1 : 0), nB;
+  f4 tA[CT][CT], tB[CT][CT];
+  u4v bA[CT][NC2], bB[CT][NC2];
+  float uA[SG][GR], uB[SG][GR];
+  if (kBF) load_tb<CT>(a.Trb + cs[0].trb_off, lane, bA);
+  else load_t<CT>(a.Tr + cs[0].tr_off, lane, tA);
 #pragma unroll
-    for (int i = 0; i < CT; ++i) {
-#pragma unroll
-      for (int j = 0; j < CT; ++j) tc[i][j] = tn[i][j];
-#pragma unroll
-      for (int c = 0; c < NC2; ++c) bc[i][c] = bn[i][c];
-    }
+  for (int gi = 0; gi < SG; ++gi) load_phi<GR>(ub[gi], tk.Bq, nA.gpos, nA.g, uA[gi]);
+  for (int t = 0;; t += 2) {
+    if (fstep(t, nA, tA, bA, uA, nB, tB, bB, uB)) break;
+    if (fstep(t + 1, nB, tB, bB, uB, nA, tA, bA, uA)) break;
   }
   if (lg == 0) {
 #pragma unroll
@@ -359,7 +365,6 @@ __device__ inline float sgn(int x, int j) { return ((x >> j) & 1) ? -1.f : 1.f; 
 template <int CT>
 __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstDesc &D,
                                  const ChainDesc &cd, char *base, const RL &L, int lane) {
-  constexpr int KS = kRegSeg;
   constexpr int GR = GroupMax<CT>::v;
   constexpr int LDT = ldt_of(CT);
   const int ls = lane & 15, lg = lane >> 4;
@@ -375,49 +380,58 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
   const float gs = ls < nvalid ? (float)a.grad[a.inst_sample_off[tk.q] + tk.b0 + ls] : 0.f;
   float *prow = a.partial + a.inst_partial_off[tk.q] + (tk.b0 / CW) * (int64_t)D.n_partial;
   const int T = cd.n_steps;
-  const int ncmax = (a.lim.max_steps + KS - 1) / KS;
   f4 *ck = reinterpret_cast<f4 *>(a.ckpt) +
-           (int64_t)(a.task_base + blockIdx.x * kWaves + (threadIdx.x >> 6)) * ncmax * kRegBwdTiles * 64 +
+           (int64_t)(a.task_base + blockIdx.x * kWaves + (threadIdx.x >> 6)) * a.lim.max_steps *
+               kRegBwdTiles * 64 +
            lane;
   const EdgeDesc *ce = a.cedges + cd.e_src;
+  const float *ub = phi_base(a, tk.q, tk.Bq, tk.b0 + ls);
 
-  // forward: checkpoints every KS steps, exponents in LDS, root value
-  const int64_t bme = tk.b0 + ls;
+  // Both passes load the operands of the next step while one step is
+  // processed, into two register sets used in turn: a loaded value is never
+  // copied (a copy would wait for the load at the end of the step).
+
+  // forward: A_t checkpointed every step, exponents in LDS, root value
   float x[CT][4];
   {
     float u[GR];
-    load_phi<GR>(a, tk.q, tk.Bq, cs[0].gpos, cs[0].g, bme, u);
+    load_phi<GR>(ub, tk.Bq, cs[0].gpos, cs[0].g, u);
     diag_from_phi<CT, GR>(u, cs[0].g, lg, x);
   }
   float raw = 1.f;
   {
-    f4 tc[CT][CT];
-    load_t<CT>(a.Tr + cs[0].tr_off, lane, tc);
-    for (int t = 0;; ++t) {
-      if (t % KS == 0) {
-#pragma unroll
-        for (int i = 0; i < CT; ++i)
-          ck[((t / KS) * kRegBwdTiles + i) * 64] = f4{x[i][0], x[i][1], x[i][2], x[i][3]};
-      }
-      const bool last = t == T - 1;
-      const ChainStep nx = step_at(cs, last ? t : t + 1);
-      f4 tn[CT][CT];
-      load_t<CT>(a.Tr + nx.tr_off, lane, tn);
-      float u[GR], d[CT][4];
-      load_phi<GR>(a, tk.q, tk.Bq, nx.gpos, nx.g, bme, u);
-      f4 acc[CT];
-      mm_fwd<CT>(tc, x, acc);
-      diag_from_phi<CT, GR>(u, nx.g, lg, d);
-      if (last) {
-        raw = __shfl(acc[0][0], ls, 64);
-        break;
-      }
-      const int e = rescale_next<CT>(acc, d, x);
-      if (lg == 0) ex[t * CW + ls] = e;
+    // step t with the descriptor nx of step t + 1, table tc of step t and
+    // unary factors uc of step t + 1's group; loads step t + 1's table and
+    // step t + 2's unary factors
+    auto fstep = [&](int t, const ChainStep &nx, const f4 (&tc)[CT][CT], const float (&uc)[GR],
+                     ChainStep &nn, f4 (&tn)[CT][CT], float (&un)[GR]) -> bool {
 #pragma unroll
       for (int i = 0; i < CT; ++i)
-#pragma unroll
-        for (int j = 0; j < CT; ++j) tc[i][j] = tn[i][j];
+        ck[(t * kRegBwdTiles + i) * 64] = f4{x[i][0], x[i][1], x[i][2], x[i][3]};
+      const bool last = t == T - 1;
+      nn = step_at(cs, t + 2 < T ? t + 2 : T - 1);
+      load_t<CT>(a.Tr + nx.tr_off, lane, tn);
+      load_phi<GR>(ub, tk.Bq, nn.gpos, nn.g, un);
+      f4 acc[CT];
+      mm_fwd<CT>(tc, x, acc);
+      if (last) {
+        raw = __shfl(acc[0][0], ls, 64);
+        return true;
+      }
+      float d[CT][4];
+      diag_from_phi<CT, GR>(uc, nx.g, lg, d);
+      const int e = rescale_next<CT>(acc, d, x);
+      if (lg == 0) ex[t * CW + ls] = e;
+      return false;
+    };
+    ChainStep nA = step_at(cs, T > 1 ? 1 : 0), nB;
+    f4 tA[CT][CT], tB[CT][CT];
+    float uA[GR], uB[GR];
+    load_t<CT>(a.Tr + cs[0].tr_off, lane, tA);
+    load_phi<GR>(ub, tk.Bq, nA.gpos, nA.g, uA);
+    for (int t = 0;; t += 2) {
+      if (fstep(t, nA, tA, uA, nB, tB, uB)) break;
+      if (fstep(t + 1, nB, tB, uB, nA, tA, uA)) break;
     }
   }
   wsync();
@@ -430,163 +444,140 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
     for (int r = 0; r < 4; ++r) R[i][r] = 0.f;
   if (lg == 0) R[0][0] = raw > 0.f ? 1.f / raw : 0.f;
 
-  const int NC = (T + KS - 1) / KS;
-  f4 ckn[CT];   // checkpoint of the next segment, loaded one segment ahead
+  // the walk, step t with its checkpoint A_t, Lambda operands and unary
+  // factors loaded during step t + 1
+  struct Pre {
+    f4 a[CT];
+    f4 tq[CT][CT];
+    float u[GR];
+  };
+  auto prefetch = [&](const ChainStep &s, int t, Pre &p) {
 #pragma unroll
-  for (int i = 0; i < CT; ++i) ckn[i] = ck[((NC - 1) * kRegBwdTiles + i) * 64];
-  // the Lambda operands of the next step walked, loaded one step ahead
-  ChainStep sn = step_at(cs, T - 1);
-  f4 tqn[CT][CT];
-  load_t<CT>(a.Tq + sn.tq_off, lane, tqn);
-  float uun[GR];   // and its unary factors (HBM, the longest wait of a step)
-  load_phi<GR>(a, tk.q, tk.Bq, sn.gpos, sn.g, bme, uun);
-  for (int seg = NC - 1; seg >= 0; --seg) {
-    const int t0 = seg * KS;
-    float As[KS][CT][4];
+    for (int i = 0; i < CT; ++i) p.a[i] = ck[(t * kRegBwdTiles + i) * 64];
+    load_t<CT>(a.Tq + s.tq_off, lane, p.tq);
+    load_phi<GR>(ub, tk.Bq, s.gpos, s.g, p.u);
+  };
+  auto walk = [&](int t, const ChainStep &st, const Pre &cur, ChainStep &sn, Pre &nxt) {
+    const int g = st.g, w = st.w;
+    float As[CT][4];
 #pragma unroll
     for (int i = 0; i < CT; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) As[0][i][r] = ckn[i][r];
+      for (int r = 0; r < 4; ++r) As[i][r] = cur.a[i][r];
+    // operands used later in this step, issued now
+    f4 tr[CT][CT], sx[CT], so[CT];
+    load_t<CT>(a.Tr + st.tr_off, lane, tr);
+    {
+      const f4 *sxo = reinterpret_cast<const f4 *>(a.Tsx + st.sx_off) + lane;
 #pragma unroll
-    for (int i = 0; i < CT; ++i) ckn[i] = ck[((seg > 0 ? seg - 1 : 0) * kRegBwdTiles + i) * 64];
-    // replay the segment (steps past the chain recompute the last one)
-#pragma unroll
-    for (int u = 1; u < KS; ++u) {
-      const int tp = t0 + u - 1 < T - 1 ? t0 + u - 1 : T - 1;
-      const ChainStep st = step_at(cs, tp), nx = step_at(cs, tp + 1 < T ? tp + 1 : tp);
-      f4 tc[CT][CT];
-      load_t<CT>(a.Tr + st.tr_off, lane, tc);
-      float uu[GR], d[CT][4];
-      load_phi<GR>(a, tk.q, tk.Bq, nx.gpos, nx.g, bme, uu);
-      f4 acc[CT];
-      mm_fwd<CT>(tc, As[u - 1], acc);
-      diag_from_phi<CT, GR>(uu, nx.g, lg, d);
-      rescale_next<CT>(acc, d, As[u]);
-    }
-    // walk the segment backwards
-#pragma unroll
-    for (int u = KS - 1; u >= 0; --u) {
-      const int t = t0 + u;
-      if (t < T) {
-        const ChainStep st = sn;
-        const int g = st.g, w = st.w;
-        f4 tq[CT][CT];
-#pragma unroll
-        for (int i = 0; i < CT; ++i)
-#pragma unroll
-          for (int j = 0; j < CT; ++j) tq[i][j] = tqn[i][j];
-        // operands used later in this step, issued now
-        f4 tr[CT][CT], sx[CT], so[CT];
-        load_t<CT>(a.Tr + st.tr_off, lane, tr);
-        {
-          const f4 *sxo = reinterpret_cast<const f4 *>(a.Tsx + st.sx_off) + lane;
-#pragma unroll
-          for (int i = 0; i < CT; ++i) {
-            sx[i] = sxo[i * 64];
-            so[i] = sxo[(CT + i) * 64];
-          }
-        }
-        float uu[GR];
-#pragma unroll
-        for (int j = 0; j < GR; ++j) uu[j] = uun[j];
-        const EdgeDesc myed = lane < st.n_edge ? ce[st.ce_off + lane] : EdgeDesc{0, 0, 0, 0};
-        // the next step's descriptor, Lambda operands and unary factors
-        sn = step_at(cs, t > 0 ? t - 1 : 0);
-        load_t<CT>(a.Tq + sn.tq_off, lane, tqn);
-        load_phi<GR>(a, tk.q, tk.Bq, sn.gpos, sn.g, bme, uun);
-        // Lambda = T R (R-layout over the group states)
-        f4 lam[CT];
-#pragma unroll
-        for (int xt = 0; xt < CT; ++xt) lam[xt] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ot = 0; ot < CT; ++ot)
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int xt = 0; xt < CT; ++xt)
-              lam[xt] = __builtin_amdgcn_mfma_f32_16x16x4f32(tq[xt][ot][r], R[ot][r], lam[xt], 0, 0, 0);
-        // W-R correlations: per-sample magnetisation of a group spin times the
-        // neighbouring width-set spin, weighted and summed over the samples
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if (k < st.n_wri) {
-            const int j = st.wri[k] & 0xff, wi = st.wri[k] >> 8;
-            float m = 0.f;
-#pragma unroll
-            for (int xt = 0; xt < CT; ++xt)
-#pragma unroll
-              for (int r = 0; r < 4; ++r) m += sgn(16 * xt + 4 * lg + r, j) * As[u][xt][r] * lam[xt][r];
-            m = xlane_sum(m) * gs;
-            const float v = row16_sum(m * sp.sigma(wi));
-            if (lane == 0) prow[D.nr + st.wre[k]] = v;
-          }
-        // R of the previous step (unused after the first step)
-        float Rn[CT][4];
-        {
-          float d[CT][4];
-          diag_from_phi<CT, GR>(uu, g, lg, d);
-          const float sc = pow2neg(ex[(t > 0 ? t - 1 : 0) * CW + ls]);
-#pragma unroll
-          for (int xt = 0; xt < CT; ++xt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) Rn[xt][r] = d[xt][r] * lam[xt][r] * sc;
-        }
-        // H = sum_s (g A)[s] R[s]^T through an LDS transpose
-#pragma unroll
-        for (int xt = 0; xt < CT; ++xt)
-          *reinterpret_cast<f4 *>(ga + ls * LDT + 16 * xt + 4 * lg) =
-              f4{gs * As[u][xt][0], gs * As[u][xt][1], gs * As[u][xt][2], gs * As[u][xt][3]};
-#pragma unroll
-        for (int ot = 0; ot < CT; ++ot)
-          *reinterpret_cast<f4 *>(rs + ls * LDT + 16 * ot + 4 * lg) =
-              f4{R[ot][0], R[ot][1], R[ot][2], R[ot][3]};
-        wsync();
-        // per output tile: H (samples contracted), G = H o T, Q'^T = G^T S_x
-        f4 qt[CT];
-#pragma unroll
-        for (int ot = 0; ot < CT; ++ot) {
-          f4 hg[CT];
-#pragma unroll
-          for (int xt = 0; xt < CT; ++xt) {
-            hg[xt] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kc = 0; kc < 4; ++kc)
-              hg[xt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                  ga[(4 * kc + lg) * LDT + 16 * xt + ls], rs[(4 * kc + lg) * LDT + 16 * ot + ls],
-                  hg[xt], 0, 0, 0);
-          }
-          qt[ot] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int xt = 0; xt < CT; ++xt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-              qt[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(hg[xt][r] * tr[ot][xt][r], sx[xt][r],
-                                                            qt[ot], 0, 0, 0);
-        }
-        wsync();
-        // Q = S_o^T Q'^T (operand tables)
-        f4 qq = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int ot = 0; ot < CT; ++ot)
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            qq = __builtin_amdgcn_mfma_f32_16x16x4f32(so[ot][r], qt[ot][r], qq, 0, 0, 0);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) qs[ls * 17 + 4 * lg + r] = qq[r];
-        wsync();
-        if (lane < st.n_edge) prow[D.nr + D.n_wr + myed.rr] = qs[(myed.pad >> 4) * 17 + (myed.pad & 15)];
-        for (int k = lane + 64; k < st.n_edge; k += 64) {
-          const EdgeDesc ed = ce[st.ce_off + k];
-          prow[D.nr + D.n_wr + ed.rr] = qs[(ed.pad >> 4) * 17 + (ed.pad & 15)];
-        }
-        if (lane < g) prow[st.gpos + lane] = qs[lane * 17 + w];
-        wsync();
-#pragma unroll
-        for (int i = 0; i < CT; ++i)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) R[i][r] = Rn[i][r];
+      for (int i = 0; i < CT; ++i) {
+        sx[i] = sxo[i * 64];
+        so[i] = sxo[(CT + i) * 64];
       }
     }
+    const EdgeDesc myed = lane < st.n_edge ? ce[st.ce_off + lane] : EdgeDesc{0, 0, 0, 0};
+    // the next step walked: descriptor and operands (step 0 reloads itself)
+    sn = step_at(cs, t > 0 ? t - 1 : 0);
+    prefetch(sn, t > 0 ? t - 1 : 0, nxt);
+    // Lambda = T R (R-layout over the group states)
+    f4 lam[CT];
+#pragma unroll
+    for (int xt = 0; xt < CT; ++xt) lam[xt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ot = 0; ot < CT; ++ot)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int xt = 0; xt < CT; ++xt)
+          lam[xt] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.tq[xt][ot][r], R[ot][r], lam[xt], 0, 0, 0);
+    // W-R correlations: per-sample magnetisation of a group spin times the
+    // neighbouring width-set spin, weighted and summed over the samples
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (k < st.n_wri) {
+        const int j = st.wri[k] & 0xff, wi = st.wri[k] >> 8;
+        float m = 0.f;
+#pragma unroll
+        for (int xt = 0; xt < CT; ++xt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) m += sgn(16 * xt + 4 * lg + r, j) * As[xt][r] * lam[xt][r];
+        m = xlane_sum(m) * gs;
+        const float v = row16_sum(m * sp.sigma(wi));
+        if (lane == 0) prow[D.nr + st.wre[k]] = v;
+      }
+    // R of the previous step (unused after the first step)
+    float Rn[CT][4];
+    {
+      float d[CT][4];
+      diag_from_phi<CT, GR>(cur.u, g, lg, d);
+      const float sc = pow2neg(ex[(t > 0 ? t - 1 : 0) * CW + ls]);
+#pragma unroll
+      for (int xt = 0; xt < CT; ++xt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Rn[xt][r] = d[xt][r] * lam[xt][r] * sc;
+    }
+    // H = sum_s (g A)[s] R[s]^T through an LDS transpose
+#pragma unroll
+    for (int xt = 0; xt < CT; ++xt)
+      *reinterpret_cast<f4 *>(ga + ls * LDT + 16 * xt + 4 * lg) =
+          f4{gs * As[xt][0], gs * As[xt][1], gs * As[xt][2], gs * As[xt][3]};
+#pragma unroll
+    for (int ot = 0; ot < CT; ++ot)
+      *reinterpret_cast<f4 *>(rs + ls * LDT + 16 * ot + 4 * lg) =
+          f4{R[ot][0], R[ot][1], R[ot][2], R[ot][3]};
+    wsync();
+    // per output tile: H (samples contracted), G = H o T, Q'^T = G^T S_x
+    f4 qt[CT];
+#pragma unroll
+    for (int ot = 0; ot < CT; ++ot) {
+      f4 hg[CT];
+#pragma unroll
+      for (int xt = 0; xt < CT; ++xt) {
+        hg[xt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc)
+          hg[xt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+              ga[(4 * kc + lg) * LDT + 16 * xt + ls], rs[(4 * kc + lg) * LDT + 16 * ot + ls],
+              hg[xt], 0, 0, 0);
+      }
+      qt[ot] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int xt = 0; xt < CT; ++xt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          qt[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(hg[xt][r] * tr[ot][xt][r], sx[xt][r],
+                                                        qt[ot], 0, 0, 0);
+    }
+    wsync();
+    // Q = S_o^T Q'^T (operand tables)
+    f4 qq = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ot = 0; ot < CT; ++ot)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        qq = __builtin_amdgcn_mfma_f32_16x16x4f32(so[ot][r], qt[ot][r], qq, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) qs[ls * 17 + 4 * lg + r] = qq[r];
+    wsync();
+    if (lane < st.n_edge) prow[D.nr + D.n_wr + myed.rr] = qs[(myed.pad >> 4) * 17 + (myed.pad & 15)];
+    for (int k = lane + 64; k < st.n_edge; k += 64) {
+      const EdgeDesc ed = ce[st.ce_off + k];
+      prow[D.nr + D.n_wr + ed.rr] = qs[(ed.pad >> 4) * 17 + (ed.pad & 15)];
+    }
+    if (lane < g) prow[st.gpos + lane] = qs[lane * 17 + w];
+    wsync();
+#pragma unroll
+    for (int i = 0; i < CT; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) R[i][r] = Rn[i][r];
+  };
+  ChainStep sA = step_at(cs, T - 1), sB;
+  Pre pA, pB;
+  prefetch(sA, T - 1, pA);
+  for (int t = T - 1; t >= 0; t -= 2) {
+    walk(t, sA, pA, sB, pB);
+    if (t == 0) break;
+    walk(t - 1, sB, pB, sA, pA);
   }
 }
 
@@ -610,7 +601,7 @@ __global__ __launch_bounds__(256, 3) void rchain_bwd_kernel(ChainArgs a) {
 size_t rchain_wave_lds(const ChainLim &L, bool bwd, int sg) { return rlayout(L, bwd, sg).end; }
 
 int64_t rchain_ckpt_floats(const ChainLim &L) {
-  return (int64_t)((L.max_steps + kRegSeg - 1) / kRegSeg) * kRegBwdTiles * 64 * 4;
+  return (int64_t)L.max_steps * kRegBwdTiles * 64 * 4;
 }
 
 // one launch per chain width: tasks [task_base, task_base + n_tasks) all

@@ -292,7 +292,6 @@ hipError_t launch_chain(const ChainArgs &a, bool bwd, hipStream_t st);
 // Forward: steps of at most 4 tiles (K, N <= 64); adjoint: at most 2 tiles.
 constexpr int kRegFwdTiles = 4;
 constexpr int kRegBwdTiles = 2;
-constexpr int kRegSeg = 1;            // adjoint checkpoint interval (1: every step, no replay)
 size_t rchain_wave_lds(const ChainLim &L, bool bwd, int sg);
 int64_t rchain_ckpt_floats(const ChainLim &L);   // per adjoint task
 hipError_t launch_rchain(const ChainArgs &a, bool bwd, hipStream_t st);
