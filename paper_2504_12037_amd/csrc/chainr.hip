@@ -202,16 +202,6 @@ __device__ inline void mm_fwd_bf(const u4v (&tb)[CT][(CT + 1) / 2], const float 
   }
 }
 
-__device__ inline float xlane_max(float v) {
-  v = fmaxf(v, __shfl_xor(v, 16, 64));
-  v = fmaxf(v, __shfl_xor(v, 32, 64));
-  return v;
-}
-__device__ inline float xlane_sum(float v) {
-  v += __shfl_xor(v, 16, 64);
-  v += __shfl_xor(v, 32, 64);
-  return v;
-}
 
 // power-of-two rescale of the step output and the next diagonal:
 // x = out * 2^-e * d; returns e of the lane's sample
@@ -222,7 +212,7 @@ __device__ inline int rescale_next(const f4 (&acc)[CT], const float (&d)[CT][4],
   for (int nt = 0; nt < CT; ++nt)
 #pragma unroll
     for (int r = 0; r < 4; ++r) m = fmaxf(m, acc[nt][r]);
-  const int e = expo32(xlane_max(m));
+  const int e = expo32(rows4_max(m));
   const float sc = pow2neg(e);
 #pragma unroll
   for (int t = 0; t < CT; ++t)
@@ -501,7 +491,7 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
         for (int xt = 0; xt < CT; ++xt)
 #pragma unroll
           for (int r = 0; r < 4; ++r) m += sgn(16 * xt + 4 * lg + r, j) * As[xt][r] * lam[xt][r];
-        m = xlane_sum(m) * gs;
+        m = rows4_sum(m) * gs;
         const float v = row16_sum(m * sp.sigma(wi));
         if (lane == 0) prow[D.nr + st.wre[k]] = v;
       }

@@ -13,6 +13,7 @@
 #include <algorithm>
 
 #include "launch.h"
+#include "wave.h"
 
 namespace tnvan {
 
@@ -659,7 +660,8 @@ __global__ __launch_bounds__(256) void msample_kernel(MSampleArgs a) {
 #pragma unroll
     for (int t = 1; t < NPT; ++t)
       if (t == ti) own = z[t][ri];
-    const float zi = __shfl(own, 16 * gi + ls, 64);
+    // broadcast from row gi: the other rows add zeros (exact)
+    const float zi = rows4_sum(lg == gi ? own : 0.f);
     float ui;
     if (kU) {
       ui = live ? cu : 0.5f;

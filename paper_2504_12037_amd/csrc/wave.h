@@ -33,6 +33,24 @@ __device__ inline float row16_max(float v) {
   return v;
 }
 
+// max / sum over the four rows of a column (lanes l, l ^ 16, l ^ 32, l ^ 48),
+// result in every lane, with the row swaps of CDNA4 (register moves, no LDS):
+// swapping rows 2,3 of one copy with rows 0,1 of another pairs rows (0,2) and
+// (1,3); swapping odd rows of one copy with even rows of another then pairs
+// (0,1) and (2,3).  Both orders of a sum agree, so every lane gets the same bits.
+__device__ inline float rows4_max(float v) {
+  const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  v = fmaxf(__uint_as_float(p[0]), __uint_as_float(p[1]));
+  const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return fmaxf(__uint_as_float(q[0]), __uint_as_float(q[1]));
+}
+__device__ inline float rows4_sum(float v) {
+  const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  v = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+  const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(q[0]) + __uint_as_float(q[1]);
+}
+
 // Exponent e with m * 2^-e in [0.5, 1) for a finite positive m (clamped so
 // that 2^-e stays a normal number); the scale factor 2^-e itself.
 __device__ inline int expo32(float m) {
