@@ -637,7 +637,7 @@ tnvan_status run_sample(tnvan_net *net, const float *uniforms, int8_t *spins, vo
   if (s) return s;
   if ((net->msample || net->mgrad) && sizeof(real) == 4) {
     // parameters repacked for the matrix-core sampler and backward
-    HIPCHK(net->mpack.ensure(std::max<int64_t>(1, net->mpack_total) * sizeof(float)));
+    HIPCHK(net->mpack.ensure((std::max<int64_t>(1, net->mpack_total) + 16) * sizeof(float)));
     HIPCHK(launch_made_pack(net->d_mi.as<MadeInst>(), net->n_inst, net->mpack_max,
                             net->params.as<float>(), net->mpack.as<float>(), net->mpt, st));
   }
@@ -921,7 +921,9 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
     UP(d_sum_off, so)
   }
   UP(d_mi, net->mi)
-  const size_t pb = std::max<int64_t>(1, net->param_total) * sizeof(float);
+  // 16 floats of padding: the kernels read parameter rows four floats at a
+  // time, and the last row of an instance may end inside such a group
+  const size_t pb = (std::max<int64_t>(1, net->param_total) + 16) * sizeof(float);
   if ((e = net->params.ensure(pb)) || (e = net->adam_m.ensure(pb)) || (e = net->adam_v.ensure(pb)) ||
       (e = net->grad.ensure(pb)) || (e = net->step_ctr.ensure(sizeof(int32_t) * n_inst)))
     return fail(e, "parameter buffers");

@@ -684,7 +684,8 @@ __global__ __launch_bounds__(256) void unary_kernel(ChainArgs a, const int32_t *
   const int p0 = blockIdx.y * kUnaryChunk;
   if (p0 >= D.nr || b >= B) return;
   const int p1 = p0 + kUnaryChunk < D.nr ? p0 + kUnaryChunk : D.nr;
-  const int8_t *s = a.spins + a.inst_spin_off[q] + b * D.nw;
+  // the sample's width-set spins as a bit mask, read with uniform indices
+  const SpinBits sb = load_bits_row(a.spins + a.inst_spin_off[q] + b * D.nw, D.nw);
   const float beta = (float)D.beta;
   float *Uq = U + a.u_off[q];
   const ci32 fptr = (ci32)(a.fld_ptr + D.fld_off);
@@ -697,11 +698,12 @@ __global__ __launch_bounds__(256) void unary_kernel(ChainArgs a, const int32_t *
     if (nn <= 4) {
       float t[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) t[k] = cr[4 * p + k] >= 0 ? cj[4 * p + k] * (float)s[cw[4 * p + k]] : 0.f;
+      for (int k = 0; k < 4; ++k) t[k] = cr[4 * p + k] >= 0 ? cj[4 * p + k] * sb.sigma(cw[4 * p + k]) : 0.f;
       f += (t[0] + t[1]) + (t[2] + t[3]);
     } else {
-      for (int k = fptr[p]; k < fptr[p + 1]; ++k)
-        f += a.fld_J[D.fld_nnz_off + k] * (float)s[a.fld_w[D.fld_nnz_off + k]];
+      const ci32 fw = (ci32)(a.fld_w + D.fld_nnz_off);
+      const cf32 fj = (cf32)(a.fld_J + D.fld_nnz_off);
+      for (int k = fptr[p]; k < fptr[p + 1]; ++k) f += fj[k] * sb.sigma(fw[k]);
     }
     const float af = beta * fabsf(f);
     const float sm = __expf(-2.f * af);

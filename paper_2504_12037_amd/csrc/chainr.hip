@@ -67,42 +67,6 @@ __host__ __device__ inline RL rlayout(const ChainLim &L, bool bwd, int sg) {
   return r;
 }
 
-// Width-set spins of one sample as a bit mask (bit w set: s_w = -1), up to
-// 128 spins; the chain kernels read a spin with a uniform index w.
-struct SpinBits {
-  uint32_t m[4];
-  __device__ float sigma(int w) const {
-    const uint32_t word = w < 32 ? m[0] : w < 64 ? m[1] : w < 96 ? m[2] : m[3];
-    return ((word >> (w & 31)) & 1u) ? -1.f : 1.f;
-  }
-};
-
-// spins s[0..nw) (+-1 bytes); a sample past the batch reads as all +1
-__device__ inline SpinBits load_bits(const int8_t *s, int nw, bool valid) {
-  SpinBits b;
-  b.m[0] = b.m[1] = b.m[2] = b.m[3] = 0u;
-  if (!valid) return b;
-  for (int w0 = 0; w0 < nw; w0 += 4) {
-    uint32_t v = 0u;
-    if ((nw & 3) == 0) {
-      v = *reinterpret_cast<const uint32_t *>(s + w0);
-    } else {
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (w0 + k < nw) v |= (uint32_t)(uint8_t)s[w0 + k] << (8 * k);
-    }
-    // sign bit of each byte
-    const uint32_t nib = ((v >> 7) & 1u) | ((v >> 14) & 2u) | ((v >> 21) & 4u) | ((v >> 28) & 8u);
-    const uint32_t sh = nib << (w0 & 31);
-    const int wd = w0 >> 5;
-    b.m[0] |= wd == 0 ? sh : 0u;
-    b.m[1] |= wd == 1 ? sh : 0u;
-    b.m[2] |= wd == 2 ? sh : 0u;
-    b.m[3] |= wd == 3 ? sh : 0u;
-  }
-  return b;
-}
-
 // d[t][r] = prod_j phi_j(bit j of x) for x = 16 t + 4 lg + r < K, else 0
 template <int CT, int GR>
 __device__ inline void make_diag(const float (&p0)[GR], const float (&p1)[GR], int K, int lg,

@@ -390,10 +390,20 @@ __global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t b = (int64_t)blockIdx.x * blockDim.x + tid; b < mi.B;
        b += (int64_t)gridDim.x * blockDim.x) {
-    const int8_t *s = a.spins + mi.spin_off + b * mi.n;
     double e1 = 0.0;
-    for (int k = 0; k < D.n_ww; ++k) e1 -= wJ[k] * (double)s[wa[k]] * (double)s[wb[k]];
-    for (int k = 0; k < mi.n; ++k) e1 -= hW[k] * (double)s[k];
+    if (mi.n <= 128) {
+      // spins as a bit mask read with uniform indices; the +-1 products are exact
+      const SpinBits sb = load_bits_row(a.spins + mi.spin_off + b * mi.n, mi.n);
+      for (int k = 0; k < D.n_ww; ++k) {
+        const double j = wJ[k];
+        e1 -= sb.sigma(wa[k]) * sb.sigma(wb[k]) > 0.f ? j : -j;
+      }
+      for (int k = 0; k < mi.n; ++k) e1 -= sb.sigma(k) > 0.f ? hW[k] : -hW[k];
+    } else {
+      const int8_t *s = a.spins + mi.spin_off + b * mi.n;
+      for (int k = 0; k < D.n_ww; ++k) e1 -= wJ[k] * (double)s[wa[k]] * (double)s[wb[k]];
+      for (int k = 0; k < mi.n; ++k) e1 -= hW[k] * (double)s[k];
+    }
     const int64_t g = mi.sample_off + b;
     const double et = e1 - a.logz[g] / beta;
     const double lqb = (double)a.logq[g] / beta;
@@ -758,7 +768,8 @@ template <int NPT, int HT>
 __global__ __launch_bounds__(256, 2) void mgrad_kernel(MGradArgs a) {
   typedef float f4 __attribute__((ext_vector_type(4)));
   constexpr int QT = HT < kMgPass ? HT : kMgPass;   // hidden tiles per pass
-  constexpr int B1 = HT < 8 ? HT : 8;               // tiles per batch of weight loads
+  constexpr int BM = NPT >= 4 ? 4 : 8;
+  constexpr int B1 = HT < BM ? HT : BM;             // tiles per batch of weight loads
   extern __shared__ __align__(16) char smem[];
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63, ls = lane & 15, lg = lane >> 4;
@@ -779,33 +790,63 @@ __global__ __launch_bounds__(256, 2) void mgrad_kernel(MGradArgs a) {
   const float *W2T = a.pack + mi.pack_off + msample_floats(n, NPT);
   const float *W1m = W2T + (int64_t)Hs * n, *W2m = W1m + (int64_t)Hs * n;
   const int nm1 = n > 1 ? n - 1 : 1;
-  // four consecutive parameters p[0..3] (rows are multiples of 4 floats long)
-  auto ld4 = [](const float *p, bool ok) {
-    return ok ? *reinterpret_cast<const f4 *>(p) : f4{0.f, 0.f, 0.f, 0.f};
+  // four consecutive parameters p[0..3], zero unless ok; the load itself is
+  // unconditional (from the array base when !ok, the buffers are padded),
+  // because a load under a lane condition is waited for at its branch join
+  auto ld4 = [](const float *base, const float *p, bool ok) {
+    const f4 v = *reinterpret_cast<const f4 *>(ok ? p : base);
+    return ok ? v : f4{0.f, 0.f, 0.f, 0.f};
   };
-  // rows of the wave's 16 samples
+  // rows of the wave's 16 samples; every load below is unconditional, at an
+  // in-bounds address, so that the loads of a stage are all in flight
+  // together (a conditional load is waited for at its branch join)
   const int64_t sb = bw + 16 * wave + ls;
   const bool valid = sb < mi.B;
-  const int8_t *spn = a.spins + mi.spin_off + (valid ? sb : 0) * n;
+  const int8_t *spn = a.spins + mi.spin_off + (valid ? sb : 0) * n;   // row 0 past the batch
   float sp[NPT][4];
+  if ((n & 3) == 0 && (reinterpret_cast<uintptr_t>(a.spins + mi.spin_off) & 3) == 0) {
+    uint32_t wv[NPT];
 #pragma unroll
-  for (int t = 0; t < NPT; ++t)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int pos = 16 * t + 4 * lg + r;
-      sp[t][r] = (valid && pos < n) ? (float)spn[pos] : 0.f;
+    for (int t = 0; t < NPT; ++t) {
+      const int p0 = 16 * t + 4 * lg;
+      wv[t] = *reinterpret_cast<const uint32_t *>(spn + (p0 < n ? p0 : 0));
     }
+#pragma unroll
+    for (int t = 0; t < NPT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int pos = 16 * t + 4 * lg + r;
+        sp[t][r] = (valid && pos < n) ? (float)(int8_t)(wv[t] >> (8 * r)) : 0.f;
+      }
+  } else {
+    int8_t bv[NPT][4];
+#pragma unroll
+    for (int t = 0; t < NPT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int pos = 16 * t + 4 * lg + r;
+        bv[t][r] = spn[pos < n ? pos : 0];
+      }
+#pragma unroll
+    for (int t = 0; t < NPT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int pos = 16 * t + 4 * lg + r;
+        sp[t][r] = (valid && pos < n) ? (float)bv[t][r] : 0.f;
+      }
+  }
   const float wt = valid ? (float)((a.f[mi.sample_off + sb] - a.stats[4 * q]) / (double)mi.B) : 0.f;
   float h[HT][4];
 #pragma unroll
   for (int h0 = 0; h0 < HT; h0 += B1) {
-    f4 wl[B1][NPT];
+    f4 wl[B1][NPT], bl[B1];
 #pragma unroll
     for (int j = 0; j < B1; ++j) {
       const int ka = 16 * (h0 + j) + ls;
 #pragma unroll
       for (int t = 0; t < NPT; ++t)
-        wl[j][t] = ld4(W1m + (int64_t)ka * n + 16 * t + 4 * lg, ka < H && 16 * t + 4 * lg < n);
+        wl[j][t] = ld4(W1m, W1m + (int64_t)ka * n + 16 * t + 4 * lg, ka < H && 16 * t + 4 * lg < n);
+      bl[j] = ld4(b1, b1 + 16 * (h0 + j) + 4 * lg, 16 * (h0 + j) + 4 * lg < H);
     }
 #pragma unroll
     for (int j = 0; j < B1; ++j) {
@@ -814,7 +855,7 @@ __global__ __launch_bounds__(256, 2) void mgrad_kernel(MGradArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int k = 16 * ht + 4 * lg + r;
-        acc[r] = k < H ? b1[k] : 0.f;
+        acc[r] = k < H ? bl[j][r] : 0.f;
       }
 #pragma unroll
       for (int t = 0; t < NPT; ++t)
@@ -825,42 +866,61 @@ __global__ __launch_bounds__(256, 2) void mgrad_kernel(MGradArgs a) {
       for (int r = 0; r < 4; ++r) h[ht][r] = (16 * ht + 4 * lg + r < H) ? ftanh(acc[r]) : 0.f;
     }
   }
-  float dl[NPT][4];
+  // logits: the NPT position tiles as independent product chains, their
+  // weights loaded in batches of B1 hidden tiles
+  f4 z[NPT];
+  {
+    f4 w0[NPT][NPT], bz[NPT];
 #pragma unroll
-  for (int pt = 0; pt < NPT; ++pt) {
-    f4 z;
+    for (int pt = 0; pt < NPT; ++pt) {
+      const int pa = 16 * pt + ls;
+      bz[pt] = ld4(b2, b2 + 16 * pt + 4 * lg, 16 * pt + 4 * lg < n);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int pos = 16 * pt + 4 * lg + r;
-      z[r] = pos < n ? b2[pos] : 0.f;
+      for (int t = 0; t < NPT; ++t)
+        w0[pt][t] = ld4(W0, W0 + (int64_t)pa * n + 16 * t + 4 * lg, pa < n && 16 * t + 4 * lg < n);
     }
-    const int pa = 16 * pt + ls;
-    f4 wz[HT];
 #pragma unroll
-    for (int ht = 0; ht < HT; ++ht)
-      wz[ht] = ld4(W2m + (int64_t)pa * Hs + 16 * ht + 4 * lg, pa < n && 16 * ht + 4 * lg < H);
+    for (int pt = 0; pt < NPT; ++pt)
 #pragma unroll
-    for (int ht = 0; ht < HT; ++ht)
+      for (int r = 0; r < 4; ++r) z[pt][r] = 16 * pt + 4 * lg + r < n ? bz[pt][r] : 0.f;
+#pragma unroll
+    for (int h0 = 0; h0 < HT; h0 += B1) {
+      f4 wz[NPT][B1];
+#pragma unroll
+      for (int pt = 0; pt < NPT; ++pt) {
+        const int pa = 16 * pt + ls;
+#pragma unroll
+        for (int j = 0; j < B1; ++j)
+          wz[pt][j] = ld4(W2m, W2m + (int64_t)pa * Hs + 16 * (h0 + j) + 4 * lg, pa < n && 16 * (h0 + j) + 4 * lg < H);
+      }
+#pragma unroll
+      for (int j = 0; j < B1; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int pt = 0; pt < NPT; ++pt)
+            z[pt] = __builtin_amdgcn_mfma_f32_16x16x4f32(wz[pt][j][r], h[h0 + j][r], z[pt], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < NPT; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        z = __builtin_amdgcn_mfma_f32_16x16x4f32(wz[ht][r], h[ht][r], z, 0, 0, 0);
 #pragma unroll
-    for (int t = 0; t < NPT; ++t) {
-      const f4 w0 = ld4(W0 + (int64_t)pa * n + 16 * t + 4 * lg, pa < n && 16 * t + 4 * lg < n);
+        for (int pt = 0; pt < NPT; ++pt) {
+          const int j = 16 * t + 4 * lg + r, pa = 16 * pt + ls;
+          const float wv = j < pa ? w0[pt][t][r] : 0.f;
+          z[pt] = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, sp[t][r], z[pt], 0, 0, 0);
+        }
+  }
+  float dl[NPT][4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int j = 16 * t + 4 * lg + r;
-        const float wv = j < pa ? w0[r] : 0.f;
-        z = __builtin_amdgcn_mfma_f32_16x16x4f32(wv, sp[t][r], z, 0, 0, 0);
-      }
-    }
+  for (int pt = 0; pt < NPT; ++pt)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int pos = 16 * pt + 4 * lg + r;
       const float s1 = sp[pt][r];
-      dl[pt][r] = pos < n ? wt * ((1.f + s1) * 0.5f - fsigmoid(z[r])) : 0.f;
+      dl[pt][r] = pos < n ? wt * ((1.f + s1) * 0.5f - fsigmoid(z[pt][r])) : 0.f;
     }
-  }
   const int srow = 16 * wave + ls;
 #pragma unroll
   for (int pt = 0; pt < NPT; ++pt) {
@@ -884,7 +944,7 @@ __global__ __launch_bounds__(256, 2) void mgrad_kernel(MGradArgs a) {
         const int ka = hbase + 16 * j + ls;
 #pragma unroll
         for (int pt = 0; pt < NPT; ++pt)
-          wt2[j][pt] = ld4(W2T + (int64_t)ka * n + 16 * pt + 4 * lg, ka < H && 16 * pt + 4 * lg < n);
+          wt2[j][pt] = ld4(W2T, W2T + (int64_t)ka * n + 16 * pt + 4 * lg, ka < H && 16 * pt + 4 * lg < n);
       }
       if (pass > 0) __syncthreads();   // the previous pass's products are done
 #pragma unroll
@@ -927,13 +987,15 @@ __global__ __launch_bounds__(256, 2) void mgrad_kernel(MGradArgs a) {
         Ab = dlb; lda = Lm.ldn; ai = 16 * pt;
         Bb = sfb; ldb = Lm.ldn; bj = 16 * jt;
       }
-      f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+      // two accumulators (even and odd sample chunks) halve the dependent chain
+      f4 acc2[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
       for (int kc = 0; kc < 16; ++kc) {
         const int s = 4 * kc + lg;
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(Ab[s * lda + ai + ls], Bb[s * ldb + bj + ls], acc,
-                                                   0, 0, 0);
+        acc2[kc & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ab[s * lda + ai + ls], Bb[s * ldb + bj + ls],
+                                                            acc2[kc & 1], 0, 0, 0);
       }
+      const f4 acc = acc2[0] + acc2[1];
       // lane holds rows ai + 4 lg + r, column bj + ls of the staged blocks
 #pragma unroll
       for (int r = 0; r < 4; ++r) {

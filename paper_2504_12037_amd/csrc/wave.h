@@ -60,4 +60,74 @@ __device__ inline int expo32(float m) {
 }
 __device__ inline float pow2neg(int e) { return __uint_as_float((uint32_t)(127 - e) << 23); }
 
+// Width-set spins of one sample as a bit mask (bit w set: s_w = -1), up to
+// 128 spins; the chain kernels read a spin with a uniform index w.
+struct SpinBits {
+  uint32_t m[4];
+  __device__ float sigma(int w) const {
+    const uint32_t word = w < 32 ? m[0] : w < 64 ? m[1] : w < 96 ? m[2] : m[3];
+    return ((word >> (w & 31)) & 1u) ? -1.f : 1.f;
+  }
+};
+
+// spins s[0..nw) (+-1 bytes); a sample past the batch reads as all +1
+__device__ inline SpinBits load_bits(const int8_t *s, int nw, bool valid) {
+  SpinBits b;
+  b.m[0] = b.m[1] = b.m[2] = b.m[3] = 0u;
+  if (!valid) return b;
+  for (int w0 = 0; w0 < nw; w0 += 4) {
+    uint32_t v = 0u;
+    if ((nw & 3) == 0 && (reinterpret_cast<uintptr_t>(s) & 3) == 0) {
+      v = *reinterpret_cast<const uint32_t *>(s + w0);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (w0 + k < nw) v |= (uint32_t)(uint8_t)s[w0 + k] << (8 * k);
+    }
+    // sign bit of each byte
+    const uint32_t nib = ((v >> 7) & 1u) | ((v >> 14) & 2u) | ((v >> 21) & 4u) | ((v >> 28) & 8u);
+    const uint32_t sh = nib << (w0 & 31);
+    const int wd = w0 >> 5;
+    b.m[0] |= wd == 0 ? sh : 0u;
+    b.m[1] |= wd == 1 ? sh : 0u;
+    b.m[2] |= wd == 2 ? sh : 0u;
+    b.m[3] |= wd == 3 ? sh : 0u;
+  }
+  return b;
+}
+
+// The same mask from 16-byte loads, all issued before any is used (a
+// per-lane caller would otherwise wait for each load in turn): rows of nw
+// bytes, nw a multiple of 16 and at most 16 NL, 16-byte aligned.  Loads past
+// the row reread its start (in bounds) and are ignored.
+template <int NL>
+__device__ inline SpinBits load_bits16(const int8_t *s, int nw) {
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  u4 v[NL];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) v[k] = *reinterpret_cast<const u4 *>(s + (16 * k < nw ? 16 * k : 0));
+  SpinBits b;
+  b.m[0] = b.m[1] = b.m[2] = b.m[3] = 0u;
+#pragma unroll
+  for (int k = 0; k < NL; ++k)
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const uint32_t x = v[k][d];
+      const uint32_t nib = ((x >> 7) & 1u) | ((x >> 14) & 2u) | ((x >> 21) & 4u) | ((x >> 28) & 8u);
+      const int w0 = 16 * k + 4 * d;
+      if (16 * k < nw) b.m[w0 >> 5] |= nib << (w0 & 31);
+    }
+  return b;
+}
+
+// a sample's spins (nw <= 128) by the fastest form its row allows
+__device__ inline SpinBits load_bits_row(const int8_t *s, int nw) {
+  if ((nw & 15) == 0 && (reinterpret_cast<uintptr_t>(s) & 15) == 0) {
+    if (nw <= 32) return load_bits16<2>(s, nw);
+    if (nw <= 64) return load_bits16<4>(s, nw);
+    return load_bits16<8>(s, nw);
+  }
+  return load_bits(s, nw, true);
+}
+
 }  // namespace tnvan
