@@ -5,13 +5,14 @@ at beta in {0.5, 1.0, 2.0} (three instances in one net), width set = columns
 6 and 11 (32 spins), remainder = strips 16x5 / 16x4 / 16x5 contracted row by
 row, masked network of hidden width 256, 8192 samples per instance.
 
-One step is one pass of the whole hot path over one batch: ancestral
-sampling (Philox uniforms), the batched conditional log Z, E_1 / F_q / the
-REINFORCE weights in FP64, the log-prob pass and the REINFORCE gradient, the
-Adam update (all inside tnvan_free_energy_step), and the adjoint
-(tnvan_logz_backward with g_b = 1/B, giving magnetisations, correlations and
-internal energy) on the step's samples.  `value` is samples per second of
-that step (3 x 8192 samples per step), inputs resident in HBM.
+One step is one pass of the whole hot path over one batch, in one call
+(tnvan_free_energy_step_adjoint): ancestral sampling (Philox uniforms), the
+batched conditional log Z together with its adjoint (g_b = 1/B, giving
+magnetisations, correlations and internal energy; one contraction, whose
+forward pass yields log Z), E_1 / F_q / the REINFORCE weights in FP64, the
+log-prob pass and the REINFORCE gradient, and the Adam update.  `value` is
+samples per second of that step (3 x 8192 samples per step), inputs resident
+in HBM.
 
 Also reported: the forward + adjoint alone for the FP32 and the plain FP64
 paths, the error of logZ against the oracle on sampled outputs, a roofline
@@ -43,7 +44,9 @@ NW = 32
 #   two 16x5 strips: 2 * (15 * (4*5*32 + 32*2) + 32) = 21184
 #   one 16x4 strip:       15 * (4*4*16 + 16*2) + 16  =  4336
 # forward 25520; the adjoint is twice the forward (reverse sweep plus the
-# per-step correlation sums), so forward + adjoint = 76560.
+# per-step correlation sums), so forward + adjoint = 76560.  The adjoint
+# kernels run the forward pass too and it yields log Z, so their count is
+# forward + adjoint.
 FWD_STRIP5 = 21184
 FWD_STRIP4 = 4336
 FWD_FLOPS = FWD_STRIP5 + FWD_STRIP4
@@ -56,13 +59,13 @@ SAMPLE_FLOPS = 2 * HIDDEN * NW + NW * NW
 # all three instances)
 KERNEL_FLOPS = {
     "chain_fwd_2": FWD_STRIP5, "chain_fwd_1": FWD_STRIP4,
-    "chain_bwd_2": 2 * FWD_STRIP5, "chain_bwd_1": 2 * FWD_STRIP4,
+    "chain_bwd_2": 3 * FWD_STRIP5, "chain_bwd_1": 3 * FWD_STRIP4,
     "made_grad": MADE_GRAD, "sample": SAMPLE_FLOPS,
 }
 KERNEL_NAMES = {
     "chain_fwd_2": "rchain_fwd_kernel<false, 2, 2>", "chain_fwd_1": "rchain_fwd_kernel<false, 1, 2>",
     "chain_bwd_2": "rchain_bwd_kernel<2>", "chain_bwd_1": "rchain_bwd_kernel<1>",
-    "made_grad": "mgrad_kernel<2, 16>", "sample": "msample_kernel<2>",
+    "made_grad": "mgrad_kernel<2, 16>", "sample": "msample_kernel<2, false>",
 }
 PEAK_FP32 = 157.3e12       # MI355X FP32 (vector and 16x16x4 matrix), published
 PEAK_FP64 = 78.6e12
@@ -169,6 +172,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    # eager launches, with the library's HIP events around each kernel (the
+    # dominant kernel's live timing)
     net = Net(insts, precision=args.precision, seed=2024, flags=Net.FLAG_PROFILE)
     for k in range(nI):
         net.set_params(k, torch.from_numpy(S.made_init(nw, HIDDEN, 7 + k)))
@@ -180,8 +185,7 @@ def main():
     db = torch.empty(nI, dtype=torch.float64, device="cuda")
 
     def step():
-        net.free_energy_step(counts, 1e-3, stats=stats, spins_out=spins)
-        net.backward(spins, g, counts, out=(dh, dJ, db))
+        net.free_energy_step(counts, 1e-3, stats=stats, spins_out=spins, adjoint=(g, dh, dJ, db))
 
     for _ in range(args.warmup):
         step()
@@ -211,7 +215,7 @@ def main():
     sp_fix = torch.from_numpy(S.uniform_spins(nI * B, nw, 102)).cuda().reshape(-1)
     logz = torch.empty(nI * B, dtype=torch.float64, device="cuda")
     out = (dh, dJ, db)
-    fa = lambda: (net.logz(sp_fix, counts, out=logz), net.backward(sp_fix, g, counts, out=out))
+    fa = lambda: net.logz_and_backward(sp_fix, g, counts, logz_out=logz, out=out)
     for _ in range(3):
         fa()
     t_fa = event_time(fa, max(5, args.steps), st)
@@ -219,14 +223,16 @@ def main():
     t_fwd = event_time(lambda: net.logz(sp_fix, counts, out=logz), max(5, args.steps), st)
     net64 = Net(insts, precision="fp64")
     logz64 = torch.empty_like(logz)
-    fa64 = lambda: (net64.logz(sp_fix, counts, out=logz64),
-                    net64.backward(sp_fix, g, counts, out=out))
+    fa64 = lambda: net64.logz_and_backward(sp_fix, g, counts, logz_out=logz64, out=out)
     for _ in range(3):
         fa64()
     t_fa64 = event_time(fa64, max(5, args.steps), st)
     # error of logZ on sampled outputs against the oracle, and vs FP64 path
-    lz = net.logz(sp_fix, counts).cpu().numpy()
-    lz64 = net64.logz(sp_fix, counts).cpu().numpy()
+    # (the logZ that the forward + adjoint call produced)
+    fa()
+    fa64()
+    lz = logz.cpu().numpy()
+    lz64 = logz64.cpu().numpy()
     spn = sp_fix.cpu().numpy().reshape(nI * B, nw)
     idx = np.random.default_rng(1).choice(B, 64, replace=False)
     err = 0.0

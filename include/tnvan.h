@@ -181,6 +181,18 @@ tnvan_status tnvan_logz_backward(tnvan_net *net, const int64_t *n_samples,
                                  double *dh, double *dJ, double *dbeta,
                                  void *stream);
 
+/* tnvan_logz_batch and tnvan_logz_backward of the same spins in one call,
+ * with the same arguments and results (logz as tnvan_logz_batch writes it).
+ * On FP32 nets whose every instance runs the register-resident chain
+ * kernels, logZ is the adjoint's own forward contraction (the forward
+ * kernel's arithmetic, step for step), so the contraction runs once;
+ * otherwise the two calls are made in turn.
+ *   logz dev double out [sum n_samples]; the other arguments as above */
+tnvan_status tnvan_logz_and_backward(tnvan_net *net, const int64_t *n_samples,
+                                     const int8_t *spins, const double *grad_logz,
+                                     double *logz, double *dh, double *dJ,
+                                     double *dbeta, void *stream);
+
 /* One training iteration of Algorithm 1 for every instance: sample with the
  * Philox stream at the current step counter, contract, form
  * f_b = E_1 - logZ_R/beta + ln q/beta, F_q = mean f (Eq. 9), REINFORCE
@@ -193,6 +205,18 @@ tnvan_status tnvan_logz_backward(tnvan_net *net, const int64_t *n_samples,
 tnvan_status tnvan_free_energy_step(tnvan_net *net, const int64_t *n_samples,
                                     float lr, double *stats, int8_t *spins_out,
                                     void *stream);
+
+/* tnvan_free_energy_step followed by tnvan_logz_backward of the spins it
+ * sampled, with per-sample weights grad_logz, in one call (one recorded
+ * graph under TNVAN_FLAG_GRAPH).  Where tnvan_logz_and_backward contracts
+ * once, the step's logZ is taken from the adjoint's forward pass.  The
+ * adjoint outputs (dh, dJ, dbeta) are those of tnvan_logz_backward; the
+ * step's results are those of tnvan_free_energy_step.
+ *   grad_logz dev double [sum n_samples] (g_b, set before the call) */
+tnvan_status tnvan_free_energy_step_adjoint(tnvan_net *net, const int64_t *n_samples,
+                                            float lr, double *stats, int8_t *spins_out,
+                                            const double *grad_logz, double *dh,
+                                            double *dJ, double *dbeta, void *stream);
 
 /* Per-instance program statistics of the compiled order (host values):
  *   info[0] steps, [1] largest message scope, [2] arena entries per sample,

@@ -153,13 +153,49 @@ class Net:
                                                   _stream()))
         return dh, dJ[:sum(self.ne)], db
 
+    def _adjoint_out(self, out):
+        if out is not None:
+            return out
+        return (torch.empty(sum(self.n), device="cuda", dtype=torch.float64),
+                torch.empty(max(sum(self.ne), 1), device="cuda", dtype=torch.float64),
+                torch.empty(len(self.instances), device="cuda", dtype=torch.float64))
+
+    def logz_and_backward(self, spins: torch.Tensor, grad: torch.Tensor, n_samples,
+                          logz_out: torch.Tensor = None, out=None):
+        """logz(spins) and backward(spins, grad) in one call (one contraction
+        where the net allows it); returns (logz, dh, dJ, dbeta)."""
+        arr, counts = self._counts(n_samples)
+        spins = spins.contiguous()
+        assert spins.dtype == torch.int8
+        assert spins.numel() == sum(b * w for b, w in zip(counts, self.nw))
+        grad = grad.to(torch.float64).contiguous()
+        assert grad.numel() == sum(counts)
+        if logz_out is None:
+            logz_out = torch.empty(max(sum(counts), 1), device="cuda", dtype=torch.float64)
+        dh, dJ, db = self._adjoint_out(out)
+        _lib.check(_lib.lib().tnvan_logz_and_backward(self._h, arr, _ptr(spins), _ptr(grad),
+                                                      _ptr(logz_out), _ptr(dh), _ptr(dJ),
+                                                      _ptr(db), _stream()))
+        return logz_out[:sum(counts)], dh, dJ[:sum(self.ne)], db
+
     def free_energy_step(self, n_samples, lr: float, stats: torch.Tensor = None,
-                         spins_out: torch.Tensor = None):
+                         spins_out: torch.Tensor = None, adjoint=None):
+        """One training step.  With adjoint=(grad, dh, dJ, dbeta) (device
+        float64 tensors; grad per sample, set before the call) the adjoint of
+        the sampled spins is computed in the same call."""
         arr, counts = self._counts(n_samples)
         if stats is None:
             stats = torch.empty(len(self.instances), 4, device="cuda", dtype=torch.float64)
-        _lib.check(_lib.lib().tnvan_free_energy_step(self._h, arr, float(lr), _ptr(stats),
-                                                     _ptr(spins_out), _stream()))
+        if adjoint is None:
+            _lib.check(_lib.lib().tnvan_free_energy_step(self._h, arr, float(lr), _ptr(stats),
+                                                         _ptr(spins_out), _stream()))
+        else:
+            grad, dh, dJ, db = adjoint
+            assert grad.dtype == torch.float64 and grad.is_contiguous()
+            assert grad.numel() == sum(counts)
+            _lib.check(_lib.lib().tnvan_free_energy_step_adjoint(
+                self._h, arr, float(lr), _ptr(stats), _ptr(spins_out), _ptr(grad), _ptr(dh),
+                _ptr(dJ), _ptr(db), _stream()))
         return stats, spins_out
 
 

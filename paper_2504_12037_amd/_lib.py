@@ -27,7 +27,8 @@ EXPORTS = ["tnvan_build_network", "tnvan_free_network", "tnvan_last_error",
            "tnvan_param_count", "tnvan_set_params", "tnvan_get_params",
            "tnvan_get_state",
            "tnvan_sample", "tnvan_logz_batch", "tnvan_logz_backward",
-           "tnvan_free_energy_step", "tnvan_program_info", "tnvan_plan",
+           "tnvan_logz_and_backward", "tnvan_free_energy_step",
+           "tnvan_free_energy_step_adjoint", "tnvan_program_info", "tnvan_plan",
            "tnvan_kernel_time"]
 
 
@@ -77,7 +78,9 @@ def lib():
     L.tnvan_sample.argtypes = [vp, vp, vp, vp, vp, vp]
     L.tnvan_logz_batch.argtypes = [vp, vp, vp, vp, vp]
     L.tnvan_logz_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.tnvan_logz_and_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.tnvan_free_energy_step.argtypes = [vp, vp, C.c_float, vp, vp, vp]
+    L.tnvan_free_energy_step_adjoint.argtypes = [vp, vp, C.c_float, vp, vp, vp, vp, vp, vp, vp]
     L.tnvan_program_info.argtypes = [vp, i32, vp]
     L.tnvan_plan.argtypes = [vp, i32, vp]
     L.tnvan_kernel_time.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(i64)]

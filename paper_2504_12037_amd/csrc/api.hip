@@ -137,6 +137,9 @@ struct tnvan_net {
     double *stats = nullptr;
     int8_t *spins = nullptr;
     float lr = 0.f;
+    bool adj = false;
+    const double *grad = nullptr;
+    double *dh = nullptr, *dJ = nullptr, *dbeta = nullptr;
     uint64_t gen = 0;
   } step_graph;
   // kernel timing (TNVAN_FLAG_PROFILE): event pairs recorded since the last read
@@ -509,9 +512,21 @@ tnvan_status run_logz(tnvan_net *net, const int8_t *spins, double *logz, hipStre
   return TNVAN_OK;
 }
 
+// logZ from the adjoint's own forward pass: FP32 nets whose every instance
+// runs the register-resident chain kernels (their adjoint forward pass is the
+// forward kernel's arithmetic, so logz is the same as tnvan_logz_batch's)
+bool logz_with_adjoint(const tnvan_net *net) {
+  if (net->precision != TNVAN_FP32 || !net->rfwd || !net->rbwd) return false;
+  for (int q = 0; q < net->n_inst; ++q)
+    if (!net->use_chain[q]) return false;
+  return true;
+}
+
+// the adjoint; with logz (only where logz_with_adjoint holds) also logZ
 template <typename real>
 tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *grad,
-                          double *dh, double *dJ, double *dbeta, hipStream_t st) {
+                          double *dh, double *dJ, double *dbeta, hipStream_t st,
+                          double *logz = nullptr) {
   tnvan_status s = ensure_tiles(net, net->tc_bwd, net->S_bwd, true);
   if (s) return s;
   TileCache &tc = net->tc_bwd;
@@ -548,6 +563,12 @@ tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *gra
         ProfScope ps(net, TNVAN_KERNEL_CHAIN_BWD_1 + gi, st);
         HIPCHK(launch_rchain(c, true, st));
       }
+      if (logz)
+        HIPCHK(launch_chain_sum(net->inst.as<InstDesc>(), net->cinst.as<ChainInst>(),
+                                net->chain_list.as<int32_t>(), net->n_chain_insts,
+                                net->d_B.as<int64_t>(), net->d_sample_off.as<int64_t>(),
+                                net->cpart_off.as<int64_t>(), net->cpart.as<double>(),
+                                net->f_off.as<int64_t>(), net->fabp.as<double>(), logz, st));
     } else {
       HIPCHK(launch_chain(c, true, st));
     }
@@ -677,9 +698,15 @@ tnvan_status run_sample(tnvan_net *net, const float *uniforms, int8_t *spins, vo
   return TNVAN_OK;
 }
 
+// outputs of the adjoint of the sampled batch (tnvan_free_energy_step_adjoint)
+struct StepAdjoint {
+  const double *grad = nullptr;
+  double *dh = nullptr, *dJ = nullptr, *dbeta = nullptr;
+};
+
 template <typename real>
 tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out,
-                      hipStream_t st) {
+                      hipStream_t st, const StepAdjoint *adj = nullptr) {
   const int64_t B = net->B_total;
   HIPCHK(net->w_spins.ensure(std::max<int64_t>(1, net->spin_total)));
   HIPCHK(net->w_logz.ensure(std::max<int64_t>(1, B) * 8));
@@ -688,7 +715,14 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
   int8_t *spins = spins_out ? spins_out : net->w_spins.as<int8_t>();
   tnvan_status s = run_sample<real>(net, nullptr, spins, net->w_logq.p, st);
   if (s) return s;
-  s = run_logz<real>(net, spins, net->w_logz.as<double>(), st);
+  // with the adjoint requested, logZ comes from its forward pass when the
+  // net allows it (one contraction instead of two), else it follows the step
+  const bool adj_logz = adj && logz_with_adjoint(net);
+  if (adj_logz)
+    s = run_backward<real>(net, spins, adj->grad, adj->dh, adj->dJ, adj->dbeta, st,
+                           net->w_logz.as<double>());
+  else
+    s = run_logz<real>(net, spins, net->w_logz.as<double>(), st);
   if (s) return s;
   // f_b and the batch statistics of every instance (Eq. 9)
   int64_t Bmax = 1;
@@ -793,6 +827,7 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
   int64_t max_pc = 1;
   for (auto pc : net->param_count) max_pc = std::max(max_pc, pc);
   HIPCHK(launch_adam_step(o, net->n_inst, max_pc, st));
+  if (adj && !adj_logz) return run_backward<real>(net, spins, adj->grad, adj->dh, adj->dJ, adj->dbeta, st);
   return TNVAN_OK;
 }
 
@@ -1131,22 +1166,31 @@ tnvan_status tnvan_logz_backward(tnvan_net *net, const int64_t *n_samples, const
   return run_backward<float>(net, spins, grad, dh, dJ, dbeta, st);
 }
 
-tnvan_status tnvan_free_energy_step(tnvan_net *net, const int64_t *n_samples, float lr,
-                                    double *stats, int8_t *spins_out, void *stream) {
+namespace {
+
+// one training step, eagerly or (TNVAN_FLAG_GRAPH) replayed from the graph
+// recorded for the same batch shape, outputs and adjoint buffers
+tnvan_status step_entry(tnvan_net *net, const int64_t *n_samples, float lr, double *stats,
+                        int8_t *spins_out, const StepAdjoint *adj, void *stream) {
   if (tnvan_status s = check_net(net)) return s;
   if (!stats) return set_err(TNVAN_E_INVALID, "stats is required");
   for (auto &D : net->P.insts)
     if (!(D.beta > 0)) return set_err(TNVAN_E_INVALID, "free_energy_step needs beta > 0");
   if (tnvan_status s = set_batch(net, n_samples)) return s;
+  if (adj && (!adj->dh || !adj->dJ || !adj->dbeta || (net->B_total > 0 && !adj->grad)))
+    return set_err(TNVAN_E_INVALID, "grad_logz, dh, dJ and dbeta are required");
   hipStream_t st = static_cast<hipStream_t>(stream);
   auto eager = [&](hipStream_t s2) {
-    return net->precision == TNVAN_FP64 ? run_step<double>(net, lr, stats, spins_out, s2)
-                                        : run_step<float>(net, lr, stats, spins_out, s2);
+    return net->precision == TNVAN_FP64 ? run_step<double>(net, lr, stats, spins_out, s2, adj)
+                                        : run_step<float>(net, lr, stats, spins_out, s2, adj);
   };
   if (!net->use_graph) return eager(st);
   auto &G = net->step_graph;
+  const StepAdjoint none{};
+  const StepAdjoint &A = adj ? *adj : none;
   if (G.exec && G.key == net->nkey && G.stats == stats && G.spins == spins_out && G.lr == lr &&
-      G.gen == g_buf_gen.load()) {
+      G.adj == (adj != nullptr) && G.grad == A.grad && G.dh == A.dh && G.dJ == A.dJ &&
+      G.dbeta == A.dbeta && G.gen == g_buf_gen.load()) {
     HIPCHK(hipGraphLaunch(G.exec, st));
     return TNVAN_OK;
   }
@@ -1181,8 +1225,50 @@ tnvan_status tnvan_free_energy_step(tnvan_net *net, const int64_t *n_samples, fl
   G.stats = stats;
   G.spins = spins_out;
   G.lr = lr;
+  G.adj = adj != nullptr;
+  G.grad = A.grad;
+  G.dh = A.dh;
+  G.dJ = A.dJ;
+  G.dbeta = A.dbeta;
   G.gen = gen;
   return TNVAN_OK;
+}
+
+}  // namespace
+
+tnvan_status tnvan_free_energy_step(tnvan_net *net, const int64_t *n_samples, float lr,
+                                    double *stats, int8_t *spins_out, void *stream) {
+  return step_entry(net, n_samples, lr, stats, spins_out, nullptr, stream);
+}
+
+tnvan_status tnvan_free_energy_step_adjoint(tnvan_net *net, const int64_t *n_samples, float lr,
+                                            double *stats, int8_t *spins_out,
+                                            const double *grad_logz, double *dh, double *dJ,
+                                            double *dbeta, void *stream) {
+  StepAdjoint adj;
+  adj.grad = grad_logz;
+  adj.dh = dh;
+  adj.dJ = dJ;
+  adj.dbeta = dbeta;
+  return step_entry(net, n_samples, lr, stats, spins_out, &adj, stream);
+}
+
+tnvan_status tnvan_logz_and_backward(tnvan_net *net, const int64_t *n_samples,
+                                     const int8_t *spins, const double *grad, double *logz,
+                                     double *dh, double *dJ, double *dbeta, void *stream) {
+  if (tnvan_status s = check_net(net)) return s;
+  if (tnvan_status s = set_batch(net, n_samples)) return s;
+  if (!dh || !dJ || !dbeta) return set_err(TNVAN_E_INVALID, "dh, dJ and dbeta are required");
+  if (net->B_total > 0 && (!grad || !logz || (!spins && net->spin_total > 0)))
+    return set_err(TNVAN_E_INVALID, "spins, grad_logz and logz are required");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (logz_with_adjoint(net)) return run_backward<float>(net, spins, grad, dh, dJ, dbeta, st, logz);
+  if (net->precision == TNVAN_FP64) {
+    if (tnvan_status s = run_logz<double>(net, spins, logz, st)) return s;
+    return run_backward<double>(net, spins, grad, dh, dJ, dbeta, st);
+  }
+  if (tnvan_status s = run_logz<float>(net, spins, logz, st)) return s;
+  return run_backward<float>(net, spins, grad, dh, dJ, dbeta, st);
 }
 
 tnvan_status tnvan_program_info(const tnvan_net *net, int32_t inst, int64_t info[6]) {

@@ -12,7 +12,9 @@
 // unary factors of a group are computed on the fly from the sample's
 // width-set spins (staged once per wave in LDS) and the W-neighbour lists.
 //
-// The adjoint walks the chain backwards from checkpoints of A (every step,
+// The adjoint's forward pass is the forward kernel's arithmetic step for
+// step, so it also writes the chain's log partial (logZ comes with the
+// adjoint).  It walks the chain backwards from checkpoints of A (every step,
 // in HBM; nothing is recomputed).  With
 // R_t = d(ln Z)/d(out_t) in R-layout:
 //   Lambda_t = T_t R_t                 (matrix core, R-layout over x)
@@ -345,8 +347,11 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
   // processed, into two register sets used in turn: a loaded value is never
   // copied (a copy would wait for the load at the end of the step).
 
-  // forward: A_t checkpointed every step, exponents in LDS, root value
+  // forward: A_t checkpointed every step, exponents in LDS, root value, and
+  // the chain's log partial (the forward kernel's exact arithmetic, so the
+  // adjoint also yields logZ)
   float x[CT][4];
+  int esum = 0;
   {
     float u[GR];
     load_phi<GR>(ub, tk.Bq, cs[0].gpos, cs[0].g, u);
@@ -375,6 +380,7 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
       float d[CT][4];
       diag_from_phi<CT, GR>(uc, nx.g, lg, d);
       const int e = rescale_next<CT>(acc, d, x);
+      esum += e;
       if (lg == 0) ex[t * CW + ls] = e;
       return false;
     };
@@ -389,6 +395,9 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
     }
   }
   wsync();
+  if (lg == 0 && tk.b0 + ls < tk.Bq)
+    a.cpart[a.cpart_off[tk.q] + (int64_t)tk.c * tk.Bq + tk.b0 + ls] =
+        (double)esum * 0.69314718055994530942 + log((double)raw);
 
   // R of the closing step: d ln(raw) / d out = 1 / raw on its single entry
   float R[CT][4];
