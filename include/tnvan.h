@@ -231,6 +231,13 @@ tnvan_status tnvan_program_info(const tnvan_net *net, int32_t inst, int64_t info
 tnvan_status tnvan_kernel_time(tnvan_net *net, int32_t kernel, double *total_ms,
                                int64_t *launches);
 
+/* Which kernels TNVAN_FLAG_PROFILE times: bit k set times tnvan_kernel k
+ * (all of them after the build).  Each timed launch adds two event records
+ * to the stream, so timing only the kernels of interest keeps the rest of
+ * the stream's launches back to back.  Needs TNVAN_FLAG_PROFILE, else
+ * TNVAN_E_STATE. */
+tnvan_status tnvan_profile_mask(tnvan_net *net, uint32_t mask);
+
 /* Host-only planning: validate and compile one instance without touching a
  * device and report the same statistics as tnvan_program_info. */
 tnvan_status tnvan_plan(const tnvan_instance *inst, int32_t max_width, int64_t info[6]);

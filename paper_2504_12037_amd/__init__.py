@@ -83,6 +83,13 @@ class Net:
     FLAG_PROFILE = 2
     FLAG_GRAPH = 4
 
+    def profile_only(self, kernels):
+        """Time only these kernels (names or ids of KERNELS) from now on."""
+        mask = 0
+        for k in kernels:
+            mask |= 1 << (self.KERNELS[k] if isinstance(k, str) else int(k))
+        _lib.check(_lib.lib().tnvan_profile_mask(self._h, mask))
+
     def kernel_time(self, kernel):
         """(total seconds, launches) of one kernel since the previous read."""
         k = self.KERNELS[kernel] if isinstance(kernel, str) else int(kernel)

@@ -29,7 +29,7 @@ EXPORTS = ["tnvan_build_network", "tnvan_free_network", "tnvan_last_error",
            "tnvan_sample", "tnvan_logz_batch", "tnvan_logz_backward",
            "tnvan_logz_and_backward", "tnvan_free_energy_step",
            "tnvan_free_energy_step_adjoint", "tnvan_program_info", "tnvan_plan",
-           "tnvan_kernel_time"]
+           "tnvan_kernel_time", "tnvan_profile_mask"]
 
 
 class TnvanError(RuntimeError):
@@ -84,6 +84,7 @@ def lib():
     L.tnvan_program_info.argtypes = [vp, i32, vp]
     L.tnvan_plan.argtypes = [vp, i32, vp]
     L.tnvan_kernel_time.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(i64)]
+    L.tnvan_profile_mask.argtypes = [vp, C.c_uint32]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("tnvan_free_network", "tnvan_last_error"):

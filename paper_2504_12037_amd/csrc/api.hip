@@ -144,6 +144,7 @@ struct tnvan_net {
   } step_graph;
   // kernel timing (TNVAN_FLAG_PROFILE): event pairs recorded since the last read
   bool profile = false;
+  uint32_t prof_mask = ~0u;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_used[TNVAN_KERNEL_COUNT], prof_pool;
   int u_chunks = 0;
   int64_t u_maxB = 0;
@@ -181,11 +182,16 @@ struct ProfScope {
   hipStream_t st;
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
   ProfScope(tnvan_net *n, int k, hipStream_t s) : net(n), kind(k), st(s) {
-    if (!net->profile || net->capturing || kind < 0 || kind >= TNVAN_KERNEL_COUNT) return;
+    if (!net->profile || net->capturing || kind < 0 || kind >= TNVAN_KERNEL_COUNT ||
+        !((net->prof_mask >> kind) & 1u))
+      return;
+    // device-scope release: the events only time, and a system-scope one
+    // would write back caches and slow the launches around the timed one
     if (!net->prof_pool.empty()) {
       ev = net->prof_pool.back();
       net->prof_pool.pop_back();
-    } else if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess) {
+    } else if (hipEventCreateWithFlags(&ev.first, hipEventReleaseToDevice) != hipSuccess ||
+               hipEventCreateWithFlags(&ev.second, hipEventReleaseToDevice) != hipSuccess) {
       ev = {nullptr, nullptr};
       return;
     }
@@ -1277,6 +1283,13 @@ tnvan_status tnvan_program_info(const tnvan_net *net, int32_t inst, int64_t info
   const InstDesc &D = net->P.insts[inst];
   info[0] = D.n_steps; info[1] = D.max_w; info[2] = D.arena_all;
   info[3] = net->P.flops_fwd[inst]; info[4] = D.nw; info[5] = D.nr;
+  return TNVAN_OK;
+}
+
+tnvan_status tnvan_profile_mask(tnvan_net *net, uint32_t mask) {
+  if (tnvan_status s = check_net(net)) return s;
+  if (!net->profile) return set_err(TNVAN_E_STATE, "net built without TNVAN_FLAG_PROFILE");
+  net->prof_mask = mask;
   return TNVAN_OK;
 }
 
