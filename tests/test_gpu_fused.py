@@ -135,3 +135,21 @@ def test_free_energy_step_adjoint_equals_step_then_backward(case, graph):
     lz = nets[1].logz(spins[1], Bs).cpu().numpy()[:Bs[0]]
     want = _oracle_logz(insts[0], sp[:48])
     assert np.abs(lz[:48] - want).max() / insts[0].n <= TOL["fp32"]
+
+
+def test_profile_mask_times_only_the_chosen_kernels():
+    from paper_2504_12037_amd import Net
+    insts = [S.c2_lattice(1.0, 64)]
+    net = _net(insts, "fp32", seed=3, flags=Net.FLAG_PROFILE)
+    net.profile_only(["chain_bwd_2"])
+    g = torch.full((512,), 1.0 / 512, dtype=torch.float64, device="cuda")
+    adj = (g, torch.empty(insts[0].n, dtype=torch.float64, device="cuda"),
+           torch.empty(insts[0].n_edges, dtype=torch.float64, device="cuda"),
+           torch.empty(1, dtype=torch.float64, device="cuda"))
+    for _ in range(2):
+        net.free_energy_step(512, 1e-3, adjoint=adj)
+    torch.cuda.synchronize()
+    tot, n = net.kernel_time("chain_bwd_2")
+    assert n == 2 and tot > 0
+    assert net.kernel_time("sample") == (0.0, 0)
+    assert net.kernel_time("made_grad") == (0.0, 0)
