@@ -79,6 +79,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-samples", type=int, default=24576,
                    help="oracle samples per instance for cpu_baseline")
+    p.add_argument("--fp32-products", action="store_true",
+                   help="FP32 matrix-core products in the chain kernels (default: split BF16)")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="run one plain device copy of MIB MiB first (counter calibration)")
     return p.parse_args()
@@ -174,7 +176,12 @@ def main():
     # the dominant kernel of the step (the 2-tile adjoint chain kernel, by the
     # rocprofv3 statistics) and of no other kernel: each timed launch adds
     # two event records to the stream
-    net = Net(insts, precision=args.precision, seed=2024, flags=Net.FLAG_PROFILE)
+    # FP32 path with split-BF16 products in the chain kernels (three BF16
+    # matrix-core products per FP32 product; the breakdown reports the logZ
+    # error this leaves against the oracle), unless --fp32-products
+    split = args.precision == "fp32" and not args.fp32_products
+    net = Net(insts, precision=args.precision, seed=2024,
+              flags=Net.FLAG_PROFILE | (Net.FLAG_SPLIT_BF16 if split else 0))
     net.profile_only(["chain_bwd_2"])
     for k in range(nI):
         net.set_params(k, torch.from_numpy(S.made_init(nw, HIDDEN, 7 + k)))
@@ -264,7 +271,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16"}[args.precision],
+        "dtype": ("f32+bf16x3" if split else
+                  {"fp32": "f32", "fp64": "f64", "bf16": "bf16"}[args.precision]),
         "data": "synthetic",
         "config": {"workload": "16x16 OBC Gaussian spin glass, W = columns 6,11, "
                                "beta in {0.5,1,2}, 8192 samples each, MADE H=256",

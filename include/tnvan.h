@@ -98,6 +98,13 @@ typedef struct {
  * buffers or tables (another batch shape in any call), runs eagerly and
  * records a new graph for the next calls. */
 #define TNVAN_FLAG_GRAPH 4
+/* FP32 nets: the register-resident chain kernels form every FP32 product
+ * as three BF16 matrix-core products of split operands (a = a_hi + a_lo,
+ * each part rounded to BF16: a_hi b_hi + a_hi b_lo + a_lo b_hi, FP32
+ * accumulation; about 16 bits of each operand, the a_lo b_lo term dropped),
+ * at 16x the multiply rate of the FP32 products.  Spin-sign operands are
+ * exact in BF16 and take two products.  Ignored by FP64 and BF16 nets. */
+#define TNVAN_FLAG_SPLIT_BF16 8
 
 /* Kernels timed under TNVAN_FLAG_PROFILE. */
 typedef enum {

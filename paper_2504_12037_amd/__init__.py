@@ -82,6 +82,7 @@ class Net:
     FLAG_LDS_CHAIN = 1
     FLAG_PROFILE = 2
     FLAG_GRAPH = 4
+    FLAG_SPLIT_BF16 = 8
 
     def profile_only(self, kernels):
         """Time only these kernels (names or ids of KERNELS) from now on."""

@@ -169,6 +169,71 @@ __device__ inline void mm_fwd_bf(const u4v (&tb)[CT][(CT + 1) / 2], const float 
 }
 
 
+// Split-BF16 products (the FP32 path under TNVAN_FLAG_SPLIT_BF16): an FP32
+// product a b is formed as a_hi b_hi + a_hi b_lo + a_lo b_hi on the BF16
+// 16x16x32 matrix cores (a_hi = a rounded to BF16, a_lo = the rest rounded
+// to BF16), FP32 accumulation.  Element j of a lane's K chunk c is state
+// 16 (2c + j/4) + 4 (lane >> 4) + j % 4, so the R-layout registers are the
+// operand as they are, zero past the chain's tiles.
+template <int CT>
+__device__ inline void split_chunk(const float (&x)[CT][4], int c, bf8 &h, bf8 &l) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int t = 2 * c + (j >> 2);
+    const float v = t < CT ? x[t < CT ? t : 0][j & 3] : 0.f;
+    h[j] = (__bf16)v;
+    l[j] = (__bf16)(v - (float)h[j]);
+  }
+}
+__device__ inline bf8 as_bf8(u4v v) { return __builtin_bit_cast(bf8, v); }
+__device__ inline f4 mfma_bf(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Forward operands of one step, per product mode (0: FP32, 1: BF16 tables,
+// 2: split BF16), loaded from the step's tables and multiplied by the
+// R-layout state: out^T = T^T A^T
+template <int kM, int CT> struct FwdOps;
+template <int CT> struct FwdOps<0, CT> {
+  f4 t[CT][CT];
+  __device__ void load(const ChainArgs &a, const ChainStep &s, int lane) { load_t<CT>(a.Tr + s.tr_off, lane, t); }
+  __device__ void mm(const float (&x)[CT][4], f4 (&acc)[CT]) const { mm_fwd<CT>(t, x, acc); }
+};
+template <int CT> struct FwdOps<1, CT> {
+  u4v b[CT][(CT + 1) / 2];
+  __device__ void load(const ChainArgs &a, const ChainStep &s, int lane) { load_tb<CT>(a.Trb + s.trb_off, lane, b); }
+  __device__ void mm(const float (&x)[CT][4], f4 (&acc)[CT]) const { mm_fwd_bf<CT>(b, x, acc); }
+};
+template <int CT> struct FwdOps<2, CT> {
+  static constexpr int NC = (CT + 1) / 2;
+  u4v h[CT][NC], l[CT][NC];
+  __device__ void load(const ChainArgs &a, const ChainStep &s, int lane) {
+    const u4v *p = reinterpret_cast<const u4v *>(a.Ts3 + s.s3_off) + lane;
+#pragma unroll
+    for (int i = 0; i < CT; ++i)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        h[i][c] = p[(i * NC + c) * 64];
+        l[i][c] = p[((CT + i) * NC + c) * 64];
+      }
+  }
+  __device__ void mm(const float (&x)[CT][4], f4 (&acc)[CT]) const {
+#pragma unroll
+    for (int nt = 0; nt < CT; ++nt) acc[nt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      bf8 xh, xl;
+      split_chunk<CT>(x, c, xh, xl);
+#pragma unroll
+      for (int nt = 0; nt < CT; ++nt) acc[nt] = mfma_bf(as_bf8(h[nt][c]), xh, acc[nt]);
+#pragma unroll
+      for (int nt = 0; nt < CT; ++nt) acc[nt] = mfma_bf(as_bf8(h[nt][c]), xl, acc[nt]);
+#pragma unroll
+      for (int nt = 0; nt < CT; ++nt) acc[nt] = mfma_bf(as_bf8(l[nt][c]), xh, acc[nt]);
+    }
+  }
+};
+
 // power-of-two rescale of the step output and the next diagonal:
 // x = out * 2^-e * d; returns e of the lane's sample
 template <int CT>
@@ -223,10 +288,9 @@ __device__ inline Task wave_task(const ChainArgs &a, int wave) {
 // forward of one chain for SG groups of 16 samples: per sample the sum of
 // the step exponents (ln 2) and ln of the root value; the unary
 // normalisations are added from unary_kernel's sums
-template <bool kBF, int CT, int SG>
+template <int kM, int CT, int SG>
 __device__ inline void fwd_chain(const ChainArgs &a, const Task &tk, const ChainDesc &cd, int lane) {
   constexpr int GR = GroupMax<CT>::v;
-  constexpr int NC2 = (CT + 1) / 2;
   const int ls = lane & 15, lg = lane >> 4;
   const ChainStep *cs = a.csteps + cd.cs_off;
   const int T = cd.n_steps;
@@ -245,25 +309,21 @@ __device__ inline void fwd_chain(const ChainArgs &a, const Task &tk, const Chain
       esum[gi] = 0;
     }
   }
-  // step t with the descriptor nx of step t + 1, the table of step t and
-  // the unary factors uc of step t + 1's group; loads step t + 1's table and
-  // step t + 2's unary factors into the other register set (two sets used in
-  // turn: a loaded value is never copied, which would wait for the load)
-  auto fstep = [&](int t, const ChainStep &nx, const f4 (&tc)[CT][CT], const u4v (&bc)[CT][NC2],
-                   const float (&uc)[SG][GR], ChainStep &nn, f4 (&tn)[CT][CT], u4v (&bn)[CT][NC2],
-                   float (&un)[SG][GR]) -> bool {
+  // step t with the descriptor nx of step t + 1, the operands of step t and
+  // the unary factors uc of step t + 1's group; loads step t + 1's operands
+  // and step t + 2's unary factors into the other register set (two sets
+  // used in turn: a loaded value is never copied, which would wait for the
+  // load)
+  auto fstep = [&](int t, const ChainStep &nx, const FwdOps<kM, CT> &oc, const float (&uc)[SG][GR],
+                   ChainStep &nn, FwdOps<kM, CT> &on, float (&un)[SG][GR]) -> bool {
     const bool last = t == T - 1;
     nn = step_at(cs, t + 2 < T ? t + 2 : T - 1);
-    if (kBF) load_tb<CT>(a.Trb + nx.trb_off, lane, bn);
-    else load_t<CT>(a.Tr + nx.tr_off, lane, tn);
+    on.load(a, nx, lane);
 #pragma unroll
     for (int gi = 0; gi < SG; ++gi) load_phi<GR>(ub[gi], tk.Bq, nn.gpos, nn.g, un[gi]);
     f4 acc[SG][CT];
 #pragma unroll
-    for (int gi = 0; gi < SG; ++gi) {
-      if (kBF) mm_fwd_bf<CT>(bc, x[gi], acc[gi]);
-      else mm_fwd<CT>(tc, x[gi], acc[gi]);
-    }
+    for (int gi = 0; gi < SG; ++gi) oc.mm(x[gi], acc[gi]);
     if (last) {
 #pragma unroll
       for (int gi = 0; gi < SG; ++gi) raw[gi] = __shfl(acc[gi][0][0], ls, 64);
@@ -278,16 +338,14 @@ __device__ inline void fwd_chain(const ChainArgs &a, const Task &tk, const Chain
     return false;
   };
   ChainStep nA = step_at(cs, T > 1 ? 1 : 0), nB;
-  f4 tA[CT][CT], tB[CT][CT];
-  u4v bA[CT][NC2], bB[CT][NC2];
+  FwdOps<kM, CT> oA, oB;
   float uA[SG][GR], uB[SG][GR];
-  if (kBF) load_tb<CT>(a.Trb + cs[0].trb_off, lane, bA);
-  else load_t<CT>(a.Tr + cs[0].tr_off, lane, tA);
+  oA.load(a, cs[0], lane);
 #pragma unroll
   for (int gi = 0; gi < SG; ++gi) load_phi<GR>(ub[gi], tk.Bq, nA.gpos, nA.g, uA[gi]);
   for (int t = 0;; t += 2) {
-    if (fstep(t, nA, tA, bA, uA, nB, tB, bB, uB)) break;
-    if (fstep(t + 1, nB, tB, bB, uB, nA, tA, bA, uA)) break;
+    if (fstep(t, nA, oA, uA, nB, oB, uB)) break;
+    if (fstep(t + 1, nB, oB, uB, nA, oA, uA)) break;
   }
   if (lg == 0) {
 #pragma unroll
@@ -300,7 +358,7 @@ __device__ inline void fwd_chain(const ChainArgs &a, const Task &tk, const Chain
   }
 }
 
-template <bool kBF, int CT, int SG>
+template <int kM, int CT, int SG>
 __global__ __launch_bounds__(256) void rchain_fwd_kernel(ChainArgs a) {
   extern __shared__ __align__(16) char smem[];
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -312,16 +370,18 @@ __global__ __launch_bounds__(256) void rchain_fwd_kernel(ChainArgs a) {
   const ChainDesc cd = a.chains[C.chain_off + tk.c];
   (void)smem;
   (void)D;
-  fwd_chain<kBF, CT, SG>(a, tk, cd, lane);
+  fwd_chain<kM, CT, SG>(a, tk, cd, lane);
 }
 
 // spin sign of bit j of the state index x
 __device__ inline float sgn(int x, int j) { return ((x >> j) & 1) ? -1.f : 1.f; }
 
-template <int CT>
+template <int CT, bool kS>
 __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstDesc &D,
                                  const ChainDesc &cd, char *base, const RL &L, int lane) {
   constexpr int GR = GroupMax<CT>::v;
+  constexpr int NC = (CT + 1) / 2;
+  constexpr int kM = kS ? 2 : 0;
   constexpr int LDT = ldt_of(CT);
   const int ls = lane & 15, lg = lane >> 4;
   const ChainStep *cs = a.csteps + cd.cs_off;
@@ -359,20 +419,20 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
   }
   float raw = 1.f;
   {
-    // step t with the descriptor nx of step t + 1, table tc of step t and
-    // unary factors uc of step t + 1's group; loads step t + 1's table and
-    // step t + 2's unary factors
-    auto fstep = [&](int t, const ChainStep &nx, const f4 (&tc)[CT][CT], const float (&uc)[GR],
-                     ChainStep &nn, f4 (&tn)[CT][CT], float (&un)[GR]) -> bool {
+    // step t with the descriptor nx of step t + 1, operands oc of step t and
+    // unary factors uc of step t + 1's group; loads step t + 1's operands
+    // and step t + 2's unary factors
+    auto fstep = [&](int t, const ChainStep &nx, const FwdOps<kM, CT> &oc, const float (&uc)[GR],
+                     ChainStep &nn, FwdOps<kM, CT> &on, float (&un)[GR]) -> bool {
 #pragma unroll
       for (int i = 0; i < CT; ++i)
         ck[(t * kRegBwdTiles + i) * 64] = f4{x[i][0], x[i][1], x[i][2], x[i][3]};
       const bool last = t == T - 1;
       nn = step_at(cs, t + 2 < T ? t + 2 : T - 1);
-      load_t<CT>(a.Tr + nx.tr_off, lane, tn);
+      on.load(a, nx, lane);
       load_phi<GR>(ub, tk.Bq, nn.gpos, nn.g, un);
       f4 acc[CT];
-      mm_fwd<CT>(tc, x, acc);
+      oc.mm(x, acc);
       if (last) {
         raw = __shfl(acc[0][0], ls, 64);
         return true;
@@ -385,13 +445,13 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
       return false;
     };
     ChainStep nA = step_at(cs, T > 1 ? 1 : 0), nB;
-    f4 tA[CT][CT], tB[CT][CT];
+    FwdOps<kM, CT> oA, oB;
     float uA[GR], uB[GR];
-    load_t<CT>(a.Tr + cs[0].tr_off, lane, tA);
+    oA.load(a, cs[0], lane);
     load_phi<GR>(ub, tk.Bq, nA.gpos, nA.g, uA);
     for (int t = 0;; t += 2) {
-      if (fstep(t, nA, tA, uA, nB, tB, uB)) break;
-      if (fstep(t + 1, nB, tB, uB, nA, tA, uA)) break;
+      if (fstep(t, nA, oA, uA, nB, oB, uB)) break;
+      if (fstep(t + 1, nB, oB, uB, nA, oA, uA)) break;
     }
   }
   wsync();
@@ -409,15 +469,28 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
 
   // the walk, step t with its checkpoint A_t, Lambda operands and unary
   // factors loaded during step t + 1
+  // (Lambda operands: FP32 tq, or split-BF16 qh / ql)
   struct Pre {
     f4 a[CT];
-    f4 tq[CT][CT];
+    f4 tq[kS ? 1 : CT][kS ? 1 : CT];
+    u4v qh[kS ? CT : 1][NC], ql[kS ? CT : 1][NC];
     float u[GR];
   };
   auto prefetch = [&](const ChainStep &s, int t, Pre &p) {
 #pragma unroll
     for (int i = 0; i < CT; ++i) p.a[i] = ck[(t * kRegBwdTiles + i) * 64];
-    load_t<CT>(a.Tq + s.tq_off, lane, p.tq);
+    if constexpr (kS) {
+      const u4v *q3 = reinterpret_cast<const u4v *>(a.Ts3 + s.s3_off) + lane + 2 * CT * NC * 64;
+#pragma unroll
+      for (int i = 0; i < CT; ++i)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          p.qh[i][c] = q3[(i * NC + c) * 64];
+          p.ql[i][c] = q3[((CT + i) * NC + c) * 64];
+        }
+    } else {
+      load_t<CT>(a.Tq + s.tq_off, lane, p.tq);
+    }
     load_phi<GR>(ub, tk.Bq, s.gpos, s.g, p.u);
   };
   auto walk = [&](int t, const ChainStep &st, const Pre &cur, ChainStep &sn, Pre &nxt) {
@@ -427,10 +500,21 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
     for (int i = 0; i < CT; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) As[i][r] = cur.a[i][r];
-    // operands used later in this step, issued now
-    f4 tr[CT][CT], sx[CT], so[CT];
-    load_t<CT>(a.Tr + st.tr_off, lane, tr);
-    {
+    // operands used later in this step, issued now: T (for G = H o T) and
+    // the S_x / S_o tables, in FP32 or split-BF16 form
+    f4 tr[kS ? 1 : CT][kS ? 1 : CT], sx[kS ? 1 : CT], so[kS ? 1 : CT];
+    FwdOps<2, CT> t3;
+    u4v sxb[NC], sob[NC];
+    if constexpr (kS) {
+      t3.load(a, st, lane);
+      const u4v *q3 = reinterpret_cast<const u4v *>(a.Ts3 + st.s3_off) + lane + 4 * CT * NC * 64;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        sxb[c] = q3[c * 64];
+        sob[c] = q3[(NC + c) * 64];
+      }
+    } else {
+      load_t<CT>(a.Tr + st.tr_off, lane, tr);
       const f4 *sxo = reinterpret_cast<const f4 *>(a.Tsx + st.sx_off) + lane;
 #pragma unroll
       for (int i = 0; i < CT; ++i) {
@@ -446,13 +530,27 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
     f4 lam[CT];
 #pragma unroll
     for (int xt = 0; xt < CT; ++xt) lam[xt] = f4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (kS) {
 #pragma unroll
-    for (int ot = 0; ot < CT; ++ot)
+      for (int c = 0; c < NC; ++c) {
+        bf8 rh, rl;
+        split_chunk<CT>(R, c, rh, rl);
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+        for (int xt = 0; xt < CT; ++xt) lam[xt] = mfma_bf(as_bf8(cur.qh[xt][c]), rh, lam[xt]);
 #pragma unroll
-        for (int xt = 0; xt < CT; ++xt)
-          lam[xt] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.tq[xt][ot][r], R[ot][r], lam[xt], 0, 0, 0);
+        for (int xt = 0; xt < CT; ++xt) lam[xt] = mfma_bf(as_bf8(cur.qh[xt][c]), rl, lam[xt]);
+#pragma unroll
+        for (int xt = 0; xt < CT; ++xt) lam[xt] = mfma_bf(as_bf8(cur.ql[xt][c]), rh, lam[xt]);
+      }
+    } else {
+#pragma unroll
+      for (int ot = 0; ot < CT; ++ot)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int xt = 0; xt < CT; ++xt)
+            lam[xt] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.tq[xt][ot][r], R[ot][r], lam[xt], 0, 0, 0);
+    }
     // W-R correlations: per-sample magnetisation of a group spin times the
     // neighbouring width-set spin, weighted and summed over the samples
 #pragma unroll
@@ -491,34 +589,88 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
     wsync();
     // per output tile: H (samples contracted), G = H o T, Q'^T = G^T S_x
     f4 qt[CT];
-#pragma unroll
-    for (int ot = 0; ot < CT; ++ot) {
-      f4 hg[CT];
-#pragma unroll
-      for (int xt = 0; xt < CT; ++xt) {
-        hg[xt] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kc = 0; kc < 4; ++kc)
-          hg[xt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-              ga[(4 * kc + lg) * LDT + 16 * xt + ls], rs[(4 * kc + lg) * LDT + 16 * ot + ls],
-              hg[xt], 0, 0, 0);
-      }
-      qt[ot] = f4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (kS) {
+      // H with the 16 samples in each half of the 32-long contraction: the
+      // first product takes hi and lo of g A against hi of R, the second hi
+      // of g A against lo of R; lane (lg, ls) supplies samples 4 lg + j
+      bf8 ah1[CT], ah2[CT], rb1[CT], rb2[CT];
 #pragma unroll
       for (int xt = 0; xt < CT; ++xt)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          qt[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(hg[xt][r] * tr[ot][xt][r], sx[xt][r],
-                                                        qt[ot], 0, 0, 0);
+        for (int j = 0; j < 4; ++j) {
+          const float va = ga[(4 * lg + j) * LDT + 16 * xt + ls];
+          const __bf16 h = (__bf16)va, l = (__bf16)(va - (float)h);
+          ah1[xt][j] = h; ah1[xt][4 + j] = l;
+          ah2[xt][j] = h; ah2[xt][4 + j] = (__bf16)0.f;
+          const float vr = rs[(4 * lg + j) * LDT + 16 * xt + ls];
+          const __bf16 rh = (__bf16)vr, rl = (__bf16)(vr - (float)rh);
+          rb1[xt][j] = rh; rb1[xt][4 + j] = rh;
+          rb2[xt][j] = rl; rb2[xt][4 + j] = (__bf16)0.f;
+        }
+#pragma unroll
+      for (int ot = 0; ot < CT; ++ot) {
+        f4 hg[CT];
+#pragma unroll
+        for (int xt = 0; xt < CT; ++xt) hg[xt] = mfma_bf(ah1[xt], rb1[ot], f4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+        for (int xt = 0; xt < CT; ++xt) hg[xt] = mfma_bf(ah2[xt], rb2[ot], hg[xt]);
+        // G = H o T (T = hi + lo of the forward table, element 4 xt + r of
+        // this lane), then Q'^T = G^T S_x with the lane's 8 G values as the
+        // operand (S_x is exact in BF16: two products)
+        const bf8 th = as_bf8(t3.h[ot][0]), tl = as_bf8(t3.l[ot][0]);
+        float gv[CT][4];
+#pragma unroll
+        for (int xt = 0; xt < CT; ++xt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            gv[xt][r] = hg[xt][r] * ((float)th[4 * xt + r] + (float)tl[4 * xt + r]);
+        bf8 gh, gl;
+        split_chunk<CT>(gv, 0, gh, gl);
+        qt[ot] = mfma_bf(gh, as_bf8(sxb[0]), f4{0.f, 0.f, 0.f, 0.f});
+        qt[ot] = mfma_bf(gl, as_bf8(sxb[0]), qt[ot]);
+      }
+    } else {
+#pragma unroll
+      for (int ot = 0; ot < CT; ++ot) {
+        f4 hg[CT];
+#pragma unroll
+        for (int xt = 0; xt < CT; ++xt) {
+          hg[xt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int kc = 0; kc < 4; ++kc)
+            hg[xt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                ga[(4 * kc + lg) * LDT + 16 * xt + ls], rs[(4 * kc + lg) * LDT + 16 * ot + ls],
+                hg[xt], 0, 0, 0);
+        }
+        qt[ot] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int xt = 0; xt < CT; ++xt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            qt[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(hg[xt][r] * tr[ot][xt][r], sx[xt][r],
+                                                          qt[ot], 0, 0, 0);
+      }
     }
     wsync();
     // Q = S_o^T Q'^T (operand tables)
     f4 qq = f4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (kS) {
+      float qv[CT][4];
 #pragma unroll
-    for (int ot = 0; ot < CT; ++ot)
+      for (int ot = 0; ot < CT; ++ot)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        qq = __builtin_amdgcn_mfma_f32_16x16x4f32(so[ot][r], qt[ot][r], qq, 0, 0, 0);
+        for (int r = 0; r < 4; ++r) qv[ot][r] = qt[ot][r];
+      bf8 qh, ql;
+      split_chunk<CT>(qv, 0, qh, ql);
+      qq = mfma_bf(as_bf8(sob[0]), qh, qq);
+      qq = mfma_bf(as_bf8(sob[0]), ql, qq);
+    } else {
+#pragma unroll
+      for (int ot = 0; ot < CT; ++ot)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          qq = __builtin_amdgcn_mfma_f32_16x16x4f32(so[ot][r], qt[ot][r], qq, 0, 0, 0);
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) qs[ls * 17 + 4 * lg + r] = qq[r];
     wsync();
@@ -544,7 +696,7 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
   }
 }
 
-template <int CT>
+template <int CT, bool kS>
 __global__ __launch_bounds__(256, 3) void rchain_bwd_kernel(ChainArgs a) {
   extern __shared__ __align__(16) char smem[];
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -556,7 +708,7 @@ __global__ __launch_bounds__(256, 3) void rchain_bwd_kernel(ChainArgs a) {
   const ChainDesc cd = a.chains[C.chain_off + tk.c];
   const RL L = rlayout(a.lim, true, 1);
   char *base = smem + (size_t)wave * L.end;
-  bwd_chain<CT>(a, tk, D, cd, base, L, lane);
+  bwd_chain<CT, kS>(a, tk, D, cd, base, L, lane);
 }
 
 }  // namespace
@@ -574,17 +726,22 @@ hipError_t launch_rchain(const ChainArgs &a, bool bwd, hipStream_t st) {
   const int sg = bwd ? 1 : (a.sg >= 2 ? 2 : 1);
   void (*k)(ChainArgs) = nullptr;
   const int ct = a.ntm;
+  const bool sp = a.split != 0 && !a.bf16;
   if (bwd) {
-    if (ct == 1) k = rchain_bwd_kernel<1>;
-    else if (ct == 2) k = rchain_bwd_kernel<2>;
+    if (ct == 1) k = sp ? rchain_bwd_kernel<1, true> : rchain_bwd_kernel<1, false>;
+    else if (ct == 2) k = sp ? rchain_bwd_kernel<2, true> : rchain_bwd_kernel<2, false>;
   } else if (a.bf16) {
-    if (ct == 1) k = sg >= 2 ? rchain_fwd_kernel<true, 1, 2> : rchain_fwd_kernel<true, 1, 1>;
-    else if (ct == 2) k = sg >= 2 ? rchain_fwd_kernel<true, 2, 2> : rchain_fwd_kernel<true, 2, 1>;
-    else if (ct == 4) k = rchain_fwd_kernel<true, 4, 1>;
+    if (ct == 1) k = sg >= 2 ? rchain_fwd_kernel<1, 1, 2> : rchain_fwd_kernel<1, 1, 1>;
+    else if (ct == 2) k = sg >= 2 ? rchain_fwd_kernel<1, 2, 2> : rchain_fwd_kernel<1, 2, 1>;
+    else if (ct == 4) k = rchain_fwd_kernel<1, 4, 1>;
+  } else if (sp) {
+    if (ct == 1) k = sg >= 2 ? rchain_fwd_kernel<2, 1, 2> : rchain_fwd_kernel<2, 1, 1>;
+    else if (ct == 2) k = sg >= 2 ? rchain_fwd_kernel<2, 2, 2> : rchain_fwd_kernel<2, 2, 1>;
+    else if (ct == 4) k = rchain_fwd_kernel<2, 4, 1>;
   } else {
-    if (ct == 1) k = sg >= 2 ? rchain_fwd_kernel<false, 1, 2> : rchain_fwd_kernel<false, 1, 1>;
-    else if (ct == 2) k = sg >= 2 ? rchain_fwd_kernel<false, 2, 2> : rchain_fwd_kernel<false, 2, 1>;
-    else if (ct == 4) k = rchain_fwd_kernel<false, 4, 1>;
+    if (ct == 1) k = sg >= 2 ? rchain_fwd_kernel<0, 1, 2> : rchain_fwd_kernel<0, 1, 1>;
+    else if (ct == 2) k = sg >= 2 ? rchain_fwd_kernel<0, 2, 2> : rchain_fwd_kernel<0, 2, 1>;
+    else if (ct == 4) k = rchain_fwd_kernel<0, 4, 1>;
   }
   if (!k) return hipErrorInvalidValue;
   const int sgl = (!bwd && ct == 4) ? 1 : sg;

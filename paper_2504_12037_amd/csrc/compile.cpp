@@ -257,12 +257,65 @@ void build_chains(const InstDesc &D, const std::vector<int32_t> &consumer, HostP
             }
             P.Tsx.push_back(v);
           }
+      auto so_val = [&](int o, int j) {
+        return j < sd.w ? (((o >> j) & 1) ? -1.f : 1.f) : (j == sd.w ? 1.f : 0.f);
+      };
+      auto sx_val = [&](int x, int col) {
+        const int code = xc[col];
+        if (code < 0) return 0.f;
+        const int cu = code & 0xff, cv = (code >> 8) & 0xff;
+        const int m = (1 << cu) | (cv < 31 ? (1 << cv) : 0);
+        return par(x & m) ? -1.f : 1.f;
+      };
       for (int ot = 0; ot < CT; ++ot)
         for (int l = 0; l < 64; ++l)
-          for (int r = 0; r < 4; ++r) {
-            const int j = l & 15, o = 16 * ot + 4 * (l >> 4) + r;
-            P.Tsx.push_back(j < sd.w ? (((o >> j) & 1) ? -1.f : 1.f) : (j == sd.w ? 1.f : 0.f));
-          }
+          for (int r = 0; r < 4; ++r) P.Tsx.push_back(so_val(16 * ot + 4 * (l >> 4) + r, l & 15));
+      // split-BF16 tables (program.h)
+      {
+        auto st3 = [&](int c, int l, int j) {   // state of element j, or -1
+          const int t = 2 * c + (j >> 2);
+          return t < CT ? 16 * t + 4 * (l >> 4) + (j & 3) : -1;
+        };
+        auto hi = [](float v) { return to_bf16(v); };
+        auto lo = [](float v) {
+          const uint16_t h = to_bf16(v);
+          uint32_t u = (uint32_t)h << 16;
+          float hv;
+          std::memcpy(&hv, &u, 4);
+          return to_bf16(v - hv);
+        };
+        cs.s3_off = (int64_t)P.Ts3.size();
+        for (int part = 0; part < 2; ++part)
+          for (int nt = 0; nt < CT; ++nt)
+            for (int c = 0; c < KC2; ++c)
+              for (int l = 0; l < 64; ++l)
+                for (int j = 0; j < 8; ++j) {
+                  const int x = st3(c, l, j);
+                  const float v = x < 0 ? 0.f : tv(x, 16 * nt + (l & 15));
+                  P.Ts3.push_back(part ? lo(v) : hi(v));
+                }
+        for (int part = 0; part < 2; ++part)
+          for (int xt = 0; xt < CT; ++xt)
+            for (int c = 0; c < KC2; ++c)
+              for (int l = 0; l < 64; ++l)
+                for (int j = 0; j < 8; ++j) {
+                  const int o = st3(c, l, j);
+                  const float v = o < 0 ? 0.f : tv(16 * xt + (l & 15), o);
+                  P.Ts3.push_back(part ? lo(v) : hi(v));
+                }
+        for (int c = 0; c < KC2; ++c)
+          for (int l = 0; l < 64; ++l)
+            for (int j = 0; j < 8; ++j) {
+              const int x = st3(c, l, j);
+              P.Ts3.push_back(to_bf16(x < 0 ? 0.f : sx_val(x, l & 15)));
+            }
+        for (int c = 0; c < KC2; ++c)
+          for (int l = 0; l < 64; ++l)
+            for (int j = 0; j < 8; ++j) {
+              const int o = st3(c, l, j);
+              P.Ts3.push_back(to_bf16(o < 0 ? 0.f : so_val(o, l & 15)));
+            }
+      }
       P.csteps.push_back(cs);
     }
     cd.tl_size = (int32_t)(P.Tl.size() - cd.tl_src);

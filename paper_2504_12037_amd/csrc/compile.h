@@ -43,6 +43,7 @@ struct HostProgram {
   std::vector<EdgeDesc> cedges;     // per chain: the edges of its steps
   std::vector<float> Tr, Tq;        // register-resident operand tables
   std::vector<uint16_t> Trb;
+  std::vector<uint16_t> Ts3;        // per chain step: split-BF16 operand tables
   std::vector<int32_t> xcol;        // 16 adjoint column codes per chain step
   std::vector<float> Tsx;           // per chain step: S_x and S_o operand tables
   // adjoint output maps: vertex -> R position (-1 on W), edge -> partial

@@ -266,6 +266,8 @@ struct ChainArgs {
   const uint16_t *Trb;
   const int32_t *xcol;
   const float *Tsx;                 // adjoint S_x / S_o operand tables
+  const uint16_t *Ts3;              // split-BF16 operand tables (ChainStep::s3_off)
+  int32_t split;                    // FP32 path with split-BF16 products
   int32_t sg;                       // 16-sample groups per wave (forward)
   int32_t task_base;                // first task of the launch
   // dense W-neighbour slots of every R position (index hr_off + position)

@@ -123,6 +123,15 @@ struct ChainStep {
   int32_t wri[4];
   int32_t wre[4];
   int32_t pad2;
+  // split-BF16 operand tables (16x16x32 order, KC = ceil(rt / 2) chunks of 32
+  // states; state of element j of lane l in chunk c: 16 (2c + j/4) +
+  // 4 (l >> 4) + j % 4, zero past the chain's tiles), BF16 [part][...]:
+  //   0/1 forward hi/lo [nt][c][lane][8]: T[state][16 nt + (l & 15)]
+  //   2/3 Lambda hi/lo  [xt][c][lane][8]: T[16 xt + (l & 15)][state]
+  //   4   S_x           [c][lane][8]:     S_x[state][column l & 15]
+  //   5   S_o           [c][lane][8]:     S_o[state][row l & 15]
+  // (hi = T rounded to BF16, lo = the rest rounded to BF16)
+  int64_t s3_off;
 };
 
 // Register-resident layout ("R-layout") of a per-sample vector over 16*KT

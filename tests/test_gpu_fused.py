@@ -48,7 +48,7 @@ def _oracle_logz(inst, spins):
     return OI.logz_r_elimination(inst, spins)
 
 
-@pytest.mark.parametrize("flags", [0, 1])
+@pytest.mark.parametrize("flags", [0, 1, 8])
 @pytest.mark.parametrize("prec", ["fp32", "fp64", "bf16"])
 @pytest.mark.parametrize("case", list(CASES))
 def test_logz_and_backward_equals_separate_calls(case, prec, flags):
@@ -96,15 +96,17 @@ def test_logz_and_backward_full_size():
         assert np.abs(got[k * B + idx] - want).max() / inst.n <= TOL["fp32"]
 
 
+@pytest.mark.parametrize("split", [False, True])
 @pytest.mark.parametrize("graph", [False, True])
 @pytest.mark.parametrize("case", ["chains3", "mixed"])
-def test_free_energy_step_adjoint_equals_step_then_backward(case, graph):
+def test_free_energy_step_adjoint_equals_step_then_backward(case, graph, split):
     from paper_2504_12037_amd import Net
     insts = CASES[case]()
     Bs = [256, 128, 384][:len(insts)]
-    print(f"\n[step-adjoint] case={case} graph={graph} B={Bs}", flush=True)
-    nets = [_net(insts, "fp32", seed=33),
-            _net(insts, "fp32", seed=33, flags=Net.FLAG_GRAPH if graph else 0)]
+    print(f"\n[step-adjoint] case={case} graph={graph} split={split} B={Bs}", flush=True)
+    sf = Net.FLAG_SPLIT_BF16 if split else 0
+    nets = [_net(insts, "fp32", seed=33, flags=sf),
+            _net(insts, "fp32", seed=33, flags=sf | (Net.FLAG_GRAPH if graph else 0))]
     for net in nets:
         for k, inst in enumerate(insts):
             th = S.made_init(inst.n_width, inst.hidden, 50 + k).astype(np.float32)

@@ -190,3 +190,45 @@ def test_lds_chain_kernels(case, prec):
     tol = GTOL[prec] * np.abs(g).sum() * max(inst.beta, 1.0)
     np.testing.assert_allclose(dh.cpu().numpy(), wdh, atol=tol, rtol=0)
     np.testing.assert_allclose(dJ.cpu().numpy(), wdJ, atol=tol, rtol=0)
+
+
+@pytest.mark.parametrize("case", ["c1", "c1_single", "c2_b05", "c2_b2", "c2_single",
+                                  "lat8_field", "c3_b1", "rrg20"])
+def test_split_bf16_products(case):
+    # FP32 path with split-BF16 products (TNVAN_FLAG_SPLIT_BF16): logZ and
+    # the adjoint against the oracle at the FP32 tolerances
+    inst = CASES[case]()
+    B = {"c2_b2": 200, "c2_single": 120, "c3_b1": 300}.get(case, 257)
+    print(f"\n[split-bf16] case={case} B={B}", flush=True)
+    spins = S.uniform_spins(B, inst.n_width, 70 + B)
+    net = _net([inst], "fp32", flags=8)
+    got = net.logz(_dev(spins), B).cpu().numpy()
+    want = _oracle_logz(inst, spins)
+    assert (np.abs(got - want) / inst.n).max() <= TOL["fp32"]
+    g = np.random.default_rng(B + 1).standard_normal(B)
+    dh, dJ, db = net.backward(_dev(spins), _dev(g), B)
+    if len(inst.order) <= 16:
+        mag, corr, e2 = OI.marginals_bruteforce(inst, spins)
+        wdh, wdJ, wdb = OI.logz_r_vjp(inst, spins, g, marg=(mag, corr, e2))
+    else:
+        wdh, wdJ, wdb = OI.logz_r_vjp(inst, spins, g)
+    tol = GTOL["fp32"] * np.abs(g).sum() * max(inst.beta, 1.0)
+    np.testing.assert_allclose(dh.cpu().numpy(), wdh, atol=tol, rtol=0)
+    np.testing.assert_allclose(dJ.cpu().numpy(), wdJ, atol=tol, rtol=0)
+    jscale = np.abs(inst.J).sum() + np.abs(inst.h).sum() + 1
+    assert abs(db.cpu().item() - wdb) <= GTOL["fp32"] * np.abs(g).sum() * jscale
+
+
+def test_split_bf16_full_size_sampled():
+    # the benchmark workload at full batch with split-BF16 products: 256
+    # sampled outputs against the oracle, spin-flip symmetry on every output
+    inst = S.c2_lattice(1.0)
+    B = 8192
+    spins = S.uniform_spins(B, inst.n_width, 102)
+    net = _net([inst], "fp32", flags=8)
+    got = net.logz(_dev(spins), B).cpu().numpy()
+    idx = np.random.default_rng(0).choice(B, 256, replace=False)
+    want = OI.logz_r_elimination(inst, spins[idx])
+    assert np.abs(got[idx] - want).max() / inst.n <= TOL["fp32"]
+    got2 = net.logz(_dev(-spins), B).cpu().numpy()
+    assert np.abs(got2 - got).max() / inst.n <= TOL["fp32"]
