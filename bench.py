@@ -63,11 +63,12 @@ KERNEL_FLOPS = {
     "made_grad": MADE_GRAD, "sample": SAMPLE_FLOPS,
 }
 KERNEL_NAMES = {
-    "chain_fwd_2": "rchain_fwd_kernel<false, 2, 2>", "chain_fwd_1": "rchain_fwd_kernel<false, 1, 2>",
-    "chain_bwd_2": "rchain_bwd_kernel<2>", "chain_bwd_1": "rchain_bwd_kernel<1>",
+    "chain_fwd_2": "rchain_fwd_kernel<{mode}, 2, 2>", "chain_fwd_1": "rchain_fwd_kernel<{mode}, 1, 2>",
+    "chain_bwd_2": "rchain_bwd_kernel<2, {split}>", "chain_bwd_1": "rchain_bwd_kernel<1, {split}>",
     "made_grad": "mgrad_kernel<2, 16>", "sample": "msample_kernel<2, false>",
 }
 PEAK_FP32 = 157.3e12       # MI355X FP32 (vector and 16x16x4 matrix), published
+PEAK_BF16 = 2.5e15         # MI355X BF16 dense matrix, published
 
 
 def parse():
@@ -255,11 +256,15 @@ def main():
         dom = "chain_bwd_2"
         dom_avg = ktime[dom][0] / ktime[dom][1]
         achieved = KERNEL_FLOPS[dom] * nI * B / dom_avg
-        peak = PEAK_FP32   # FP32 matrix-core products in every precision but FP64
+        # the peak of the units the products run on: BF16 dense for split
+        # products (three BF16 products per algorithmic FP32 product, so at
+        # most a third of it is attainable), FP32 matrix otherwise
+        peak = PEAK_BF16 if split else PEAK_FP32
         roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": measured_traffic(dom),
-                    "kernel": KERNEL_NAMES[dom], "kernel_avg_s": dom_avg,
-                    "flops_per_launch": KERNEL_FLOPS[dom] * nI * B}
+                    "kernel": KERNEL_NAMES[dom].format(split=str(split).lower(), mode=2 if split else 0),
+                    "kernel_avg_s": dom_avg, "flops_per_launch": KERNEL_FLOPS[dom] * nI * B,
+                    "peak_units": "bf16 dense, 3 products per flop" if split else "fp32 matrix"}
     res = {
         "metric": METRIC,
         "value": value,
@@ -287,7 +292,8 @@ def main():
             "max_abs_dlogZ_per_N_vs_oracle": err,
             "max_abs_dlogZ_per_N_vs_fp64_path": err64,
             "wall_s_timed_region": wall,
-            "kernel_avg_us": {KERNEL_NAMES.get(k, k): 1e6 * t / n for k, (t, n) in ktime.items()},
+            "kernel_avg_us": {KERNEL_NAMES.get(k, k).format(split=str(split).lower(), mode=2 if split else 0): 1e6 * t / n
+                              for k, (t, n) in ktime.items()},
         },
     }
     if not args.no_cpu_baseline:
