@@ -394,10 +394,14 @@ __global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
     if (mi.n <= 128) {
       // spins as a bit mask read with uniform indices; the +-1 products are exact
       const SpinBits sb = load_bits_row(a.spins + mi.spin_off + b * mi.n, mi.n);
+      // unrolled: the wave-uniform couplings and indices of several terms
+      // are fetched together instead of one scalar round trip per term
+#pragma unroll 8
       for (int k = 0; k < D.n_ww; ++k) {
         const double j = wJ[k];
         e1 -= sb.sigma(wa[k]) * sb.sigma(wb[k]) > 0.f ? j : -j;
       }
+#pragma unroll 8
       for (int k = 0; k < mi.n; ++k) e1 -= sb.sigma(k) > 0.f ? hW[k] : -hW[k];
     } else {
       const int8_t *s = a.spins + mi.spin_off + b * mi.n;
