@@ -726,10 +726,10 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
   if (s) return s;
   // with the adjoint requested, logZ comes from its forward pass when the
   // net allows it (one contraction instead of two), else it follows the step
+  // (the free-energy kernel then sums the chain partials itself)
   const bool adj_logz = adj && logz_with_adjoint(net);
   if (adj_logz)
-    s = run_backward<real>(net, spins, adj->grad, adj->dh, adj->dJ, adj->dbeta, st,
-                           net->w_logz.as<double>());
+    s = run_backward<real>(net, spins, adj->grad, adj->dh, adj->dJ, adj->dbeta, st);
   else
     s = run_logz<real>(net, spins, net->w_logz.as<double>(), st);
   if (s) return s;
@@ -742,6 +742,13 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
   f.hw_off = net->d_hw_off.as<int32_t>();
   f.spins = spins;
   f.logz = net->w_logz.as<double>();
+  if (adj_logz) {
+    f.cinst = net->cinst.as<ChainInst>();
+    f.cpart_off = net->cpart_off.as<int64_t>();
+    f.cpart = net->cpart.as<double>();
+    f.f_off = net->f_off.as<int64_t>();
+    f.fabp = net->fabp.as<double>();
+  }
   f.logq = net->w_logq.as<real>();
   f.ww_a = net->ww_a.as<int32_t>();
   f.ww_b = net->ww_b.as<int32_t>();

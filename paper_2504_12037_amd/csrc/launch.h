@@ -193,6 +193,14 @@ struct FreeArgs {
   const int32_t *hw_off;     // per instance offset into hW
   const int8_t *spins;
   const double *logz;
+  // logZ from the chain partials instead (when cpart is set): log_const plus
+  // the instance's per-chain partials in chain order, then its unary sums,
+  // as launch_chain_sum
+  const ChainInst *cinst;
+  const int64_t *cpart_off;
+  const double *cpart;
+  const int64_t *f_off;
+  const double *fabp;
   const real *logq;
   const int32_t *ww_a, *ww_b;
   const double *ww_J;

@@ -409,7 +409,16 @@ __global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
       for (int k = 0; k < mi.n; ++k) e1 -= hW[k] * (double)s[k];
     }
     const int64_t g = mi.sample_off + b;
-    const double et = e1 - a.logz[g] / beta;
+    double lz;
+    if (a.cpart) {
+      lz = D.log_const;
+      for (int c = 0; c < a.cinst[q].n_chains; ++c) lz += a.cpart[a.cpart_off[q] + (int64_t)c * mi.B + b];
+      const int nf = (D.nr + kUnaryChunk - 1) / kUnaryChunk;
+      for (int c = 0; c < nf; ++c) lz += a.fabp[a.f_off[q] + (int64_t)c * mi.B + b];
+    } else {
+      lz = a.logz[g];
+    }
+    const double et = e1 - lz / beta;
     const double lqb = (double)a.logq[g] / beta;
     const double f = et + lqb;
     a.f[g] = f;
