@@ -18,7 +18,6 @@
 #include "launch.h"
 
 namespace tnvan {
-hipError_t zero_doubles(double *p, int64_t n, hipStream_t st);
 }
 
 using namespace tnvan;
@@ -115,8 +114,7 @@ struct tnvan_net {
   std::vector<int64_t> skey;
   // workspaces
   DBuf garena, partial, w_logz, w_logq, w_spins, w_f, w_fpart, w_hid, w_da, w_dlogit, w_sf,
-      w_part, d_hw_off, d_sum_off, sumP;
-  int64_t sum_total = 0;
+      w_part, d_hw_off, d_sum_off;
   int max_partial = 0;
   int sample_reps = 1;
   // transfer-matrix form (chain kernels, FP32 / BF16 precisions)
@@ -127,8 +125,7 @@ struct tnvan_net {
   // register-resident chain kernels (per-wave tasks)
   DBuf Tr, Tq, Trb, xcol, cf_w, cf_r, cf_J, Tsx, Ts3;
   bool split = false;   // TNVAN_FLAG_SPLIT_BF16 on an FP32 net
-  DBuf Ubuf, fabp, u_off, f_off, vjp_part, tickets, inv_v, inv_e, pcoef, vjp_bpart;
-  int max_out = 1;
+  DBuf Ubuf, fabp, u_off, f_off, vjp_part, tickets, inv_v, inv_e, pcoef;
   // training step replayed from a captured graph (TNVAN_FLAG_GRAPH)
   bool use_graph = false, capturing = false;
   hipStream_t cap_stream = nullptr;
@@ -158,6 +155,9 @@ struct tnvan_net {
   int mpt = 1;
   int64_t mpack_total = 0, mpack_max = 0;
   DBuf mpack, mtask_inst, mtask_start;
+  // the packed tables hold the current parameters: set by a full pack, kept
+  // by the optimiser (which writes them as it updates), cleared by an upload
+  bool pack_valid = false;
   int n_mtasks = 0;
   // fused REINFORCE backward
   bool mgrad = false;
@@ -599,19 +599,13 @@ tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *gra
   v.dJ = dJ;
   v.dbeta = dbeta;
   v.inst_sum_off = net->d_sum_off.as<int64_t>();
-  HIPCHK(net->sumP.ensure(std::max<int64_t>(1, net->sum_total) * sizeof(double)));
-  v.sumP = net->sumP.as<double>();
   HIPCHK(net->vjp_part.ensure((size_t)std::max(1, net->n_inst * vjp_split() * net->max_partial) *
                               sizeof(double)));
   v.part2 = net->vjp_part.as<double>();
   v.maxp = net->max_partial;
-  v.max_out = net->max_out;
   v.inv_v = net->inv_v.as<int32_t>();
   v.inv_e = net->inv_e.as<int32_t>();
   v.pcoef = net->pcoef.as<double>();
-  HIPCHK(net->vjp_bpart.ensure((size_t)net->n_inst * vjp_finish_blocks(net->max_out) * sizeof(double)));
-  v.bpart = net->vjp_bpart.as<double>();
-  v.done = net->tickets.as<int32_t>() + 2 * net->n_inst;
   HIPCHK(launch_vjp_reduce<real>(v, net->partial.as<real>(), net->n_inst, net->max_partial, st));
   return TNVAN_OK;
 }
@@ -666,10 +660,16 @@ tnvan_status run_sample(tnvan_net *net, const float *uniforms, int8_t *spins, vo
   tnvan_status s = ensure_sample_blocks(net);
   if (s) return s;
   if ((net->msample || net->mgrad) && sizeof(real) == 4) {
-    // parameters repacked for the matrix-core sampler and backward
+    // parameters repacked for the matrix-core sampler and backward, unless
+    // the tables already hold them
+    const void *had = net->mpack.p;
     HIPCHK(net->mpack.ensure((std::max<int64_t>(1, net->mpack_total) + 16) * sizeof(float)));
-    HIPCHK(launch_made_pack(net->d_mi.as<MadeInst>(), net->n_inst, net->mpack_max,
-                            net->params.as<float>(), net->mpack.as<float>(), net->mpt, st));
+    if (net->mpack.p != had) net->pack_valid = false;
+    if (!net->pack_valid) {
+      HIPCHK(launch_made_pack(net->d_mi.as<MadeInst>(), net->n_inst, net->mpack_max,
+                              net->params.as<float>(), net->mpack.as<float>(), net->mpt, st));
+      net->pack_valid = true;
+    }
   }
   if (net->msample && sizeof(real) == 4) {
     MSampleArgs m{};
@@ -760,7 +760,23 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
   f.part = net->w_fpart.as<double>();
   f.stats = stats;
   f.done = net->tickets.as<int32_t>();
+  f.step_ctr = net->step_ctr.as<int32_t>();
   HIPCHK(launch_free<real>(f, net->n_inst, st));
+  // Adam on every instance and the step counters (one launch, or inside the
+  // fused backward's reduction)
+  OptArgs o{};
+  o.mi = net->d_mi.as<MadeInst>();
+  o.params = net->params.as<float>();
+  o.grad = net->grad.as<float>();
+  o.m = net->adam_m.as<float>();
+  o.v = net->adam_v.as<float>();
+  o.pack = (net->msample || net->mgrad) && sizeof(real) == 4 ? net->mpack.as<float>() : nullptr;
+  o.npt = net->mpt;
+  o.lr = lr;
+  o.step_ctr = net->step_ctr.as<int32_t>();
+  o.part2 = nullptr;
+  o.pstride = net->mg_pstride;
+  o.nsplit = mgrad_split();
   if (net->mgrad && sizeof(real) == 4) {
     // fused REINFORCE backward of every instance (Eq. 10)
     HIPCHK(net->w_part.ensure(std::max<int64_t>(1, (int64_t)net->n_mgtasks * net->mg_pstride) *
@@ -789,6 +805,7 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
       HIPCHK(launch_mgrad(g, net->mpt, st));
     }
     HIPCHK(launch_mgrad_reduce(g, st));
+    o.part2 = g.part2;
   }
   const bool fused = net->mgrad && sizeof(real) == 4;
   for (int q = 0; q < net->n_inst && !fused; ++q) {
@@ -827,22 +844,11 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     HIPCHK(launch_atb<real>(r.dlogit, n, r.sf, n, m.B, n, n, part, ks, gW0, n, 2, n, st));
     HIPCHK(launch_colsum<real>(r.dlogit, n, m.B, n, part, ks, gb2, st));
   }
-  // Adam on every instance and the step counters, one launch
-  OptArgs o{};
-  o.mi = net->d_mi.as<MadeInst>();
-  o.params = net->params.as<float>();
-  o.grad = net->grad.as<float>();
-  o.m = net->adam_m.as<float>();
-  o.v = net->adam_v.as<float>();
-  o.part2 = fused ? net->w_part2.as<float>() : nullptr;
-  o.pstride = net->mg_pstride;
-  o.nsplit = mgrad_split();
-  o.lr = lr;
-  o.step_ctr = net->step_ctr.as<int32_t>();
-  o.done = net->tickets.as<int32_t>() + net->n_inst;
-  int64_t max_pc = 1;
-  for (auto pc : net->param_count) max_pc = std::max(max_pc, pc);
-  HIPCHK(launch_adam_step(o, net->n_inst, max_pc, st));
+  {
+    int64_t max_pc = 1;
+    for (auto pc : net->param_count) max_pc = std::max(max_pc, pc);
+    HIPCHK(launch_adam_step(o, net->n_inst, max_pc, st));
+  }
   if (adj && !adj_logz) return run_backward<real>(net, spins, adj->grad, adj->dh, adj->dJ, adj->dbeta, st);
   return TNVAN_OK;
 }
@@ -969,7 +975,6 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
       tot += P.insts[q].n_partial;
       net->max_partial = std::max(net->max_partial, (int)P.insts[q].n_partial);
     }
-    net->sum_total = tot;
     UP(d_sum_off, so)
   }
   UP(d_mi, net->mi)
@@ -983,10 +988,10 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
       (e = hipMemset(net->adam_v.p, 0, pb)) || (e = hipMemset(net->grad.p, 0, pb)) ||
       (e = hipMemset(net->step_ctr.p, 0, sizeof(int32_t) * n_inst)))
     return fail(e, "parameter init");
-  // completion tickets of the last-block reductions (free energy, optimiser,
-  // adjoint): zero between launches, each launch resets what it used
-  if ((e = net->tickets.ensure(sizeof(int32_t) * 3 * n_inst)) ||
-      (e = hipMemset(net->tickets.p, 0, sizeof(int32_t) * 3 * n_inst)))
+  // completion tickets of the free-energy kernel's last-block reduction:
+  // zero between launches, each launch resets what it used
+  if ((e = net->tickets.ensure(sizeof(int32_t) * n_inst)) ||
+      (e = hipMemset(net->tickets.p, 0, sizeof(int32_t) * n_inst)))
     return fail(e, "tickets");
   {
     std::vector<float> fj(P.fld_J.begin(), P.fld_J.end()), hr(P.hR.begin(), P.hR.end());
@@ -996,7 +1001,6 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   UP2(Tl, P.Tl) UP2(Tbl, P.Tbl) UP2(cedges, P.cedges)
   UP2(Tr, P.Tr) UP2(Tq, P.Tq) UP2(Trb, P.Trb) UP2(xcol, P.xcol)
   UP2(inv_v, P.inv_v) UP2(inv_e, P.inv_e) UP2(pcoef, P.pcoef)
-  for (auto &D : P.insts) net->max_out = std::max(net->max_out, (int)(D.n + D.n_edges));
   UP2(cf_w, P.cf_w) UP2(cf_r, P.cf_r) UP2(cf_J, P.cf_J) UP2(Tsx, P.Tsx) UP2(Ts3, P.Ts3)
   // transfer-matrix form: instances whose program is a set of dense chains
   // (FP32 / BF16 only); the launch-wide maxima size the LDS layout
@@ -1085,14 +1089,14 @@ void tnvan_free_network(tnvan_net *net) {
                  &net->d_spin_off, &net->d_spin_base, &net->d_edge_base, &net->blk_inst,
                  &net->blk_start, &net->garena, &net->partial, &net->w_logz, &net->w_logq,
                  &net->w_spins, &net->w_f, &net->w_fpart, &net->w_hid, &net->w_da, &net->d_hw_off,
-                 &net->d_sum_off, &net->sumP,
+                 &net->d_sum_off,
                  &net->w_dlogit, &net->w_sf, &net->w_part, &net->cinst, &net->chains,
                  &net->csteps, &net->Tp, &net->Tt, &net->Tb, &net->fld_wr, &net->fld_J32,
                  &net->hR32, &net->task_inst, &net->task_chain, &net->task_start,
                  &net->btask_inst, &net->btask_chain, &net->btask_start, &net->Tl, &net->Tbl,
                  &net->cedges, &net->ckpt, &net->Tr, &net->Tq, &net->Trb, &net->xcol,
                  &net->cf_w, &net->cf_r, &net->cf_J, &net->Tsx, &net->Ts3, &net->Ubuf, &net->vjp_part,
-                 &net->tickets, &net->inv_v, &net->inv_e, &net->pcoef, &net->vjp_bpart, &net->fabp, &net->u_off,
+                 &net->tickets, &net->inv_v, &net->inv_e, &net->pcoef, &net->fabp, &net->u_off,
                  &net->f_off,
                  &net->mpack, &net->mtask_inst, &net->mtask_start, &net->mg_task_inst,
                  &net->mg_task_start, &net->mg_first, &net->mg_count, &net->w_part2,
@@ -1123,6 +1127,10 @@ tnvan_status tnvan_set_params(tnvan_net *net, int32_t inst, const float *src, vo
   HIPCHK(hipMemsetAsync(net->adam_m.as<float>() + off, 0, bytes, st));
   HIPCHK(hipMemsetAsync(net->adam_v.as<float>() + off, 0, bytes, st));
   HIPCHK(hipMemsetAsync(net->step_ctr.as<int32_t>() + inst, 0, sizeof(int32_t), st));
+  // the packed tables are rebuilt from the new parameters at the next use,
+  // and a recorded step (which does not repack) is recorded again
+  net->pack_valid = false;
+  g_buf_gen.fetch_add(1);
   return TNVAN_OK;
 }
 

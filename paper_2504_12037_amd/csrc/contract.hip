@@ -471,103 +471,42 @@ __global__ __launch_bounds__(256) void vjp_colsum_kernel(VjpArgs a, const real *
     a.part2[((int64_t)q * kColSplit + sp) * a.maxp + k] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
 }
 
-__global__ void vjp_colsum_finish(VjpArgs a) {
-  const int q = blockIdx.y;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= a.inst[q].n_partial) return;
-  double s = 0.0;
-#pragma unroll 8
-  for (int sp = 0; sp < kColSplit; ++sp) s += a.part2[((int64_t)q * kColSplit + sp) * a.maxp + k];
-  a.sumP[a.inst_sum_off[q] + k] = s;
-}
-
-// Every output of the adjoint in one launch: dh over the instance's
-// vertices and dJ over its edges, each the fixed-order sum of the split
-// column sums of its partial column times beta (0 on W vertices and W-W
-// edges), and dbeta = sum over columns of coefficient x column sum (block
-// sums, then the last block of the instance in block order).
-__global__ __launch_bounds__(256) void vjp_finish_kernel(VjpArgs a) {
-  __shared__ double sh[256];
-  __shared__ int last;
-  const int q = blockIdx.y;
+// Every output of the adjoint in one launch, one block per instance: dh
+// over the instance's vertices and dJ over its edges, each the fixed-order
+// sum of the split column sums of its partial column times beta (0 on W
+// vertices and W-W edges), and dbeta = sum over columns of coefficient x
+// column sum (per-thread sums in index order, then a fixed tree).
+constexpr int kFinishThreads = 1024;
+__global__ __launch_bounds__(kFinishThreads) void vjp_finish_kernel(VjpArgs a) {
+  __shared__ double sh[kFinishThreads];
+  const int q = blockIdx.x;
   const InstDesc D = a.inst[q];
   const int64_t vb = a.inst_spin_base[q], eb = a.inst_edge_base[q];
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const double *p2 = a.part2 + (int64_t)q * kColSplit * a.maxp;
   double contrib = 0.0;
-  if (idx < D.n + D.n_edges) {
+  for (int idx = threadIdx.x; idx < D.n + D.n_edges; idx += kFinishThreads) {
     const int k = idx < D.n ? a.inv_v[vb + idx] : a.inv_e[eb + idx - D.n];
     double S = 0.0;
     if (k >= 0) {
-      for (int sp = 0; sp < kColSplit; ++sp) S += a.part2[((int64_t)q * kColSplit + sp) * a.maxp + k];
-      contrib = a.pcoef[a.inst_sum_off[q] + k] * S;
+      double c[kColSplit];
+#pragma unroll
+      for (int sp = 0; sp < kColSplit; ++sp) c[sp] = p2[(int64_t)sp * a.maxp + k];
+#pragma unroll
+      for (int sp = 0; sp < kColSplit; ++sp) S += c[sp];
+      contrib += a.pcoef[a.inst_sum_off[q] + k] * S;
     }
     if (idx < D.n) a.dh[vb + idx] = D.beta * S;
     else a.dJ[eb + idx - D.n] = D.beta * S;
   }
   sh[threadIdx.x] = contrib;
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
-    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    a.bpart[(int64_t)q * gridDim.x + blockIdx.x] = sh[0];
-    __threadfence();
-    last = atomicAdd(a.done + q, 1) == (int)gridDim.x - 1;
-    if (last) atomicExch(a.done + q, 0);
-  }
-  __syncthreads();
-  if (!last || threadIdx.x != 0) return;
-  __threadfence();
-  double db = 0.0;
-  for (int b = 0; b < (int)gridDim.x; ++b)
-    db += __hip_atomic_load(a.bpart + (int64_t)q * gridDim.x + b, __ATOMIC_RELAXED,
-                            __HIP_MEMORY_SCOPE_AGENT);
-  a.dbeta[q] = db;
-}
-
-// dh, dJ from the column sums (times beta); W vertices and W-W edges stay 0
-__global__ void vjp_scatter_kernel(VjpArgs a) {
-  const int q = blockIdx.y;
-  const InstDesc D = a.inst[q];
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= D.n_partial) return;
-  double *dh = a.dh + a.inst_spin_base[q];
-  double *dJ = a.dJ + a.inst_edge_base[q];
-  const double v = D.beta * a.sumP[a.inst_sum_off[q] + k];
-  if (k < D.nr) dh[a.vr[D.vr_off + k]] = v;
-  else if (k < D.nr + D.n_wr) dJ[a.wr_edge[D.wr_off + k - D.nr]] = v;
-  else dJ[a.rr_edge[D.rr_off + k - D.nr - D.n_wr]] = v;
-}
-
-// dbeta = -<E_2> weighted = sum_RR J C + sum_R h U + sum_WR J UW
-__global__ __launch_bounds__(256) void vjp_beta_kernel(VjpArgs a) {
-  __shared__ double sh[256];
-  const int q = blockIdx.x;
-  const InstDesc D = a.inst[q];
-  const double *sp = a.sumP + a.inst_sum_off[q];
-  double acc = 0.0;
-  for (int k = threadIdx.x; k < D.n_partial; k += blockDim.x) {
-    double coef;
-    if (k < D.nr) coef = a.hR[D.hr_off + k];
-    else if (k < D.nr + D.n_wr) coef = a.wr_J[D.wr_off + k - D.nr];
-    else coef = a.rr_J[D.rr_off + k - D.nr - D.n_wr];
-    acc += coef * sp[k];
-  }
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
+  for (int st = kFinishThreads / 2; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
     __syncthreads();
   }
   if (threadIdx.x == 0) a.dbeta[q] = sh[0];
 }
 
-__global__ void zero_kernel(double *p, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0.0;
-}
 
 }  // namespace
 
@@ -600,20 +539,12 @@ hipError_t launch_vjp_reduce(const VjpArgs &a, const real *partial, int n_inst, 
   if (n_inst <= 0 || max_partial <= 0) return hipSuccess;
   hipLaunchKernelGGL(vjp_colsum_kernel<real>, dim3((max_partial + 63) / 64, kColSplit, n_inst),
                      dim3(256), 0, st, a, partial);
-  hipLaunchKernelGGL(vjp_finish_kernel, dim3((a.max_out + 255) / 256, n_inst), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(vjp_finish_kernel, dim3(n_inst), dim3(kFinishThreads), 0, st, a);
   return hipGetLastError();
 }
 
 int vjp_split() { return kColSplit; }
-int vjp_finish_blocks(int max_out) { return (max_out + 255) / 256; }
 
-hipError_t zero_doubles(double *p, int64_t n, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  int blocks = (int)((n + 255) / 256);
-  if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, st, p, n);
-  return hipGetLastError();
-}
 
 template hipError_t launch_contract<float>(const ContractArgs<float> &, int, size_t, bool, bool, hipStream_t);
 template hipError_t launch_contract<double>(const ContractArgs<double> &, int, size_t, bool, bool, hipStream_t);

@@ -67,19 +67,14 @@ struct VjpArgs {
   const int64_t *inst_partial_off;
   const int64_t *inst_spin_base;   // offset of instance i in dh (sum of n)
   const int64_t *inst_edge_base;   // offset of instance i in dJ
-  const int64_t *inst_sum_off;     // offset of instance i in sumP
-  double *sumP;                    // column sums of the partial rows
+  const int64_t *inst_sum_off;     // offset of instance i in pcoef
   double *dh, *dJ, *dbeta;
   double *part2;                   // [n_inst][vjp_split()][maxp] split sums
   int32_t maxp;                    // largest n_partial
-  int32_t max_out;                 // largest n_spins + n_edges
   const int32_t *inv_v, *inv_e;    // vertex / edge -> partial column (-1: none)
   const double *pcoef;             // dbeta coefficient of every partial column
-  double *bpart;                   // [n_inst][vjp_finish_blocks()] block sums
-  int32_t *done;                   // [n_inst] completion tickets
 };
 int vjp_split();
-int vjp_finish_blocks(int max_out);
 template <typename real>
 hipError_t launch_vjp_reduce(const VjpArgs &a, const real *partial, int n_inst, int max_partial,
                              hipStream_t st);
@@ -210,13 +205,10 @@ struct FreeArgs {
   int32_t nblk;
   double *stats;             // out [n_inst][4]
   int32_t *done;             // [n_inst] completion tickets, zero between launches
+  int32_t *step_ctr;         // advanced by one per instance, or null
 };
 template <typename real>
 hipError_t launch_free(const FreeArgs<real> &a, int n_inst, hipStream_t st);
-
-hipError_t launch_adam(float *params, const float *grad, float *m, float *v,
-                       int64_t n, float lr, int32_t *step_ctr, hipStream_t st);
-hipError_t launch_bump(int32_t *step_ctr, int n, hipStream_t st);
 
 // One optimiser step of every instance (see adam_step_kernel).
 struct OptArgs {
@@ -225,9 +217,10 @@ struct OptArgs {
   const float *part2;        // split gradient rows [n_inst][nsplit][pstride], or null
   int64_t pstride;
   int32_t nsplit;
+  float *pack;               // packed operand tables kept current, or null
+  int32_t npt;               // position tiles of the packed tables
   float lr;
-  int32_t *step_ctr;
-  int32_t *done;             // [n_inst] completion tickets, zero between launches
+  const int32_t *step_ctr;   // already counting this step
 };
 hipError_t launch_adam_step(const OptArgs &a, int n_inst, int64_t max_pc, hipStream_t st);
 

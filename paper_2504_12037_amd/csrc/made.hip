@@ -70,6 +70,7 @@ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
 }
 
 constexpr int kRedSplit = 16;   // row splits of the REINFORCE gradient reduction
+constexpr int kFreeStage = 2048;   // W-W couplings staged in LDS by the free-energy kernel
 constexpr int KH = 16;    // hidden units per lane
 constexpr int KN = 32;    // width-set positions per lane
 
@@ -388,21 +389,36 @@ __global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
   const int32_t *wa = a.ww_a + D.ww_off, *wb = a.ww_b + D.ww_off;
   const double *wJ = a.ww_J + D.ww_off, *hW = a.hW + a.hw_off[q];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  // the first kFreeStage W-W couplings (endpoints packed in one word) and
+  // the W fields staged in LDS once per block: the per-sample loops then
+  // read them without a memory round trip per batch of terms
+  __shared__ int32_t s_ab[kFreeStage];
+  __shared__ double s_J[kFreeStage], s_h[128];
+  const int nst = mi.n <= 128 ? min(D.n_ww, kFreeStage) : 0;
+  for (int k = tid; k < nst; k += blockDim.x) {
+    s_ab[k] = wa[k] | (wb[k] << 16);
+    s_J[k] = wJ[k];
+  }
+  for (int k = tid; k < mi.n && k < 128; k += blockDim.x) s_h[k] = hW[k];
+  __syncthreads();
   for (int64_t b = (int64_t)blockIdx.x * blockDim.x + tid; b < mi.B;
        b += (int64_t)gridDim.x * blockDim.x) {
     double e1 = 0.0;
     if (mi.n <= 128) {
-      // spins as a bit mask read with uniform indices; the +-1 products are exact
+      // spins as a bit mask; the +-1 products are exact
       const SpinBits sb = load_bits_row(a.spins + mi.spin_off + b * mi.n, mi.n);
-      // unrolled: the wave-uniform couplings and indices of several terms
-      // are fetched together instead of one scalar round trip per term
 #pragma unroll 8
-      for (int k = 0; k < D.n_ww; ++k) {
+      for (int k = 0; k < nst; ++k) {
+        const int ab = s_ab[k];
+        const double j = s_J[k];
+        e1 -= sb.sigma(ab & 0xffff) * sb.sigma(ab >> 16) > 0.f ? j : -j;
+      }
+      for (int k = nst; k < D.n_ww; ++k) {
         const double j = wJ[k];
         e1 -= sb.sigma(wa[k]) * sb.sigma(wb[k]) > 0.f ? j : -j;
       }
 #pragma unroll 8
-      for (int k = 0; k < mi.n; ++k) e1 -= sb.sigma(k) > 0.f ? hW[k] : -hW[k];
+      for (int k = 0; k < mi.n; ++k) e1 -= sb.sigma(k) > 0.f ? s_h[k] : -s_h[k];
     } else {
       const int8_t *s = a.spins + mi.spin_off + b * mi.n;
       for (int k = 0; k < D.n_ww; ++k) e1 -= wJ[k] * (double)s[wa[k]] * (double)s[wb[k]];
@@ -439,7 +455,13 @@ __global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
     __threadfence();
     const int prev = atomicAdd(a.done + q, 1);
     last = prev == (int)gridDim.x - 1;
-    if (last) atomicExch(a.done + q, 0);
+    if (last) {
+      atomicExch(a.done + q, 0);
+      // the step's sampler (the counter's reader) has run: the step counter
+      // advances here, and the optimiser then reads the step's own number
+      // (an atomic add whose result is unused: nothing waits for a load)
+      if (a.step_ctr) atomicAdd(a.step_ctr + q, 1);
+    }
   }
   __syncthreads();
   if (!last || mi.B <= 0) return;
@@ -468,68 +490,60 @@ __global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
   a.stats[4 * q + 3] = sm[3] / Bd;
 }
 
+// Adam (Kingma & Ba; beta1 = 0.9, beta2 = 0.999, eps = 1e-8) on one
+// parameter, with the bias corrections c1 = 1 - 0.9^t, c2 = 1 - 0.999^t of
+// step t taken in FP64.  Masked parameters have zero gradient, so they and
+// their moments never move.
+__device__ inline void adam_one(float gi, float &p, float &m, float &v, double c1, double c2,
+                                float lr) {
+  m = 0.9f * m + 0.1f * gi;
+  v = 0.999f * v + 0.001f * gi * gi;
+  const double mh = (double)m / c1, vh = (double)v / c2;
+  p = (float)((double)p - (double)lr * mh / (sqrt(vh) + 1e-8));
+}
+
+__device__ inline void pack_scatter(float *P, int n, int Hs, int npt, int64_t i, float v);
+
 // Adam for every instance in one launch (grid.y = instance).  The gradient
 // is either the flat gradient buffer or, after the fused REINFORCE backward,
-// the fixed-order sum of its split rows (then also stored as the gradient).
-// The last block of an instance (completion ticket) advances its step
-// counter, after every block has read it.
+// the fixed-order FP64 sum of its split rows (then also stored as the
+// gradient).  The step counter already counts this step (the free-energy
+// kernel advanced it).  With pack set, each updated parameter is also
+// written into the packed operand tables (pack_scatter), which then stay
+// current.
 __global__ __launch_bounds__(256) void adam_step_kernel(OptArgs a) {
   const int q = blockIdx.y;
   const MadeInst mi = a.mi[q];
+  // an instance without samples this step keeps its parameters and moments
+  if (mi.B <= 0) return;
   const int64_t pc = (int64_t)mi.H * mi.n + mi.H + (int64_t)mi.n * mi.H + mi.n + (int64_t)mi.n * mi.n;
-  const double t = (double)(a.step_ctr[q] + 1);
-  const double c1 = 1.0 - pow(0.9, t), c2 = 1.0 - pow(0.999, t);
   float *P = a.params + mi.param_off, *G = a.grad + mi.param_off, *M = a.m + mi.param_off,
         *V = a.v + mi.param_off;
-  // an instance without samples this step keeps its parameters and moments
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; mi.B > 0 && i < pc;
+  const float *p2 = a.part2 ? a.part2 + (int64_t)q * kRedSplit * a.pstride : nullptr;
+  const double t = (double)a.step_ctr[q];
+  const double c1 = 1.0 - pow(0.9, t), c2 = 1.0 - pow(0.999, t);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < pc;
        i += (int64_t)gridDim.x * blockDim.x) {
-    float gi;
-    if (a.part2) {
+    // every load first, then the stores
+    float p = P[i], m = M[i], v = V[i], gi;
+    if (p2) {
+      float z[kRedSplit];
+#pragma unroll
+      for (int k = 0; k < kRedSplit; ++k) z[k] = p2[(int64_t)k * a.pstride + i];
       double acc = 0.0;
 #pragma unroll
-      for (int z = 0; z < kRedSplit; ++z) acc += (double)a.part2[((int64_t)q * kRedSplit + z) * a.pstride + i];
+      for (int k = 0; k < kRedSplit; ++k) acc += (double)z[k];
       gi = (float)acc;
       G[i] = gi;
     } else {
       gi = G[i];
     }
-    const float mv = 0.9f * M[i] + 0.1f * gi;
-    const float vv = 0.999f * V[i] + 0.001f * gi * gi;
-    M[i] = mv;
-    V[i] = vv;
-    const double mh = (double)mv / c1, vh = (double)vv / c2;
-    P[i] = (float)((double)P[i] - (double)a.lr * mh / (sqrt(vh) + 1e-8));
+    adam_one(gi, p, m, v, c1, c2, a.lr);
+    M[i] = m;
+    V[i] = v;
+    P[i] = p;
+    if (a.pack) pack_scatter(a.pack + mi.pack_off, mi.n, mi.H, a.npt, i, p);
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    if (atomicAdd(a.done + q, 1) == (int)gridDim.x - 1) {
-      atomicAdd(a.step_ctr + q, 1);
-      atomicExch(a.done + q, 0);
-    }
-  }
-}
-
-__global__ void adam_kernel(float *p, const float *g, float *m, float *v, int64_t n,
-                            float lr, const int32_t *step_ctr) {
-  const double t = (double)(*step_ctr + 1);
-  const double c1 = 1.0 - pow(0.9, t), c2 = 1.0 - pow(0.999, t);
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const float gi = g[i];
-    const float mi = 0.9f * m[i] + 0.1f * gi;
-    const float vi = 0.999f * v[i] + 0.001f * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    const double mh = (double)mi / c1, vh = (double)vi / c2;
-    p[i] = (float)((double)p[i] - (double)lr * mh / (sqrt(vh) + 1e-8));
-  }
-}
-
-__global__ void bump_kernel(int32_t *c, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) c[i] += 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -620,6 +634,59 @@ __global__ void made_pack_kernel(const MadeInst *mi, const float *params, float 
     }
     P[idx] = v;
   }
+}
+
+// Parameter i of an instance (flat index into W1, b1, W2, b2, W0) written
+// into every slot of the packed tables that made_pack_kernel fills from it:
+// the inverse of that kernel's gather.  Slots it leaves zero never hold a
+// parameter, so after one full pack these writes keep the tables equal to a
+// fresh pack of the current parameters.
+__device__ inline void pack_scatter(float *P, int n, int Hs, int npt, int64_t i, float v) {
+  const int H = n >= 2 ? Hs : 0;
+  const int64_t hn = (int64_t)Hs * n, sa = (int64_t)n * npt * 256, sb = (int64_t)n * 256;
+  const int64_t tsamp = msample_floats(n, npt);
+  // slot r of lane l in position tile t of step i0
+  auto at = [&](int i0, int t, int l, int r) { return (((int64_t)i0 * npt + t) * 64 + l) * 4 + r; };
+  if (i < hn) {                          // W1[k][j], j below the degree of k
+    const int k = (int)(i / n), j = (int)(i % n);
+    if (k >= H) return;
+    const int i0 = k % (n - 1), u = k / (n - 1);
+    if (j > i0) return;
+    P[tsamp + hn + i] = v;               // W1m
+    if (u < 15) P[at(i0, j >> 4, 16 * ((j & 15) >> 2) + u, j & 3)] = v;   // PA
+    return;
+  }
+  i -= hn;
+  if (i < Hs) {                          // b1[k]: one slot per sample lane
+    const int k = (int)i;
+    if (k >= H) return;
+    const int i0 = k % (n - 1), u = k / (n - 1);
+    if (u >= 15) return;
+    for (int ls = 0; ls < 16; ++ls) P[2 * sa + ((int64_t)i0 * 64 + 16 * (u >> 2) + ls) * 4 + (u & 3)] = v;
+    return;
+  }
+  i -= Hs;
+  if (i < hn) {                          // W2[pos][k], pos above the degree of k
+    const int pos = (int)(i / Hs), k = (int)(i % Hs);
+    if (k >= H) return;
+    const int i0 = k % (n - 1), u = k / (n - 1);
+    if (pos <= i0) return;
+    P[tsamp + (int64_t)k * n + pos] = v;     // W2T
+    P[tsamp + 2 * hn + i] = v;               // W2m
+    if (u < 15) P[sa + at(i0, pos >> 4, 16 * (u >> 2) + (pos & 15), u & 3)] = v;   // PZ
+    return;
+  }
+  i -= hn;
+  if (i < n) {                           // b2[pos]: one slot per sample lane
+    const int pos = (int)i;
+    for (int ls = 0; ls < 16; ++ls)
+      P[2 * sa + sb + ((int64_t)(pos >> 4) * 64 + 16 * ((pos & 15) >> 2) + ls) * 4 + (pos & 3)] = v;
+    return;
+  }
+  i -= n;                                // W0[ip][i0], ip > i0: PZ slot 15
+  const int ip = (int)(i / n), i0 = (int)(i % n);
+  if (ip <= i0) return;
+  P[sa + at(i0, ip >> 4, 48 + (ip & 15), 3)] = v;
 }
 
 template <int NPT, bool kU>
@@ -1044,8 +1111,9 @@ __global__ __launch_bounds__(256, 2) void mgrad_kernel(MGradArgs a) {
 }
 
 // Sum of the instance's workgroup rows in a fixed order, in two passes:
-// slice z of the rows (rows r0 + z, r0 + z + kRedSplit, ...) into part2[q][z],
-// then the kRedSplit slices into grad.  Four parameters per thread.
+// slice z of the rows (rows r0 + z, r0 + z + kRedSplit, ...) into part2[q][z]
+// here, then the kRedSplit slices in the optimiser.  Four parameters per
+// thread.
 __device__ inline int64_t made_pc(const MadeInst &m) {
   return (int64_t)m.H * m.n + m.H + (int64_t)m.n * m.H + m.n + (int64_t)m.n * m.n;
 }
@@ -1061,18 +1129,6 @@ __global__ void mgrad_reduce1(const MadeInst *mi, const int32_t *first_row, cons
   for (int r = z; r < nr; r += kRedSplit)
     acc += *reinterpret_cast<const f4 *>(part + (int64_t)(r0 + r) * pstride + p);
   *reinterpret_cast<f4 *>(part2 + ((int64_t)q * kRedSplit + z) * pstride + p) = acc;
-}
-__global__ void mgrad_reduce2(const MadeInst *mi, const float *part2, int64_t pstride,
-                              float *grad) {
-  const int q = blockIdx.y;
-  const MadeInst m = mi[q];
-  const int64_t pc = made_pc(m);
-  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (p >= pc) return;
-  double acc = 0.0;
-#pragma unroll
-  for (int z = 0; z < kRedSplit; ++z) acc += (double)part2[((int64_t)q * kRedSplit + z) * pstride + p];
-  grad[m.param_off + p] = (float)acc;
 }
 
 template <int NPT>
@@ -1219,26 +1275,11 @@ hipError_t launch_free(const FreeArgs<real> &a, int n_inst, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_adam(float *params, const float *grad, float *m, float *v, int64_t n,
-                       float lr, int32_t *step_ctr, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  int blocks = (int)((n + 255) / 256);
-  if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(adam_kernel, dim3(blocks), dim3(256), 0, st, params, grad, m, v, n, lr,
-                     step_ctr);
-  return hipGetLastError();
-}
-
 hipError_t launch_adam_step(const OptArgs &a, int n_inst, int64_t max_pc, hipStream_t st) {
   if (n_inst <= 0) return hipSuccess;
   if (a.part2 && a.nsplit != kRedSplit) return hipErrorInvalidValue;
   const int bx = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (max_pc + 255) / 256));
   hipLaunchKernelGGL(adam_step_kernel, dim3(bx, n_inst), dim3(256), 0, st, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_bump(int32_t *step_ctr, int n, hipStream_t st) {
-  hipLaunchKernelGGL(bump_kernel, dim3((n + 255) / 256), dim3(256), 0, st, step_ctr, n);
   return hipGetLastError();
 }
 

@@ -183,3 +183,86 @@ def test_free_energy_step_graph_replay():
             assert torch.isfinite(lz).all()
     for k in range(len(insts)):
         assert torch.equal(nets[0].get_params(k), nets[1].get_params(k))
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_training_steps_track_the_oracle(graph):
+    # several iterations of Algorithm 1 on the GPU beside the FP64 oracle's
+    # own run from the same start (its own spins, logZ, gradients and Adam
+    # state).  Between steps the optimiser keeps the sampler's packed tables
+    # current; a parameter upload in the middle restarts instance 0 (new
+    # parameters, moments and step counter) and must take effect at once,
+    # also for a recorded step.
+    from paper_2504_12037_amd import Net
+    insts = [S.c1_small_lattice(16),
+             S.lattice_column_split(S.lattice_2d(12, seed=6), [5, 9], hidden=32)]
+    Bs = [512, 256]
+    seed, lr = 41, 1e-2
+    net = _net(insts, "fp32", seed=seed, flags=Net.FLAG_GRAPH if graph else 0)
+    ora = []
+
+    def restart(k, th):
+        net.set_params(k, torch.from_numpy(th))
+        z = np.zeros(th.shape, np.float64)
+        if k < len(ora):
+            ora[k] = [th.astype(np.float64), z, z.copy(), 0]
+        else:
+            ora.append([th.astype(np.float64), z, z.copy(), 0])
+
+    for k, inst in enumerate(insts):
+        restart(k, _theta(inst.n_width, inst.hidden, 60 + k, 0.2))
+    spins = torch.empty(sum(b * i.n_width for b, i in zip(Bs, insts)), dtype=torch.int8,
+                        device="cuda")
+    stats = torch.empty(len(insts), 4, dtype=torch.float64, device="cuda")
+    ties = 0
+    for it in range(6):
+        if it == 3:
+            restart(0, _theta(insts[0].n_width, insts[0].hidden, 70, 0.3))
+        print(f"\n[train] graph={graph} iteration {it}", flush=True)
+        net.free_energy_step(Bs, lr, stats=stats, spins_out=spins)
+        torch.cuda.synchronize()
+        sp_all, st_all = spins.cpu().numpy(), stats.cpu().numpy()
+        off = 0
+        for k, (inst, b) in enumerate(zip(insts, Bs)):
+            n, H = inst.n_width, inst.hidden
+            sp = sp_all[off:off + b * n].reshape(b, n)
+            off += b * n
+            th, m, v, t = ora[k]
+            u = OP.sampler_uniforms(seed, t, k, b, n)
+            nt, lq = _check_spins(th, u, n, H, sp)
+            ties += nt
+            lz = (OI.logz_r_bruteforce if len(inst.order) <= 16 else OI.logz_r_elimination)(inst, sp)
+            f, st = OO.free_energy_terms(inst, sp, lq, lz)
+            np.testing.assert_allclose(st_all[k], st, atol=2e-4, rtol=2e-5)
+            g = OM.logq_backward(th, sp, OO.reinforce_weights(f), n, H)
+            g_gpu = net.get_state(k, 1).cpu().numpy()
+            assert np.abs(g_gpu - g).max() <= 1e-6 + 1e-4 * np.abs(g).max(), (it, k)
+            th, m, v = OO.adam_step(th, g, m, v, t + 1, lr)
+            ora[k] = [th, m, v, t + 1]
+            d = np.abs(net.get_params(k).cpu().numpy() - th).max()
+            print(f"[train] it={it} inst={k} max|theta_gpu - theta_oracle|={d:.2e}", flush=True)
+            assert d <= 1e-4, (it, k, d)
+    print(f"[train] near-ties adopted: {ties}", flush=True)
+
+
+def test_packed_tables_after_training_equal_a_fresh_pack():
+    # the sampler after optimiser steps (tables written by the optimiser)
+    # equals, bit for bit, the sampler of a net given the same parameters
+    # (tables packed from scratch), on the same uniforms
+    insts = [S.c1_small_lattice(16),
+             S.lattice_column_split(S.lattice_2d(12, seed=6), [5, 9], hidden=32)]
+    Bs = [300, 200]
+    a = _net(insts, "fp32", seed=5)
+    for k, inst in enumerate(insts):
+        a.set_params(k, torch.from_numpy(_theta(inst.n_width, inst.hidden, 80 + k, 0.2)))
+    for _ in range(3):
+        a.free_energy_step(Bs, 2e-2)
+    b = _net(insts, "fp32", seed=5)
+    for k in range(len(insts)):
+        b.set_params(k, a.get_params(k))
+    u = _dev(np.concatenate([S.uniforms(bb, i.n_width, 90 + k).reshape(-1)
+                             for k, (bb, i) in enumerate(zip(Bs, insts))]))
+    sa, la = a.sample(Bs, u)
+    sb, lb = b.sample(Bs, u)
+    torch.cuda.synchronize()
+    assert torch.equal(sa, sb) and torch.equal(la, lb)
