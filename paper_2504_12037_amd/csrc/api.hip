@@ -760,10 +760,12 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
   f.part = net->w_fpart.as<double>();
   f.stats = stats;
   f.done = net->tickets.as<int32_t>();
+  // with the fused backward, its workgroups sum the block sums themselves
+  const bool fused = net->mgrad && sizeof(real) == 4;
+  f.finish = !fused;
   f.step_ctr = net->step_ctr.as<int32_t>();
   HIPCHK(launch_free<real>(f, net->n_inst, st));
-  // Adam on every instance and the step counters (one launch, or inside the
-  // fused backward's reduction)
+  // Adam on every instance (one launch, after the REINFORCE gradient)
   OptArgs o{};
   o.mi = net->d_mi.as<MadeInst>();
   o.params = net->params.as<float>();
@@ -789,6 +791,8 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     g.spins = spins;
     g.f = net->w_f.as<double>();
     g.stats = stats;
+    g.fpart = f.part;
+    g.fnblk = f.nblk;
     g.task_inst = net->mg_task_inst.as<int32_t>();
     g.task_start = net->mg_task_start.as<int32_t>();
     g.n_tasks = net->n_mgtasks;
@@ -807,7 +811,6 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     HIPCHK(launch_mgrad_reduce(g, st));
     o.part2 = g.part2;
   }
-  const bool fused = net->mgrad && sizeof(real) == 4;
   for (int q = 0; q < net->n_inst && !fused; ++q) {
     const MadeInst &m = net->mi[q];
     if (m.B <= 0) continue;

@@ -134,7 +134,9 @@ struct MGradArgs {
   const float *params;
   const int8_t *spins;          // all instances
   const double *f;              // f_b per global sample
-  const double *stats;          // [n_inst][4], F_q first
+  const double *fpart;          // free-energy block sums [n_inst][4][fnblk]
+  int32_t fnblk;
+  double *stats;                // out [n_inst][4] (free_stats), by the first workgroup
   const int32_t *task_inst;     // per workgroup
   const int32_t *task_start;    // first local sample (multiple of 64)
   int32_t n_tasks;
@@ -201,8 +203,9 @@ struct FreeArgs {
   const double *ww_J;
   const double *hW;
   double *f;                 // out [sum B]
-  double *part;              // scratch [n_inst][nblk][4]
+  double *part;              // block sums [n_inst][4][nblk]
   int32_t nblk;
+  int32_t finish;            // form stats here (else the fused backward does)
   double *stats;             // out [n_inst][4]
   int32_t *done;             // [n_inst] completion tickets, zero between launches
   int32_t *step_ctr;         // advanced by one per instance, or null

@@ -379,6 +379,19 @@ __global__ void colsum_finish(const real *part, int ksplit, int M, float *out) {
 // f_b = E_1 - logZ_R / beta + ln q / beta (FP64, Eqs. 4 and 9) per sample and
 // per-block sums of f, f^2, Etilde and ln q / beta; every instance of the
 // batch in one launch (grid.y = instance).
+// F_q = mean f, its standard error, mean effective energy and mean ln q / beta
+// (Eq. 9) from the batch sums of f, f^2, the effective energy and ln q / beta
+__device__ inline void free_stats(const double sm[4], int64_t B, double *out) {
+  const double Bd = (double)B;
+  const double Fq = sm[0] / Bd;
+  double var = B > 1 ? (sm[1] - Bd * Fq * Fq) / (Bd - 1.0) : 0.0;
+  if (var < 0.0) var = 0.0;
+  out[0] = Fq;
+  out[1] = sqrt(var / Bd);
+  out[2] = sm[2] / Bd;
+  out[3] = sm[3] / Bd;
+}
+
 template <typename real>
 __global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
   __shared__ double sh[4][256];
@@ -389,24 +402,68 @@ __global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
   const int32_t *wa = a.ww_a + D.ww_off, *wb = a.ww_b + D.ww_off;
   const double *wJ = a.ww_J + D.ww_off, *hW = a.hW + a.hw_off[q];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  // per-sample inputs: spins (as a bit mask when n <= 128), logZ and ln q.
+  // logZ is either given or log_const plus the chain partials in chain
+  // order, then the unary sums (the order of launch_chain_sum), loaded 16 at
+  // a time with every load of a batch in flight together
+  struct In {
+    SpinBits sb;
+    double lz, lq;
+  };
+  const bool bits = mi.n <= 128;
+  auto inputs = [&](int64_t b) {
+    In r;
+    if (bits) r.sb = load_bits_row(a.spins + mi.spin_off + b * mi.n, mi.n);
+    const int64_t g = mi.sample_off + b;
+    r.lq = (double)a.logq[g];
+    if (a.cpart) {
+      const int nch = a.cinst[q].n_chains, nf = (D.nr + kUnaryChunk - 1) / kUnaryChunk;
+      const int tot = nch + nf;
+      const double *cp = a.cpart + a.cpart_off[q] + b, *fa = a.fabp + a.f_off[q] + b;
+      double lz = D.log_const;
+      for (int c0 = 0; c0 < tot; c0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int c = c0 + j;
+          const double *src = c < nch ? cp + (int64_t)c * mi.B
+                              : c < tot ? fa + (int64_t)(c - nch) * mi.B
+                              : nch > 0 ? cp : fa;
+          v[j] = *src;
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if (c0 + j < tot) lz += v[j];
+      }
+      r.lz = lz;
+    } else {
+      r.lz = a.logz[g];
+    }
+    return r;
+  };
+  const int64_t b0 = (int64_t)blockIdx.x * blockDim.x + tid, bstride = (int64_t)gridDim.x * blockDim.x;
+  // the first sample's inputs are requested before the tables are staged,
+  // so that both are one memory round trip
+  In cur;
+  if (mi.B > 0) cur = inputs(b0 < mi.B ? b0 : 0);
   // the first kFreeStage W-W couplings (endpoints packed in one word) and
   // the W fields staged in LDS once per block: the per-sample loops then
   // read them without a memory round trip per batch of terms
   __shared__ int32_t s_ab[kFreeStage];
   __shared__ double s_J[kFreeStage], s_h[128];
-  const int nst = mi.n <= 128 ? min(D.n_ww, kFreeStage) : 0;
+  const int nst = bits ? min(D.n_ww, kFreeStage) : 0;
   for (int k = tid; k < nst; k += blockDim.x) {
     s_ab[k] = wa[k] | (wb[k] << 16);
     s_J[k] = wJ[k];
   }
   for (int k = tid; k < mi.n && k < 128; k += blockDim.x) s_h[k] = hW[k];
   __syncthreads();
-  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + tid; b < mi.B;
-       b += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t b = b0; b < mi.B; b += bstride) {
+    if (b != b0) cur = inputs(b);
     double e1 = 0.0;
-    if (mi.n <= 128) {
-      // spins as a bit mask; the +-1 products are exact
-      const SpinBits sb = load_bits_row(a.spins + mi.spin_off + b * mi.n, mi.n);
+    if (bits) {
+      // the +-1 products are exact
+      const SpinBits &sb = cur.sb;
 #pragma unroll 8
       for (int k = 0; k < nst; ++k) {
         const int ab = s_ab[k];
@@ -424,20 +481,10 @@ __global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
       for (int k = 0; k < D.n_ww; ++k) e1 -= wJ[k] * (double)s[wa[k]] * (double)s[wb[k]];
       for (int k = 0; k < mi.n; ++k) e1 -= hW[k] * (double)s[k];
     }
-    const int64_t g = mi.sample_off + b;
-    double lz;
-    if (a.cpart) {
-      lz = D.log_const;
-      for (int c = 0; c < a.cinst[q].n_chains; ++c) lz += a.cpart[a.cpart_off[q] + (int64_t)c * mi.B + b];
-      const int nf = (D.nr + kUnaryChunk - 1) / kUnaryChunk;
-      for (int c = 0; c < nf; ++c) lz += a.fabp[a.f_off[q] + (int64_t)c * mi.B + b];
-    } else {
-      lz = a.logz[g];
-    }
-    const double et = e1 - lz / beta;
-    const double lqb = (double)a.logq[g] / beta;
+    const double et = e1 - cur.lz / beta;
+    const double lqb = cur.lq / beta;
     const double f = et + lqb;
-    a.f[g] = f;
+    a.f[mi.sample_off + b] = f;
     acc[0] += f; acc[1] += f * f; acc[2] += et; acc[3] += lqb;
   }
   for (int c = 0; c < 4; ++c) sh[c][tid] = acc[c];
@@ -447,29 +494,29 @@ __global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
       for (int c = 0; c < 4; ++c) sh[c][tid] += sh[c][tid + st];
     __syncthreads();
   }
+  // block sums, component-major: part[q][c][block]
+  if (tid == 0)
+    for (int c = 0; c < 4; ++c) a.part[((int64_t)q * 4 + c) * gridDim.x + blockIdx.x] = sh[c][0];
+  // the step's sampler (the counter's only earlier reader) has run: the
+  // step counter advances here, and the optimiser then reads the step's own
+  // number (an atomic add whose result is unused: nothing waits for a load)
+  if (blockIdx.x == 0 && tid == 0 && a.step_ctr) atomicAdd(a.step_ctr + q, 1);
+  if (!a.finish) return;
   // the last block of the instance (completion ticket) forms the statistics
-  // from the block sums, in block order
+  // from the block sums: thread k holds block k, then a fixed tree
   __shared__ int last;
   if (tid == 0) {
-    for (int c = 0; c < 4; ++c) a.part[((int64_t)q * gridDim.x + blockIdx.x) * 4 + c] = sh[c][0];
     __threadfence();
     const int prev = atomicAdd(a.done + q, 1);
     last = prev == (int)gridDim.x - 1;
-    if (last) {
-      atomicExch(a.done + q, 0);
-      // the step's sampler (the counter's reader) has run: the step counter
-      // advances here, and the optimiser then reads the step's own number
-      // (an atomic add whose result is unused: nothing waits for a load)
-      if (a.step_ctr) atomicAdd(a.step_ctr + q, 1);
-    }
+    if (last) atomicExch(a.done + q, 0);
   }
   __syncthreads();
   if (!last || mi.B <= 0) return;
   __threadfence();
-  // block sums of the instance: thread k holds block k, then a fixed tree
   for (int c = 0; c < 4; ++c)
     sh[c][tid] = tid < (int)gridDim.x
-                     ? __hip_atomic_load(a.part + ((int64_t)q * gridDim.x + tid) * 4 + c,
+                     ? __hip_atomic_load(a.part + ((int64_t)q * 4 + c) * gridDim.x + tid,
                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                      : 0.0;
   __syncthreads();
@@ -480,14 +527,7 @@ __global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
   }
   if (tid != 0) return;
   const double sm[4] = {sh[0][0], sh[1][0], sh[2][0], sh[3][0]};
-  const double Bd = (double)mi.B;
-  const double Fq = sm[0] / Bd;
-  double var = mi.B > 1 ? (sm[1] - Bd * Fq * Fq) / (Bd - 1.0) : 0.0;
-  if (var < 0.0) var = 0.0;
-  a.stats[4 * q + 0] = Fq;
-  a.stats[4 * q + 1] = sqrt(var / Bd);
-  a.stats[4 * q + 2] = sm[2] / Bd;
-  a.stats[4 * q + 3] = sm[3] / Bd;
+  free_stats(sm, mi.B, a.stats + 4 * q);
 }
 
 // Adam (Kingma & Ba; beta1 = 0.9, beta2 = 0.999, eps = 1e-8) on one
@@ -859,6 +899,28 @@ __global__ __launch_bounds__(256, 2) void mgrad_kernel(MGradArgs a) {
   // HT tiles of 16 hidden units cover the widest instance of the launch;
   // units past an instance's H read as zero
   const int64_t bw = a.task_start[blockIdx.x];
+  // F_q from the free-energy kernel's block sums, added in block order (the
+  // same value in every workgroup); the instance's first workgroup also
+  // writes the step statistics
+  // (lane k holds block k, at most 64 blocks; a fixed tree down to lane 0,
+  // then a broadcast)
+  double Fq;
+  {
+    const double *fp = a.fpart + (int64_t)q * 4 * a.fnblk;
+    auto bsum = [&](int c) {
+      double v = fp[c * a.fnblk + (lane < a.fnblk ? lane : 0)];
+      v = lane < a.fnblk ? v : 0.0;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+      return __shfl(v, 0, 64);
+    };
+    const double s0 = bsum(0);
+    Fq = s0 / (double)mi.B;
+    if (bw == 0 && wave == 0) {
+      const double sm[4] = {s0, bsum(1), bsum(2), bsum(3)};
+      if (lane == 0) free_stats(sm, mi.B, a.stats + 4 * q);
+    }
+  }
   const MgLayout Lm = mg_layout(NPT);
   float *hid = reinterpret_cast<float *>(smem + Lm.hid);
   float *dab = reinterpret_cast<float *>(smem + Lm.da);
@@ -915,7 +977,7 @@ __global__ __launch_bounds__(256, 2) void mgrad_kernel(MGradArgs a) {
         sp[t][r] = (valid && pos < n) ? (float)bv[t][r] : 0.f;
       }
   }
-  const float wt = valid ? (float)((a.f[mi.sample_off + sb] - a.stats[4 * q]) / (double)mi.B) : 0.f;
+  const float wt = valid ? (float)((a.f[mi.sample_off + sb] - Fq) / (double)mi.B) : 0.f;
   float h[HT][4];
 #pragma unroll
   for (int h0 = 0; h0 < HT; h0 += B1) {
