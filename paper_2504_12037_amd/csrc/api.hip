@@ -123,7 +123,7 @@ struct tnvan_net {
   ChainLim lim_fwd{}, lim_bwd{};
   DBuf Tl, Tbl, cedges, ckpt;
   // register-resident chain kernels (per-wave tasks)
-  DBuf Tr, Tq, Trb, xcol, cf_w, cf_r, cf_J, Tsx, Ts3;
+  DBuf Tr, Tq, Trb, xcol, cf_w, cf_r, cf_J, Tsx, Ts3, Tdq;
   bool split = false;   // TNVAN_FLAG_SPLIT_BF16 on an FP32 net
   DBuf Ubuf, fabp, u_off, f_off, vjp_part, tickets, inv_v, inv_e, pcoef;
   // training step replayed from a captured graph (TNVAN_FLAG_GRAPH)
@@ -438,6 +438,7 @@ ChainArgs chain_args(tnvan_net *net, bool bwd) {
   a.xcol = net->xcol.as<int32_t>();
   a.Tsx = net->Tsx.as<float>();
   a.Ts3 = net->Ts3.as<uint16_t>();
+  a.Tdq = net->Tdq.as<int32_t>();
   a.split = net->split ? 1 : 0;
   a.cf_w = net->cf_w.as<int32_t>();
   a.cf_r = net->cf_r.as<int32_t>();
@@ -1004,7 +1005,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   UP2(Tl, P.Tl) UP2(Tbl, P.Tbl) UP2(cedges, P.cedges)
   UP2(Tr, P.Tr) UP2(Tq, P.Tq) UP2(Trb, P.Trb) UP2(xcol, P.xcol)
   UP2(inv_v, P.inv_v) UP2(inv_e, P.inv_e) UP2(pcoef, P.pcoef)
-  UP2(cf_w, P.cf_w) UP2(cf_r, P.cf_r) UP2(cf_J, P.cf_J) UP2(Tsx, P.Tsx) UP2(Ts3, P.Ts3)
+  UP2(cf_w, P.cf_w) UP2(cf_r, P.cf_r) UP2(cf_J, P.cf_J) UP2(Tsx, P.Tsx) UP2(Ts3, P.Ts3) UP2(Tdq, P.Tdq)
   // transfer-matrix form: instances whose program is a set of dense chains
   // (FP32 / BF16 only); the launch-wide maxima size the LDS layout
   net->use_chain.assign(n_inst, 0);
@@ -1098,7 +1099,7 @@ void tnvan_free_network(tnvan_net *net) {
                  &net->hR32, &net->task_inst, &net->task_chain, &net->task_start,
                  &net->btask_inst, &net->btask_chain, &net->btask_start, &net->Tl, &net->Tbl,
                  &net->cedges, &net->ckpt, &net->Tr, &net->Tq, &net->Trb, &net->xcol,
-                 &net->cf_w, &net->cf_r, &net->cf_J, &net->Tsx, &net->Ts3, &net->Ubuf, &net->vjp_part,
+                 &net->cf_w, &net->cf_r, &net->cf_J, &net->Tsx, &net->Ts3, &net->Tdq, &net->Ubuf, &net->vjp_part,
                  &net->tickets, &net->inv_v, &net->inv_e, &net->pcoef, &net->fabp, &net->u_off,
                  &net->f_off,
                  &net->mpack, &net->mtask_inst, &net->mtask_start, &net->mg_task_inst,

@@ -26,8 +26,9 @@
 // where the columns of S_x are the group's spins and the products of the
 // spins of each edge inside the group, and the columns of S_o the output
 // spins and a column of ones.  Q_t holds, weighted by g and summed over the
-// samples, every edge correlation of the step and the group magnetisations;
-// the W-R correlations come from p_t and the spins directly.
+// samples, every edge correlation of the step and the group magnetisations,
+// which each lane stores from its registers to the columns a per-step table
+// names; the W-R correlations come from p_t and the spins directly.
 #include <hip/hip_runtime.h>
 
 #include "launch.h"
@@ -40,6 +41,7 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+typedef int i4v __attribute__((ext_vector_type(4)));
 
 constexpr int CW = 16;       // samples per 16-sample group
 constexpr int kWaves = 4;    // waves per workgroup
@@ -51,7 +53,7 @@ __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~(size_t)15
 __host__ __device__ constexpr int ldt_of(int tiles) { return 16 * tiles + ((tiles & 1) ? 32 : 16); }
 
 struct RL {
-  size_t sp, ex, ga, rs, qs, end;
+  size_t sp, ex, ga, rs, end;
 };
 __host__ __device__ inline RL rlayout(const ChainLim &L, bool bwd, int sg) {
   RL r{};
@@ -63,7 +65,6 @@ __host__ __device__ inline RL rlayout(const ChainLim &L, bool bwd, int sg) {
     r.ex = o; o = al16(o + (size_t)L.max_steps * CW * 4);
     r.ga = o; o = al16(o + (size_t)CW * ldt * 4);
     r.rs = o; o = al16(o + (size_t)CW * ldt * 4);
-    r.qs = o; o = al16(o + (size_t)CW * 17 * 4);
   }
   r.end = al16(o);
   return r;
@@ -388,7 +389,6 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
   int *ex = reinterpret_cast<int *>(base + L.ex);
   float *ga = reinterpret_cast<float *>(base + L.ga);
   float *rs = reinterpret_cast<float *>(base + L.rs);
-  float *qs = reinterpret_cast<float *>(base + L.qs);
   const int64_t left = tk.Bq - tk.b0;
   const int nvalid = (int)(left < CW ? left : CW);
   const SpinBits sp = load_bits(a.spins + a.inst_spin_off[tk.q] + (tk.b0 + (ls < nvalid ? ls : 0)) * D.nw,
@@ -400,7 +400,6 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
            (int64_t)(a.task_base + blockIdx.x * kWaves + (threadIdx.x >> 6)) * a.lim.max_steps *
                kRegBwdTiles * 64 +
            lane;
-  const EdgeDesc *ce = a.cedges + cd.e_src;
   const float *ub = phi_base(a, tk.q, tk.Bq, tk.b0 + ls);
 
   // Both passes load the operands of the next step while one step is
@@ -522,7 +521,8 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
         so[i] = sxo[(CT + i) * 64];
       }
     }
-    const EdgeDesc myed = lane < st.n_edge ? ce[st.ce_off + lane] : EdgeDesc{0, 0, 0, 0};
+    // where this lane's four cells of the step's correlations are stored
+    const i4v dq = reinterpret_cast<const i4v *>(a.Tdq + st.dq_off)[lane];
     // the next step walked: descriptor and operands (step 0 reloads itself)
     sn = step_at(cs, t > 0 ? t - 1 : 0);
     prefetch(sn, t > 0 ? t - 1 : 0, nxt);
@@ -671,16 +671,10 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
         for (int r = 0; r < 4; ++r)
           qq = __builtin_amdgcn_mfma_f32_16x16x4f32(so[ot][r], qt[ot][r], qq, 0, 0, 0);
     }
+    // magnetisations and edge correlations straight from the registers
 #pragma unroll
-    for (int r = 0; r < 4; ++r) qs[ls * 17 + 4 * lg + r] = qq[r];
-    wsync();
-    if (lane < st.n_edge) prow[D.nr + D.n_wr + myed.rr] = qs[(myed.pad >> 4) * 17 + (myed.pad & 15)];
-    for (int k = lane + 64; k < st.n_edge; k += 64) {
-      const EdgeDesc ed = ce[st.ce_off + k];
-      prow[D.nr + D.n_wr + ed.rr] = qs[(ed.pad >> 4) * 17 + (ed.pad & 15)];
-    }
-    if (lane < g) prow[st.gpos + lane] = qs[lane * 17 + w];
-    wsync();
+    for (int r = 0; r < 4; ++r)
+      if (dq[r] >= 0) prow[dq[r]] = qq[r];
 #pragma unroll
     for (int i = 0; i < CT; ++i)
 #pragma unroll

@@ -229,6 +229,21 @@ void build_chains(const InstDesc &D, const std::vector<int32_t> &consumer, HostP
       }
       if (sd.w >= 16) ok_rq = false;
       for (int c = 0; c < 16; ++c) P.xcol.push_back(xc[c]);
+      // adjoint destinations of the 256 cells, in the R-layout lane order
+      {
+        int32_t dq[256];
+        for (int c = 0; c < 256; ++c) dq[c] = -1;
+        if (sd.w < 16) {
+          for (int j = 0; j < sd.g && j < 16; ++j) dq[j * 16 + sd.w] = sd.gpos + j;
+          for (int k = cs.ce_off; k < (int)P.cedges.size() - cd.e_src; ++k) {
+            const EdgeDesc &e = P.cedges[cd.e_src + k];
+            if (e.pad >= 0 && e.pad < 256) dq[e.pad] = D.nr + D.n_wr + e.rr;
+          }
+        }
+        cs.dq_off = (int32_t)P.Tdq.size();
+        for (int l = 0; l < 64; ++l)
+          for (int r = 0; r < 4; ++r) P.Tdq.push_back(dq[(l & 15) * 16 + 4 * (l >> 4) + r]);
+      }
       // S_x operand of lane l: column l & 15 at state x = 16 xt + 4 (l >> 4) + r;
       // S_o operand: row j = l & 15 (output spin j < w, all-ones j = w) at
       // output state o = 16 ot + 4 (l >> 4) + r

@@ -46,6 +46,7 @@ struct HostProgram {
   std::vector<uint16_t> Ts3;        // per chain step: split-BF16 operand tables
   std::vector<int32_t> xcol;        // 16 adjoint column codes per chain step
   std::vector<float> Tsx;           // per chain step: S_x and S_o operand tables
+  std::vector<int32_t> Tdq;         // per chain step: adjoint destinations [lane][4]
   // adjoint output maps: vertex -> R position (-1 on W), edge -> partial
   // column (-1 on W-W edges), and the dbeta coefficient of every column
   std::vector<int32_t> inv_v, inv_e;

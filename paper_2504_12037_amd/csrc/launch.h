@@ -270,6 +270,7 @@ struct ChainArgs {
   const uint16_t *Trb;
   const int32_t *xcol;
   const float *Tsx;                 // adjoint S_x / S_o operand tables
+  const int32_t *Tdq;               // adjoint destinations (ChainStep::dq_off)
   const uint16_t *Ts3;              // split-BF16 operand tables (ChainStep::s3_off)
   int32_t split;                    // FP32 path with split-BF16 products
   int32_t sg;                       // 16-sample groups per wave (forward)

@@ -122,7 +122,7 @@ struct ChainStep {
   int32_t n_wri;
   int32_t wri[4];
   int32_t wre[4];
-  int32_t pad2;
+  int32_t dq_off;     // adjoint destinations [lane][4] (see below)
   // split-BF16 operand tables (16x16x32 order, KC = ceil(rt / 2) chunks of 32
   // states; state of element j of lane l in chunk c: 16 (2c + j/4) +
   // 4 (l >> 4) + j % 4, zero past the chain's tiles), BF16 [part][...]:
@@ -148,7 +148,11 @@ struct ChainStep {
 // 0..g-1 are the group's spins, then one column per edge with both ends in
 // the group.  Every edge of the step stores in EdgeDesc::pad the cell
 // (column * 16 + output-spin row) of S_x^T G S_o that holds its correlation
-// (row w = the all-ones column of S_o).
+// (row w = the all-ones column of S_o).  The adjoint's 16x16 product
+// S_x^T G S_o ends in the R-layout: lane l holds cell (l & 15) * 16 +
+// 4 (l >> 4) + r in register r.  dq_off indexes, per lane and register, the
+// partial-row column that cell is stored to (-1: none): group spin j's
+// magnetisation at cell j * 16 + w, an edge's correlation at its pad.
 
 struct ChainDesc {
   int32_t n_steps, cs_off;   // ChainStep range
