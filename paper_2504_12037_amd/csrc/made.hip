@@ -772,9 +772,9 @@ __global__ __launch_bounds__(256) void msample_kernel(MSampleArgs a) {
   // spin, log q, then the hidden units of degree i + 1 and every later
   // logit; the operands of position i + 1 are loaded meanwhile into the
   // other register set (R = i mod 4 is static after the unroll by four)
-  auto position = [&](const int i, auto RC, const f4 (&ca)[NPT], const f4 (&cz)[NPT], const f4 &cb,
-                      const float cu, f4 (&na)[NPT], f4 (&nz)[NPT], f4 &nb, float &nu) {
-    constexpr int ri = decltype(RC)::value;
+  auto position = [&](const int i, auto TC, auto RC, const f4 (&ca)[NPT], const f4 (&cz)[NPT],
+                      const f4 &cb, const float cu, f4 (&na)[NPT], f4 (&nz)[NPT], f4 &nb, float &nu) {
+    constexpr int ti = decltype(TC)::value, ri = decltype(RC)::value;
     // unconditional (the last position reloads itself), so that the wait
     // for this position's operands can leave the new loads in flight
     const int nx = i + 1 < n ? i + 1 : i;
@@ -785,7 +785,17 @@ __global__ __launch_bounds__(256) void msample_kernel(MSampleArgs a) {
     }
     nb = PB1[(int64_t)nx * 64];
     if (kU) nu = u[nx];
-    const int ti = i >> 4, gi = (i >> 2) & 3;
+    const int gi = (i >> 2) & 3;
+    // hidden pre-activations of the units of degree i + 1: every product
+    // that does not hold the new spin is issued before the spin is drawn
+    f4 acc = cb;
+#pragma unroll
+    for (int t = 0; t < NPT; ++t)
+      if (t <= ti)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (t != ti || r != ri)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[t][r], sp[t][r], acc, 0, 0, 0);
     float own = z[0][ri];
 #pragma unroll
     for (int t = 1; t < NPT; ++t)
@@ -809,29 +819,49 @@ __global__ __launch_bounds__(256) void msample_kernel(MSampleArgs a) {
 #pragma unroll
     for (int t = 0; t < NPT; ++t)
       if (t == ti) sp[t][ri] = mine ? si : sp[t][ri];
-    f4 acc = cb;
+    // the product holding the new spin (slot ri of tile ti), last
 #pragma unroll
     for (int t = 0; t < NPT; ++t)
-      if (t <= ti)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[t][r], sp[t][r], acc, 0, 0, 0);
+      if (t == ti) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[t][ri], sp[t][ri], acc, 0, 0, 0);
     float h[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) h[r] = ftanh(acc[r]);
     if (lg == 3) h[3] = si;
+    // later logits only: tiles before ti hold positions already drawn
 #pragma unroll
     for (int t = 0; t < NPT; ++t)
+      if (t >= ti)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        z[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(cz[t][r], h[r], z[t], 0, 0, 0);
+        for (int r = 0; r < 4; ++r)
+          z[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(cz[t][r], h[r], z[t], 0, 0, 0);
   };
-  for (int i = 0; i < n; i += 4) {
-    position(i, std::integral_constant<int, 0>{}, pa, pz, pb, pu, qa, qz, qb, qu);
-    if (i + 1 < n) position(i + 1, std::integral_constant<int, 1>{}, qa, qz, qb, qu, pa, pz, pb, pu);
-    if (i + 2 < n) position(i + 2, std::integral_constant<int, 2>{}, pa, pz, pb, pu, qa, qz, qb, qu);
-    if (i + 3 < n) position(i + 3, std::integral_constant<int, 3>{}, qa, qz, qb, qu, pa, pz, pb, pu);
-  }
+  // tile by tile (the tile index static), four positions at a time with no
+  // branch between them: a branch between positions makes the compiler wait
+  // for every load in flight, the next position's operands included
+  auto tile = [&](auto TC) {
+    constexpr int t = decltype(TC)::value;
+    using R0 = std::integral_constant<int, 0>;
+    using R1 = std::integral_constant<int, 1>;
+    using R2 = std::integral_constant<int, 2>;
+    using R3 = std::integral_constant<int, 3>;
+    const int end = n < 16 * t + 16 ? n : 16 * t + 16;
+    int i = 16 * t;
+    for (; i + 4 <= end; i += 4) {
+      position(i, TC, R0{}, pa, pz, pb, pu, qa, qz, qb, qu);
+      position(i + 1, TC, R1{}, qa, qz, qb, qu, pa, pz, pb, pu);
+      position(i + 2, TC, R2{}, pa, pz, pb, pu, qa, qz, qb, qu);
+      position(i + 3, TC, R3{}, qa, qz, qb, qu, pa, pz, pb, pu);
+    }
+    if (i < end) {
+      position(i, TC, R0{}, pa, pz, pb, pu, qa, qz, qb, qu);
+      if (i + 1 < end) position(i + 1, TC, R1{}, qa, qz, qb, qu, pa, pz, pb, pu);
+      if (i + 2 < end) position(i + 2, TC, R2{}, pa, pz, pb, pu, qa, qz, qb, qu);
+    }
+  };
+  tile(std::integral_constant<int, 0>{});
+  if (NPT > 1) tile(std::integral_constant<int, (NPT > 1 ? 1 : 0)>{});
+  if (NPT > 2) tile(std::integral_constant<int, (NPT > 2 ? 2 : 0)>{});
+  if (NPT > 3) tile(std::integral_constant<int, (NPT > 3 ? 3 : 0)>{});
   if (live) {
     int8_t *so = a.spins + mi.spin_off + b * n;
 #pragma unroll
