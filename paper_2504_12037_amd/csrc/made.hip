@@ -891,6 +891,9 @@ __global__ __launch_bounds__(256) void msample_kernel(MSampleArgs a) {
 // The workgroup writes its masked partial gradient as one row; mgrad_reduce
 // sums the rows of an instance in a fixed order.
 constexpr int kMgTiles = 16;    // hidden tiles (H <= 256)
+// sched_barrier mask: every instruction kind but vector-memory reads may be
+// scheduled across it
+constexpr int kNoVmemRead = 0x0001 | 0x0002 | 0x0004 | 0x0008 | 0x0040 | 0x0080 | 0x0400;
 constexpr int kMgPass = 4;      // hidden tiles staged per pass
 
 struct MgLayout {
@@ -918,7 +921,7 @@ template <int NPT, int HT>
 __global__ __launch_bounds__(256, 2) void mgrad_kernel(MGradArgs a) {
   typedef float f4 __attribute__((ext_vector_type(4)));
   constexpr int QT = HT < kMgPass ? HT : kMgPass;   // hidden tiles per pass
-  constexpr int BM = NPT >= 4 ? 4 : 8;
+  constexpr int BM = 4;
   constexpr int B1 = HT < BM ? HT : BM;             // tiles per batch of weight loads
   extern __shared__ __align__(16) char smem[];
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -1020,6 +1023,9 @@ __global__ __launch_bounds__(256, 2) void mgrad_kernel(MGradArgs a) {
         wl[j][t] = ld4(W1m, W1m + (int64_t)ka * n + 16 * t + 4 * lg, ka < H && 16 * t + 4 * lg < n);
       bl[j] = ld4(b1, b1 + 16 * (h0 + j) + 4 * lg, 16 * (h0 + j) + 4 * lg < H);
     }
+    // the batch's loads stay together ahead of its products (the scheduler
+    // would otherwise sink each next to its use, one round trip per tile)
+    __builtin_amdgcn_sched_barrier(kNoVmemRead);
 #pragma unroll
     for (int j = 0; j < B1; ++j) {
       const int ht = h0 + j;
@@ -1065,6 +1071,7 @@ __global__ __launch_bounds__(256, 2) void mgrad_kernel(MGradArgs a) {
         for (int j = 0; j < B1; ++j)
           wz[pt][j] = ld4(W2m, W2m + (int64_t)pa * Hs + 16 * (h0 + j) + 4 * lg, pa < n && 16 * (h0 + j) + 4 * lg < H);
       }
+      __builtin_amdgcn_sched_barrier(kNoVmemRead);
 #pragma unroll
       for (int j = 0; j < B1; ++j)
 #pragma unroll
@@ -1118,6 +1125,7 @@ __global__ __launch_bounds__(256, 2) void mgrad_kernel(MGradArgs a) {
         for (int pt = 0; pt < NPT; ++pt)
           wt2[j][pt] = ld4(W2T, W2T + (int64_t)ka * n + 16 * pt + 4 * lg, ka < H && 16 * pt + 4 * lg < n);
       }
+      __builtin_amdgcn_sched_barrier(kNoVmemRead);
       if (pass > 0) __syncthreads();   // the previous pass's products are done
 #pragma unroll
       for (int j = 0; j < QT; ++j) {
