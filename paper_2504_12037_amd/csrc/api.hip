@@ -797,6 +797,7 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     g.task_inst = net->mg_task_inst.as<int32_t>();
     g.task_start = net->mg_task_start.as<int32_t>();
     g.n_tasks = net->n_mgtasks;
+    g.split = net->split && net->mpt <= 2 ? 1 : 0;
     g.part = net->w_part.as<float>();
     g.pstride = net->mg_pstride;
     g.first_row = net->mg_first.as<int32_t>();
@@ -944,7 +945,8 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
     }
     for (auto pc : net->param_count) net->mg_pstride = std::max(net->mg_pstride, pc);
     net->mg_pstride = (net->mg_pstride + 63) / 64 * 64;
-    net->mgrad = gfit && mgrad_lds_bytes(net->mg_hmax, net->mpt) <= (size_t)maxlds;
+    net->mgrad = gfit && mgrad_lds_bytes(net->mg_hmax, net->mpt, net->split && net->mpt <= 2) <=
+                             (size_t)maxlds;
   }
   auto fail = [&](hipError_t e, const char *what) {
     tnvan_free_network(net);

@@ -146,8 +146,9 @@ struct MGradArgs {
   float *part2;                 // [n_inst][mgrad_split()][pstride]
   const float *pack;            // made_pack_kernel output (holds the masked W2^T)
   float *grad;                  // flat parameter gradient
+  int32_t split;                // products as split-BF16 (mgrad3_kernel)
 };
-size_t mgrad_lds_bytes(int H, int npt);
+size_t mgrad_lds_bytes(int H, int npt, bool split);
 int mgrad_split();
 hipError_t launch_mgrad(const MGradArgs &a, int npt, hipStream_t st);
 hipError_t launch_mgrad_reduce(const MGradArgs &a, hipStream_t st);

@@ -1210,6 +1210,438 @@ __global__ __launch_bounds__(256, 2) void mgrad_kernel(MGradArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same fused REINFORCE backward with split-BF16 products (the nets made
+// with TNVAN_FLAG_SPLIT_BF16).  Every product is formed on the BF16
+// 16x16x32 matrix cores from split operands: x = x_hi + x_lo, each part
+// rounded to BF16, and x y ~ x_hi y_hi + x_hi y_lo + x_lo y_hi with FP32
+// accumulation; spins are exact in BF16, so products with them take two.
+// A lane's K chunk c holds, in element j, index 16 (2c + j/4) + 4 (l >> 4) +
+// j % 4 of the contracted dimension, so R-layout registers (spins, h, dlogit)
+// are B operands as they are, and the A operands are the FP32 weight rows the
+// FP32 kernel loads, split in registers.  The gradient blocks contract over
+// the workgroup's 64 samples from operands staged feature-major in LDS as
+// BF16 hi and lo rows, eight samples per lane in one 16-byte read.  The bias
+// gradients are FP32 sums of the registers (16 samples per wave, then the
+// four waves in order).
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef unsigned int u4w __attribute__((ext_vector_type(4)));
+typedef float f4v_t __attribute__((ext_vector_type(4)));
+constexpr int kMg3K = 72;       // BF16 per staged row: 64 samples + 8 (bank spread)
+
+// LDS of mgrad3_kernel.  The network phase holds the first-layer and logit
+// weights, split, in operand order (16 bytes per lane and chunk); the
+// backward passes reuse that space for the W2m^T slices of two passes and
+// the staged rows.  The degree table follows both.
+struct Mg3Layout {
+  size_t a1, a2, b1s;                       // network phase
+  size_t wt, dlh, dll, st, hh, hl, dah, dal, b2p, b1p;   // backward passes
+  size_t deg, end;
+};
+__host__ __device__ inline Mg3Layout mg3_layout(int npt, int ht) {
+  Mg3Layout L;
+  const int nc = (npt + 1) / 2, nch = (ht + 1) / 2, qt = ht < kMgPass ? ht : kMgPass;
+  size_t o = 0;
+  L.a1 = o; o += (size_t)2 * ht * nc * 64 * 16;
+  L.a2 = o; o += (size_t)2 * npt * nch * 64 * 16;
+  L.b1s = o; o += (size_t)16 * ht * 4;
+  const size_t net = o;
+  const size_t rp = (size_t)16 * npt * kMg3K * 2, rq = (size_t)16 * qt * kMg3K * 2;
+  o = 0;
+  L.wt = o; o += (size_t)2 * 2 * qt * nc * 64 * 16;
+  L.dlh = o; o += rp;
+  L.dll = o; o += rp;
+  L.st = o; o += rp;
+  L.hh = o; o += rq;
+  L.hl = o; o += rq;
+  L.dah = o; o += rq;
+  L.dal = o; o += rq;
+  L.b2p = o; o += (size_t)4 * 16 * npt * 4;
+  L.b1p = o; o += (size_t)4 * 16 * qt * 4;
+  L.deg = o > net ? o : net;
+  L.end = L.deg + (size_t)16 * (ht > 0 ? ht : 1) * 4;
+  return L;
+}
+
+__device__ inline f4v_t mfma_b(bf8v a, bf8v b, f4v_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+// chunk c of R-layout registers x[t][r] (t < NT; zero past NT), split
+template <int NT>
+__device__ inline void split_c(const float (&x)[NT][4], int c, bf8v &h, bf8v &l) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int t = 2 * c + (j >> 2);
+    const float v = t < NT ? x[t < NT ? t : 0][j & 3] : 0.f;
+    h[j] = (__bf16)v;
+    l[j] = (__bf16)(v - (float)h[j]);
+  }
+}
+// chunk c of R-layout spins (exact in BF16)
+template <int NT>
+__device__ inline bf8v spin_c(const float (&x)[NT][4], int c) {
+  bf8v h;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int t = 2 * c + (j >> 2);
+    h[j] = (__bf16)(t < NT ? x[t < NT ? t : 0][j & 3] : 0.f);
+  }
+  return h;
+}
+
+template <int NPT, int HT>
+__global__ __launch_bounds__(256, 2) void mgrad3_kernel(MGradArgs a) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  constexpr int QT = HT < kMgPass ? HT : kMgPass;   // hidden tiles per pass
+  constexpr int NC = (NPT + 1) / 2;                 // K chunks over positions
+  constexpr int NCH = (HT + 1) / 2;                 // K chunks over hidden units
+  constexpr int G1 = (HT * NC * 64 + 255) / 256;    // first-layer operand groups per thread
+  constexpr int G2 = (NPT * NCH * 64 + 255) / 256;  // logit operand groups per thread
+  constexpr int GT = (QT * NC * 64 + 255) / 256;    // W2m^T operand groups per thread
+  extern __shared__ __align__(16) char smem[];
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(tid >> 6));
+  const int lane = tid & 63, ls = lane & 15, lg = lane >> 4;
+  const int q = a.task_inst[blockIdx.x];
+  const MadeInst mi = a.mi[q];
+  const int n = mi.n, Hs = mi.H, H = n >= 2 ? mi.H : 0;
+  const int64_t bw = a.task_start[blockIdx.x];
+  const Mg3Layout Lm = mg3_layout(NPT, HT);
+  u4w *A1 = reinterpret_cast<u4w *>(smem + Lm.a1);   // [hi, lo][HT][NC][64]
+  u4w *A2 = reinterpret_cast<u4w *>(smem + Lm.a2);   // [hi, lo][NPT][NCH][64]
+  float *b1s = reinterpret_cast<float *>(smem + Lm.b1s);
+  u4w *WT = reinterpret_cast<u4w *>(smem + Lm.wt);   // [buffer][hi, lo][QT][NC][64]
+  __bf16 *dlh = reinterpret_cast<__bf16 *>(smem + Lm.dlh), *dll = reinterpret_cast<__bf16 *>(smem + Lm.dll);
+  __bf16 *sT = reinterpret_cast<__bf16 *>(smem + Lm.st);
+  __bf16 *hh = reinterpret_cast<__bf16 *>(smem + Lm.hh), *hl = reinterpret_cast<__bf16 *>(smem + Lm.hl);
+  __bf16 *dah = reinterpret_cast<__bf16 *>(smem + Lm.dah), *dal = reinterpret_cast<__bf16 *>(smem + Lm.dal);
+  float *b2p = reinterpret_cast<float *>(smem + Lm.b2p), *b1p = reinterpret_cast<float *>(smem + Lm.b1p);
+  int32_t *deg = reinterpret_cast<int32_t *>(smem + Lm.deg);
+  const float *W1 = a.params + mi.param_off, *b1 = W1 + (int64_t)Hs * n, *W2 = b1 + Hs,
+              *b2 = W2 + (int64_t)n * Hs, *W0 = b2 + n;
+  const float *W2T = a.pack + mi.pack_off + msample_floats(n, NPT);
+  const float *W1m = W2T + (int64_t)Hs * n, *W2m = W1m + (int64_t)Hs * n;
+  const int nm1 = n > 1 ? n - 1 : 1;
+  auto ld4 = [](const float *base, const float *p, bool ok) {
+    const f4 v = *reinterpret_cast<const f4 *>(ok ? p : base);
+    return ok ? v : f4{0.f, 0.f, 0.f, 0.f};
+  };
+  // 8 values (two f4) split into BF16 hi and lo, as two 16-byte words
+  auto split8 = [](const f4 &x0, const f4 &x1, u4w &hi, u4w &lo) {
+    bf8v h, l;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float v = j < 4 ? x0[j] : x1[j - 4];
+      h[j] = (__bf16)v;
+      l[j] = (__bf16)(v - (float)h[j]);
+    }
+    hi = __builtin_bit_cast(u4w, h);
+    lo = __builtin_bit_cast(u4w, l);
+  };
+  auto as8 = [](const u4w &v) { return __builtin_bit_cast(bf8v, v); };
+
+  // -- the network's weights, staged once per workgroup: every load first --
+  // operand group (tile, chunk c, lane l): row 16 tile + (l & 15), elements
+  // 16 (2c + j/4) + 4 (l >> 4) + j % 4 of the contracted dimension
+  f4 x1[G1][2], x2[G2][2], xb;
+#pragma unroll
+  for (int i = 0; i < G1; ++i) {
+    const int g = tid + 256 * i;
+    const int ht = g / (NC * 64), c = (g / 64) % NC, l = g % 64;
+    const int row = 16 * ht + (l & 15);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int k = 16 * (2 * c + e) + 4 * (l >> 4);
+      x1[i][e] = ld4(W1m, W1m + (int64_t)row * n + k, g < HT * NC * 64 && row < H && 2 * c + e < NPT && k < n);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < G2; ++i) {
+    const int g = tid + 256 * i;
+    const int pt = g / (NCH * 64), c = (g / 64) % NCH, l = g % 64;
+    const int row = 16 * pt + (l & 15);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int k = 16 * (2 * c + e) + 4 * (l >> 4);
+      x2[i][e] = ld4(W2m, W2m + (int64_t)row * Hs + k, g < NPT * NCH * 64 && row < n && 2 * c + e < HT && k < H);
+    }
+  }
+  xb = ld4(b1, b1 + 4 * tid, 4 * tid < H && 4 * tid < 16 * HT);
+  // this wave's samples: spins, the direct and bias terms of the logits
+  const int64_t sb = bw + 16 * wave + ls;
+  const bool valid = sb < mi.B;
+  const int8_t *spn = a.spins + mi.spin_off + (valid ? sb : 0) * n;
+  uint32_t wv[NPT];
+#pragma unroll
+  for (int t = 0; t < NPT; ++t) {
+    const int p0 = 16 * t + 4 * lg;
+    wv[t] = *reinterpret_cast<const uint32_t *>(spn + (p0 < n ? p0 : 0));
+  }
+  f4 w0[NPT][2 * NC], bz[NPT];
+#pragma unroll
+  for (int pt = 0; pt < NPT; ++pt) {
+    const int pa = 16 * pt + ls;
+    bz[pt] = ld4(b2, b2 + 16 * pt + 4 * lg, 16 * pt + 4 * lg < n);
+#pragma unroll
+    for (int t = 0; t < 2 * NC; ++t)
+      w0[pt][t] = t < NPT ? ld4(W0, W0 + (int64_t)pa * n + 16 * t + 4 * lg, pa < n && 16 * t + 4 * lg < n)
+                          : f4{0.f, 0.f, 0.f, 0.f};
+  }
+  const double fv = a.f[mi.sample_off + (valid ? sb : 0)];
+  // F_q from the free-energy kernel's block sums (as mgrad_kernel)
+  double Fq;
+  {
+    const double *fp = a.fpart + (int64_t)q * 4 * a.fnblk;
+    auto bsum = [&](int c) {
+      double v = fp[c * a.fnblk + (lane < a.fnblk ? lane : 0)];
+      v = lane < a.fnblk ? v : 0.0;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+      return __shfl(v, 0, 64);
+    };
+    const double s0 = bsum(0);
+    Fq = s0 / (double)mi.B;
+    if (bw == 0 && wave == 0) {
+      const double sm[4] = {s0, bsum(1), bsum(2), bsum(3)};
+      if (lane == 0) free_stats(sm, mi.B, a.stats + 4 * q);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < G1; ++i) {
+    const int g = tid + 256 * i;
+    if (g < HT * NC * 64) split8(x1[i][0], x1[i][1], A1[g], A1[HT * NC * 64 + g]);
+  }
+#pragma unroll
+  for (int i = 0; i < G2; ++i) {
+    const int g = tid + 256 * i;
+    if (g < NPT * NCH * 64) split8(x2[i][0], x2[i][1], A2[g], A2[NPT * NCH * 64 + g]);
+  }
+  if (4 * tid < 16 * HT) *reinterpret_cast<f4 *>(b1s + 4 * tid) = xb;
+  for (int k = tid; k < 16 * HT; k += blockDim.x) deg[k] = k < H ? 1 + k % nm1 : 1 << 30;
+  float sp[NPT][4];
+#pragma unroll
+  for (int t = 0; t < NPT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int pos = 16 * t + 4 * lg + r;
+      sp[t][r] = (valid && pos < n) ? (float)(int8_t)(wv[t] >> (8 * r)) : 0.f;
+    }
+  bf8v sc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) sc[c] = spin_c<NPT>(sp, c);
+  const float wt = valid ? (float)((fv - Fq) / (double)mi.B) : 0.f;
+  __syncthreads();
+
+  // hidden layer: h = tanh(b1 + W1m s), R-layout, 16 units per tile
+  float h[HT][4];
+#pragma unroll
+  for (int ht = 0; ht < HT; ++ht) {
+    const f4 bl = *reinterpret_cast<const f4 *>(b1s + 16 * ht + 4 * lg);
+    f4 acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = 16 * ht + 4 * lg + r < H ? bl[r] : 0.f;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const int g = (ht * NC + c) * 64 + lane;
+      acc = mfma_b(as8(A1[g]), sc[c], acc);
+      acc = mfma_b(as8(A1[HT * NC * 64 + g]), sc[c], acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) h[ht][r] = (16 * ht + 4 * lg + r < H) ? ftanh(acc[r]) : 0.f;
+  }
+  // logits: z = b2 + W0m s + W2m h, R-layout, 16 positions per tile
+  f4 z[NPT];
+#pragma unroll
+  for (int pt = 0; pt < NPT; ++pt) {
+    const int pa = 16 * pt + ls;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) z[pt][r] = 16 * pt + 4 * lg + r < n ? bz[pt][r] : 0.f;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      f4 m0, m1;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {   // strictly lower
+        m0[r] = 16 * (2 * c) + 4 * lg + r < pa ? w0[pt][2 * c][r] : 0.f;
+        m1[r] = 16 * (2 * c + 1) + 4 * lg + r < pa ? w0[pt][2 * c + 1][r] : 0.f;
+      }
+      u4w hi, lo;
+      split8(m0, m1, hi, lo);
+      z[pt] = mfma_b(as8(hi), sc[c], z[pt]);
+      z[pt] = mfma_b(as8(lo), sc[c], z[pt]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    bf8v hb, hs;
+    split_c<HT>(h, c, hb, hs);
+#pragma unroll
+    for (int pt = 0; pt < NPT; ++pt) {
+      const int g = (pt * NCH + c) * 64 + lane;
+      const bf8v ah = as8(A2[g]), al = as8(A2[NPT * NCH * 64 + g]);
+      z[pt] = mfma_b(ah, hb, z[pt]);
+      z[pt] = mfma_b(ah, hs, z[pt]);
+      z[pt] = mfma_b(al, hb, z[pt]);
+    }
+  }
+  float dl[NPT][4];
+#pragma unroll
+  for (int pt = 0; pt < NPT; ++pt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int pos = 16 * pt + 4 * lg + r;
+      const float s1 = sp[pt][r];
+      dl[pt][r] = pos < n ? wt * ((1.f + s1) * 0.5f - fsigmoid(z[pt][r])) : 0.f;
+    }
+  bf8v dlb[NC], dls[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) split_c<NPT>(dl, c, dlb[c], dls[c]);
+
+  // -- backward passes; W2m^T slices loaded one pass ahead --
+  f4 xt[GT][2];
+  auto wt_load = [&](int pass) {
+#pragma unroll
+    for (int i = 0; i < GT; ++i) {
+      const int g = tid + 256 * i;
+      const int j = g / (NC * 64), c = (g / 64) % NC, l = g % 64;
+      const int row = 16 * (QT * pass + j) + (l & 15);
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int k = 16 * (2 * c + e) + 4 * (l >> 4);
+        xt[i][e] = ld4(W2T, W2T + (int64_t)row * n + k, g < QT * NC * 64 && row < H && 2 * c + e < NPT && k < n);
+      }
+    }
+  };
+  wt_load(0);
+  __syncthreads();   // the network phase's LDS is free
+  // staged feature-major: dlogit (hi, lo) and the spins; the bias-2 sums of
+  // the wave's 16 samples
+  const int srow = 16 * wave + ls;
+#pragma unroll
+  for (int pt = 0; pt < NPT; ++pt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * pt + 4 * lg + r;
+      const __bf16 vh = (__bf16)dl[pt][r];
+      dlh[row * kMg3K + srow] = vh;
+      dll[row * kMg3K + srow] = (__bf16)(dl[pt][r] - (float)vh);
+      sT[row * kMg3K + srow] = (__bf16)sp[pt][r];
+      const float bs = row16_sum(dl[pt][r]);
+      if (ls == 0) b2p[wave * 16 * NPT + row] = bs;
+    }
+  float *prow = a.part + (int64_t)blockIdx.x * a.pstride;
+  const int64_t o_b1 = (int64_t)Hs * n, o_W2 = o_b1 + Hs, o_b2 = o_W2 + (int64_t)n * Hs,
+                o_W0 = o_b2 + n;
+  // one staged row chunk: 8 samples (32 c + 8 lg ...) of row r, as BF16
+  auto rd = [&](const __bf16 *X, int row, int c) {
+    return __builtin_bit_cast(bf8v, *reinterpret_cast<const u4w *>(X + row * kMg3K + 32 * c + 8 * lg));
+  };
+#pragma unroll
+  for (int pass = 0; pass < HT / QT; ++pass) {
+    const int hbase = 16 * QT * pass;   // first hidden unit of the pass
+    u4w *wb = WT + (pass & 1) * 2 * QT * NC * 64;
+#pragma unroll
+    for (int i = 0; i < GT; ++i) {
+      const int g = tid + 256 * i;
+      if (g < QT * NC * 64) split8(xt[i][0], xt[i][1], wb[g], wb[QT * NC * 64 + g]);
+    }
+    if (pass + 1 < HT / QT) wt_load(pass + 1);
+    __syncthreads();   // the slice is staged; the previous pass's products are done
+#pragma unroll
+    for (int j = 0; j < QT; ++j) {
+      // dh = W2m^T dlogit, da = dh (1 - h^2)
+      f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int g = (j * NC + c) * 64 + lane;
+        const bf8v ah = as8(wb[g]), al = as8(wb[QT * NC * 64 + g]);
+        acc = mfma_b(ah, dlb[c], acc);
+        acc = mfma_b(ah, dls[c], acc);
+        acc = mfma_b(al, dlb[c], acc);
+      }
+      const float *hv = h[QT * pass + j];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * j + 4 * lg + r;
+        const float dv = acc[r] * (1.f - hv[r] * hv[r]);
+        const __bf16 xh = (__bf16)hv[r], dh = (__bf16)dv;
+        hh[row * kMg3K + srow] = xh;
+        hl[row * kMg3K + srow] = (__bf16)(hv[r] - (float)xh);
+        dah[row * kMg3K + srow] = dh;
+        dal[row * kMg3K + srow] = (__bf16)(dv - (float)dh);
+        const float bs = row16_sum(dv);
+        if (ls == 0) b1p[wave * 16 * QT + row] = bs;
+      }
+    }
+    __syncthreads();
+    // tiles of the pass: NPT*QT of gW2 (pt, j), QT*NPT of gW1 (j, jt), and
+    // in the first pass NPT*NPT of gW0 (pt, jt); wave w takes w, w + 4, ...
+    constexpr int n2 = NPT * QT, n1 = QT * NPT;
+    const int ntile = n2 + n1 + (pass == 0 ? NPT * NPT : 0);
+    for (int tile = wave; tile < ntile; tile += 4) {
+      f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+      int ai, bj, kind;
+      if (tile < n2) {
+        kind = 2;   // gW2 = dlogit^T h
+        const int pt = tile / QT, j = tile % QT;
+        ai = 16 * pt; bj = 16 * j;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const bf8v xh = rd(dlh, ai + ls, c), xl = rd(dll, ai + ls, c);
+          const bf8v yh = rd(hh, bj + ls, c), yl = rd(hl, bj + ls, c);
+          acc = mfma_b(xh, yh, acc);
+          acc = mfma_b(xh, yl, acc);
+          acc = mfma_b(xl, yh, acc);
+        }
+      } else if (tile < n2 + n1) {
+        kind = 1;   // gW1 = da^T s
+        const int e = tile - n2, j = e / NPT, jt = e % NPT;
+        ai = 16 * j; bj = 16 * jt;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const bf8v xh = rd(dah, ai + ls, c), xl = rd(dal, ai + ls, c), ys = rd(sT, bj + ls, c);
+          acc = mfma_b(xh, ys, acc);
+          acc = mfma_b(xl, ys, acc);
+        }
+      } else {
+        kind = 0;   // gW0 = dlogit^T s
+        const int e = tile - n2 - n1, pt = e / NPT, jt = e % NPT;
+        ai = 16 * pt; bj = 16 * jt;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const bf8v xh = rd(dlh, ai + ls, c), xl = rd(dll, ai + ls, c), ys = rd(sT, bj + ls, c);
+          acc = mfma_b(xh, ys, acc);
+          acc = mfma_b(xl, ys, acc);
+        }
+      }
+      // lane holds rows ai + 4 lg + r, column bj + ls (as mgrad_kernel)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = ai + 4 * lg + r, col = bj + ls;
+        if (kind == 2) {         // gW2[pos][k]: deg(k) <= pos
+          const int k = hbase + col;
+          if (row < n && k < Hs)
+            prow[o_W2 + (int64_t)row * Hs + k] = deg[k] <= row ? acc[r] : 0.f;
+        } else if (kind == 1) {  // gW1[k][j]: j < deg(k)
+          const int k = hbase + row;
+          if (k < Hs && col < n) prow[(int64_t)k * n + col] = col < deg[k] ? acc[r] : 0.f;
+        } else {                 // gW0[pos][j]: j < pos
+          if (row < n && col < n) prow[o_W0 + (int64_t)row * n + col] = col < row ? acc[r] : 0.f;
+        }
+      }
+    }
+    // bias gradients of the pass: the four waves' 16-sample sums in order
+    for (int k = tid; k < 16 * QT; k += blockDim.x) {
+      const int kk = hbase + k;
+      if (kk >= Hs) continue;
+      const float v = kk < H ? ((b1p[k] + b1p[16 * QT + k]) + b1p[32 * QT + k]) + b1p[48 * QT + k] : 0.f;
+      prow[o_b1 + kk] = v;
+    }
+    if (pass == 0)
+      for (int i = tid; i < n; i += blockDim.x)
+        prow[o_b2 + i] = ((b2p[i] + b2p[16 * NPT + i]) + b2p[32 * NPT + i]) + b2p[48 * NPT + i];
+  }
+}
+
 // Sum of the instance's workgroup rows in a fixed order, in two passes:
 // slice z of the rows (rows r0 + z, r0 + z + kRedSplit, ...) into part2[q][z]
 // here, then the kRedSplit slices in the optimiser.  Four parameters per
@@ -1232,6 +1664,17 @@ __global__ void mgrad_reduce1(const MadeInst *mi, const int32_t *first_row, cons
 }
 
 template <int NPT>
+void (*pick_mgrad3(int ht))(MGradArgs) {
+  switch (ht) {
+    case 1: return mgrad3_kernel<NPT, 1>;
+    case 2: return mgrad3_kernel<NPT, 2>;
+    case 4: return mgrad3_kernel<NPT, 4>;
+    case 8: return mgrad3_kernel<NPT, 8>;
+    default: return mgrad3_kernel<NPT, 16>;
+  }
+}
+
+template <int NPT>
 void (*pick_mgrad(int ht))(MGradArgs) {
   switch (ht) {
     case 1: return mgrad_kernel<NPT, 1>;
@@ -1251,25 +1694,30 @@ size_t made_param_bytes(int n, int H) { return made_stage_bytes(n, H); }
 int64_t made_pack_floats(int n, int npt, int H) { return mpack_floats(n, npt, H); }
 int64_t made_w2t_offset(int n, int npt) { return msample_floats(n, npt); }
 
-size_t mgrad_lds_bytes(int H, int npt) {
-  int hpad = 16;
-  while (hpad < H) hpad <<= 1;
-  return mg_bytes(hpad, npt);
+size_t mgrad_lds_bytes(int H, int npt, bool split) {
+  int ht = 1;
+  while (16 * ht < H) ht <<= 1;
+  return split ? mg3_layout(npt, ht).end : mg_bytes(16 * ht, npt);
 }
 int mgrad_split() { return kRedSplit; }
 
 hipError_t launch_mgrad(const MGradArgs &a, int npt, hipStream_t st) {
   if (a.n_tasks <= 0) return hipSuccess;
-  int hpad = 16;
-  while (hpad < a.hmax) hpad <<= 1;
-  const size_t lds = mg_bytes(hpad, npt);
-    int ht = 1;
+  int ht = 1;
   while (16 * ht < a.hmax) ht <<= 1;
   if (npt > 4 || ht > 16) return hipErrorInvalidValue;
+  const size_t lds = mgrad_lds_bytes(a.hmax, npt, a.split != 0);
   void (*k)(MGradArgs) = nullptr;
-  if (npt <= 1) k = pick_mgrad<1>(ht);
-  else if (npt <= 2) k = pick_mgrad<2>(ht);
-  else k = pick_mgrad<4>(ht);
+  if (a.split) {
+    // (|W| <= 32: the 4-tile form would spill registers)
+    if (npt <= 1) k = pick_mgrad3<1>(ht);
+    else if (npt <= 2) k = pick_mgrad3<2>(ht);
+    else return hipErrorInvalidValue;
+  } else {
+    if (npt <= 1) k = pick_mgrad<1>(ht);
+    else if (npt <= 2) k = pick_mgrad<2>(ht);
+    else k = pick_mgrad<4>(ht);
+  }
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;

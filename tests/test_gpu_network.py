@@ -77,13 +77,14 @@ def test_sampler_philox_stream():
     _check_spins(theta, u, n, H, sp)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_free_energy_step_parity(prec):
+@pytest.mark.parametrize("prec,split", [("fp64", False), ("fp32", False), ("fp32", True)])
+def test_free_energy_step_parity(prec, split):
+    from paper_2504_12037_amd import Net
     inst = S.c1_small_lattice(16)
     n, H, B = 4, 16, 1024
     seed, lr = 77, 1e-2
     theta = _theta(n, H, 5, 0.4)
-    net = _net([inst], prec, seed=seed)
+    net = _net([inst], prec, seed=seed, flags=Net.FLAG_SPLIT_BF16 if split else 0)
     net.set_params(0, torch.from_numpy(theta))
     spins = torch.empty(B * n, dtype=torch.int8, device="cuda")
     stats, _ = net.free_energy_step(B, lr, spins_out=spins)
@@ -185,8 +186,8 @@ def test_free_energy_step_graph_replay():
         assert torch.equal(nets[0].get_params(k), nets[1].get_params(k))
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_training_steps_track_the_oracle(graph):
+@pytest.mark.parametrize("graph,split", [(False, False), (True, False), (False, True)])
+def test_training_steps_track_the_oracle(graph, split):
     # several iterations of Algorithm 1 on the GPU beside the FP64 oracle's
     # own run from the same start (its own spins, logZ, gradients and Adam
     # state).  Between steps the optimiser keeps the sampler's packed tables
@@ -198,7 +199,8 @@ def test_training_steps_track_the_oracle(graph):
              S.lattice_column_split(S.lattice_2d(12, seed=6), [5, 9], hidden=32)]
     Bs = [512, 256]
     seed, lr = 41, 1e-2
-    net = _net(insts, "fp32", seed=seed, flags=Net.FLAG_GRAPH if graph else 0)
+    net = _net(insts, "fp32", seed=seed, flags=(Net.FLAG_GRAPH if graph else 0) |
+               (Net.FLAG_SPLIT_BF16 if split else 0))
     ora = []
 
     def restart(k, th):
@@ -218,7 +220,7 @@ def test_training_steps_track_the_oracle(graph):
     for it in range(6):
         if it == 3:
             restart(0, _theta(insts[0].n_width, insts[0].hidden, 70, 0.3))
-        print(f"\n[train] graph={graph} iteration {it}", flush=True)
+        print(f"\n[train] graph={graph} split={split} iteration {it}", flush=True)
         net.free_energy_step(Bs, lr, stats=stats, spins_out=spins)
         torch.cuda.synchronize()
         sp_all, st_all = spins.cpu().numpy(), stats.cpu().numpy()
@@ -266,3 +268,31 @@ def test_packed_tables_after_training_equal_a_fresh_pack():
     sb, lb = b.sample(Bs, u)
     torch.cuda.synchronize()
     assert torch.equal(sa, sb) and torch.equal(la, lb)
+
+
+def test_reinforce_gradient_full_width_split_products():
+    # the 16x16 lattice workload's network (|W| = 32, H = 256) with
+    # split-BF16 products: one step's statistics and REINFORCE gradient
+    # against the oracle on the step's own samples
+    from paper_2504_12037_amd import Net
+    inst = S.c2_lattice(1.0)
+    n, H, B = 32, 256, 2048
+    seed, lr = 19, 1e-3
+    theta = _theta(n, H, 6, 0.05)
+    net = _net([inst], "fp32", seed=seed, flags=Net.FLAG_SPLIT_BF16)
+    net.set_params(0, torch.from_numpy(theta))
+    spins = torch.empty(B * n, dtype=torch.int8, device="cuda")
+    print("\n[split-grad] C2 network, 2048 samples", flush=True)
+    stats, _ = net.free_energy_step(B, lr, spins_out=spins)
+    torch.cuda.synchronize()
+    sp = spins.cpu().numpy().reshape(B, n)
+    u = OP.sampler_uniforms(seed, 0, 0, B, n)
+    _, lq = _check_spins(theta, u, n, H, sp)
+    lz = OI.logz_r_elimination(inst, sp)
+    f, st = OO.free_energy_terms(inst, sp, lq, lz)
+    np.testing.assert_allclose(stats.cpu().numpy()[0], st, atol=2e-4, rtol=2e-5)
+    g = OM.logq_backward(theta.astype(np.float64), sp, OO.reinforce_weights(f), n, H)
+    g_gpu = net.get_state(0, 1).cpu().numpy()
+    err = np.abs(g_gpu - g).max() / np.abs(g).max()
+    print(f"[split-grad] max |g_gpu - g| / max |g| = {err:.2e}", flush=True)
+    assert err <= 1e-4
