@@ -682,25 +682,43 @@ __global__ __launch_bounds__(256) void unary_kernel(ChainArgs a, const int32_t *
   const int64_t B = a.inst_B[q];
   const int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int p0 = blockIdx.y * kUnaryChunk;
-  if (p0 >= D.nr || b >= B) return;
+  if (p0 >= D.nr) return;
   const int p1 = p0 + kUnaryChunk < D.nr ? p0 + kUnaryChunk : D.nr;
+  // the chunk's descriptors (field, four W-neighbour records, neighbour
+  // count) staged in LDS by one load per thread, then read with uniform
+  // addresses: no scalar round trip per position
+  __shared__ float s_h[kUnaryChunk], s_j[kUnaryChunk][4];
+  __shared__ int32_t s_w[kUnaryChunk][4], s_r[kUnaryChunk][4], s_n[kUnaryChunk];
+  {
+    const int t = threadIdx.x, np = p1 - p0;
+    if (t < 4 * np) {
+      const int64_t e = 4 * ((int64_t)D.hr_off + p0) + t;
+      s_w[t >> 2][t & 3] = a.cf_w[e];
+      s_r[t >> 2][t & 3] = a.cf_r[e];
+      s_j[t >> 2][t & 3] = a.cf_J[e];
+    } else if (t >= 64 && t < 64 + np) {
+      const int p = p0 + t - 64;
+      s_h[t - 64] = a.hR[D.hr_off + p];
+      s_n[t - 64] = a.fld_ptr[D.fld_off + p + 1] - a.fld_ptr[D.fld_off + p];
+    }
+  }
+  __syncthreads();
+  if (b >= B) return;
   // the sample's width-set spins as a bit mask, read with uniform indices
   const SpinBits sb = load_bits_row(a.spins + a.inst_spin_off[q] + b * D.nw, D.nw);
   const float beta = (float)D.beta;
   float *Uq = U + a.u_off[q];
-  const ci32 fptr = (ci32)(a.fld_ptr + D.fld_off);
-  const ci32 cw = (ci32)(a.cf_w + 4 * (int64_t)D.hr_off), cr = (ci32)(a.cf_r + 4 * (int64_t)D.hr_off);
-  const cf32 cj = (cf32)(a.cf_J + 4 * (int64_t)D.hr_off), hr = (cf32)(a.hR + D.hr_off);
   double fab = 0.0;
   for (int p = p0; p < p1; ++p) {
-    float f = hr[p];
-    const int nn = fptr[p + 1] - fptr[p];
-    if (nn <= 4) {
+    const int i = p - p0;
+    float f = s_h[i];
+    if (s_n[i] <= 4) {
       float t[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) t[k] = cr[4 * p + k] >= 0 ? cj[4 * p + k] * sb.sigma(cw[4 * p + k]) : 0.f;
+      for (int k = 0; k < 4; ++k) t[k] = s_r[i][k] >= 0 ? s_j[i][k] * sb.sigma(s_w[i][k]) : 0.f;
       f += (t[0] + t[1]) + (t[2] + t[3]);
     } else {
+      const ci32 fptr = (ci32)(a.fld_ptr + D.fld_off);
       const ci32 fw = (ci32)(a.fld_w + D.fld_nnz_off);
       const cf32 fj = (cf32)(a.fld_J + D.fld_nnz_off);
       for (int k = fptr[p]; k < fptr[p + 1]; ++k) f += fj[k] * sb.sigma(fw[k]);
