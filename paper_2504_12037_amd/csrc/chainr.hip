@@ -501,11 +501,10 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
       for (int r = 0; r < 4; ++r) As[i][r] = cur.a[i][r];
     // operands used later in this step, issued now: T (for G = H o T) and
     // the S_x / S_o tables, in FP32 or split-BF16 form
-    f4 tr[kS ? 1 : CT][kS ? 1 : CT], sx[kS ? 1 : CT], so[kS ? 1 : CT];
-    FwdOps<2, CT> t3;
+    f4 tr[CT][CT], sx[kS ? 1 : CT], so[kS ? 1 : CT];
     u4v sxb[NC], sob[NC];
+    load_t<CT>(a.Tr + st.tr_off, lane, tr);
     if constexpr (kS) {
-      t3.load(a, st, lane);
       const u4v *q3 = reinterpret_cast<const u4v *>(a.Ts3 + st.s3_off) + lane + 4 * CT * NC * 64;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
@@ -513,7 +512,6 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
         sob[c] = q3[(NC + c) * 64];
       }
     } else {
-      load_t<CT>(a.Tr + st.tr_off, lane, tr);
       const f4 *sxo = reinterpret_cast<const f4 *>(a.Tsx + st.sx_off) + lane;
 #pragma unroll
       for (int i = 0; i < CT; ++i) {
@@ -614,16 +612,14 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
         for (int xt = 0; xt < CT; ++xt) hg[xt] = mfma_bf(ah1[xt], rb1[ot], f4{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
         for (int xt = 0; xt < CT; ++xt) hg[xt] = mfma_bf(ah2[xt], rb2[ot], hg[xt]);
-        // G = H o T (T = hi + lo of the forward table, element 4 xt + r of
-        // this lane), then Q'^T = G^T S_x with the lane's 8 G values as the
-        // operand (S_x is exact in BF16: two products)
-        const bf8 th = as_bf8(t3.h[ot][0]), tl = as_bf8(t3.l[ot][0]);
+        // G = H o T (the FP32 table, R-layout), then Q'^T = G^T S_x with the
+        // lane's 8 G values as the operand (S_x is exact in BF16: two
+        // products)
         float gv[CT][4];
 #pragma unroll
         for (int xt = 0; xt < CT; ++xt)
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            gv[xt][r] = hg[xt][r] * ((float)th[4 * xt + r] + (float)tl[4 * xt + r]);
+          for (int r = 0; r < 4; ++r) gv[xt][r] = hg[xt][r] * tr[ot][xt][r];
         bf8 gh, gl;
         split_chunk<CT>(gv, 0, gh, gl);
         qt[ot] = mfma_bf(gh, as_bf8(sxb[0]), f4{0.f, 0.f, 0.f, 0.f});

@@ -186,8 +186,9 @@ def test_free_energy_step_graph_replay():
         assert torch.equal(nets[0].get_params(k), nets[1].get_params(k))
 
 
-@pytest.mark.parametrize("graph,split", [(False, False), (True, False), (False, True)])
-def test_training_steps_track_the_oracle(graph, split):
+@pytest.mark.parametrize("graph,split,Bs", [(False, False, (512, 256)), (True, False, (512, 256)),
+                                             (False, True, (512, 256)), (False, True, (300, 77))])
+def test_training_steps_track_the_oracle(graph, split, Bs):
     # several iterations of Algorithm 1 on the GPU beside the FP64 oracle's
     # own run from the same start (its own spins, logZ, gradients and Adam
     # state).  Between steps the optimiser keeps the sampler's packed tables
@@ -197,7 +198,7 @@ def test_training_steps_track_the_oracle(graph, split):
     from paper_2504_12037_amd import Net
     insts = [S.c1_small_lattice(16),
              S.lattice_column_split(S.lattice_2d(12, seed=6), [5, 9], hidden=32)]
-    Bs = [512, 256]
+    Bs = list(Bs)
     seed, lr = 41, 1e-2
     net = _net(insts, "fp32", seed=seed, flags=(Net.FLAG_GRAPH if graph else 0) |
                (Net.FLAG_SPLIT_BF16 if split else 0))
