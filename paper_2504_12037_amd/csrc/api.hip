@@ -55,13 +55,13 @@ struct DBuf {
   size_t bytes = 0;
   hipError_t ensure(size_t need) {
     if (need <= bytes) return hipSuccess;
-    if (p) { hipFree(p); p = nullptr; bytes = 0; }
+    if (p) { (void)hipFree(p); p = nullptr; bytes = 0; }
     g_buf_gen.fetch_add(1);
     hipError_t e = hipMalloc(&p, need);
     if (e == hipSuccess) bytes = need;
     return e;
   }
-  void release() { if (p) hipFree(p); p = nullptr; bytes = 0; }
+  void release() { if (p) (void)hipFree(p); p = nullptr; bytes = 0; }
   template <typename T> T *as() const { return static_cast<T *>(p); }
 };
 
@@ -196,11 +196,11 @@ struct ProfScope {
       ev = {nullptr, nullptr};
       return;
     }
-    hipEventRecord(ev.first, st);
+    (void)hipEventRecord(ev.first, st);
   }
   ~ProfScope() {
     if (!ev.first) return;
-    hipEventRecord(ev.second, st);
+    (void)hipEventRecord(ev.second, st);
     net->prof_used[kind].push_back(ev);
   }
 };
@@ -208,9 +208,9 @@ struct ProfScope {
 // Largest S (power of two <= 64) whose tile fits the LDS budget.
 void choose_tiles(tnvan_net *net, bool bwd) {
   int dev = 0;
-  hipGetDevice(&dev);
+  (void)hipGetDevice(&dev);
   int maxlds = 65536;
-  hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  (void)hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   const size_t budget = std::min<size_t>((size_t)maxlds, 80 * 1024);
   // instances in transfer-matrix form run in the chain kernels instead
   auto worst_of = [&](int S, bool glob) {
@@ -621,11 +621,12 @@ tnvan_status ensure_sample_blocks(tnvan_net *net) {
     HIPCHK(upload(net->mtask_inst, ti));
     HIPCHK(upload(net->mtask_start, ts));
     net->n_mtasks = (int)ti.size();
-    // fused REINFORCE backward: one workgroup per 64 samples
+    // fused REINFORCE backward: one workgroup per mgrad_task_samples samples
+    const int tsz = mgrad_task_samples(net->split && net->mpt <= 2);
     std::vector<int32_t> gi, gs, gf(net->n_inst), gc(net->n_inst);
     for (int q = 0; q < net->n_inst; ++q) {
       gf[q] = (int32_t)gi.size();
-      for (int64_t b = 0; b < net->nkey[q]; b += 64) { gi.push_back(q); gs.push_back((int32_t)b); }
+      for (int64_t b = 0; b < net->nkey[q]; b += tsz) { gi.push_back(q); gs.push_back((int32_t)b); }
       gc[q] = (int32_t)gi.size() - gf[q];
     }
     HIPCHK(upload(net->mg_task_inst, gi));
@@ -937,7 +938,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
     // fused REINFORCE backward: n <= 64, H <= 256, rows of 64 samples in LDS
     int dev = 0, maxlds = 65536;
     hipGetDevice(&dev);
-    hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    (void)hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     bool gfit = net->precision != TNVAN_FP64;
     for (auto &m : net->mi) {
       net->mg_hmax = std::max(net->mg_hmax, (int)m.H);
@@ -1014,7 +1015,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   {
     int dev = 0, maxlds = 65536;
     hipGetDevice(&dev);
-    hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    (void)hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     ChainLim lim{};
     bool rq = true;
     lim.kbuf = 16;

@@ -150,6 +150,7 @@ struct MGradArgs {
 };
 size_t mgrad_lds_bytes(int H, int npt, bool split);
 int mgrad_split();
+int mgrad_task_samples(bool split);   // samples per workgroup of the fused backward
 hipError_t launch_mgrad(const MGradArgs &a, int npt, hipStream_t st);
 hipError_t launch_mgrad_reduce(const MGradArgs &a, hipStream_t st);
 int64_t made_pack_floats(int n, int npt, int H);

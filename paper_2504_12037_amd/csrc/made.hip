@@ -1218,16 +1218,18 @@ __global__ __launch_bounds__(256, 2) void mgrad_kernel(MGradArgs a) {
 // accumulation; spins are exact in BF16, so products with them take two.
 // A lane's K chunk c holds, in element j, index 16 (2c + j/4) + 4 (l >> 4) +
 // j % 4 of the contracted dimension, so R-layout registers (spins, h, dlogit)
-// are B operands as they are, and the A operands are the FP32 weight rows the
-// FP32 kernel loads, split in registers.  The gradient blocks contract over
-// the workgroup's 64 samples from operands staged feature-major in LDS as
-// BF16 hi and lo rows, eight samples per lane in one 16-byte read.  The bias
-// gradients are FP32 sums of the registers (16 samples per wave, then the
-// four waves in order).
+// are B operands as they are.  A workgroup takes kMg3W waves of 16 samples.
+// It stages the first-layer and logit weights once, every load issued
+// together, split and in operand order in LDS (one 16-byte read per lane and
+// chunk); each backward pass's W2m^T slice is loaded one pass ahead.  The
+// gradient blocks contract over the workgroup's samples from operands staged
+// feature-major in LDS as BF16 hi and lo rows, eight samples per lane in one
+// 16-byte read.  The bias gradients are FP32 sums of the registers (16
+// samples per wave, then the waves in order).
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef unsigned int u4w __attribute__((ext_vector_type(4)));
 typedef float f4v_t __attribute__((ext_vector_type(4)));
-constexpr int kMg3K = 72;       // BF16 per staged row: 64 samples + 8 (bank spread)
+constexpr int kMg3W = 8;        // waves (16 samples each) per workgroup
 
 // LDS of mgrad3_kernel.  The network phase holds the first-layer and logit
 // weights, split, in operand order (16 bytes per lane and chunk); the
@@ -1238,15 +1240,16 @@ struct Mg3Layout {
   size_t wt, dlh, dll, st, hh, hl, dah, dal, b2p, b1p;   // backward passes
   size_t deg, end;
 };
-__host__ __device__ inline Mg3Layout mg3_layout(int npt, int ht) {
+__host__ __device__ inline Mg3Layout mg3_layout(int npt, int ht, int nw) {
   Mg3Layout L;
   const int nc = (npt + 1) / 2, nch = (ht + 1) / 2, qt = ht < kMgPass ? ht : kMgPass;
+  const int kk = 16 * nw + 8;
   size_t o = 0;
   L.a1 = o; o += (size_t)2 * ht * nc * 64 * 16;
   L.a2 = o; o += (size_t)2 * npt * nch * 64 * 16;
   L.b1s = o; o += (size_t)16 * ht * 4;
   const size_t net = o;
-  const size_t rp = (size_t)16 * npt * kMg3K * 2, rq = (size_t)16 * qt * kMg3K * 2;
+  const size_t rp = (size_t)16 * npt * kk * 2, rq = (size_t)16 * qt * kk * 2;
   o = 0;
   L.wt = o; o += (size_t)2 * 2 * qt * nc * 64 * 16;
   L.dlh = o; o += rp;
@@ -1256,8 +1259,8 @@ __host__ __device__ inline Mg3Layout mg3_layout(int npt, int ht) {
   L.hl = o; o += rq;
   L.dah = o; o += rq;
   L.dal = o; o += rq;
-  L.b2p = o; o += (size_t)4 * 16 * npt * 4;
-  L.b1p = o; o += (size_t)4 * 16 * qt * 4;
+  L.b2p = o; o += (size_t)nw * 16 * npt * 4;
+  L.b1p = o; o += (size_t)nw * 16 * qt * 4;
   L.deg = o > net ? o : net;
   L.end = L.deg + (size_t)16 * (ht > 0 ? ht : 1) * 4;
   return L;
@@ -1290,14 +1293,16 @@ __device__ inline bf8v spin_c(const float (&x)[NT][4], int c) {
 }
 
 template <int NPT, int HT>
-__global__ __launch_bounds__(256, 2) void mgrad3_kernel(MGradArgs a) {
+__global__ __launch_bounds__(64 * kMg3W, 8 / kMg3W) void mgrad3_kernel(MGradArgs a) {
   typedef float f4 __attribute__((ext_vector_type(4)));
+  constexpr int NW = kMg3W, NT = 64 * NW;            // waves, threads
+  constexpr int KS = 16 * NW + 8;                   // BF16 per staged row (samples + bank spread)
   constexpr int QT = HT < kMgPass ? HT : kMgPass;   // hidden tiles per pass
   constexpr int NC = (NPT + 1) / 2;                 // K chunks over positions
   constexpr int NCH = (HT + 1) / 2;                 // K chunks over hidden units
-  constexpr int G1 = (HT * NC * 64 + 255) / 256;    // first-layer operand groups per thread
-  constexpr int G2 = (NPT * NCH * 64 + 255) / 256;  // logit operand groups per thread
-  constexpr int GT = (QT * NC * 64 + 255) / 256;    // W2m^T operand groups per thread
+  constexpr int G1 = (HT * NC * 64 + NT - 1) / NT;    // first-layer operand groups per thread
+  constexpr int G2 = (NPT * NCH * 64 + NT - 1) / NT;  // logit operand groups per thread
+  constexpr int GT = (QT * NC * 64 + NT - 1) / NT;    // W2m^T operand groups per thread
   extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane((int)(tid >> 6));
@@ -1306,7 +1311,7 @@ __global__ __launch_bounds__(256, 2) void mgrad3_kernel(MGradArgs a) {
   const MadeInst mi = a.mi[q];
   const int n = mi.n, Hs = mi.H, H = n >= 2 ? mi.H : 0;
   const int64_t bw = a.task_start[blockIdx.x];
-  const Mg3Layout Lm = mg3_layout(NPT, HT);
+  const Mg3Layout Lm = mg3_layout(NPT, HT, NW);
   u4w *A1 = reinterpret_cast<u4w *>(smem + Lm.a1);   // [hi, lo][HT][NC][64]
   u4w *A2 = reinterpret_cast<u4w *>(smem + Lm.a2);   // [hi, lo][NPT][NCH][64]
   float *b1s = reinterpret_cast<float *>(smem + Lm.b1s);
@@ -1346,7 +1351,7 @@ __global__ __launch_bounds__(256, 2) void mgrad3_kernel(MGradArgs a) {
   f4 x1[G1][2], x2[G2][2], xb;
 #pragma unroll
   for (int i = 0; i < G1; ++i) {
-    const int g = tid + 256 * i;
+    const int g = tid + NT * i;
     const int ht = g / (NC * 64), c = (g / 64) % NC, l = g % 64;
     const int row = 16 * ht + (l & 15);
 #pragma unroll
@@ -1357,7 +1362,7 @@ __global__ __launch_bounds__(256, 2) void mgrad3_kernel(MGradArgs a) {
   }
 #pragma unroll
   for (int i = 0; i < G2; ++i) {
-    const int g = tid + 256 * i;
+    const int g = tid + NT * i;
     const int pt = g / (NCH * 64), c = (g / 64) % NCH, l = g % 64;
     const int row = 16 * pt + (l & 15);
 #pragma unroll
@@ -1408,12 +1413,12 @@ __global__ __launch_bounds__(256, 2) void mgrad3_kernel(MGradArgs a) {
   }
 #pragma unroll
   for (int i = 0; i < G1; ++i) {
-    const int g = tid + 256 * i;
+    const int g = tid + NT * i;
     if (g < HT * NC * 64) split8(x1[i][0], x1[i][1], A1[g], A1[HT * NC * 64 + g]);
   }
 #pragma unroll
   for (int i = 0; i < G2; ++i) {
-    const int g = tid + 256 * i;
+    const int g = tid + NT * i;
     if (g < NPT * NCH * 64) split8(x2[i][0], x2[i][1], A2[g], A2[NPT * NCH * 64 + g]);
   }
   if (4 * tid < 16 * HT) *reinterpret_cast<f4 *>(b1s + 4 * tid) = xb;
@@ -1501,7 +1506,7 @@ __global__ __launch_bounds__(256, 2) void mgrad3_kernel(MGradArgs a) {
   auto wt_load = [&](int pass) {
 #pragma unroll
     for (int i = 0; i < GT; ++i) {
-      const int g = tid + 256 * i;
+      const int g = tid + NT * i;
       const int j = g / (NC * 64), c = (g / 64) % NC, l = g % 64;
       const int row = 16 * (QT * pass + j) + (l & 15);
 #pragma unroll
@@ -1522,9 +1527,9 @@ __global__ __launch_bounds__(256, 2) void mgrad3_kernel(MGradArgs a) {
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * pt + 4 * lg + r;
       const __bf16 vh = (__bf16)dl[pt][r];
-      dlh[row * kMg3K + srow] = vh;
-      dll[row * kMg3K + srow] = (__bf16)(dl[pt][r] - (float)vh);
-      sT[row * kMg3K + srow] = (__bf16)sp[pt][r];
+      dlh[row * KS + srow] = vh;
+      dll[row * KS + srow] = (__bf16)(dl[pt][r] - (float)vh);
+      sT[row * KS + srow] = (__bf16)sp[pt][r];
       const float bs = row16_sum(dl[pt][r]);
       if (ls == 0) b2p[wave * 16 * NPT + row] = bs;
     }
@@ -1533,7 +1538,7 @@ __global__ __launch_bounds__(256, 2) void mgrad3_kernel(MGradArgs a) {
                 o_W0 = o_b2 + n;
   // one staged row chunk: 8 samples (32 c + 8 lg ...) of row r, as BF16
   auto rd = [&](const __bf16 *X, int row, int c) {
-    return __builtin_bit_cast(bf8v, *reinterpret_cast<const u4w *>(X + row * kMg3K + 32 * c + 8 * lg));
+    return __builtin_bit_cast(bf8v, *reinterpret_cast<const u4w *>(X + row * KS + 32 * c + 8 * lg));
   };
 #pragma unroll
   for (int pass = 0; pass < HT / QT; ++pass) {
@@ -1541,7 +1546,7 @@ __global__ __launch_bounds__(256, 2) void mgrad3_kernel(MGradArgs a) {
     u4w *wb = WT + (pass & 1) * 2 * QT * NC * 64;
 #pragma unroll
     for (int i = 0; i < GT; ++i) {
-      const int g = tid + 256 * i;
+      const int g = tid + NT * i;
       if (g < QT * NC * 64) split8(xt[i][0], xt[i][1], wb[g], wb[QT * NC * 64 + g]);
     }
     if (pass + 1 < HT / QT) wt_load(pass + 1);
@@ -1564,20 +1569,20 @@ __global__ __launch_bounds__(256, 2) void mgrad3_kernel(MGradArgs a) {
         const int row = 16 * j + 4 * lg + r;
         const float dv = acc[r] * (1.f - hv[r] * hv[r]);
         const __bf16 xh = (__bf16)hv[r], dh = (__bf16)dv;
-        hh[row * kMg3K + srow] = xh;
-        hl[row * kMg3K + srow] = (__bf16)(hv[r] - (float)xh);
-        dah[row * kMg3K + srow] = dh;
-        dal[row * kMg3K + srow] = (__bf16)(dv - (float)dh);
+        hh[row * KS + srow] = xh;
+        hl[row * KS + srow] = (__bf16)(hv[r] - (float)xh);
+        dah[row * KS + srow] = dh;
+        dal[row * KS + srow] = (__bf16)(dv - (float)dh);
         const float bs = row16_sum(dv);
         if (ls == 0) b1p[wave * 16 * QT + row] = bs;
       }
     }
     __syncthreads();
     // tiles of the pass: NPT*QT of gW2 (pt, j), QT*NPT of gW1 (j, jt), and
-    // in the first pass NPT*NPT of gW0 (pt, jt); wave w takes w, w + 4, ...
+    // in the first pass NPT*NPT of gW0 (pt, jt); wave w takes w, w + NW, ...
     constexpr int n2 = NPT * QT, n1 = QT * NPT;
     const int ntile = n2 + n1 + (pass == 0 ? NPT * NPT : 0);
-    for (int tile = wave; tile < ntile; tile += 4) {
+    for (int tile = wave; tile < ntile; tile += NW) {
       f4 acc = f4{0.f, 0.f, 0.f, 0.f};
       int ai, bj, kind;
       if (tile < n2) {
@@ -1585,7 +1590,7 @@ __global__ __launch_bounds__(256, 2) void mgrad3_kernel(MGradArgs a) {
         const int pt = tile / QT, j = tile % QT;
         ai = 16 * pt; bj = 16 * j;
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < NW / 2; ++c) {
           const bf8v xh = rd(dlh, ai + ls, c), xl = rd(dll, ai + ls, c);
           const bf8v yh = rd(hh, bj + ls, c), yl = rd(hl, bj + ls, c);
           acc = mfma_b(xh, yh, acc);
@@ -1597,7 +1602,7 @@ __global__ __launch_bounds__(256, 2) void mgrad3_kernel(MGradArgs a) {
         const int e = tile - n2, j = e / NPT, jt = e % NPT;
         ai = 16 * j; bj = 16 * jt;
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < NW / 2; ++c) {
           const bf8v xh = rd(dah, ai + ls, c), xl = rd(dal, ai + ls, c), ys = rd(sT, bj + ls, c);
           acc = mfma_b(xh, ys, acc);
           acc = mfma_b(xl, ys, acc);
@@ -1607,7 +1612,7 @@ __global__ __launch_bounds__(256, 2) void mgrad3_kernel(MGradArgs a) {
         const int e = tile - n2 - n1, pt = e / NPT, jt = e % NPT;
         ai = 16 * pt; bj = 16 * jt;
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < NW / 2; ++c) {
           const bf8v xh = rd(dlh, ai + ls, c), xl = rd(dll, ai + ls, c), ys = rd(sT, bj + ls, c);
           acc = mfma_b(xh, ys, acc);
           acc = mfma_b(xl, ys, acc);
@@ -1629,16 +1634,23 @@ __global__ __launch_bounds__(256, 2) void mgrad3_kernel(MGradArgs a) {
         }
       }
     }
-    // bias gradients of the pass: the four waves' 16-sample sums in order
+    // bias gradients of the pass: the waves' 16-sample sums in order
     for (int k = tid; k < 16 * QT; k += blockDim.x) {
       const int kk = hbase + k;
       if (kk >= Hs) continue;
-      const float v = kk < H ? ((b1p[k] + b1p[16 * QT + k]) + b1p[32 * QT + k]) + b1p[48 * QT + k] : 0.f;
+      float v = 0.f;
+      if (kk < H)
+#pragma unroll
+        for (int w = 0; w < NW; ++w) v += b1p[w * 16 * QT + k];
       prow[o_b1 + kk] = v;
     }
     if (pass == 0)
-      for (int i = tid; i < n; i += blockDim.x)
-        prow[o_b2 + i] = ((b2p[i] + b2p[16 * NPT + i]) + b2p[32 * NPT + i]) + b2p[48 * NPT + i];
+      for (int i = tid; i < n; i += blockDim.x) {
+        float v = 0.f;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) v += b2p[w * 16 * NPT + i];
+        prow[o_b2 + i] = v;
+      }
   }
 }
 
@@ -1697,7 +1709,7 @@ int64_t made_w2t_offset(int n, int npt) { return msample_floats(n, npt); }
 size_t mgrad_lds_bytes(int H, int npt, bool split) {
   int ht = 1;
   while (16 * ht < H) ht <<= 1;
-  return split ? mg3_layout(npt, ht).end : mg_bytes(16 * ht, npt);
+  return split ? mg3_layout(npt, ht, kMg3W).end : mg_bytes(16 * ht, npt);
 }
 int mgrad_split() { return kRedSplit; }
 
@@ -1721,9 +1733,11 @@ hipError_t launch_mgrad(const MGradArgs &a, int npt, hipStream_t st) {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(a.n_tasks), dim3(256), lds, st, a);
+  hipLaunchKernelGGL(k, dim3(a.n_tasks), dim3(a.split ? 64 * kMg3W : 256), lds, st, a);
   return hipGetLastError();
 }
+
+int mgrad_task_samples(bool split) { return split ? 16 * kMg3W : 64; }
 
 hipError_t launch_mgrad_reduce(const MGradArgs &a, hipStream_t st) {
   if (a.n_tasks <= 0) return hipSuccess;
