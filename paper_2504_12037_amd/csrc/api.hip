@@ -757,7 +757,7 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
   f.ww_J = net->ww_J.as<double>();
   f.hW = net->hW.as<double>();
   f.f = net->w_f.as<double>();
-  f.nblk = (int)std::min<int64_t>(64, (Bmax + 255) / 256);
+  f.nblk = (int)std::min<int64_t>(256, (4 * Bmax + 255) / 256);   // 4 lanes per sample
   HIPCHK(net->w_fpart.ensure((size_t)net->n_inst * f.nblk * 4 * sizeof(double)));
   f.part = net->w_fpart.as<double>();
   f.stats = stats;

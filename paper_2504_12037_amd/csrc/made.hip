@@ -71,6 +71,7 @@ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
 
 constexpr int kRedSplit = 16;   // row splits of the REINFORCE gradient reduction
 constexpr int kFreeStage = 2048;   // W-W couplings staged in LDS by the free-energy kernel
+constexpr int kFreeLanes = 4;      // lanes per sample in the free-energy kernel
 constexpr int KH = 16;    // hidden units per lane
 constexpr int KN = 32;    // width-set positions per lane
 
@@ -411,9 +412,11 @@ __global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
     double lz, lq;
   };
   const bool bits = mi.n <= 128;
-  auto inputs = [&](int64_t b) {
+  auto inputs = [&](int64_t b, bool first) {
     In r;
     if (bits) r.sb = load_bits_row(a.spins + mi.spin_off + b * mi.n, mi.n);
+    r.lz = r.lq = 0.0;
+    if (!first) return r;
     const int64_t g = mi.sample_off + b;
     r.lq = (double)a.logq[g];
     if (a.cpart) {
@@ -441,11 +444,16 @@ __global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
     }
     return r;
   };
-  const int64_t b0 = (int64_t)blockIdx.x * blockDim.x + tid, bstride = (int64_t)gridDim.x * blockDim.x;
+  // kFreeLanes lanes per sample: each sums every kFreeLanes-th E_1 term,
+  // then a butterfly (the same sum on every lane of the group); the first
+  // lane of the group reads the sample's other inputs and forms f
+  const int part = tid % kFreeLanes;
+  const int64_t b0 = ((int64_t)blockIdx.x * blockDim.x + tid) / kFreeLanes,
+                bstride = (int64_t)gridDim.x * blockDim.x / kFreeLanes;
   // the first sample's inputs are requested before the tables are staged,
   // so that both are one memory round trip
   In cur;
-  if (mi.B > 0) cur = inputs(b0 < mi.B ? b0 : 0);
+  if (mi.B > 0) cur = inputs(b0 < mi.B ? b0 : 0, part == 0);
   // the first kFreeStage W-W couplings (endpoints packed in one word) and
   // the W fields staged in LDS once per block: the per-sample loops then
   // read them without a memory round trip per batch of terms
@@ -458,34 +466,41 @@ __global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
   }
   for (int k = tid; k < mi.n && k < 128; k += blockDim.x) s_h[k] = hW[k];
   __syncthreads();
+  const double ib = 1.0 / beta;
+  // (every lane of a group walks the same samples: the loop trip count and
+  // the butterfly are uniform over the group)
   for (int64_t b = b0; b < mi.B; b += bstride) {
-    if (b != b0) cur = inputs(b);
+    if (b != b0) cur = inputs(b, part == 0);
     double e1 = 0.0;
     if (bits) {
       // the +-1 products are exact
       const SpinBits &sb = cur.sb;
-#pragma unroll 8
-      for (int k = 0; k < nst; ++k) {
+#pragma unroll 4
+      for (int k = part; k < nst; k += kFreeLanes) {
         const int ab = s_ab[k];
         const double j = s_J[k];
         e1 -= sb.sigma(ab & 0xffff) * sb.sigma(ab >> 16) > 0.f ? j : -j;
       }
-      for (int k = nst; k < D.n_ww; ++k) {
+      for (int k = nst + part; k < D.n_ww; k += kFreeLanes) {
         const double j = wJ[k];
         e1 -= sb.sigma(wa[k]) * sb.sigma(wb[k]) > 0.f ? j : -j;
       }
-#pragma unroll 8
-      for (int k = 0; k < mi.n; ++k) e1 -= sb.sigma(k) > 0.f ? s_h[k] : -s_h[k];
+#pragma unroll 4
+      for (int k = part; k < mi.n; k += kFreeLanes) e1 -= sb.sigma(k) > 0.f ? s_h[k] : -s_h[k];
     } else {
       const int8_t *s = a.spins + mi.spin_off + b * mi.n;
-      for (int k = 0; k < D.n_ww; ++k) e1 -= wJ[k] * (double)s[wa[k]] * (double)s[wb[k]];
-      for (int k = 0; k < mi.n; ++k) e1 -= hW[k] * (double)s[k];
+      for (int k = part; k < D.n_ww; k += kFreeLanes) e1 -= wJ[k] * (double)s[wa[k]] * (double)s[wb[k]];
+      for (int k = part; k < mi.n; k += kFreeLanes) e1 -= hW[k] * (double)s[k];
     }
-    const double et = e1 - cur.lz / beta;
-    const double lqb = cur.lq / beta;
-    const double f = et + lqb;
-    a.f[mi.sample_off + b] = f;
-    acc[0] += f; acc[1] += f * f; acc[2] += et; acc[3] += lqb;
+#pragma unroll
+    for (int o = 1; o < kFreeLanes; o <<= 1) e1 += __shfl_xor(e1, o, 64);
+    if (part == 0) {
+      const double et = e1 - cur.lz * ib;
+      const double lqb = cur.lq * ib;
+      const double f = et + lqb;
+      a.f[mi.sample_off + b] = f;
+      acc[0] += f; acc[1] += f * f; acc[2] += et; acc[3] += lqb;
+    }
   }
   for (int c = 0; c < 4; ++c) sh[c][tid] = acc[c];
   __syncthreads();
@@ -935,14 +950,19 @@ __global__ __launch_bounds__(256, 2) void mgrad_kernel(MGradArgs a) {
   // F_q from the free-energy kernel's block sums, added in block order (the
   // same value in every workgroup); the instance's first workgroup also
   // writes the step statistics
-  // (lane k holds block k, at most 64 blocks; a fixed tree down to lane 0,
+  // (a fixed order over at most 256 blocks and a fixed tree down to lane 0,
   // then a broadcast)
   double Fq;
   {
     const double *fp = a.fpart + (int64_t)q * 4 * a.fnblk;
     auto bsum = [&](int c) {
-      double v = fp[c * a.fnblk + (lane < a.fnblk ? lane : 0)];
-      v = lane < a.fnblk ? v : 0.0;
+      // lane k holds blocks k, k + 64, ... (in that order)
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < 256; k += 64) {
+        const double x = fp[c * a.fnblk + (lane + k < a.fnblk ? lane + k : 0)];
+        v += lane + k < a.fnblk ? x : 0.0;
+      }
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
       return __shfl(v, 0, 64);
@@ -1398,8 +1418,13 @@ __global__ __launch_bounds__(64 * kMg3W, 8 / kMg3W) void mgrad3_kernel(MGradArgs
   {
     const double *fp = a.fpart + (int64_t)q * 4 * a.fnblk;
     auto bsum = [&](int c) {
-      double v = fp[c * a.fnblk + (lane < a.fnblk ? lane : 0)];
-      v = lane < a.fnblk ? v : 0.0;
+      // lane k holds blocks k, k + 64, ... (in that order)
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < 256; k += 64) {
+        const double x = fp[c * a.fnblk + (lane + k < a.fnblk ? lane + k : 0)];
+        v += lane + k < a.fnblk ? x : 0.0;
+      }
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
       return __shfl(v, 0, 64);
