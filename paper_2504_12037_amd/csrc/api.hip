@@ -163,7 +163,7 @@ struct tnvan_net {
   bool mgrad = false;
   int mg_hmax = 0;
   int64_t mg_pstride = 0;
-  DBuf mg_task_inst, mg_task_start, mg_first, mg_count, w_part2;
+  DBuf mg_task_inst, mg_task_start, mg_first, mg_count;
   int n_mgtasks = 0;
   DBuf task_inst, task_chain, task_start, btask_inst, btask_chain, btask_start, cpart_off,
       chain_list, cpart;
@@ -778,9 +778,6 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
   o.npt = net->mpt;
   o.lr = lr;
   o.step_ctr = net->step_ctr.as<int32_t>();
-  o.part2 = nullptr;
-  o.pstride = net->mg_pstride;
-  o.nsplit = mgrad_split();
   if (net->mgrad && sizeof(real) == 4) {
     // fused REINFORCE backward of every instance (Eq. 10)
     HIPCHK(net->w_part.ensure(std::max<int64_t>(1, (int64_t)net->n_mgtasks * net->mg_pstride) *
@@ -803,16 +800,15 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     g.pstride = net->mg_pstride;
     g.first_row = net->mg_first.as<int32_t>();
     g.n_rows = net->mg_count.as<int32_t>();
-    HIPCHK(net->w_part2.ensure((size_t)net->n_inst * mgrad_split() * net->mg_pstride * sizeof(float)));
-    g.part2 = net->w_part2.as<float>();
     g.pack = net->mpack.as<float>();
     g.grad = net->grad.as<float>();
     {
       ProfScope ps(net, TNVAN_KERNEL_MADE_GRAD, st);
       HIPCHK(launch_mgrad(g, net->mpt, st));
     }
-    HIPCHK(launch_mgrad_reduce(g, st));
-    o.part2 = g.part2;
+    int64_t max_pc = 1;
+    for (auto pc : net->param_count) max_pc = std::max(max_pc, pc);
+    HIPCHK(launch_grad_adam(g, o, max_pc, st));
   }
   for (int q = 0; q < net->n_inst && !fused; ++q) {
     const MadeInst &m = net->mi[q];
@@ -850,7 +846,7 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     HIPCHK(launch_atb<real>(r.dlogit, n, r.sf, n, m.B, n, n, part, ks, gW0, n, 2, n, st));
     HIPCHK(launch_colsum<real>(r.dlogit, n, m.B, n, part, ks, gb2, st));
   }
-  {
+  if (!fused) {
     int64_t max_pc = 1;
     for (auto pc : net->param_count) max_pc = std::max(max_pc, pc);
     HIPCHK(launch_adam_step(o, net->n_inst, max_pc, st));
@@ -1106,7 +1102,7 @@ void tnvan_free_network(tnvan_net *net) {
                  &net->tickets, &net->inv_v, &net->inv_e, &net->pcoef, &net->fabp, &net->u_off,
                  &net->f_off,
                  &net->mpack, &net->mtask_inst, &net->mtask_start, &net->mg_task_inst,
-                 &net->mg_task_start, &net->mg_first, &net->mg_count, &net->w_part2,
+                 &net->mg_task_start, &net->mg_first, &net->mg_count,
                  &net->cpart_off, &net->chain_list, &net->cpart};
   for (DBuf *b : all) b->release();
   TileCache *tcs[] = {&net->tc_fwd, &net->tc_bwd};

@@ -143,16 +143,17 @@ struct MGradArgs {
   float *part;                  // [n_tasks][pstride]
   int64_t pstride;
   const int32_t *first_row, *n_rows;   // per instance: its workgroup rows
-  float *part2;                 // [n_inst][mgrad_split()][pstride]
   const float *pack;            // made_pack_kernel output (holds the masked W2^T)
   float *grad;                  // flat parameter gradient
   int32_t split;                // products as split-BF16 (mgrad3_kernel)
 };
 size_t mgrad_lds_bytes(int H, int npt, bool split);
-int mgrad_split();
 int mgrad_task_samples(bool split);   // samples per workgroup of the fused backward
 hipError_t launch_mgrad(const MGradArgs &a, int npt, hipStream_t st);
-hipError_t launch_mgrad_reduce(const MGradArgs &a, hipStream_t st);
+struct OptArgs;
+// the REINFORCE gradient (the fixed-order sum of each instance's workgroup
+// rows) and the Adam step in one launch (grad_adam_kernel)
+hipError_t launch_grad_adam(const MGradArgs &g, const OptArgs &o, int64_t max_pc, hipStream_t st);
 int64_t made_pack_floats(int n, int npt, int H);
 hipError_t launch_made_pack(const MadeInst *mi, int n_inst, int64_t max_floats, const float *params,
                             float *pack, int npt, hipStream_t st);
@@ -219,9 +220,6 @@ hipError_t launch_free(const FreeArgs<real> &a, int n_inst, hipStream_t st);
 struct OptArgs {
   const MadeInst *mi;
   float *params, *grad, *m, *v;
-  const float *part2;        // split gradient rows [n_inst][nsplit][pstride], or null
-  int64_t pstride;
-  int32_t nsplit;
   float *pack;               // packed operand tables kept current, or null
   int32_t npt;               // position tiles of the packed tables
   float lr;

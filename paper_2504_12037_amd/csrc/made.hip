@@ -69,7 +69,6 @@ __device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
   }
 }
 
-constexpr int kRedSplit = 16;   // row splits of the REINFORCE gradient reduction
 constexpr int kFreeStage = 2048;   // W-W couplings staged in LDS by the free-energy kernel
 constexpr int kFreeLanes = 4;      // lanes per sample in the free-energy kernel
 constexpr int KH = 16;    // hidden units per lane
@@ -559,41 +558,25 @@ __device__ inline void adam_one(float gi, float &p, float &m, float &v, double c
 
 __device__ inline void pack_scatter(float *P, int n, int Hs, int npt, int64_t i, float v);
 
-// Adam for every instance in one launch (grid.y = instance).  The gradient
-// is either the flat gradient buffer or, after the fused REINFORCE backward,
-// the fixed-order FP64 sum of its split rows (then also stored as the
-// gradient).  The step counter already counts this step (the free-energy
-// kernel advanced it).  With pack set, each updated parameter is also
-// written into the packed operand tables (pack_scatter), which then stay
-// current.
+// Adam for every instance in one launch (grid.y = instance), on the flat
+// gradient buffer.  The step counter already counts this step (the
+// free-energy kernel advanced it).  With pack set, each updated parameter
+// is also written into the packed operand tables (pack_scatter), which then
+// stay current.
 __global__ __launch_bounds__(256) void adam_step_kernel(OptArgs a) {
   const int q = blockIdx.y;
   const MadeInst mi = a.mi[q];
   // an instance without samples this step keeps its parameters and moments
   if (mi.B <= 0) return;
   const int64_t pc = (int64_t)mi.H * mi.n + mi.H + (int64_t)mi.n * mi.H + mi.n + (int64_t)mi.n * mi.n;
-  float *P = a.params + mi.param_off, *G = a.grad + mi.param_off, *M = a.m + mi.param_off,
-        *V = a.v + mi.param_off;
-  const float *p2 = a.part2 ? a.part2 + (int64_t)q * kRedSplit * a.pstride : nullptr;
+  float *P = a.params + mi.param_off, *M = a.m + mi.param_off, *V = a.v + mi.param_off;
+  const float *G = a.grad + mi.param_off;
   const double t = (double)a.step_ctr[q];
   const double c1 = 1.0 - pow(0.9, t), c2 = 1.0 - pow(0.999, t);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < pc;
        i += (int64_t)gridDim.x * blockDim.x) {
-    // every load first, then the stores
-    float p = P[i], m = M[i], v = V[i], gi;
-    if (p2) {
-      float z[kRedSplit];
-#pragma unroll
-      for (int k = 0; k < kRedSplit; ++k) z[k] = p2[(int64_t)k * a.pstride + i];
-      double acc = 0.0;
-#pragma unroll
-      for (int k = 0; k < kRedSplit; ++k) acc += (double)z[k];
-      gi = (float)acc;
-      G[i] = gi;
-    } else {
-      gi = G[i];
-    }
-    adam_one(gi, p, m, v, c1, c2, a.lr);
+    float p = P[i], m = M[i], v = V[i];
+    adam_one(G[i], p, m, v, c1, c2, a.lr);
     M[i] = m;
     V[i] = v;
     P[i] = p;
@@ -1679,25 +1662,53 @@ __global__ __launch_bounds__(64 * kMg3W, 8 / kMg3W) void mgrad3_kernel(MGradArgs
   }
 }
 
-// Sum of the instance's workgroup rows in a fixed order, in two passes:
-// slice z of the rows (rows r0 + z, r0 + z + kRedSplit, ...) into part2[q][z]
-// here, then the kRedSplit slices in the optimiser.  Four parameters per
-// thread.
+// The REINFORCE gradient (the fixed-order sum of the instance's workgroup
+// rows) and the Adam step in one launch.  A block takes 64 parameters of one
+// instance (grid.y); its four row quarters sum rows k, k + 4, ... in order in
+// FP64, sixteen loads in flight at a time; the quarters are added in order,
+// then the parameter's thread stores the gradient, applies Adam and updates
+// the packed tables (as adam_step_kernel).
 __device__ inline int64_t made_pc(const MadeInst &m) {
   return (int64_t)m.H * m.n + m.H + (int64_t)m.n * m.H + m.n + (int64_t)m.n * m.n;
 }
-__global__ void mgrad_reduce1(const MadeInst *mi, const int32_t *first_row, const int32_t *n_rows,
-                              const float *part, int64_t pstride, float *part2) {
-  typedef float f4 __attribute__((ext_vector_type(4)));
-  const int q = blockIdx.y, z = blockIdx.z;
-  const int64_t pc = made_pc(mi[q]);
-  const int r0 = first_row[q], nr = n_rows[q];
-  const int64_t p = 4 * (blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
-  if (p >= pc) return;
-  f4 acc = f4{0.f, 0.f, 0.f, 0.f};
-  for (int r = z; r < nr; r += kRedSplit)
-    acc += *reinterpret_cast<const f4 *>(part + (int64_t)(r0 + r) * pstride + p);
-  *reinterpret_cast<f4 *>(part2 + ((int64_t)q * kRedSplit + z) * pstride + p) = acc;
+constexpr int kGaRows = 16;   // row loads in flight per thread
+__global__ __launch_bounds__(256) void grad_adam_kernel(MGradArgs g, OptArgs o) {
+  __shared__ double sh[4][64];
+  const int q = blockIdx.y;
+  const MadeInst mi = o.mi[q];
+  // an instance without samples this step keeps its parameters and moments
+  if (mi.B <= 0) return;
+  const int64_t pc = made_pc(mi);
+  const int pl = threadIdx.x & 63, qr = threadIdx.x >> 6;
+  const int64_t i = blockIdx.x * (int64_t)64 + pl;
+  const int r0 = g.first_row[q], nr = g.n_rows[q];
+  const float *col = g.part + (i < pc ? i : 0);
+  double acc = 0.0;
+  for (int rb = qr; rb < nr; rb += 4 * kGaRows) {
+    float v[kGaRows];
+#pragma unroll
+    for (int j = 0; j < kGaRows; ++j) {
+      const int r = rb + 4 * j;
+      v[j] = col[(int64_t)(r0 + (r < nr ? r : 0)) * g.pstride];
+    }
+#pragma unroll
+    for (int j = 0; j < kGaRows; ++j)
+      if (rb + 4 * j < nr) acc += (double)v[j];
+  }
+  sh[qr][pl] = acc;
+  __syncthreads();
+  if (qr != 0 || i >= pc) return;
+  const double t = (double)o.step_ctr[q];
+  const double c1 = 1.0 - pow(0.9, t), c2 = 1.0 - pow(0.999, t);
+  float *P = o.params + mi.param_off, *M = o.m + mi.param_off, *V = o.v + mi.param_off;
+  float p = P[i], m = M[i], v = V[i];
+  const float gi = (float)(((sh[0][pl] + sh[1][pl]) + sh[2][pl]) + sh[3][pl]);
+  o.grad[mi.param_off + i] = gi;
+  adam_one(gi, p, m, v, c1, c2, o.lr);
+  M[i] = m;
+  V[i] = v;
+  P[i] = p;
+  if (o.pack) pack_scatter(o.pack + mi.pack_off, mi.n, mi.H, o.npt, i, p);
 }
 
 template <int NPT>
@@ -1736,7 +1747,6 @@ size_t mgrad_lds_bytes(int H, int npt, bool split) {
   while (16 * ht < H) ht <<= 1;
   return split ? mg3_layout(npt, ht, kMg3W).end : mg_bytes(16 * ht, npt);
 }
-int mgrad_split() { return kRedSplit; }
 
 hipError_t launch_mgrad(const MGradArgs &a, int npt, hipStream_t st) {
   if (a.n_tasks <= 0) return hipSuccess;
@@ -1764,11 +1774,10 @@ hipError_t launch_mgrad(const MGradArgs &a, int npt, hipStream_t st) {
 
 int mgrad_task_samples(bool split) { return split ? 16 * kMg3W : 64; }
 
-hipError_t launch_mgrad_reduce(const MGradArgs &a, hipStream_t st) {
-  if (a.n_tasks <= 0) return hipSuccess;
-  const unsigned bx1 = (unsigned)((a.pstride / 4 + 255) / 256);
-  hipLaunchKernelGGL(mgrad_reduce1, dim3(bx1, a.n_inst, kRedSplit), dim3(256), 0, st, a.mi,
-                     a.first_row, a.n_rows, a.part, a.pstride, a.part2);
+hipError_t launch_grad_adam(const MGradArgs &g, const OptArgs &o, int64_t max_pc, hipStream_t st) {
+  if (g.n_inst <= 0) return hipSuccess;
+  hipLaunchKernelGGL(grad_adam_kernel, dim3((unsigned)((max_pc + 63) / 64), g.n_inst), dim3(256), 0,
+                     st, g, o);
   return hipGetLastError();
 }
 
@@ -1864,7 +1873,6 @@ hipError_t launch_free(const FreeArgs<real> &a, int n_inst, hipStream_t st) {
 
 hipError_t launch_adam_step(const OptArgs &a, int n_inst, int64_t max_pc, hipStream_t st) {
   if (n_inst <= 0) return hipSuccess;
-  if (a.part2 && a.nsplit != kRedSplit) return hipErrorInvalidValue;
   const int bx = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (max_pc + 255) / 256));
   hipLaunchKernelGGL(adam_step_kernel, dim3(bx, n_inst), dim3(256), 0, st, a);
   return hipGetLastError();
