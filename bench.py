@@ -36,6 +36,7 @@ METRIC = ("conditional logZ samples/s (fwd+adjoint) at |dlogZ|/N<=1e-5 vs plain 
 BETAS = (0.5, 1.0, 2.0)
 B = 8192
 HIDDEN = 256
+PROFILE_EVERY = 4      # timed steps per step whose dominant kernel is timed by events
 NW = 32
 # Algorithmic flops per sample (one multiply-add = 2).  Remainder
 # contraction in the pairwise form: per row transition, one 2x2 mix per
@@ -175,8 +176,9 @@ def main():
         del src, dst
     # eager launches; the library records HIP events around the launches of
     # the dominant kernel of the step (the 2-tile adjoint chain kernel, by the
-    # rocprofv3 statistics) and of no other kernel: each timed launch adds
-    # two event records to the stream
+    # rocprofv3 statistics) and of no other kernel, in every PROFILE_EVERY-th
+    # timed step: each timed launch adds two event records to the stream,
+    # which serialise the queue around it (about 10 us per step)
     # FP32 path with split-BF16 products in the chain kernels (three BF16
     # matrix-core products per FP32 product; the breakdown reports the logZ
     # error this leaves against the oracle), unless --fp32-products
@@ -205,7 +207,8 @@ def main():
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(st)
-    for _ in range(args.steps):
+    for i in range(args.steps):
+        net.profile_only(["chain_bwd_2"] if i % PROFILE_EVERY == 0 else [])
         step()
     e1.record(st)
     torch.cuda.synchronize()
@@ -263,7 +266,8 @@ def main():
         roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": measured_traffic(dom),
                     "kernel": KERNEL_NAMES[dom].format(split=str(split).lower(), mode=2 if split else 0),
-                    "kernel_avg_s": dom_avg, "flops_per_launch": KERNEL_FLOPS[dom] * nI * B,
+                    "kernel_avg_s": dom_avg, "kernel_launches_timed": ktime[dom][1],
+                    "flops_per_launch": KERNEL_FLOPS[dom] * nI * B,
                     "peak_units": "bf16 dense, 3 products per flop" if split else "fp32 matrix"}
     res = {
         "metric": METRIC,
