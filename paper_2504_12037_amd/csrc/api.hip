@@ -377,6 +377,14 @@ tnvan_status ensure_chain_tasks(tnvan_net *net) {
     if (net->rfwd || net->rbwd) {
       HIPCHK(net->Ubuf.ensure(std::max<int64_t>(1, ut) * sizeof(float)));
       HIPCHK(net->fabp.ensure(std::max<int64_t>(1, ft) * sizeof(double)));
+      // every factor +1 (float bits 0x3f800000): the unary kernel then only
+      // writes the positions with a W-neighbour or a field (this runs in an
+      // eager call when the batch shape changes, never inside a recording)
+      // (complete before any later launch, on whatever stream it comes)
+      if (ut > 0) {
+        HIPCHK(hipMemsetD32(reinterpret_cast<hipDeviceptr_t>(net->Ubuf.p), 0x3f800000, (size_t)ut));
+        HIPCHK(hipDeviceSynchronize());
+      }
     }
   }
   HIPCHK(net->cpart.ensure(std::max<int64_t>(1, ctot) * sizeof(double)));

@@ -711,6 +711,9 @@ __global__ __launch_bounds__(256) void unary_kernel(ChainArgs a, const int32_t *
   double fab = 0.0;
   for (int p = p0; p < p1; ++p) {
     const int i = p - p0;
+    // a position with no W-neighbour and no field has the factor +1, which
+    // the table holds from its set-up: nothing to store
+    if (s_n[i] == 0 && s_h[i] == 0.f) continue;
     float f = s_h[i];
     if (s_n[i] <= 4) {
       float t[4];
