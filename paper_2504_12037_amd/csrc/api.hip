@@ -115,7 +115,7 @@ struct tnvan_net {
   // workspaces
   DBuf garena, partial, w_logz, w_logq, w_spins, w_f, w_fpart, w_hid, w_da, w_dlogit, w_sf,
       w_part, d_hw_off, d_sum_off;
-  int max_partial = 0;
+  int max_partial = 0, max_out = 1;
   int sample_reps = 1;
   // transfer-matrix form (chain kernels, FP32 / BF16 precisions)
   std::vector<int32_t> use_chain;
@@ -125,7 +125,7 @@ struct tnvan_net {
   // register-resident chain kernels (per-wave tasks)
   DBuf Tr, Tq, Trb, xcol, cf_w, cf_r, cf_J, Tsx, Ts3, Tdq;
   bool split = false;   // TNVAN_FLAG_SPLIT_BF16 on an FP32 net
-  DBuf Ubuf, fabp, u_off, f_off, vjp_part, tickets, inv_v, inv_e, pcoef;
+  DBuf Ubuf, fabp, u_off, f_off, vjp_part, tickets, col_out, pcoef_out;
   // training step replayed from a captured graph (TNVAN_FLAG_GRAPH)
   bool use_graph = false, capturing = false;
   hipStream_t cap_stream = nullptr;
@@ -608,13 +608,10 @@ tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *gra
   v.dJ = dJ;
   v.dbeta = dbeta;
   v.inst_sum_off = net->d_sum_off.as<int64_t>();
-  HIPCHK(net->vjp_part.ensure((size_t)std::max(1, net->n_inst * vjp_split() * net->max_partial) *
-                              sizeof(double)));
   v.part2 = net->vjp_part.as<double>();
-  v.maxp = net->max_partial;
-  v.inv_v = net->inv_v.as<int32_t>();
-  v.inv_e = net->inv_e.as<int32_t>();
-  v.pcoef = net->pcoef.as<double>();
+  v.maxo = net->max_out;
+  v.col_out = net->col_out.as<int32_t>();
+  v.pcoef_out = net->pcoef_out.as<double>();
   HIPCHK(launch_vjp_reduce<real>(v, net->partial.as<real>(), net->n_inst, net->max_partial, st));
   return TNVAN_OK;
 }
@@ -1011,7 +1008,14 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   }
   UP2(Tl, P.Tl) UP2(Tbl, P.Tbl) UP2(cedges, P.cedges)
   UP2(Tr, P.Tr) UP2(Tq, P.Tq) UP2(Trb, P.Trb) UP2(xcol, P.xcol)
-  UP2(inv_v, P.inv_v) UP2(inv_e, P.inv_e) UP2(pcoef, P.pcoef)
+  UP2(col_out, P.col_out) UP2(pcoef_out, P.pcoef_out)
+  // the adjoint's split column sums, in output order: the outputs without a
+  // column are never written and keep these zeros
+  for (auto &D : P.insts) net->max_out = std::max(net->max_out, (int)(D.n + D.n_edges));
+  {
+    const size_t vb = sizeof(double) * std::max(1, n_inst * vjp_split() * net->max_out);
+    if ((e = net->vjp_part.ensure(vb)) || (e = hipMemset(net->vjp_part.p, 0, vb))) return fail(e, "adjoint sums");
+  }
   UP2(cf_w, P.cf_w) UP2(cf_r, P.cf_r) UP2(cf_J, P.cf_J) UP2(Tsx, P.Tsx) UP2(Ts3, P.Ts3) UP2(Tdq, P.Tdq)
   // transfer-matrix form: instances whose program is a set of dense chains
   // (FP32 / BF16 only); the launch-wide maxima size the LDS layout
@@ -1107,7 +1111,7 @@ void tnvan_free_network(tnvan_net *net) {
                  &net->btask_inst, &net->btask_chain, &net->btask_start, &net->Tl, &net->Tbl,
                  &net->cedges, &net->ckpt, &net->Tr, &net->Tq, &net->Trb, &net->xcol,
                  &net->cf_w, &net->cf_r, &net->cf_J, &net->Tsx, &net->Ts3, &net->Tdq, &net->Ubuf, &net->vjp_part,
-                 &net->tickets, &net->inv_v, &net->inv_e, &net->pcoef, &net->fabp, &net->u_off,
+                 &net->tickets, &net->col_out, &net->pcoef_out, &net->fabp, &net->u_off,
                  &net->f_off,
                  &net->mpack, &net->mtask_inst, &net->mtask_start, &net->mg_task_inst,
                  &net->mg_task_start, &net->mg_first, &net->mg_count,

@@ -606,15 +606,26 @@ tnvan_status compile_instance(const tnvan_instance &in, int max_width,
   }
   build_chains(D, consumer, P);
   {
-    const size_t v0 = P.inv_v.size(), e0 = P.inv_e.size();
-    P.inv_v.resize(v0 + n, -1);
-    P.inv_e.resize(e0 + in.n_edges, -1);
-    for (int k = 0; k < nr; ++k) P.inv_v[v0 + P.vr[D.vr_off + k]] = k;
-    for (int j = 0; j < D.n_wr; ++j) P.inv_e[e0 + P.wr_edge[D.wr_off + j]] = nr + j;
-    for (int j = 0; j < D.n_rr; ++j) P.inv_e[e0 + P.rr_edge[D.rr_off + j]] = nr + D.n_wr + j;
-    for (int k = 0; k < nr; ++k) P.pcoef.push_back(P.hR[D.hr_off + k]);
-    for (int j = 0; j < D.n_wr; ++j) P.pcoef.push_back(P.wr_J[D.wr_off + j]);
-    for (int j = 0; j < D.n_rr; ++j) P.pcoef.push_back(P.rr_J[D.rr_off + j]);
+    // the adjoint's outputs, vertices then edges: the output of every
+    // partial column, and per output the dbeta coefficient of its column
+    // (0 for W vertices and W-W edges, which have none)
+    const size_t o0 = P.pcoef_out.size();
+    P.pcoef_out.resize(o0 + n + in.n_edges, 0.0);
+    for (int k = 0; k < nr; ++k) {
+      const int o = P.vr[D.vr_off + k];
+      P.col_out.push_back(o);
+      P.pcoef_out[o0 + o] = P.hR[D.hr_off + k];
+    }
+    for (int j = 0; j < D.n_wr; ++j) {
+      const int o = n + P.wr_edge[D.wr_off + j];
+      P.col_out.push_back(o);
+      P.pcoef_out[o0 + o] = P.wr_J[D.wr_off + j];
+    }
+    for (int j = 0; j < D.n_rr; ++j) {
+      const int o = n + P.rr_edge[D.rr_off + j];
+      P.col_out.push_back(o);
+      P.pcoef_out[o0 + o] = P.rr_J[D.rr_off + j];
+    }
   }
   P.insts.push_back(D);
   P.hidden.push_back(in.hidden);

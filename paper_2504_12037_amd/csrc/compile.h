@@ -49,8 +49,8 @@ struct HostProgram {
   std::vector<int32_t> Tdq;         // per chain step: adjoint destinations [lane][4]
   // adjoint output maps: vertex -> R position (-1 on W), edge -> partial
   // column (-1 on W-W edges), and the dbeta coefficient of every column
-  std::vector<int32_t> inv_v, inv_e;
-  std::vector<double> pcoef;
+  std::vector<int32_t> col_out;      // per partial column: its adjoint output (vertex, or n + edge)
+  std::vector<double> pcoef_out;     // per adjoint output: dbeta coefficient of its column, or 0
   std::vector<int32_t> cf_w, cf_r;  // 4 W-neighbour slots per R position (index, W-R edge)
   std::vector<float> cf_J;          // their couplings
 };

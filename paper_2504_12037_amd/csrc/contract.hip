@@ -467,14 +467,15 @@ __global__ __launch_bounds__(256) void vjp_colsum_kernel(VjpArgs a, const real *
   }
   sh[rl][c] = acc;
   __syncthreads();
-  if (rl == 0 && blockIdx.x * 64 + c < a.maxp)
-    a.part2[((int64_t)q * kColSplit + sp) * a.maxp + k] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
+  if (rl == 0 && k < D.n_partial)
+    a.part2[((int64_t)q * kColSplit + sp) * a.maxo + a.col_out[a.inst_sum_off[q] + k]] =
+        (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
 }
 
 // Every output of the adjoint in one launch, one block per instance: dh
 // over the instance's vertices and dJ over its edges, each the fixed-order
-// sum of the split column sums of its partial column times beta (0 on W
-// vertices and W-W edges), and dbeta = sum over columns of coefficient x
+// sum of its split column sums (stored in output order; 0 for W vertices
+// and W-W edges) times beta, and dbeta = sum over outputs of coefficient x
 // column sum (per-thread sums in index order, then a fixed tree).
 constexpr int kFinishThreads = 1024;
 __global__ __launch_bounds__(kFinishThreads) void vjp_finish_kernel(VjpArgs a) {
@@ -482,19 +483,18 @@ __global__ __launch_bounds__(kFinishThreads) void vjp_finish_kernel(VjpArgs a) {
   const int q = blockIdx.x;
   const InstDesc D = a.inst[q];
   const int64_t vb = a.inst_spin_base[q], eb = a.inst_edge_base[q];
-  const double *p2 = a.part2 + (int64_t)q * kColSplit * a.maxp;
+  const double *p2 = a.part2 + (int64_t)q * kColSplit * a.maxo;
+  const double *pc = a.pcoef_out + vb + eb;
   double contrib = 0.0;
   for (int idx = threadIdx.x; idx < D.n + D.n_edges; idx += kFinishThreads) {
-    const int k = idx < D.n ? a.inv_v[vb + idx] : a.inv_e[eb + idx - D.n];
+    double c[kColSplit];
+#pragma unroll
+    for (int sp = 0; sp < kColSplit; ++sp) c[sp] = p2[(int64_t)sp * a.maxo + idx];
+    const double w = pc[idx];
     double S = 0.0;
-    if (k >= 0) {
-      double c[kColSplit];
 #pragma unroll
-      for (int sp = 0; sp < kColSplit; ++sp) c[sp] = p2[(int64_t)sp * a.maxp + k];
-#pragma unroll
-      for (int sp = 0; sp < kColSplit; ++sp) S += c[sp];
-      contrib += a.pcoef[a.inst_sum_off[q] + k] * S;
-    }
+    for (int sp = 0; sp < kColSplit; ++sp) S += c[sp];
+    contrib += w * S;
     if (idx < D.n) a.dh[vb + idx] = D.beta * S;
     else a.dJ[eb + idx - D.n] = D.beta * S;
   }

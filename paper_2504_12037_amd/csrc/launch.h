@@ -67,12 +67,14 @@ struct VjpArgs {
   const int64_t *inst_partial_off;
   const int64_t *inst_spin_base;   // offset of instance i in dh (sum of n)
   const int64_t *inst_edge_base;   // offset of instance i in dJ
-  const int64_t *inst_sum_off;     // offset of instance i in pcoef
+  const int64_t *inst_sum_off;     // offset of instance i in col_out
   double *dh, *dJ, *dbeta;
-  double *part2;                   // [n_inst][vjp_split()][maxp] split sums
-  int32_t maxp;                    // largest n_partial
-  const int32_t *inv_v, *inv_e;    // vertex / edge -> partial column (-1: none)
-  const double *pcoef;             // dbeta coefficient of every partial column
+  // split column sums in output order [n_inst][vjp_split()][maxo]; an
+  // output without a column keeps the zero the buffer starts with
+  double *part2;
+  int32_t maxo;                    // largest n_spins + n_edges
+  const int32_t *col_out;          // partial column -> output (vertex, or n + edge)
+  const double *pcoef_out;         // per output: dbeta coefficient of its column, or 0
 };
 int vjp_split();
 template <typename real>
