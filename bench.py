@@ -253,6 +253,20 @@ def main():
         err = max(err, float(np.abs(lz[k * B + idx] - want).max() / inst.n))
     err64 = float(np.abs(lz - lz64).max() / insts[0].n)
 
+    # exact slicing (every width-set configuration contracted as one sample,
+    # Eqs. 3-4): a 12x12 Gaussian lattice with W = columns 5 and 9 (|W| = 24,
+    # 16.8M configurations), timed on this path; logZ also by the FP64 path
+    inst_x = S.lattice_column_split(S.lattice_2d(12, seed=6), [5, 9])
+    netx = Net([inst_x], precision=args.precision, flags=Net.FLAG_SPLIT_BF16 if split else 0)
+    outx = torch.empty(2, dtype=torch.float64, device="cuda")
+    netx.exact_free_energy(0, out=outx)
+    torch.cuda.synchronize()
+    t_x = event_time(lambda: netx.exact_free_energy(0, out=outx), 2, st)
+    lzx, Fx = (float(v) for v in outx.cpu().numpy())
+    netx64 = Net([inst_x], precision="fp64")
+    lzx64 = float(netx64.exact_free_energy(0).cpu().numpy()[0])
+    del netx, netx64
+
     # the dominant kernel's live timing (none on paths without it, e.g. FP64)
     roofline = None
     if "chain_bwd_2" in ktime:
@@ -296,6 +310,11 @@ def main():
             "max_abs_dlogZ_per_N_vs_oracle": err,
             "max_abs_dlogZ_per_N_vs_fp64_path": err64,
             "wall_s_timed_region": wall,
+            "exact_slicing": {"workload": "12x12 OBC Gaussian lattice (seed 6), W = columns 5,9, beta 1",
+                              "configurations": 1 << inst_x.n_width, "s": t_x,
+                              "configurations_per_s": (1 << inst_x.n_width) / t_x,
+                              "logZ": lzx, "F": Fx,
+                              "abs_dlogZ_per_N_vs_fp64_path": abs(lzx - lzx64) / inst_x.n},
             "kernel_avg_us": {KERNEL_NAMES.get(k, k).format(split=str(split).lower(), mode=2 if split else 0): 1e6 * t / n
                               for k, (t, n) in ktime.items()},
         },

@@ -225,6 +225,20 @@ tnvan_status tnvan_free_energy_step_adjoint(tnvan_net *net, const int64_t *n_sam
                                             const double *grad_logz, double *dh,
                                             double *dJ, double *dbeta, void *stream);
 
+/* Exact free energy of one instance by slicing (Sec. 2, Eqs. 3-4): every
+ * configuration s of its width set W is contracted as one sample, and
+ *   logZ = ln sum_s exp(-beta E_1(s) + logZ_R(s)),   F = -logZ / beta,
+ * with the sum taken as a log-sum-exp in FP64 in a fixed order (bit-for-bit
+ * repeatable).  Spin i of configuration x (0 <= x < 2^|W|, W in width_set
+ * order) is -1 where bit i of x is set.  The configurations run in passes of
+ * at most 65,536 through the net's logZ path (its precision and kernels);
+ * the call sets the net's batch to one pass of this instance, so other
+ * entry points re-lay their tables at their next call.
+ *   inst  instance index
+ *   out   dev double out [2]: logZ, F
+ * Errors: |W| > 28 (TNVAN_E_WIDTH); beta <= 0 (TNVAN_E_INVALID). */
+tnvan_status tnvan_exact_free_energy(tnvan_net *net, int32_t inst, double *out, void *stream);
+
 /* Per-instance program statistics of the compiled order (host values):
  *   info[0] steps, [1] largest message scope, [2] arena entries per sample,
  *   [3] flops per sample of the forward contraction (2 per multiply-add,

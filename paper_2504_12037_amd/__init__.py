@@ -145,6 +145,15 @@ class Net:
                                                _stream()))
         return out[:sum(counts)]
 
+    def exact_free_energy(self, inst: int = 0, out: torch.Tensor = None):
+        """(logZ, F) of one instance by slicing over all 2^|W| width-set
+        configurations (device float64 tensor [2]; the net's batch is left
+        at one pass of that instance)."""
+        if out is None:
+            out = torch.empty(2, device="cuda", dtype=torch.float64)
+        _lib.check(_lib.lib().tnvan_exact_free_energy(self._h, int(inst), _ptr(out), _stream()))
+        return out
+
     def backward(self, spins: torch.Tensor, grad: torch.Tensor, n_samples, out=None):
         arr, counts = self._counts(n_samples)
         spins = spins.contiguous()

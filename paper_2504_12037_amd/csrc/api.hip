@@ -113,6 +113,7 @@ struct tnvan_net {
   int n_sblocks = 0;
   std::vector<int64_t> skey;
   // workspaces
+  DBuf w_xspins, w_xlogz, w_xpart;   // exact slicing
   DBuf garena, partial, w_logz, w_logq, w_spins, w_f, w_fpart, w_hid, w_da, w_dlogit, w_sf,
       w_part, d_hw_off, d_sum_off;
   int max_partial = 0, max_out = 1;
@@ -1111,7 +1112,7 @@ void tnvan_free_network(tnvan_net *net) {
                  &net->btask_inst, &net->btask_chain, &net->btask_start, &net->Tl, &net->Tbl,
                  &net->cedges, &net->ckpt, &net->Tr, &net->Tq, &net->Trb, &net->xcol,
                  &net->cf_w, &net->cf_r, &net->cf_J, &net->Tsx, &net->Ts3, &net->Tdq, &net->Ubuf, &net->vjp_part,
-                 &net->tickets, &net->col_out, &net->pcoef_out, &net->fabp, &net->u_off,
+                 &net->tickets, &net->col_out, &net->pcoef_out, &net->w_xspins, &net->w_xlogz, &net->w_xpart, &net->fabp, &net->u_off,
                  &net->f_off,
                  &net->mpack, &net->mtask_inst, &net->mtask_start, &net->mg_task_inst,
                  &net->mg_task_start, &net->mg_first, &net->mg_count,
@@ -1191,6 +1192,53 @@ tnvan_status tnvan_logz_batch(tnvan_net *net, const int64_t *n_samples, const in
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (net->precision == TNVAN_FP64) return run_logz<double>(net, spins, logz, st);
   return run_logz<float>(net, spins, logz, st);
+}
+
+namespace {
+constexpr int kExactMaxW = 28;                  // |W| of exact slicing
+constexpr int64_t kExactChunk = (int64_t)1 << 16;   // configurations per pass
+}  // namespace
+
+tnvan_status tnvan_exact_free_energy(tnvan_net *net, int32_t inst, double *out, void *stream) {
+  if (tnvan_status s = check_net(net)) return s;
+  if (inst < 0 || inst >= net->n_inst || !out) return set_err(TNVAN_E_INVALID, "bad instance or output");
+  const InstDesc &D = net->P.insts[inst];
+  if (D.nw > kExactMaxW)
+    return set_err(TNVAN_E_WIDTH, "exact slicing takes |W| <= %d (here %d)", kExactMaxW, (int)D.nw);
+  if (!(D.beta > 0)) return set_err(TNVAN_E_INVALID, "exact free energy needs beta > 0");
+  const int64_t total = (int64_t)1 << D.nw, chunk = std::min(total, kExactChunk);
+  const int64_t passes = total / chunk;
+  std::vector<int64_t> key(net->n_inst, 0);
+  key[inst] = chunk;
+  if (tnvan_status s = set_batch(net, key.data())) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIPCHK(net->w_xspins.ensure((size_t)std::max<int64_t>(1, chunk * D.nw)));
+  HIPCHK(net->w_xlogz.ensure((size_t)chunk * sizeof(double)));
+  HIPCHK(net->w_xpart.ensure((size_t)passes * kSliceBlocks * 2 * sizeof(double)));
+  int8_t *sp = net->w_xspins.as<int8_t>();
+  SliceArgs a{};
+  a.inst = net->inst.as<InstDesc>();
+  a.q = inst;
+  a.ww_a = net->ww_a.as<int32_t>();
+  a.ww_b = net->ww_b.as<int32_t>();
+  a.ww_J = net->ww_J.as<double>();
+  a.hW = net->hW.as<double>();
+  a.hw_off = net->d_hw_off.as<int32_t>();
+  a.logz = net->w_xlogz.as<double>();
+  a.n = chunk;
+  a.part = net->w_xpart.as<double>();
+  for (int64_t p = 0; p < passes; ++p) {
+    a.c0 = p * chunk;
+    a.pass = p;
+    HIPCHK(launch_slice_spins(sp, D.nw, a.c0, chunk, st));
+    const tnvan_status s = net->precision == TNVAN_FP64
+                               ? run_logz<double>(net, sp, net->w_xlogz.as<double>(), st)
+                               : run_logz<float>(net, sp, net->w_xlogz.as<double>(), st);
+    if (s) return s;
+    HIPCHK(launch_slice_lse(a, st));
+  }
+  HIPCHK(launch_slice_final(a.part, passes * kSliceBlocks, D.beta, out, st));
+  return TNVAN_OK;
 }
 
 tnvan_status tnvan_logz_backward(tnvan_net *net, const int64_t *n_samples, const int8_t *spins,

@@ -218,6 +218,27 @@ struct FreeArgs {
 template <typename real>
 hipError_t launch_free(const FreeArgs<real> &a, int n_inst, hipStream_t st);
 
+// Exact slicing over every configuration of one instance's width set
+// (slice_*_kernel): the configurations of one pass as spins, the per-block
+// log-sum-exp pairs of -beta E_1 + logZ_R, and their fixed-order merge.
+constexpr int kSliceBlocks = 64;   // blocks (and pairs) per pass
+struct SliceArgs {
+  const InstDesc *inst;
+  int32_t q;                 // the instance
+  const int32_t *ww_a, *ww_b;
+  const double *ww_J;
+  const double *hW;
+  const int32_t *hw_off;
+  const double *logz;        // logZ_R of the pass's configurations
+  int64_t c0, n;             // first configuration of the pass, configurations
+  int64_t pass;
+  double *part;              // [passes][kSliceBlocks][2] (max, scaled sum)
+};
+hipError_t launch_slice_spins(int8_t *spins, int nw, int64_t c0, int64_t n, hipStream_t st);
+hipError_t launch_slice_lse(const SliceArgs &a, hipStream_t st);
+hipError_t launch_slice_final(const double *part, int64_t count, double beta, double *out,
+                              hipStream_t st);
+
 // One optimiser step of every instance (see adam_step_kernel).
 struct OptArgs {
   const MadeInst *mi;

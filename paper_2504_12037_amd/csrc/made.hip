@@ -585,6 +585,91 @@ __global__ __launch_bounds__(256) void adam_step_kernel(OptArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Exact slicing (Sec. 2, Eqs. 3-4): every configuration of the width set W is
+// one sample.  slice_spins_kernel writes configurations c0 .. c0 + n - 1
+// (spin i of configuration x is -1 where bit i of x is set, else +1);
+// slice_lse_kernel forms t = -beta E_1(s) + logZ_R(s) per configuration and
+// a per-block log-sum-exp pair (max m, sum of exp(t - m)), in FP64 and in a
+// fixed order; slice_final_kernel merges the pairs in order into
+// logZ = m + ln(sum) and F = -logZ / beta.
+__global__ void slice_spins_kernel(int8_t *spins, int nw, int64_t c0, int64_t nbytes) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nbytes;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / nw;
+    const int i = (int)(e - b * nw);
+    spins[e] = (((c0 + b) >> i) & 1) ? (int8_t)-1 : (int8_t)1;
+  }
+}
+
+__device__ inline void lse_merge(double &m, double &s, double m2, double s2) {
+  if (s2 == 0.0) return;
+  if (s == 0.0) { m = m2; s = s2; return; }
+  const double M = m > m2 ? m : m2;
+  s = s * exp(m - M) + s2 * exp(m2 - M);
+  m = M;
+}
+
+__global__ __launch_bounds__(256) void slice_lse_kernel(SliceArgs a) {
+  __shared__ double sm[256], ss[256];
+  const int tid = threadIdx.x;
+  const InstDesc D = a.inst[a.q];
+  const int32_t *wa = a.ww_a + D.ww_off, *wb = a.ww_b + D.ww_off;
+  const double *wJ = a.ww_J + D.ww_off, *hW = a.hW + a.hw_off[a.q];
+  double m = 0.0, s = 0.0;
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + tid; b < a.n; b += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t x = a.c0 + b;
+    double e1 = 0.0;
+    for (int k = 0; k < D.n_ww; ++k) {
+      const bool neg = (((x >> wa[k]) ^ (x >> wb[k])) & 1) != 0;   // s_a s_b = -1
+      e1 -= neg ? -wJ[k] : wJ[k];
+    }
+    for (int k = 0; k < D.nw; ++k) e1 -= ((x >> k) & 1) ? -hW[k] : hW[k];
+    lse_merge(m, s, -D.beta * e1 + a.logz[b], 1.0);
+  }
+  sm[tid] = m;
+  ss[tid] = s;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) {
+      double m1 = sm[tid], s1 = ss[tid];
+      lse_merge(m1, s1, sm[tid + st], ss[tid + st]);
+      sm[tid] = m1;
+      ss[tid] = s1;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    a.part[2 * (a.pass * (int64_t)gridDim.x + blockIdx.x)] = sm[0];
+    a.part[2 * (a.pass * (int64_t)gridDim.x + blockIdx.x) + 1] = ss[0];
+  }
+}
+
+__global__ __launch_bounds__(256) void slice_final_kernel(const double *part, int64_t count,
+                                                          double beta, double *out) {
+  __shared__ double sm[256], ss[256];
+  const int tid = threadIdx.x;
+  double m = 0.0, s = 0.0;
+  for (int64_t k = tid; k < count; k += 256) lse_merge(m, s, part[2 * k], part[2 * k + 1]);
+  sm[tid] = m;
+  ss[tid] = s;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (tid < st) {
+      double m1 = sm[tid], s1 = ss[tid];
+      lse_merge(m1, s1, sm[tid + st], ss[tid + st]);
+      sm[tid] = m1;
+      ss[tid] = s1;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const double lz = sm[0] + log(ss[0]);
+    out[0] = lz;
+    out[1] = -lz / beta;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Matrix-core sampler (FP32).  A wave draws 16 samples.  Logits z and spins
 // of the wave's samples live in the R-layout of the chain kernels (lane l
 // holds positions 16 t + 4 (l >> 4) + r of sample l & 15).  After position i
@@ -1875,6 +1960,25 @@ hipError_t launch_adam_step(const OptArgs &a, int n_inst, int64_t max_pc, hipStr
   if (n_inst <= 0) return hipSuccess;
   const int bx = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (max_pc + 255) / 256));
   hipLaunchKernelGGL(adam_step_kernel, dim3(bx, n_inst), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_slice_spins(int8_t *spins, int nw, int64_t c0, int64_t n, hipStream_t st) {
+  const int64_t nbytes = n * nw;
+  if (nbytes <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>(1024, (nbytes + 255) / 256);
+  hipLaunchKernelGGL(slice_spins_kernel, dim3(blocks), dim3(256), 0, st, spins, nw, c0, nbytes);
+  return hipGetLastError();
+}
+
+hipError_t launch_slice_lse(const SliceArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL(slice_lse_kernel, dim3(kSliceBlocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_slice_final(const double *part, int64_t count, double beta, double *out,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(slice_final_kernel, dim3(1), dim3(256), 0, st, part, count, beta, out);
   return hipGetLastError();
 }
 
