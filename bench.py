@@ -267,6 +267,15 @@ def main():
     lzx64 = float(netx64.exact_free_energy(0).cpu().numpy()[0])
     del netx, netx64
 
+    # moments of p from samples of q (self-normalised importance weights and
+    # the adjoint's conditional moments): the step's network and batch
+    sp_o, lq_o = net.sample(counts)
+    obs = lambda: net.observables(sp_o, lq_o, counts)
+    _, _, ess_o = obs()
+    torch.cuda.synchronize()
+    t_obs = event_time(obs, 5, st)
+    ess_o = [float(v) for v in ess_o.cpu().numpy()]
+
     # the dominant kernel's live timing (none on paths without it, e.g. FP64)
     roofline = None
     if "chain_bwd_2" in ktime:
@@ -315,6 +324,9 @@ def main():
                               "configurations_per_s": (1 << inst_x.n_width) / t_x,
                               "logZ": lzx, "F": Fx,
                               "abs_dlogZ_per_N_vs_fp64_path": abs(lzx - lzx64) / inst_x.n},
+            "observables": {"workload": "the step's network and batch (samples of q)",
+                            "s": t_obs, "samples_per_s": nI * B / t_obs,
+                            "effective_sample_size": ess_o},
             "kernel_avg_us": {KERNEL_NAMES.get(k, k).format(split=str(split).lower(), mode=2 if split else 0): 1e6 * t / n
                               for k, (t, n) in ktime.items()},
         },

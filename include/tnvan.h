@@ -239,6 +239,28 @@ tnvan_status tnvan_free_energy_step_adjoint(tnvan_net *net, const int64_t *n_sam
  * Errors: |W| > 28 (TNVAN_E_WIDTH); beta <= 0 (TNVAN_E_INVALID). */
 tnvan_status tnvan_exact_free_energy(tnvan_net *net, int32_t inst, double *out, void *stream);
 
+/* Moments of the Boltzmann distribution p (Eq. 1) from samples of q: the
+ * magnetisations <sigma_i>_p of every vertex and correlations
+ * <sigma_i sigma_j>_p of every edge, by self-normalised importance weights.
+ * The W-marginal of p is exp(-beta E_1) Z_R / Z, so the weight of sample b
+ * is w_b = exp(-beta f_b) / sum_c exp(-beta f_c) with f_b of Eq. 9
+ * (per instance).  Each moment is sum_b w_b times its expectation given s_W:
+ * s_i on W, s_i s_j on W-W edges, and on the remainder the conditional
+ * magnetisations and correlations, which the adjoint gives with grad_logz
+ * = w_b / beta (as tnvan_logz_backward: dh = beta sum g <r>, dJ = beta sum
+ * g <x x>).  All sums FP64, fixed order.  The step counter is not advanced.
+ *   n_samples, spins  as tnvan_logz_batch (e.g. from tnvan_sample)
+ *   logq  dev ln q(s_b) as tnvan_sample writes it: double for TNVAN_FP64,
+ *         else float
+ *   mag   dev double out [sum_i n_spins_i]; corr dev double out
+ *         [sum_i n_edges_i]; ess dev double out [n_inst], the effective
+ *         sample size (sum w)^2 / sum w^2
+ * Errors: beta <= 0 on any instance; a buffer that is plain host memory
+ * (not device, managed or device-mapped pinned memory) (TNVAN_E_INVALID). */
+tnvan_status tnvan_observables(tnvan_net *net, const int64_t *n_samples, const int8_t *spins,
+                               const void *logq, double *mag, double *corr, double *ess,
+                               void *stream);
+
 /* Per-instance program statistics of the compiled order (host values):
  *   info[0] steps, [1] largest message scope, [2] arena entries per sample,
  *   [3] flops per sample of the forward contraction (2 per multiply-add,

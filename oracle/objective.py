@@ -24,6 +24,10 @@ Functions and what pins them (tests/test_oracle_objective.py):
                       (update = lr * g / (|g| + eps)) and a hand-computed
                       second step
   train               Algorithm 1 (sample -> contract -> loss/grad -> update)
+  observables         <sigma_i>_p and <sigma_i sigma_j>_p estimated from
+                      samples of q by self-normalised importance weights;
+                      pinned by the full enumeration of W with uniform q,
+                      where the estimate is exact (brute-force moments)
 """
 
 from __future__ import annotations
@@ -109,3 +113,34 @@ def train(inst, theta0, H: int, steps: int, B: int, lr: float, seed: int,
         theta, m, v = adam_step(theta, g, m, v, t + 1, lr)
         stats.append(st)
     return theta, np.asarray(stats)
+
+
+def observables(inst, spins, logq, marg=None):
+    """Moments of the Boltzmann distribution p (Eq. 1) from samples of q.
+
+    The W-marginal of p is p(s_W) = exp(-beta E_1(s_W)) Z_R(s_W) / Z, so the
+    weight of a sample is p/q up to a constant: exp(-beta f_b) with f_b of
+    Eq. 9 (free_energy_terms).  Normalised, w_b = exp(-beta f_b) / sum.
+    Each moment is the weighted mean of its conditional expectation given
+    s_W: s_i on W vertices, s_i s_j on W-W edges, and the conditional
+    marginals and correlations of the remainder (marginals_elimination)
+    elsewhere.  Returns (mag [n], corr [E], ess) with the effective sample
+    size ess = 1 / sum w_b^2.
+    """
+    beta = float(inst.beta)
+    s = np.asarray(spins)
+    if marg is None:
+        lz, mag, corr, _ = ising.marginals_elimination(inst, s)
+    else:
+        lz, mag, corr = marg
+    f, _ = free_energy_terms(inst, s, logq, lz)
+    lw = -beta * f
+    w = np.exp(lw - lw.max())
+    w /= w.sum()
+    sp = ising.Split(inst)
+    sf = s.astype(np.float64)
+    m = w @ mag
+    for i, v in enumerate(sp.W):
+        m[v] = w @ sf[:, i]
+    c = w @ corr          # W-W edges: s_a s_b already
+    return m, c, float(1.0 / np.sum(w * w))

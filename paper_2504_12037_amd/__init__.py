@@ -145,6 +145,21 @@ class Net:
                                                _stream()))
         return out[:sum(counts)]
 
+    def observables(self, spins: torch.Tensor, logq: torch.Tensor, n_samples):
+        """(mag [sum n], corr [sum E], ess [n_inst]) device float64 tensors:
+        <sigma_i>_p and <sigma_i sigma_j>_p estimated from samples of q
+        (self-normalised importance weights) and the effective sample size."""
+        arr, counts = self._counts(n_samples)
+        spins = spins.to(device="cuda").contiguous()
+        logq = logq.to(device="cuda", dtype=self.logq_dtype).contiguous()
+        assert spins.dtype == torch.int8 and logq.numel() == sum(counts)
+        mag = torch.empty(sum(self.n), device="cuda", dtype=torch.float64)
+        corr = torch.empty(max(sum(self.ne), 1), device="cuda", dtype=torch.float64)
+        ess = torch.empty(len(counts), device="cuda", dtype=torch.float64)
+        _lib.check(_lib.lib().tnvan_observables(self._h, arr, _ptr(spins), _ptr(logq), _ptr(mag),
+                                                _ptr(corr), _ptr(ess), _stream()))
+        return mag, corr[:sum(self.ne)], ess
+
     def exact_free_energy(self, inst: int = 0, out: torch.Tensor = None):
         """(logZ, F) of one instance by slicing over all 2^|W| width-set
         configurations (device float64 tensor [2]; the net's batch is left

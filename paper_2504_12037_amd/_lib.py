@@ -27,7 +27,8 @@ EXPORTS = ["tnvan_build_network", "tnvan_free_network", "tnvan_last_error",
            "tnvan_param_count", "tnvan_set_params", "tnvan_get_params",
            "tnvan_get_state",
            "tnvan_sample", "tnvan_logz_batch", "tnvan_logz_backward",
-           "tnvan_logz_and_backward", "tnvan_exact_free_energy", "tnvan_free_energy_step",
+           "tnvan_logz_and_backward", "tnvan_exact_free_energy", "tnvan_observables",
+           "tnvan_free_energy_step",
            "tnvan_free_energy_step_adjoint", "tnvan_program_info", "tnvan_plan",
            "tnvan_kernel_time", "tnvan_profile_mask"]
 
@@ -80,6 +81,7 @@ def lib():
     L.tnvan_logz_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.tnvan_logz_and_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.tnvan_exact_free_energy.argtypes = [vp, i32, vp, vp]
+    L.tnvan_observables.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.tnvan_free_energy_step.argtypes = [vp, vp, C.c_float, vp, vp, vp]
     L.tnvan_free_energy_step_adjoint.argtypes = [vp, vp, C.c_float, vp, vp, vp, vp, vp, vp, vp]
     L.tnvan_program_info.argtypes = [vp, i32, vp]

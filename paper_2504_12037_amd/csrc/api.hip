@@ -114,6 +114,7 @@ struct tnvan_net {
   std::vector<int64_t> skey;
   // workspaces
   DBuf w_xspins, w_xlogz, w_xpart;   // exact slicing
+  DBuf ww_e, d_wv, w_og, w_ostats, w_odb;   // observables
   DBuf garena, partial, w_logz, w_logq, w_spins, w_f, w_fpart, w_hid, w_da, w_dlogit, w_sf,
       w_part, d_hw_off, d_sum_off;
   int max_partial = 0, max_out = 1;
@@ -861,6 +862,79 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
   return TNVAN_OK;
 }
 
+// moments of p from samples of q (tnvan_observables)
+template <typename real>
+tnvan_status run_observables(tnvan_net *net, const int8_t *spins, const void *logq, double *mag,
+                             double *corr, double *ess, hipStream_t st) {
+  const int64_t B = net->B_total;
+  HIPCHK(net->w_logz.ensure(std::max<int64_t>(1, B) * 8));
+  HIPCHK(net->w_f.ensure(std::max<int64_t>(1, B) * 8));
+  HIPCHK(net->w_og.ensure(std::max<int64_t>(1, B) * 8));
+  HIPCHK(net->w_ostats.ensure((size_t)net->n_inst * 4 * sizeof(double)));
+  HIPCHK(net->w_odb.ensure((size_t)net->n_inst * sizeof(double)));
+  if (tnvan_status s = run_logz<real>(net, spins, net->w_logz.as<double>(), st)) return s;
+  // f_b (Eq. 9); the step counter is not advanced
+  int64_t Bmax = 1;
+  for (int q = 0; q < net->n_inst; ++q) Bmax = std::max(Bmax, net->nkey[q]);
+  FreeArgs<real> f{};
+  f.inst = net->inst.as<InstDesc>();
+  f.mi = net->d_mi.as<MadeInst>();
+  f.hw_off = net->d_hw_off.as<int32_t>();
+  f.spins = spins;
+  f.logz = net->w_logz.as<double>();
+  f.logq = static_cast<const real *>(logq);
+  f.ww_a = net->ww_a.as<int32_t>();
+  f.ww_b = net->ww_b.as<int32_t>();
+  f.ww_J = net->ww_J.as<double>();
+  f.hW = net->hW.as<double>();
+  f.f = net->w_f.as<double>();
+  f.nblk = (int)std::min<int64_t>(256, (4 * Bmax + 255) / 256);
+  HIPCHK(net->w_fpart.ensure((size_t)net->n_inst * f.nblk * 4 * sizeof(double)));
+  f.part = net->w_fpart.as<double>();
+  f.finish = 1;
+  f.stats = net->w_ostats.as<double>();
+  f.done = net->tickets.as<int32_t>();
+  f.step_ctr = nullptr;
+  HIPCHK(launch_free<real>(f, net->n_inst, st));
+  ObsArgs o{};
+  o.inst = net->inst.as<InstDesc>();
+  o.mi = net->d_mi.as<MadeInst>();
+  o.f = net->w_f.as<double>();
+  o.g = net->w_og.as<double>();
+  o.ess = ess;
+  o.spins = spins;
+  o.ww_a = net->ww_a.as<int32_t>();
+  o.ww_b = net->ww_b.as<int32_t>();
+  o.ww_e = net->ww_e.as<int32_t>();
+  o.wv = net->d_wv.as<int32_t>();
+  o.hw_off = net->d_hw_off.as<int32_t>();
+  o.spin_base = net->d_spin_base.as<int64_t>();
+  o.edge_base = net->d_edge_base.as<int64_t>();
+  o.mag = mag;
+  o.corr = corr;
+  for (auto &D : net->P.insts) o.max_out = std::max(o.max_out, (int32_t)(D.nw + D.n_ww));
+  HIPCHK(launch_obs_weights(o, net->n_inst, st));
+  // the remainder's moments: the adjoint with g_b = w_b / beta (dh = sum
+  // w_b <r>, dJ = sum w_b <x x>; zero on W vertices and W-W edges) ...
+  if (tnvan_status s = run_backward<real>(net, spins, net->w_og.as<double>(), mag, corr,
+                                          net->w_odb.as<double>(), st))
+    return s;
+  // ... and the width set's, written over those zeros
+  HIPCHK(launch_obs_w(o, net->n_inst, st));
+  return TNVAN_OK;
+}
+// a pointer the GPU can access (device or managed memory, or pinned host
+// memory mapped for the device); plain host memory is rejected
+bool is_device_ptr(const void *p) {
+  hipPointerAttribute_t at{};
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();   // clear the sticky error of the query
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged ||
+         (at.type == hipMemoryTypeHost && at.devicePointer != nullptr);
+}
+
 tnvan_status check_net(const tnvan_net *net) {
   if (!net) return set_err(TNVAN_E_INVALID, "net is NULL");
   return TNVAN_OK;
@@ -964,7 +1038,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   UP(fld_ptr, P.fld_ptr) UP(fld_w, P.fld_w) UP(wr_pos, P.wr_pos) UP(wr_w, P.wr_w)
   UP(rr_edge, P.rr_edge) UP(rr_J, P.rr_J) UP(wr_edge, P.wr_edge) UP(wr_J, P.wr_J)
   UP(hR64, P.hR) UP(vr, P.vr) UP(ww_a, P.ww_a) UP(ww_b, P.ww_b) UP(ww_J, P.ww_J)
-  UP(hW, P.hW) UP(d_hw_off, P.hw_off)
+  UP(hW, P.hW) UP(d_hw_off, P.hw_off) UP(ww_e, P.ww_e) UP(d_wv, P.wv)
   if (net->precision == TNVAN_FP64) {
     UP(T, P.T) UP(fld_J, P.fld_J) UP(hR, P.hR)
   } else {
@@ -1112,7 +1186,8 @@ void tnvan_free_network(tnvan_net *net) {
                  &net->btask_inst, &net->btask_chain, &net->btask_start, &net->Tl, &net->Tbl,
                  &net->cedges, &net->ckpt, &net->Tr, &net->Tq, &net->Trb, &net->xcol,
                  &net->cf_w, &net->cf_r, &net->cf_J, &net->Tsx, &net->Ts3, &net->Tdq, &net->Ubuf, &net->vjp_part,
-                 &net->tickets, &net->col_out, &net->pcoef_out, &net->w_xspins, &net->w_xlogz, &net->w_xpart, &net->fabp, &net->u_off,
+                 &net->tickets, &net->col_out, &net->pcoef_out, &net->w_xspins, &net->w_xlogz, &net->w_xpart, &net->ww_e, &net->d_wv, &net->w_og,
+                 &net->w_ostats, &net->w_odb, &net->fabp, &net->u_off,
                  &net->f_off,
                  &net->mpack, &net->mtask_inst, &net->mtask_start, &net->mg_task_inst,
                  &net->mg_task_start, &net->mg_first, &net->mg_count,
@@ -1202,6 +1277,7 @@ constexpr int64_t kExactChunk = (int64_t)1 << 16;   // configurations per pass
 tnvan_status tnvan_exact_free_energy(tnvan_net *net, int32_t inst, double *out, void *stream) {
   if (tnvan_status s = check_net(net)) return s;
   if (inst < 0 || inst >= net->n_inst || !out) return set_err(TNVAN_E_INVALID, "bad instance or output");
+  if (!is_device_ptr(out)) return set_err(TNVAN_E_INVALID, "out is not device memory");
   const InstDesc &D = net->P.insts[inst];
   if (D.nw > kExactMaxW)
     return set_err(TNVAN_E_WIDTH, "exact slicing takes |W| <= %d (here %d)", kExactMaxW, (int)D.nw);
@@ -1239,6 +1315,24 @@ tnvan_status tnvan_exact_free_energy(tnvan_net *net, int32_t inst, double *out, 
   }
   HIPCHK(launch_slice_final(a.part, passes * kSliceBlocks, D.beta, out, st));
   return TNVAN_OK;
+}
+
+tnvan_status tnvan_observables(tnvan_net *net, const int64_t *n_samples, const int8_t *spins,
+                               const void *logq, double *mag, double *corr, double *ess,
+                               void *stream) {
+  if (tnvan_status s = check_net(net)) return s;
+  for (const void *p : {(const void *)spins, logq, (const void *)mag, (const void *)corr,
+                        (const void *)ess})
+    if (p && !is_device_ptr(p)) return set_err(TNVAN_E_INVALID, "a buffer is not device memory");
+  for (auto &D : net->P.insts)
+    if (!(D.beta > 0)) return set_err(TNVAN_E_INVALID, "observables need beta > 0");
+  if (tnvan_status s = set_batch(net, n_samples)) return s;
+  if (!mag || !corr || !ess) return set_err(TNVAN_E_INVALID, "mag, corr and ess are required");
+  if (net->B_total > 0 && (!logq || (!spins && net->spin_total > 0)))
+    return set_err(TNVAN_E_INVALID, "spins and logq are required");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (net->precision == TNVAN_FP64) return run_observables<double>(net, spins, logq, mag, corr, ess, st);
+  return run_observables<float>(net, spins, logq, mag, corr, ess, st);
 }
 
 tnvan_status tnvan_logz_backward(tnvan_net *net, const int64_t *n_samples, const int8_t *spins,

@@ -421,6 +421,7 @@ tnvan_status compile_instance(const tnvan_instance &in, int max_width,
     bool wa = widx[a] >= 0, wb = widx[b] >= 0;
     if (wa && wb) {
       P.ww_a.push_back(widx[a]); P.ww_b.push_back(widx[b]); P.ww_J.push_back(J);
+      P.ww_e.push_back(e);
     } else if (wa || wb) {
       int w = wa ? a : b, r = wa ? b : a;
       P.wr_pos.push_back(pos[r]); P.wr_w.push_back(widx[w]);

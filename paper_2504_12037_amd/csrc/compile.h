@@ -25,6 +25,7 @@ struct HostProgram {
   std::vector<int32_t> rr_edge;   // R-R edges (global edge id per instance)
   std::vector<double> rr_J;
   std::vector<int32_t> ww_a, ww_b;  // W-W edges as W indices
+  std::vector<int32_t> ww_e;        // W-W edges: edge index
   std::vector<double> ww_J;
   std::vector<double> hW;           // h on W indices (for E_1)
   std::vector<int32_t> vr, wv;      // R position -> vertex, W index -> vertex

@@ -239,6 +239,25 @@ hipError_t launch_slice_lse(const SliceArgs &a, hipStream_t st);
 hipError_t launch_slice_final(const double *part, int64_t count, double beta, double *out,
                               hipStream_t st);
 
+// Moments of the Boltzmann distribution from samples of q (obs_*_kernel):
+// self-normalised importance weights exp(-beta f_b) / sum per instance, and
+// the width-set moments (W magnetisations, W-W correlations) they weight.
+struct ObsArgs {
+  const InstDesc *inst;
+  const MadeInst *mi;        // sample_off, B, spin_off, n (= |W|)
+  const double *f;           // f_b per global sample (free_f_kernel)
+  double *g;                 // out: w_b / beta per global sample
+  double *ess;               // out [n_inst]: effective sample size 1 / sum w^2
+  const int8_t *spins;
+  const int32_t *ww_a, *ww_b, *ww_e;
+  const int32_t *wv, *hw_off;   // W index -> vertex, per instance offset
+  const int64_t *spin_base, *edge_base;   // per instance offsets of mag / corr
+  double *mag, *corr;
+  int32_t max_out;           // largest |W| + W-W edge count
+};
+hipError_t launch_obs_weights(const ObsArgs &a, int n_inst, hipStream_t st);
+hipError_t launch_obs_w(const ObsArgs &a, int n_inst, hipStream_t st);
+
 // One optimiser step of every instance (see adam_step_kernel).
 struct OptArgs {
   const MadeInst *mi;

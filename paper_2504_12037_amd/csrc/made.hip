@@ -670,6 +670,71 @@ __global__ __launch_bounds__(256) void slice_final_kernel(const double *part, in
 }
 
 // ---------------------------------------------------------------------------
+// Moments of p from samples of q.  The W-marginal of p is exp(-beta E_1)
+// Z_R / Z, so a sample's weight p / q is exp(-beta f_b) up to a constant
+// (f_b of Eq. 9); normalised over the instance's batch, w_b.  The adjoint
+// with g_b = w_b / beta then sums w_b times the conditional moments of the
+// remainder (dh = beta sum g_b <r>, dJ = beta sum g_b <x x>);
+// obs_w_kernel adds the width-set moments, sum_b w_b s_i and
+// sum_b w_b s_a s_b.  Every sum is FP64 in a fixed order.
+constexpr int kObsThreads = 1024;
+__device__ inline double block_reduce(double v, double *sh, bool is_max) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int st = kObsThreads / 2; st > 0; st >>= 1) {
+    if (t < st) sh[t] = is_max ? fmax(sh[t], sh[t + st]) : sh[t] + sh[t + st];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+__global__ __launch_bounds__(kObsThreads) void obs_weights_kernel(ObsArgs a) {
+  __shared__ double sh[kObsThreads];
+  const int q = blockIdx.x;
+  const MadeInst mi = a.mi[q];
+  const double beta = a.inst[q].beta;
+  const double *f = a.f + mi.sample_off;
+  double m = -INFINITY;
+  for (int64_t b = threadIdx.x; b < mi.B; b += kObsThreads) m = fmax(m, -beta * f[b]);
+  m = block_reduce(m, sh, true);
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t b = threadIdx.x; b < mi.B; b += kObsThreads) {
+    const double e = exp(-beta * f[b] - m);
+    s1 += e;
+    s2 += e * e;
+  }
+  s1 = block_reduce(s1, sh, false);
+  s2 = block_reduce(s2, sh, false);
+  for (int64_t b = threadIdx.x; b < mi.B; b += kObsThreads)
+    a.g[mi.sample_off + b] = exp(-beta * f[b] - m) / (s1 * beta);
+  if (threadIdx.x == 0) a.ess[q] = mi.B > 0 ? s1 * s1 / s2 : 0.0;
+}
+// block (output o, instance q): o < |W| the magnetisation of W vertex o,
+// else W-W edge o - |W|
+__global__ __launch_bounds__(kObsThreads) void obs_w_kernel(ObsArgs a) {
+  __shared__ double sh[kObsThreads];
+  const int q = blockIdx.y, o = blockIdx.x;
+  const InstDesc D = a.inst[q];
+  const MadeInst mi = a.mi[q];
+  if (o >= D.nw + D.n_ww) return;
+  const bool vert = o < D.nw;
+  const int i0 = vert ? o : a.ww_a[D.ww_off + o - D.nw], i1 = vert ? -1 : a.ww_b[D.ww_off + o - D.nw];
+  const double beta = D.beta;
+  const int8_t *s = a.spins + mi.spin_off;
+  double acc = 0.0;
+  for (int64_t b = threadIdx.x; b < mi.B; b += kObsThreads) {
+    const double x = (double)s[b * D.nw + i0] * (i1 >= 0 ? (double)s[b * D.nw + i1] : 1.0);
+    acc += beta * a.g[mi.sample_off + b] * x;
+  }
+  acc = block_reduce(acc, sh, false);
+  if (threadIdx.x != 0) return;
+  if (vert) a.mag[a.spin_base[q] + a.wv[a.hw_off[q] + o]] = acc;
+  else a.corr[a.edge_base[q] + a.ww_e[D.ww_off + o - D.nw]] = acc;
+}
+
+// ---------------------------------------------------------------------------
 // Matrix-core sampler (FP32).  A wave draws 16 samples.  Logits z and spins
 // of the wave's samples live in the R-layout of the chain kernels (lane l
 // holds positions 16 t + 4 (l >> 4) + r of sample l & 15).  After position i
@@ -1979,6 +2044,18 @@ hipError_t launch_slice_lse(const SliceArgs &a, hipStream_t st) {
 hipError_t launch_slice_final(const double *part, int64_t count, double beta, double *out,
                               hipStream_t st) {
   hipLaunchKernelGGL(slice_final_kernel, dim3(1), dim3(256), 0, st, part, count, beta, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_obs_weights(const ObsArgs &a, int n_inst, hipStream_t st) {
+  if (n_inst <= 0) return hipSuccess;
+  hipLaunchKernelGGL(obs_weights_kernel, dim3(n_inst), dim3(kObsThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_obs_w(const ObsArgs &a, int n_inst, hipStream_t st) {
+  if (n_inst <= 0 || a.max_out <= 0) return hipSuccess;
+  hipLaunchKernelGGL(obs_w_kernel, dim3(a.max_out, n_inst), dim3(kObsThreads), 0, st, a);
   return hipGetLastError();
 }
 

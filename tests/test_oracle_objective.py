@@ -107,3 +107,26 @@ def test_training_reduces_exact_fq_and_respects_bound():
     Fq1, _ = O.exact_fq_and_grad(inst, th1, 16)
     assert F - 1e-12 <= Fq1 < Fq0
     assert stats.shape == (60, 4)
+
+
+def test_observables_exact_under_full_enumeration_with_uniform_q():
+    # every width-set configuration once, with a uniform q: the
+    # self-normalised weights are the exact W-marginal of p, so the estimates
+    # are the exact moments (brute force over all 2^16 states)
+    inst = S.c1_small_lattice()
+    nw = inst.n_width
+    x = np.arange(1 << nw)[:, None]
+    sw = (1 - 2 * ((x >> np.arange(nw)[None, :]) & 1)).astype(np.int8)
+    m, c, ess = O.observables(inst, sw, np.zeros(sw.shape[0]))
+    n = inst.n
+    y = np.arange(1 << n)[:, None]
+    full = (1 - 2 * ((y >> np.arange(n)[None, :]) & 1)).astype(np.float64)
+    e = I.energy(inst, full)
+    p = np.exp(-inst.beta * (e - e.min()))
+    p /= p.sum()
+    m_ex = p @ full
+    ed = np.asarray(inst.edges).reshape(-1, 2)
+    c_ex = p @ (full[:, ed[:, 0]] * full[:, ed[:, 1]])
+    np.testing.assert_allclose(m, m_ex, atol=1e-12)
+    np.testing.assert_allclose(c, c_ex, atol=1e-12)
+    assert 1.0 <= ess <= sw.shape[0]
