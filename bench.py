@@ -276,6 +276,21 @@ def main():
     t_obs = event_time(obs, 5, st)
     ess_o = [float(v) for v in ess_o.cpu().numpy()]
 
+    # the width-set planner (host only, Sec. 2 dynamic slicing) on the
+    # paper's graph sizes: a 40x40 lattice and an n = 1000, d = 3 random
+    # regular graph at w_u = 20 with the tree kept, an n = 300, d = 4 random
+    # regular graph at w_u = 20 with the tree rebuilt after every pick
+    from paper_2504_12037_amd import plan_width_set
+    from synthetic import instances as SI
+    plans = {}
+    for pname, pn, pe, pw, prg in [
+            ("lattice40_wu20", 1600, SI.lattice_edges(40), 20, False),
+            ("rrg1000d3_wu20", 1000, SI.random_regular_edges(1000, 3, np.random.default_rng(9)), 20, False),
+            ("rrg300d4_wu20_regreedy", 300, SI.random_regular_edges(300, 4, np.random.default_rng(7)), 20, True)]:
+        t0 = time.perf_counter()
+        Wp, _, wp, _ = plan_width_set(pn, pe, pw, regreedy=prg)
+        plans[pname] = {"s": time.perf_counter() - t0, "width_set": int(Wp.shape[0]), "width": wp}
+
     # the dominant kernel's live timing (none on paths without it, e.g. FP64)
     roofline = None
     if "chain_bwd_2" in ktime:
@@ -327,6 +342,7 @@ def main():
             "observables": {"workload": "the step's network and batch (samples of q)",
                             "s": t_obs, "samples_per_s": nI * B / t_obs,
                             "effective_sample_size": ess_o},
+            "planner": plans,
             "kernel_avg_us": {KERNEL_NAMES.get(k, k).format(split=str(split).lower(), mode=2 if split else 0): 1e6 * t / n
                               for k, (t, n) in ktime.items()},
         },

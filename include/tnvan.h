@@ -285,6 +285,47 @@ tnvan_status tnvan_profile_mask(tnvan_net *net, uint32_t mask);
  * device and report the same statistics as tnvan_program_info. */
 tnvan_status tnvan_plan(const tnvan_instance *inst, int32_t max_width, int64_t info[6]);
 
+/* Width set W and elimination order of R = V \ W for a bound w_u on the
+ * contraction width, by the recipe of Sec. 2 (finding the width set): a
+ * greedy order pi of the whole interaction graph, then dynamic slicing, then
+ * indices put back from W.  Host only; touches no device.
+ *  - The width of an elimination order is its largest scope, the neighbours
+ *    (fill edges included) of a vertex not yet eliminated when it is; the
+ *    message it leaves has 2^scope entries.  Fixing W removes W and its
+ *    edges; the order of R is always pi with the W vertices skipped.
+ *  - pi is min-fill: the vertex whose current neighbours miss the fewest
+ *    edges among themselves first (ties: fewest current neighbours, then
+ *    smallest key).
+ *  - Slicing: while the width exceeds w_u, the vertex lying in the most
+ *    scopes of the maximum size moves to W (ties: larger degree, then
+ *    smallest key).
+ *  - Then each W vertex, in ascending key order, goes back to R if the
+ *    width stays <= w_u.  At w_u = 1, R is a forest: W is a feedback vertex
+ *    set.
+ *  - With TNVAN_PLAN_REGREEDY in flags the tree is rebuilt instead of kept:
+ *    after every pick and for every re-adding test, the min-fill order of
+ *    the graph induced on R replaces pi restricted to R (slower; smaller W
+ *    at small w_u).
+ *   n_spins        1..16384
+ *   edge_i, edge_j host int32 [n_edges], 0-based, i != j (duplicates ignored)
+ *   w_u            width bound, >= 1
+ *   key            host int32 [n_spins], a permutation of 0..n_spins-1
+ *                  (random draws of the caller), or NULL for key = id
+ *   flags          0 or TNVAN_PLAN_REGREEDY
+ *   width_set      host int32 out [n_spins]: W ascending in the first
+ *                  *n_width entries
+ *   order          host int32 out [n_spins]: the order of R in the first
+ *                  n_spins - *n_width entries
+ *   greedy         host int32 out [n_spins]: pi, or NULL
+ *   width          host out: the width of `order` (<= w_u)
+ * Errors: any size, bound, endpoint, loop, key or flag out of range
+ * (TNVAN_E_INVALID). */
+#define TNVAN_PLAN_REGREEDY 1
+tnvan_status tnvan_plan_width_set(int32_t n_spins, int32_t n_edges, const int32_t *edge_i,
+                                  const int32_t *edge_j, int32_t w_u, const int32_t *key,
+                                  int32_t flags, int32_t *width_set, int32_t *n_width,
+                                  int32_t *order, int32_t *greedy, int32_t *width);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,6 +31,11 @@ within the bound.  The readings taken here:
     a permutation of the vertex ids passed in by the caller (the identity
     when none is given).
 
+With ``regreedy`` the tree is rebuilt instead of kept: after every slicing
+pick, and for every re-adding test, the min-fill order of the graph induced
+on R replaces pi restricted to R (the greedy heuristic run again on the
+network left after fixing W).
+
 Pinned in tests/test_oracle_planner.py against closed forms (trees, cycles,
 complete graphs, grids in row-major order, k-trees), a union-find forest
 check, and brute-force minimum feedback vertex sets on tiny graphs.
@@ -76,10 +81,12 @@ def width(edges, vertices: Sequence[int], order: Sequence[int]) -> int:
     return max((len(s) for _, s in scopes(edges, vertices, order)), default=0)
 
 
-def min_fill_order(n: int, edges, key: Optional[Sequence[int]] = None) -> List[int]:
-    """Greedy min-fill elimination order of all n vertices."""
+def min_fill_order(n: int, edges, key: Optional[Sequence[int]] = None,
+                   vertices: Optional[Sequence[int]] = None) -> List[int]:
+    """Greedy min-fill elimination order of the graph induced on
+    ``vertices`` (all n vertices when None)."""
     key = list(range(n)) if key is None else [int(k) for k in key]
-    adj = _graph(range(n), edges)
+    adj = _graph(range(n) if vertices is None else vertices, edges)
     order = []
     while adj:
         def fill(v):
@@ -96,8 +103,9 @@ def restrict(order: Sequence[int], W: Set[int]) -> List[int]:
     return [int(v) for v in order if int(v) not in W]
 
 
-def plan(n: int, edges, w_u: int, key: Optional[Sequence[int]] = None):
-    """Width set W (ascending id), order of R (pi without W) and its width.
+def plan(n: int, edges, w_u: int, key: Optional[Sequence[int]] = None,
+         regreedy: bool = False):
+    """Width set W (ascending id), order of R and its width.
 
     Returns (W, order, width, pi)."""
     if w_u < 1:
@@ -110,9 +118,15 @@ def plan(n: int, edges, w_u: int, key: Optional[Sequence[int]] = None):
         deg[int(b)] += 1
     pi = min_fill_order(n, edges, key)
     W: Set[int] = set()
+
+    def order_of(Wset):
+        if not regreedy:
+            return restrict(pi, Wset)
+        return min_fill_order(n, edges, key, [v for v in range(n) if v not in Wset])
+
     # dynamic slicing
     while True:
-        R = restrict(pi, W)
+        R = order_of(W)
         sc = scopes(edges, R, R)
         w = max((len(s) for _, s in sc), default=0)
         if w <= w_u:
@@ -126,8 +140,8 @@ def plan(n: int, edges, w_u: int, key: Optional[Sequence[int]] = None):
         W.add(pick)
     # re-adding in ascending key order
     for v in sorted(W, key=lambda u: key[u]):
-        R2 = restrict(pi, W - {v})
+        R2 = order_of(W - {v})
         if width(edges, R2, R2) <= w_u:
             W.discard(v)
-    order = restrict(pi, W)
+    order = order_of(W)
     return sorted(W), order, width(edges, order, order), pi

@@ -19,9 +19,9 @@ from typing import Sequence
 import torch
 
 from . import _lib
-from ._lib import TnvanError, plan  # noqa: F401
+from ._lib import TnvanError, plan, plan_width_set  # noqa: F401
 
-__all__ = ["Net", "LogZ", "plan", "TnvanError"]
+__all__ = ["Net", "LogZ", "plan", "plan_width_set", "TnvanError"]
 
 
 def _ptr(t):

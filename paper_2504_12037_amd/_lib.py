@@ -30,6 +30,7 @@ EXPORTS = ["tnvan_build_network", "tnvan_free_network", "tnvan_last_error",
            "tnvan_logz_and_backward", "tnvan_exact_free_energy", "tnvan_observables",
            "tnvan_free_energy_step",
            "tnvan_free_energy_step_adjoint", "tnvan_program_info", "tnvan_plan",
+           "tnvan_plan_width_set",
            "tnvan_kernel_time", "tnvan_profile_mask"]
 
 
@@ -86,6 +87,7 @@ def lib():
     L.tnvan_free_energy_step_adjoint.argtypes = [vp, vp, C.c_float, vp, vp, vp, vp, vp, vp, vp]
     L.tnvan_program_info.argtypes = [vp, i32, vp]
     L.tnvan_plan.argtypes = [vp, i32, vp]
+    L.tnvan_plan_width_set.argtypes = [i32, i32, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp]
     L.tnvan_kernel_time.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(i64)]
     L.tnvan_profile_mask.argtypes = [vp, C.c_uint32]
     for name in EXPORTS:
@@ -140,3 +142,33 @@ def plan(inst, max_width: int = 14):
     info = (C.c_int64 * 6)()
     check(lib().tnvan_plan(C.byref(c), int(max_width), info))
     return tuple(int(x) for x in info)
+
+
+PLAN_REGREEDY = 1
+
+
+def plan_width_set(n: int, edges, w_u: int, key=None, regreedy: bool = False):
+    """Width set and order of R for the bound w_u (dynamic slicing, host
+    only): returns (W ascending, order of R, width of the order, greedy
+    order pi of all spins).  ``key``: a permutation of range(n) that breaks
+    ties and orders the re-adding phase (identity when None).  ``regreedy``
+    rebuilds the min-fill order of R after every slicing pick."""
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+    ei = np.ascontiguousarray(e[:, 0])
+    ej = np.ascontiguousarray(e[:, 1])
+    k = None if key is None else np.ascontiguousarray(np.asarray(key, dtype=np.int32))
+    if k is not None and k.shape != (n,):
+        raise ValueError("key must have n entries")
+    W = np.zeros(max(n, 1), np.int32)
+    O = np.zeros(max(n, 1), np.int32)
+    pi = np.zeros(max(n, 1), np.int32)
+    nw = C.c_int32(0)
+    w = C.c_int32(0)
+    check(lib().tnvan_plan_width_set(int(n), int(e.shape[0]),
+                                     ei.ctypes.data if e.shape[0] else None,
+                                     ej.ctypes.data if e.shape[0] else None, int(w_u),
+                                     None if k is None else k.ctypes.data,
+                                     PLAN_REGREEDY if regreedy else 0, W.ctypes.data, C.byref(nw), O.ctypes.data,
+                                     pi.ctypes.data, C.byref(w)))
+    m = int(nw.value)
+    return W[:m].copy(), O[:n - m].copy(), int(w.value), pi[:n].copy()

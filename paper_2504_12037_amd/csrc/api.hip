@@ -16,6 +16,7 @@
 #include "../../include/tnvan.h"
 #include "compile.h"
 #include "launch.h"
+#include "plan.h"
 
 namespace tnvan {
 }
@@ -1502,6 +1503,32 @@ tnvan_status tnvan_plan(const tnvan_instance *inst, int32_t max_width, int64_t i
   const InstDesc &D = P.insts[0];
   info[0] = D.n_steps; info[1] = D.max_w; info[2] = D.arena_all;
   info[3] = P.flops_fwd[0]; info[4] = D.nw; info[5] = D.nr;
+  return TNVAN_OK;
+}
+
+tnvan_status tnvan_plan_width_set(int32_t n_spins, int32_t n_edges, const int32_t *edge_i,
+                                  const int32_t *edge_j, int32_t w_u, const int32_t *key,
+                                  int32_t flags, int32_t *width_set, int32_t *n_width,
+                                  int32_t *order, int32_t *greedy, int32_t *width) {
+  if (flags & ~TNVAN_PLAN_REGREEDY) return set_err(TNVAN_E_INVALID, "unknown plan flags %d", flags);
+  if (!width_set || !n_width || !order || !width)
+    return set_err(TNVAN_E_INVALID, "width_set, n_width, order and width are required");
+  if (n_edges < 0 || (n_edges > 0 && (!edge_i || !edge_j)))
+    return set_err(TNVAN_E_INVALID, "bad edge arrays");
+  if (n_spins <= 0 || n_spins > kPlanMaxSpins)
+    return set_err(TNVAN_E_INVALID, "n_spins %d out of range 1..%d", n_spins, kPlanMaxSpins);
+  std::vector<int32_t> ei(edge_i, edge_i + n_edges), ej(edge_j, edge_j + n_edges), k;
+  if (key) k.assign(key, key + n_spins);
+  PlanResult R;
+  std::string msg;
+  if (tnvan_status s = plan_width_set(n_spins, ei, ej, w_u, k, (flags & TNVAN_PLAN_REGREEDY) != 0,
+                                      R, msg))
+    return set_err(s, "%s", msg.c_str());
+  std::copy(R.W.begin(), R.W.end(), width_set);
+  std::copy(R.order.begin(), R.order.end(), order);
+  if (greedy) std::copy(R.pi.begin(), R.pi.end(), greedy);
+  *n_width = (int32_t)R.W.size();
+  *width = R.width;
   return TNVAN_OK;
 }
 

@@ -1,0 +1,80 @@
+"""Instances decomposed by the native width-set planner (Sec. 2) run through
+the contraction path: a random regular graph and a lattice, W and the order
+of R from tnvan_plan_width_set at a given bound, then the batched logZ_R and
+its adjoint against the oracle's variable elimination, and the exact free
+energy by slicing against the oracle's brute force where it is small."""
+
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import ising as OI
+from synthetic import instances as SI
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5}
+
+
+def _planned(n, edges, w_u, seed, regreedy, beta=0.5, hidden=16):
+    from paper_2504_12037_amd import plan_width_set
+    rng = np.random.default_rng(seed)
+    J = rng.choice(np.array([-1.0, 1.0]), edges.shape[0])
+    h = rng.normal(0.0, 0.3, n)
+    W, order, w, _ = plan_width_set(n, edges, w_u, rng.permutation(n), regreedy=regreedy)
+    assert w <= w_u
+    return SI.Instance(n, edges.astype(np.int32), J, h, float(beta), W.astype(np.int32),
+                       order.astype(np.int32), None, hidden, f"planned{n}_w{w_u}")
+
+
+def _lattice(L):
+    e = []
+    for i in range(L):
+        for j in range(L):
+            v = i * L + j
+            if j + 1 < L:
+                e.append((v, v + 1))
+            if i + 1 < L:
+                e.append((v, v + L))
+    return np.asarray(e, np.int32)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("graph,w_u,regreedy", [("rrg60d3", 6, True), ("rrg60d3", 4, False),
+                                                ("lattice10", 5, True)])
+def test_planned_instances_logz_and_adjoint(prec, graph, w_u, regreedy):
+    from paper_2504_12037_amd import Net
+    if graph == "rrg60d3":
+        n, e = 60, SI.random_regular_edges(60, 3, np.random.default_rng(3))
+    else:
+        n, e = 100, _lattice(10)
+    inst = _planned(n, e, w_u, 4, regreedy)
+    B = 257
+    spins = S.uniform_spins(B, inst.n_width, 5)
+    print(f"\n[planned] {graph} w_u={w_u} regreedy={regreedy} |W|={inst.n_width} "
+          f"prec={prec}", flush=True)
+    net = Net([inst], precision=prec)
+    sp = torch.from_numpy(spins).cuda().reshape(-1)
+    lz = net.logz(sp, B).cpu().numpy()
+    want = OI.logz_r_elimination(inst, spins)
+    assert np.abs(lz - want).max() / inst.n <= TOL[prec]
+    g = np.random.default_rng(6).standard_normal(B)
+    dh, dJ, db = net.backward(sp, torch.from_numpy(g).cuda(), B)
+    wdh, wdJ, wdb = OI.logz_r_vjp(inst, spins, g)
+    scale = np.abs(g).sum()
+    tol = 50 * TOL[prec] * scale
+    assert np.abs(dh.cpu().numpy() - wdh).max() <= tol
+    assert np.abs(dJ.cpu().numpy() - wdJ).max() <= tol
+    assert abs(db.cpu().item() - wdb) <= tol
+
+
+def test_planned_small_instance_exact_free_energy():
+    # n = 20, d = 3: |W| small enough to enumerate; against brute-force ln Z
+    from paper_2504_12037_amd import Net
+    n, e = 20, SI.random_regular_edges(20, 3, np.random.default_rng(8))
+    inst = _planned(n, e, 2, 9, True)
+    print(f"\n[planned] rrg20d3 exact, |W|={inst.n_width}", flush=True)
+    net = Net([inst], precision="fp64")
+    lz, _ = net.exact_free_energy(0).cpu().numpy()
+    assert abs(lz - OI.logz_full_bruteforce(inst)) / n <= 1e-10

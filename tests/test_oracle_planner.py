@@ -135,46 +135,59 @@ def test_min_fill_on_forests_and_cycles():
     assert P.width(c, range(15), P.min_fill_order(15, c)) == 2
 
 
-def _check_plan(n, edges, w_u, key=None):
-    W, order, w, pi = P.plan(n, edges, w_u, key)
+def _check_plan(n, edges, w_u, key=None, regreedy=False):
+    W, order, w, pi = P.plan(n, edges, w_u, key, regreedy)
     assert sorted(W + order) == list(range(n))
-    assert order == [v for v in pi if v not in set(W)]
+    if regreedy:
+        R = [v for v in range(n) if v not in set(W)]
+        assert order == P.min_fill_order(n, edges, key, R)
+    else:
+        assert order == [v for v in pi if v not in set(W)]
     assert w == P.width(edges, order, order) <= w_u
     if w_u == 1:
         assert _is_forest(set(order), edges)
     return W, order, w, pi
 
 
+@pytest.mark.parametrize("regreedy", [False, True])
 @pytest.mark.parametrize("w_u", [1, 2, 3, 5])
-def test_plan_outputs_are_valid(w_u):
+def test_plan_outputs_are_valid(w_u, regreedy):
     rng = np.random.default_rng(10 + w_u)
     graphs = [(36, _grid(6, 6)), (40, _rrg(40, 3, rng)), (30, _rrg(30, 4, rng)),
               (10, _complete(10))]
     for n, e in graphs:
-        _check_plan(n, e, w_u, key=list(rng.permutation(n)))
+        _check_plan(n, e, w_u, key=list(rng.permutation(n)), regreedy=regreedy)
 
 
+@pytest.mark.parametrize("regreedy", [False, True])
 @pytest.mark.parametrize("seed", range(4))
-def test_plan_at_width_one_is_a_feedback_vertex_set(seed):
+def test_plan_at_width_one_is_a_feedback_vertex_set(seed, regreedy):
     rng = np.random.default_rng(20 + seed)
     n = 11
     e = _rrg(n - 1, 3, rng) + [(int(rng.integers(0, n - 1)), n - 1)]
     e = sorted({(min(a, b), max(a, b)) for a, b in e})
-    W, _, _, _ = _check_plan(n, e, 1, key=list(rng.permutation(n)))
+    W, _, _, _ = _check_plan(n, e, 1, key=list(rng.permutation(n)), regreedy=regreedy)
     assert len(W) >= _min_fvs(n, e)
 
 
-def test_plan_forced_sizes():
+@pytest.mark.parametrize("regreedy", [False, True])
+def test_plan_forced_sizes(regreedy):
     # one vertex per disjoint cycle
     e = _cycle(7) + _cycle(5, start=7) + _cycle(4, start=12)
-    W, _, _, _ = _check_plan(16, e, 1)
+    W, _, _, _ = _check_plan(16, e, 1, regreedy=regreedy)
     assert len(W) == 3
     assert len(set(W) & set(range(7))) == 1 and len(set(W) & set(range(7, 12))) == 1
     # complete graph: n - w_u - 1 vertices, whatever the key
     rng = np.random.default_rng(30)
     for w_u in (1, 3, 6):
-        W, _, _, _ = _check_plan(12, _complete(12), w_u, key=list(rng.permutation(12)))
+        W, _, _, _ = _check_plan(12, _complete(12), w_u, key=list(rng.permutation(12)),
+                                 regreedy=regreedy)
         assert len(W) == 12 - w_u - 1
+    # a forest needs no width set at w_u = 1 once the order is rebuilt on it
+    if regreedy:
+        t = [(int(rng.integers(0, i)), i) for i in range(1, 20)]
+        W, _, w, _ = _check_plan(20, t, 1, key=list(rng.permutation(20)), regreedy=True)
+        assert W == [] and w == 1
     # a bound at or above the greedy order's width slices nothing
     n, e = 36, _grid(6, 6)
     pi = P.min_fill_order(n, e)
