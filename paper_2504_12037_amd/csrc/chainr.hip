@@ -9,8 +9,9 @@
 // table loads (prefetched one step ahead, pre-permuted so that every lane
 // reads 16 contiguous bytes), matrix-core products, a cross-lane max for the
 // power-of-two rescale and the per-sample diagonal of the next group.  The
-// unary factors of a group are computed on the fly from the sample's
-// width-set spins (staged once per wave in LDS) and the W-neighbour lists.
+// diagonal's unary factors (fields plus W-R couplings, Eq. 4) are read from
+// the table unary_kernel fills once per (sample, position), one load per
+// position, issued steps ahead of their use.
 //
 // The adjoint's forward pass is the forward kernel's arithmetic step for
 // step, so it also writes the chain's log partial (logZ comes with the
