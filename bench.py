@@ -291,6 +291,23 @@ def main():
         Wp, _, wp, _ = plan_width_set(pn, pe, pw, regreedy=prg)
         plans[pname] = {"s": time.perf_counter() - t0, "width_set": int(Wp.shape[0]), "width": wp}
 
+    # the paper's 40x40 ferromagnet at the critical temperature (Fig. 2)
+    # with Table 1's settings: one masked layer, batch 1000, 1000 steps,
+    # learning rate 0.01; W = columns 7, 14, 21, 28, 35 (|W| = 200)
+    beta_c = 0.5 * float(np.log(1.0 + np.sqrt(2.0)))
+    inst40 = S.lattice_column_split(S.lattice_2d(40, seed=0, beta=beta_c, ferro=True),
+                                    [7, 14, 21, 28, 35], hidden=0)
+    net40 = Net([inst40], precision=args.precision, flags=Net.FLAG_SPLIT_BF16 if split else 0)
+    st40 = torch.empty(1, 4, device="cuda", dtype=torch.float64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(1000):
+        net40.free_energy_step(1000, 0.01, stats=st40)
+    torch.cuda.synchronize()
+    t40 = (time.perf_counter() - t0) / 1000
+    F40 = [float(v) / inst40.n for v in st40.cpu().numpy()[0, :2]]
+    del net40
+
     # the dominant kernel's live timing (none on paths without it, e.g. FP64)
     roofline = None
     if "chain_bwd_2" in ktime:
@@ -343,6 +360,11 @@ def main():
                             "s": t_obs, "samples_per_s": nI * B / t_obs,
                             "effective_sample_size": ess_o},
             "planner": plans,
+            "lattice40_ferro_tc": {"workload": "40x40 OBC ferromagnet at beta_c, W = columns "
+                                               "7,14,21,28,35, one masked layer, batch 1000, "
+                                               "1000 steps, lr 0.01",
+                                   "ms_per_step": 1e3 * t40, "F_q_per_spin": F40[0],
+                                   "stderr_per_spin": F40[1]},
             "kernel_avg_us": {KERNEL_NAMES.get(k, k).format(split=str(split).lower(), mode=2 if split else 0): 1e6 * t / n
                               for k, (t, n) in ktime.items()},
         },
