@@ -153,6 +153,11 @@ struct tnvan_net {
   int rtiles = 1, sg = 2;
   int rg_lo[3] = {0, 0, 0}, rg_n[3] = {0, 0, 0}, brg_lo[3] = {0, 0, 0}, brg_n[3] = {0, 0, 0};
   int sg_of(int rt) const { return rt >= 4 ? 1 : sg; }
+  // one-layer sampler (every instance H = 0, the general path): W0's
+  // columns, n_q^2 floats per instance
+  bool h0 = false;
+  int h0_nmax = 0;
+  DBuf w0t, d_w0t_off, w_sig;
   // matrix-core sampler
   bool msample = false;
   int mpt = 1;
@@ -703,6 +708,24 @@ tnvan_status run_sample(tnvan_net *net, const float *uniforms, int8_t *spins, vo
   a.mi = net->d_mi.as<MadeInst>();
   a.params = net->params.as<float>();
   a.uniforms = uniforms;
+  if (net->h0) {
+    // the current parameters' columns of W0, then a wave per sample
+    a.spins = spins;
+    a.logq = static_cast<real *>(logq);
+    a.seed = net->seed;
+    a.step_ctr = net->step_ctr.as<int32_t>();
+    a.w0t = net->w0t.as<float>();
+    a.w0t_off = net->d_w0t_off.as<int64_t>();
+    HIPCHK(net->w_sig.ensure((size_t)std::max<int64_t>(1, net->spin_total) * sizeof(real)));
+    a.sig = net->w_sig.as<real>();
+    int64_t maxB = 0;
+    for (int q = 0; q < net->n_inst; ++q) maxB = std::max(maxB, net->nkey[q]);
+    HIPCHK(launch_w0t(a.mi, net->n_inst, net->h0_nmax, a.params, a.w0t_off, net->w0t.as<float>(),
+                      st));
+    ProfScope ps(net, TNVAN_KERNEL_SAMPLE, st);
+    HIPCHK(launch_sample_h0<real>(a, net->n_inst, maxB, net->h0_nmax, st));
+    return TNVAN_OK;
+  }
   a.blk_inst = net->blk_inst.as<int32_t>();
   a.blk_start = net->blk_start.as<int32_t>();
   a.spins = spins;
@@ -839,7 +862,13 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     r.da = net->w_da.as<real>();
     r.dlogit = net->w_dlogit.as<real>();
     r.sf = net->w_sf.as<real>();
-    HIPCHK(launch_rows<real>(r, st));
+    if (net->h0) {
+      // the conditionals the sampler stored for these spins and parameters
+      r.sig = net->w_sig.as<real>() + m.spin_off;
+      HIPCHK(launch_rows_h0<real>(r, st));
+    } else {
+      HIPCHK(launch_rows<real>(r, st));
+    }
     const int ks = (int)std::max<int64_t>(1, std::min<int64_t>(64, m.B / 256));
     const int64_t maxmn = std::max<int64_t>({(int64_t)n * H, (int64_t)n * n, (int64_t)H});
     HIPCHK(net->w_part.ensure(std::max<int64_t>(1, maxmn * ks) * sizeof(real)));
@@ -1005,6 +1034,26 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
     }
     net->mpt = nmax <= 16 ? 1 : nmax <= 32 ? 2 : 4;
     net->msample = fits;
+    // one-layer nets outside the matrix-core sampler: a wave per sample
+    bool h0 = !fits && nmax <= kH0MaxN;
+    std::vector<int64_t> w0off;
+    int64_t wo = 0;
+    for (auto &m : net->mi) {
+      if (m.H != 0 && m.n >= 2) h0 = false;
+      w0off.push_back(wo);
+      wo += (int64_t)m.n * m.n;
+    }
+    net->h0 = h0;
+    net->h0_nmax = nmax;
+    if (h0) {
+      hipError_t e0 = upload(net->d_w0t_off, w0off);
+      if (e0 == hipSuccess) e0 = net->w0t.ensure((size_t)std::max<int64_t>(1, wo) * sizeof(float));
+      if (e0 != hipSuccess) {
+        tnvan_free_network(net);
+        return set_err(e0 == hipErrorOutOfMemory ? TNVAN_E_NOMEM : TNVAN_E_HIP, "w0t: %s",
+                       hipGetErrorString(e0));
+      }
+    }
     int64_t po = 0;
     for (auto &m : net->mi) {
       m.pack_off = po;

@@ -106,11 +106,24 @@ struct SampleArgs {
   const int32_t *step_ctr;      // per instance (device), Philox counter word 2
   int32_t spb;                  // samples per round of a block (256 / L)
   int32_t reps;                 // rounds per block
+  const float *w0t;             // one-layer sampler: columns of W0 (w0t_kernel)
+  const int64_t *w0t_off;       // per instance, floats
+  real *sig;                    // one-layer sampler: q(s_i = +1 | s_<i) in the
+                                // spins' layout, or null
 };
 // stage_bytes: LDS for the parameters (0 or too large: read them from HBM)
 template <typename real>
 hipError_t launch_sample(const SampleArgs<real> &a, int n_blocks, size_t stage_bytes,
                          hipStream_t st);
+// One-layer nets (every instance H = 0, |W| <= kH0MaxN): one wave per
+// sample, W0's columns from w0t (written by launch_w0t from the parameters;
+// w0t_off[q] is instance q's offset, n_q^2 floats each).
+constexpr int kH0MaxN = 512;
+hipError_t launch_w0t(const MadeInst *mi, int n_inst, int max_n, const float *params,
+                      const int64_t *w0t_off, float *w0t, hipStream_t st);
+template <typename real>
+hipError_t launch_sample_h0(const SampleArgs<real> &a, int n_inst, int64_t max_B, int max_n,
+                            hipStream_t st);
 size_t made_param_bytes(int n, int H);
 
 // Matrix-core sampler (FP32): one wave per 16 samples of one instance.
@@ -174,9 +187,13 @@ struct RowArgs {
   real *da;                // [B, H]
   real *dlogit;            // [B, n]
   real *sf;                // [B, n] spins as real
+  const real *sig;         // one-layer nets: the sampler's conditionals [B, n]
 };
 template <typename real>
 hipError_t launch_rows(const RowArgs<real> &a, hipStream_t st);
+// one-layer nets: the rows from the conditionals the sampler stored
+template <typename real>
+hipError_t launch_rows_h0(const RowArgs<real> &a, hipStream_t st);
 
 // C[M, N] (+)= X^T Y over the batch; X [B, ldx] column offset, Y likewise.
 template <typename real>

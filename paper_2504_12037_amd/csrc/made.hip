@@ -27,6 +27,9 @@ template <> __device__ inline double rexp<double>(double x) { return exp(x); }
 template <typename real> __device__ inline real rlog1p(real x);
 template <> __device__ inline float rlog1p<float>(float x) { return log1pf(x); }
 template <> __device__ inline double rlog1p<double>(double x) { return log1p(x); }
+template <typename real> __device__ inline real rlog(real x);
+template <> __device__ inline float rlog<float>(float x) { return logf(x); }
+template <> __device__ inline double rlog<double>(double x) { return log(x); }
 template <typename real> __device__ inline real rtanh(real x);
 template <> __device__ inline float rtanh<float>(float x) { return tanhf(x); }
 template <> __device__ inline double rtanh<double>(double x) { return tanh(x); }
@@ -219,6 +222,136 @@ __global__ __launch_bounds__(256) void sample_kernel(SampleArgs<real> a) {
   }
 }
 
+// Columns of W0 for the one-layer sampler: w0t[i][k] = W0[k][i] for k > i,
+// 0 on and above the diagonal (whatever the parameters hold there, as the
+// masks of Eq. 7 require).  32x32 tiles through LDS, both sides coalesced.
+__global__ __launch_bounds__(256) void w0t_kernel(const MadeInst *mis, const float *params,
+                                                  const int64_t *w0t_off, float *w0t) {
+  const MadeInst mi = mis[blockIdx.z];
+  const int n = mi.n;
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  if (r0 >= n || c0 >= n) return;
+  const float *W0 = made_view(params + mi.param_off, n, mi.H).W0;
+  float *T = w0t + w0t_off[blockIdx.z];
+  __shared__ float tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int y = ty; y < 32; y += 8) {
+    const int k = r0 + y, i = c0 + tx;   // W0[k][i]
+    tile[y][tx] = (k < n && i < n && k > i) ? W0[(int64_t)k * n + i] : 0.f;
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int i = c0 + y, k = r0 + tx;   // T[i][k]
+    if (i < n && k < n) T[(int64_t)i * n + k] = tile[tx][y];
+  }
+}
+
+// Ancestral sampling for one-layer nets (H = 0: logit_i = b_i + sum_{j<i}
+// W0[i][j] s_j, Eq. 7), one wave per sample.  Lane l owns positions
+// l + 64 m (m < NM).  Their logits start at b and take the rank-1 update
+// W0[:, i] s_i as soon as s_i is drawn, so position i's logit is complete
+// when its turn comes; entries on and above the diagonal are zero, so it
+// stays fixed afterwards.  The draw s_i = +1 iff u_i < sigmoid(logit_i) is
+// taken as logit_i > ln(u_i / (1 - u_i)), with the right side formed by
+// the owning lane before the block of 64 positions starts: the sequential
+// part of a step is one compare in lane i, one read of that lane and the
+// rank-1 update.  ln q is summed from the final logits after each block.
+// The four waves of a workgroup share the columns of W0: chunks of 16
+// columns are staged in LDS (two buffers, the next chunk loaded while the
+// current one is used).  Waves past the batch run along (the barriers need
+// them) and store nothing.
+constexpr int kH0Chunk = 16;
+template <typename real, int NM>
+__global__ __launch_bounds__(256) void sample_h0_kernel(SampleArgs<real> a) {
+  const int q = blockIdx.y;
+  const MadeInst mi = a.mi[q];
+  if ((int64_t)blockIdx.x * 4 >= mi.B) return;   // the whole block
+  const int n = mi.n;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t b = (int64_t)blockIdx.x * 4 + wave;
+  const bool live = b < mi.B;
+  const int64_t bs = live ? b : 0;
+  const float *b2 = made_view(a.params + mi.param_off, n, mi.H).b2;
+  const float *T = a.w0t + a.w0t_off[q];
+  constexpr int RS = 64 * NM;                     // LDS row stride
+  constexpr int PER = kH0Chunk * RS / 256;        // staged floats per thread
+  __shared__ float buf[2][kH0Chunk * RS];
+  const int n_chunks = (n + kH0Chunk - 1) / kH0Chunk;
+  float st[PER];
+  auto fetch = [&](int c) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int e = threadIdx.x + 256 * j, r = c * kH0Chunk + e / RS, k = e % RS;
+      st[j] = (r < n && k < n) ? T[(int64_t)r * n + k] : 0.f;
+    }
+  };
+  auto put = [&](int c) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) buf[c & 1][threadIdx.x + 256 * j] = st[j];
+  };
+  fetch(0);
+  put(0);
+  __syncthreads();
+  real z[NM];
+#pragma unroll
+  for (int m = 0; m < NM; ++m) z[m] = (lane + 64 * m < n) ? (real)b2[lane + 64 * m] : (real)0;
+  const uint32_t step = a.step_ctr ? (uint32_t)a.step_ctr[q] : 0u;
+  const float *u = a.uniforms ? a.uniforms + mi.spin_off + bs * n : nullptr;
+  int8_t *so = a.spins + mi.spin_off + bs * n;
+  real lq = 0;
+#pragma unroll
+  for (int mb = 0; mb < NM; ++mb) {
+    if (64 * mb >= n) break;
+    const int pos = 64 * mb + lane;
+    // the threshold of this lane's position: ln(u / (1 - u)) of its uniform
+    // (given, or Philox word pos & 3 of counter pos >> 2)
+    float ul;
+    if (u) {
+      ul = pos < n ? u[pos] : 0.5f;
+    } else {
+      uint32_t pw[4] = {(uint32_t)(pos >> 2), (uint32_t)bs, step, (uint32_t)q};
+      philox4x32_10(pw, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+      const uint32_t wd = (pos & 3) == 0 ? pw[0] : (pos & 3) == 1 ? pw[1] : (pos & 3) == 2 ? pw[2] : pw[3];
+      ul = (float)(wd >> 8) * 5.9604644775390625e-08f;
+    }
+    const real uu = (real)ul;
+    const real thr = rlog<real>(uu) - rlog1p<real>(-uu);   // -inf at u = 0: always +1
+    for (int c4 = 0; c4 < 4; ++c4) {
+      const int c = 4 * mb + c4;
+      if (c >= n_chunks) break;
+      if (c + 1 < n_chunks) fetch(c + 1);
+      const float *cb = buf[c & 1];
+      for (int g = 0; g < kH0Chunk; g += 4) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int il = kH0Chunk * c4 + g + r;
+          if (64 * mb + il < n) {
+            const float d = z[mb] > thr ? 1.f : -1.f;
+            const real si = (real)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(d), il));
+            const float *row = cb + (g + r) * RS + lane;
+#pragma unroll
+            for (int m = 0; m < NM; ++m) z[m] += (real)row[64 * m] * si;
+          }
+        }
+      }
+      if (c + 1 < n_chunks) put(c + 1);
+      __syncthreads();
+    }
+    // the block's logits are final: spins, their ln q terms and (for the
+    // REINFORCE backward of the same parameters) q(s_i = +1 | s_<i)
+    if (pos < n) {
+      const real sv = z[mb] > thr ? (real)1 : (real)-1;
+      lq += log_sigmoid<real>(sv * z[mb]);
+      if (live) {
+        so[pos] = (int8_t)(sv > 0 ? 1 : -1);
+        if (a.sig) a.sig[mi.spin_off + bs * n + pos] = sigmoid<real>(z[mb]);
+      }
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) lq += __shfl_xor(lq, off, 64);
+  if (live && lane == 0) a.logq[mi.sample_off + b] = lq;
+}
+
 // Per-sample rows of the log-prob pass and the REINFORCE backward:
 // a, tanh(a), logits, dlogit = w ((1+s)/2 - sigmoid(logit)) with the weight
 // w_b = (f_b - F_q) / B, and da = (dlogit . W2m) (1 - tanh^2).  A block walks
@@ -293,6 +426,22 @@ __global__ __launch_bounds__(256) void rows_kernel(RowArgs<real> a) {
     }
     __syncthreads();
   }
+}
+
+// The rows of the REINFORCE backward for one-layer nets: dlogit = w_b
+// ((1 + s) / 2 - q(s_i = +1 | s_<i)) with the conditionals the sampler
+// stored for these spins, and the spins as real; one thread per entry.
+template <typename real>
+__global__ __launch_bounds__(256) void rows_h0_kernel(RowArgs<real> a) {
+  const MadeInst mi = a.mi;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = mi.n;
+  if (e >= mi.B * n) return;
+  const int64_t r = e / n;
+  const real s = (real)a.spins[e];
+  const real wt = (real)((a.f[mi.sample_off + r] - a.stats[0]) / (double)mi.B);
+  a.dlogit[e] = wt * (((real)1 + s) * (real)0.5 - a.sig[e]);
+  a.sf[e] = s;
 }
 
 // part[ks][m][n] = sum over batch rows of slice ks of X[b, m] * Y[b, n]
@@ -1969,6 +2118,41 @@ hipError_t launch_sample(const SampleArgs<real> &a, int n_blocks, size_t stage_b
   return hipGetLastError();
 }
 
+hipError_t launch_w0t(const MadeInst *mi, int n_inst, int max_n, const float *params,
+                      const int64_t *w0t_off, float *w0t, hipStream_t st) {
+  if (n_inst <= 0 || max_n <= 0) return hipSuccess;
+  const unsigned t = (unsigned)((max_n + 31) / 32);
+  hipLaunchKernelGGL(w0t_kernel, dim3(t, t, n_inst), dim3(256), 0, st, mi, params, w0t_off, w0t);
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_sample_h0(const SampleArgs<real> &a, int n_inst, int64_t max_B, int max_n,
+                            hipStream_t st) {
+  if (n_inst <= 0 || max_B <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((max_B + 3) / 4), (unsigned)n_inst);
+  if (max_n <= 64)
+    hipLaunchKernelGGL((sample_h0_kernel<real, 1>), grid, dim3(256), 0, st, a);
+  else if (max_n <= 128)
+    hipLaunchKernelGGL((sample_h0_kernel<real, 2>), grid, dim3(256), 0, st, a);
+  else if (max_n <= 256)
+    hipLaunchKernelGGL((sample_h0_kernel<real, 4>), grid, dim3(256), 0, st, a);
+  else if (max_n <= kH0MaxN)
+    hipLaunchKernelGGL((sample_h0_kernel<real, 8>), grid, dim3(256), 0, st, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_rows_h0(const RowArgs<real> &a, hipStream_t st) {
+  const int64_t total = a.mi.B * a.mi.n;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL((rows_h0_kernel<real>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     st, a);
+  return hipGetLastError();
+}
+
 template <typename real>
 hipError_t launch_rows(const RowArgs<real> &a, hipStream_t st) {
   if (a.mi.B <= 0) return hipSuccess;
@@ -2061,8 +2245,12 @@ hipError_t launch_obs_w(const ObsArgs &a, int n_inst, hipStream_t st) {
 
 template hipError_t launch_sample<float>(const SampleArgs<float> &, int, size_t, hipStream_t);
 template hipError_t launch_sample<double>(const SampleArgs<double> &, int, size_t, hipStream_t);
+template hipError_t launch_sample_h0<float>(const SampleArgs<float> &, int, int64_t, int, hipStream_t);
+template hipError_t launch_sample_h0<double>(const SampleArgs<double> &, int, int64_t, int, hipStream_t);
 template hipError_t launch_rows<float>(const RowArgs<float> &, hipStream_t);
 template hipError_t launch_rows<double>(const RowArgs<double> &, hipStream_t);
+template hipError_t launch_rows_h0<float>(const RowArgs<float> &, hipStream_t);
+template hipError_t launch_rows_h0<double>(const RowArgs<double> &, hipStream_t);
 template hipError_t launch_atb<float>(const float *, int, const float *, int, int64_t, int, int, float *, int, float *, int, int, int, hipStream_t);
 template hipError_t launch_atb<double>(const double *, int, const double *, int, int64_t, int, int, double *, int, float *, int, int, int, hipStream_t);
 template hipError_t launch_colsum<float>(const float *, int, int64_t, int, float *, int, float *, hipStream_t);
