@@ -1171,11 +1171,12 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
       rq = rq && C.rq_ok;
     }
     const bool any = std::count(net->use_chain.begin(), net->use_chain.end(), 1) > 0;
-    // register-resident kernels when every chain step is narrow enough
-    const bool reg = any && !(opt->flags & TNVAN_FLAG_LDS_CHAIN) && lim.nw <= 128;
+    // register-resident kernels when every chain step is narrow enough; the
+    // adjoint's W-R sums hold the width-set spins as a 128-bit mask
+    const bool reg = any && !(opt->flags & TNVAN_FLAG_LDS_CHAIN);
     net->rfwd = reg && rq && net->rtiles <= kRegFwdTiles &&
                 4 * rchain_wave_lds(lim, false, net->sg) <= (size_t)maxlds;
-    net->rbwd = reg && rq && net->rtiles <= kRegBwdTiles &&
+    net->rbwd = reg && lim.nw <= 128 && rq && net->rtiles <= kRegBwdTiles &&
                 4 * rchain_wave_lds(lim, true, 1) <= (size_t)maxlds;
     const bool bf = net->precision == TNVAN_BF16;
     bool ok = true;

@@ -704,8 +704,12 @@ __global__ __launch_bounds__(256) void unary_kernel(ChainArgs a, const int32_t *
   }
   __syncthreads();
   if (b >= B) return;
-  // the sample's width-set spins as a bit mask, read with uniform indices
-  const SpinBits sb = load_bits_row(a.spins + a.inst_spin_off[q] + b * D.nw, D.nw);
+  // the sample's width-set spins as a bit mask, read with uniform indices;
+  // width sets beyond the mask's 128 bits read the spin bytes instead
+  const int8_t *srow = a.spins + a.inst_spin_off[q] + b * D.nw;
+  const bool bits = D.nw <= 128;
+  const SpinBits sb = bits ? load_bits_row(srow, D.nw) : SpinBits{{0u, 0u, 0u, 0u}};
+  auto sigma = [&](int w) { return bits ? sb.sigma(w) : (float)srow[w]; };
   const float beta = (float)D.beta;
   float *Uq = U + a.u_off[q];
   double fab = 0.0;
@@ -718,13 +722,13 @@ __global__ __launch_bounds__(256) void unary_kernel(ChainArgs a, const int32_t *
     if (s_n[i] <= 4) {
       float t[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) t[k] = s_r[i][k] >= 0 ? s_j[i][k] * sb.sigma(s_w[i][k]) : 0.f;
+      for (int k = 0; k < 4; ++k) t[k] = s_r[i][k] >= 0 ? s_j[i][k] * sigma(s_w[i][k]) : 0.f;
       f += (t[0] + t[1]) + (t[2] + t[3]);
     } else {
       const ci32 fptr = (ci32)(a.fld_ptr + D.fld_off);
       const ci32 fw = (ci32)(a.fld_w + D.fld_nnz_off);
       const cf32 fj = (cf32)(a.fld_J + D.fld_nnz_off);
-      for (int k = fptr[p]; k < fptr[p + 1]; ++k) f += fj[k] * sb.sigma(fw[k]);
+      for (int k = fptr[p]; k < fptr[p + 1]; ++k) f += fj[k] * sigma(fw[k]);
     }
     const float af = beta * fabsf(f);
     const float sm = __expf(-2.f * af);

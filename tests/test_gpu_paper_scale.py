@@ -39,3 +39,29 @@ def test_lattice40_ferromagnet_at_tc_against_kac_ward():
     # the paper's order of accuracy at T_c
     Fq, _ = seen[-1]
     assert (Fq - F_exact) / abs(F_exact) <= 3e-4
+
+
+@pytest.mark.parametrize("split", [False, True])
+def test_lattice40_logz_and_adjoint_wide_width_set(split):
+    # |W| = 200 (beyond the adjoint's 128-bit spin mask): the forward runs
+    # the register-resident chain kernels with the unary factors read from
+    # the spin bytes, the adjoint the LDS-staged ones; Gaussian couplings and
+    # fields, against the oracle's elimination and its reverse pass
+    from oracle import ising as OI
+    from paper_2504_12037_amd import Net
+    inst = S.lattice_column_split(S.lattice_2d(40, seed=21, beta=0.6, h_var=0.1),
+                                  [7, 14, 21, 28, 35])
+    B = 67
+    print(f"\n[paper-scale] 40x40 Gaussian, |W|={inst.n_width}, split={split}", flush=True)
+    spins = S.uniform_spins(B, inst.n_width, 3)
+    net = Net([inst], precision="fp32", flags=Net.FLAG_SPLIT_BF16 if split else 0)
+    sp = torch.from_numpy(spins).cuda().reshape(-1)
+    lz = net.logz(sp, B).cpu().numpy()
+    assert np.abs(lz - OI.logz_r_elimination(inst, spins)).max() / inst.n <= 1e-5
+    g = np.random.default_rng(4).standard_normal(B)
+    dh, dJ, db = net.backward(sp, torch.from_numpy(g).cuda(), B)
+    wdh, wdJ, wdb = OI.logz_r_vjp(inst, spins, g)
+    tol = 5e-5 * np.abs(g).sum()
+    assert np.abs(dh.cpu().numpy() - wdh).max() <= tol
+    assert np.abs(dJ.cpu().numpy() - wdJ).max() <= tol
+    assert abs(db.cpu().item() - wdb) <= tol
