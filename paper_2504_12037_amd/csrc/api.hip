@@ -869,7 +869,8 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     } else {
       HIPCHK(launch_rows<real>(r, st));
     }
-    const int ks = (int)std::max<int64_t>(1, std::min<int64_t>(64, m.B / 256));
+    // batch slices of at least 64 rows, at most 64 slices
+    const int ks = (int)std::max<int64_t>(1, std::min<int64_t>(64, m.B / 64));
     const int64_t maxmn = std::max<int64_t>({(int64_t)n * H, (int64_t)n * n, (int64_t)H});
     HIPCHK(net->w_part.ensure(std::max<int64_t>(1, maxmn * ks) * sizeof(real)));
     float *gW1 = g, *gb1 = g + (int64_t)H * n, *gW2 = gb1 + H, *gb2 = gW2 + (int64_t)n * H,

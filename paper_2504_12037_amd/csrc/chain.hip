@@ -661,8 +661,19 @@ __global__ void chain_sum_kernel(const InstDesc *inst, const ChainInst *cinst,
        b += (int64_t)gridDim.x * blockDim.x) {
     double acc = lc;
     for (int c = 0; c < nc; ++c) acc += cpart[cpart_off[q] + (int64_t)c * B + b];
-    if (fabp)
-      for (int c = 0; c < nf; ++c) acc += fabp[f_off[q] + (int64_t)c * B + b];
+    if (fabp) {
+      // loads in batches of 8 (independent), additions in chunk order
+      const double *fp = fabp + f_off[q] + b;
+      int c = 0;
+      for (; c + 8 <= nf; c += 8) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = fp[(int64_t)(c + k) * B];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc += v[k];
+      }
+      for (; c < nf; ++c) acc += fp[(int64_t)c * B];
+    }
     logz[inst_sample_off[q] + b] = acc;
   }
 }

@@ -512,7 +512,16 @@ __global__ void colsum_kernel(const real *X, int ldx, int64_t B, int M, real *pa
   const int64_t b0 = (int64_t)ks * chunk;
   const int64_t b1 = (b0 + chunk) < B ? (b0 + chunk) : B;
   real acc = 0;
-  for (int64_t b = b0; b < b1; ++b) acc += X[b * ldx + m];
+  int64_t b = b0;
+  // loads in batches of 8 (independent), additions in row order
+  for (; b + 8 <= b1; b += 8) {
+    real v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = X[(b + k) * ldx + m];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc += v[k];
+  }
+  for (; b < b1; ++b) acc += X[b * ldx + m];
   part[(int64_t)ks * M + m] = acc;
 }
 
