@@ -15,7 +15,10 @@
  * Conventions for every entry point
  *  - Host arrays are read during the call and copied; the caller keeps
  *    ownership.  Device pointers ("dev") are caller-owned device memory that
- *    must stay valid until the work queued on `stream` has completed.
+ *    must stay valid until the work queued on `stream` has completed.  A
+ *    "dev" argument that is plain host memory (not device, managed or
+ *    device-mapped pinned memory) is rejected with TNVAN_E_INVALID before
+ *    any work is queued.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
  *    device work of a call is queued on it; calls return without waiting
  *    unless stated otherwise.

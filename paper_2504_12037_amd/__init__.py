@@ -128,7 +128,7 @@ class Net:
         spins = torch.empty(max(tot, 1), device="cuda", dtype=torch.int8)
         logq = torch.empty(max(sum(counts), 1), device="cuda", dtype=self.logq_dtype)
         if uniforms is not None:
-            uniforms = uniforms.contiguous()
+            uniforms = uniforms.to(device="cuda").contiguous()
             assert uniforms.dtype == torch.float32 and uniforms.numel() == tot
         _lib.check(_lib.lib().tnvan_sample(self._h, arr, _ptr(uniforms), _ptr(spins),
                                            _ptr(logq), _stream()))
@@ -136,7 +136,7 @@ class Net:
 
     def logz(self, spins: torch.Tensor, n_samples, out: torch.Tensor = None):
         arr, counts = self._counts(n_samples)
-        spins = spins.contiguous()
+        spins = spins.to(device="cuda").contiguous()
         assert spins.dtype == torch.int8
         assert spins.numel() == sum(b * w for b, w in zip(counts, self.nw))
         if out is None:
@@ -171,8 +171,8 @@ class Net:
 
     def backward(self, spins: torch.Tensor, grad: torch.Tensor, n_samples, out=None):
         arr, counts = self._counts(n_samples)
-        spins = spins.contiguous()
-        grad = grad.to(torch.float64).contiguous()
+        spins = spins.to(device="cuda").contiguous()
+        grad = grad.to(device="cuda", dtype=torch.float64).contiguous()
         assert grad.numel() == sum(counts)
         if out is None:
             dh = torch.empty(sum(self.n), device="cuda", dtype=torch.float64)
@@ -197,10 +197,10 @@ class Net:
         """logz(spins) and backward(spins, grad) in one call (one contraction
         where the net allows it); returns (logz, dh, dJ, dbeta)."""
         arr, counts = self._counts(n_samples)
-        spins = spins.contiguous()
+        spins = spins.to(device="cuda").contiguous()
         assert spins.dtype == torch.int8
         assert spins.numel() == sum(b * w for b, w in zip(counts, self.nw))
-        grad = grad.to(torch.float64).contiguous()
+        grad = grad.to(device="cuda", dtype=torch.float64).contiguous()
         assert grad.numel() == sum(counts)
         if logz_out is None:
             logz_out = torch.empty(max(sum(counts), 1), device="cuda", dtype=torch.float64)

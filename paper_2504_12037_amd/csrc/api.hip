@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <new>
 #include <string>
 #include <vector>
@@ -966,6 +967,13 @@ bool is_device_ptr(const void *p) {
          (at.type == hipMemoryTypeHost && at.devicePointer != nullptr);
 }
 
+// every non-null pointer of the list must be accessible by the device
+tnvan_status check_device(std::initializer_list<const void *> ps) {
+  for (const void *p : ps)
+    if (p && !is_device_ptr(p)) return set_err(TNVAN_E_INVALID, "a buffer is not device memory");
+  return TNVAN_OK;
+}
+
 tnvan_status check_net(const tnvan_net *net) {
   if (!net) return set_err(TNVAN_E_INVALID, "net is NULL");
   return TNVAN_OK;
@@ -1263,6 +1271,7 @@ tnvan_status tnvan_param_count(const tnvan_net *net, int32_t inst, int64_t *coun
 tnvan_status tnvan_set_params(tnvan_net *net, int32_t inst, const float *src, void *stream) {
   if (tnvan_status s = check_net(net)) return s;
   if (inst < 0 || inst >= net->n_inst || !src) return set_err(TNVAN_E_INVALID, "bad instance or source");
+  if (tnvan_status s = check_device({src})) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t bytes = net->param_count[inst] * sizeof(float);
   const int64_t off = net->mi[inst].param_off;
@@ -1280,6 +1289,7 @@ tnvan_status tnvan_set_params(tnvan_net *net, int32_t inst, const float *src, vo
 tnvan_status tnvan_get_params(tnvan_net *net, int32_t inst, float *dst, void *stream) {
   if (tnvan_status s = check_net(net)) return s;
   if (inst < 0 || inst >= net->n_inst || !dst) return set_err(TNVAN_E_INVALID, "bad instance or destination");
+  if (tnvan_status s = check_device({dst})) return s;
   HIPCHK(hipMemcpyAsync(dst, net->params.as<float>() + net->mi[inst].param_off,
                         net->param_count[inst] * sizeof(float), hipMemcpyDeviceToDevice,
                         static_cast<hipStream_t>(stream)));
@@ -1293,6 +1303,7 @@ tnvan_status tnvan_get_state(tnvan_net *net, int32_t inst, int32_t which, float 
   const DBuf *src = which == 0 ? &net->params : which == 1 ? &net->grad
                   : which == 2 ? &net->adam_m : which == 3 ? &net->adam_v : nullptr;
   if (!src) return set_err(TNVAN_E_INVALID, "unknown state %d", which);
+  if (tnvan_status s = check_device({dst})) return s;
   HIPCHK(hipMemcpyAsync(dst, src->as<float>() + net->mi[inst].param_off,
                         net->param_count[inst] * sizeof(float), hipMemcpyDeviceToDevice,
                         static_cast<hipStream_t>(stream)));
@@ -1305,6 +1316,7 @@ tnvan_status tnvan_sample(tnvan_net *net, const int64_t *n_samples, const float 
   if (tnvan_status s = set_batch(net, n_samples)) return s;
   if (net->B_total == 0) return TNVAN_OK;
   if (!spins || !logq) return set_err(TNVAN_E_INVALID, "spins and logq are required");
+  if (tnvan_status s = check_device({uniforms, spins, logq})) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (net->precision == TNVAN_FP64) return run_sample<double>(net, uniforms, spins, logq, st);
   return run_sample<float>(net, uniforms, spins, logq, st);
@@ -1316,6 +1328,7 @@ tnvan_status tnvan_logz_batch(tnvan_net *net, const int64_t *n_samples, const in
   if (tnvan_status s = set_batch(net, n_samples)) return s;
   if (net->B_total == 0) return TNVAN_OK;
   if (!logz || (!spins && net->spin_total > 0)) return set_err(TNVAN_E_INVALID, "spins and logz are required");
+  if (tnvan_status s = check_device({spins, logz})) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (net->precision == TNVAN_FP64) return run_logz<double>(net, spins, logz, st);
   return run_logz<float>(net, spins, logz, st);
@@ -1373,9 +1386,7 @@ tnvan_status tnvan_observables(tnvan_net *net, const int64_t *n_samples, const i
                                const void *logq, double *mag, double *corr, double *ess,
                                void *stream) {
   if (tnvan_status s = check_net(net)) return s;
-  for (const void *p : {(const void *)spins, logq, (const void *)mag, (const void *)corr,
-                        (const void *)ess})
-    if (p && !is_device_ptr(p)) return set_err(TNVAN_E_INVALID, "a buffer is not device memory");
+  if (tnvan_status s = check_device({spins, logq, mag, corr, ess})) return s;
   for (auto &D : net->P.insts)
     if (!(D.beta > 0)) return set_err(TNVAN_E_INVALID, "observables need beta > 0");
   if (tnvan_status s = set_batch(net, n_samples)) return s;
@@ -1395,6 +1406,7 @@ tnvan_status tnvan_logz_backward(tnvan_net *net, const int64_t *n_samples, const
   if (!dh || !dJ || !dbeta) return set_err(TNVAN_E_INVALID, "dh, dJ and dbeta are required");
   if (net->B_total > 0 && (!grad || (!spins && net->spin_total > 0)))
     return set_err(TNVAN_E_INVALID, "spins and grad_logz are required");
+  if (tnvan_status s = check_device({spins, grad, dh, dJ, dbeta})) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (net->precision == TNVAN_FP64) return run_backward<double>(net, spins, grad, dh, dJ, dbeta, st);
   return run_backward<float>(net, spins, grad, dh, dJ, dbeta, st);
@@ -1413,6 +1425,9 @@ tnvan_status step_entry(tnvan_net *net, const int64_t *n_samples, float lr, doub
   if (tnvan_status s = set_batch(net, n_samples)) return s;
   if (adj && (!adj->dh || !adj->dJ || !adj->dbeta || (net->B_total > 0 && !adj->grad)))
     return set_err(TNVAN_E_INVALID, "grad_logz, dh, dJ and dbeta are required");
+  if (tnvan_status s = check_device({stats, spins_out})) return s;
+  if (adj)
+    if (tnvan_status s = check_device({adj->grad, adj->dh, adj->dJ, adj->dbeta})) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   auto eager = [&](hipStream_t s2) {
     return net->precision == TNVAN_FP64 ? run_step<double>(net, lr, stats, spins_out, s2, adj)
@@ -1495,6 +1510,7 @@ tnvan_status tnvan_logz_and_backward(tnvan_net *net, const int64_t *n_samples,
   if (!dh || !dJ || !dbeta) return set_err(TNVAN_E_INVALID, "dh, dJ and dbeta are required");
   if (net->B_total > 0 && (!grad || !logz || (!spins && net->spin_total > 0)))
     return set_err(TNVAN_E_INVALID, "spins, grad_logz and logz are required");
+  if (tnvan_status s = check_device({spins, grad, logz, dh, dJ, dbeta})) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (logz_with_adjoint(net)) return run_backward<float>(net, spins, grad, dh, dJ, dbeta, st, logz);
   if (net->precision == TNVAN_FP64) {
