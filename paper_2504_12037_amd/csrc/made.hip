@@ -616,7 +616,7 @@ __global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
   // read them without a memory round trip per batch of terms
   __shared__ int32_t s_ab[kFreeStage];
   __shared__ double s_J[kFreeStage], s_h[128];
-  const int nst = bits ? min(D.n_ww, kFreeStage) : 0;
+  const int nst = min(D.n_ww, kFreeStage);
   for (int k = tid; k < nst; k += blockDim.x) {
     s_ab[k] = wa[k] | (wb[k] << 16);
     s_J[k] = wJ[k];
@@ -645,8 +645,17 @@ __global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
 #pragma unroll 4
       for (int k = part; k < mi.n; k += kFreeLanes) e1 -= sb.sigma(k) > 0.f ? s_h[k] : -s_h[k];
     } else {
+      // width sets beyond the mask: spin bytes, the staged couplings first
+      // (the same terms in the same order as above)
       const int8_t *s = a.spins + mi.spin_off + b * mi.n;
-      for (int k = part; k < D.n_ww; k += kFreeLanes) e1 -= wJ[k] * (double)s[wa[k]] * (double)s[wb[k]];
+#pragma unroll 4
+      for (int k = part; k < nst; k += kFreeLanes) {
+        const int ab = s_ab[k];
+        e1 -= s_J[k] * (double)s[ab & 0xffff] * (double)s[ab >> 16];
+      }
+      for (int k = nst + part; k < D.n_ww; k += kFreeLanes)
+        e1 -= wJ[k] * (double)s[wa[k]] * (double)s[wb[k]];
+#pragma unroll 4
       for (int k = part; k < mi.n; k += kFreeLanes) e1 -= hW[k] * (double)s[k];
     }
 #pragma unroll
