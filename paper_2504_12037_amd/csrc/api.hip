@@ -314,6 +314,15 @@ tnvan_status ensure_tiles(tnvan_net *net, TileCache &tc, int S, bool bwd) {
 // workgroup, hence two lists.
 tnvan_status ensure_chain_tasks(tnvan_net *net) {
   if (net->ckey == net->nkey) return TNVAN_OK;
+  // two sample groups per forward wave on chains of 1-2 tiles (the groups
+  // hide each other's latency) when that still leaves a wave per SIMD;
+  // small batches take one group per wave and twice the waves
+  {
+    int64_t waves2 = 0;
+    for (int q = 0; q < net->n_inst; ++q)
+      if (net->use_chain[q]) waves2 += net->P.cinst[q].n_chains * ((net->nkey[q] + 31) / 32);
+    net->sg = waves2 >= 1024 ? 2 : 1;
+  }
   std::vector<int32_t> clist;
   std::vector<int64_t> coff(net->n_inst, 0);
   int64_t ctot = 0;
