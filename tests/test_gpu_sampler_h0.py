@@ -127,3 +127,33 @@ def test_one_layer_training_step_parity(prec, nw):
     M1, M2, M0 = OM.masks(nw, 0)
     mask = OM.pack(M1, np.ones(0), M2, np.ones(nw), M0)
     assert np.all(g_gpu[mask == 0] == 0)
+
+
+def test_one_layer_training_step_graph_replay():
+    # the one-layer step (columns of W0, sampler, stored conditionals, rows,
+    # sums, Adam) recorded once and replayed, against an identical eager net,
+    # with eager work on another batch shape between replays
+    from paper_2504_12037_amd import Net
+    insts = [_chain_instance(200, 61), _chain_instance(90, 62)]
+    Bs = [300, 129]
+    nets = [Net(insts, precision="fp32", seed=5),
+            Net(insts, precision="fp32", seed=5, flags=Net.FLAG_GRAPH)]
+    for net in nets:
+        for k, inst in enumerate(insts):
+            net.set_params(k, torch.from_numpy(_theta(inst.n_width, 70 + k)))
+    stats = [torch.empty(2, 4, dtype=torch.float64, device="cuda") for _ in nets]
+    spins = [torch.empty(sum(b * i.n_width for b, i in zip(Bs, insts)), dtype=torch.int8,
+                         device="cuda") for _ in nets]
+    for it in range(6):
+        print(f"\n[graph-h0] iteration {it}", flush=True)
+        for net, st, sp in zip(nets, stats, spins):
+            net.free_energy_step(Bs, 1e-2, stats=st, spins_out=sp)
+        torch.cuda.synchronize()
+        assert torch.equal(stats[0], stats[1]), it
+        assert torch.equal(spins[0], spins[1]), it
+        if it == 2:
+            sp_o, _ = nets[1].sample([17, 5])
+            torch.cuda.synchronize()
+            assert sp_o.numel() == 17 * 200 + 5 * 90
+    for k in range(len(insts)):
+        assert torch.equal(nets[0].get_params(k), nets[1].get_params(k))
