@@ -320,18 +320,45 @@ __global__ __launch_bounds__(256) void sample_h0_kernel(SampleArgs<real> a) {
       const int c = 4 * mb + c4;
       if (c >= n_chunks) break;
       if (c + 1 < n_chunks) fetch(c + 1);
-      const float *cb = buf[c & 1];
-      for (int g = 0; g < kH0Chunk; g += 4) {
+      const float *cb = buf[c & 1] + lane;
+      // the columns of a group of four positions are read from LDS while
+      // the previous group is drawn (two register sets used in turn)
+      float wa[4][NM], wb[4][NM];
+      (void)wb;
+      auto rows = [&](int g, float (&w)[4][NM]) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int m = 0; m < NM; ++m) w[r][m] = cb[(g + r) * RS + 64 * m];
+      };
+      auto group = [&](int g, const float (&w)[4][NM]) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int il = kH0Chunk * c4 + g + r;
           if (64 * mb + il < n) {
             const float d = z[mb] > thr ? 1.f : -1.f;
             const real si = (real)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(d), il));
-            const float *row = cb + (g + r) * RS + lane;
 #pragma unroll
-            for (int m = 0; m < NM; ++m) z[m] += (real)row[64 * m] * si;
+            for (int m = 0; m < NM; ++m) z[m] += (real)w[r][m] * si;
           }
+        }
+      };
+      static_assert(kH0Chunk == 16, "four groups of four positions per chunk");
+      if constexpr (NM <= 4) {
+        rows(0, wa);
+        rows(4, wb);
+        group(0, wa);
+        rows(8, wa);
+        group(4, wb);
+        rows(12, wb);
+        group(8, wa);
+        group(12, wb);
+      } else {
+        // wide width sets: one register set (two would spill)
+#pragma unroll 1
+        for (int g = 0; g < kH0Chunk; g += 4) {
+          rows(g, wa);
+          group(g, wa);
         }
       }
       if (c + 1 < n_chunks) put(c + 1);
