@@ -14,12 +14,20 @@ with beta1 = 0.9, beta2 = 0.999, eps = 1e-8 (the paper says gradient
 descent, Algorithm 1 step (d)).
 
 Functions and what pins them (tests/test_oracle_objective.py):
-  free_energy_terms   Eq. 9 written out; pinned by the variational bound
-                      F_q >= F (exact enumeration, Eq. 5)
-  exact_fq_and_grad   enumeration of all 2^|W| width-set states; the exact
-                      gradient pinned by central finite differences of the
-                      exact F_q, and the sampled REINFORCE estimator is
-                      checked against it statistically
+  free_energy_terms   Eq. 9 written out; pinned at beta = 0.5 and 2 by
+                      Eq. 5's equality case (q = the W-marginal of p from
+                      a full enumeration of Eq. 1 makes every f_b equal
+                      -ln Z / beta, its standard error zero, and Etilde
+                      equal -(ln p_W + ln Z) / beta), by the KL identity
+                      beta (F_q - F) = KL(q | p_W) for a network q, and its
+                      standard error by the spread of F_q over 400
+                      independent batches
+  exact_fq_and_grad   enumeration of all 2^|W| width-set states; pinned by
+                      the KL identity of Eq. 5 at beta = 0.5 and 2 and the
+                      bound F_q >= F; the exact gradient by central finite
+                      differences of the exact F_q, and the sampled
+                      REINFORCE estimator is checked against it
+                      statistically (beta = 0.5, 1, 2)
   adam_step           pinned by the closed form of the first step
                       (update = lr * g / (|g| + eps)) and a hand-computed
                       second step

@@ -1,9 +1,13 @@
 """Pins of the oracle's objective, gradient estimator, optimiser and random
-number generator (Sec. 3 Eqs. 5, 9, 10; Algorithm 1)."""
+number generator (Sec. 3 Eqs. 5, 9, 10; Algorithm 1).
+
+Every pin of the objective runs at beta != 1 as well: at beta = 1 the
+entropy term ln q / beta of Eq. 9 cannot be told from ln q * beta."""
 
 import os
 
 import numpy as np
+import pytest
 
 import synthetic as S
 from oracle import ising as I
@@ -49,25 +53,30 @@ def test_adam_first_steps_by_hand():
     np.testing.assert_allclose(th2, want, atol=1e-14)
 
 
-def _c1(H=16, seed=0, noise=0.0):
-    inst = S.c1_small_lattice(hidden=H)
+BETAS = (0.5, 1.0, 2.0)
+
+
+def _c1(H=16, seed=0, noise=0.0, beta=1.0):
+    inst = S.c1_small_lattice(hidden=H).with_beta(beta)
     th = S.made_init(4, H, seed).astype(np.float64)
     if noise:
         th = th + noise * np.random.default_rng(seed).standard_normal(th.shape)
     return inst, th
 
 
-def test_variational_bound():
+@pytest.mark.parametrize("beta", BETAS)
+def test_variational_bound(beta):
     # Eq. 5: F_q >= F for every q; equality needs q = p
     for seed, noise in [(0, 0.0), (1, 1.0), (2, 3.0)]:
-        inst, th = _c1(seed=seed, noise=noise)
+        inst, th = _c1(seed=seed, noise=noise, beta=beta)
         Fq, _ = O.exact_fq_and_grad(inst, th, 16)
         F = O.exact_free_energy(inst)
         assert Fq >= F - 1e-12
 
 
-def test_exact_gradient_finite_differences():
-    inst, th = _c1(noise=0.5)
+@pytest.mark.parametrize("beta", BETAS)
+def test_exact_gradient_finite_differences(beta):
+    inst, th = _c1(noise=0.5, beta=beta)
     _, g = O.exact_fq_and_grad(inst, th, 16)
     eps = 1e-6
     rng = np.random.default_rng(0)
@@ -80,8 +89,9 @@ def test_exact_gradient_finite_differences():
         assert abs(fd - g[k]) < 1e-7
 
 
-def test_reinforce_estimator_is_unbiased():
-    inst, th = _c1(noise=0.7)
+@pytest.mark.parametrize("beta", BETAS)
+def test_reinforce_estimator_is_unbiased(beta):
+    inst, th = _c1(noise=0.7, beta=beta)
     _, gex = O.exact_fq_and_grad(inst, th, 16)
     reps, B = 400, 256
     acc = []
@@ -99,8 +109,9 @@ def test_reinforce_estimator_is_unbiased():
     assert np.all(np.abs(mean - gex) <= 4 * se + 2.0 / B * np.abs(gex) + 1e-12)
 
 
-def test_training_reduces_exact_fq_and_respects_bound():
-    inst, th = _c1()
+@pytest.mark.parametrize("beta", (0.5, 2.0))
+def test_training_reduces_exact_fq_and_respects_bound(beta):
+    inst, th = _c1(beta=beta)
     F = O.exact_free_energy(inst)
     Fq0, _ = O.exact_fq_and_grad(inst, th, 16)
     th1, stats = O.train(inst, th, 16, steps=60, B=256, lr=1e-2, seed=1)
@@ -130,3 +141,116 @@ def test_observables_exact_under_full_enumeration_with_uniform_q():
     np.testing.assert_allclose(m, m_ex, atol=1e-12)
     np.testing.assert_allclose(c, c_ex, atol=1e-12)
     assert 1.0 <= ess <= sw.shape[0]
+
+
+# --------------------------------------------------------------------------
+# Eq. 5 written against the full Boltzmann distribution (Eq. 1), at beta != 1
+
+def _w_marginal(inst):
+    """ln p_W(s) of every width-set configuration (the order of
+    objective.all_width_states: bit i of the index set <=> s_{W_i} = -1) and
+    ln Z, by enumerating all 2^n states of Eq. 1 and summing out R."""
+    n, nw = int(inst.n), int(inst.n_width)
+    W = np.asarray(inst.width_set, np.int64)
+    lw_parts, idx_parts = [], []
+    step = 1 << 16
+    for y0 in range(0, 1 << n, step):
+        y = np.arange(y0, min(1 << n, y0 + step), dtype=np.int64)[:, None]
+        full = (1 - 2 * ((y >> np.arange(n)[None, :]) & 1)).astype(np.float64)
+        lw_parts.append(-inst.beta * I.energy(inst, full))
+        idx_parts.append(((full[:, W] < 0).astype(np.int64) << np.arange(nw)).sum(1))
+    lw = np.concatenate(lw_parts)
+    idx = np.concatenate(idx_parts)
+    m = lw.max()
+    acc = np.zeros(1 << nw)
+    np.add.at(acc, idx, np.exp(lw - m))
+    lnZ = float(np.log(acc.sum()) + m)
+    return np.log(acc) + m - lnZ, lnZ
+
+
+def _eq5_cases():
+    out = []
+    for beta in (0.5, 2.0):
+        out.append(("c1", S.c1_small_lattice(hidden=16).with_beta(beta)))
+        # an N = 20 random 3-regular +-J graph with Gaussian fields
+        out.append(("rrg20", S.c4_small_copies(limit=3)[1].with_beta(beta)))
+    return out
+
+
+@pytest.mark.parametrize("name,inst", _eq5_cases(), ids=lambda v: v if isinstance(v, str) else v.name)
+def test_eq5_equality_when_q_is_the_exact_w_marginal(name, inst):
+    # With q(s) = p_W(s) = exp(-beta Etilde(s)) / Z, Eq. 5 makes the KL
+    # divergence zero, so every per-sample f_b of Eq. 9 equals F = -ln Z /
+    # beta exactly (zero variance), and Etilde(s) = -(ln p_W(s) + ln Z)/beta
+    # sample by sample; all of it from the full enumeration, none from the
+    # E_1 / E_2 split or the elimination that free_energy_terms is fed
+    ln_pw, lnZ = _w_marginal(inst)
+    beta = float(inst.beta)
+    s = O.all_width_states(inst.n_width)
+    lz = I.logz_r_elimination(inst, s)
+    f, st = O.free_energy_terms(inst, s, ln_pw, lz)
+    F = -lnZ / beta
+    tol = 1e-11 * max(1.0, abs(F))
+    assert np.abs(f - F).max() <= tol
+    assert abs(st[0] - F) <= tol
+    assert abs(st[1]) <= tol
+    et = -(ln_pw + lnZ) / beta
+    assert abs(st[2] - et.mean()) <= tol
+    assert abs(st[3] - ln_pw.mean() / beta) <= tol
+    # and the slice sum (Eq. 3) reproduces ln Z from the same split
+    assert abs(O.exact_free_energy(inst) - F) <= tol
+
+
+@pytest.mark.parametrize("beta", (0.5, 2.0))
+@pytest.mark.parametrize("which", ("c1", "rrg20"))
+def test_eq5_kl_identity_for_a_network_q(beta, which):
+    # Eq. 5 for any q: beta (F_q - F) = KL(q | p_W), with p_W from the full
+    # enumeration; F_q both from exact_fq_and_grad and from the q-weighted
+    # per-sample f of free_energy_terms over every width-set configuration
+    if which == "c1":
+        inst = S.c1_small_lattice(hidden=16).with_beta(beta)
+        H = 16
+    else:
+        inst = S.c4_small_copies(limit=3)[1].with_beta(beta)
+        H = 2 * inst.n_width
+    nw = inst.n_width
+    th = S.made_init(nw, H, 11).astype(np.float64)
+    th += 0.8 * np.random.default_rng(11).standard_normal(th.shape)
+    ln_pw, lnZ = _w_marginal(inst)
+    s = O.all_width_states(nw)
+    lq = M.logq(th, s, nw, H)
+    q = np.exp(lq)
+    kl = float(np.sum(q * (lq - ln_pw)))
+    F = -lnZ / beta
+    Fq, _ = O.exact_fq_and_grad(inst, th, H)
+    assert kl > 1e-3
+    assert abs(beta * (Fq - F) - kl) <= 1e-10 * max(1.0, abs(beta * F))
+    f, _ = O.free_energy_terms(inst, s, lq, I.logz_r_elimination(inst, s))
+    assert abs(float(q @ f) - Fq) <= 1e-10 * max(1.0, abs(F))
+
+
+def test_stderr_matches_the_spread_of_batch_means():
+    # the standard error free_energy_terms reports is the spread of F_q over
+    # independent batches: 400 batches of 64 samples of a network q (C1 at
+    # beta = 2); the root mean square of the reported standard errors and
+    # the standard deviation of the 400 batch means agree within the
+    # sampling error of a 400-point spread (about 3.5%, 4 sigma = 15%), and
+    # the mean of the batch means is the exact F_q within 4 standard errors
+    beta, B, reps = 2.0, 64, 400
+    inst, th = _c1(noise=0.7, beta=beta)
+    Fq_exact, _ = O.exact_fq_and_grad(inst, th, 16)
+    s_all = O.all_width_states(4)
+    lz_all = I.logz_r_elimination(inst, s_all)
+    means, ses = [], []
+    for r in range(reps):
+        u = P.sampler_uniforms(314, r, 0, B, 4)
+        s, lq, _ = M.sample(th, u, 4, 16)
+        k = ((s < 0).astype(np.int64) << np.arange(4)).sum(1)
+        _, st = O.free_energy_terms(inst, s, lq, lz_all[k])
+        means.append(st[0])
+        ses.append(st[1])
+    means = np.asarray(means)
+    spread = float(means.std(ddof=1))
+    rms_se = float(np.sqrt(np.mean(np.square(ses))))
+    assert 0.85 <= rms_se / spread <= 1.15
+    assert abs(means.mean() - Fq_exact) <= 4 * spread / np.sqrt(reps)
