@@ -52,6 +52,16 @@ class Net:
         self.nw = [int(len(i.width_set)) for i in self.instances]
         self.n = [int(i.n) for i in self.instances]
         self.ne = [int(len(i.edges)) for i in self.instances]
+        # the couplings, fields and inverse temperatures the tables were
+        # compiled from (LogZ checks its arguments against them)
+        import numpy as np
+        self.couplings = (
+            torch.from_numpy(np.concatenate([np.asarray(i.J, np.float64).reshape(-1)
+                                             for i in self.instances])),
+            torch.from_numpy(np.concatenate([np.zeros(i.n) if i.h is None else
+                                             np.asarray(i.h, np.float64).reshape(-1)
+                                             for i in self.instances])),
+            torch.tensor([float(i.beta) for i in self.instances], dtype=torch.float64))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -234,15 +244,30 @@ class Net:
 class LogZ(torch.autograd.Function):
     """logZ_R(s_W) per sample as a differentiable function of (J, h, beta).
 
-    ``net`` must have been built from the same couplings, fields and beta as
-    the tensors passed in (they are used for their gradients only); the
-    backward runs the library's adjoint.
+        logz = LogZ.apply(J, h, beta, spins, net, n_samples)
+
+    J [sum E], h [sum N] and beta [n_inst] are the couplings, fields and
+    inverse temperatures of the net's instances, concatenated in instance
+    order.  The net's tables are compiled from them at build, so the values
+    passed must be the ones the net was built with, rounded to the dtype
+    passed (else ValueError: build a new net for new couplings); they take
+    part for their gradients.  The
+    forward is tnvan_logz_batch, the backward tnvan_logz_backward with the
+    incoming gradient as g_b, returning (dJ, dh, dbeta) = (beta sum g <x x>,
+    beta sum g <r>, -sum g <E_2>) (Eqs. 3-4 differentiated).
     """
 
     @staticmethod
     def forward(ctx, J, h, beta, spins, net: Net, n_samples):
+        for name, got, built in zip(("J", "h", "beta"), (J, h, beta), net.couplings):
+            # compared in the caller's dtype: the built values rounded to it
+            g = got.detach().to("cpu").reshape(-1)
+            if g.shape != built.shape or not torch.equal(g, built.to(g.dtype)):
+                raise ValueError(f"LogZ: {name} differs from the values the net was built "
+                                 "with; build a net for the new couplings")
         ctx.net = net
         ctx.n_samples = n_samples
+        ctx.meta = [(t.dtype, t.device, t.shape) for t in (J, h, beta)]
         ctx.save_for_backward(spins)
         return net.logz(spins, n_samples).clone()
 
@@ -250,4 +275,6 @@ class LogZ(torch.autograd.Function):
     def backward(ctx, g):
         (spins,) = ctx.saved_tensors
         dh, dJ, db = ctx.net.backward(spins, g.contiguous(), ctx.n_samples)
-        return dJ, dh, db, None, None, None
+        out = [t.to(dtype=dt, device=dev).reshape(shape)
+               for t, (dt, dev, shape) in zip((dJ, dh, db), ctx.meta)]
+        return out[0], out[1], out[2], None, None, None
