@@ -178,12 +178,38 @@ struct tnvan_net {
       chain_list, cpart;
   int n_tasks = 0, n_btasks = 0, n_chain_insts = 0;
   std::vector<int64_t> ckey;
+  // streams this net's calls have queued work on since the last wait; the
+  // per-call tables are re-uploaded with synchronous copies on the null
+  // stream, which does not order with non-blocking streams, so an upload
+  // first waits for these
+  std::vector<hipStream_t> call_streams;
   int rs() const { return precision == TNVAN_FP64 ? 8 : 4; }
 };
 
 namespace {
 
 int ilog2(int x) { int r = 0; while ((1 << r) < x) ++r; return r; }
+
+// Entry of a device call on `stream`: remember the stream, so that a later
+// table upload waits for the work queued on it.
+void note_stream(tnvan_net *net, void *stream) {
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (std::find(net->call_streams.begin(), net->call_streams.end(), st) ==
+      net->call_streams.end())
+    net->call_streams.push_back(st);
+}
+
+// Before overwriting a per-call table that kernels queued earlier (in this
+// call or in earlier ones) may still read: wait for every stream the net has
+// used.  Not while recording a graph (nothing is uploaded then: the eager
+// step before the recording made every table current).
+tnvan_status quiesce(tnvan_net *net) {
+  if (net->capturing) return TNVAN_OK;
+  for (hipStream_t st : net->call_streams) HIPCHK(hipStreamSynchronize(st));
+  if (net->call_streams.size() > 1) net->call_streams.erase(net->call_streams.begin(),
+                                                            net->call_streams.end() - 1);
+  return TNVAN_OK;
+}
 
 // Events around one launch of a profiled kernel (no-op unless profiling).
 struct ProfScope {
@@ -250,6 +276,7 @@ tnvan_status set_batch(tnvan_net *net, const int64_t *n_samples) {
   for (auto b : key)
     if (b < 0 || b > ((int64_t)1 << 31)) return set_err(TNVAN_E_INVALID, "bad sample count");
   if (key == net->nkey) return TNVAN_OK;
+  if (tnvan_status s = quiesce(net)) return s;
   net->sample_off.assign(net->n_inst, 0);
   net->spin_off.assign(net->n_inst, 0);
   int64_t so = 0, sp = 0;
@@ -280,6 +307,7 @@ tnvan_status set_batch(tnvan_net *net, const int64_t *n_samples) {
 
 tnvan_status ensure_tiles(tnvan_net *net, TileCache &tc, int S, bool bwd) {
   if (tc.key == net->nkey && tc.S == S) return TNVAN_OK;
+  if (tnvan_status s = quiesce(net)) return s;
   std::vector<int32_t> ti, ts, first(net->n_inst), cnt(net->n_inst);
   std::vector<int64_t> poff(net->n_inst);
   int64_t ptot = 0;
@@ -314,6 +342,7 @@ tnvan_status ensure_tiles(tnvan_net *net, TileCache &tc, int S, bool bwd) {
 // workgroup, hence two lists.
 tnvan_status ensure_chain_tasks(tnvan_net *net) {
   if (net->ckey == net->nkey) return TNVAN_OK;
+  if (tnvan_status s = quiesce(net)) return s;
   // two sample groups per forward wave on chains of 1-2 tiles (the groups
   // hide each other's latency) when that still leaves a wave per SIMD;
   // small batches take one group per wave and twice the waves
@@ -636,6 +665,7 @@ tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *gra
 
 tnvan_status ensure_sample_blocks(tnvan_net *net) {
   if (net->skey == net->nkey) return TNVAN_OK;
+  if (tnvan_status s = quiesce(net)) return s;
   {
     // matrix-core sampler: one wave per 16 samples
     std::vector<int32_t> ti, ts;
@@ -1322,6 +1352,7 @@ tnvan_status tnvan_get_state(tnvan_net *net, int32_t inst, int32_t which, float 
 tnvan_status tnvan_sample(tnvan_net *net, const int64_t *n_samples, const float *uniforms,
                           int8_t *spins, void *logq, void *stream) {
   if (tnvan_status s = check_net(net)) return s;
+  note_stream(net, stream);
   if (tnvan_status s = set_batch(net, n_samples)) return s;
   if (net->B_total == 0) return TNVAN_OK;
   if (!spins || !logq) return set_err(TNVAN_E_INVALID, "spins and logq are required");
@@ -1334,6 +1365,7 @@ tnvan_status tnvan_sample(tnvan_net *net, const int64_t *n_samples, const float 
 tnvan_status tnvan_logz_batch(tnvan_net *net, const int64_t *n_samples, const int8_t *spins,
                               double *logz, void *stream) {
   if (tnvan_status s = check_net(net)) return s;
+  note_stream(net, stream);
   if (tnvan_status s = set_batch(net, n_samples)) return s;
   if (net->B_total == 0) return TNVAN_OK;
   if (!logz || (!spins && net->spin_total > 0)) return set_err(TNVAN_E_INVALID, "spins and logz are required");
@@ -1360,6 +1392,7 @@ tnvan_status tnvan_exact_free_energy(tnvan_net *net, int32_t inst, double *out, 
   const int64_t passes = total / chunk;
   std::vector<int64_t> key(net->n_inst, 0);
   key[inst] = chunk;
+  note_stream(net, stream);
   if (tnvan_status s = set_batch(net, key.data())) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   HIPCHK(net->w_xspins.ensure((size_t)std::max<int64_t>(1, chunk * D.nw)));
@@ -1398,6 +1431,7 @@ tnvan_status tnvan_observables(tnvan_net *net, const int64_t *n_samples, const i
   if (tnvan_status s = check_device({spins, logq, mag, corr, ess})) return s;
   for (auto &D : net->P.insts)
     if (!(D.beta > 0)) return set_err(TNVAN_E_INVALID, "observables need beta > 0");
+  note_stream(net, stream);
   if (tnvan_status s = set_batch(net, n_samples)) return s;
   if (!mag || !corr || !ess) return set_err(TNVAN_E_INVALID, "mag, corr and ess are required");
   if (net->B_total > 0 && (!logq || (!spins && net->spin_total > 0)))
@@ -1411,6 +1445,7 @@ tnvan_status tnvan_logz_backward(tnvan_net *net, const int64_t *n_samples, const
                                  const double *grad, double *dh, double *dJ, double *dbeta,
                                  void *stream) {
   if (tnvan_status s = check_net(net)) return s;
+  note_stream(net, stream);
   if (tnvan_status s = set_batch(net, n_samples)) return s;
   if (!dh || !dJ || !dbeta) return set_err(TNVAN_E_INVALID, "dh, dJ and dbeta are required");
   if (net->B_total > 0 && (!grad || (!spins && net->spin_total > 0)))
@@ -1431,6 +1466,7 @@ tnvan_status step_entry(tnvan_net *net, const int64_t *n_samples, float lr, doub
   if (!stats) return set_err(TNVAN_E_INVALID, "stats is required");
   for (auto &D : net->P.insts)
     if (!(D.beta > 0)) return set_err(TNVAN_E_INVALID, "free_energy_step needs beta > 0");
+  note_stream(net, stream);
   if (tnvan_status s = set_batch(net, n_samples)) return s;
   if (adj && (!adj->dh || !adj->dJ || !adj->dbeta || (net->B_total > 0 && !adj->grad)))
     return set_err(TNVAN_E_INVALID, "grad_logz, dh, dJ and dbeta are required");
@@ -1515,6 +1551,7 @@ tnvan_status tnvan_logz_and_backward(tnvan_net *net, const int64_t *n_samples,
                                      const int8_t *spins, const double *grad, double *logz,
                                      double *dh, double *dJ, double *dbeta, void *stream) {
   if (tnvan_status s = check_net(net)) return s;
+  note_stream(net, stream);
   if (tnvan_status s = set_batch(net, n_samples)) return s;
   if (!dh || !dJ || !dbeta) return set_err(TNVAN_E_INVALID, "dh, dJ and dbeta are required");
   if (net->B_total > 0 && (!grad || !logz || (!spins && net->spin_total > 0)))

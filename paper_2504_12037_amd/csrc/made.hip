@@ -583,6 +583,12 @@ __global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
   const int q = blockIdx.y, tid = threadIdx.x;
   const InstDesc D = a.inst[q];
   const MadeInst mi = a.mi[q];
+  // an instance without samples this step: a zero statistics row, and its
+  // step counter stays (its parameters and moments do not move either)
+  if (mi.B <= 0) {
+    if (blockIdx.x == 0 && tid < 4 && a.stats) a.stats[4 * q + tid] = 0.0;
+    return;
+  }
   const double beta = D.beta;
   const int32_t *wa = a.ww_a + D.ww_off, *wb = a.ww_b + D.ww_off;
   const double *wJ = a.ww_J + D.ww_off, *hW = a.hW + a.hw_off[q];

@@ -297,3 +297,51 @@ def test_reinforce_gradient_full_width_split_products():
     err = np.abs(g_gpu - g).max() / np.abs(g).max()
     print(f"[split-grad] max |g_gpu - g| / max |g| = {err:.2e}", flush=True)
     assert err <= 1e-4
+
+
+@pytest.mark.parametrize("prec,split", [("fp32", True), ("fp32", False), ("fp64", False)])
+def test_training_with_an_instance_left_empty(prec, split):
+    # an instance with no samples in some steps keeps its parameters, Adam
+    # moments and step counter, and gets a zero statistics row; its next real
+    # step is the oracle's next Adam step (bias corrections of step t + 1)
+    from paper_2504_12037_amd import Net
+    insts = [S.c1_small_lattice(16),
+             S.lattice_column_split(S.lattice_2d(12, seed=6), [5, 9], hidden=32)]
+    seed, lr = 43, 1e-2
+    net = _net(insts, prec, seed=seed, flags=Net.FLAG_SPLIT_BF16 if split else 0)
+    ora = []
+    for k, inst in enumerate(insts):
+        th = _theta(inst.n_width, inst.hidden, 90 + k, 0.2)
+        net.set_params(k, torch.from_numpy(th))
+        z = np.zeros(th.shape, np.float64)
+        ora.append([th.astype(np.float64), z, z.copy(), 0])
+    stats = torch.empty(len(insts), 4, dtype=torch.float64, device="cuda")
+    for it, Bs in enumerate([(256, 128), (256, 0), (192, 0), (256, 160)]):
+        print(f"\n[train-empty] prec={prec} split={split} iteration {it} B={Bs}", flush=True)
+        spins = torch.empty(max(1, sum(b * i.n_width for b, i in zip(Bs, insts))),
+                            dtype=torch.int8, device="cuda")
+        stats.fill_(np.nan)
+        net.free_energy_step(list(Bs), lr, stats=stats, spins_out=spins)
+        torch.cuda.synchronize()
+        sp_all, st_all = spins.cpu().numpy(), stats.cpu().numpy()
+        off = 0
+        for k, (inst, b) in enumerate(zip(insts, Bs)):
+            n, H = inst.n_width, inst.hidden
+            th, m, v, t = ora[k]
+            if b == 0:
+                assert np.all(st_all[k] == 0.0), st_all[k]
+            else:
+                sp = sp_all[off:off + b * n].reshape(b, n)
+                off += b * n
+                u = OP.sampler_uniforms(seed, t, k, b, n)
+                _, lq = _check_spins(th, u, n, H, sp)
+                lz = (OI.logz_r_bruteforce if len(inst.order) <= 16
+                      else OI.logz_r_elimination)(inst, sp)
+                f, st = OO.free_energy_terms(inst, sp, lq, lz)
+                np.testing.assert_allclose(st_all[k], st, atol=2e-4, rtol=2e-5)
+                g = OM.logq_backward(th, sp, OO.reinforce_weights(f), n, H)
+                th, m, v = OO.adam_step(th, g, m, v, t + 1, lr)
+                ora[k] = [th, m, v, t + 1]
+            d = np.abs(net.get_params(k).cpu().numpy() - th).max()
+            dm = np.abs(net.get_state(k, 2).cpu().numpy() - m).max()
+            assert d <= 1e-4 and dm <= 1e-5, (it, k, d, dm)

@@ -297,3 +297,37 @@ def test_logz_autograd_function(prec):
         LogZ.apply(J.detach() * 1.01, h, beta, flat, net, Bs)
     with pytest.raises(ValueError):
         LogZ.apply(J, h, beta.detach() + 0.1, flat, net, Bs)
+
+
+def test_batch_shapes_alternating_on_a_side_stream():
+    # calls that change the batch shape re-lay the net's per-call tables;
+    # on a non-blocking stream, with no synchronisation between the calls,
+    # every result must still be that of its own shape (the tables of one
+    # call are not overwritten while its kernels run)
+    insts = [S.c2_lattice(1.0), S.c1_small_lattice()]
+    shapes = [[4096, 700], [1000, 64], [0, 333], [8192, 1]]
+    spins = [[S.uniform_spins(b, i.n_width, 500 + 7 * k + j) for j, (b, i) in
+              enumerate(zip(Bs, insts))] for k, Bs in enumerate(shapes)]
+    flat = [_dev(np.concatenate([s.reshape(-1) for s in sp])) for sp in spins]
+    gs = [_dev(np.full(sum(Bs), 0.01)) for Bs in shapes]
+    torch.cuda.synchronize()
+    for prec in ("fp32", "fp64"):
+        print(f"\n[side-stream] prec={prec}", flush=True)
+        net = _net(insts, prec)
+        side = torch.cuda.Stream()
+        outs = []
+        with torch.cuda.stream(side):
+            for rep in range(3):
+                for k, Bs in enumerate(shapes):
+                    outs.append((k, net.logz(flat[k], Bs)))
+                    outs.append((k, net.logz_and_backward(flat[k], gs[k], Bs)[0]))
+        side.synchronize()
+        for k, lz in outs:
+            got = lz.cpu().numpy()
+            off = 0
+            for inst, b, s in zip(insts, shapes[k], spins[k]):
+                idx = np.arange(0, b, max(1, b // 16))
+                if b:
+                    want = _oracle_logz(inst, s[idx])
+                    assert np.abs(got[off + idx] - want).max() / inst.n <= TOL[prec], (prec, k)
+                off += b
