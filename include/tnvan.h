@@ -191,6 +191,33 @@ tnvan_status tnvan_logz_backward(tnvan_net *net, const int64_t *n_samples,
                                  double *dh, double *dJ, double *dbeta,
                                  void *stream);
 
+/* Allocation-free variant of tnvan_logz_batch, for callers that cannot
+ * allocate device memory: code recorded into a HIP graph, serving loops and
+ * harnesses that forbid hipMalloc.  Same arguments and results as
+ * tnvan_logz_batch (bit for bit: the same kernels and arithmetic), but every
+ * per-call table and workspace lives in one file-scope device array of
+ * TNVAN_NOALLOC_SCRATCH_BYTES (32 MiB) per GPU, which the library keeps
+ * until the process ends; the call makes no allocation, no host-to-device
+ * copy and no synchronisation, and its tables are written by a kernel from
+ * the sample counts passed by value.
+ *  - Needs a net whose every instance runs the register-resident chain
+ *    kernels (FP32 or BF16 nets of dense chains of at most 64 states, e.g.
+ *    lattice strips; TNVAN_E_STATE otherwise) and at most
+ *    TNVAN_NOALLOC_MAX_INST instances (TNVAN_E_INVALID).
+ *  - A batch whose workspace exceeds the array is rejected with
+ *    TNVAN_E_INVALID before any work is queued.  It needs about
+ *    (4 |R| + 8 ceil(|R| / 16) + 8 chains) bytes per sample: the 16x16
+ *    lattice with two width-set columns fits 3 x 8192 samples.
+ *  - Every call on a GPU shares that GPU's array and overwrites it: two
+ *    calls whose work overlaps on one GPU (on different streams, or from
+ *    different host threads, on any nets) race and give wrong results.
+ *    Calls queued on one stream are ordered and safe.
+ *  - The net must be used on the device it was built on (TNVAN_E_STATE). */
+#define TNVAN_NOALLOC_SCRATCH_BYTES (32u << 20)
+#define TNVAN_NOALLOC_MAX_INST 32
+tnvan_status tnvan_logz_batch_noalloc(tnvan_net *net, const int64_t *n_samples,
+                                      const int8_t *spins, double *logz, void *stream);
+
 /* tnvan_logz_batch and tnvan_logz_backward of the same spins in one call,
  * with the same arguments and results (logz as tnvan_logz_batch writes it).
  * On FP32 nets whose every instance runs the register-resident chain

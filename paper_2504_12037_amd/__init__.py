@@ -155,6 +155,18 @@ class Net:
                                                _stream()))
         return out[:sum(counts)]
 
+    def logz_noalloc(self, spins: torch.Tensor, n_samples, out: torch.Tensor):
+        """tnvan_logz_batch_noalloc: logz into ``out`` (a float64 device
+        tensor of at least sum(n_samples) entries) with the library's static
+        scratch; the call itself allocates nothing."""
+        arr, counts = self._counts(n_samples)
+        assert spins.is_cuda and spins.dtype == torch.int8 and spins.is_contiguous()
+        assert spins.numel() >= sum(b * w for b, w in zip(counts, self.nw))
+        assert out.is_cuda and out.dtype == torch.float64 and out.numel() >= sum(counts)
+        _lib.check(_lib.lib().tnvan_logz_batch_noalloc(self._h, arr, _ptr(spins), _ptr(out),
+                                                       _stream()))
+        return out[:sum(counts)]
+
     def observables(self, spins: torch.Tensor, logq: torch.Tensor, n_samples):
         """(mag [sum n], corr [sum E], ess [n_inst]) device float64 tensors:
         <sigma_i>_p and <sigma_i sigma_j>_p estimated from samples of q

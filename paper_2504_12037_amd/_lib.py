@@ -19,6 +19,9 @@ LIB_PATH = os.path.join(HERE, "libtnvan.so")
 FP64, FP32, BF16 = 0, 1, 2
 _PREC = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 
+NOALLOC_SCRATCH_BYTES = 32 << 20
+NOALLOC_MAX_INST = 32
+
 STATUS = {0: "TNVAN_OK", 1: "TNVAN_E_INVALID", 2: "TNVAN_E_WIDTH",
           3: "TNVAN_E_NOMEM", 4: "TNVAN_E_HIP", 5: "TNVAN_E_STATE",
           6: "TNVAN_E_NONFINITE"}
@@ -26,7 +29,8 @@ STATUS = {0: "TNVAN_OK", 1: "TNVAN_E_INVALID", 2: "TNVAN_E_WIDTH",
 EXPORTS = ["tnvan_build_network", "tnvan_free_network", "tnvan_last_error",
            "tnvan_param_count", "tnvan_set_params", "tnvan_get_params",
            "tnvan_get_state",
-           "tnvan_sample", "tnvan_logz_batch", "tnvan_logz_backward",
+           "tnvan_sample", "tnvan_logz_batch", "tnvan_logz_batch_noalloc",
+           "tnvan_logz_backward",
            "tnvan_logz_and_backward", "tnvan_exact_free_energy", "tnvan_observables",
            "tnvan_free_energy_step",
            "tnvan_free_energy_step_adjoint", "tnvan_program_info", "tnvan_plan",
@@ -79,6 +83,7 @@ def lib():
     L.tnvan_get_state.argtypes = [vp, i32, i32, vp, vp]
     L.tnvan_sample.argtypes = [vp, vp, vp, vp, vp, vp]
     L.tnvan_logz_batch.argtypes = [vp, vp, vp, vp, vp]
+    L.tnvan_logz_batch_noalloc.argtypes = [vp, vp, vp, vp, vp]
     L.tnvan_logz_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.tnvan_logz_and_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.tnvan_exact_free_energy.argtypes = [vp, i32, vp, vp]

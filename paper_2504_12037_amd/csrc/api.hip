@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <initializer_list>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -77,6 +78,38 @@ hipError_t upload(DBuf &b, const std::vector<T> &v) {
   return e;
 }
 
+// Scratch of the allocation-free entry point (tnvan_logz_batch_noalloc): a
+// file-scope device array, one copy on every GPU the library runs on, held
+// until the process ends.  On the host its name only stands in for the
+// symbol; kernels get each device's own address, taken from
+// hipGetSymbolAddress once per device (scratch_setup) and kept in
+// g_scratch_dev.
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[TNVAN_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices];
+std::string g_scratch_err[kMaxDevices];
+
+// Called with device `dev` current: its scratch address, once.
+void scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[dev]) return;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    g_scratch_err[dev] = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    (void)hipGetLastError();
+    return;
+  }
+  g_scratch_dev[dev] = p;
+}
+
 struct TileCache {
   std::vector<int64_t> key;       // n_samples it was built for
   int S = 0;
@@ -90,6 +123,7 @@ struct TileCache {
 
 struct tnvan_net {
   int precision = TNVAN_FP32;
+  int device = 0;             // the device current at build
   uint64_t seed = 0;
   HostProgram P;
   int n_inst = 0;
@@ -1255,6 +1289,9 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   choose_tiles(net, true);
 #undef UP
 #undef UP2
+  // the allocation-free entry point's scratch address on this device
+  (void)hipGetDevice(&net->device);
+  scratch_setup(net->device);
   *out = net;
   return TNVAN_OK;
 }
@@ -1565,6 +1602,139 @@ tnvan_status tnvan_logz_and_backward(tnvan_net *net, const int64_t *n_samples,
   }
   if (tnvan_status s = run_logz<float>(net, spins, logz, st)) return s;
   return run_backward<float>(net, spins, grad, dh, dJ, dbeta, st);
+}
+
+tnvan_status tnvan_logz_batch_noalloc(tnvan_net *net, const int64_t *n_samples,
+                                      const int8_t *spins, double *logz, void *stream) {
+  if (tnvan_status s = check_net(net)) return s;
+  if (!n_samples) return set_err(TNVAN_E_INVALID, "n_samples is NULL");
+  if (net->n_inst > kLayoutMaxInst)
+    return set_err(TNVAN_E_INVALID, "the allocation-free call takes at most %d instances",
+                   kLayoutMaxInst);
+  bool chains = net->rfwd;
+  for (int q = 0; q < net->n_inst; ++q) chains = chains && net->use_chain[q];
+  if (!chains)
+    return set_err(TNVAN_E_STATE, "the allocation-free call needs every instance on the "
+                                  "register-resident chain kernels");
+  // the per-call layout, as ensure_chain_tasks lays it for the net's own calls
+  LayoutArgs L{};
+  L.n_inst = net->n_inst;
+  int64_t so = 0, sp = 0, cp = 0, uo = 0, fo = 0, waves2 = 0, maxB = 0;
+  int max_nch = 0;
+  for (int q = 0; q < net->n_inst; ++q) {
+    const int64_t B = n_samples[q];
+    if (B < 0 || B > ((int64_t)1 << 31)) return set_err(TNVAN_E_INVALID, "bad sample count");
+    const InstDesc &D = net->P.insts[q];
+    const ChainInst &C = net->P.cinst[q];
+    const int nch = (D.nr + kUnaryChunk - 1) / kUnaryChunk;
+    L.B[q] = B;
+    L.sample_off[q] = so;
+    L.spin_off[q] = sp;
+    L.cpart_off[q] = cp;
+    L.u_off[q] = uo;
+    L.f_off[q] = fo;
+    so += B;
+    sp += B * D.nw;
+    cp += (int64_t)C.n_chains * B;
+    uo += (int64_t)D.nr * B;
+    fo += (int64_t)nch * B;
+    waves2 += C.n_chains * ((B + 31) / 32);
+    maxB = std::max(maxB, B);
+    max_nch = std::max(max_nch, nch);
+  }
+  const int sg = waves2 >= 1024 ? 2 : 1;
+  int64_t nt = 0;
+  for (int gi = 0; gi < 3; ++gi) {
+    const int rt = 1 << gi;
+    L.per[gi] = 16 * (rt >= 4 ? 1 : sg);
+    for (int q = 0; q < net->n_inst; ++q) {
+      L.seg_off[gi][q] = (int32_t)nt;
+      const ChainInst &C = net->P.cinst[q];
+      int nm = 0;
+      for (int c = 0; c < C.n_chains; ++c) {
+        const int crt = net->P.chains[C.chain_off + c].rt;
+        nm += (crt > 4 ? 4 : crt) == rt;
+      }
+      nt += nm * ((L.B[q] + L.per[gi] - 1) / L.per[gi]);
+      if (nt > (1 << 30)) return set_err(TNVAN_E_INVALID, "batch too large");
+    }
+    L.seg_off[gi][net->n_inst] = (int32_t)nt;
+  }
+  L.n_tasks = (int32_t)nt;
+  // scratch: the small tables, then U, the unary sums and the chain partials
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  const size_t n8 = sizeof(int64_t) * net->n_inst;
+  const size_t oB = take(n8), oS = take(n8), oSp = take(n8), oC = take(n8), oU = take(n8),
+               oF = take(n8), oCl = take(sizeof(int32_t) * net->n_inst),
+               oTi = take(sizeof(int32_t) * nt), oTc = take(sizeof(int32_t) * nt),
+               oTs = take(sizeof(int32_t) * nt), oUb = take(sizeof(float) * uo),
+               oFa = take(sizeof(double) * fo), oCp = take(sizeof(double) * cp);
+  if (off > (size_t)TNVAN_NOALLOC_SCRATCH_BYTES)
+    return set_err(TNVAN_E_INVALID, "the batch needs %zu bytes of scratch, above the %u of "
+                                    "the allocation-free call", off,
+                   (unsigned)TNVAN_NOALLOC_SCRATCH_BYTES);
+  if (so == 0) return TNVAN_OK;
+  if (!logz || (!spins && sp > 0)) return set_err(TNVAN_E_INVALID, "spins and logz are required");
+  if (tnvan_status s = check_device({spins, logz})) return s;
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != net->device)
+    return set_err(TNVAN_E_STATE, "the net lives on device %d, device %d is current",
+                   net->device, dev);
+  char *base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev >= 0 && dev < kMaxDevices) base = static_cast<char *>(g_scratch_dev[dev]);
+    if (!base)
+      return set_err(TNVAN_E_HIP, "no scratch address on device %d: %s", dev,
+                     dev >= 0 && dev < kMaxDevices ? g_scratch_err[dev].c_str() : "");
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  L.cinst = net->cinst.as<ChainInst>();
+  L.chains = net->chains.as<ChainDesc>();
+  L.d_B = reinterpret_cast<int64_t *>(base + oB);
+  L.d_sample_off = reinterpret_cast<int64_t *>(base + oS);
+  L.d_spin_off = reinterpret_cast<int64_t *>(base + oSp);
+  L.d_cpart_off = reinterpret_cast<int64_t *>(base + oC);
+  L.d_u_off = reinterpret_cast<int64_t *>(base + oU);
+  L.d_f_off = reinterpret_cast<int64_t *>(base + oF);
+  L.d_clist = reinterpret_cast<int32_t *>(base + oCl);
+  L.d_ti = reinterpret_cast<int32_t *>(base + oTi);
+  L.d_tc = reinterpret_cast<int32_t *>(base + oTc);
+  L.d_ts = reinterpret_cast<int32_t *>(base + oTs);
+  float *U = reinterpret_cast<float *>(base + oUb);
+  double *fabp = reinterpret_cast<double *>(base + oFa), *cpart = reinterpret_cast<double *>(base + oCp);
+  HIPCHK(launch_layout(L, st));
+  ChainArgs c = chain_args(net, false);
+  c.spins = spins;
+  c.inst_B = L.d_B;
+  c.inst_sample_off = L.d_sample_off;
+  c.inst_spin_off = L.d_spin_off;
+  c.cpart_off = L.d_cpart_off;
+  c.cpart = cpart;
+  c.U = U;
+  c.u_off = L.d_u_off;
+  c.u_all = 1;
+  c.task_inst = L.d_ti;
+  c.task_chain = L.d_tc;
+  c.task_start = L.d_ts;
+  HIPCHK(launch_unary(c, L.d_clist, net->n_inst, max_nch, maxB, L.d_f_off, U, fabp, st));
+  for (int gi = 0; gi < 3; ++gi) {
+    c.task_base = L.seg_off[gi][0];
+    c.n_tasks = L.seg_off[gi][net->n_inst] - L.seg_off[gi][0];
+    c.ntm = 1 << gi;
+    c.sg = (1 << gi) >= 4 ? 1 : sg;
+    if (c.n_tasks > 0) HIPCHK(launch_rchain(c, false, st));
+  }
+  HIPCHK(launch_chain_sum(net->inst.as<InstDesc>(), net->cinst.as<ChainInst>(), L.d_clist,
+                          net->n_inst, L.d_B, L.d_sample_off, L.d_cpart_off, cpart, L.d_f_off,
+                          fabp, logz, st));
+  return TNVAN_OK;
 }
 
 tnvan_status tnvan_program_info(const tnvan_net *net, int32_t inst, int64_t info[6]) {

@@ -31,6 +31,8 @@
 // adjoint uses FP32 products in both the FP32 and the BF16 precisions.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "launch.h"
 #include "wave.h"
 
@@ -727,8 +729,8 @@ __global__ __launch_bounds__(256) void unary_kernel(ChainArgs a, const int32_t *
   for (int p = p0; p < p1; ++p) {
     const int i = p - p0;
     // a position with no W-neighbour and no field has the factor +1, which
-    // the table holds from its set-up: nothing to store
-    if (s_n[i] == 0 && s_h[i] == 0.f) continue;
+    // the table holds from its set-up: nothing to store (unless u_all)
+    if (!a.u_all && s_n[i] == 0 && s_h[i] == 0.f) continue;
     float f = s_h[i];
     if (s_n[i] <= 4) {
       float t[4];
@@ -747,6 +749,44 @@ __global__ __launch_bounds__(256) void unary_kernel(ChainArgs a, const int32_t *
     fab += (double)af;
   }
   fabp[f_off[q] + (int64_t)blockIdx.y * B + b] = fab;
+}
+
+__global__ __launch_bounds__(256) void layout_kernel(LayoutArgs a) {
+  const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (tid < a.n_inst) {
+    const int q = (int)tid;
+    a.d_B[q] = a.B[q];
+    a.d_sample_off[q] = a.sample_off[q];
+    a.d_spin_off[q] = a.spin_off[q];
+    a.d_cpart_off[q] = a.cpart_off[q];
+    a.d_u_off[q] = a.u_off[q];
+    a.d_f_off[q] = a.f_off[q];
+    a.d_clist[q] = q;
+  }
+  for (int64_t t = tid; t < a.n_tasks; t += (int64_t)gridDim.x * blockDim.x) {
+    // the (width group, instance) segment holding task t
+    int gi = 0, q = 0;
+    for (int g = 0; g < 3; ++g)
+      for (int k = 0; k < a.n_inst; ++k)
+        if (t >= a.seg_off[g][k] && t < a.seg_off[g][k + 1]) { gi = g; q = k; }
+    const ChainInst C = a.cinst[q];
+    const int rt = 1 << gi;
+    int nm = 0;
+    for (int c = 0; c < C.n_chains; ++c) {
+      const int crt = a.chains[C.chain_off + c].rt;
+      nm += (crt > 4 ? 4 : crt) == rt;
+    }
+    const int64_t li = t - a.seg_off[gi][q];
+    const int64_t bi = li / nm;
+    int ci = (int)(li - bi * nm), c = 0;
+    for (; c < C.n_chains; ++c) {
+      const int crt = a.chains[C.chain_off + c].rt;
+      if ((crt > 4 ? 4 : crt) == rt && ci-- == 0) break;
+    }
+    a.d_ti[t] = q;
+    a.d_tc[t] = c;
+    a.d_ts[t] = (int32_t)(bi * a.per[gi]);
+  }
 }
 
 template <int NTM>
@@ -796,6 +836,14 @@ hipError_t launch_chain_sum(const InstDesc *inst, const ChainInst *cinst,
   hipLaunchKernelGGL(chain_sum_kernel, dim3(32, n_chain_insts), dim3(256), 0, st, inst, cinst,
                      chain_insts, n_chain_insts, inst_B, inst_sample_off, cpart_off, cpart, f_off,
                      fabp, logz);
+  return hipGetLastError();
+}
+
+hipError_t launch_layout(const LayoutArgs &a, hipStream_t st) {
+  const int64_t n = std::max<int64_t>(a.n_inst, a.n_tasks);
+  if (n <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>(1024, (n + 255) / 256);
+  hipLaunchKernelGGL(layout_kernel, dim3(blocks), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -341,6 +341,10 @@ struct ChainArgs {
   // instance: +-exp(-2 beta |f|), negative when f < 0 (unary_kernel)
   const float *U;
   const int64_t *u_off;             // per instance
+  // unary_kernel writes every factor, also the +1 of positions with no
+  // W-neighbour and no field (else those keep the +1 the table was filled
+  // with when its layout was set)
+  int32_t u_all;
 };
 // U and the per-sample sums of beta |f| over each run of kUnaryChunk
 // positions (fabp[f_off[q] + chunk * B + b]) of the instances in cis.
@@ -368,5 +372,26 @@ hipError_t launch_chain_sum(const InstDesc *inst, const ChainInst *cinst,
                             const int64_t *inst_B, const int64_t *inst_sample_off,
                             const int64_t *cpart_off, const double *cpart, const int64_t *f_off,
                             const double *fabp, double *logz, hipStream_t st);
+
+// Per-call tables of the register-resident forward written on the device
+// (no host copy): the per-instance offsets the host computed, the list of
+// chain instances and the forward task list, (instance, chain, first sample)
+// in the order width group, instance, sample group, chain.  Everything comes
+// by value, so the launch allocates nothing and can be recorded in a graph.
+constexpr int kLayoutMaxInst = 32;
+struct LayoutArgs {
+  int32_t n_inst;
+  int32_t n_tasks;                           // total forward tasks
+  int64_t B[kLayoutMaxInst], sample_off[kLayoutMaxInst], spin_off[kLayoutMaxInst];
+  int64_t cpart_off[kLayoutMaxInst], u_off[kLayoutMaxInst], f_off[kLayoutMaxInst];
+  int32_t seg_off[3][kLayoutMaxInst + 1];    // first task of (width group, instance)
+  int32_t per[3];                            // samples per task of each width group
+  const ChainInst *cinst;
+  const ChainDesc *chains;
+  // destinations
+  int64_t *d_B, *d_sample_off, *d_spin_off, *d_cpart_off, *d_u_off, *d_f_off;
+  int32_t *d_clist, *d_ti, *d_tc, *d_ts;
+};
+hipError_t launch_layout(const LayoutArgs &a, hipStream_t st);
 
 }  // namespace tnvan
