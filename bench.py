@@ -14,9 +14,24 @@ log-prob pass and the REINFORCE gradient, and the Adam update.  `value` is
 samples per second of that step (3 x 8192 samples per step), inputs resident
 in HBM.
 
-Also reported: the forward + adjoint alone for the FP32 and the plain FP64
-paths, the error of logZ against the oracle on sampled outputs, a roofline
-line for the dominant kernel and the oracle timed on the host cores.
+The metric's own rate, the forward + adjoint
+alone (tnvan_logz_and_backward), is breakdown.fwd_adj_samples_per_s, beside
+the plain FP64 path on the same inputs.
+
+The breakdown also measures the other workloads, each forward + adjoint per
+path with its error against the oracle:
+  c1   4x4 lattice, FP64 training (200 Adam steps, lr 1e-3, 1024 samples,
+       hidden 16), exact F_q of the trained network against the 2^16-state F
+  c2   the step's lattices with FP32 products and in the BF16 precision
+  c3   SK N = 64 (beta 0.5, 1, 1.5; 48-spin width set, 2048 samples each)
+  c4   random 3-regular N = 256, +-J, Gaussian fields, 4096 samples
+  c5   64 uneven instances (lattices L = 8..24, random regular graphs
+       N = 64..256, 512-4096 samples each, 122,880 in all), forward +
+       adjoint and the training step replayed from a HIP graph
+plus a roofline line for the dominant kernel and the oracle timed on the
+host cores.  Every use of the oracle (the timed CPU baseline and every error
+against it) is in the oracle leg at the end (--no-cpu-baseline skips it and
+leaves the errors null).
 """
 
 from __future__ import annotations
@@ -69,6 +84,7 @@ KERNEL_NAMES = {
     "made_grad": "mgrad_kernel<2, 16>", "sample": "msample_kernel<2, false>",
 }
 PEAK_FP32 = 157.3e12       # MI355X FP32 (vector and 16x16x4 matrix), published
+PEAK_FP64 = 78.6e12        # MI355X FP64 (vector and matrix), published
 PEAK_BF16 = 2.5e15         # MI355X BF16 dense matrix, published
 
 
@@ -146,6 +162,24 @@ def measured_traffic(kernel):
         return None
 
 
+def fwd_adj(net, flat, counts, iters, st, g=None):
+    """Time tnvan_logz_and_backward with g_b = 1/B (per instance); returns
+    (seconds per call, logz, (dh, dJ, dbeta)) of the last call, on the host."""
+    import torch
+    if g is None:
+        g = torch.cat([torch.full((b,), 1.0 / max(b, 1), dtype=torch.float64, device="cuda")
+                       for b in counts])
+    logz = torch.empty(max(1, sum(counts)), dtype=torch.float64, device="cuda")
+    out = net._adjoint_out(None)
+    fa = lambda: net.logz_and_backward(flat, g, counts, logz_out=logz, out=out)
+    for _ in range(2):
+        fa()
+    t = event_time(fa, iters, st)
+    fa()
+    torch.cuda.synchronize()
+    return t, logz[:sum(counts)].cpu().numpy(), tuple(x.cpu().numpy() for x in out)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -156,7 +190,6 @@ def main():
     import torch
 
     import synthetic as S
-    from oracle import ising as OI
     from paper_2504_12037_amd import Net
 
     torch.cuda.set_device(0)
@@ -165,6 +198,8 @@ def main():
     nI = len(insts)
     counts = [B] * nI
     nw = insts[0].n_width
+    iters = max(5, args.steps)
+    keep = {}          # GPU results the oracle leg checks
     if args.calibrate_copy > 0:
         # a plain copy of known size: the HBM traffic counters of every kernel
         # are scaled by what they read for it
@@ -223,35 +258,107 @@ def main():
         if n:
             ktime[k] = (tot, n)
 
-    # forward + adjoint alone, FP32 (or the chosen) path and plain FP64 path
-    sp_fix = torch.from_numpy(S.uniform_spins(nI * B, nw, 102)).cuda().reshape(-1)
+    # ---- C2: forward + adjoint alone, this path and the others, same inputs
+    sp_np = S.uniform_spins(nI * B, nw, 102)
+    sp_fix = torch.from_numpy(sp_np).cuda().reshape(-1)
+    keep["c2_spins"] = sp_np
+    t_fa, lz, adj = fwd_adj(net, sp_fix, counts, iters, st)
+    keep["c2"] = {"run": (lz, adj)}
     logz = torch.empty(nI * B, dtype=torch.float64, device="cuda")
     out = (dh, dJ, db)
-    fa = lambda: net.logz_and_backward(sp_fix, g, counts, logz_out=logz, out=out)
-    for _ in range(3):
-        fa()
-    t_fa = event_time(fa, max(5, args.steps), st)
-    t_bwd = event_time(lambda: net.backward(sp_fix, g, counts, out=out), max(5, args.steps), st)
-    t_fwd = event_time(lambda: net.logz(sp_fix, counts, out=logz), max(5, args.steps), st)
-    net64 = Net(insts, precision="fp64")
-    logz64 = torch.empty_like(logz)
-    fa64 = lambda: net64.logz_and_backward(sp_fix, g, counts, logz_out=logz64, out=out)
-    for _ in range(3):
-        fa64()
-    t_fa64 = event_time(fa64, max(5, args.steps), st)
-    # error of logZ on sampled outputs against the oracle, and vs FP64 path
-    # (the logZ that the forward + adjoint call produced)
-    fa()
-    fa64()
-    lz = logz.cpu().numpy()
-    lz64 = logz64.cpu().numpy()
-    spn = sp_fix.cpu().numpy().reshape(nI * B, nw)
-    idx = np.random.default_rng(1).choice(B, 64, replace=False)
-    err = 0.0
-    for k, inst in enumerate(insts):
-        want = OI.logz_r_elimination(inst, spn[k * B + idx])
-        err = max(err, float(np.abs(lz[k * B + idx] - want).max() / inst.n))
+    t_bwd = event_time(lambda: net.backward(sp_fix, g, counts, out=out), iters, st)
+    t_fwd = event_time(lambda: net.logz(sp_fix, counts, out=logz), iters, st)
+    c2_paths = {}
+    for pname, prec, flags in (("fp64", "fp64", 0), ("fp32_products", "fp32", 0),
+                               ("bf16", "bf16", 0), ("split_bf16", "fp32", Net.FLAG_SPLIT_BF16)):
+        if prec == args.precision and (flags != 0) == split:
+            continue
+        n2 = Net(insts, precision=prec, flags=flags)
+        t2, lz2, adj2 = fwd_adj(n2, sp_fix, counts, iters, st)
+        keep["c2"][pname] = (lz2, adj2)
+        c2_paths[pname] = {"fwd_adj_s": t2, "fwd_adj_samples_per_s": nI * B / t2}
+        del n2
+    t_fa64 = c2_paths["fp64"]["fwd_adj_s"] if "fp64" in c2_paths else t_fa
+    lz64 = keep["c2"].get("fp64", (lz, None))[0]
     err64 = float(np.abs(lz - lz64).max() / insts[0].n)
+
+    # ---- C1: plain FP64 training on the 4x4 lattice (Algorithm 1)
+    c1 = S.c1_small_lattice(hidden=16)
+    net1 = Net([c1], precision="fp64", seed=1)
+    net1.set_params(0, torch.from_numpy(S.made_init(4, 16, 3)))
+    st1 = torch.empty(1, 4, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(200):
+        net1.free_energy_step(1024, 1e-3, stats=st1)
+    torch.cuda.synchronize()
+    t_c1 = (time.perf_counter() - t0) / 200
+    keep["c1_theta"] = net1.get_params(0).cpu().numpy()
+    keep["c1_last_Fq"] = float(st1.cpu().numpy()[0, 0])
+    del net1
+
+    # ---- C3: SK N = 64, dense 256 x 256 steps (LDS-staged chain kernels)
+    c3 = [S.c3_sk(b) for b in (0.5, 1.0, 1.5)]
+    B3 = 2048
+    sp3 = S.uniform_spins(3 * B3, 48, 103)
+    keep["c3_spins"] = sp3
+    flat3 = torch.from_numpy(sp3).cuda().reshape(-1)
+    c3_paths = {}
+    keep["c3"] = {}
+    for pname, prec in (("fp32", "fp32"), ("bf16", "bf16"), ("fp64", "fp64")):
+        n3 = Net(c3, precision=prec)
+        t3, lz3, adj3 = fwd_adj(n3, flat3, [B3] * 3, iters, st)
+        keep["c3"][pname] = (lz3, adj3)
+        c3_paths[pname] = {"fwd_adj_s": t3, "fwd_adj_samples_per_s": 3 * B3 / t3}
+        if pname == "fp32":
+            c3_flops = n3.info(0)[3]
+        del n3
+
+    # ---- C4: random 3-regular N = 256 (general single-spin steps)
+    c4 = S.c4_rrg()
+    B4 = 4096
+    sp4 = S.uniform_spins(B4, c4.n_width, 104)
+    keep["c4_spins"] = sp4
+    flat4 = torch.from_numpy(sp4).cuda().reshape(-1)
+    c4_paths = {}
+    keep["c4"] = {}
+    for pname, prec in (("fp32", "fp32"), ("fp64", "fp64")):
+        n4 = Net([c4], precision=prec)
+        t4, lz4, adj4 = fwd_adj(n4, flat4, [B4], iters, st)
+        keep["c4"][pname] = (lz4, adj4)
+        c4_paths[pname] = {"fwd_adj_s": t4, "fwd_adj_samples_per_s": B4 / t4}
+        if pname == "fp32":
+            c4_flops = n4.info(0)[3]
+        del n4
+
+    # ---- C5: 64 uneven instances in one net
+    c5 = S.mixed_batch_instances()
+    B5 = S.mixed_batch_sizes(c5)
+    sp5 = [S.uniform_spins(b, i.n_width, 900 + k) for k, (b, i) in enumerate(zip(B5, c5))]
+    keep["c5_spins"] = sp5
+    flat5 = torch.from_numpy(np.concatenate([x.reshape(-1) for x in sp5])).cuda()
+    c5_paths = {}
+    keep["c5"] = {}
+    for pname, prec, flags in (("split_bf16", "fp32", Net.FLAG_SPLIT_BF16), ("bf16", "bf16", 0),
+                               ("fp64", "fp64", 0)):
+        n5 = Net(c5, precision=prec, flags=flags | (Net.FLAG_GRAPH if prec != "fp64" else 0))
+        t5, lz5, _ = fwd_adj(n5, flat5, B5, 3, st)
+        keep["c5"][pname] = lz5
+        c5_paths[pname] = {"fwd_adj_s": t5, "fwd_adj_samples_per_s": sum(B5) / t5}
+        if prec != "fp64":
+            for k, inst in enumerate(c5):
+                n5.set_params(k, torch.from_numpy(S.made_init(inst.n_width, inst.hidden, 7 + k)))
+            st5 = torch.empty(len(c5), 4, dtype=torch.float64, device="cuda")
+            g5 = torch.cat([torch.full((b,), 1.0 / b, dtype=torch.float64, device="cuda")
+                            for b in B5])
+            a5 = (g5,) + n5._adjoint_out(None)
+            s5 = lambda: n5.free_energy_step(B5, 1e-3, stats=st5, adjoint=a5)
+            for _ in range(2):
+                s5()        # eager, then recorded; replays after
+            t_s5 = event_time(s5, 3, st)
+            c5_paths[pname].update({"train_step_graph_s": t_s5,
+                                    "train_step_samples_per_s": sum(B5) / t_s5})
+        del n5
 
     # exact slicing (every width-set configuration contracted as one sample,
     # Eqs. 3-4): a 12x12 Gaussian lattice with W = columns 5 and 9 (|W| = 24,
@@ -324,6 +431,20 @@ def main():
                     "kernel_avg_s": dom_avg, "kernel_launches_timed": ktime[dom][1],
                     "flops_per_launch": KERNEL_FLOPS[dom] * nI * B,
                     "peak_units": "bf16 dense, 3 products per flop" if split else "fp32 matrix"}
+    # call-level rooflines of the other workloads: algorithmic flops of the
+    # forward + adjoint call (three times the forward) per second
+    c3_alg = 3 * 2 * 65536          # [256] x [256, 256] per sample, forward x 3
+    c4_alg = 3 * c4_flops
+    for pth, d in c3_paths.items():
+        pk = {"fp32": PEAK_FP32, "bf16": PEAK_BF16, "fp64": PEAK_FP64}[pth]
+        d["roofline_call"] = {"bound": "mfma", "achieved_TFLOPs": c3_alg * d["fwd_adj_samples_per_s"] / 1e12,
+                              "peak_TFLOPs": pk / 1e12,
+                              "frac": c3_alg * d["fwd_adj_samples_per_s"] / pk}
+    for pth, d in c4_paths.items():
+        pk = {"fp32": PEAK_FP32, "fp64": PEAK_FP64}[pth]
+        d["roofline_call"] = {"bound": "alu", "achieved_TFLOPs": c4_alg * d["fwd_adj_samples_per_s"] / 1e12,
+                              "peak_TFLOPs": pk / 1e12,
+                              "frac": c4_alg * d["fwd_adj_samples_per_s"] / pk}
     res = {
         "metric": METRIC,
         "value": value,
@@ -341,6 +462,9 @@ def main():
         "config": {"workload": "16x16 OBC Gaussian spin glass, W = columns 6,11, "
                                "beta in {0.5,1,2}, 8192 samples each, MADE H=256",
                    "global_batch": nI * B, "instances": nI, "parallelism": "single GPU"},
+        "value_is": ("samples/s of the whole training step (sample, logZ with its adjoint, "
+                     "F_q, REINFORCE, Adam); the forward + adjoint alone is "
+                     "breakdown.fwd_adj_samples_per_s"),
         "roofline": roofline,
         "breakdown": {
             "fwd_adj_samples_per_s": nI * B / t_fa,
@@ -348,9 +472,26 @@ def main():
             "speedup_vs_fp64_path": t_fa64 / t_fa,
             "logz_fwd_s": t_fwd, "logz_bwd_s": t_bwd, "fwd_adj_s": t_fa,
             "fwd_adj_fp64_s": t_fa64,
-            "max_abs_dlogZ_per_N_vs_oracle": err,
+            "max_abs_dlogZ_per_N_vs_oracle": None,
             "max_abs_dlogZ_per_N_vs_fp64_path": err64,
+            "adjoint_max_err_over_max_entry_vs_oracle": None,
+            "c2_other_paths": c2_paths,
             "wall_s_timed_region": wall,
+            "c1": {"workload": "4x4 Gaussian lattice (seed 1), W = column 2, FP64 path, "
+                               "200 Adam steps, lr 1e-3, 1024 samples, MADE H=16",
+                   "ms_per_step": 1e3 * t_c1, "samples_per_s": 1024 / t_c1,
+                   "last_batch_F_q": keep["c1_last_Fq"]},
+            "c3": {"workload": "SK N=64, J ~ N(0,1/64) (seed 3), beta 0.5/1/1.5, |W| = 48, "
+                               "R = 16 spins in two groups of 8, 2048 samples each",
+                   "algorithmic_flops_per_sample_fwd_adj": c3_alg, "paths": c3_paths,
+                   "speedup_fp32_vs_fp64": c3_paths["fp64"]["fwd_adj_s"] / c3_paths["fp32"]["fwd_adj_s"]},
+            "c4": {"workload": "random 3-regular N=256, +-J, h ~ N(0,0.1) (seed 4), greedy "
+                               f"width limit 10 (|W| = {c4.n_width}), 4096 samples",
+                   "algorithmic_flops_per_sample_fwd_adj": c4_alg, "paths": c4_paths,
+                   "speedup_fp32_vs_fp64": c4_paths["fp64"]["fwd_adj_s"] / c4_paths["fp32"]["fwd_adj_s"]},
+            "c5": {"workload": "64 instances: lattices L in {8,12,16,24}, random 3-regular "
+                               "N in {64,128,256}, 512-4096 samples each",
+                   "samples": sum(B5), "paths": c5_paths},
             "exact_slicing": {"workload": "12x12 OBC Gaussian lattice (seed 6), W = columns 5,9, beta 1",
                               "configurations": 1 << inst_x.n_width, "s": t_x,
                               "configurations_per_s": (1 << inst_x.n_width) / t_x,
@@ -371,7 +512,69 @@ def main():
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(insts, args.cpu_samples)
+        oracle_checks(res["breakdown"], keep, insts, c3, c4, c5, B5)
     print(json.dumps(res), flush=True)
+
+
+def oracle_checks(bd, keep, insts, c3, c4, c5, B5):
+    """The oracle leg's errors: every GPU result kept above against the FP64
+    oracle on the same inputs (per-sample logZ error per spin; adjoint error
+    relative to the largest entry, with g_b = 1/B)."""
+    import synthetic as S
+    from oracle import ising as OI
+    from oracle import objective as OO
+
+    def vjp_err(inst, spins, adj, k=0):
+        Bk = spins.shape[0]
+        wdh, wdJ, wdb = OI.logz_r_vjp(inst, spins, np.full(Bk, 1.0 / Bk))
+        dh, dJ, db = adj
+        eh = np.abs(dh[k * inst.n:(k + 1) * inst.n] - wdh).max()
+        eJ = np.abs(dJ[k * inst.n_edges:(k + 1) * inst.n_edges] - wdJ).max()
+        return float(max(eh, eJ) / max(np.abs(wdh).max(), np.abs(wdJ).max()))
+
+    # C2, full batch of every beta
+    sp = keep["c2_spins"]
+    nI = len(insts)
+    want = [OI.logz_r_elimination(inst, sp[k * B:(k + 1) * B]) for k, inst in enumerate(insts)]
+    for pname, (lz, adj) in keep["c2"].items():
+        e = max(float(np.abs(lz[k * B:(k + 1) * B] - want[k]).max() / inst.n)
+                for k, inst in enumerate(insts))
+        ea = max(vjp_err(inst, sp[k * B:(k + 1) * B], adj, k) for k, inst in enumerate(insts))
+        if pname == "run":
+            bd["max_abs_dlogZ_per_N_vs_oracle"] = e
+            bd["adjoint_max_err_over_max_entry_vs_oracle"] = ea
+        else:
+            bd["c2_other_paths"][pname]["max_abs_dlogZ_per_N_vs_oracle"] = e
+            bd["c2_other_paths"][pname]["adjoint_max_err_over_max_entry_vs_oracle"] = ea
+    # C1: exact F_q of the trained network (enumeration of q) against F
+    c1 = S.c1_small_lattice(hidden=16)
+    Fq, _ = OO.exact_fq_and_grad(c1, keep["c1_theta"].astype(np.float64), 16)
+    F = OO.exact_free_energy(c1)
+    bd["c1"].update({"exact_F_q_after_training": Fq, "exact_F": F,
+                     "relative_gap": (Fq - F) / abs(F)})
+    # C3, full batch (brute force over the 2^16 remainder states)
+    sp3 = keep["c3_spins"]
+    B3 = sp3.shape[0] // 3
+    want3 = [OI.logz_r_bruteforce(inst, sp3[k * B3:(k + 1) * B3]) for k, inst in enumerate(c3)]
+    for pname, (lz, adj) in keep["c3"].items():
+        d = bd["c3"]["paths"][pname]
+        d["max_abs_dlogZ_per_N_vs_oracle"] = max(
+            float(np.abs(lz[k * B3:(k + 1) * B3] - want3[k]).max() / inst.n)
+            for k, inst in enumerate(c3))
+    # C4, full batch logZ and the adjoint
+    sp4 = keep["c4_spins"]
+    want4 = OI.logz_r_elimination(c4, sp4)
+    for pname, (lz, adj) in keep["c4"].items():
+        d = bd["c4"]["paths"][pname]
+        d["max_abs_dlogZ_per_N_vs_oracle"] = float(np.abs(lz - want4).max() / c4.n)
+        d["adjoint_max_err_over_max_entry_vs_oracle"] = vjp_err(c4, sp4, adj)
+    # C5, 16 samples of every instance
+    off = np.concatenate([[0], np.cumsum(B5)])
+    want5 = [OI.logz_r_elimination(inst, keep["c5_spins"][k][:16]) for k, inst in enumerate(c5)]
+    for pname, lz in keep["c5"].items():
+        bd["c5"]["paths"][pname]["max_abs_dlogZ_per_N_vs_oracle_16_per_instance"] = max(
+            float(np.abs(lz[off[k]:off[k] + 16] - want5[k]).max() / inst.n)
+            for k, inst in enumerate(c5))
 
 
 if __name__ == "__main__":
