@@ -128,7 +128,7 @@ struct tnvan_net {
   HostProgram P;
   int n_inst = 0;
   // program on the device
-  DBuf inst, steps, inputs, edges, T, fld_ptr, fld_w, fld_J, hR, wr_pos, wr_w;
+  DBuf inst, steps, inputs, gtab, edges, T, fld_ptr, fld_w, fld_J, hR, wr_pos, wr_w;
   DBuf rr_edge, rr_J, wr_edge, wr_J, hR64, vr, ww_a, ww_b, ww_J, hW;
   // network
   std::vector<MadeInst> mi;
@@ -545,6 +545,7 @@ ContractArgs<real> contract_args(tnvan_net *net, TileCache &tc, int S) {
   a.inst = net->inst.as<InstDesc>();
   a.steps = net->steps.as<StepDesc>();
   a.inputs = net->inputs.as<InputDesc>();
+  a.gtab = net->gtab.as<uint16_t>();
   a.edges = net->edges.as<EdgeDesc>();
   a.T = net->T.as<real>();
   a.fld_ptr = net->fld_ptr.as<int32_t>();
@@ -1166,7 +1167,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   HostProgram &P = net->P;
 #define UP(buf, vec) if ((e = upload(net->buf, vec)) != hipSuccess) return fail(e, #buf);
 #define UP2(buf, vec) if ((e = upload(net->buf, vec)) != hipSuccess) return fail(e, #buf);
-  UP(inst, P.insts) UP(steps, P.steps) UP(inputs, P.inputs) UP(edges, P.edges)
+  UP(inst, P.insts) UP(steps, P.steps) UP(inputs, P.inputs) UP(gtab, P.gtab) UP(edges, P.edges)
   UP(fld_ptr, P.fld_ptr) UP(fld_w, P.fld_w) UP(wr_pos, P.wr_pos) UP(wr_w, P.wr_w)
   UP(rr_edge, P.rr_edge) UP(rr_J, P.rr_J) UP(wr_edge, P.wr_edge) UP(wr_J, P.wr_J)
   UP(hR64, P.hR) UP(vr, P.vr) UP(ww_a, P.ww_a) UP(ww_b, P.ww_b) UP(ww_J, P.ww_J)
@@ -1307,7 +1308,7 @@ void tnvan_free_network(tnvan_net *net) {
     hipEventDestroy(e.second);
   }
   net->prof_pool.clear();
-  DBuf *all[] = {&net->inst, &net->steps, &net->inputs, &net->edges, &net->T, &net->fld_ptr,
+  DBuf *all[] = {&net->inst, &net->steps, &net->inputs, &net->gtab, &net->edges, &net->T, &net->fld_ptr,
                  &net->fld_w, &net->fld_J, &net->hR, &net->wr_pos, &net->wr_w, &net->rr_edge,
                  &net->rr_J, &net->wr_edge, &net->wr_J, &net->hR64, &net->vr, &net->ww_a,
                  &net->ww_b, &net->ww_J, &net->hW, &net->d_mi, &net->params, &net->adam_m,

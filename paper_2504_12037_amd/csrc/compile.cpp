@@ -529,6 +529,21 @@ tnvan_status compile_instance(const tnvan_instance &in, int max_width,
           id.src[b] = (int8_t)j;
         }
       }
+      id.gb_off = -1;
+      if (!dense) {
+        // the input's entry for every output entry o (eliminated spin +1)
+        if (P.gtab.size() + ((size_t)1 << w) > (size_t)INT32_MAX) {
+          fail(msg, "gather tables above 2^31 entries");
+          return TNVAN_E_INVALID;
+        }
+        id.gb_off = (int32_t)P.gtab.size();
+        for (int o = 0; o < (1 << w); ++o) {
+          int idx = 0;
+          for (int b = 0; b < id.nbits; ++b)
+            if (id.src[b] >= 0) idx |= ((o >> id.src[b]) & 1) << b;
+          P.gtab.push_back((uint16_t)idx);
+        }
+      }
       consumer[m.step] = t;
       P.inputs.push_back(id);
     }

@@ -14,6 +14,7 @@ struct HostProgram {
   std::vector<InstDesc> insts;
   std::vector<StepDesc> steps;
   std::vector<InputDesc> inputs;
+  std::vector<uint16_t> gtab;     // gather tables of SINGLE steps' inputs
   std::vector<EdgeDesc> edges;
   std::vector<double> T;          // all step tables, FP64
   std::vector<int32_t> fld_ptr;   // per instance: nr + 1 entries (local)

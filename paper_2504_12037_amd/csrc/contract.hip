@@ -24,6 +24,8 @@
 // are reduced in a fixed order into one partial row per tile.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "launch.h"
 
 namespace tnvan {
@@ -103,6 +105,75 @@ __device__ inline int gather_index(const InputDesc &id, int o, int x) {
     idx |= bit << b;
   }
   return idx;
+}
+
+// SINGLE steps with at most kFastIn inputs: each input's arena offset,
+// gather table, x bit and (per sample) scale are read once per step, and the
+// loop over output entries is unrolled over the inputs.  The products are
+// formed in the order of the general loop below (same results bit for bit).
+constexpr int kFastIn = 4;
+template <typename real>
+struct FastIn {
+  int ioff[kFastIn], xs[kFastIn];
+  const uint16_t *gb[kFastIn];
+  real sc[kFastIn];
+};
+
+template <typename real, bool kBwd>
+__device__ inline FastIn<real> fast_inputs(const ContractArgs<real> &a, const StepDesc &sd,
+                                           const StepDesc *steps,
+                                           const typename FBits<real>::U *mx, int S, int sme) {
+  using FB = FBits<real>;
+  FastIn<real> f;
+#pragma unroll
+  for (int k = 0; k < kFastIn; ++k) {
+    if (k < sd.n_in) {
+      const InputDesc id = a.inputs[sd.in_off + k];
+      const StepDesc ps = steps[id.step];
+      f.ioff[k] = kBwd ? ps.off_all : ps.off_fwd;
+      f.xs[k] = 1 << id.xbit;
+      f.gb[k] = a.gtab + id.gb_off;
+      f.sc[k] = FB::scale(FB::expo(mx[id.step * S + sme]));
+    } else {
+      f.ioff[k] = 0;
+      f.xs[k] = 0;
+      f.gb[k] = a.gtab;
+      f.sc[k] = (real)1;
+    }
+  }
+  return f;
+}
+
+// the two products of output entry o (eliminated spin +1 and -1), started
+// from p0 and p1
+template <typename real, int NI>
+__device__ inline void fast_pair(const FastIn<real> &f, const real *arena, int S, int sme, int o,
+                                 real &p0, real &p1) {
+#pragma unroll
+  for (int k = 0; k < NI; ++k) {
+    const int e = f.ioff[k] + (int)f.gb[k][o];
+    p0 *= arena[e * S + sme] * f.sc[k];
+    p1 *= arena[(e + f.xs[k]) * S + sme] * f.sc[k];
+  }
+}
+
+// forward of a SINGLE step: out[o] = sum_x T[x, o] phi[x] prod_k m_k; returns
+// this thread's largest output
+template <typename real, int NI>
+__device__ inline real fast_fwd(const FastIn<real> &f, const real *Tt, int w, real ph0, real ph1,
+                                real *arena, int off, int S, int logS, int sme, int tid) {
+  real lmax = 0;
+  for (int i = tid; i < (S << w); i += kThreads) {
+    const int o = i >> logS;
+    real p0 = Tt[o] * ph0, p1 = Tt[(1 << w) | o] * ph1;
+    fast_pair<real, NI>(f, arena, S, sme, o, p0, p1);
+    real acc = 0;
+    acc += p0;
+    acc += p1;
+    arena[(off + o) * S + sme] = acc;
+    lmax = acc > lmax ? acc : lmax;
+  }
+  return lmax;
 }
 
 template <typename real, bool kGlobal, bool kBwd>
@@ -188,6 +259,16 @@ __global__ __launch_bounds__(kThreads) void contract_kernel(ContractArgs<real> a
         for (int x = 0; x < nx; ++x) acc += Tt[(x << w) | o] * scr[x * S + sme];
         arena[(off + o) * S + sme] = acc;
         lmax = acc > lmax ? acc : lmax;
+      }
+    } else if (sd.n_in <= kFastIn) {
+      const FastIn<real> f = fast_inputs<real, kBwd>(a, sd, steps, mx, S, sme);
+      const real ph0 = phi[(2 * sd.gpos) * S + sme], ph1 = phi[(2 * sd.gpos + 1) * S + sme];
+      switch (sd.n_in) {
+        case 0: lmax = fast_fwd<real, 0>(f, Tt, w, ph0, ph1, arena, off, S, logS, sme, tid); break;
+        case 1: lmax = fast_fwd<real, 1>(f, Tt, w, ph0, ph1, arena, off, S, logS, sme, tid); break;
+        case 2: lmax = fast_fwd<real, 2>(f, Tt, w, ph0, ph1, arena, off, S, logS, sme, tid); break;
+        case 3: lmax = fast_fwd<real, 3>(f, Tt, w, ph0, ph1, arena, off, S, logS, sme, tid); break;
+        default: lmax = fast_fwd<real, 4>(f, Tt, w, ph0, ph1, arena, off, S, logS, sme, tid); break;
       }
     } else {
       for (int i = tid; i < (S << w); i += kThreads) {
@@ -333,6 +414,28 @@ __global__ __launch_bounds__(kThreads) void contract_kernel(ContractArgs<real> a
       __syncthreads();
     } else {
       // SINGLE: joint weights c(o, x) into scratch [(o*2 + x)][S]
+      if (sd.n_in <= kFastIn) {
+        const FastIn<real> f = fast_inputs<real, true>(a, sd, steps, mx, S, sme);
+        const real ph0 = phi[(2 * sd.gpos) * S + sme], ph1 = phi[(2 * sd.gpos + 1) * S + sme];
+        auto joint = [&](auto ni) {
+          constexpr int NI = decltype(ni)::value;
+          for (int i = tid; i < (S << w); i += kThreads) {
+            const int o = i >> logS;
+            const real r = rfac(o);
+            real p0 = r * Tt[o] * ph0, p1 = r * Tt[(1 << w) | o] * ph1;
+            fast_pair<real, NI>(f, arena, S, sme, o, p0, p1);
+            scr[(o * 2) * S + sme] = p0;
+            scr[(o * 2 + 1) * S + sme] = p1;
+          }
+        };
+        switch (sd.n_in) {
+          case 0: joint(std::integral_constant<int, 0>{}); break;
+          case 1: joint(std::integral_constant<int, 1>{}); break;
+          case 2: joint(std::integral_constant<int, 2>{}); break;
+          case 3: joint(std::integral_constant<int, 3>{}); break;
+          default: joint(std::integral_constant<int, 4>{}); break;
+        }
+      } else
       for (int i = tid; i < (S << w); i += kThreads) {
         const int o = i >> logS;
         const real r = rfac(o);

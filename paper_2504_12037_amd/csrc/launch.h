@@ -13,6 +13,7 @@ struct ContractArgs {
   const InstDesc *inst;
   const StepDesc *steps;
   const InputDesc *inputs;
+  const uint16_t *gtab;             // gather tables of SINGLE steps' inputs
   const EdgeDesc *edges;
   const real *T;
   const int32_t *fld_ptr;

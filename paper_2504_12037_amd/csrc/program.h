@@ -55,9 +55,12 @@ struct InputDesc {
   int32_t step;       // producing step (local index within the instance)
   int32_t nbits;      // scope size of the message
   int32_t xbit;       // SINGLE: bit of the eliminated vertex in this scope
-  int32_t pad;
+  int32_t gb_off;     // SINGLE: offset of its gather table in gtab, or -1
   int8_t src[kMaxScope];  // scope bit b -> o-bit index, or -1 for x (SINGLE)
 };
+// Gather table of a SINGLE step's input (gtab[gb_off + o], 2^w entries):
+// the entry of the input message that output entry o reads when the
+// eliminated spin is +1; with the spin -1 it reads that entry | 1 << xbit.
 
 struct EdgeDesc {
   int32_t rr;         // local index of the edge among the instance's R-R edges
