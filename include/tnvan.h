@@ -109,6 +109,60 @@ typedef struct {
  * exact in BF16 and take two products.  Ignored by FP64 and BF16 nets. */
 #define TNVAN_FLAG_SPLIT_BF16 8
 
+/* Launch shapes of a net (tnvan_get_tuning, tnvan_set_tuning,
+ * tnvan_autotune).  They change how the work is tiled, not what is computed:
+ * every choice gives the same results up to the summation order of the
+ * kernels involved (within each path's tolerance).  A field set to 0 takes
+ * the library's default rule. */
+#define TNVAN_TUNE_GENERAL 1     /* kinds: the general-step kernel runs */
+#define TNVAN_TUNE_REG_CHAIN 2   /* the register-resident chain kernels run */
+#define TNVAN_TUNE_LDS_CHAIN 4   /* the LDS-staged chain kernels run */
+typedef struct {
+  /* samples per workgroup tile of the general-step kernel (dense and
+   * single-spin steps of non-chain programs), forward and adjoint: 0 or a
+   * power of two 1..64 (the arena stays in LDS when the tile fits it, else
+   * it moves to device memory) */
+  int32_t general_tile_fwd;
+  int32_t general_tile_bwd;
+  /* 16-sample groups per wave of the register-resident chain forward on
+   * chains of 1-2 tiles: 0, 1 or 2 */
+  int32_t chain_groups;
+  /* tnvan_get_tuning only: TNVAN_TUNE_* bits of the kernels the net runs */
+  int32_t kinds;
+  int32_t reserved[4];
+} tnvan_tuning;
+
+/* The launch shapes in effect (defaults resolved; chain_groups 0 until a
+ * batch has been laid out). */
+tnvan_status tnvan_get_tuning(const tnvan_net *net, tnvan_tuning *out);
+/* Request launch shapes (0 = default rule per field).  The next call lays
+ * its tables out again.  Errors: a field out of range or a general tile
+ * whose LDS part does not fit even with the arena in device memory
+ * (TNVAN_E_INVALID; the previous shapes stay). */
+tnvan_status tnvan_set_tuning(tnvan_net *net, const tnvan_tuning *in);
+
+/* Autotuner: on the given batch (the net's own sample counts and spins),
+ * times tnvan_logz_batch for every candidate forward shape and
+ * tnvan_logz_backward for every candidate adjoint shape of the kernels the
+ * net runs (general tiles 1..64 samples, chain groups 1 or 2), one field at
+ * a time with the others at their best so far, each candidate as the mean
+ * of 5 calls after one that lays the tables out (HIP events on `stream`).
+ * A field keeps its default rule unless a candidate is at least 2% faster.
+ * The choice is applied (tnvan_set_tuning) and written to *out.
+ *   spins, grad_logz  dev inputs as tnvan_logz_backward
+ *   logz, dh, dJ, dbeta  dev workspaces the timed calls write (as there)
+ *   cache_path  host path of a JSON cache, or NULL: a key (GPU
+ *               architecture | precision and product form | kernels |
+ *               widest message scope | instances | batch size bucket)
+ *               found there is applied without timing; a new choice is
+ *               added to the file (rewritten through a temporary file)
+ * Synchronises the stream.  Errors: those of the timed calls; an
+ * unwritable cache (TNVAN_E_INVALID, the choice is still applied). */
+tnvan_status tnvan_autotune(tnvan_net *net, const int64_t *n_samples, const int8_t *spins,
+                            const double *grad_logz, double *logz, double *dh, double *dJ,
+                            double *dbeta, const char *cache_path, tnvan_tuning *out,
+                            void *stream);
+
 /* Kernels timed under TNVAN_FLAG_PROFILE. */
 typedef enum {
   TNVAN_KERNEL_CHAIN_FWD_1 = 0,   /* register-resident forward, chains of 1 tile (K, N <= 16) */

@@ -109,6 +109,39 @@ class Net:
         _lib.check(_lib.lib().tnvan_kernel_time(self._h, k, C.byref(ms), C.byref(n)))
         return ms.value / 1e3, int(n.value)
 
+    # ---------------------------------------------------------- launch shapes
+    def get_tuning(self) -> dict:
+        """Launch shapes in effect (tnvan_get_tuning) as a dict."""
+        t = _lib.CTuning()
+        _lib.check(_lib.lib().tnvan_get_tuning(self._h, C.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **shapes):
+        """Request launch shapes (general_tile_fwd, general_tile_bwd,
+        chain_groups; 0 or absent = default rule)."""
+        t = _lib.CTuning()
+        for k, v in shapes.items():
+            if k not in _lib.CTuning.FIELDS:
+                raise KeyError(k)
+            setattr(t, k, int(v))
+        _lib.check(_lib.lib().tnvan_set_tuning(self._h, C.byref(t)))
+
+    def autotune(self, spins: torch.Tensor, grad: torch.Tensor, n_samples,
+                 cache_path: str = None) -> dict:
+        """tnvan_autotune on this batch: times the candidate launch shapes,
+        applies the fastest and returns it (JSON cache at cache_path)."""
+        arr, counts = self._counts(n_samples)
+        spins = spins.to(device="cuda").contiguous()
+        grad = grad.to(device="cuda", dtype=torch.float64).contiguous()
+        logz = torch.empty(max(1, sum(counts)), device="cuda", dtype=torch.float64)
+        dh, dJ, db = self._adjoint_out(None)
+        t = _lib.CTuning()
+        path = None if cache_path is None else str(cache_path).encode()
+        _lib.check(_lib.lib().tnvan_autotune(self._h, arr, _ptr(spins), _ptr(grad), _ptr(logz),
+                                             _ptr(dh), _ptr(dJ), _ptr(db), path, C.byref(t),
+                                             _stream()))
+        return t.as_dict()
+
     def param_count(self, inst: int = 0) -> int:
         n = C.c_int64()
         _lib.check(_lib.lib().tnvan_param_count(self._h, inst, C.byref(n)))

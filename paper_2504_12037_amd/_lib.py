@@ -35,7 +35,8 @@ EXPORTS = ["tnvan_build_network", "tnvan_free_network", "tnvan_last_error",
            "tnvan_free_energy_step",
            "tnvan_free_energy_step_adjoint", "tnvan_program_info", "tnvan_plan",
            "tnvan_plan_width_set",
-           "tnvan_kernel_time", "tnvan_profile_mask"]
+           "tnvan_kernel_time", "tnvan_profile_mask",
+           "tnvan_get_tuning", "tnvan_set_tuning", "tnvan_autotune"]
 
 
 class TnvanError(RuntimeError):
@@ -59,6 +60,19 @@ class COptions(C.Structure):
                 ("deterministic", C.c_int32), ("flags", C.c_int32),
                 ("seed", C.c_uint64)]
 
+
+class CTuning(C.Structure):
+    _fields_ = [("general_tile_fwd", C.c_int32), ("general_tile_bwd", C.c_int32),
+                ("chain_groups", C.c_int32), ("kinds", C.c_int32),
+                ("reserved", C.c_int32 * 4)]
+
+    FIELDS = ("general_tile_fwd", "general_tile_bwd", "chain_groups")
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k in self.FIELDS + ("kinds",)}
+
+
+TUNE_GENERAL, TUNE_REG_CHAIN, TUNE_LDS_CHAIN = 1, 2, 4
 
 _lib = None
 
@@ -95,6 +109,9 @@ def lib():
     L.tnvan_plan_width_set.argtypes = [i32, i32, vp, vp, i32, vp, i32, vp, vp, vp, vp, vp]
     L.tnvan_kernel_time.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(i64)]
     L.tnvan_profile_mask.argtypes = [vp, C.c_uint32]
+    L.tnvan_get_tuning.argtypes = [vp, vp]
+    L.tnvan_set_tuning.argtypes = [vp, vp]
+    L.tnvan_autotune.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.c_char_p, vp, vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("tnvan_free_network", "tnvan_last_error"):

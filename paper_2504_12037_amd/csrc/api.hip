@@ -217,6 +217,7 @@ struct tnvan_net {
   // stream, which does not order with non-blocking streams, so an upload
   // first waits for these
   std::vector<hipStream_t> call_streams;
+  tnvan_tuning tune{};        // requested launch shapes (0: default rule)
   int rs() const { return precision == TNVAN_FP64 ? 8 : 4; }
 };
 
@@ -274,8 +275,13 @@ struct ProfScope {
   }
 };
 
-// Largest S (power of two <= 64) whose tile fits the LDS budget.
-void choose_tiles(tnvan_net *net, bool bwd) {
+// Samples per tile S of the general-step kernel (a power of two <= 64).
+// Default rule: the largest S whose tile, arena included, fits the LDS
+// budget (80 KB, two workgroups per CU); below 4 the arena moves to global
+// memory and S is the largest <= 16 that fits.  A requested S (tuning) is
+// taken with the arena in LDS when it fits the whole LDS, else in global
+// memory; false when even that does not fit.
+bool choose_tiles(tnvan_net *net, bool bwd, int req = 0) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   int maxlds = 65536;
@@ -291,17 +297,32 @@ void choose_tiles(tnvan_net *net, bool bwd) {
   };
   int S = 64;
   bool glob = false;
-  for (; S >= 1; S >>= 1)
-    if (worst_of(S, false) <= budget) break;
-  if (S < 4) {
-    glob = true;
-    for (S = 64; S >= 1; S >>= 1)
-      if (worst_of(S, true) <= budget && S <= 16) break;
-    if (S < 1) S = 1;
+  if (req > 0) {
+    S = req;
+    glob = worst_of(S, false) > (size_t)maxlds;
+    if (glob && worst_of(S, true) > (size_t)maxlds) return false;
+  } else {
+    for (; S >= 1; S >>= 1)
+      if (worst_of(S, false) <= budget) break;
+    if (S < 4) {
+      glob = true;
+      for (S = 64; S >= 1; S >>= 1)
+        if (worst_of(S, true) <= budget && S <= 16) break;
+      if (S < 1) S = 1;
+    }
   }
   const size_t worst = worst_of(S, glob);
   if (bwd) { net->S_bwd = S; net->glob_bwd = glob; net->lds_bwd = worst; }
   else { net->S_fwd = S; net->glob_fwd = glob; net->lds_fwd = worst; }
+  return true;
+}
+
+// 16-sample groups per wave of the register-resident forward on chains of
+// 1-2 tiles (the tuned value, else two when that still leaves a wave per
+// SIMD for waves2 two-group waves, else one)
+int chain_groups(const tnvan_net *net, int64_t waves2) {
+  if (net->tune.chain_groups > 0) return net->tune.chain_groups;
+  return waves2 >= 1024 ? 2 : 1;
 }
 
 tnvan_status set_batch(tnvan_net *net, const int64_t *n_samples) {
@@ -384,7 +405,7 @@ tnvan_status ensure_chain_tasks(tnvan_net *net) {
     int64_t waves2 = 0;
     for (int q = 0; q < net->n_inst; ++q)
       if (net->use_chain[q]) waves2 += net->P.cinst[q].n_chains * ((net->nkey[q] + 31) / 32);
-    net->sg = waves2 >= 1024 ? 2 : 1;
+    net->sg = chain_groups(net, waves2);
   }
   std::vector<int32_t> clist;
   std::vector<int64_t> coff(net->n_inst, 0);
@@ -1055,6 +1076,26 @@ tnvan_status check_net(const tnvan_net *net) {
 
 }  // namespace
 
+namespace tnvan {
+
+tnvan_status net_signature(const tnvan_net *net, std::string &out) {
+  if (tnvan_status s = check_net(net)) return s;
+  tnvan_tuning t{};
+  if (tnvan_status s = tnvan_get_tuning(net, &t)) return s;
+  int maxw = 0;
+  for (auto &D : net->P.insts) maxw = std::max(maxw, (int)D.max_w);
+  static const char *prec[] = {"fp64", "fp32", "bf16"};
+  out = std::string(prec[net->precision]) + (net->split ? "+split" : "") + "|k" +
+        std::to_string(t.kinds) + "|w" + std::to_string(maxw) + "|n" + std::to_string(net->n_inst);
+  return TNVAN_OK;
+}
+
+int net_instances(const tnvan_net *net) { return net ? net->n_inst : 0; }
+
+void set_last_error(const char *msg) { g_err = msg; }
+
+}  // namespace tnvan
+
 extern "C" {
 
 const char *tnvan_last_error(void) { return g_err.c_str(); }
@@ -1643,7 +1684,7 @@ tnvan_status tnvan_logz_batch_noalloc(tnvan_net *net, const int64_t *n_samples,
     maxB = std::max(maxB, B);
     max_nch = std::max(max_nch, nch);
   }
-  const int sg = waves2 >= 1024 ? 2 : 1;
+  const int sg = chain_groups(net, waves2);
   int64_t nt = 0;
   for (int gi = 0; gi < 3; ++gi) {
     const int rt = 1 << gi;
@@ -1735,6 +1776,50 @@ tnvan_status tnvan_logz_batch_noalloc(tnvan_net *net, const int64_t *n_samples,
   HIPCHK(launch_chain_sum(net->inst.as<InstDesc>(), net->cinst.as<ChainInst>(), L.d_clist,
                           net->n_inst, L.d_B, L.d_sample_off, L.d_cpart_off, cpart, L.d_f_off,
                           fabp, logz, st));
+  return TNVAN_OK;
+}
+
+tnvan_status tnvan_get_tuning(const tnvan_net *net, tnvan_tuning *out) {
+  if (tnvan_status s = check_net(net)) return s;
+  if (!out) return set_err(TNVAN_E_INVALID, "out is NULL");
+  *out = tnvan_tuning{};
+  bool gen = false, chain = false;
+  for (int q = 0; q < net->n_inst; ++q) (net->use_chain[q] ? chain : gen) = true;
+  out->kinds = (gen ? TNVAN_TUNE_GENERAL : 0) | (chain && net->rfwd ? TNVAN_TUNE_REG_CHAIN : 0) |
+               (chain && !net->rfwd ? TNVAN_TUNE_LDS_CHAIN : 0);
+  out->general_tile_fwd = gen ? net->S_fwd : 0;
+  out->general_tile_bwd = gen ? net->S_bwd : 0;
+  out->chain_groups = chain && net->rfwd ? (net->tune.chain_groups > 0 ? net->tune.chain_groups
+                                                                       : net->ckey.empty() ? 0 : net->sg)
+                                         : 0;
+  return TNVAN_OK;
+}
+
+tnvan_status tnvan_set_tuning(tnvan_net *net, const tnvan_tuning *in) {
+  if (tnvan_status s = check_net(net)) return s;
+  if (!in) return set_err(TNVAN_E_INVALID, "tuning is NULL");
+  auto tile_ok = [](int v) { return v == 0 || (v >= 1 && v <= 64 && (v & (v - 1)) == 0); };
+  if (!tile_ok(in->general_tile_fwd) || !tile_ok(in->general_tile_bwd))
+    return set_err(TNVAN_E_INVALID, "general tiles must be 0 or a power of two up to 64");
+  if (in->chain_groups < 0 || in->chain_groups > 2)
+    return set_err(TNVAN_E_INVALID, "chain_groups must be 0, 1 or 2");
+  const tnvan_tuning old = net->tune;
+  net->tune = tnvan_tuning{};
+  net->tune.general_tile_fwd = in->general_tile_fwd;
+  net->tune.general_tile_bwd = in->general_tile_bwd;
+  net->tune.chain_groups = in->chain_groups;
+  if (!choose_tiles(net, false, in->general_tile_fwd) || !choose_tiles(net, true, in->general_tile_bwd)) {
+    net->tune = old;
+    choose_tiles(net, false, old.general_tile_fwd);
+    choose_tiles(net, true, old.general_tile_bwd);
+    return set_err(TNVAN_E_INVALID, "a requested general tile does not fit the LDS");
+  }
+  // every per-call table is laid out again at the next call (after a wait
+  // for the work queued with the old layout), and a recorded step is stale
+  net->tc_fwd.key.clear();
+  net->tc_bwd.key.clear();
+  net->ckey.clear();
+  g_buf_gen.fetch_add(1);
   return TNVAN_OK;
 }
 

@@ -3,6 +3,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
+#include "../../include/tnvan.h"
 #include "program.h"
 
 namespace tnvan {
@@ -286,6 +289,13 @@ struct OptArgs {
   const int32_t *step_ctr;   // already counting this step
 };
 hipError_t launch_adam_step(const OptArgs &a, int n_inst, int64_t max_pc, hipStream_t st);
+
+// The net's signature for the autotuner's cache (precision, product form,
+// kernels, widest message scope, instance count), its instance count, and
+// the thread-local error message of the C ABI.
+tnvan_status net_signature(const tnvan_net *net, std::string &out);
+int net_instances(const tnvan_net *net);
+void set_last_error(const char *msg);
 
 }  // namespace tnvan
 

@@ -1,0 +1,117 @@
+"""Launch shapes and the autotuner (tnvan_set_tuning, tnvan_autotune)
+through the C ABI.
+
+A launch shape changes how the samples are tiled, not what is computed per
+sample: logZ must be the same bit for bit under every shape, and the
+adjoint (whose batch sums run in tile order) must meet the error model of
+adjtol.py against the oracle.  The autotuner must apply its choice, report
+it, and read it back from its cache."""
+
+import json
+
+import numpy as np
+import pytest
+
+import synthetic as S
+from adjtol import check_vjp
+from oracle import ising as OI
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda().reshape(-1)
+
+
+def _mixed():
+    # a general-step instance (random regular graph with fields) and a
+    # lattice on the register-resident chain kernels
+    return [S.c4_small_copies(limit=3)[2], S.c4_rrg(),
+            S.lattice_column_split(S.lattice_2d(8, seed=4, h_var=0.1), [5])]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_every_launch_shape_keeps_parity(prec):
+    from paper_2504_12037_amd import Net
+    insts = _mixed()
+    Bs = [300, 517, 1000]
+    sp = [S.uniform_spins(b, i.n_width, 31 + k) for k, (b, i) in enumerate(zip(Bs, insts))]
+    flat = _dev(np.concatenate([x.reshape(-1) for x in sp]))
+    g = np.concatenate([np.random.default_rng(k).standard_normal(b) for k, b in enumerate(Bs)])
+    net = Net(insts, precision=prec)
+    ref = net.logz(flat, Bs).clone()
+    wants = [OI.logz_r_vjp(inst, s, g[sum(Bs[:k]):sum(Bs[:k + 1])])
+             for k, (inst, s) in enumerate(zip(insts, sp))]
+    shapes = [dict(general_tile_fwd=t, general_tile_bwd=u, chain_groups=c)
+              for t, u, c in [(1, 1, 1), (4, 2, 2), (16, 8, 1), (64, 64, 2), (2, 32, 0)]]
+    from paper_2504_12037_amd import TnvanError
+    tried = 0
+    for sh in shapes:
+        print(f"\n[tuning] prec={prec} {sh}", flush=True)
+        before = net.get_tuning()
+        try:
+            net.set_tuning(**sh)
+        except TnvanError as e:
+            # a tile whose LDS part does not fit: refused, nothing changed
+            assert e.code == 1 and net.get_tuning() == before
+            continue
+        tried += 1
+        got = net.get_tuning()
+        for k in ("general_tile_fwd", "general_tile_bwd"):
+            assert got[k] == sh[k]
+        assert torch.equal(net.logz(flat, Bs), ref)
+        dh, dJ, db = (x.cpu().numpy() for x in net.backward(flat, _dev(g), Bs))
+        ho = eo = so = 0
+        for k, (inst, b) in enumerate(zip(insts, Bs)):
+            check_vjp((dh[ho:ho + inst.n], dJ[eo:eo + inst.n_edges], db[k]), wants[k], inst,
+                      g[so:so + b], prec, (sh, k))
+            ho += inst.n
+            eo += inst.n_edges
+            so += b
+    assert tried >= 3
+
+
+def test_set_tuning_refuses_bad_shapes():
+    from paper_2504_12037_amd import Net, TnvanError
+    net = Net([S.c4_rrg()], precision="fp32")
+    before = net.get_tuning()
+    for bad in (dict(general_tile_fwd=3), dict(general_tile_bwd=128), dict(chain_groups=3)):
+        with pytest.raises(TnvanError):
+            net.set_tuning(**bad)
+    assert net.get_tuning() == before
+
+
+def test_autotune_applies_and_caches(tmp_path):
+    from paper_2504_12037_amd import Net
+    insts = _mixed()
+    Bs = [256, 4096, 2048]
+    sp = [S.uniform_spins(b, i.n_width, 61 + k) for k, (b, i) in enumerate(zip(Bs, insts))]
+    flat = _dev(np.concatenate([x.reshape(-1) for x in sp]))
+    g = _dev(np.concatenate([np.full(b, 1.0 / b) for b in Bs]))
+    cache = tmp_path / "tune.json"
+    net = Net(insts, precision="fp32", flags=Net.FLAG_SPLIT_BF16)
+    print("\n[autotune] timing", flush=True)
+    chosen = net.autotune(flat, g, Bs, cache_path=cache)
+    print(f"[autotune] chosen {chosen}", flush=True)
+    got = net.get_tuning()
+    assert got == chosen
+    assert chosen["kinds"] == 3
+    entries = json.loads(cache.read_text())
+    assert len(entries) == 1
+    (key, val), = entries.items()
+    assert key.startswith("gfx950") and "fp32+split" in key
+    # results after tuning, against the oracle
+    lz = net.logz(flat, Bs).cpu().numpy()
+    off = 0
+    for inst, b, s in zip(insts, Bs, sp):
+        want = OI.logz_r_elimination(inst, s[:40])
+        assert np.abs(lz[off:off + 40] - want).max() / inst.n <= 1e-5
+        off += b
+    # a second net of the same signature takes the cached shapes
+    net2 = Net(insts, precision="fp32", flags=Net.FLAG_SPLIT_BF16)
+    again = net2.autotune(flat, g, Bs, cache_path=cache)
+    for k in ("general_tile_fwd", "general_tile_bwd", "chain_groups"):
+        if val[k]:
+            assert again[k] == val[k]
+    assert json.loads(cache.read_text()) == entries
