@@ -108,6 +108,12 @@ typedef struct {
  * at 16x the multiply rate of the FP32 products.  Spin-sign operands are
  * exact in BF16 and take two products.  Ignored by FP64 and BF16 nets. */
 #define TNVAN_FLAG_SPLIT_BF16 8
+/* tnvan_free_energy_step(_adjoint) waits for its step (eager or replayed),
+ * and returns TNVAN_E_NONFINITE when any sample's free energy f_b (Eq. 9)
+ * was not finite (a NaN or infinite parameter, log-probability or logZ);
+ * the step's work has run, and the flags are cleared for the next call.
+ * Without the flag the step does not wait and reports nothing. */
+#define TNVAN_FLAG_CHECK_FINITE 16
 
 /* Launch shapes of a net (tnvan_get_tuning, tnvan_set_tuning,
  * tnvan_autotune).  They change how the work is tiled, not what is computed:
@@ -207,6 +213,23 @@ tnvan_status tnvan_get_params(tnvan_net *net, int32_t inst, float *dst_dev,
  * Used for checkpoints and for checking the REINFORCE gradient. */
 tnvan_status tnvan_get_state(tnvan_net *net, int32_t inst, int32_t which,
                              float *dst_dev, void *stream);
+
+/* Restore one state vector of instance i from device memory (float32,
+ * param_count entries, stream-ordered): which = 0 parameters (unlike
+ * tnvan_set_params, the Adam moments and the step counter stay), 2 Adam
+ * first moment, 3 Adam second moment.  With tnvan_set_step this resumes
+ * Algorithm 1 from a checkpoint taken with tnvan_get_state and
+ * tnvan_get_step: the continued run equals the uninterrupted one bit for bit.
+ * Errors: which 1 (the gradient is recomputed every step) or out of range
+ * (TNVAN_E_INVALID). */
+tnvan_status tnvan_set_state(tnvan_net *net, int32_t inst, int32_t which, const float *src_dev,
+                             void *stream);
+
+/* The step counter of instance i: the number of training steps taken with
+ * samples (Adam's t, and the step word of the Philox counter of q's
+ * uniforms).  get waits for the stream; set is stream-ordered (step >= 0). */
+tnvan_status tnvan_get_step(tnvan_net *net, int32_t inst, int32_t *step, void *stream);
+tnvan_status tnvan_set_step(tnvan_net *net, int32_t inst, int32_t step, void *stream);
 
 /* Ancestral sampling from q (Sec. 3, Eq. 8): for each position i in the
  * order of width_set, p_i = sigmoid(logit_i(s_<i)) and s_i = +1 iff

@@ -93,6 +93,7 @@ class Net:
     FLAG_PROFILE = 2
     FLAG_GRAPH = 4
     FLAG_SPLIT_BF16 = 8
+    FLAG_CHECK_FINITE = 16
 
     def profile_only(self, kernels):
         """Time only these kernels (names or ids of KERNELS) from now on."""
@@ -163,6 +164,36 @@ class Net:
         t = torch.empty(self.param_count(inst), device="cuda", dtype=torch.float32)
         _lib.check(_lib.lib().tnvan_get_state(self._h, inst, which, _ptr(t), _stream()))
         return t
+
+    def set_state(self, inst: int, which: int, value: torch.Tensor):
+        """0 params (moments and step counter kept), 2 Adam m, 3 Adam v."""
+        t = value.to(device="cuda", dtype=torch.float32).contiguous()
+        assert t.numel() == self.param_count(inst)
+        _lib.check(_lib.lib().tnvan_set_state(self._h, inst, which, _ptr(t), _stream()))
+        torch.cuda.current_stream().synchronize()
+
+    def get_step(self, inst: int = 0) -> int:
+        v = C.c_int32()
+        _lib.check(_lib.lib().tnvan_get_step(self._h, inst, C.byref(v), _stream()))
+        return int(v.value)
+
+    def set_step(self, inst: int, step: int):
+        _lib.check(_lib.lib().tnvan_set_step(self._h, inst, int(step), _stream()))
+
+    def checkpoint(self) -> list:
+        """Per instance (params, Adam m, Adam v, step) on the host."""
+        return [(self.get_state(k, 0).cpu(), self.get_state(k, 2).cpu(),
+                 self.get_state(k, 3).cpu(), self.get_step(k))
+                for k in range(len(self.instances))]
+
+    def restore(self, ckpt: list):
+        """Resume from checkpoint() (bit for bit)."""
+        for k, (p, m, v, t) in enumerate(ckpt):
+            self.set_state(k, 0, p)
+            self.set_state(k, 2, m)
+            self.set_state(k, 3, v)
+            self.set_step(k, t)
+        torch.cuda.current_stream().synchronize()
 
     # ----------------------------------------------------------- entry points
     def sample(self, n_samples, uniforms: torch.Tensor = None):

@@ -28,7 +28,7 @@ STATUS = {0: "TNVAN_OK", 1: "TNVAN_E_INVALID", 2: "TNVAN_E_WIDTH",
 
 EXPORTS = ["tnvan_build_network", "tnvan_free_network", "tnvan_last_error",
            "tnvan_param_count", "tnvan_set_params", "tnvan_get_params",
-           "tnvan_get_state",
+           "tnvan_get_state", "tnvan_set_state", "tnvan_get_step", "tnvan_set_step",
            "tnvan_sample", "tnvan_logz_batch", "tnvan_logz_batch_noalloc",
            "tnvan_logz_backward",
            "tnvan_logz_and_backward", "tnvan_exact_free_energy", "tnvan_observables",
@@ -95,6 +95,9 @@ def lib():
     L.tnvan_set_params.argtypes = [vp, i32, vp, vp]
     L.tnvan_get_params.argtypes = [vp, i32, vp, vp]
     L.tnvan_get_state.argtypes = [vp, i32, i32, vp, vp]
+    L.tnvan_set_state.argtypes = [vp, i32, i32, vp, vp]
+    L.tnvan_get_step.argtypes = [vp, i32, C.POINTER(i32), vp]
+    L.tnvan_set_step.argtypes = [vp, i32, i32, vp]
     L.tnvan_sample.argtypes = [vp, vp, vp, vp, vp, vp]
     L.tnvan_logz_batch.argtypes = [vp, vp, vp, vp, vp]
     L.tnvan_logz_batch_noalloc.argtypes = [vp, vp, vp, vp, vp]

@@ -135,6 +135,8 @@ struct tnvan_net {
   std::vector<int64_t> param_count;
   int64_t param_total = 0;
   DBuf d_mi, params, adam_m, adam_v, grad, step_ctr;
+  DBuf nonfinite;             // [n_inst] flags of the free-energy kernel
+  bool check_finite = false;  // TNVAN_FLAG_CHECK_FINITE
   // per-call tables
   std::vector<int64_t> nkey;
   std::vector<int64_t> sample_off, spin_off;
@@ -893,6 +895,7 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
   const bool fused = net->mgrad && sizeof(real) == 4;
   f.finish = !fused;
   f.step_ctr = net->step_ctr.as<int32_t>();
+  f.nonfinite = net->nonfinite.as<int32_t>();
   HIPCHK(launch_free<real>(f, net->n_inst, st));
   // Adam on every instance (one launch, after the REINFORCE gradient)
   OptArgs o{};
@@ -1115,6 +1118,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   net->profile = (opt->flags & TNVAN_FLAG_PROFILE) != 0;
   net->use_graph = (opt->flags & TNVAN_FLAG_GRAPH) != 0;
   net->split = (opt->flags & TNVAN_FLAG_SPLIT_BF16) != 0 && net->precision == TNVAN_FP32;
+  net->check_finite = (opt->flags & TNVAN_FLAG_CHECK_FINITE) != 0;
   net->n_inst = n_inst;
   for (int q = 0; q < n_inst; ++q) {
     std::string msg;
@@ -1250,6 +1254,9 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   if ((e = net->tickets.ensure(sizeof(int32_t) * n_inst)) ||
       (e = hipMemset(net->tickets.p, 0, sizeof(int32_t) * n_inst)))
     return fail(e, "tickets");
+  if ((e = net->nonfinite.ensure(sizeof(int32_t) * n_inst)) ||
+      (e = hipMemset(net->nonfinite.p, 0, sizeof(int32_t) * n_inst)))
+    return fail(e, "non-finite flags");
   {
     std::vector<float> fj(P.fld_J.begin(), P.fld_J.end()), hr(P.hR.begin(), P.hR.end());
     UP2(fld_J32, fj) UP2(hR32, hr) UP2(fld_wr, P.fld_wr) UP2(cinst, P.cinst)
@@ -1364,7 +1371,7 @@ void tnvan_free_network(tnvan_net *net) {
                  &net->btask_inst, &net->btask_chain, &net->btask_start, &net->Tl, &net->Tbl,
                  &net->cedges, &net->ckpt, &net->Tr, &net->Tq, &net->Trb, &net->xcol,
                  &net->cf_w, &net->cf_r, &net->cf_J, &net->Tsx, &net->Ts3, &net->Tdq, &net->Ubuf, &net->vjp_part,
-                 &net->tickets, &net->col_out, &net->pcoef_out, &net->w_xspins, &net->w_xlogz, &net->w_xpart, &net->ww_e, &net->d_wv, &net->w_og,
+                 &net->tickets, &net->nonfinite, &net->col_out, &net->pcoef_out, &net->w_xspins, &net->w_xlogz, &net->w_xpart, &net->ww_e, &net->d_wv, &net->w_og,
                  &net->w_ostats, &net->w_odb, &net->fabp, &net->u_off,
                  &net->f_off,
                  &net->mpack, &net->mtask_inst, &net->mtask_start, &net->mg_task_inst,
@@ -1425,6 +1432,44 @@ tnvan_status tnvan_get_state(tnvan_net *net, int32_t inst, int32_t which, float 
   HIPCHK(hipMemcpyAsync(dst, src->as<float>() + net->mi[inst].param_off,
                         net->param_count[inst] * sizeof(float), hipMemcpyDeviceToDevice,
                         static_cast<hipStream_t>(stream)));
+  return TNVAN_OK;
+}
+
+tnvan_status tnvan_set_state(tnvan_net *net, int32_t inst, int32_t which, const float *src,
+                             void *stream) {
+  if (tnvan_status s = check_net(net)) return s;
+  if (inst < 0 || inst >= net->n_inst || !src) return set_err(TNVAN_E_INVALID, "bad instance or source");
+  DBuf *dst = which == 0 ? &net->params : which == 2 ? &net->adam_m : which == 3 ? &net->adam_v : nullptr;
+  if (!dst) return set_err(TNVAN_E_INVALID, "state %d cannot be set (0, 2 or 3)", which);
+  if (tnvan_status s = check_device({src})) return s;
+  HIPCHK(hipMemcpyAsync(dst->as<float>() + net->mi[inst].param_off, src,
+                        net->param_count[inst] * sizeof(float), hipMemcpyDeviceToDevice,
+                        static_cast<hipStream_t>(stream)));
+  if (which == 0) {
+    // as tnvan_set_params: the packed tables follow at the next use
+    net->pack_valid = false;
+    g_buf_gen.fetch_add(1);
+  }
+  return TNVAN_OK;
+}
+
+tnvan_status tnvan_get_step(tnvan_net *net, int32_t inst, int32_t *step, void *stream) {
+  if (tnvan_status s = check_net(net)) return s;
+  if (inst < 0 || inst >= net->n_inst || !step) return set_err(TNVAN_E_INVALID, "bad instance or output");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int32_t v = 0;
+  HIPCHK(hipMemcpyAsync(&v, net->step_ctr.as<int32_t>() + inst, sizeof(int32_t),
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  *step = v;
+  return TNVAN_OK;
+}
+
+tnvan_status tnvan_set_step(tnvan_net *net, int32_t inst, int32_t step, void *stream) {
+  if (tnvan_status s = check_net(net)) return s;
+  if (inst < 0 || inst >= net->n_inst || step < 0) return set_err(TNVAN_E_INVALID, "bad instance or step");
+  HIPCHK(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(net->step_ctr.as<int32_t>() + inst),
+                           step, 1, static_cast<hipStream_t>(stream)));
   return TNVAN_OK;
 }
 
@@ -1609,9 +1654,33 @@ tnvan_status step_entry(tnvan_net *net, const int64_t *n_samples, float lr, doub
 
 }  // namespace
 
+namespace {
+
+// TNVAN_FLAG_CHECK_FINITE: after the step (eager or replayed), wait for it,
+// read the free-energy kernel's per-instance flags and clear them
+tnvan_status finite_check(tnvan_net *net, void *stream) {
+  if (!net->check_finite) return TNVAN_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<int32_t> fl(net->n_inst, 0);
+  HIPCHK(hipMemcpyAsync(fl.data(), net->nonfinite.p, sizeof(int32_t) * net->n_inst,
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int q = 0; q < net->n_inst; ++q)
+    if (fl[q]) {
+      HIPCHK(hipMemsetAsync(net->nonfinite.p, 0, sizeof(int32_t) * net->n_inst, st));
+      HIPCHK(hipStreamSynchronize(st));
+      return set_err(TNVAN_E_NONFINITE, "instance %d: a non-finite free energy f_b (Eq. 9) in "
+                                        "this step", q);
+    }
+  return TNVAN_OK;
+}
+
+}  // namespace
+
 tnvan_status tnvan_free_energy_step(tnvan_net *net, const int64_t *n_samples, float lr,
                                     double *stats, int8_t *spins_out, void *stream) {
-  return step_entry(net, n_samples, lr, stats, spins_out, nullptr, stream);
+  if (tnvan_status s = step_entry(net, n_samples, lr, stats, spins_out, nullptr, stream)) return s;
+  return finite_check(net, stream);
 }
 
 tnvan_status tnvan_free_energy_step_adjoint(tnvan_net *net, const int64_t *n_samples, float lr,
@@ -1623,7 +1692,8 @@ tnvan_status tnvan_free_energy_step_adjoint(tnvan_net *net, const int64_t *n_sam
   adj.dh = dh;
   adj.dJ = dJ;
   adj.dbeta = dbeta;
-  return step_entry(net, n_samples, lr, stats, spins_out, &adj, stream);
+  if (tnvan_status s = step_entry(net, n_samples, lr, stats, spins_out, &adj, stream)) return s;
+  return finite_check(net, stream);
 }
 
 tnvan_status tnvan_logz_and_backward(tnvan_net *net, const int64_t *n_samples,

@@ -235,6 +235,7 @@ struct FreeArgs {
   double *stats;             // out [n_inst][4]
   int32_t *done;             // [n_inst] completion tickets, zero between launches
   int32_t *step_ctr;         // advanced by one per instance, or null
+  int32_t *nonfinite;        // [n_inst] set to 1 where some f_b is not finite, or null
 };
 template <typename real>
 hipError_t launch_free(const FreeArgs<real> &a, int n_inst, hipStream_t st);

@@ -698,6 +698,7 @@ __global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
       const double lqb = cur.lq * ib;
       const double f = et + lqb;
       a.f[mi.sample_off + b] = f;
+      if (a.nonfinite && !__builtin_isfinite(f)) a.nonfinite[q] = 1;
       acc[0] += f; acc[1] += f * f; acc[2] += et; acc[3] += lqb;
     }
   }

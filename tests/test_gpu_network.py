@@ -345,3 +345,69 @@ def test_training_with_an_instance_left_empty(prec, split):
             d = np.abs(net.get_params(k).cpu().numpy() - th).max()
             dm = np.abs(net.get_state(k, 2).cpu().numpy() - m).max()
             assert d <= 1e-4 and dm <= 1e-5, (it, k, d, dm)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_nonfinite_free_energy_is_reported(graph):
+    # one NaN parameter makes every f_b of its instance NaN: with
+    # TNVAN_FLAG_CHECK_FINITE the step reports TNVAN_E_NONFINITE (eager and
+    # replayed), the flag clears, and finite parameters step normally again
+    from paper_2504_12037_amd import Net, TnvanError
+    insts = [S.c1_small_lattice(16), S.lattice_column_split(S.lattice_2d(8, seed=2), [5], hidden=16)]
+    Bs = [256, 128]
+    flags = Net.FLAG_CHECK_FINITE | (Net.FLAG_GRAPH if graph else 0)
+    net = _net(insts, "fp32", seed=5, flags=flags)
+    good = [_theta(i.n_width, i.hidden, 20 + k, 0.1) for k, i in enumerate(insts)]
+    for k, th in enumerate(good):
+        net.set_params(k, torch.from_numpy(th))
+    for _ in range(3):
+        net.free_energy_step(Bs, 1e-3)
+    bad = good[1].copy()
+    n1, H1 = insts[1].n_width, insts[1].hidden
+    bad[H1 * n1 + H1 + n1 * H1] = np.nan      # b2[0], the first logit's bias
+    net.set_params(1, torch.from_numpy(bad))
+    print(f"\n[nonfinite] graph={graph}", flush=True)
+    for _ in range(2):      # eager (and recorded), then replayed
+        with pytest.raises(TnvanError) as e:
+            net.free_energy_step(Bs, 1e-3)
+        assert e.value.code == 6 and "instance 1" in str(e.value)
+    net.set_params(1, torch.from_numpy(good[1]))
+    stats, _ = net.free_energy_step(Bs, 1e-3)
+    assert np.all(np.isfinite(stats.cpu().numpy()))
+    # without the flag the step does not look
+    plain = _net(insts, "fp32", seed=5)
+    for k, th in enumerate(good):
+        plain.set_params(k, torch.from_numpy(th))
+    plain.set_params(1, torch.from_numpy(bad))
+    st2, _ = plain.free_energy_step(Bs, 1e-3)
+    assert np.isnan(st2.cpu().numpy()[1, 0])
+
+
+@pytest.mark.parametrize("prec,split", [("fp32", True), ("fp64", False)])
+def test_checkpoint_and_resume_bit_for_bit(prec, split):
+    # Algorithm 1 resumed from a checkpoint (parameters, Adam moments, step
+    # counter) in a new net continues exactly as the uninterrupted run
+    from paper_2504_12037_amd import Net
+    insts = [S.c1_small_lattice(16),
+             S.lattice_column_split(S.lattice_2d(12, seed=6), [5, 9], hidden=32)]
+    Bs = [384, 256]
+    fl = Net.FLAG_SPLIT_BF16 if split else 0
+    a = _net(insts, prec, seed=77, flags=fl)
+    for k, inst in enumerate(insts):
+        a.set_params(k, torch.from_numpy(_theta(inst.n_width, inst.hidden, 40 + k, 0.2)))
+    for _ in range(3):
+        a.free_energy_step(Bs, 1e-2)
+    ck = a.checkpoint()
+    assert [c[3] for c in ck] == [3, 3]
+    b = _net(insts, prec, seed=77, flags=fl)
+    b.restore(ck)
+    print(f"\n[resume] prec={prec} split={split}", flush=True)
+    for it in range(3):
+        sa, _ = a.free_energy_step(Bs, 1e-2)
+        sb, _ = b.free_energy_step(Bs, 1e-2)
+        torch.cuda.synchronize()
+        assert torch.equal(sa, sb), it
+    for k in range(len(insts)):
+        for which in (0, 2, 3):
+            assert torch.equal(a.get_state(k, which), b.get_state(k, which)), (k, which)
+        assert a.get_step(k) == b.get_step(k) == 6
