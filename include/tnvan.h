@@ -86,6 +86,11 @@ typedef struct {
   int32_t deterministic;      /* reserved: every reduction is ordered */
   int32_t flags;              /* TNVAN_FLAG_* bits, 0 for the defaults */
   uint64_t seed;              /* key of the Philox4x32-10 stream of q */
+  /* adjoint checkpoint interval k of the register-resident chain kernels:
+   * the chain state is stored every k steps and the others are recomputed
+   * from the checkpoint in the reverse walk (0 or 1: every step; 2, 4, 8).
+   * Same results bit for bit; fewer HBM bytes, more work. */
+  int32_t checkpoint_every;
 } tnvan_options;
 
 /* Run chains of narrow dense steps in the LDS-staged transfer-matrix kernels
@@ -135,7 +140,10 @@ typedef struct {
   int32_t chain_groups;
   /* tnvan_get_tuning only: TNVAN_TUNE_* bits of the kernels the net runs */
   int32_t kinds;
-  int32_t reserved[4];
+  /* adjoint checkpoint interval of the register-resident chain kernels
+   * (0: the tnvan_options value; 1, 2, 4, 8) */
+  int32_t checkpoint_every;
+  int32_t reserved[3];
 } tnvan_tuning;
 
 /* The launch shapes in effect (defaults resolved; chain_groups 0 until a
@@ -150,7 +158,8 @@ tnvan_status tnvan_set_tuning(tnvan_net *net, const tnvan_tuning *in);
 /* Autotuner: on the given batch (the net's own sample counts and spins),
  * times tnvan_logz_batch for every candidate forward shape and
  * tnvan_logz_backward for every candidate adjoint shape of the kernels the
- * net runs (general tiles 1..64 samples, chain groups 1 or 2), one field at
+ * net runs (general tiles 1..64 samples, chain groups 1 or 2, adjoint
+ * checkpoint intervals 1, 2, 4), one field at
  * a time with the others at their best so far, each candidate as the mean
  * of 5 calls after one that lays the tables out (HIP events on `stream`).
  * A field keeps its default rule unless a candidate is at least 2% faster.

@@ -36,7 +36,8 @@ class Net:
     """One or more compiled instances sharing a device program."""
 
     def __init__(self, instances: Sequence, precision: str = "fp32",
-                 max_width: int = 14, seed: int = 0, flags: int = 0):
+                 max_width: int = 14, seed: int = 0, flags: int = 0,
+                 checkpoint_every: int = 0):
         L = _lib.lib()
         self.instances = list(instances)
         self.precision = precision
@@ -44,7 +45,8 @@ class Net:
         arr = (_lib.CInstance * len(self.instances))()
         for k, inst in enumerate(self.instances):
             arr[k] = _lib.make_cinstance(inst, keep)
-        opt = _lib.COptions(_lib._PREC[precision], int(max_width), 1, int(flags), int(seed))
+        opt = _lib.COptions(_lib._PREC[precision], int(max_width), 1, int(flags), int(seed),
+                            int(checkpoint_every))
         h = C.c_void_p()
         _lib.check(L.tnvan_build_network(arr, len(self.instances), C.byref(opt),
                                          C.byref(h)))

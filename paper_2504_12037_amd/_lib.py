@@ -58,15 +58,15 @@ class CInstance(C.Structure):
 class COptions(C.Structure):
     _fields_ = [("precision", C.c_int32), ("max_width", C.c_int32),
                 ("deterministic", C.c_int32), ("flags", C.c_int32),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("checkpoint_every", C.c_int32)]
 
 
 class CTuning(C.Structure):
     _fields_ = [("general_tile_fwd", C.c_int32), ("general_tile_bwd", C.c_int32),
                 ("chain_groups", C.c_int32), ("kinds", C.c_int32),
-                ("reserved", C.c_int32 * 4)]
+                ("checkpoint_every", C.c_int32), ("reserved", C.c_int32 * 3)]
 
-    FIELDS = ("general_tile_fwd", "general_tile_bwd", "chain_groups")
+    FIELDS = ("general_tile_fwd", "general_tile_bwd", "chain_groups", "checkpoint_every")
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k in self.FIELDS + ("kinds",)}

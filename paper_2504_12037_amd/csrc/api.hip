@@ -220,6 +220,7 @@ struct tnvan_net {
   // first waits for these
   std::vector<hipStream_t> call_streams;
   tnvan_tuning tune{};        // requested launch shapes (0: default rule)
+  int rk_build = 1;           // adjoint checkpoint interval from the options
   int rs() const { return precision == TNVAN_FP64 ? 8 : 4; }
 };
 
@@ -1119,6 +1120,14 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   net->use_graph = (opt->flags & TNVAN_FLAG_GRAPH) != 0;
   net->split = (opt->flags & TNVAN_FLAG_SPLIT_BF16) != 0 && net->precision == TNVAN_FP32;
   net->check_finite = (opt->flags & TNVAN_FLAG_CHECK_FINITE) != 0;
+  {
+    const int k = opt->checkpoint_every;
+    if (k != 0 && k != 1 && k != 2 && k != 4 && k != 8) {
+      delete net;
+      return set_err(TNVAN_E_INVALID, "checkpoint_every must be 0, 1, 2, 4 or 8");
+    }
+    net->rk_build = k > 1 ? k : 1;
+  }
   net->n_inst = n_inst;
   for (int q = 0; q < n_inst; ++q) {
     std::string msg;
@@ -1284,6 +1293,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
     bool rq = true;
     lim.kbuf = 16;
     lim.kseg = 1;
+    lim.rk = net->rk_build;
     for (int q = 0; q < n_inst; ++q) {
       const ChainInst &C = P.cinst[q];
       if (net->precision == TNVAN_FP64 || !C.ok) continue;
@@ -1862,6 +1872,7 @@ tnvan_status tnvan_get_tuning(const tnvan_net *net, tnvan_tuning *out) {
   out->chain_groups = chain && net->rfwd ? (net->tune.chain_groups > 0 ? net->tune.chain_groups
                                                                        : net->ckey.empty() ? 0 : net->sg)
                                          : 0;
+  out->checkpoint_every = chain && net->rbwd ? net->lim_bwd.rk : 0;
   return TNVAN_OK;
 }
 
@@ -1873,13 +1884,29 @@ tnvan_status tnvan_set_tuning(tnvan_net *net, const tnvan_tuning *in) {
     return set_err(TNVAN_E_INVALID, "general tiles must be 0 or a power of two up to 64");
   if (in->chain_groups < 0 || in->chain_groups > 2)
     return set_err(TNVAN_E_INVALID, "chain_groups must be 0, 1 or 2");
+  const int k = in->checkpoint_every;
+  if (k != 0 && k != 1 && k != 2 && k != 4 && k != 8)
+    return set_err(TNVAN_E_INVALID, "checkpoint_every must be 0, 1, 2, 4 or 8");
+  if (net->rbwd) {
+    // the replayed states of one segment live in LDS beside each wave's data
+    ChainLim L = net->lim_bwd;
+    L.rk = k > 0 ? k : net->rk_build;
+    int dev = 0, maxlds = 65536;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (4 * rchain_wave_lds(L, true, 1) > (size_t)maxlds)
+      return set_err(TNVAN_E_INVALID, "checkpoint_every %d does not fit the LDS", L.rk);
+  }
   const tnvan_tuning old = net->tune;
   net->tune = tnvan_tuning{};
   net->tune.general_tile_fwd = in->general_tile_fwd;
   net->tune.general_tile_bwd = in->general_tile_bwd;
   net->tune.chain_groups = in->chain_groups;
+  net->tune.checkpoint_every = k;
+  net->lim_bwd.rk = k > 0 ? k : net->rk_build;
   if (!choose_tiles(net, false, in->general_tile_fwd) || !choose_tiles(net, true, in->general_tile_bwd)) {
     net->tune = old;
+    net->lim_bwd.rk = old.checkpoint_every > 0 ? old.checkpoint_every : net->rk_build;
     choose_tiles(net, false, old.general_tile_fwd);
     choose_tiles(net, true, old.general_tile_bwd);
     return set_err(TNVAN_E_INVALID, "a requested general tile does not fit the LDS");

@@ -54,8 +54,9 @@ __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~(size_t)15
 __host__ __device__ constexpr int ldt_of(int tiles) { return 16 * tiles + ((tiles & 1) ? 32 : 16); }
 
 struct RL {
-  size_t sp, ex, ga, rs, end;
+  size_t sp, ex, ga, rs, seg, end;
 };
+__host__ __device__ inline int rk_of(const ChainLim &L) { return L.rk > 1 ? L.rk : 1; }
 __host__ __device__ inline RL rlayout(const ChainLim &L, bool bwd, int sg) {
   RL r{};
   size_t o = 0;
@@ -66,6 +67,8 @@ __host__ __device__ inline RL rlayout(const ChainLim &L, bool bwd, int sg) {
     r.ex = o; o = al16(o + (size_t)L.max_steps * CW * 4);
     r.ga = o; o = al16(o + (size_t)CW * ldt * 4);
     r.rs = o; o = al16(o + (size_t)CW * ldt * 4);
+    // states A_t of one checkpoint segment replayed in the reverse walk
+    r.seg = o; o = al16(o + (size_t)(rk_of(L) - 1) * kRegBwdTiles * 64 * 16);
   }
   r.end = al16(o);
   return r;
@@ -378,9 +381,13 @@ __global__ __launch_bounds__(256) void rchain_fwd_kernel(ChainArgs a) {
 // spin sign of bit j of the state index x
 __device__ inline float sgn(int x, int j) { return ((x >> j) & 1) ? -1.f : 1.f; }
 
-template <int CT, bool kS>
+template <int CT, bool kS, bool kK>
 __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstDesc &D,
                                  const ChainDesc &cd, char *base, const RL &L, int lane) {
+  // checkpoint interval: A_t is kept for t = 0, k, 2k, ...; the reverse walk
+  // replays each segment's other states from its checkpoint into LDS with
+  // the forward pass's own operations (so they are the same values)
+  const int kk = kK ? rk_of(a.lim) : 1;
   constexpr int GR = GroupMax<CT>::v;
   constexpr int NC = (CT + 1) / 2;
   constexpr int kM = kS ? 2 : 0;
@@ -397,10 +404,12 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
   const float gs = ls < nvalid ? (float)a.grad[a.inst_sample_off[tk.q] + tk.b0 + ls] : 0.f;
   float *prow = a.partial + a.inst_partial_off[tk.q] + (tk.b0 / CW) * (int64_t)D.n_partial;
   const int T = cd.n_steps;
+  const int nslots = (a.lim.max_steps + kk - 1) / kk;
   f4 *ck = reinterpret_cast<f4 *>(a.ckpt) +
-           (int64_t)(a.task_base + blockIdx.x * kWaves + (threadIdx.x >> 6)) * a.lim.max_steps *
+           (int64_t)(a.task_base + blockIdx.x * kWaves + (threadIdx.x >> 6)) * nslots *
                kRegBwdTiles * 64 +
            lane;
+  f4 *seg = reinterpret_cast<f4 *>(base + L.seg) + lane;
   const float *ub = phi_base(a, tk.q, tk.Bq, tk.b0 + ls);
 
   // Both passes load the operands of the next step while one step is
@@ -424,9 +433,11 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
     // and step t + 2's unary factors
     auto fstep = [&](int t, const ChainStep &nx, const FwdOps<kM, CT> &oc, const float (&uc)[GR],
                      ChainStep &nn, FwdOps<kM, CT> &on, float (&un)[GR]) -> bool {
+      if (!kK || t % kk == 0) {
 #pragma unroll
-      for (int i = 0; i < CT; ++i)
-        ck[(t * kRegBwdTiles + i) * 64] = f4{x[i][0], x[i][1], x[i][2], x[i][3]};
+        for (int i = 0; i < CT; ++i)
+          ck[((t / kk) * kRegBwdTiles + i) * 64] = f4{x[i][0], x[i][1], x[i][2], x[i][3]};
+      }
       const bool last = t == T - 1;
       nn = step_at(cs, t + 2 < T ? t + 2 : T - 1);
       on.load(a, nx, lane);
@@ -477,8 +488,10 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
     float u[GR];
   };
   auto prefetch = [&](const ChainStep &s, int t, Pre &p) {
+    if (!kK || t % kk == 0) {
 #pragma unroll
-    for (int i = 0; i < CT; ++i) p.a[i] = ck[(t * kRegBwdTiles + i) * 64];
+      for (int i = 0; i < CT; ++i) p.a[i] = ck[((t / kk) * kRegBwdTiles + i) * 64];
+    }
     if constexpr (kS) {
       const u4v *q3 = reinterpret_cast<const u4v *>(a.Ts3 + s.s3_off) + lane + 2 * CT * NC * 64;
 #pragma unroll
@@ -493,13 +506,49 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
     }
     load_phi<GR>(ub, tk.Bq, s.gpos, s.g, p.u);
   };
+  // A_{t0+1} .. A_top of the segment from its checkpoint A_t0
+  auto replay = [&](int t0, int top) {
+    float xr[CT][4];
+#pragma unroll
+    for (int i = 0; i < CT; ++i) {
+      const f4 v = ck[((t0 / kk) * kRegBwdTiles + i) * 64];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) xr[i][r] = v[r];
+    }
+    for (int j = t0; j < top; ++j) {
+      const ChainStep sj = step_at(cs, j), sn1 = step_at(cs, j + 1);
+      FwdOps<kM, CT> o;
+      o.load(a, sj, lane);
+      float u[GR];
+      load_phi<GR>(ub, tk.Bq, sn1.gpos, sn1.g, u);
+      f4 acc[CT];
+      o.mm(xr, acc);
+      float d[CT][4];
+      diag_from_phi<CT, GR>(u, sn1.g, lg, d);
+      (void)rescale_next<CT>(acc, d, xr);
+#pragma unroll
+      for (int i = 0; i < CT; ++i)
+        seg[((j - t0) * kRegBwdTiles + i) * 64] = f4{xr[i][0], xr[i][1], xr[i][2], xr[i][3]};
+    }
+  };
   auto walk = [&](int t, const ChainStep &st, const Pre &cur, ChainStep &sn, Pre &nxt) {
     const int g = st.g, w = st.w;
     float As[CT][4];
+    if (kK && t % kk != 0) {
+      // the top of a segment replays it; its other steps read the result
+      if (t % kk == kk - 1 || t == T - 1) replay(t - t % kk, t);
 #pragma unroll
-    for (int i = 0; i < CT; ++i)
+      for (int i = 0; i < CT; ++i) {
+        const f4 v = seg[((t % kk - 1) * kRegBwdTiles + i) * 64];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) As[i][r] = cur.a[i][r];
+        for (int r = 0; r < 4; ++r) As[i][r] = v[r];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < CT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) As[i][r] = cur.a[i][r];
+    }
     // operands used later in this step, issued now: T (for G = H o T) and
     // the S_x / S_o tables, in FP32 or split-BF16 form
     f4 tr[CT][CT], sx[kS ? 1 : CT], so[kS ? 1 : CT];
@@ -687,7 +736,7 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
   }
 }
 
-template <int CT, bool kS>
+template <int CT, bool kS, bool kK>
 __global__ __launch_bounds__(256, 3) void rchain_bwd_kernel(ChainArgs a) {
   extern __shared__ __align__(16) char smem[];
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -699,7 +748,7 @@ __global__ __launch_bounds__(256, 3) void rchain_bwd_kernel(ChainArgs a) {
   const ChainDesc cd = a.chains[C.chain_off + tk.c];
   const RL L = rlayout(a.lim, true, 1);
   char *base = smem + (size_t)wave * L.end;
-  bwd_chain<CT, kS>(a, tk, D, cd, base, L, lane);
+  bwd_chain<CT, kS, kK>(a, tk, D, cd, base, L, lane);
 }
 
 }  // namespace
@@ -707,7 +756,7 @@ __global__ __launch_bounds__(256, 3) void rchain_bwd_kernel(ChainArgs a) {
 size_t rchain_wave_lds(const ChainLim &L, bool bwd, int sg) { return rlayout(L, bwd, sg).end; }
 
 int64_t rchain_ckpt_floats(const ChainLim &L) {
-  return (int64_t)L.max_steps * kRegBwdTiles * 64 * 4;
+  return (int64_t)((L.max_steps + rk_of(L) - 1) / rk_of(L)) * kRegBwdTiles * 64 * 4;
 }
 
 // one launch per chain width: tasks [task_base, task_base + n_tasks) all
@@ -719,8 +768,13 @@ hipError_t launch_rchain(const ChainArgs &a, bool bwd, hipStream_t st) {
   const int ct = a.ntm;
   const bool sp = a.split != 0 && !a.bf16;
   if (bwd) {
-    if (ct == 1) k = sp ? rchain_bwd_kernel<1, true> : rchain_bwd_kernel<1, false>;
-    else if (ct == 2) k = sp ? rchain_bwd_kernel<2, true> : rchain_bwd_kernel<2, false>;
+    const bool kk = rk_of(a.lim) > 1;
+    if (ct == 1)
+      k = sp ? (kk ? rchain_bwd_kernel<1, true, true> : rchain_bwd_kernel<1, true, false>)
+             : (kk ? rchain_bwd_kernel<1, false, true> : rchain_bwd_kernel<1, false, false>);
+    else if (ct == 2)
+      k = sp ? (kk ? rchain_bwd_kernel<2, true, true> : rchain_bwd_kernel<2, true, false>)
+             : (kk ? rchain_bwd_kernel<2, false, true> : rchain_bwd_kernel<2, false, false>);
   } else if (a.bf16) {
     if (ct == 1) k = sg >= 2 ? rchain_fwd_kernel<1, 1, 2> : rchain_fwd_kernel<1, 1, 1>;
     else if (ct == 2) k = sg >= 2 ? rchain_fwd_kernel<1, 2, 2> : rchain_fwd_kernel<1, 2, 1>;

@@ -310,6 +310,7 @@ struct ChainLim {             // launch-wide maxima that size the LDS layout
   int32_t kseg;               // checkpoint interval of the adjoint
   int32_t wpb;                // waves per workgroup
   int32_t tlds;               // transfer tables staged in LDS
+  int32_t rk;                 // register-resident adjoint: checkpoint every rk steps (1, 2, 4, 8)
 };
 struct ChainArgs {
   const InstDesc *inst;
