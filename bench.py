@@ -80,7 +80,7 @@ KERNEL_FLOPS = {
 }
 KERNEL_NAMES = {
     "chain_fwd_2": "rchain_fwd_kernel<{mode}, 2, 2>", "chain_fwd_1": "rchain_fwd_kernel<{mode}, 1, 2>",
-    "chain_bwd_2": "rchain_bwd_kernel<2, {split}>", "chain_bwd_1": "rchain_bwd_kernel<1, {split}>",
+    "chain_bwd_2": "rchain_bwd_kernel<2, {split}, {kk}>", "chain_bwd_1": "rchain_bwd_kernel<1, {split}, {kk}>",
     "made_grad": "mgrad_kernel<2, 16>", "sample": "msample_kernel<2, false>",
 }
 PEAK_FP32 = 157.3e12       # MI355X FP32 (vector and 16x16x4 matrix), published
@@ -101,6 +101,11 @@ def parse():
                    help="FP32 matrix-core products in the chain kernels (default: split BF16)")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="run one plain device copy of MIB MiB first (counter calibration)")
+    p.add_argument("--checkpoint-every", type=int, default=0, metavar="K",
+                   help="adjoint checkpoint interval of the step's net (0: the default, 1)")
+    p.add_argument("--quick", action="store_true",
+                   help="the timed step and its roofline line only (no breakdown, no "
+                        "CPU baseline); for counter runs")
     return p.parse_args()
 
 
@@ -162,9 +167,13 @@ def measured_traffic(kernel):
         return None
 
 
-def fwd_adj(net, flat, counts, iters, st, g=None):
+def fwd_adj(net, flat, counts, iters, st, g=None, tune=None):
     """Time tnvan_logz_and_backward with g_b = 1/B (per instance); returns
-    (seconds per call, logz, (dh, dJ, dbeta)) of the last call, on the host."""
+    (seconds per call, logz, (dh, dJ, dbeta)) of the last call, on the host.
+    With tune (a dict), the call is timed with the default launch shapes,
+    then the autotuner picks shapes on this batch and the call is timed
+    again; tune receives both times and the choice, and the returned time
+    is the tuned one."""
     import torch
     if g is None:
         g = torch.cat([torch.full((b,), 1.0 / max(b, 1), dtype=torch.float64, device="cuda")
@@ -175,6 +184,16 @@ def fwd_adj(net, flat, counts, iters, st, g=None):
     for _ in range(2):
         fa()
     t = event_time(fa, iters, st)
+    if tune is not None:
+        tune["default_s"] = t
+        tune["default_shapes"] = net.get_tuning()
+        t0 = time.perf_counter()
+        tune["chosen"] = net.autotune(flat, g, counts)
+        tune["tuning_s"] = time.perf_counter() - t0
+        for _ in range(2):
+            fa()
+        t = event_time(fa, iters, st)
+        tune["tuned_s"] = t
     fa()
     torch.cuda.synchronize()
     return t, logz[:sum(counts)].cpu().numpy(), tuple(x.cpu().numpy() for x in out)
@@ -219,7 +238,8 @@ def main():
     # error this leaves against the oracle), unless --fp32-products
     split = args.precision == "fp32" and not args.fp32_products
     net = Net(insts, precision=args.precision, seed=2024,
-              flags=Net.FLAG_PROFILE | (Net.FLAG_SPLIT_BF16 if split else 0))
+              flags=Net.FLAG_PROFILE | (Net.FLAG_SPLIT_BF16 if split else 0),
+              checkpoint_every=args.checkpoint_every)
     net.profile_only(["chain_bwd_2"])
     for k in range(nI):
         net.set_params(k, torch.from_numpy(S.made_init(nw, HIDDEN, 7 + k)))
@@ -258,11 +278,16 @@ def main():
         if n:
             ktime[k] = (tot, n)
 
+    if args.quick:
+        quick_line(args, value, ms, ktime, nI, split, wall)
+        return
+
     # ---- C2: forward + adjoint alone, this path and the others, same inputs
     sp_np = S.uniform_spins(nI * B, nw, 102)
     sp_fix = torch.from_numpy(sp_np).cuda().reshape(-1)
     keep["c2_spins"] = sp_np
-    t_fa, lz, adj = fwd_adj(net, sp_fix, counts, iters, st)
+    tune_c2 = {}
+    t_fa, lz, adj = fwd_adj(net, sp_fix, counts, iters, st, tune=tune_c2)
     keep["c2"] = {"run": (lz, adj)}
     logz = torch.empty(nI * B, dtype=torch.float64, device="cuda")
     out = (dh, dJ, db)
@@ -278,6 +303,19 @@ def main():
         keep["c2"][pname] = (lz2, adj2)
         c2_paths[pname] = {"fwd_adj_s": t2, "fwd_adj_samples_per_s": nI * B / t2}
         del n2
+    # the adjoint checkpoint interval k: time of the forward + adjoint call
+    # and of the dominant kernel per k (same results bit for bit)
+    ck_k = {}
+    if args.precision != "fp64":
+        for kk in (1, 2, 4, 8):
+            nk = Net(insts, precision=args.precision, flags=Net.FLAG_PROFILE |
+                     (Net.FLAG_SPLIT_BF16 if split else 0), checkpoint_every=kk)
+            nk.profile_only(["chain_bwd_2"])
+            tk, _, _ = fwd_adj(nk, sp_fix, counts, iters, st)
+            ktot, kn = nk.kernel_time("chain_bwd_2")
+            ck_k[kk] = {"fwd_adj_s": tk, "chain_bwd_2_avg_s": ktot / max(kn, 1),
+                        "checkpoint_bytes_per_launch": 2 * nI * B * 2 * 16 * 4 * ((16 + kk - 1) // kk)}
+            del nk
     t_fa64 = c2_paths["fp64"]["fwd_adj_s"] if "fp64" in c2_paths else t_fa
     lz64 = keep["c2"].get("fp64", (lz, None))[0]
     err64 = float(np.abs(lz - lz64).max() / insts[0].n)
@@ -307,9 +345,10 @@ def main():
     keep["c3"] = {}
     for pname, prec in (("fp32", "fp32"), ("bf16", "bf16"), ("fp64", "fp64")):
         n3 = Net(c3, precision=prec)
-        t3, lz3, adj3 = fwd_adj(n3, flat3, [B3] * 3, iters, st)
+        tn = {}
+        t3, lz3, adj3 = fwd_adj(n3, flat3, [B3] * 3, iters, st, tune=tn)
         keep["c3"][pname] = (lz3, adj3)
-        c3_paths[pname] = {"fwd_adj_s": t3, "fwd_adj_samples_per_s": 3 * B3 / t3}
+        c3_paths[pname] = {"fwd_adj_s": t3, "fwd_adj_samples_per_s": 3 * B3 / t3, "tuning": tn}
         if pname == "fp32":
             c3_flops = n3.info(0)[3]
         del n3
@@ -324,9 +363,10 @@ def main():
     keep["c4"] = {}
     for pname, prec in (("fp32", "fp32"), ("fp64", "fp64")):
         n4 = Net([c4], precision=prec)
-        t4, lz4, adj4 = fwd_adj(n4, flat4, [B4], iters, st)
+        tn = {}
+        t4, lz4, adj4 = fwd_adj(n4, flat4, [B4], iters, st, tune=tn)
         keep["c4"][pname] = (lz4, adj4)
-        c4_paths[pname] = {"fwd_adj_s": t4, "fwd_adj_samples_per_s": B4 / t4}
+        c4_paths[pname] = {"fwd_adj_s": t4, "fwd_adj_samples_per_s": B4 / t4, "tuning": tn}
         if pname == "fp32":
             c4_flops = n4.info(0)[3]
         del n4
@@ -342,9 +382,10 @@ def main():
     for pname, prec, flags in (("split_bf16", "fp32", Net.FLAG_SPLIT_BF16), ("bf16", "bf16", 0),
                                ("fp64", "fp64", 0)):
         n5 = Net(c5, precision=prec, flags=flags | (Net.FLAG_GRAPH if prec != "fp64" else 0))
-        t5, lz5, _ = fwd_adj(n5, flat5, B5, 3, st)
+        tn = {}
+        t5, lz5, _ = fwd_adj(n5, flat5, B5, 3, st, tune=tn)
         keep["c5"][pname] = lz5
-        c5_paths[pname] = {"fwd_adj_s": t5, "fwd_adj_samples_per_s": sum(B5) / t5}
+        c5_paths[pname] = {"fwd_adj_s": t5, "fwd_adj_samples_per_s": sum(B5) / t5, "tuning": tn}
         if prec != "fp64":
             for k, inst in enumerate(c5):
                 n5.set_params(k, torch.from_numpy(S.made_init(inst.n_width, inst.hidden, 7 + k)))
@@ -416,21 +457,7 @@ def main():
     del net40
 
     # the dominant kernel's live timing (none on paths without it, e.g. FP64)
-    roofline = None
-    if "chain_bwd_2" in ktime:
-        dom = "chain_bwd_2"
-        dom_avg = ktime[dom][0] / ktime[dom][1]
-        achieved = KERNEL_FLOPS[dom] * nI * B / dom_avg
-        # the peak of the units the products run on: BF16 dense for split
-        # products (three BF16 products per algorithmic FP32 product, so at
-        # most a third of it is attainable), FP32 matrix otherwise
-        peak = PEAK_BF16 if split else PEAK_FP32
-        roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                    "unit": "TFLOP/s", "frac": achieved / peak, "traffic": measured_traffic(dom),
-                    "kernel": KERNEL_NAMES[dom].format(split=str(split).lower(), mode=2 if split else 0),
-                    "kernel_avg_s": dom_avg, "kernel_launches_timed": ktime[dom][1],
-                    "flops_per_launch": KERNEL_FLOPS[dom] * nI * B,
-                    "peak_units": "bf16 dense, 3 products per flop" if split else "fp32 matrix"}
+    roofline = roofline_line(ktime, nI, split, args.checkpoint_every)
     # call-level rooflines of the other workloads: algorithmic flops of the
     # forward + adjoint call (three times the forward) per second
     c3_alg = 3 * 2 * 65536          # [256] x [256, 256] per sample, forward x 3
@@ -476,6 +503,8 @@ def main():
             "max_abs_dlogZ_per_N_vs_fp64_path": err64,
             "adjoint_max_err_over_max_entry_vs_oracle": None,
             "c2_other_paths": c2_paths,
+            "checkpoint_every": ck_k,
+            "tuning": tune_c2,
             "wall_s_timed_region": wall,
             "c1": {"workload": "4x4 Gaussian lattice (seed 1), W = column 2, FP64 path, "
                                "200 Adam steps, lr 1e-3, 1024 samples, MADE H=16",
@@ -506,7 +535,7 @@ def main():
                                                "1000 steps, lr 0.01",
                                    "ms_per_step": 1e3 * t40, "F_q_per_spin": F40[0],
                                    "stderr_per_spin": F40[1]},
-            "kernel_avg_us": {KERNEL_NAMES.get(k, k).format(split=str(split).lower(), mode=2 if split else 0): 1e6 * t / n
+            "kernel_avg_us": {kname(k, split, args.checkpoint_every): 1e6 * t / n
                               for k, (t, n) in ktime.items()},
         },
     }
@@ -514,6 +543,46 @@ def main():
         res["cpu_baseline"] = cpu_baseline(insts, args.cpu_samples)
         oracle_checks(res["breakdown"], keep, insts, c3, c4, c5, B5)
     print(json.dumps(res), flush=True)
+
+
+def kname(k, split, ck=1):
+    return KERNEL_NAMES.get(k, k).format(split=str(split).lower(), mode=2 if split else 0,
+                                         kk=str(ck > 1).lower())
+
+
+def roofline_line(ktime, nI, split, ck=1):
+    """The dominant kernel's live timing against its peak (None on paths
+    without it, e.g. FP64)."""
+    if "chain_bwd_2" not in ktime:
+        return None
+    dom = "chain_bwd_2"
+    dom_avg = ktime[dom][0] / ktime[dom][1]
+    achieved = KERNEL_FLOPS[dom] * nI * B / dom_avg
+    # the peak of the units the products run on: BF16 dense for split
+    # products (three BF16 products per algorithmic FP32 product, so at most
+    # a third of it is attainable), FP32 matrix otherwise
+    peak = PEAK_BF16 if split else PEAK_FP32
+    return {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": measured_traffic(dom) if ck <= 1 else None,
+            "kernel": kname(dom, split, ck), "kernel_avg_s": dom_avg, "kernel_launches_timed": ktime[dom][1],
+            "flops_per_launch": KERNEL_FLOPS[dom] * nI * B,
+            "peak_units": "bf16 dense, 3 products per flop" if split else "fp32 matrix"}
+
+
+def quick_line(args, value, ms, ktime, nI, split, wall):
+    print(json.dumps({"metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                      "dtype": "f32+bf16x3" if split else args.precision, "data": "synthetic",
+                      "config": {"workload": "16x16 OBC Gaussian spin glass, W = columns 6,11, "
+                                             "beta in {0.5,1,2}, 8192 samples each, MADE H=256",
+                                 "global_batch": nI * B, "instances": nI,
+                                 "parallelism": "single GPU"},
+                      "roofline": roofline_line(ktime, nI, split, args.checkpoint_every),
+                      "quick": True,
+                      "checkpoint_every": args.checkpoint_every or 1,
+                      "wall_s_timed_region": wall}), flush=True)
 
 
 def oracle_checks(bd, keep, insts, c3, c4, c5, B5):
