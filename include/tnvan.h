@@ -143,7 +143,13 @@ typedef struct {
   /* adjoint checkpoint interval of the register-resident chain kernels
    * (0: the tnvan_options value; 1, 2, 4, 8) */
   int32_t checkpoint_every;
-  int32_t reserved[3];
+  /* how the uneven batch is launched: 1 one workgroup per tile of the
+   * general kernel and one launch per chain width; 2 persistent launches:
+   * the general kernel's workgroups, and the chain kernels' waves over every
+   * width, take (instance, tile or chain, sample group) items from a device
+   * work queue, the costliest first (0: the default, 1) */
+  int32_t launch_mode;
+  int32_t reserved[2];
 } tnvan_tuning;
 
 /* The launch shapes in effect (defaults resolved; chain_groups 0 until a
@@ -159,7 +165,7 @@ tnvan_status tnvan_set_tuning(tnvan_net *net, const tnvan_tuning *in);
  * times tnvan_logz_batch for every candidate forward shape and
  * tnvan_logz_backward for every candidate adjoint shape of the kernels the
  * net runs (general tiles 1..64 samples, chain groups 1 or 2, adjoint
- * checkpoint intervals 1, 2, 4), one field at
+ * checkpoint intervals 1, 2, 4, launch modes 1 and 2), one field at
  * a time with the others at their best so far, each candidate as the mean
  * of 5 calls after one that lays the tables out (HIP events on `stream`).
  * A field keeps its default rule unless a candidate is at least 2% faster.
@@ -187,7 +193,9 @@ typedef enum {
   TNVAN_KERNEL_CHAIN_BWD_2 = 4,   /* ... 2 tiles */
   TNVAN_KERNEL_SAMPLE = 5,        /* matrix-core sampler */
   TNVAN_KERNEL_MADE_GRAD = 6,     /* fused REINFORCE backward (without its row reduction) */
-  TNVAN_KERNEL_COUNT = 7
+  TNVAN_KERNEL_CHAIN_FWD_ALL = 7, /* register-resident forward, every width in one persistent launch */
+  TNVAN_KERNEL_CHAIN_BWD_ALL = 8, /* register-resident adjoint, every width in one persistent launch */
+  TNVAN_KERNEL_COUNT = 9
 } tnvan_kernel;
 
 /* Compile n_inst instances into one net (host work plus device uploads,

@@ -90,7 +90,8 @@ class Net:
 
     # kernel ids of tnvan_kernel_time (built with flags=FLAG_PROFILE)
     KERNELS = {"chain_fwd_1": 0, "chain_fwd_2": 1, "chain_fwd_4": 2, "chain_bwd_1": 3,
-               "chain_bwd_2": 4, "sample": 5, "made_grad": 6}
+               "chain_bwd_2": 4, "sample": 5, "made_grad": 6, "chain_fwd_all": 7,
+               "chain_bwd_all": 8}
     FLAG_LDS_CHAIN = 1
     FLAG_PROFILE = 2
     FLAG_GRAPH = 4
@@ -121,7 +122,8 @@ class Net:
 
     def set_tuning(self, **shapes):
         """Request launch shapes (general_tile_fwd, general_tile_bwd,
-        chain_groups; 0 or absent = default rule)."""
+        chain_groups, checkpoint_every, launch_mode; 0 or absent = default
+        rule)."""
         t = _lib.CTuning()
         for k, v in shapes.items():
             if k not in _lib.CTuning.FIELDS:

@@ -64,9 +64,11 @@ class COptions(C.Structure):
 class CTuning(C.Structure):
     _fields_ = [("general_tile_fwd", C.c_int32), ("general_tile_bwd", C.c_int32),
                 ("chain_groups", C.c_int32), ("kinds", C.c_int32),
-                ("checkpoint_every", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("checkpoint_every", C.c_int32), ("launch_mode", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
-    FIELDS = ("general_tile_fwd", "general_tile_bwd", "chain_groups", "checkpoint_every")
+    FIELDS = ("general_tile_fwd", "general_tile_bwd", "chain_groups", "checkpoint_every",
+              "launch_mode")
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k in self.FIELDS + ("kinds",)}

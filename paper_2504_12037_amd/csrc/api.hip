@@ -136,6 +136,7 @@ struct tnvan_net {
   int64_t param_total = 0;
   DBuf d_mi, params, adam_m, adam_v, grad, step_ctr;
   DBuf nonfinite;             // [n_inst] flags of the free-energy kernel
+  DBuf pq;                    // work-queue counters of the persistent launches [8]
   bool check_finite = false;  // TNVAN_FLAG_CHECK_FINITE
   // per-call tables
   std::vector<int64_t> nkey;
@@ -320,6 +321,8 @@ bool choose_tiles(tnvan_net *net, bool bwd, int req = 0) {
   return true;
 }
 
+bool persistent(const tnvan_net *net) { return net->tune.launch_mode == 2; }
+
 // 16-sample groups per wave of the register-resident forward on chains of
 // 1-2 tiles (the tuned value, else two when that still leaves a wave per
 // SIMD for waves2 two-group waves, else one)
@@ -369,7 +372,15 @@ tnvan_status ensure_tiles(tnvan_net *net, TileCache &tc, int S, bool bwd) {
   std::vector<int32_t> ti, ts, first(net->n_inst), cnt(net->n_inst);
   std::vector<int64_t> poff(net->n_inst);
   int64_t ptot = 0;
-  for (int q = 0; q < net->n_inst; ++q) {
+  // tiles of the instances with the costliest samples first (each
+  // instance's tiles stay contiguous): the long tiles start early and the
+  // short ones fill the end of the launch
+  std::vector<int> by_cost(net->n_inst);
+  for (int q = 0; q < net->n_inst; ++q) by_cost[q] = q;
+  std::stable_sort(by_cost.begin(), by_cost.end(), [&](int x, int y) {
+    return net->P.flops_fwd[x] > net->P.flops_fwd[y];
+  });
+  for (int q : by_cost) {
     first[q] = (int32_t)ti.size();
     const int64_t B = net->nkey[q];
     if (net->use_chain[q]) {
@@ -378,6 +389,8 @@ tnvan_status ensure_tiles(tnvan_net *net, TileCache &tc, int S, bool bwd) {
       for (int64_t b = 0; b < B; b += S) { ti.push_back(q); ts.push_back((int32_t)b); }
       cnt[q] = (int32_t)ti.size() - first[q];
     }
+  }
+  for (int q = 0; q < net->n_inst; ++q) {
     poff[q] = ptot;
     if (bwd) ptot += (int64_t)cnt[q] * net->P.insts[q].n_partial;
   }
@@ -604,7 +617,9 @@ tnvan_status run_logz(tnvan_net *net, const int8_t *spins, double *logz, hipStre
     a.garena = net->garena.as<real>();
     a.garena_stride = per;
   }
-  HIPCHK(launch_contract<real>(a, net->tc_fwd.n_tiles, net->lds_fwd, false, net->glob_fwd, st));
+  a.pq = net->pq.as<int32_t>();
+  HIPCHK(launch_contract<real>(a, net->tc_fwd.n_tiles, net->lds_fwd, false, net->glob_fwd, st,
+                               persistent(net)));
   if (std::count(net->use_chain.begin(), net->use_chain.end(), 1)) {
     s = ensure_chain_tasks(net);
     if (s) return s;
@@ -614,14 +629,22 @@ tnvan_status run_logz(tnvan_net *net, const int8_t *spins, double *logz, hipStre
       HIPCHK(launch_unary(c, net->chain_list.as<int32_t>(), net->n_chain_insts, net->u_chunks,
                           net->u_maxB, net->f_off.as<int64_t>(), net->Ubuf.as<float>(),
                           net->fabp.as<double>(), st));
-      for (int gi = 0; gi < 3; ++gi) {
-        c.task_base = net->rg_lo[gi];
-        c.n_tasks = net->rg_n[gi];
-        c.ntm = 1 << gi;
-        c.sg = net->sg_of(1 << gi);
-        if (c.n_tasks <= 0) continue;
-        ProfScope ps(net, TNVAN_KERNEL_CHAIN_FWD_1 + gi, st);
-        HIPCHK(launch_rchain(c, false, st));
+      if (persistent(net)) {
+        c.pq = net->pq.as<int32_t>() + 4;
+        for (int gi = 0; gi < 3; ++gi) { c.pq_lo[gi] = net->rg_lo[gi]; c.pq_n[gi] = net->rg_n[gi]; }
+        c.sg = net->sg;
+        ProfScope ps(net, TNVAN_KERNEL_CHAIN_FWD_ALL, st);
+        HIPCHK(launch_rchain_pq(c, false, st));
+      } else {
+        for (int gi = 0; gi < 3; ++gi) {
+          c.task_base = net->rg_lo[gi];
+          c.n_tasks = net->rg_n[gi];
+          c.ntm = 1 << gi;
+          c.sg = net->sg_of(1 << gi);
+          if (c.n_tasks <= 0) continue;
+          ProfScope ps(net, TNVAN_KERNEL_CHAIN_FWD_1 + gi, st);
+          HIPCHK(launch_rchain(c, false, st));
+        }
       }
     } else {
       HIPCHK(launch_chain(c, false, st));
@@ -666,7 +689,9 @@ tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *gra
     a.garena = net->garena.as<real>();
     a.garena_stride = per;
   }
-  HIPCHK(launch_contract<real>(a, tc.n_tiles, net->lds_bwd, true, net->glob_bwd, st));
+  a.pq = net->pq.as<int32_t>() + 2;
+  HIPCHK(launch_contract<real>(a, tc.n_tiles, net->lds_bwd, true, net->glob_bwd, st,
+                               persistent(net)));
   if (std::count(net->use_chain.begin(), net->use_chain.end(), 1)) {
     s = ensure_chain_tasks(net);
     if (s) return s;
@@ -679,13 +704,20 @@ tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *gra
       HIPCHK(launch_unary(c, net->chain_list.as<int32_t>(), net->n_chain_insts, net->u_chunks,
                           net->u_maxB, net->f_off.as<int64_t>(), net->Ubuf.as<float>(),
                           net->fabp.as<double>(), st));
-      for (int gi = 0; gi < 2; ++gi) {
-        c.task_base = net->brg_lo[gi];
-        c.n_tasks = net->brg_n[gi];
-        c.ntm = 1 << gi;
-        if (c.n_tasks <= 0) continue;
-        ProfScope ps(net, TNVAN_KERNEL_CHAIN_BWD_1 + gi, st);
-        HIPCHK(launch_rchain(c, true, st));
+      if (persistent(net)) {
+        c.pq = net->pq.as<int32_t>() + 6;
+        for (int gi = 0; gi < 3; ++gi) { c.pq_lo[gi] = net->brg_lo[gi]; c.pq_n[gi] = gi < 2 ? net->brg_n[gi] : 0; }
+        ProfScope ps(net, TNVAN_KERNEL_CHAIN_BWD_ALL, st);
+        HIPCHK(launch_rchain_pq(c, true, st));
+      } else {
+        for (int gi = 0; gi < 2; ++gi) {
+          c.task_base = net->brg_lo[gi];
+          c.n_tasks = net->brg_n[gi];
+          c.ntm = 1 << gi;
+          if (c.n_tasks <= 0) continue;
+          ProfScope ps(net, TNVAN_KERNEL_CHAIN_BWD_1 + gi, st);
+          HIPCHK(launch_rchain(c, true, st));
+        }
       }
       if (logz)
         HIPCHK(launch_chain_sum(net->inst.as<InstDesc>(), net->cinst.as<ChainInst>(),
@@ -1266,6 +1298,11 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   if ((e = net->nonfinite.ensure(sizeof(int32_t) * n_inst)) ||
       (e = hipMemset(net->nonfinite.p, 0, sizeof(int32_t) * n_inst)))
     return fail(e, "non-finite flags");
+  // counters of the persistent launches (each launch leaves them at zero):
+  // [0,1] general forward, [2,3] general adjoint, [4,5] chain forward,
+  // [6,7] chain adjoint
+  if ((e = net->pq.ensure(sizeof(int32_t) * 8)) || (e = hipMemset(net->pq.p, 0, sizeof(int32_t) * 8)))
+    return fail(e, "work-queue counters");
   {
     std::vector<float> fj(P.fld_J.begin(), P.fld_J.end()), hr(P.hR.begin(), P.hR.end());
     UP2(fld_J32, fj) UP2(hR32, hr) UP2(fld_wr, P.fld_wr) UP2(cinst, P.cinst)
@@ -1381,7 +1418,7 @@ void tnvan_free_network(tnvan_net *net) {
                  &net->btask_inst, &net->btask_chain, &net->btask_start, &net->Tl, &net->Tbl,
                  &net->cedges, &net->ckpt, &net->Tr, &net->Tq, &net->Trb, &net->xcol,
                  &net->cf_w, &net->cf_r, &net->cf_J, &net->Tsx, &net->Ts3, &net->Tdq, &net->Ubuf, &net->vjp_part,
-                 &net->tickets, &net->nonfinite, &net->col_out, &net->pcoef_out, &net->w_xspins, &net->w_xlogz, &net->w_xpart, &net->ww_e, &net->d_wv, &net->w_og,
+                 &net->tickets, &net->nonfinite, &net->pq, &net->col_out, &net->pcoef_out, &net->w_xspins, &net->w_xlogz, &net->w_xpart, &net->ww_e, &net->d_wv, &net->w_og,
                  &net->w_ostats, &net->w_odb, &net->fabp, &net->u_off,
                  &net->f_off,
                  &net->mpack, &net->mtask_inst, &net->mtask_start, &net->mg_task_inst,
@@ -1873,6 +1910,7 @@ tnvan_status tnvan_get_tuning(const tnvan_net *net, tnvan_tuning *out) {
                                                                        : net->ckey.empty() ? 0 : net->sg)
                                          : 0;
   out->checkpoint_every = chain && net->rbwd ? net->lim_bwd.rk : 0;
+  out->launch_mode = net->tune.launch_mode > 0 ? net->tune.launch_mode : 1;
   return TNVAN_OK;
 }
 
@@ -1887,6 +1925,8 @@ tnvan_status tnvan_set_tuning(tnvan_net *net, const tnvan_tuning *in) {
   const int k = in->checkpoint_every;
   if (k != 0 && k != 1 && k != 2 && k != 4 && k != 8)
     return set_err(TNVAN_E_INVALID, "checkpoint_every must be 0, 1, 2, 4 or 8");
+  if (in->launch_mode < 0 || in->launch_mode > 2)
+    return set_err(TNVAN_E_INVALID, "launch_mode must be 0, 1 or 2");
   if (net->rbwd) {
     // the replayed states of one segment live in LDS beside each wave's data
     ChainLim L = net->lim_bwd;
@@ -1903,6 +1943,7 @@ tnvan_status tnvan_set_tuning(tnvan_net *net, const tnvan_tuning *in) {
   net->tune.general_tile_bwd = in->general_tile_bwd;
   net->tune.chain_groups = in->chain_groups;
   net->tune.checkpoint_every = k;
+  net->tune.launch_mode = in->launch_mode;
   net->lim_bwd.rk = k > 0 ? k : net->rk_build;
   if (!choose_tiles(net, false, in->general_tile_fwd) || !choose_tiles(net, true, in->general_tile_bwd)) {
     net->tune = old;

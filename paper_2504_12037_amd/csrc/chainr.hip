@@ -32,6 +32,8 @@
 // names; the W-R correlations come from p_t and the spins directly.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "launch.h"
 #include "wave.h"
 
@@ -278,6 +280,39 @@ struct Task {
   int64_t b0, Bq;
 };
 
+__device__ inline Task task_at(const ChainArgs &a, int i) {
+  Task k;
+  k.q = a.task_inst[i];
+  k.c = a.task_chain[i];
+  k.b0 = a.task_start[i];
+  k.Bq = a.inst_B[k.q];
+  return k;
+}
+
+// Persistent form: the next task of a wave from the device counter, widest
+// chains first (false when none is left); gi = width index (1 << gi tiles)
+__device__ inline bool pq_task(const ChainArgs &a, int lane, int &task, int &gi) {
+  int v = 0;
+  if (lane == 0) v = atomicAdd(a.pq, 1);
+  v = __builtin_amdgcn_readfirstlane(__shfl(v, 0, 64));
+  for (int g = 2; g >= 0; --g) {
+    if (v < a.pq_n[g]) {
+      task = a.pq_lo[g] + v;
+      gi = g;
+      return true;
+    }
+    v -= a.pq_n[g];
+  }
+  return false;
+}
+// the last wave to leave resets the counter and the exit count
+__device__ inline void pq_exit(const ChainArgs &a, int lane) {
+  if (lane == 0 && atomicAdd(a.pq + 1, 1) == (int)gridDim.x * kWaves - 1) {
+    atomicExch(a.pq, 0);
+    atomicExch(a.pq + 1, 0);
+  }
+}
+
 __device__ inline Task wave_task(const ChainArgs &a, int wave) {
   Task k;
   const int i = a.task_base + blockIdx.x * kWaves + wave;
@@ -383,7 +418,8 @@ __device__ inline float sgn(int x, int j) { return ((x >> j) & 1) ? -1.f : 1.f; 
 
 template <int CT, bool kS, bool kK>
 __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstDesc &D,
-                                 const ChainDesc &cd, char *base, const RL &L, int lane) {
+                                 const ChainDesc &cd, char *base, const RL &L, int lane,
+                                 int task_id) {
   // checkpoint interval: A_t is kept for t = 0, k, 2k, ...; the reverse walk
   // replays each segment's other states from its checkpoint into LDS with
   // the forward pass's own operations (so they are the same values)
@@ -405,10 +441,7 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
   float *prow = a.partial + a.inst_partial_off[tk.q] + (tk.b0 / CW) * (int64_t)D.n_partial;
   const int T = cd.n_steps;
   const int nslots = (a.lim.max_steps + kk - 1) / kk;
-  f4 *ck = reinterpret_cast<f4 *>(a.ckpt) +
-           (int64_t)(a.task_base + blockIdx.x * kWaves + (threadIdx.x >> 6)) * nslots *
-               kRegBwdTiles * 64 +
-           lane;
+  f4 *ck = reinterpret_cast<f4 *>(a.ckpt) + (int64_t)task_id * nslots * kRegBwdTiles * 64 + lane;
   f4 *seg = reinterpret_cast<f4 *>(base + L.seg) + lane;
   const float *ub = phi_base(a, tk.q, tk.Bq, tk.b0 + ls);
 
@@ -748,12 +781,84 @@ __global__ __launch_bounds__(256, 3) void rchain_bwd_kernel(ChainArgs a) {
   const ChainDesc cd = a.chains[C.chain_off + tk.c];
   const RL L = rlayout(a.lim, true, 1);
   char *base = smem + (size_t)wave * L.end;
-  bwd_chain<CT, kS, kK>(a, tk, D, cd, base, L, lane);
+  bwd_chain<CT, kS, kK>(a, tk, D, cd, base, L, lane, a.task_base + blockIdx.x * kWaves + wave);
+}
+
+// Persistent forward over every chain width (SG groups per wave on 1-2
+// tile chains, one on 4-tile chains)
+template <int kM, int SG>
+__global__ __launch_bounds__(256) void rchain_fwd_pq_kernel(ChainArgs a) {
+  const int lane = threadIdx.x & 63;
+  int task = 0, gi = 0;
+  while (pq_task(a, lane, task, gi)) {
+    const Task tk = task_at(a, task);
+    const ChainInst C = a.cinst[tk.q];
+    const ChainDesc cd = a.chains[C.chain_off + tk.c];
+    if (gi == 0) fwd_chain<kM, 1, SG>(a, tk, cd, lane);
+    else if (gi == 1) fwd_chain<kM, 2, SG>(a, tk, cd, lane);
+    else fwd_chain<kM, 4, 1>(a, tk, cd, lane);
+  }
+  pq_exit(a, lane);
+}
+
+// Persistent adjoint over both chain widths
+template <bool kS, bool kK>
+__global__ __launch_bounds__(256, 3) void rchain_bwd_pq_kernel(ChainArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const RL L = rlayout(a.lim, true, 1);
+  char *base = smem + (size_t)wave * L.end;
+  int task = 0, gi = 0;
+  while (pq_task(a, lane, task, gi)) {
+    const Task tk = task_at(a, task);
+    const InstDesc D = a.inst[tk.q];
+    const ChainInst C = a.cinst[tk.q];
+    const ChainDesc cd = a.chains[C.chain_off + tk.c];
+    if (gi == 0) bwd_chain<1, kS, kK>(a, tk, D, cd, base, L, lane, task);
+    else bwd_chain<2, kS, kK>(a, tk, D, cd, base, L, lane, task);
+    wsync();
+  }
+  pq_exit(a, lane);
 }
 
 }  // namespace
 
 size_t rchain_wave_lds(const ChainLim &L, bool bwd, int sg) { return rlayout(L, bwd, sg).end; }
+
+hipError_t launch_rchain_pq(const ChainArgs &a, bool bwd, hipStream_t st) {
+  const int total = a.pq_n[0] + a.pq_n[1] + a.pq_n[2];
+  if (total <= 0) return hipSuccess;
+  const bool sp = a.split != 0 && !a.bf16;
+  const int sg = bwd ? 1 : (a.sg >= 2 ? 2 : 1);
+  void (*k)(ChainArgs) = nullptr;
+  if (bwd) {
+    if (a.pq_n[2] > 0) return hipErrorInvalidValue;   // the adjoint takes chains of <= 2 tiles
+    const bool kk = rk_of(a.lim) > 1;
+    k = sp ? (kk ? rchain_bwd_pq_kernel<true, true> : rchain_bwd_pq_kernel<true, false>)
+           : (kk ? rchain_bwd_pq_kernel<false, true> : rchain_bwd_pq_kernel<false, false>);
+  } else {
+    const int m = a.bf16 ? 1 : sp ? 2 : 0;
+    if (m == 0) k = sg >= 2 ? rchain_fwd_pq_kernel<0, 2> : rchain_fwd_pq_kernel<0, 1>;
+    else if (m == 1) k = sg >= 2 ? rchain_fwd_pq_kernel<1, 2> : rchain_fwd_pq_kernel<1, 1>;
+    else k = sg >= 2 ? rchain_fwd_pq_kernel<2, 2> : rchain_fwd_pq_kernel<2, 1>;
+  }
+  const size_t lds = (size_t)kWaves * rlayout(a.lim, bwd, sg).end;
+  hipError_t e;
+  if (lds > 65536 && (e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                                              (int)lds)) != hipSuccess)
+    return e;
+  int dev = 0, cus = 0, per = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess ||
+      (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess ||
+      (e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void *>(k),
+                                                        64 * kWaves, lds)) != hipSuccess)
+    return e;
+  const int grid = std::max(1, std::min((total + kWaves - 1) / kWaves, cus * std::max(per, 1)));
+  hipLaunchKernelGGL(k, dim3(grid), dim3(64 * kWaves), lds, st, a);
+  return hipGetLastError();
+}
 
 int64_t rchain_ckpt_floats(const ChainLim &L) {
   return (int64_t)((L.max_steps + rk_of(L) - 1) / rk_of(L)) * kRegBwdTiles * 64 * 4;

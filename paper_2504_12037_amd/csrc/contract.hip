@@ -24,6 +24,7 @@
 // are reduced in a fixed order into one partial row per tile.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "launch.h"
@@ -176,13 +177,13 @@ __device__ inline real fast_fwd(const FastIn<real> &f, const real *Tt, int w, re
   return lmax;
 }
 
+// One tile of S samples of one instance through every step (forward, or
+// forward then reverse), the workgroup's LDS at smem.
 template <typename real, bool kGlobal, bool kBwd>
-__global__ __launch_bounds__(kThreads) void contract_kernel(ContractArgs<real> a) {
+__device__ inline void contract_tile(const ContractArgs<real> &a, const int tile, char *smem) {
   using FB = FBits<real>;
   using U = typename FB::U;
-  extern __shared__ __align__(16) char smem[];
   const int tid = threadIdx.x;
-  const int tile = blockIdx.x;
   const int q = a.tile_inst[tile];
   const InstDesc D = a.inst[q];
   const int S = a.S, logS = a.logS;
@@ -546,6 +547,34 @@ __global__ __launch_bounds__(kThreads) void contract_kernel(ContractArgs<real> a
   for (int k = tid; k < D.n_rr; k += kThreads) a.partial[prow + D.nr + D.n_wr + k] = Cw[k];
 }
 
+template <typename real, bool kGlobal, bool kBwd>
+__global__ __launch_bounds__(kThreads) void contract_kernel(ContractArgs<real> a) {
+  extern __shared__ __align__(16) char smem[];
+  contract_tile<real, kGlobal, kBwd>(a, blockIdx.x, smem);
+}
+
+// Persistent form: the launch's workgroups take tiles from a device counter
+// (a.pq[0]) in tile order (the instances with the costliest samples first)
+// until none is left; the last workgroup to leave resets the counter and
+// its exit count (a.pq[1]) for the next launch on the stream.
+template <typename real, bool kGlobal, bool kBwd>
+__global__ __launch_bounds__(kThreads) void contract_pq_kernel(ContractArgs<real> a, int n_tiles) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ int next;
+  for (;;) {
+    __syncthreads();   // every thread has read `next` and left the last tile
+    if (threadIdx.x == 0) next = atomicAdd(a.pq, 1);
+    __syncthreads();
+    const int tile = next;
+    if (tile >= n_tiles) break;
+    contract_tile<real, kGlobal, kBwd>(a, tile, smem);
+  }
+  if (threadIdx.x == 0 && atomicAdd(a.pq + 1, 1) == (int)gridDim.x - 1) {
+    atomicExch(a.pq, 0);
+    atomicExch(a.pq + 1, 0);
+  }
+}
+
 // Column sums of the per-tile partial rows of every instance (rows in a
 // fixed order, FP64): 16 columns x 16 row groups per block.
 // Column sums of the partial rows in two passes with a fixed order: block
@@ -624,8 +653,26 @@ int64_t contract_garena_entries(const InstDesc &D, int S, bool bwd) {
 
 template <typename real>
 hipError_t launch_contract(const ContractArgs<real> &a, int n_tiles, size_t lds,
-                           bool bwd, bool global_arena, hipStream_t st) {
+                           bool bwd, bool global_arena, hipStream_t st, bool persistent) {
   if (n_tiles <= 0) return hipSuccess;
+  if (persistent) {
+    void (*k)(ContractArgs<real>, int);
+    if (bwd) k = global_arena ? contract_pq_kernel<real, true, true> : contract_pq_kernel<real, false, true>;
+    else k = global_arena ? contract_pq_kernel<real, true, false> : contract_pq_kernel<real, false, false>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    // as many workgroups as are resident at once, at most one per tile
+    int dev = 0, cus = 0, per = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess ||
+        (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess ||
+        (e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void *>(k),
+                                                          kThreads, lds)) != hipSuccess)
+      return e;
+    const int grid = std::max(1, std::min(n_tiles, cus * std::max(per, 1)));
+    hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, st, a, n_tiles);
+    return hipGetLastError();
+  }
   void (*k)(ContractArgs<real>);
   if (bwd) k = global_arena ? contract_kernel<real, true, true> : contract_kernel<real, false, true>;
   else k = global_arena ? contract_kernel<real, true, false> : contract_kernel<real, false, false>;
@@ -649,8 +696,8 @@ hipError_t launch_vjp_reduce(const VjpArgs &a, const real *partial, int n_inst, 
 int vjp_split() { return kColSplit; }
 
 
-template hipError_t launch_contract<float>(const ContractArgs<float> &, int, size_t, bool, bool, hipStream_t);
-template hipError_t launch_contract<double>(const ContractArgs<double> &, int, size_t, bool, bool, hipStream_t);
+template hipError_t launch_contract<float>(const ContractArgs<float> &, int, size_t, bool, bool, hipStream_t, bool);
+template hipError_t launch_contract<double>(const ContractArgs<double> &, int, size_t, bool, bool, hipStream_t, bool);
 template hipError_t launch_vjp_reduce<float>(const VjpArgs &, const float *, int, int, hipStream_t);
 template hipError_t launch_vjp_reduce<double>(const VjpArgs &, const double *, int, int, hipStream_t);
 

@@ -40,6 +40,7 @@ struct ContractArgs {
   real *garena;                     // arena in global memory (or null)
   int64_t garena_stride;            // entries per tile
   int32_t S, logS;                  // samples per tile (power of two <= 64)
+  int32_t *pq;                      // persistent form: tile counter and exit count (zero between launches)
 };
 
 struct LdsPlan {
@@ -53,9 +54,11 @@ size_t contract_lds_bytes(const InstDesc &D, int S, bool bwd, bool global_arena,
 // Global arena entries per tile (per sample entries times S).
 int64_t contract_garena_entries(const InstDesc &D, int S, bool bwd);
 
+// persistent: one workgroup per resident slot, tiles taken from a.pq in
+// order (else one workgroup per tile)
 template <typename real>
 hipError_t launch_contract(const ContractArgs<real> &a, int n_tiles, size_t lds,
-                           bool bwd, bool global_arena, hipStream_t st);
+                           bool bwd, bool global_arena, hipStream_t st, bool persistent = false);
 
 // Sum per-tile partials and scatter dh, dJ, dbeta (FP64).
 struct VjpArgs {
@@ -358,6 +361,11 @@ struct ChainArgs {
   // W-neighbour and no field (else those keep the +1 the table was filled
   // with when its layout was set)
   int32_t u_all;
+  // persistent form of the register-resident kernels: task counter and exit
+  // count (zero between launches), and the task range of each width (1, 2,
+  // 4 tiles), taken widest first
+  int32_t *pq;
+  int32_t pq_lo[3], pq_n[3];
 };
 // U and the per-sample sums of beta |f| over each run of kUnaryChunk
 // positions (fabp[f_off[q] + chunk * B + b]) of the instances in cis.
@@ -378,6 +386,8 @@ constexpr int kRegBwdTiles = 2;
 size_t rchain_wave_lds(const ChainLim &L, bool bwd, int sg);
 int64_t rchain_ckpt_floats(const ChainLim &L);   // per adjoint task
 hipError_t launch_rchain(const ChainArgs &a, bool bwd, hipStream_t st);
+// every width of a.pq_lo / a.pq_n in one persistent launch
+hipError_t launch_rchain_pq(const ChainArgs &a, bool bwd, hipStream_t st);
 // logz[b] = log_const + sum over chains of the per-chain partials
 // (plus the unary sums fabp of launch_unary when fabp is not null)
 hipError_t launch_chain_sum(const InstDesc *inst, const ChainInst *cinst,

@@ -108,7 +108,8 @@ Shapes to_shapes(const tnvan_tuning &t) {
   return {{"general_tile_fwd", t.general_tile_fwd},
           {"general_tile_bwd", t.general_tile_bwd},
           {"chain_groups", t.chain_groups},
-          {"checkpoint_every", t.checkpoint_every}};
+          {"checkpoint_every", t.checkpoint_every},
+          {"launch_mode", t.launch_mode}};
 }
 
 void from_shapes(const Shapes &s, tnvan_tuning &t) {
@@ -117,6 +118,7 @@ void from_shapes(const Shapes &s, tnvan_tuning &t) {
   t.general_tile_bwd = get("general_tile_bwd");
   t.chain_groups = get("chain_groups");
   t.checkpoint_every = get("checkpoint_every");
+  t.launch_mode = get("launch_mode");
 }
 
 }  // namespace
@@ -186,6 +188,7 @@ extern "C" tnvan_status tnvan_autotune(tnvan_net *net, const int64_t *n_samples,
   };
   tnvan_tuning best{};
   best.general_tile_fwd = best.general_tile_bwd = best.chain_groups = best.checkpoint_every = 0;
+  best.launch_mode = 0;
   tnvan_status status = TNVAN_OK;
   // coordinate by coordinate: each field over its candidates with the others
   // at their best so far; the default rule (0) stays unless another
@@ -195,7 +198,8 @@ extern "C" tnvan_status tnvan_autotune(tnvan_net *net, const int64_t *n_samples,
       {&tnvan_tuning::general_tile_fwd, false, {1, 2, 4, 8, 16, 32, 64}, TNVAN_TUNE_GENERAL},
       {&tnvan_tuning::general_tile_bwd, true, {1, 2, 4, 8, 16, 32, 64}, TNVAN_TUNE_GENERAL},
       {&tnvan_tuning::chain_groups, false, {1, 2}, TNVAN_TUNE_REG_CHAIN},
-      {&tnvan_tuning::checkpoint_every, true, {1, 2, 4}, TNVAN_TUNE_REG_CHAIN}};
+      {&tnvan_tuning::checkpoint_every, true, {1, 2, 4}, TNVAN_TUNE_REG_CHAIN},
+      {&tnvan_tuning::launch_mode, true, {2}, TNVAN_TUNE_GENERAL | TNVAN_TUNE_REG_CHAIN}};
   for (const Field &fd : fields) {
     if (!(cur.kinds & fd.kind)) continue;
     tnvan_tuning t = best;

@@ -411,3 +411,28 @@ def test_checkpoint_and_resume_bit_for_bit(prec, split):
         for which in (0, 2, 3):
             assert torch.equal(a.get_state(k, which), b.get_state(k, which)), (k, which)
         assert a.get_step(k) == b.get_step(k) == 6
+
+
+def test_c1_as_configured_fp64_training():
+    # the 4x4 workload as specified: FP64 path, 1024 samples, hidden 16,
+    # 200 Adam steps at lr 1e-3; the exact F_q of the trained network
+    # (enumeration of its 16 width-set states) lies between F (2^16-state
+    # enumeration, Eq. 5) and the exact F_q it started from
+    inst = S.c1_small_lattice(16)
+    net = _net([inst], "fp64", seed=1)
+    th0 = S.made_init(4, 16, 3)
+    net.set_params(0, torch.from_numpy(th0))
+    stats = torch.empty(1, 4, dtype=torch.float64, device="cuda")
+    print("\n[c1] 200 FP64 training steps", flush=True)
+    for _ in range(200):
+        net.free_energy_step(1024, 1e-3, stats=stats)
+    th = net.get_params(0).cpu().numpy().astype(np.float64)
+    F = OO.exact_free_energy(inst)
+    Fq0, _ = OO.exact_fq_and_grad(inst, th0.astype(np.float64), 16)
+    Fq1, _ = OO.exact_fq_and_grad(inst, th, 16)
+    print(f"[c1] F = {F:.6f}, exact F_q {Fq0:.6f} -> {Fq1:.6f}", flush=True)
+    assert F - 1e-12 <= Fq1 < Fq0
+    assert net.get_step(0) == 200
+    # the last batch estimate is within 5 standard errors of the exact F_q
+    st = stats.cpu().numpy()[0]
+    assert abs(st[0] - Fq1) <= 5 * st[1] + 1e-9

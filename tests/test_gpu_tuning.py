@@ -115,3 +115,74 @@ def test_autotune_applies_and_caches(tmp_path):
         if val[k]:
             assert again[k] == val[k]
     assert json.loads(cache.read_text()) == entries
+
+
+def _uneven():
+    # lattices of three chain widths, random regular graphs (general steps)
+    # and an empty instance, with uneven batches
+    insts = [S.c2_lattice(1.0, 32), S.c1_small_lattice(16), S.c4_rrg(),
+             S.lattice_column_split(S.lattice_2d(8, seed=4, h_var=0.1), [5], hidden=16),
+             S.c4_small_copies(limit=3)[3], S.lattice_column_split(S.lattice_2d(12, seed=8), [5, 9], hidden=16)]
+    for i in insts:
+        if not i.hidden:
+            i.hidden = 8
+    return insts, [1000, 333, 517, 0, 129, 2048]
+
+
+@pytest.mark.parametrize("prec,split", [("fp32", True), ("fp32", False), ("bf16", False), ("fp64", False)])
+def test_persistent_launches_equal_per_tile_launches(prec, split):
+    # every (instance, tile or chain, sample group) item writes only its own
+    # outputs, so the persistent work-queue launches give the same logZ and
+    # adjoint bit for bit; called repeatedly (the queue counters reset)
+    from paper_2504_12037_amd import Net
+    insts, Bs = _uneven()
+    sp = [S.uniform_spins(b, i.n_width, 140 + k) for k, (b, i) in enumerate(zip(Bs, insts))]
+    flat = _dev(np.concatenate([x.reshape(-1) for x in sp]))
+    g = _dev(np.concatenate([np.random.default_rng(k).standard_normal(b) for k, b in enumerate(Bs)]))
+    fl = Net.FLAG_SPLIT_BF16 if split else 0
+    ref_net = Net(insts, precision=prec, flags=fl)
+    ref = [x.clone() for x in ref_net.logz_and_backward(flat, g, Bs)]
+    ref_f = ref_net.logz(flat, Bs).clone()
+    net = Net(insts, precision=prec, flags=fl)
+    net.set_tuning(launch_mode=2)
+    assert net.get_tuning()["launch_mode"] == 2
+    print(f"\n[persistent] prec={prec} split={split}", flush=True)
+    for rep in range(3):
+        out = net.logz_and_backward(flat, g, Bs)
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b), rep
+        assert torch.equal(net.logz(flat, Bs), ref_f)
+    lz = ref_f.cpu().numpy()
+    off = 0
+    for inst, b, s in zip(insts, Bs, sp):
+        if b:
+            want = OI.logz_r_elimination(inst, s[:24])
+            tol = {"fp64": 1e-10, "fp32": 1e-5, "bf16": 1e-3}[prec]
+            assert np.abs(lz[off:off + 24] - want).max() / inst.n <= tol
+        off += b
+
+
+def test_persistent_training_step_replayed():
+    # the recorded training step with the adjoint in persistent launches,
+    # replayed, equals the eager per-tile step bit for bit
+    from paper_2504_12037_amd import Net
+    insts, Bs = _uneven()
+    runs = []
+    for mode, flags in ((1, 0), (2, Net.FLAG_GRAPH)):
+        net = Net(insts, precision="fp32", seed=4, flags=Net.FLAG_SPLIT_BF16 | flags)
+        net.set_tuning(launch_mode=mode)
+        for q, inst in enumerate(insts):
+            net.set_params(q, torch.from_numpy(S.made_init(inst.n_width, inst.hidden, 30 + q)))
+        g = torch.cat([torch.full((b,), 1.0 / max(b, 1), dtype=torch.float64, device="cuda")
+                       for b in Bs])
+        adj = (g,) + net._adjoint_out(None)
+        res = []
+        for it in range(4):
+            print(f"\n[persistent-step] mode={mode} it={it}", flush=True)
+            st, _ = net.free_energy_step(Bs, 1e-2, adjoint=adj)
+            res.append([st.clone()] + [a.clone() for a in adj[1:]])
+        torch.cuda.synchronize()
+        runs.append(res)
+    for it, (a, b) in enumerate(zip(runs[0], runs[1])):
+        for x, y in zip(a, b):
+            assert torch.equal(x, y), it
