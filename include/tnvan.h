@@ -82,7 +82,9 @@ typedef struct {
 
 typedef struct {
   int32_t precision;          /* tnvan_precision */
-  int32_t max_width;          /* largest message scope allowed (<= 14) */
+  int32_t max_width;          /* largest message scope allowed (<= 20; scopes of 15-20
+                               * only for single-spin steps, whose transfer factors
+                               * are formed on the fly) */
   int32_t deterministic;      /* reserved: every reduction is ordered */
   int32_t flags;              /* TNVAN_FLAG_* bits, 0 for the defaults */
   uint64_t seed;              /* key of the Philox4x32-10 stream of q */

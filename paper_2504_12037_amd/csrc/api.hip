@@ -128,7 +128,7 @@ struct tnvan_net {
   HostProgram P;
   int n_inst = 0;
   // program on the device
-  DBuf inst, steps, inputs, gtab, edges, T, fld_ptr, fld_w, fld_J, hR, wr_pos, wr_w;
+  DBuf inst, steps, inputs, gtab, gtab2, esmall, edges, T, fld_ptr, fld_w, fld_J, hR, wr_pos, wr_w;
   DBuf rr_edge, rr_J, wr_edge, wr_J, hR64, vr, ww_a, ww_b, ww_J, hW;
   // network
   std::vector<MadeInst> mi;
@@ -222,6 +222,7 @@ struct tnvan_net {
   std::vector<hipStream_t> call_streams;
   tnvan_tuning tune{};        // requested launch shapes (0: default rule)
   int rk_build = 1;           // adjoint checkpoint interval from the options
+  bool wide = false;          // some general-kernel instance has a step wider than kTabW
   int rs() const { return precision == TNVAN_FP64 ? 8 : 4; }
 };
 
@@ -301,6 +302,22 @@ bool choose_tiles(tnvan_net *net, bool bwd, int req = 0) {
   };
   int S = 64;
   bool glob = false;
+  if (net->wide) {
+    // wide steps: the arena is in device memory, S the largest <= 16 whose
+    // LDS part fits (or the requested one)
+    glob = true;
+    if (req > 0) {
+      S = req;
+      if (worst_of(S, true) > (size_t)maxlds) return false;
+    } else {
+      for (S = 16; S > 1; S >>= 1)
+        if (worst_of(S, true) <= budget) break;
+    }
+    const size_t worst = worst_of(S, true);
+    if (bwd) { net->S_bwd = S; net->glob_bwd = true; net->lds_bwd = worst; }
+    else { net->S_fwd = S; net->glob_fwd = true; net->lds_fwd = worst; }
+    return true;
+  }
   if (req > 0) {
     S = req;
     glob = worst_of(S, false) > (size_t)maxlds;
@@ -322,6 +339,16 @@ bool choose_tiles(tnvan_net *net, bool bwd, int req = 0) {
 }
 
 bool persistent(const tnvan_net *net) { return net->tune.launch_mode == 2; }
+
+// Device arenas of the general kernel above this many bytes are not laid
+// out per tile: the launch goes persistent with one arena per workgroup, at
+// most as many workgroups as fit (the batch then runs in chunks of that many
+// tiles).  Returns that workgroup count, or 0 when one arena per tile fits.
+constexpr int64_t kArenaBudget = (int64_t)48 << 30;
+int arena_cap(int64_t tile_bytes, int n_tiles) {
+  if (tile_bytes <= 0 || tile_bytes * (int64_t)n_tiles <= kArenaBudget) return 0;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(n_tiles, kArenaBudget / tile_bytes));
+}
 
 // 16-sample groups per wave of the register-resident forward on chains of
 // 1-2 tiles (the tuned value, else two when that still leaves a wave per
@@ -583,6 +610,8 @@ ContractArgs<real> contract_args(tnvan_net *net, TileCache &tc, int S) {
   a.steps = net->steps.as<StepDesc>();
   a.inputs = net->inputs.as<InputDesc>();
   a.gtab = net->gtab.as<uint16_t>();
+  a.gtab2 = net->gtab2.as<uint32_t>();
+  a.esmall = net->esmall.as<real>();
   a.edges = net->edges.as<EdgeDesc>();
   a.T = net->T.as<real>();
   a.fld_ptr = net->fld_ptr.as<int32_t>();
@@ -600,6 +629,7 @@ ContractArgs<real> contract_args(tnvan_net *net, TileCache &tc, int S) {
   a.inst_partial_off = tc.partial_off.as<int64_t>();
   a.S = S;
   a.logS = ilog2(S);
+  a.wide = net->wide ? 1 : 0;
   return a;
 }
 
@@ -610,16 +640,19 @@ tnvan_status run_logz(tnvan_net *net, const int8_t *spins, double *logz, hipStre
   auto a = contract_args<real>(net, net->tc_fwd, net->S_fwd);
   a.spins = spins;
   a.logz = logz;
+  int cap = 0;
   if (net->glob_fwd) {
     int64_t per = 0;
     for (auto &D : net->P.insts) per = std::max(per, contract_garena_entries(D, net->S_fwd, false));
-    HIPCHK(net->garena.ensure((size_t)per * net->tc_fwd.n_tiles * sizeof(real)));
+    cap = arena_cap(per * (int64_t)sizeof(real), net->tc_fwd.n_tiles);
+    HIPCHK(net->garena.ensure((size_t)per * (cap ? cap : net->tc_fwd.n_tiles) * sizeof(real)));
     a.garena = net->garena.as<real>();
     a.garena_stride = per;
+    a.arena_per_block = cap > 0;
   }
   a.pq = net->pq.as<int32_t>();
   HIPCHK(launch_contract<real>(a, net->tc_fwd.n_tiles, net->lds_fwd, false, net->glob_fwd, st,
-                               persistent(net)));
+                               persistent(net) || cap > 0, cap));
   if (std::count(net->use_chain.begin(), net->use_chain.end(), 1)) {
     s = ensure_chain_tasks(net);
     if (s) return s;
@@ -682,16 +715,19 @@ tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *gra
   a.grad = grad;
   HIPCHK(net->partial.ensure(std::max<int64_t>(1, tc.partial_total) * sizeof(real)));
   a.partial = net->partial.as<real>();
+  int cap = 0;
   if (net->glob_bwd) {
     int64_t per = 0;
     for (auto &D : net->P.insts) per = std::max(per, contract_garena_entries(D, net->S_bwd, true));
-    HIPCHK(net->garena.ensure((size_t)per * tc.n_tiles * sizeof(real)));
+    cap = arena_cap(per * (int64_t)sizeof(real), tc.n_tiles);
+    HIPCHK(net->garena.ensure((size_t)per * (cap ? cap : tc.n_tiles) * sizeof(real)));
     a.garena = net->garena.as<real>();
     a.garena_stride = per;
+    a.arena_per_block = cap > 0;
   }
   a.pq = net->pq.as<int32_t>() + 2;
   HIPCHK(launch_contract<real>(a, tc.n_tiles, net->lds_bwd, true, net->glob_bwd, st,
-                               persistent(net)));
+                               persistent(net) || cap > 0, cap));
   if (std::count(net->use_chain.begin(), net->use_chain.end(), 1)) {
     s = ensure_chain_tasks(net);
     if (s) return s;
@@ -1253,17 +1289,18 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   HostProgram &P = net->P;
 #define UP(buf, vec) if ((e = upload(net->buf, vec)) != hipSuccess) return fail(e, #buf);
 #define UP2(buf, vec) if ((e = upload(net->buf, vec)) != hipSuccess) return fail(e, #buf);
-  UP(inst, P.insts) UP(steps, P.steps) UP(inputs, P.inputs) UP(gtab, P.gtab) UP(edges, P.edges)
+  UP(inst, P.insts) UP(steps, P.steps) UP(inputs, P.inputs) UP(gtab, P.gtab) UP(gtab2, P.gtab2)
+  UP(edges, P.edges)
   UP(fld_ptr, P.fld_ptr) UP(fld_w, P.fld_w) UP(wr_pos, P.wr_pos) UP(wr_w, P.wr_w)
   UP(rr_edge, P.rr_edge) UP(rr_J, P.rr_J) UP(wr_edge, P.wr_edge) UP(wr_J, P.wr_J)
   UP(hR64, P.hR) UP(vr, P.vr) UP(ww_a, P.ww_a) UP(ww_b, P.ww_b) UP(ww_J, P.ww_J)
   UP(hW, P.hW) UP(d_hw_off, P.hw_off) UP(ww_e, P.ww_e) UP(d_wv, P.wv)
   if (net->precision == TNVAN_FP64) {
-    UP(T, P.T) UP(fld_J, P.fld_J) UP(hR, P.hR)
+    UP(T, P.T) UP(fld_J, P.fld_J) UP(hR, P.hR) UP(esmall, P.esmall)
   } else {
     std::vector<float> t(P.T.begin(), P.T.end()), fj(P.fld_J.begin(), P.fld_J.end()),
-        hr(P.hR.begin(), P.hR.end());
-    UP(T, t) UP(fld_J, fj) UP(hR, hr)
+        hr(P.hR.begin(), P.hR.end()), es(P.esmall.begin(), P.esmall.end());
+    UP(T, t) UP(fld_J, fj) UP(hR, hr) UP(esmall, es)
   }
   {
     std::vector<int64_t> sb(n_inst), eb(n_inst);
@@ -1381,6 +1418,8 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
       net->rfwd = net->rbwd = false;
     }
   }
+  for (int q = 0; q < n_inst; ++q)
+    if (!net->use_chain[q] && net->P.insts[q].max_w > kTabW) net->wide = true;
   choose_tiles(net, false);
   choose_tiles(net, true);
 #undef UP
@@ -1403,7 +1442,8 @@ void tnvan_free_network(tnvan_net *net) {
     hipEventDestroy(e.second);
   }
   net->prof_pool.clear();
-  DBuf *all[] = {&net->inst, &net->steps, &net->inputs, &net->gtab, &net->edges, &net->T, &net->fld_ptr,
+  DBuf *all[] = {&net->inst, &net->steps, &net->inputs, &net->gtab, &net->gtab2, &net->esmall,
+                 &net->edges, &net->T, &net->fld_ptr,
                  &net->fld_w, &net->fld_J, &net->hR, &net->wr_pos, &net->wr_w, &net->rr_edge,
                  &net->rr_J, &net->wr_edge, &net->wr_J, &net->hR64, &net->vr, &net->ww_a,
                  &net->ww_b, &net->ww_J, &net->hW, &net->d_mi, &net->params, &net->adam_m,

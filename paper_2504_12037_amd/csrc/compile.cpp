@@ -499,7 +499,9 @@ tnvan_status compile_instance(const tnvan_instance &in, int max_width,
       fail(msg, "step %ld creates a message over %ld spins (above the width limit)", t, w);
       return TNVAN_E_WIDTH;
     }
-    if (g + w > 20) { fail(msg, "step %ld: group plus scope above 20 bits", t); return TNVAN_E_WIDTH; }
+    // single-spin steps may reach kMaxW output bits (wide steps); grouped
+    // steps keep their full tables, 2^(g + w) <= 2^20 entries
+    if (g + w > 20 && !(g == 1 && w <= kMaxW)) { fail(msg, "step %ld: group plus scope above 20 bits", t); return TNVAN_E_WIDTH; }
     if ((int)ins.size() > kMaxInputs) { fail(msg, "step %ld has too many input messages", t); return TNVAN_E_INVALID; }
     StepDesc sd{};
     sd.g = g; sd.gpos = gs; sd.w = w; sd.n_in = (int32_t)ins.size();
@@ -513,6 +515,11 @@ tnvan_status compile_instance(const tnvan_instance &in, int max_width,
     else {
       fail(msg, "grouped step %ld: its input messages must form exactly one message over the group", t);
       return TNVAN_E_INVALID;
+    }
+    const bool wide = w > kTabW;
+    if (wide && (dense || (int)ins.size() > kWideIn)) {
+      fail(msg, "step %ld: a message over %ld spins from a grouped step or with too many inputs", t, w);
+      return TNVAN_E_WIDTH;
     }
     // inputs
     sd.in_off = (int32_t)P.inputs.size();
@@ -530,7 +537,18 @@ tnvan_status compile_instance(const tnvan_instance &in, int max_width,
         }
       }
       id.gb_off = -1;
-      if (!dense) {
+      if (wide) {
+        // split tables: the entry for o's low 10 bits and for its high bits
+        id.gb_off = (int32_t)P.gtab2.size();
+        for (int part = 0; part < 2; ++part)
+          for (int j = 0; j < 1024; ++j) {
+            const int o = part ? j << 10 : j;
+            uint32_t idx = 0;
+            for (int b = 0; b < id.nbits; ++b)
+              if (id.src[b] >= 0 && o < (1 << w)) idx |= (uint32_t)((o >> id.src[b]) & 1) << b;
+            P.gtab2.push_back(idx);
+          }
+      } else if (!dense) {
         // the input's entry for every output entry o (eliminated spin +1)
         if (P.gtab.size() + ((size_t)1 << w) > (size_t)INT32_MAX) {
           fail(msg, "gather tables above 2^31 entries");
@@ -561,15 +579,25 @@ tnvan_status compile_instance(const tnvan_instance &in, int max_width,
         EdgeDesc ed{};
         ed.rr = nb.second; ed.bu = bu; ed.bv = bv;
         P.edges.push_back(ed);
+        {
+          const double Jv = rrJ[nb.second];
+          const double sm = std::exp(-2.0 * beta * std::fabs(Jv));
+          P.esmall.push_back(Jv < 0.0 ? -sm : sm);
+        }
         tb.push_back({bu, bv});
         tj.push_back(rrJ[nb.second]);
         log_const += beta * std::fabs(rrJ[nb.second]);
       }
     }
     sd.n_edge = (int32_t)P.edges.size() - sd.edge_off;
+    if (wide && sd.n_edge > kWideEdges) {
+      fail(msg, "step %ld: a message over %ld spins consuming too many edges", t, w);
+      return TNVAN_E_WIDTH;
+    }
     // T[(x << w) | o] = prod_e exp(beta J s_u s_v - beta |J|), bit 1 <=> spin -1
-    sd.t_off = (int64_t)P.T.size();
-    const int64_t nT = (int64_t)1 << (g + w);
+    // (a wide step forms it on the fly from its edges)
+    sd.t_off = wide ? -1 : (int64_t)P.T.size();
+    const int64_t nT = wide ? 0 : (int64_t)1 << (g + w);
     for (int64_t c = 0; c < nT; ++c) {
       double lg = 0.0;
       for (size_t e = 0; e < tb.size(); ++e) {

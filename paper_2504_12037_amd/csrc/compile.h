@@ -15,6 +15,8 @@ struct HostProgram {
   std::vector<StepDesc> steps;
   std::vector<InputDesc> inputs;
   std::vector<uint16_t> gtab;     // gather tables of SINGLE steps' inputs
+  std::vector<uint32_t> gtab2;    // split gather tables of wide steps' inputs (2 x 1024 each)
+  std::vector<double> esmall;     // per EdgeDesc: exp(-2 beta |J|), negated for J < 0
   std::vector<EdgeDesc> edges;
   std::vector<double> T;          // all step tables, FP64
   std::vector<int32_t> fld_ptr;   // per instance: nr + 1 entries (local)

@@ -177,9 +177,88 @@ __device__ inline real fast_fwd(const FastIn<real> &f, const real *Tt, int w, re
   return lmax;
 }
 
+// Wide single-spin steps (output scope above kTabW bits, no full table):
+// each input's arena offset, split gather tables, x bit and scale, and the
+// step's edges (o bit and signed small factor), read once per step.
+template <typename real>
+struct WideIn {
+  int n_in, n_e;
+  int ioff[kWideIn], xs[kWideIn];
+  const uint32_t *lo[kWideIn];
+  const uint32_t *hi[kWideIn];
+  real sc[kWideIn];
+  int eb[kWideEdges];
+  real es[kWideEdges];
+};
+
+template <typename real, bool kBwd>
+__device__ inline WideIn<real> wide_inputs(const ContractArgs<real> &a, const StepDesc &sd,
+                                           const StepDesc *steps,
+                                           const typename FBits<real>::U *mx, int S, int sme) {
+  using FB = FBits<real>;
+  WideIn<real> f;
+  f.n_in = sd.n_in;
+  f.n_e = sd.n_edge;
+#pragma unroll
+  for (int k = 0; k < kWideIn; ++k) {
+    if (k < sd.n_in) {
+      const InputDesc id = a.inputs[sd.in_off + k];
+      const StepDesc ps = steps[id.step];
+      f.ioff[k] = kBwd ? ps.off_all : ps.off_fwd;
+      f.xs[k] = 1 << id.xbit;
+      f.lo[k] = a.gtab2 + id.gb_off;
+      f.hi[k] = a.gtab2 + id.gb_off + 1024;
+      f.sc[k] = FB::scale(FB::expo(mx[id.step * S + sme]));
+    } else {
+      f.ioff[k] = 0;
+      f.xs[k] = 0;
+      f.lo[k] = f.hi[k] = a.gtab2;
+      f.sc[k] = (real)1;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < kWideEdges; ++e) {
+    if (e < sd.n_edge) {
+      f.eb[e] = a.edges[sd.edge_off + e].bv;
+      f.es[e] = a.esmall[sd.edge_off + e];
+    } else {
+      f.eb[e] = 0;
+      f.es[e] = (real)1;
+    }
+  }
+  return f;
+}
+
+// p0 and p1 (output entry o, eliminated spin +1 and -1) times the step's
+// transfer factors and the inputs' entries
+template <typename real>
+__device__ inline void wide_pair(const WideIn<real> &f, const real *arena, int S, int sme, int o,
+                                 real &p0, real &p1) {
+  real t0 = 1, t1 = 1;
+#pragma unroll
+  for (int e = 0; e < kWideEdges; ++e)
+    if (e < f.n_e) {
+      // J s_x s_o > 0: factor 1, else exp(-2 beta |J|); bit 1 <=> spin -1
+      const int ob = (o >> f.eb[e]) & 1;
+      const bool pos = f.es[e] > (real)0;
+      const real sm = pos ? f.es[e] : -f.es[e];
+      t0 *= ((ob == 0) == pos) ? (real)1 : sm;
+      t1 *= ((ob == 1) == pos) ? (real)1 : sm;
+    }
+  p0 *= t0;
+  p1 *= t1;
+#pragma unroll
+  for (int k = 0; k < kWideIn; ++k)
+    if (k < f.n_in) {
+      const int64_t e = (int64_t)f.ioff[k] + (int64_t)(f.lo[k][o & 1023] | f.hi[k][o >> 10]);
+      p0 *= arena[e * S + sme] * f.sc[k];
+      p1 *= arena[(e + f.xs[k]) * S + sme] * f.sc[k];
+    }
+}
+
 // One tile of S samples of one instance through every step (forward, or
 // forward then reverse), the workgroup's LDS at smem.
-template <typename real, bool kGlobal, bool kBwd>
+template <typename real, bool kGlobal, bool kBwd, bool kWide>
 __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile, char *smem) {
   using FB = FBits<real>;
   using U = typename FB::U;
@@ -198,7 +277,9 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
   real *arena;
   real *scr;
   if (kGlobal) {
-    arena = a.garena + (int64_t)tile * a.garena_stride;
+    // one arena per tile, or per resident workgroup (a persistent launch
+    // whose batch does not fit device memory at once)
+    arena = a.garena + (int64_t)(a.arena_per_block ? (int)blockIdx.x : tile) * a.garena_stride;
     scr = arena + (int64_t)(kBwd ? D.arena_all : D.arena_fwd) * S;
   } else {
     arena = reinterpret_cast<real *>(smem + Lo.arena);
@@ -233,7 +314,7 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
     const StepDesc sd = steps[t];
     const int w = sd.w, g = sd.g;
     const int off = kBwd ? sd.off_all : sd.off_fwd;
-    const real *Tt = a.T + sd.t_off;
+    const real *Tt = a.T + (sd.t_off >= 0 ? sd.t_off : 0);
     real lmax = 0;
     if (sd.kind == STEP_DENSE) {
       int inoff = 0;
@@ -259,6 +340,20 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
 #pragma unroll 8
         for (int x = 0; x < nx; ++x) acc += Tt[(x << w) | o] * scr[x * S + sme];
         arena[(off + o) * S + sme] = acc;
+        lmax = acc > lmax ? acc : lmax;
+      }
+    } else if (kWide && sd.t_off < 0) {
+      // wide step: transfer factors from the edges, split gathers
+      const WideIn<real> f = wide_inputs<real, kBwd>(a, sd, steps, mx, S, sme);
+      const real ph0 = phi[(2 * sd.gpos) * S + sme], ph1 = phi[(2 * sd.gpos + 1) * S + sme];
+      for (int i = tid; i < (S << w); i += kThreads) {
+        const int o = i >> logS;
+        real p0 = ph0, p1 = ph1;
+        wide_pair<real>(f, arena, S, sme, o, p0, p1);
+        real acc = 0;
+        acc += p0;
+        acc += p1;
+        arena[((int64_t)off + o) * S + sme] = acc;
         lmax = acc > lmax ? acc : lmax;
       }
     } else if (sd.n_in <= kFastIn) {
@@ -327,7 +422,7 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
     const StepDesc sd = steps[t];
     const int w = sd.w, g = sd.g;
     const int off = sd.off_all;
-    const real *Tt = a.T + sd.t_off;
+    const real *Tt = a.T + (sd.t_off >= 0 ? sd.t_off : 0);
     const real sct = FB::scale(FB::expo(mx[t * S + sme]));
     // adjoint factor of the output entry o for sample sme
     auto rfac = [&](int o) -> real {
@@ -352,21 +447,21 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
         for (int j = 0; j < g; ++j) A *= phi[(2 * (sd.gpos + j) + ((x >> j) & 1)) * S + sme];
         if (sd.n_in) A *= arena[(inoff + x) * S + sme] * insc;
         real lam = 0;
-        real lj[kMaxW];
+        real lj[kTabW];
 #pragma unroll
-        for (int j = 0; j < kMaxW; ++j) lj[j] = 0;
+        for (int j = 0; j < kTabW; ++j) lj[j] = 0;
         const int no = 1 << w;
 #pragma unroll 4
         for (int o = 0; o < no; ++o) {
           const real tr = Tt[(x << w) | o] * rfac(o);
           lam += tr;
 #pragma unroll
-          for (int j = 0; j < kMaxW; ++j)
+          for (int j = 0; j < kTabW; ++j)
             if (j < w) lj[j] += ((o >> j) & 1) ? -tr : tr;
         }
         sA[x * S + sme] = A;
 #pragma unroll
-        for (int j = 0; j < kMaxW; ++j)
+        for (int j = 0; j < kTabW; ++j)
           if (j < w) sL[(x * (w + 1) + j) * S + sme] = lj[j];
         sL[(x * (w + 1) + w) * S + sme] = lam;
       }
@@ -415,7 +510,18 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
       __syncthreads();
     } else {
       // SINGLE: joint weights c(o, x) into scratch [(o*2 + x)][S]
-      if (sd.n_in <= kFastIn) {
+      if (kWide && sd.t_off < 0) {
+        const WideIn<real> f = wide_inputs<real, true>(a, sd, steps, mx, S, sme);
+        const real ph0 = phi[(2 * sd.gpos) * S + sme], ph1 = phi[(2 * sd.gpos + 1) * S + sme];
+        for (int i = tid; i < (S << w); i += kThreads) {
+          const int o = i >> logS;
+          const real r = rfac(o);
+          real p0 = r * ph0, p1 = r * ph1;
+          wide_pair<real>(f, arena, S, sme, o, p0, p1);
+          scr[(o * 2) * S + sme] = p0;
+          scr[(o * 2 + 1) * S + sme] = p1;
+        }
+      } else if (sd.n_in <= kFastIn) {
         const FastIn<real> f = fast_inputs<real, true>(a, sd, steps, mx, S, sme);
         const real ph0 = phi[(2 * sd.gpos) * S + sme], ph1 = phi[(2 * sd.gpos + 1) * S + sme];
         auto joint = [&](auto ni) {
@@ -547,17 +653,17 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
   for (int k = tid; k < D.n_rr; k += kThreads) a.partial[prow + D.nr + D.n_wr + k] = Cw[k];
 }
 
-template <typename real, bool kGlobal, bool kBwd>
+template <typename real, bool kGlobal, bool kBwd, bool kWide>
 __global__ __launch_bounds__(kThreads) void contract_kernel(ContractArgs<real> a) {
   extern __shared__ __align__(16) char smem[];
-  contract_tile<real, kGlobal, kBwd>(a, blockIdx.x, smem);
+  contract_tile<real, kGlobal, kBwd, kWide>(a, blockIdx.x, smem);
 }
 
 // Persistent form: the launch's workgroups take tiles from a device counter
 // (a.pq[0]) in tile order (the instances with the costliest samples first)
 // until none is left; the last workgroup to leave resets the counter and
 // its exit count (a.pq[1]) for the next launch on the stream.
-template <typename real, bool kGlobal, bool kBwd>
+template <typename real, bool kGlobal, bool kBwd, bool kWide>
 __global__ __launch_bounds__(kThreads) void contract_pq_kernel(ContractArgs<real> a, int n_tiles) {
   extern __shared__ __align__(16) char smem[];
   __shared__ int next;
@@ -567,7 +673,7 @@ __global__ __launch_bounds__(kThreads) void contract_pq_kernel(ContractArgs<real
     __syncthreads();
     const int tile = next;
     if (tile >= n_tiles) break;
-    contract_tile<real, kGlobal, kBwd>(a, tile, smem);
+    contract_tile<real, kGlobal, kBwd, kWide>(a, tile, smem);
   }
   if (threadIdx.x == 0 && atomicAdd(a.pq + 1, 1) == (int)gridDim.x - 1) {
     atomicExch(a.pq, 0);
@@ -653,12 +759,16 @@ int64_t contract_garena_entries(const InstDesc &D, int S, bool bwd) {
 
 template <typename real>
 hipError_t launch_contract(const ContractArgs<real> &a, int n_tiles, size_t lds,
-                           bool bwd, bool global_arena, hipStream_t st, bool persistent) {
+                           bool bwd, bool global_arena, hipStream_t st, bool persistent,
+                           int max_grid) {
   if (n_tiles <= 0) return hipSuccess;
+  if (a.wide && !global_arena) return hipErrorInvalidValue;
   if (persistent) {
+    // (nets with wide steps always have their arena in device memory)
     void (*k)(ContractArgs<real>, int);
-    if (bwd) k = global_arena ? contract_pq_kernel<real, true, true> : contract_pq_kernel<real, false, true>;
-    else k = global_arena ? contract_pq_kernel<real, true, false> : contract_pq_kernel<real, false, false>;
+    if (a.wide) k = bwd ? contract_pq_kernel<real, true, true, true> : contract_pq_kernel<real, true, false, true>;
+    else if (bwd) k = global_arena ? contract_pq_kernel<real, true, true, false> : contract_pq_kernel<real, false, true, false>;
+    else k = global_arena ? contract_pq_kernel<real, true, false, false> : contract_pq_kernel<real, false, false, false>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -669,13 +779,15 @@ hipError_t launch_contract(const ContractArgs<real> &a, int n_tiles, size_t lds,
         (e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void *>(k),
                                                           kThreads, lds)) != hipSuccess)
       return e;
-    const int grid = std::max(1, std::min(n_tiles, cus * std::max(per, 1)));
+    int grid = std::max(1, std::min(n_tiles, cus * std::max(per, 1)));
+    if (max_grid > 0) grid = std::min(grid, max_grid);
     hipLaunchKernelGGL(k, dim3(grid), dim3(kThreads), lds, st, a, n_tiles);
     return hipGetLastError();
   }
   void (*k)(ContractArgs<real>);
-  if (bwd) k = global_arena ? contract_kernel<real, true, true> : contract_kernel<real, false, true>;
-  else k = global_arena ? contract_kernel<real, true, false> : contract_kernel<real, false, false>;
+  if (a.wide) k = bwd ? contract_kernel<real, true, true, true> : contract_kernel<real, true, false, true>;
+  else if (bwd) k = global_arena ? contract_kernel<real, true, true, false> : contract_kernel<real, false, true, false>;
+  else k = global_arena ? contract_kernel<real, true, false, false> : contract_kernel<real, false, false, false>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -696,8 +808,8 @@ hipError_t launch_vjp_reduce(const VjpArgs &a, const real *partial, int n_inst, 
 int vjp_split() { return kColSplit; }
 
 
-template hipError_t launch_contract<float>(const ContractArgs<float> &, int, size_t, bool, bool, hipStream_t, bool);
-template hipError_t launch_contract<double>(const ContractArgs<double> &, int, size_t, bool, bool, hipStream_t, bool);
+template hipError_t launch_contract<float>(const ContractArgs<float> &, int, size_t, bool, bool, hipStream_t, bool, int);
+template hipError_t launch_contract<double>(const ContractArgs<double> &, int, size_t, bool, bool, hipStream_t, bool, int);
 template hipError_t launch_vjp_reduce<float>(const VjpArgs &, const float *, int, int, hipStream_t);
 template hipError_t launch_vjp_reduce<double>(const VjpArgs &, const double *, int, int, hipStream_t);
 

@@ -17,7 +17,9 @@ struct ContractArgs {
   const StepDesc *steps;
   const InputDesc *inputs;
   const uint16_t *gtab;             // gather tables of SINGLE steps' inputs
+  const uint32_t *gtab2;            // split gather tables of wide steps' inputs
   const EdgeDesc *edges;
+  const real *esmall;               // per edge: exp(-2 beta |J|), negated for J < 0
   const real *T;
   const int32_t *fld_ptr;
   const int32_t *fld_w;
@@ -41,6 +43,8 @@ struct ContractArgs {
   int64_t garena_stride;            // entries per tile
   int32_t S, logS;                  // samples per tile (power of two <= 64)
   int32_t *pq;                      // persistent form: tile counter and exit count (zero between launches)
+  int32_t arena_per_block;          // device arena per resident workgroup (persistent), not per tile
+  int32_t wide;                     // some instance has wide steps (their kernel variant)
 };
 
 struct LdsPlan {
@@ -56,9 +60,12 @@ int64_t contract_garena_entries(const InstDesc &D, int S, bool bwd);
 
 // persistent: one workgroup per resident slot, tiles taken from a.pq in
 // order (else one workgroup per tile)
+// persistent with max_grid > 0: at most that many workgroups (each with its
+// own arena when a.arena_per_block)
 template <typename real>
 hipError_t launch_contract(const ContractArgs<real> &a, int n_tiles, size_t lds,
-                           bool bwd, bool global_arena, hipStream_t st, bool persistent = false);
+                           bool bwd, bool global_arena, hipStream_t st, bool persistent = false,
+                           int max_grid = 0);
 
 // Sum per-tile partials and scatter dh, dJ, dbeta (FP64).
 struct VjpArgs {

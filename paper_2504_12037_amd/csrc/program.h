@@ -32,10 +32,20 @@ enum StepKind : int32_t {
   STEP_SINGLE = 1,
 };
 
-constexpr int kMaxScope = 16;   // bits of any message / input scope
-constexpr int kMaxW = 14;       // output scope bits
+constexpr int kMaxScope = 24;   // bits of any message / input scope
+constexpr int kMaxW = 20;       // output scope bits
+constexpr int kTabW = 14;       // widest step with a full transfer table and gather tables
 constexpr int kMaxG = 8;        // group size
 constexpr int kMaxInputs = 24;
+constexpr int kWideIn = 8;      // most inputs of a wide step
+constexpr int kWideEdges = 8;   // most R-R edges a wide step consumes
+
+// Wide steps (single-spin steps with an output scope of kTabW + 1 .. kMaxW
+// bits): no 2^(w+1)-entry transfer table (t_off = -1); T[x, o] is formed on
+// the fly from the step's edges as the product over them of 1 where
+// J s_x s_o > 0, else exp(-2 beta |J|) (esmall holds that value per edge,
+// negated for J < 0); each input gathers through two 1024-entry tables
+// (gtab2: the entry for the low 10 and for the high 10 bits of o, or-ed).
 
 struct StepDesc {
   int32_t kind;
@@ -55,7 +65,7 @@ struct InputDesc {
   int32_t step;       // producing step (local index within the instance)
   int32_t nbits;      // scope size of the message
   int32_t xbit;       // SINGLE: bit of the eliminated vertex in this scope
-  int32_t gb_off;     // SINGLE: offset of its gather table in gtab, or -1
+  int32_t gb_off;     // SINGLE: offset of its gather table in gtab (gtab2 for a wide step), or -1
   int8_t src[kMaxScope];  // scope bit b -> o-bit index, or -1 for x (SINGLE)
 };
 // Gather table of a SINGLE step's input (gtab[gb_off + o], 2^w entries):

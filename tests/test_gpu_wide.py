@@ -1,0 +1,102 @@
+"""Message scopes of 15-20 spins (the paper's w_u = 20 plans, Sec. 4 and
+Figs. 2-3) through the C ABI: wide single-spin steps form their transfer
+factors on the fly and gather through split tables, and a batch whose
+device arenas exceed the arena budget runs persistent, in chunks of
+resident workgroups.  Sampled outputs against the oracle's elimination,
+the adjoint against its reverse pass, and global-flip symmetry on every
+output of a large batch."""
+
+import numpy as np
+import pytest
+
+import synthetic as S
+from adjtol import check_vjp
+from oracle import ising as OI
+from synthetic import instances as SI
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5}
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda().reshape(-1)
+
+
+def _rrg1000():
+    # n = 1000, d = 3, +-J, beta 0.5 (Sec. 4 / Fig. 3), W from the planner at w_u = 20
+    from paper_2504_12037_amd import plan_width_set
+    e = SI.random_regular_edges(1000, 3, np.random.default_rng(9))
+    W, order, width, _ = plan_width_set(1000, e, 20)
+    J = np.random.default_rng(1).choice([-1.0, 1.0], len(e))
+    h = np.random.default_rng(2).normal(0.0, np.sqrt(0.1), 1000)
+    return S.Instance(1000, e.astype(np.int32), J, h, 0.5, W.astype(np.int32),
+                      order.astype(np.int32), None, 0, "rrg1000_wu20"), width
+
+
+def _lattice40():
+    # the 40x40 ferromagnet at beta_c (Fig. 2), W from the planner at w_u = 20
+    from paper_2504_12037_amd import plan_width_set
+    e = SI.lattice_edges(40)
+    W, order, width, _ = plan_width_set(1600, e, 20, regreedy=True)
+    beta_c = 0.5 * np.log(1.0 + np.sqrt(2.0))
+    return S.Instance(1600, e.astype(np.int32), np.ones(len(e)), np.zeros(1600), beta_c,
+                      W.astype(np.int32), order.astype(np.int32), None, 0, "lattice40_wu20"), width
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("which", ["rrg1000", "lattice40"])
+def test_scope_20_logz_against_the_oracle(which, prec):
+    from paper_2504_12037_amd import Net, plan
+    inst, width = {"rrg1000": _rrg1000, "lattice40": _lattice40}[which]()
+    assert width == 20
+    info = plan(inst, max_width=20)
+    assert info[1] == 20
+    B = 5
+    print(f"\n[wide] {which} prec={prec} |W|={inst.n_width} scope={info[1]} B={B}", flush=True)
+    sp = S.uniform_spins(B, inst.n_width, 17)
+    net = Net([inst], precision=prec, max_width=20)
+    lz = net.logz(_dev(sp), B).cpu().numpy()
+    want = OI.logz_r_elimination(inst, sp, chunk=1)
+    err = np.abs(lz - want).max() / inst.n
+    print(f"[wide] max |dlogZ|/N = {err:.2e}", flush=True)
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_scope_20_adjoint_against_the_oracle(prec):
+    from paper_2504_12037_amd import Net
+    inst, _ = _rrg1000()
+    B = 3
+    print(f"\n[wide-adjoint] prec={prec}", flush=True)
+    sp = S.uniform_spins(B, inst.n_width, 23)
+    g = np.random.default_rng(5).standard_normal(B)
+    net = Net([inst], precision=prec, max_width=20)
+    got = [x.cpu().numpy() for x in net.backward(_dev(sp), _dev(g), B)]
+    check_vjp(got, OI.logz_r_vjp(inst, sp, g), inst, g, prec, "rrg1000_wu20")
+
+
+def test_scope_20_large_batch_in_chunks():
+    # 512 samples of the 40x40 plan: their adjoint arenas (about 0.26 GB per
+    # two-sample tile) exceed the arena budget, so the launch runs resident
+    # workgroups over the tiles in chunks; h = 0, so logZ_R(s) = logZ_R(-s)
+    # on every output, and three outputs against the oracle
+    from paper_2504_12037_amd import Net
+    inst, _ = _lattice40()
+    B = 512
+    print(f"\n[wide-chunks] B={B}", flush=True)
+    sp = S.uniform_spins(B, inst.n_width, 29)
+    net = Net([inst], precision="fp32", max_width=20)
+    g = np.full(B, 1.0 / B)
+    lz, dh, dJ, db = net.logz_and_backward(_dev(sp), _dev(g), B)
+    lz2 = net.logz(_dev(-sp), B)
+    torch.cuda.synchronize()
+    lz, lz2 = lz.cpu().numpy(), lz2.cpu().numpy()
+    assert np.abs(lz - lz2).max() / inst.n <= TOL["fp32"]
+    idx = [0, 211, 511]
+    want = OI.logz_r_elimination(inst, sp[idx], chunk=1)
+    assert np.abs(lz[idx] - want).max() / inst.n <= TOL["fp32"]
+    # the ferromagnet's edge correlations are non-negative averages
+    dJ = dJ.cpu().numpy()
+    assert np.all(np.isfinite(dJ)) and dJ.min() >= -1e-6
