@@ -151,7 +151,13 @@ typedef struct {
    * width, take (instance, tile or chain, sample group) items from a device
    * work queue, the costliest first (0: the default, 1) */
   int32_t launch_mode;
-  int32_t reserved[2];
+  /* upper bound in MiB on the general kernel's device arenas of one call
+   * (0: the default budget, half of the device memory that is free or held
+   * by the arena, at most 96 GiB); a batch whose arenas exceed it runs in
+   * chunks of resident workgroups.  Not timed by the autotuner, which keeps
+   * the value in effect. */
+  int32_t arena_limit_mib;
+  int32_t reserved[1];
 } tnvan_tuning;
 
 /* The launch shapes in effect (defaults resolved; chain_groups 0 until a

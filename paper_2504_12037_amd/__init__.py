@@ -122,8 +122,8 @@ class Net:
 
     def set_tuning(self, **shapes):
         """Request launch shapes (general_tile_fwd, general_tile_bwd,
-        chain_groups, checkpoint_every, launch_mode; 0 or absent = default
-        rule)."""
+        chain_groups, checkpoint_every, launch_mode, arena_limit_mib; 0 or
+        absent = default rule)."""
         t = _lib.CTuning()
         for k, v in shapes.items():
             if k not in _lib.CTuning.FIELDS:

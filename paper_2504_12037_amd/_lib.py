@@ -65,10 +65,10 @@ class CTuning(C.Structure):
     _fields_ = [("general_tile_fwd", C.c_int32), ("general_tile_bwd", C.c_int32),
                 ("chain_groups", C.c_int32), ("kinds", C.c_int32),
                 ("checkpoint_every", C.c_int32), ("launch_mode", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("arena_limit_mib", C.c_int32), ("reserved", C.c_int32 * 1)]
 
     FIELDS = ("general_tile_fwd", "general_tile_bwd", "chain_groups", "checkpoint_every",
-              "launch_mode")
+              "launch_mode", "arena_limit_mib")
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k in self.FIELDS + ("kinds",)}

@@ -303,16 +303,13 @@ bool choose_tiles(tnvan_net *net, bool bwd, int req = 0) {
   int S = 64;
   bool glob = false;
   if (net->wide) {
-    // wide steps: the arena is in device memory, S the largest <= 16 whose
-    // LDS part fits (or the requested one)
+    // wide steps: the arena is in device memory and S = 1 (or the requested
+    // one).  Each sample's step has 2^15 or more entries, enough for a
+    // workgroup, and the samples the arena budget holds at once make the most
+    // waves one sample per workgroup.
     glob = true;
-    if (req > 0) {
-      S = req;
-      if (worst_of(S, true) > (size_t)maxlds) return false;
-    } else {
-      for (S = 16; S > 1; S >>= 1)
-        if (worst_of(S, true) <= budget) break;
-    }
+    S = req > 0 ? req : 1;
+    if (worst_of(S, true) > (size_t)maxlds) return false;
     const size_t worst = worst_of(S, true);
     if (bwd) { net->S_bwd = S; net->glob_bwd = true; net->lds_bwd = worst; }
     else { net->S_fwd = S; net->glob_fwd = true; net->lds_fwd = worst; }
@@ -340,14 +337,22 @@ bool choose_tiles(tnvan_net *net, bool bwd, int req = 0) {
 
 bool persistent(const tnvan_net *net) { return net->tune.launch_mode == 2; }
 
-// Device arenas of the general kernel above this many bytes are not laid
+// Device arenas of the general kernel above the arena budget are not laid
 // out per tile: the launch goes persistent with one arena per workgroup, at
 // most as many workgroups as fit (the batch then runs in chunks of that many
-// tiles).  Returns that workgroup count, or 0 when one arena per tile fits.
-constexpr int64_t kArenaBudget = (int64_t)48 << 30;
-int arena_cap(int64_t tile_bytes, int n_tiles) {
-  if (tile_bytes <= 0 || tile_bytes * (int64_t)n_tiles <= kArenaBudget) return 0;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(n_tiles, kArenaBudget / tile_bytes));
+// tiles).  The budget is half of the device memory that is free or already
+// held by the arena, at most 96 GiB (or the tuned limit).  Returns that workgroup count, or 0
+// when one arena per tile fits.
+constexpr int64_t kArenaMax = (int64_t)96 << 30;
+int arena_cap(const tnvan_net *net, int64_t tile_bytes, int n_tiles) {
+  size_t fr = 0, tot = 0;
+  int64_t budget = kArenaMax;
+  if (hipMemGetInfo(&fr, &tot) == hipSuccess)
+    budget = std::min<int64_t>(budget, (int64_t)(fr + net->garena.bytes) / 2);
+  if (net->tune.arena_limit_mib > 0)
+    budget = std::min<int64_t>(budget, (int64_t)net->tune.arena_limit_mib << 20);
+  if (tile_bytes <= 0 || tile_bytes * (int64_t)n_tiles <= budget) return 0;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(n_tiles, budget / tile_bytes));
 }
 
 // 16-sample groups per wave of the register-resident forward on chains of
@@ -644,7 +649,7 @@ tnvan_status run_logz(tnvan_net *net, const int8_t *spins, double *logz, hipStre
   if (net->glob_fwd) {
     int64_t per = 0;
     for (auto &D : net->P.insts) per = std::max(per, contract_garena_entries(D, net->S_fwd, false));
-    cap = arena_cap(per * (int64_t)sizeof(real), net->tc_fwd.n_tiles);
+    cap = arena_cap(net, per * (int64_t)sizeof(real), net->tc_fwd.n_tiles);
     HIPCHK(net->garena.ensure((size_t)per * (cap ? cap : net->tc_fwd.n_tiles) * sizeof(real)));
     a.garena = net->garena.as<real>();
     a.garena_stride = per;
@@ -719,7 +724,7 @@ tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *gra
   if (net->glob_bwd) {
     int64_t per = 0;
     for (auto &D : net->P.insts) per = std::max(per, contract_garena_entries(D, net->S_bwd, true));
-    cap = arena_cap(per * (int64_t)sizeof(real), tc.n_tiles);
+    cap = arena_cap(net, per * (int64_t)sizeof(real), tc.n_tiles);
     HIPCHK(net->garena.ensure((size_t)per * (cap ? cap : tc.n_tiles) * sizeof(real)));
     a.garena = net->garena.as<real>();
     a.garena_stride = per;
@@ -1951,6 +1956,7 @@ tnvan_status tnvan_get_tuning(const tnvan_net *net, tnvan_tuning *out) {
                                          : 0;
   out->checkpoint_every = chain && net->rbwd ? net->lim_bwd.rk : 0;
   out->launch_mode = net->tune.launch_mode > 0 ? net->tune.launch_mode : 1;
+  out->arena_limit_mib = net->tune.arena_limit_mib;
   return TNVAN_OK;
 }
 
@@ -1967,6 +1973,7 @@ tnvan_status tnvan_set_tuning(tnvan_net *net, const tnvan_tuning *in) {
     return set_err(TNVAN_E_INVALID, "checkpoint_every must be 0, 1, 2, 4 or 8");
   if (in->launch_mode < 0 || in->launch_mode > 2)
     return set_err(TNVAN_E_INVALID, "launch_mode must be 0, 1 or 2");
+  if (in->arena_limit_mib < 0) return set_err(TNVAN_E_INVALID, "arena_limit_mib must be >= 0");
   if (net->rbwd) {
     // the replayed states of one segment live in LDS beside each wave's data
     ChainLim L = net->lim_bwd;
@@ -1984,6 +1991,7 @@ tnvan_status tnvan_set_tuning(tnvan_net *net, const tnvan_tuning *in) {
   net->tune.chain_groups = in->chain_groups;
   net->tune.checkpoint_every = k;
   net->tune.launch_mode = in->launch_mode;
+  net->tune.arena_limit_mib = in->arena_limit_mib;
   net->lim_bwd.rk = k > 0 ? k : net->rk_build;
   if (!choose_tiles(net, false, in->general_tile_fwd) || !choose_tiles(net, true, in->general_tile_bwd)) {
     net->tune = old;

@@ -528,12 +528,14 @@ tnvan_status compile_instance(const tnvan_instance &in, int max_width,
       id.step = m.step;
       id.nbits = (int32_t)m.scope.size();
       id.xbit = -1;
+      id.omask = 0;
       for (int b = 0; b < id.nbits; ++b) {
         int p = m.scope[b];
         if (p >= gs && p < ge) { id.src[b] = -1; id.xbit = b; }
         else {
           int j = (int)(std::lower_bound(S.begin(), S.end(), p) - S.begin());
           id.src[b] = (int8_t)j;
+          id.omask |= 1 << j;
         }
       }
       id.gb_off = -1;

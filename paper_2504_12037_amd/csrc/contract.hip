@@ -34,6 +34,7 @@ namespace tnvan {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kLogThreads = 8;
 constexpr int kWaves = kThreads / 64;
 constexpr int kRed = 4;         // values per column reduction pass
 
@@ -98,10 +99,11 @@ template <> __device__ inline float rexp<float>(float x) { return expf(x); }
 template <> __device__ inline double rexp<double>(double x) { return exp(x); }
 
 // index of the input message entry for output entry o and group state x
-__device__ inline int gather_index(const InputDesc &id, int o, int x) {
+// (id in device memory: its scope map is read there, not from a private copy)
+__device__ inline int gather_index(const InputDesc *id, int o, int x) {
   int idx = 0;
-  for (int b = 0; b < id.nbits; ++b) {
-    int sb = id.src[b];
+  for (int b = 0; b < id->nbits; ++b) {
+    int sb = id->src[b];
     int bit = sb < 0 ? x : ((o >> sb) & 1);
     idx |= bit << b;
   }
@@ -373,10 +375,10 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
         for (int x = 0; x < 2; ++x) {
           real p = Tt[(x << w) | o] * phi[(2 * sd.gpos + x) * S + sme];
           for (int k = 0; k < sd.n_in; ++k) {
-            const InputDesc id = a.inputs[sd.in_off + k];
-            const StepDesc ps = steps[id.step];
+            const InputDesc *id = a.inputs + sd.in_off + k;
+            const StepDesc ps = steps[id->step];
             const int ioff = kBwd ? ps.off_all : ps.off_fwd;
-            const real sc = FB::scale(FB::expo(mx[id.step * S + sme]));
+            const real sc = FB::scale(FB::expo(mx[id->step * S + sme]));
             p *= arena[(ioff + gather_index(id, o, x)) * S + sme] * sc;
           }
           acc += p;
@@ -385,7 +387,13 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
         lmax = acc > lmax ? acc : lmax;
       }
     }
-    if (tid < (S << w)) atomicMax(&mx[t * S + sme], FB::bits(lmax));
+    // the step's largest entry per sample: the wave's lanes of one sample
+    // first, then one LDS atomic per sample and wave
+    for (int sh = S; sh < 64; sh <<= 1) {
+      const real o = __shfl_xor(lmax, sh, 64);
+      lmax = o > lmax ? o : lmax;
+    }
+    if ((tid & 63) < S && tid < (S << w)) atomicMax(&mx[t * S + sme], FB::bits(lmax));
     __syncthreads();
   }
 
@@ -549,9 +557,9 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
         for (int x = 0; x < 2; ++x) {
           real p = r * Tt[(x << w) | o] * phi[(2 * sd.gpos + x) * S + sme];
           for (int k = 0; k < sd.n_in; ++k) {
-            const InputDesc id = a.inputs[sd.in_off + k];
-            const StepDesc ps = steps[id.step];
-            const real sc = FB::scale(FB::expo(mx[id.step * S + sme]));
+            const InputDesc *id = a.inputs + sd.in_off + k;
+            const StepDesc ps = steps[id->step];
+            const real sc = FB::scale(FB::expo(mx[id->step * S + sme]));
             p *= arena[(ps.off_all + gather_index(id, o, x)) * S + sme] * sc;
           }
           scr[(o * 2 + x) * S + sme] = p;
@@ -563,27 +571,64 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
         const InputDesc id = a.inputs[sd.in_off + k];
         const StepDesc ps = steps[id.step];
         const real sc = FB::scale(FB::expo(mx[id.step * S + sme]));
-        int omask = 0;
-        for (int b = 0; b < id.nbits; ++b)
-          if (id.src[b] >= 0) omask |= 1 << id.src[b];
+        const int omask = id.omask;
         const int freem = ((1 << w) - 1) & ~omask;
-        for (int i = tid; i < (S << id.nbits); i += kThreads) {
-          const int j = i >> logS;
-          int ofix = 0, x = 0;
-          for (int b = 0; b < id.nbits; ++b) {
-            const int bit = (j >> b) & 1;
-            if (id.src[b] < 0) x = bit;
-            else ofix |= bit << id.src[b];
+        // 2^lc lanes share one (entry, sample) sum: each takes one pattern of
+        // the lowest lc free bits and walks the others, and the wave adds
+        // the lanes' parts (lc aims at two passes of the workgroup; a lane
+        // group never leaves its wave)
+        int lc = kLogThreads + 1 - logS - id.nbits;
+        lc = lc < 0 ? 0 : lc;
+        lc = lc < 6 - logS ? lc : 6 - logS;
+        lc = lc < __popc(freem) ? lc : __popc(freem);
+        int highm = freem;
+        for (int b = 0; b < lc; ++b) highm &= highm - 1;
+        const int nit = 1 << __popc(highm);
+        for (int i = tid; i < (S << (id.nbits + lc)); i += kThreads) {
+          const int c = (i >> logS) & ((1 << lc) - 1);
+          const int j = i >> (logS + lc);
+          // entry j: the eliminated spin's bit, the others deposited in
+          // order on the output bits of the scope (both scopes ascend)
+          const int x = (j >> id.xbit) & 1;
+          int rest = ((j >> (id.xbit + 1)) << id.xbit) | (j & ((1 << id.xbit) - 1));
+          int ofix = 0;
+          for (int om = omask; om; om &= om - 1) {
+            if (rest & 1) ofix |= om & -om;
+            rest >>= 1;
           }
-          real mu = 0;
+          int mm = freem & ~highm;
+          for (int b = 0; b < lc; ++b) {
+            const int lsb = mm & -mm;
+            if ((c >> b) & 1) ofix |= lsb;
+            mm ^= lsb;
+          }
+          // the subsets z of highm in increasing order, four at a time
+          const real *col = scr + x * S + sme;
+          real m0 = 0, m1 = 0, m2 = 0, m3 = 0;
           int z = 0;
-          do {
-            mu += scr[(((ofix | z) * 2) + x) * S + sme];
-            z = (z - freem) & freem;
-          } while (z != 0);
-          real *slot = &arena[(ps.off_all + j) * S + sme];
-          const real m = *slot * sc;
-          *slot = m > 0 ? mu / m : (real)0;
+          if (nit >= 4) {
+            for (int it = 0; it < nit; it += 4) {
+              const int z1 = (z - highm) & highm, z2 = (z1 - highm) & highm;
+              const int z3 = (z2 - highm) & highm;
+              m0 += col[(int64_t)((ofix | z) * 2) * S];
+              m1 += col[(int64_t)((ofix | z1) * 2) * S];
+              m2 += col[(int64_t)((ofix | z2) * 2) * S];
+              m3 += col[(int64_t)((ofix | z3) * 2) * S];
+              z = (z3 - highm) & highm;
+            }
+          } else {
+            for (int it = 0; it < nit; ++it) {
+              m0 += col[(int64_t)((ofix | z) * 2) * S];
+              z = (z - highm) & highm;
+            }
+          }
+          real mu = (m0 + m1) + (m2 + m3);
+          for (int sh = S; sh < (S << lc); sh <<= 1) mu += __shfl_xor(mu, sh, 64);
+          if (c == 0) {
+            real *slot = &arena[((int64_t)ps.off_all + j) * S + sme];
+            const real m = *slot * sc;
+            *slot = m > 0 ? mu / m : (real)0;
+          }
         }
       }
       // per-sample sums over o: magnetisation of v and its edge correlations

@@ -66,6 +66,7 @@ struct InputDesc {
   int32_t nbits;      // scope size of the message
   int32_t xbit;       // SINGLE: bit of the eliminated vertex in this scope
   int32_t gb_off;     // SINGLE: offset of its gather table in gtab (gtab2 for a wide step), or -1
+  int32_t omask;      // SINGLE: the output bits that are in this scope (OR of 1 << src[b] >= 0)
   int8_t src[kMaxScope];  // scope bit b -> o-bit index, or -1 for x (SINGLE)
 };
 // Gather table of a SINGLE step's input (gtab[gb_off + o], 2^w entries):

@@ -160,6 +160,7 @@ extern "C" tnvan_status tnvan_autotune(tnvan_net *net, const int64_t *n_samples,
     if (it != cache.end()) {
       tnvan_tuning t{};
       from_shapes(it->second, t);
+      t.arena_limit_mib = cur.arena_limit_mib;
       if (tnvan_set_tuning(net, &t) == TNVAN_OK) return tnvan_get_tuning(net, out);
     }
   }
@@ -189,6 +190,7 @@ extern "C" tnvan_status tnvan_autotune(tnvan_net *net, const int64_t *n_samples,
   tnvan_tuning best{};
   best.general_tile_fwd = best.general_tile_bwd = best.chain_groups = best.checkpoint_every = 0;
   best.launch_mode = 0;
+  best.arena_limit_mib = cur.arena_limit_mib;
   tnvan_status status = TNVAN_OK;
   // coordinate by coordinate: each field over its candidates with the others
   // at their best so far; the default rule (0) stays unless another

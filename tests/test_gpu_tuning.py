@@ -186,3 +186,43 @@ def test_persistent_training_step_replayed():
     for it, (a, b) in enumerate(zip(runs[0], runs[1])):
         for x, y in zip(a, b):
             assert torch.equal(x, y), it
+
+
+def _wide16():
+    # random 3-regular graph, n = 100, planned at w_u = 16: single-spin steps
+    # of up to 16-spin scopes, whose arenas are in device memory
+    from paper_2504_12037_amd import plan_width_set
+    from synthetic import instances as SI
+    e = SI.random_regular_edges(100, 3, np.random.default_rng(3))
+    W, order, width, _ = plan_width_set(100, e, 16)
+    assert width == 16
+    rng = np.random.default_rng(8)
+    return S.Instance(100, e.astype(np.int32), rng.choice([-1.0, 1.0], len(e)),
+                      rng.normal(0.0, 0.3, 100), 0.7, W.astype(np.int32),
+                      order.astype(np.int32), None, 0, "rrg100_wu16")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_arena_limit_runs_the_batch_in_chunks(prec):
+    # a 1 MiB limit leaves one resident workgroup, which takes every tile in
+    # turn: the same per-tile arithmetic in the same tile order, so logZ and
+    # the adjoint are unchanged bit for bit
+    from paper_2504_12037_amd import Net
+    inst = _wide16()
+    B = 300
+    sp = S.uniform_spins(B, inst.n_width, 41)
+    flat = _dev(sp)
+    g = _dev(np.random.default_rng(7).standard_normal(B))
+    outs = []
+    for lim in (0, 1):
+        print(f"\n[arena-limit] prec={prec} limit={lim}", flush=True)
+        net = Net([inst], precision=prec, max_width=20)
+        net.set_tuning(arena_limit_mib=lim)
+        assert net.get_tuning()["arena_limit_mib"] == lim
+        outs.append([net.logz(flat, B).clone()] +
+                    [x.clone() for x in net.logz_and_backward(flat, g, B)])
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
+    want = OI.logz_r_elimination(inst, sp[:6], chunk=1)
+    tol = {"fp64": 1e-10, "fp32": 1e-5}[prec]
+    assert np.abs(outs[0][0].cpu().numpy()[:6] - want).max() / inst.n <= tol

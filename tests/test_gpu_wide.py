@@ -78,8 +78,8 @@ def test_scope_20_adjoint_against_the_oracle(prec):
 
 
 def test_scope_20_large_batch_in_chunks():
-    # 512 samples of the 40x40 plan: their adjoint arenas (about 0.26 GB per
-    # two-sample tile) exceed the arena budget, so the launch runs resident
+    # 512 samples of the 40x40 plan under an 8 GiB arena limit: their adjoint
+    # arenas (about 0.13 GB per sample) exceed it, so the launch runs resident
     # workgroups over the tiles in chunks; h = 0, so logZ_R(s) = logZ_R(-s)
     # on every output, and three outputs against the oracle
     from paper_2504_12037_amd import Net
@@ -88,6 +88,7 @@ def test_scope_20_large_batch_in_chunks():
     print(f"\n[wide-chunks] B={B}", flush=True)
     sp = S.uniform_spins(B, inst.n_width, 29)
     net = Net([inst], precision="fp32", max_width=20)
+    net.set_tuning(arena_limit_mib=8192)
     g = np.full(B, 1.0 / B)
     lz, dh, dJ, db = net.logz_and_backward(_dev(sp), _dev(g), B)
     lz2 = net.logz(_dev(-sp), B)
