@@ -17,8 +17,11 @@ Modules
             exact enumeration over small width sets, the training loop of
             Algorithm 1
   philox    Philox4x32-10 counter-based generator (Salmon et al., SC'11)
+  magnetisation
+            conditional law of the remainder's magnetisation given s_W and
+            the importance-weighted susceptibility estimator (Sec. 3)
 
 Parity status of every function is listed in its module header.
 """
 
-from . import ising, made, objective, philox  # noqa: F401
+from . import ising, made, magnetisation, objective, philox  # noqa: F401
