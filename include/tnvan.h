@@ -232,6 +232,25 @@ tnvan_status tnvan_set_params(tnvan_net *net, int32_t inst, const float *src_dev
 tnvan_status tnvan_get_params(tnvan_net *net, int32_t inst, float *dst_dev,
                               void *stream);
 
+/* New couplings J, fields h and inverse temperature beta for instance i of
+ * a built net (Sec. 2: E of Eq. 1 plus fields, and with it E_1, E_2 and the
+ * static transfer factors exp(beta J s s') of the contraction, Eqs. 2-4).
+ * The instance is compiled again from its build-time edges, width set,
+ * order and grouping with the new values, and every device table is
+ * rewritten in place; the parameters of q, the Adam moments, the step
+ * counter and the launch shapes stay.  Synchronous: waits for all work the
+ * net has queued (on any stream) before the tables change; the next call
+ * lays its per-call tables out again, and a recorded training-step graph is
+ * recorded anew.
+ *   J     host double [n_edges], in the edge order of the build
+ *   h     host double [n_spins], or NULL for h = 0
+ *   beta  finite, >= 0
+ * Errors: instance index out of range, J NULL with edges, non-finite J or h,
+ * beta < 0 or not finite (TNVAN_E_INVALID; nothing changes); called while a
+ * graph is recorded (TNVAN_E_STATE). */
+tnvan_status tnvan_set_couplings(tnvan_net *net, int32_t inst, const double *J, const double *h,
+                                 double beta);
+
 /* Copy one state vector of instance i into device memory (float32,
  * param_count entries, stream-ordered): which = 0 parameters, 1 gradient of
  * the last free_energy_step, 2 Adam first moment, 3 Adam second moment.
@@ -272,11 +291,15 @@ tnvan_status tnvan_sample(tnvan_net *net, const int64_t *n_samples,
 /* Batched conditional log-partition function (Eqs. 3-4): for every sample,
  * logz[b] = ln sum_r exp(-beta E_2(s_W(b), r)), by exact contraction along
  * the compiled order with per-step power-of-two rescaling; the log-norm and
- * the result are FP64 in every precision.
+ * the result are FP64 in every precision.  Optionally also the width-set
+ * energy of Eq. 4, E_1(s_W) = -sum_{W-W edges} J_ij s_i s_j - sum_{i in W}
+ * h_i s_i, so that Etilde = E_1 - logz / beta (Eq. 3) needs nothing more.
  *   spins  dev int8 [sum n_samples * |W|] (layout as tnvan_sample)
- *   logz   dev double out [sum n_samples] */
+ *   logz   dev double out [sum n_samples]
+ *   e1     dev double out [sum n_samples], or NULL (not computed); FP64 in
+ *          every precision, the W-W terms in edge order, then the fields */
 tnvan_status tnvan_logz_batch(tnvan_net *net, const int64_t *n_samples,
-                              const int8_t *spins, double *logz, void *stream);
+                              const int8_t *spins, double *logz, double *e1, void *stream);
 
 /* Adjoint of tnvan_logz_batch: writes the vector-Jacobian product
  *   dh[i]    = sum_b g_b dlogZ_R(b)/dh_i     = beta sum_b g_b <r_i>_b
@@ -295,8 +318,9 @@ tnvan_status tnvan_logz_backward(tnvan_net *net, const int64_t *n_samples,
 
 /* Allocation-free variant of tnvan_logz_batch, for callers that cannot
  * allocate device memory: code recorded into a HIP graph, serving loops and
- * harnesses that forbid hipMalloc.  Same arguments and results as
- * tnvan_logz_batch (bit for bit: the same kernels and arithmetic), but every
+ * harnesses that forbid hipMalloc.  The arguments of tnvan_logz_batch
+ * without e1, and the same logz (bit for bit: the same kernels and
+ * arithmetic), but every
  * per-call table and workspace lives in one file-scope device array of
  * TNVAN_NOALLOC_SCRATCH_BYTES (32 MiB) per GPU, which the library keeps
  * until the process ends; the call makes no allocation, no host-to-device
@@ -392,6 +416,44 @@ tnvan_status tnvan_exact_free_energy(tnvan_net *net, int32_t inst, double *out, 
 tnvan_status tnvan_observables(tnvan_net *net, const int64_t *n_samples, const int8_t *spins,
                                const void *logq, double *mag, double *corr, double *ess,
                                void *stream);
+
+/* Conditional moments of the remainder's magnetisation M_R = sum_{r in R} r
+ * given each sample's width-set spins, under p(r | s_W) proportional to
+ * exp(-beta E_2(s_W, r)) (Eqs. 3-4): the ingredients of the susceptibility
+ * (Sec. 3: magnetisation and susceptibility from the trained network).
+ * With eta = beta H for a uniform field H on R, the mean is d ln Z_R / d eta
+ * and the variance d^2 ln Z_R / d eta^2; both come exactly from one
+ * contraction of second-order Taylor coefficients in eta (jets) along the
+ * compiled order, in the net's precision (FP64 for TNVAN_FP64, else FP32
+ * jets with the dense products in FP32), cumulants formed in FP64.
+ *   spins  dev int8 as tnvan_logz_batch
+ *   logz   dev double out [sum n_samples], or NULL: ln Z_R of the same pass
+ *   mean   dev double out [sum n_samples]: <M_R | s_W>
+ *   var    dev double out [sum n_samples]: Var(M_R | s_W)
+ * Device workspace: (arena + scratch entries of the program) x 3 jets per
+ * sample.  Errors: a message scope above 14 (TNVAN_E_WIDTH). */
+tnvan_status tnvan_remainder_moments(tnvan_net *net, const int64_t *n_samples,
+                                     const int8_t *spins, double *logz, double *mean, double *var,
+                                     void *stream);
+
+/* Magnetisation moments and susceptibility of the Boltzmann distribution p
+ * (Eq. 1) from samples of q (Sec. 3), per instance with M = sum_i s_i over
+ * all N spins:
+ *   out[4 i + 0] = <M>_p / N
+ *   out[4 i + 1] = <M^2>_p / N^2
+ *   out[4 i + 2] = chi = beta N (out[1] - out[0]^2)  (beta (<M^2> - <M>^2) / N)
+ *   out[4 i + 3] = effective sample size (sum w)^2 / sum w^2
+ * Importance weights as tnvan_observables (w_b proportional to
+ * exp(-beta f_b), f_b of Eq. 9); given s_W, M = M_W + M_R, so each sample
+ * contributes M_W + <M_R> to <M> and (M_W + <M_R>)^2 + Var(M_R) to <M^2>
+ * (tnvan_remainder_moments).  FP64 sums in a fixed order.  The step counter
+ * is not advanced.
+ *   n_samples, spins, logq  as tnvan_observables
+ *   out   dev double out [n_inst * 4]
+ * Errors: beta <= 0 on any instance; a plain host buffer (TNVAN_E_INVALID);
+ * a message scope above 14 (TNVAN_E_WIDTH). */
+tnvan_status tnvan_susceptibility(tnvan_net *net, const int64_t *n_samples, const int8_t *spins,
+                                  const void *logq, double *out, void *stream);
 
 /* Per-instance program statistics of the compiled order (host values):
  *   info[0] steps, [1] largest message scope, [2] arena entries per sample,

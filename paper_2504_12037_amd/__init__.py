@@ -212,16 +212,42 @@ class Net:
                                            _ptr(logq), _stream()))
         return spins[:tot], logq[:sum(counts)]
 
-    def logz(self, spins: torch.Tensor, n_samples, out: torch.Tensor = None):
+    def logz(self, spins: torch.Tensor, n_samples, out: torch.Tensor = None,
+             e1: bool = False):
+        """logZ_R per sample (float64 device tensor); with e1=True also
+        E_1(s_W) per sample: returns (logz, e1)."""
         arr, counts = self._counts(n_samples)
         spins = spins.to(device="cuda").contiguous()
         assert spins.dtype == torch.int8
         assert spins.numel() == sum(b * w for b, w in zip(counts, self.nw))
         if out is None:
             out = torch.empty(max(sum(counts), 1), device="cuda", dtype=torch.float64)
-        _lib.check(_lib.lib().tnvan_logz_batch(self._h, arr, _ptr(spins), _ptr(out),
+        e = torch.empty(max(sum(counts), 1), device="cuda", dtype=torch.float64) if e1 else None
+        _lib.check(_lib.lib().tnvan_logz_batch(self._h, arr, _ptr(spins), _ptr(out), _ptr(e),
                                                _stream()))
+        if e1:
+            return out[:sum(counts)], e[:sum(counts)]
         return out[:sum(counts)]
+
+    def set_couplings(self, inst: int, J, h, beta: float):
+        """tnvan_set_couplings: new couplings [n_edges], fields [n] (or None)
+        and inverse temperature of instance ``inst``; the tables are compiled
+        again, the parameters of q and the optimiser state stay."""
+        import numpy as np
+        Jn = np.ascontiguousarray(np.asarray(J, dtype=np.float64).reshape(-1))
+        assert Jn.size == self.ne[inst]
+        hn = None
+        if h is not None:
+            hn = np.ascontiguousarray(np.asarray(h, dtype=np.float64).reshape(-1))
+            assert hn.size == self.n[inst]
+        ptr = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)
+        _lib.check(_lib.lib().tnvan_set_couplings(self._h, int(inst), ptr(Jn), ptr(hn),
+                                                  float(beta)))
+        e0, n0 = sum(self.ne[:inst]), sum(self.n[:inst])
+        Jt, ht, bt = self.couplings
+        Jt[e0:e0 + Jn.size] = torch.from_numpy(Jn)
+        ht[n0:n0 + self.n[inst]] = 0.0 if hn is None else torch.from_numpy(hn)
+        bt[inst] = float(beta)
 
     def logz_noalloc(self, spins: torch.Tensor, n_samples, out: torch.Tensor):
         """tnvan_logz_batch_noalloc: logz into ``out`` (a float64 device
@@ -249,6 +275,32 @@ class Net:
         _lib.check(_lib.lib().tnvan_observables(self._h, arr, _ptr(spins), _ptr(logq), _ptr(mag),
                                                 _ptr(corr), _ptr(ess), _stream()))
         return mag, corr[:sum(self.ne)], ess
+
+    def remainder_moments(self, spins: torch.Tensor, n_samples):
+        """(logz, mean, var) device float64 tensors [sum n_samples]: ln Z_R,
+        <M_R | s_W> and Var(M_R | s_W) per sample (tnvan_remainder_moments)."""
+        arr, counts = self._counts(n_samples)
+        spins = spins.to(device="cuda").contiguous()
+        assert spins.dtype == torch.int8
+        assert spins.numel() == sum(b * w for b, w in zip(counts, self.nw))
+        out = [torch.empty(max(sum(counts), 1), device="cuda", dtype=torch.float64)
+               for _ in range(3)]
+        _lib.check(_lib.lib().tnvan_remainder_moments(self._h, arr, _ptr(spins), _ptr(out[0]),
+                                                      _ptr(out[1]), _ptr(out[2]), _stream()))
+        return tuple(t[:sum(counts)] for t in out)
+
+    def susceptibility(self, spins: torch.Tensor, logq: torch.Tensor, n_samples):
+        """[n_inst, 4] device float64: <M>/N, <M^2>/N^2, chi = beta N
+        (<M^2>/N^2 - (<M>/N)^2) and the effective sample size, estimated
+        from samples of q (tnvan_susceptibility)."""
+        arr, counts = self._counts(n_samples)
+        spins = spins.to(device="cuda").contiguous()
+        logq = logq.to(device="cuda", dtype=self.logq_dtype).contiguous()
+        assert spins.dtype == torch.int8 and logq.numel() == sum(counts)
+        out = torch.empty(len(counts), 4, device="cuda", dtype=torch.float64)
+        _lib.check(_lib.lib().tnvan_susceptibility(self._h, arr, _ptr(spins), _ptr(logq),
+                                                   _ptr(out), _stream()))
+        return out
 
     def exact_free_energy(self, inst: int = 0, out: torch.Tensor = None):
         """(logZ, F) of one instance by slicing over all 2^|W| width-set
@@ -328,10 +380,10 @@ class LogZ(torch.autograd.Function):
 
     J [sum E], h [sum N] and beta [n_inst] are the couplings, fields and
     inverse temperatures of the net's instances, concatenated in instance
-    order.  The net's tables are compiled from them at build, so the values
-    passed must be the ones the net was built with, rounded to the dtype
-    passed (else ValueError: build a new net for new couplings); they take
-    part for their gradients.  The
+    order.  Where an instance's values differ from those its tables hold
+    (compared in the caller's dtype, i.e. the held values rounded to it),
+    tnvan_set_couplings compiles that instance again with the values passed
+    (as float64) before the forward.  The
     forward is tnvan_logz_batch, the backward tnvan_logz_backward with the
     incoming gradient as g_b, returning (dJ, dh, dbeta) = (beta sum g <x x>,
     beta sum g <r>, -sum g <E_2>) (Eqs. 3-4 differentiated).
@@ -339,12 +391,20 @@ class LogZ(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, J, h, beta, spins, net: Net, n_samples):
-        for name, got, built in zip(("J", "h", "beta"), (J, h, beta), net.couplings):
-            # compared in the caller's dtype: the built values rounded to it
-            g = got.detach().to("cpu").reshape(-1)
-            if g.shape != built.shape or not torch.equal(g, built.to(g.dtype)):
-                raise ValueError(f"LogZ: {name} differs from the values the net was built "
-                                 "with; build a net for the new couplings")
+        got = [t.detach().to("cpu").reshape(-1) for t in (J, h, beta)]
+        for name, g, held in zip(("J", "h", "beta"), got, net.couplings):
+            if g.shape != held.shape:
+                raise ValueError(f"LogZ: {name} has {g.numel()} entries, the net "
+                                 f"holds {held.numel()}")
+        e0 = n0 = 0
+        for k in range(len(net.instances)):
+            sl = [slice(e0, e0 + net.ne[k]), slice(n0, n0 + net.n[k]), slice(k, k + 1)]
+            if any(not torch.equal(g[s], held[s].to(g.dtype))
+                   for g, held, s in zip(got, net.couplings, sl)):
+                net.set_couplings(k, got[0][sl[0]].double().numpy(),
+                                  got[1][sl[1]].double().numpy(), float(got[2][k]))
+            e0 += net.ne[k]
+            n0 += net.n[k]
         ctx.net = net
         ctx.n_samples = n_samples
         ctx.meta = [(t.dtype, t.device, t.shape) for t in (J, h, beta)]

@@ -29,9 +29,11 @@ STATUS = {0: "TNVAN_OK", 1: "TNVAN_E_INVALID", 2: "TNVAN_E_WIDTH",
 EXPORTS = ["tnvan_build_network", "tnvan_free_network", "tnvan_last_error",
            "tnvan_param_count", "tnvan_set_params", "tnvan_get_params",
            "tnvan_get_state", "tnvan_set_state", "tnvan_get_step", "tnvan_set_step",
+           "tnvan_set_couplings",
            "tnvan_sample", "tnvan_logz_batch", "tnvan_logz_batch_noalloc",
            "tnvan_logz_backward",
            "tnvan_logz_and_backward", "tnvan_exact_free_energy", "tnvan_observables",
+           "tnvan_remainder_moments", "tnvan_susceptibility",
            "tnvan_free_energy_step",
            "tnvan_free_energy_step_adjoint", "tnvan_program_info", "tnvan_plan",
            "tnvan_plan_width_set",
@@ -100,13 +102,16 @@ def lib():
     L.tnvan_set_state.argtypes = [vp, i32, i32, vp, vp]
     L.tnvan_get_step.argtypes = [vp, i32, C.POINTER(i32), vp]
     L.tnvan_set_step.argtypes = [vp, i32, i32, vp]
+    L.tnvan_set_couplings.argtypes = [vp, i32, vp, vp, C.c_double]
     L.tnvan_sample.argtypes = [vp, vp, vp, vp, vp, vp]
-    L.tnvan_logz_batch.argtypes = [vp, vp, vp, vp, vp]
+    L.tnvan_logz_batch.argtypes = [vp, vp, vp, vp, vp, vp]
     L.tnvan_logz_batch_noalloc.argtypes = [vp, vp, vp, vp, vp]
     L.tnvan_logz_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
     L.tnvan_logz_and_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.tnvan_exact_free_energy.argtypes = [vp, i32, vp, vp]
     L.tnvan_observables.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.tnvan_remainder_moments.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.tnvan_susceptibility.argtypes = [vp, vp, vp, vp, vp, vp]
     L.tnvan_free_energy_step.argtypes = [vp, vp, C.c_float, vp, vp, vp]
     L.tnvan_free_energy_step_adjoint.argtypes = [vp, vp, C.c_float, vp, vp, vp, vp, vp, vp, vp]
     L.tnvan_program_info.argtypes = [vp, i32, vp]

@@ -17,7 +17,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtnvan.so")
-SOURCES = ["compile.cpp", "plan.cpp", "contract.hip", "chain.hip", "chainr.hip", "made.hip", "api.hip", "tune.hip"]
+SOURCES = ["compile.cpp", "plan.cpp", "contract.hip", "chain.hip", "chainr.hip", "made.hip", "moments.hip", "api.hip", "tune.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -154,6 +154,11 @@ struct tnvan_net {
   // workspaces
   DBuf w_xspins, w_xlogz, w_xpart;   // exact slicing
   DBuf ww_e, d_wv, w_og, w_ostats, w_odb;   // observables
+  // magnetisation moments: jets and step exponents of the Taylor contraction,
+  // their per-instance offsets (for the batch key mkey), and the
+  // susceptibility's per-sample moments and effective sample sizes
+  DBuf w_jar, w_jexp, d_jar_off, d_jexp_off, w_mmean, w_mvar, w_oess;
+  std::vector<int64_t> mkey;
   DBuf garena, partial, w_logz, w_logq, w_spins, w_f, w_fpart, w_hid, w_da, w_dlogit, w_sf,
       w_part, d_hw_off, d_sum_off;
   int max_partial = 0, max_out = 1;
@@ -220,6 +225,16 @@ struct tnvan_net {
   // stream, which does not order with non-blocking streams, so an upload
   // first waits for these
   std::vector<hipStream_t> call_streams;
+  // the instances as built (host copies): tnvan_set_couplings recompiles
+  // them with new couplings, fields and inverse temperatures
+  struct SrcInst {
+    int32_t n_spins = 0, n_edges = 0, hidden = 0;
+    std::vector<int32_t> ei, ej, W, order, gp;
+    std::vector<double> J, h;
+    double beta = 0.0;
+  };
+  std::vector<SrcInst> src;
+  int max_width = 0;
   tnvan_tuning tune{};        // requested launch shapes (0: default rule)
   int rk_build = 1;           // adjoint checkpoint interval from the options
   bool wide = false;          // some general-kernel instance has a step wider than kTabW
@@ -361,6 +376,102 @@ int arena_cap(const tnvan_net *net, int64_t tile_bytes, int n_tiles) {
 int chain_groups(const tnvan_net *net, int64_t waves2) {
   if (net->tune.chain_groups > 0) return net->tune.chain_groups;
   return waves2 >= 1024 ? 2 : 1;
+}
+
+// Every device table compiled from the instances (the program, the
+// couplings and fields in their edge classes, the transfer tables of every
+// kernel family): written at build, and rewritten in place by
+// tnvan_set_couplings (same sizes).  *what names the table that failed.
+hipError_t upload_tables(tnvan_net *net, const char **what) {
+  HostProgram &P = net->P;
+  hipError_t e;
+#define UPT(buf, vec) if ((e = upload(net->buf, vec)) != hipSuccess) { *what = #buf; return e; }
+  UPT(inst, P.insts) UPT(steps, P.steps) UPT(inputs, P.inputs) UPT(gtab, P.gtab)
+  UPT(gtab2, P.gtab2) UPT(edges, P.edges)
+  UPT(fld_ptr, P.fld_ptr) UPT(fld_w, P.fld_w) UPT(wr_pos, P.wr_pos) UPT(wr_w, P.wr_w)
+  UPT(rr_edge, P.rr_edge) UPT(rr_J, P.rr_J) UPT(wr_edge, P.wr_edge) UPT(wr_J, P.wr_J)
+  UPT(hR64, P.hR) UPT(vr, P.vr) UPT(ww_a, P.ww_a) UPT(ww_b, P.ww_b) UPT(ww_J, P.ww_J)
+  UPT(hW, P.hW) UPT(d_hw_off, P.hw_off) UPT(ww_e, P.ww_e) UPT(d_wv, P.wv)
+  if (net->precision == TNVAN_FP64) {
+    UPT(T, P.T) UPT(fld_J, P.fld_J) UPT(hR, P.hR) UPT(esmall, P.esmall)
+  } else {
+    std::vector<float> t(P.T.begin(), P.T.end()), fj(P.fld_J.begin(), P.fld_J.end()),
+        hr(P.hR.begin(), P.hR.end()), es(P.esmall.begin(), P.esmall.end());
+    UPT(T, t) UPT(fld_J, fj) UPT(hR, hr) UPT(esmall, es)
+  }
+  {
+    std::vector<float> fj(P.fld_J.begin(), P.fld_J.end()), hr(P.hR.begin(), P.hR.end());
+    UPT(fld_J32, fj) UPT(hR32, hr) UPT(fld_wr, P.fld_wr) UPT(cinst, P.cinst)
+    UPT(chains, P.chains) UPT(csteps, P.csteps) UPT(Tp, P.Tp) UPT(Tt, P.Tt) UPT(Tb, P.Tb)
+  }
+  UPT(Tl, P.Tl) UPT(Tbl, P.Tbl) UPT(cedges, P.cedges)
+  UPT(Tr, P.Tr) UPT(Tq, P.Tq) UPT(Trb, P.Trb) UPT(xcol, P.xcol)
+  UPT(col_out, P.col_out) UPT(pcoef_out, P.pcoef_out)
+  UPT(cf_w, P.cf_w) UPT(cf_r, P.cf_r) UPT(cf_J, P.cf_J) UPT(Tsx, P.Tsx) UPT(Ts3, P.Ts3)
+  UPT(Tdq, P.Tdq)
+#undef UPT
+  return hipSuccess;
+}
+
+// Whether two compiled programs have the same structure: every table of the
+// same size, and the same integers everywhere (steps, edge classes, gather
+// tables, chain layouts, output maps).  Values that follow from J, h and
+// beta may differ.
+template <typename T>
+bool same_bytes(const std::vector<T> &a, const std::vector<T> &b) {
+  return a.size() == b.size() && (a.empty() || !std::memcmp(a.data(), b.data(), a.size() * sizeof(T)));
+}
+bool same_structure(const HostProgram &a, const HostProgram &b) {
+  if (a.insts.size() != b.insts.size()) return false;
+  for (size_t q = 0; q < a.insts.size(); ++q) {
+    InstDesc x = a.insts[q];
+    x.beta = b.insts[q].beta;
+    x.log_const = b.insts[q].log_const;
+    if (std::memcmp(&x, &b.insts[q], sizeof(InstDesc))) return false;
+  }
+  return same_bytes(a.steps, b.steps) && same_bytes(a.inputs, b.inputs) &&
+         same_bytes(a.gtab, b.gtab) && same_bytes(a.gtab2, b.gtab2) &&
+         same_bytes(a.edges, b.edges) && same_bytes(a.fld_ptr, b.fld_ptr) &&
+         same_bytes(a.fld_w, b.fld_w) && same_bytes(a.wr_pos, b.wr_pos) &&
+         same_bytes(a.wr_w, b.wr_w) && same_bytes(a.wr_edge, b.wr_edge) &&
+         same_bytes(a.rr_edge, b.rr_edge) && same_bytes(a.ww_a, b.ww_a) &&
+         same_bytes(a.ww_b, b.ww_b) && same_bytes(a.ww_e, b.ww_e) && same_bytes(a.vr, b.vr) &&
+         same_bytes(a.wv, b.wv) && same_bytes(a.hidden, b.hidden) &&
+         same_bytes(a.hw_off, b.hw_off) && same_bytes(a.fld_wr, b.fld_wr) &&
+         same_bytes(a.cinst, b.cinst) && same_bytes(a.chains, b.chains) &&
+         same_bytes(a.csteps, b.csteps) && same_bytes(a.xcol, b.xcol) &&
+         same_bytes(a.Tdq, b.Tdq) && same_bytes(a.col_out, b.col_out) &&
+         same_bytes(a.cf_w, b.cf_w) && same_bytes(a.cf_r, b.cf_r) &&
+         a.T.size() == b.T.size() && a.esmall.size() == b.esmall.size() &&
+         a.fld_J.size() == b.fld_J.size() && a.hR.size() == b.hR.size() &&
+         a.wr_J.size() == b.wr_J.size() && a.rr_J.size() == b.rr_J.size() &&
+         a.ww_J.size() == b.ww_J.size() && a.hW.size() == b.hW.size() &&
+         a.Tp.size() == b.Tp.size() && a.Tt.size() == b.Tt.size() && a.Tb.size() == b.Tb.size() &&
+         a.Tl.size() == b.Tl.size() && a.Tbl.size() == b.Tbl.size() &&
+         a.cedges.size() == b.cedges.size() && a.Tr.size() == b.Tr.size() &&
+         a.Tq.size() == b.Tq.size() && a.Trb.size() == b.Trb.size() &&
+         a.Tsx.size() == b.Tsx.size() && a.Ts3.size() == b.Ts3.size() &&
+         a.pcoef_out.size() == b.pcoef_out.size() && a.cf_J.size() == b.cf_J.size() &&
+         a.flops_fwd == b.flops_fwd;
+}
+
+tnvan_instance src_view(const tnvan_net::SrcInst &c) {
+  tnvan_instance v{};
+  v.n_spins = c.n_spins;
+  v.n_edges = c.n_edges;
+  v.edge_i = c.ei.data();
+  v.edge_j = c.ej.data();
+  v.J = c.J.data();
+  v.h = c.h.data();
+  v.beta = c.beta;
+  v.n_width = (int32_t)c.W.size();
+  v.width_set = c.W.data();
+  v.n_order = (int32_t)c.order.size();
+  v.order = c.order.data();
+  v.n_groups = c.gp.empty() ? 0 : (int32_t)c.gp.size() - 1;
+  v.group_ptr = c.gp.empty() ? nullptr : c.gp.data();
+  v.hidden = c.hidden;
+  return v;
 }
 
 tnvan_status set_batch(tnvan_net *net, const int64_t *n_samples) {
@@ -1066,10 +1177,12 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
   return TNVAN_OK;
 }
 
-// moments of p from samples of q (tnvan_observables)
+// logZ, f_b (Eq. 9; the step counter is not advanced) and the
+// self-normalised importance weights of the batch: w_og = w_b / beta, ess
+// per instance.  *o is left set up for obs_w_kernel.
 template <typename real>
-tnvan_status run_observables(tnvan_net *net, const int8_t *spins, const void *logq, double *mag,
-                             double *corr, double *ess, hipStream_t st) {
+tnvan_status obs_weights(tnvan_net *net, const int8_t *spins, const void *logq, double *ess,
+                         ObsArgs *o, hipStream_t st) {
   const int64_t B = net->B_total;
   HIPCHK(net->w_logz.ensure(std::max<int64_t>(1, B) * 8));
   HIPCHK(net->w_f.ensure(std::max<int64_t>(1, B) * 8));
@@ -1100,24 +1213,33 @@ tnvan_status run_observables(tnvan_net *net, const int8_t *spins, const void *lo
   f.done = net->tickets.as<int32_t>();
   f.step_ctr = nullptr;
   HIPCHK(launch_free<real>(f, net->n_inst, st));
+  *o = ObsArgs{};
+  o->inst = net->inst.as<InstDesc>();
+  o->mi = net->d_mi.as<MadeInst>();
+  o->f = net->w_f.as<double>();
+  o->g = net->w_og.as<double>();
+  o->ess = ess;
+  o->spins = spins;
+  o->ww_a = net->ww_a.as<int32_t>();
+  o->ww_b = net->ww_b.as<int32_t>();
+  o->ww_e = net->ww_e.as<int32_t>();
+  o->wv = net->d_wv.as<int32_t>();
+  o->hw_off = net->d_hw_off.as<int32_t>();
+  o->spin_base = net->d_spin_base.as<int64_t>();
+  o->edge_base = net->d_edge_base.as<int64_t>();
+  for (auto &D : net->P.insts) o->max_out = std::max(o->max_out, (int32_t)(D.nw + D.n_ww));
+  HIPCHK(launch_obs_weights(*o, net->n_inst, st));
+  return TNVAN_OK;
+}
+
+// moments of p from samples of q (tnvan_observables)
+template <typename real>
+tnvan_status run_observables(tnvan_net *net, const int8_t *spins, const void *logq, double *mag,
+                             double *corr, double *ess, hipStream_t st) {
   ObsArgs o{};
-  o.inst = net->inst.as<InstDesc>();
-  o.mi = net->d_mi.as<MadeInst>();
-  o.f = net->w_f.as<double>();
-  o.g = net->w_og.as<double>();
-  o.ess = ess;
-  o.spins = spins;
-  o.ww_a = net->ww_a.as<int32_t>();
-  o.ww_b = net->ww_b.as<int32_t>();
-  o.ww_e = net->ww_e.as<int32_t>();
-  o.wv = net->d_wv.as<int32_t>();
-  o.hw_off = net->d_hw_off.as<int32_t>();
-  o.spin_base = net->d_spin_base.as<int64_t>();
-  o.edge_base = net->d_edge_base.as<int64_t>();
+  if (tnvan_status s = obs_weights<real>(net, spins, logq, ess, &o, st)) return s;
   o.mag = mag;
   o.corr = corr;
-  for (auto &D : net->P.insts) o.max_out = std::max(o.max_out, (int32_t)(D.nw + D.n_ww));
-  HIPCHK(launch_obs_weights(o, net->n_inst, st));
   // the remainder's moments: the adjoint with g_b = w_b / beta (dh = sum
   // w_b <r>, dJ = sum w_b <x x>; zero on W vertices and W-W edges) ...
   if (tnvan_status s = run_backward<real>(net, spins, net->w_og.as<double>(), mag, corr,
@@ -1127,6 +1249,90 @@ tnvan_status run_observables(tnvan_net *net, const int8_t *spins, const void *lo
   HIPCHK(launch_obs_w(o, net->n_inst, st));
   return TNVAN_OK;
 }
+// the conditional mean and variance of M_R per sample (tnvan_remainder_moments)
+template <typename real>
+tnvan_status run_moments(tnvan_net *net, const int8_t *spins, double *logz, double *mean,
+                         double *var, hipStream_t st) {
+  for (int q = 0; q < net->n_inst; ++q)
+    if (net->P.insts[q].max_w > kTabW)
+      return set_err(TNVAN_E_WIDTH, "instance %d: magnetisation moments need message scopes <= %d",
+                     q, kTabW);
+  // (every step of such programs has its transfer table)
+  for (const StepDesc &sd : net->P.steps)
+    if (sd.t_off < 0) return set_err(TNVAN_E_WIDTH, "magnetisation moments need every step's table");
+  if (net->mkey != net->nkey) {
+    std::vector<int64_t> jo(net->n_inst), eo(net->n_inst);
+    int64_t jt = 0, et = 0;
+    for (int q = 0; q < net->n_inst; ++q) {
+      const InstDesc &D = net->P.insts[q];
+      jo[q] = jt;
+      eo[q] = et;
+      jt += ((int64_t)D.arena_fwd + D.scr_fwd) * 3 * net->nkey[q];
+      et += (int64_t)D.n_steps * net->nkey[q];
+    }
+    if (tnvan_status s = quiesce(net)) return s;
+    HIPCHK(upload(net->d_jar_off, jo));
+    HIPCHK(upload(net->d_jexp_off, eo));
+    HIPCHK(net->w_jar.ensure((size_t)std::max<int64_t>(1, jt) * sizeof(real)));
+    HIPCHK(net->w_jexp.ensure((size_t)std::max<int64_t>(1, et) * sizeof(int32_t)));
+    net->mkey = net->nkey;
+  }
+  MomentArgs<real> a{};
+  a.inst = net->inst.as<InstDesc>();
+  a.steps = net->steps.as<StepDesc>();
+  a.inputs = net->inputs.as<InputDesc>();
+  a.gtab = net->gtab.as<uint16_t>();
+  a.T = net->T.as<real>();
+  a.fld_ptr = net->fld_ptr.as<int32_t>();
+  a.fld_w = net->fld_w.as<int32_t>();
+  a.fld_J = net->fld_J.as<real>();
+  a.hR = net->hR.as<real>();
+  a.inst_sample_off = net->d_sample_off.as<int64_t>();
+  a.inst_B = net->d_B.as<int64_t>();
+  a.inst_spin_off = net->d_spin_off.as<int64_t>();
+  a.spins = spins;
+  a.jarena = net->w_jar.as<real>();
+  a.jexp = net->w_jexp.as<int32_t>();
+  a.jar_off = net->d_jar_off.as<int64_t>();
+  a.jexp_off = net->d_jexp_off.as<int64_t>();
+  a.logz = logz;
+  a.mean = mean;
+  a.var = var;
+  int64_t maxB = 0;
+  for (auto b : net->nkey) maxB = std::max(maxB, b);
+  HIPCHK(launch_moments<real>(a, net->n_inst, maxB, st));
+  return TNVAN_OK;
+}
+
+// importance-weighted magnetisation moments and susceptibility of p
+// (tnvan_susceptibility)
+template <typename real>
+tnvan_status run_susceptibility(tnvan_net *net, const int8_t *spins, const void *logq,
+                                double *out, hipStream_t st) {
+  const int64_t B = std::max<int64_t>(1, net->B_total);
+  HIPCHK(net->w_oess.ensure((size_t)net->n_inst * sizeof(double)));
+  HIPCHK(net->w_mmean.ensure((size_t)B * sizeof(double)));
+  HIPCHK(net->w_mvar.ensure((size_t)B * sizeof(double)));
+  ObsArgs o{};
+  if (tnvan_status s = obs_weights<real>(net, spins, logq, net->w_oess.as<double>(), &o, st)) return s;
+  if (tnvan_status s = run_moments<real>(net, spins, nullptr, net->w_mmean.as<double>(),
+                                         net->w_mvar.as<double>(), st))
+    return s;
+  SusArgs a{};
+  a.inst = net->inst.as<InstDesc>();
+  a.inst_sample_off = net->d_sample_off.as<int64_t>();
+  a.inst_B = net->d_B.as<int64_t>();
+  a.inst_spin_off = net->d_spin_off.as<int64_t>();
+  a.spins = spins;
+  a.g = net->w_og.as<double>();
+  a.ess = net->w_oess.as<double>();
+  a.mean = net->w_mmean.as<double>();
+  a.var = net->w_mvar.as<double>();
+  a.out = out;
+  HIPCHK(launch_sus_reduce(a, net->n_inst, st));
+  return TNVAN_OK;
+}
+
 // a pointer the GPU can access (device or managed memory, or pinned host
 // memory mapped for the device); plain host memory is rejected
 bool is_device_ptr(const void *p) {
@@ -1202,6 +1408,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
     net->rk_build = k > 1 ? k : 1;
   }
   net->n_inst = n_inst;
+  net->max_width = opt->max_width;
   for (int q = 0; q < n_inst; ++q) {
     std::string msg;
     tnvan_status s = compile_instance(inst[q], opt->max_width, net->P, msg);
@@ -1209,6 +1416,22 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
       delete net;
       return set_err(s, "instance %d: %s", q, msg.c_str());
     }
+    // the arrays were validated by the compiler
+    const tnvan_instance &in = inst[q];
+    tnvan_net::SrcInst c;
+    c.n_spins = in.n_spins;
+    c.n_edges = in.n_edges;
+    c.hidden = in.hidden;
+    c.beta = in.beta;
+    c.ei.assign(in.edge_i, in.edge_i + in.n_edges);
+    c.ej.assign(in.edge_j, in.edge_j + in.n_edges);
+    c.J.assign(in.J, in.J + in.n_edges);
+    c.h.assign(in.n_spins, 0.0);
+    if (in.h) c.h.assign(in.h, in.h + in.n_spins);
+    c.W.assign(in.width_set, in.width_set + in.n_width);
+    c.order.assign(in.order, in.order + in.n_order);
+    if (in.n_groups > 0 && in.group_ptr) c.gp.assign(in.group_ptr, in.group_ptr + in.n_groups + 1);
+    net->src.push_back(std::move(c));
     const InstDesc &D = net->P.insts[q];
     if (D.nw > 2048) { delete net; return set_err(TNVAN_E_INVALID, "instance %d: |W| above 2048", q); }
   }
@@ -1293,19 +1516,9 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   hipError_t e;
   HostProgram &P = net->P;
 #define UP(buf, vec) if ((e = upload(net->buf, vec)) != hipSuccess) return fail(e, #buf);
-#define UP2(buf, vec) if ((e = upload(net->buf, vec)) != hipSuccess) return fail(e, #buf);
-  UP(inst, P.insts) UP(steps, P.steps) UP(inputs, P.inputs) UP(gtab, P.gtab) UP(gtab2, P.gtab2)
-  UP(edges, P.edges)
-  UP(fld_ptr, P.fld_ptr) UP(fld_w, P.fld_w) UP(wr_pos, P.wr_pos) UP(wr_w, P.wr_w)
-  UP(rr_edge, P.rr_edge) UP(rr_J, P.rr_J) UP(wr_edge, P.wr_edge) UP(wr_J, P.wr_J)
-  UP(hR64, P.hR) UP(vr, P.vr) UP(ww_a, P.ww_a) UP(ww_b, P.ww_b) UP(ww_J, P.ww_J)
-  UP(hW, P.hW) UP(d_hw_off, P.hw_off) UP(ww_e, P.ww_e) UP(d_wv, P.wv)
-  if (net->precision == TNVAN_FP64) {
-    UP(T, P.T) UP(fld_J, P.fld_J) UP(hR, P.hR) UP(esmall, P.esmall)
-  } else {
-    std::vector<float> t(P.T.begin(), P.T.end()), fj(P.fld_J.begin(), P.fld_J.end()),
-        hr(P.hR.begin(), P.hR.end()), es(P.esmall.begin(), P.esmall.end());
-    UP(T, t) UP(fld_J, fj) UP(hR, hr) UP(esmall, es)
+  {
+    const char *what = "";
+    if ((e = upload_tables(net, &what)) != hipSuccess) return fail(e, what);
   }
   {
     std::vector<int64_t> sb(n_inst), eb(n_inst);
@@ -1345,14 +1558,6 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   // [6,7] chain adjoint
   if ((e = net->pq.ensure(sizeof(int32_t) * 8)) || (e = hipMemset(net->pq.p, 0, sizeof(int32_t) * 8)))
     return fail(e, "work-queue counters");
-  {
-    std::vector<float> fj(P.fld_J.begin(), P.fld_J.end()), hr(P.hR.begin(), P.hR.end());
-    UP2(fld_J32, fj) UP2(hR32, hr) UP2(fld_wr, P.fld_wr) UP2(cinst, P.cinst)
-    UP2(chains, P.chains) UP2(csteps, P.csteps) UP2(Tp, P.Tp) UP2(Tt, P.Tt) UP2(Tb, P.Tb)
-  }
-  UP2(Tl, P.Tl) UP2(Tbl, P.Tbl) UP2(cedges, P.cedges)
-  UP2(Tr, P.Tr) UP2(Tq, P.Tq) UP2(Trb, P.Trb) UP2(xcol, P.xcol)
-  UP2(col_out, P.col_out) UP2(pcoef_out, P.pcoef_out)
   // the adjoint's split column sums, in output order: the outputs without a
   // column are never written and keep these zeros
   for (auto &D : P.insts) net->max_out = std::max(net->max_out, (int)(D.n + D.n_edges));
@@ -1360,7 +1565,6 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
     const size_t vb = sizeof(double) * std::max(1, n_inst * vjp_split() * net->max_out);
     if ((e = net->vjp_part.ensure(vb)) || (e = hipMemset(net->vjp_part.p, 0, vb))) return fail(e, "adjoint sums");
   }
-  UP2(cf_w, P.cf_w) UP2(cf_r, P.cf_r) UP2(cf_J, P.cf_J) UP2(Tsx, P.Tsx) UP2(Ts3, P.Ts3) UP2(Tdq, P.Tdq)
   // transfer-matrix form: instances whose program is a set of dense chains
   // (FP32 / BF16 only); the launch-wide maxima size the LDS layout
   net->use_chain.assign(n_inst, 0);
@@ -1428,7 +1632,6 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   choose_tiles(net, false);
   choose_tiles(net, true);
 #undef UP
-#undef UP2
   // the allocation-free entry point's scratch address on this device
   (void)hipGetDevice(&net->device);
   scratch_setup(net->device);
@@ -1465,6 +1668,8 @@ void tnvan_free_network(tnvan_net *net) {
                  &net->cf_w, &net->cf_r, &net->cf_J, &net->Tsx, &net->Ts3, &net->Tdq, &net->Ubuf, &net->vjp_part,
                  &net->tickets, &net->nonfinite, &net->pq, &net->col_out, &net->pcoef_out, &net->w_xspins, &net->w_xlogz, &net->w_xpart, &net->ww_e, &net->d_wv, &net->w_og,
                  &net->w_ostats, &net->w_odb, &net->fabp, &net->u_off,
+                 &net->w_jar, &net->w_jexp, &net->d_jar_off, &net->d_jexp_off, &net->w_mmean,
+                 &net->w_mvar, &net->w_oess,
                  &net->f_off,
                  &net->mpack, &net->mtask_inst, &net->mtask_start, &net->mg_task_inst,
                  &net->mg_task_start, &net->mg_first, &net->mg_count,
@@ -1510,6 +1715,52 @@ tnvan_status tnvan_get_params(tnvan_net *net, int32_t inst, float *dst, void *st
   HIPCHK(hipMemcpyAsync(dst, net->params.as<float>() + net->mi[inst].param_off,
                         net->param_count[inst] * sizeof(float), hipMemcpyDeviceToDevice,
                         static_cast<hipStream_t>(stream)));
+  return TNVAN_OK;
+}
+
+tnvan_status tnvan_set_couplings(tnvan_net *net, int32_t inst, const double *J, const double *h,
+                                 double beta) {
+  if (tnvan_status s = check_net(net)) return s;
+  if (inst < 0 || inst >= net->n_inst) return set_err(TNVAN_E_INVALID, "bad instance index");
+  if (net->capturing) return set_err(TNVAN_E_STATE, "set_couplings while a graph is recorded");
+  tnvan_net::SrcInst c = net->src[inst];
+  if (c.n_edges > 0 && !J) return set_err(TNVAN_E_INVALID, "J is NULL");
+  if (c.n_edges > 0) c.J.assign(J, J + c.n_edges);
+  c.h.assign(c.n_spins, 0.0);
+  if (h) c.h.assign(h, h + c.n_spins);
+  c.beta = beta;
+  // compile every instance again (the program's offsets run over all of
+  // them); the compiler validates the new values
+  HostProgram P2;
+  for (int q = 0; q < net->n_inst; ++q) {
+    std::string msg;
+    const tnvan_instance v = src_view(q == inst ? c : net->src[q]);
+    tnvan_status s = compile_instance(v, net->max_width, P2, msg);
+    if (s != TNVAN_OK) return set_err(s, "instance %d: %s", q, msg.c_str());
+  }
+  if (!same_structure(net->P, P2))
+    return set_err(TNVAN_E_STATE, "instance %d: the new values change the program's structure", inst);
+  // kernels queued earlier may still read the tables
+  if (tnvan_status s = quiesce(net)) return s;
+  HIPCHK(hipDeviceSynchronize());
+  std::swap(net->P, P2);
+  const char *what = "";
+  const hipError_t e = upload_tables(net, &what);
+  if (e != hipSuccess) {
+    // the device tables are now partly new: put the old program back
+    // (same sizes, so nothing is reallocated)
+    std::swap(net->P, P2);
+    const char *w2 = "";
+    (void)upload_tables(net, &w2);
+    net->nkey.clear();
+    return set_err(e == hipErrorOutOfMemory ? TNVAN_E_NOMEM : TNVAN_E_HIP, "%s: %s", what,
+                   hipGetErrorString(e));
+  }
+  net->src[inst] = std::move(c);
+  // the next call lays its per-call tables out again, which also refills
+  // the unary-factor table (positions without a field or a W-neighbour keep
+  // the +1 of that fill and are skipped by the unary kernel)
+  net->nkey.clear();
   return TNVAN_OK;
 }
 
@@ -1579,16 +1830,33 @@ tnvan_status tnvan_sample(tnvan_net *net, const int64_t *n_samples, const float 
 }
 
 tnvan_status tnvan_logz_batch(tnvan_net *net, const int64_t *n_samples, const int8_t *spins,
-                              double *logz, void *stream) {
+                              double *logz, double *e1, void *stream) {
   if (tnvan_status s = check_net(net)) return s;
   note_stream(net, stream);
   if (tnvan_status s = set_batch(net, n_samples)) return s;
   if (net->B_total == 0) return TNVAN_OK;
   if (!logz || (!spins && net->spin_total > 0)) return set_err(TNVAN_E_INVALID, "spins and logz are required");
   if (tnvan_status s = check_device({spins, logz})) return s;
+  if (e1)
+    if (tnvan_status s = check_device({e1})) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (net->precision == TNVAN_FP64) return run_logz<double>(net, spins, logz, st);
-  return run_logz<float>(net, spins, logz, st);
+  tnvan_status s = net->precision == TNVAN_FP64 ? run_logz<double>(net, spins, logz, st)
+                                                : run_logz<float>(net, spins, logz, st);
+  if (s != TNVAN_OK || !e1) return s;
+  E1Args a{};
+  a.inst = net->inst.as<InstDesc>();
+  a.mi = net->d_mi.as<MadeInst>();
+  a.hw_off = net->d_hw_off.as<int32_t>();
+  a.spins = spins;
+  a.ww_a = net->ww_a.as<int32_t>();
+  a.ww_b = net->ww_b.as<int32_t>();
+  a.ww_J = net->ww_J.as<double>();
+  a.hW = net->hW.as<double>();
+  a.e1 = e1;
+  int64_t maxB = 0;
+  for (auto b : net->nkey) maxB = std::max(maxB, b);
+  HIPCHK(launch_e1(a, net->n_inst, maxB, st));
+  return TNVAN_OK;
 }
 
 namespace {
@@ -1655,6 +1923,39 @@ tnvan_status tnvan_observables(tnvan_net *net, const int64_t *n_samples, const i
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (net->precision == TNVAN_FP64) return run_observables<double>(net, spins, logq, mag, corr, ess, st);
   return run_observables<float>(net, spins, logq, mag, corr, ess, st);
+}
+
+tnvan_status tnvan_remainder_moments(tnvan_net *net, const int64_t *n_samples,
+                                     const int8_t *spins, double *logz, double *mean, double *var,
+                                     void *stream) {
+  if (tnvan_status s = check_net(net)) return s;
+  note_stream(net, stream);
+  if (tnvan_status s = set_batch(net, n_samples)) return s;
+  if (net->B_total == 0) return TNVAN_OK;
+  if (!mean || !var || (!spins && net->spin_total > 0))
+    return set_err(TNVAN_E_INVALID, "spins, mean and var are required");
+  if (tnvan_status s = check_device({spins, mean, var})) return s;
+  if (logz)
+    if (tnvan_status s = check_device({logz})) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (net->precision == TNVAN_FP64) return run_moments<double>(net, spins, logz, mean, var, st);
+  return run_moments<float>(net, spins, logz, mean, var, st);
+}
+
+tnvan_status tnvan_susceptibility(tnvan_net *net, const int64_t *n_samples, const int8_t *spins,
+                                  const void *logq, double *out, void *stream) {
+  if (tnvan_status s = check_net(net)) return s;
+  for (const InstDesc &D : net->P.insts)
+    if (!(D.beta > 0)) return set_err(TNVAN_E_INVALID, "the susceptibility needs beta > 0");
+  if (tnvan_status s = check_device({spins, logq, out})) return s;
+  note_stream(net, stream);
+  if (tnvan_status s = set_batch(net, n_samples)) return s;
+  if (!out) return set_err(TNVAN_E_INVALID, "out is required");
+  if (net->B_total > 0 && (!logq || (!spins && net->spin_total > 0)))
+    return set_err(TNVAN_E_INVALID, "spins and logq are required");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (net->precision == TNVAN_FP64) return run_susceptibility<double>(net, spins, logq, out, st);
+  return run_susceptibility<float>(net, spins, logq, out, st);
 }
 
 tnvan_status tnvan_logz_backward(tnvan_net *net, const int64_t *n_samples, const int8_t *spins,

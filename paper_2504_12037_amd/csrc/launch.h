@@ -250,6 +250,59 @@ struct FreeArgs {
 template <typename real>
 hipError_t launch_free(const FreeArgs<real> &a, int n_inst, hipStream_t st);
 
+// E_1(s_W) per sample (Eq. 4: the couplings and fields inside the width set)
+// in FP64, every instance in one launch (grid.y = instance); the W-W terms in
+// edge order, then the fields in width-set order.
+struct E1Args {
+  const InstDesc *inst;
+  const MadeInst *mi;          // per-call B, sample_off and spin_off
+  const int32_t *hw_off;
+  const int8_t *spins;
+  const int32_t *ww_a, *ww_b;
+  const double *ww_J;
+  const double *hW;
+  double *e1;                  // out [sum B]
+};
+hipError_t launch_e1(const E1Args &a, int n_inst, int64_t max_B, hipStream_t st);
+
+// Conditional mean and variance of the remainder's magnetisation given s_W
+// (moments.hip): a second-order Taylor (jet) contraction of every
+// instance's general step program in a uniform field on R, one thread per
+// sample.  Programs with wide steps are not supported.
+template <typename real>
+struct MomentArgs {
+  const InstDesc *inst;
+  const StepDesc *steps;
+  const InputDesc *inputs;
+  const uint16_t *gtab;
+  const real *T;
+  const int32_t *fld_ptr, *fld_w;
+  const real *fld_J;
+  const real *hR;
+  const int64_t *inst_sample_off, *inst_B, *inst_spin_off;
+  const int8_t *spins;
+  real *jarena;               // per instance (arena_fwd + scr_fwd) * 3 * B jets
+  int32_t *jexp;              // per instance n_steps * B step exponents
+  const int64_t *jar_off, *jexp_off;
+  double *logz;               // out [sum B] or null
+  double *mean, *var;         // out [sum B]
+};
+template <typename real>
+hipError_t launch_moments(const MomentArgs<real> &a, int n_inst, int64_t max_B, hipStream_t st);
+
+// Importance-weighted magnetisation moments of p per instance (moments.hip):
+// out[q] = (<M>/N, <M^2>/N^2, beta N (<M^2>/N^2 - (<M>/N)^2), ess)
+struct SusArgs {
+  const InstDesc *inst;
+  const int64_t *inst_sample_off, *inst_B, *inst_spin_off;
+  const int8_t *spins;
+  const double *g;            // w_b / beta (obs_weights_kernel)
+  const double *ess;          // [n_inst]
+  const double *mean, *var;   // conditional moments of M_R per sample
+  double *out;                // [n_inst][4]
+};
+hipError_t launch_sus_reduce(const SusArgs &a, int n_inst, hipStream_t st);
+
 // Exact slicing over every configuration of one instance's width set
 // (slice_*_kernel): the configurations of one pass as spins, the per-block
 // log-sum-exp pairs of -beta E_1 + logZ_R, and their fixed-order merge.

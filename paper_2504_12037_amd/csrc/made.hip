@@ -745,6 +745,25 @@ __global__ __launch_bounds__(256) void free_f_kernel(FreeArgs<real> a) {
   free_stats(sm, mi.B, a.stats + 4 * q);
 }
 
+// E_1(s_W) = -sum_{W-W edges} J s_i s_j - sum_{i in W} h_i s_i (Eq. 4) of
+// every sample, one thread per sample (the couplings are read by every
+// thread of a block at the same index: one cache line per term)
+__global__ __launch_bounds__(256) void e1_kernel(E1Args a) {
+  const int q = blockIdx.y;
+  const MadeInst mi = a.mi[q];
+  const InstDesc D = a.inst[q];
+  const int32_t *wa = a.ww_a + D.ww_off, *wb = a.ww_b + D.ww_off;
+  const double *wJ = a.ww_J + D.ww_off, *hW = a.hW + a.hw_off[q];
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < mi.B;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    const int8_t *s = a.spins + mi.spin_off + b * mi.n;
+    double e1 = 0.0;
+    for (int k = 0; k < D.n_ww; ++k) e1 -= wJ[k] * (double)(s[wa[k]] * s[wb[k]]);
+    for (int k = 0; k < mi.n; ++k) e1 -= hW[k] * (double)s[k];
+    a.e1[mi.sample_off + b] = e1;
+  }
+}
+
 // Adam (Kingma & Ba; beta1 = 0.9, beta2 = 0.999, eps = 1e-8) on one
 // parameter, with the bias corrections c1 = 1 - 0.9^t, c2 = 1 - 0.999^t of
 // step t taken in FP64.  Masked parameters have zero gradient, so they and
@@ -2254,6 +2273,13 @@ template <typename real>
 hipError_t launch_free(const FreeArgs<real> &a, int n_inst, hipStream_t st) {
   if (n_inst <= 0) return hipSuccess;
   hipLaunchKernelGGL(free_f_kernel<real>, dim3(a.nblk, n_inst), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_e1(const E1Args &a, int n_inst, int64_t max_B, hipStream_t st) {
+  if (n_inst <= 0 || max_B <= 0) return hipSuccess;
+  const int bx = (int)std::min<int64_t>(65535, (max_B + 255) / 256);
+  hipLaunchKernelGGL(e1_kernel, dim3(bx, n_inst), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

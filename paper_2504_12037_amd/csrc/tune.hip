@@ -173,7 +173,7 @@ extern "C" tnvan_status tnvan_autotune(tnvan_net *net, const int64_t *n_samples,
   auto timed = [&](bool bwd, double &ms) -> tnvan_status {
     auto call = [&]() {
       return bwd ? tnvan_logz_backward(net, counts.data(), spins, grad_logz, dh, dJ, dbeta, stream)
-                 : tnvan_logz_batch(net, counts.data(), spins, logz, stream);
+                 : tnvan_logz_batch(net, counts.data(), spins, logz, nullptr, stream);
     };
     if (tnvan_status s = call()) return s;
     const int reps = 5;

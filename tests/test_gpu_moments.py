@@ -1,0 +1,151 @@
+"""Magnetisation moments of the remainder given s_W (second-order Taylor
+contraction in a uniform field on R) and the susceptibility of p from
+samples of q, through the C ABI, against the oracle (brute force for
+|R| <= 16, the count-resolved elimination beyond) and against full
+enumeration of the whole system.
+
+Error model of the per-sample moments: the jets carry the raw moments, so
+the variance is 2 z2 / z0 - (z1 / z0)^2, both terms of the size of the raw
+second moment s2 = Var + mean^2 of M_R.  Each coefficient has a relative
+rounding error of about (steps) x eps, so the bounds are taken relative to
+s2: FP64 1e-12 s2, FP32 1e-5 s2 for the variance and the same times
+sqrt(s2) for the mean (about eps x 100 steps in FP32; measured at most
+2e-14 and 1.2e-6)."""
+
+import numpy as np
+import pytest
+
+import synthetic as S
+from oracle import ising as OI
+from oracle import made as OM
+from oracle import magnetisation as MG
+from oracle import philox as OP
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+REL = {"fp64": 1e-12, "fp32": 1e-5, "bf16": 1e-5}
+TOL_LZ = {"fp64": 1e-10, "fp32": 1e-5, "bf16": 1e-5}
+
+
+def _net(insts, prec, **kw):
+    from paper_2504_12037_amd import Net
+    return Net(insts, precision=prec, **kw)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda().reshape(-1)
+
+
+def _oracle(inst, s):
+    if len(inst.order) <= 16:
+        return MG.remainder_magnetisation_bruteforce(inst, s), OI.logz_r_bruteforce(inst, s)
+    return MG.remainder_magnetisation(inst, s), OI.logz_r_elimination(inst, s)
+
+
+CASES = {
+    "c1": lambda: S.c1_small_lattice(),
+    "lat8_field": lambda: S.lattice_column_split(
+        S.lattice_2d(8, seed=9, beta=0.7, h_var=0.2), [5]),
+    "lat8_b2": lambda: S.lattice_column_split(S.lattice_2d(8, seed=3, beta=2.0), [4]),
+    "lat6_ferro": lambda: S.lattice_column_split(
+        S.lattice_2d(6, seed=1, beta=0.6, ferro=True), [3]),
+    "sk64": lambda: S.c3_sk(1.0),
+    "rrg20": lambda: S.c4_small_copies()[0],
+    "rrg48": lambda: S.random_regular(48, 3, seed=77, beta=1.2, h_var=0.1, width_limit=6),
+}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_remainder_moments_against_the_oracle(prec):
+    # every case in one net (uneven batches, chain and general programs,
+    # dense and single-spin steps), one call
+    names = list(CASES)
+    insts = [CASES[k]() for k in names]
+    Bs = [64, 48, 40, 33, 24, 64, 17]
+    spins = [S.uniform_spins(b, i.n_width, 300 + k) for k, (b, i) in enumerate(zip(Bs, insts))]
+    print(f"\n[moments] prec={prec}", flush=True)
+    net = _net(insts, prec)
+    lz, mean, var = net.remainder_moments(_dev(np.concatenate([s.reshape(-1) for s in spins])),
+                                          Bs)
+    torch.cuda.synchronize()
+    lz, mean, var = lz.cpu().numpy(), mean.cpu().numpy(), var.cpu().numpy()
+    off = 0
+    for name, inst, b, s in zip(names, insts, Bs, spins):
+        (m_o, v_o), lz_o = _oracle(inst, s)
+        s2 = v_o + m_o * m_o + 1.0
+        em = np.abs(mean[off:off + b] - m_o) / np.sqrt(s2)
+        ev = np.abs(var[off:off + b] - v_o) / s2
+        el = np.abs(lz[off:off + b] - lz_o).max() / inst.n
+        print(f"  {name}: |R|={len(inst.order)} mean err {em.max():.2e} var err {ev.max():.2e} "
+              f"logz err/N {el:.2e}", flush=True)
+        assert em.max() <= REL[prec], name
+        assert ev.max() <= REL[prec], name
+        assert el <= TOL_LZ[prec], name
+        assert np.all(var[off:off + b] >= -REL[prec] * s2)
+        off += b
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_susceptibility_exact_under_full_enumeration(prec):
+    # every width-set configuration once with a uniform q: the estimate is
+    # the exact magnetisation moments of p (enumeration of all 2^N states)
+    insts = [S.c1_small_lattice(),
+             S.lattice_column_split(S.lattice_2d(4, seed=1, beta=0.44, ferro=True), [2]),
+             S.c4_small_copies()[3]]
+    sws, Bs = [], []
+    for inst in insts:
+        nw = inst.n_width
+        x = np.arange(1 << nw)[:, None]
+        sws.append((1 - 2 * ((x >> np.arange(nw)[None, :]) & 1)).astype(np.int8))
+        Bs.append(1 << nw)
+    print(f"\n[susceptibility] full enumeration prec={prec}", flush=True)
+    net = _net(insts, prec)
+    logq = torch.cat([torch.full((b,), -np.log(b)) for b in Bs])
+    out = net.susceptibility(_dev(np.concatenate([s.reshape(-1) for s in sws])), logq, Bs)
+    out = out.cpu().numpy()
+    for k, inst in enumerate(insts):
+        n = inst.n
+        y = np.arange(1 << n)[:, None]
+        full = (1 - 2 * ((y >> np.arange(n)[None, :]) & 1)).astype(np.float64)
+        e = OI.energy(inst, full)
+        p = np.exp(-inst.beta * (e - e.min()))
+        p /= p.sum()
+        M = full.sum(1)
+        m1, m2 = p @ M, p @ (M * M)
+        want = [m1 / n, m2 / n ** 2, inst.beta * (m2 - m1 * m1) / n]
+        tol = 1e-9 if prec == "fp64" else 2e-4
+        print(f"  {inst.name}: m {out[k, 0]:.6f} m2 {out[k, 1]:.6f} chi {out[k, 2]:.6f} "
+              f"(exact {want[2]:.6f})", flush=True)
+        np.testing.assert_allclose(out[k, :3], want, atol=tol * max(1.0, abs(want[2])))
+        assert 1.0 <= out[k, 3] <= Bs[k] + 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_susceptibility_matches_the_oracle_estimator(prec):
+    # oracle-drawn MADE samples on two instances, one of them empty in a
+    # second call (its row is zero)
+    insts = [S.lattice_column_split(S.lattice_2d(8, seed=14, h_var=0.1), [5], hidden=16),
+             S.c4_small_copies()[2]]
+    Bs = [300, 200]
+    spins, logqs = [], []
+    for k, inst in enumerate(insts):
+        n, H = inst.n_width, inst.hidden
+        th = S.made_init(n, H, 40 + k).astype(np.float64)
+        u = OP.sampler_uniforms(5, 0, k, Bs[k], n)
+        s, lq, _ = OM.sample(th, u, n, H)
+        spins.append(s.astype(np.int8))
+        logqs.append(lq)
+    print(f"\n[susceptibility] oracle samples prec={prec}", flush=True)
+    net = _net(insts, prec)
+    out = net.susceptibility(_dev(np.concatenate([s.reshape(-1) for s in spins])),
+                             torch.from_numpy(np.concatenate(logqs)), Bs).cpu().numpy()
+    for k, inst in enumerate(insts):
+        want = MG.susceptibility(inst, spins[k], logqs[k])
+        tol = 1e-9 if prec == "fp64" else 2e-4
+        np.testing.assert_allclose(out[k, :3], want[:3], rtol=tol, atol=tol)
+        assert abs(out[k, 3] - want[3]) <= 1e-3 * want[3]
+    out2 = net.susceptibility(_dev(spins[0].reshape(-1)), torch.from_numpy(logqs[0]),
+                              [Bs[0], 0]).cpu().numpy()
+    np.testing.assert_allclose(out2[0], out[0], rtol=1e-12, atol=0)
+    np.testing.assert_array_equal(out2[1], np.zeros(4))

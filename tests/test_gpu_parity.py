@@ -12,6 +12,7 @@ import pytest
 
 import synthetic as S
 from adjtol import check_vjp
+from synthetic.instances import Instance
 from oracle import ising as OI
 
 torch = pytest.importorskip("torch")
@@ -293,10 +294,126 @@ def test_logz_autograd_function(prec):
         off += b
         hoff += inst.n
         eoff += inst.n_edges
+    # new couplings, fields and inverse temperatures: the instances whose
+    # values changed are compiled again before the forward (tnvan_set_couplings)
+    rng = np.random.default_rng(77)
+    J2 = (J.detach() * 1.01).requires_grad_(True)
+    h2 = (h.detach() + torch.from_numpy(rng.normal(0, 0.1, h.numel())).float()).requires_grad_(True)
+    b2 = torch.tensor([insts[0].beta, 0.45], dtype=torch.float64, requires_grad=True)
+    lz2 = LogZ.apply(J2, h2, b2, flat, net, Bs)
+    dJ2, dh2, db2 = torch.autograd.grad((lz2 * torch.from_numpy(w).cuda()).sum(), [J2, h2, b2])
+    Jn, hn = J2.detach().cpu().numpy(), h2.detach().double().numpy()
+    off = eoff = hoff = 0
+    for k, (inst, b, s) in enumerate(zip(insts, Bs, spins)):
+        new = Instance(inst.n, inst.edges, Jn[eoff:eoff + inst.n_edges].copy(),
+                       hn[hoff:hoff + inst.n].copy(), float(b2[k].detach()), inst.width_set,
+                       inst.order,
+                       inst.group_ptr, inst.hidden)
+        assert np.abs(lz2.detach().cpu().numpy()[off:off + b] - _oracle_logz(new, s)).max() \
+            / inst.n <= TOL[prec]
+        want = OI.logz_r_vjp(new, s, w[off:off + b])
+        got = (dh2.detach().double().numpy()[hoff:hoff + inst.n],
+               dJ2.detach().cpu().numpy()[eoff:eoff + inst.n_edges], db2.detach().numpy()[k])
+        if prec == "fp64":
+            np.testing.assert_allclose(got[0], want[0], rtol=1e-6, atol=1e-6)
+            got = (want[0],) + got[1:]
+        check_vjp(got, want, new, w[off:off + b], prec, k)
+        off += b
+        eoff += inst.n_edges
+        hoff += inst.n
+    # back to the first values (h as passed: rounded to float32), and to
+    # the exact built values through set_couplings: bit for bit the built net
+    lz3 = LogZ.apply(J, h, beta, flat, net, Bs)
+    torch.testing.assert_close(lz3, lz, rtol=1e-6, atol=0)
+    for k, inst in enumerate(insts):
+        net.set_couplings(k, inst.J, inst.h, inst.beta)
+    assert torch.equal(net.logz(flat, Bs), lz)
     with pytest.raises(ValueError):
-        LogZ.apply(J.detach() * 1.01, h, beta, flat, net, Bs)
-    with pytest.raises(ValueError):
-        LogZ.apply(J, h, beta.detach() + 0.1, flat, net, Bs)
+        LogZ.apply(J[:-1], h, beta, flat, net, Bs)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_logz_batch_e1_output(prec):
+    # the optional E_1 output of tnvan_logz_batch (Eq. 4) against the
+    # oracle's, on instances with W-W couplings and fields (C1, an 8x8
+    # lattice with fields, the N = 64 SK model, a random regular graph)
+    insts = [S.c1_small_lattice(),
+             S.lattice_column_split(S.lattice_2d(8, seed=9, beta=0.7, h_var=0.2), [5]),
+             S.c3_sk(1.0), S.c4_small_copies()[0]]
+    Bs = [97, 130, 64, 200]
+    spins = [S.uniform_spins(b, i.n_width, 41 + k) for k, (b, i) in enumerate(zip(Bs, insts))]
+    flat = _dev(np.concatenate([s.reshape(-1) for s in spins]))
+    net = _net(insts, prec)
+    lz, e1 = net.logz(flat, Bs, e1=True)
+    lz0 = net.logz(flat, Bs)
+    assert torch.equal(lz, lz0)
+    e1 = e1.cpu().numpy()
+    off = 0
+    for inst, b, s in zip(insts, Bs, spins):
+        want = OI.e1_energy(inst, s)
+        np.testing.assert_allclose(e1[off:off + b], want, rtol=1e-13,
+                                   atol=1e-13 * (np.abs(inst.J).sum() + np.abs(inst.h).sum()))
+        off += b
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_set_couplings_recompiles_one_instance(prec):
+    # tnvan_set_couplings on one instance of a three-instance net (chain
+    # kernels, and the general kernel with fields): the changed instance
+    # follows the oracle at its new values, the others are unchanged bit for
+    # bit, the network parameters stay; a field set to zero where it was
+    # not (a unary-table position that the kernel then skips) is honoured
+    insts = [S.c2_lattice(1.0, hidden=16),
+             S.lattice_column_split(S.lattice_2d(8, seed=9, beta=0.7, h_var=0.2), [5]),
+             S.c4_small_copies()[1]]
+    Bs = [512, 300, 256]
+    spins = [S.uniform_spins(b, i.n_width, 61 + k) for k, (b, i) in enumerate(zip(Bs, insts))]
+    flat = _dev(np.concatenate([s.reshape(-1) for s in spins]))
+    net = _net(insts, prec)
+    theta = torch.from_numpy(S.made_init(insts[0].n_width, 16, 3))
+    net.set_params(0, theta)
+    before = net.logz(flat, Bs).cpu().numpy()
+    rng = np.random.default_rng(5)
+    changed = set()
+    for k in (1, 2, 0):
+        inst = insts[k]
+        J = rng.standard_normal(inst.n_edges)
+        h = rng.normal(0, 0.3, inst.n)
+        h[::3] = 0.0
+        new = Instance(inst.n, inst.edges, J, h, 0.8, inst.width_set, inst.order,
+                       inst.group_ptr, inst.hidden)
+        net.set_couplings(k, J, h, 0.8)
+        got = net.logz(flat, Bs).cpu().numpy()
+        off = 0
+        for q, (b, s) in enumerate(zip(Bs, spins)):
+            if q == k:
+                assert np.abs(got[off:off + b] - _oracle_logz(new, s)).max() / inst.n <= TOL[prec]
+            elif q not in changed:
+                assert np.array_equal(got[off:off + b], before[off:off + b]), q
+            off += b
+        insts[k] = new
+        changed.add(k)
+    # every instance at its new values, the parameters untouched
+    got = net.logz(flat, Bs).cpu().numpy()
+    off = 0
+    for inst, b, s in zip(insts, Bs, spins):
+        assert np.abs(got[off:off + b] - _oracle_logz(inst, s)).max() / inst.n <= TOL[prec]
+        off += b
+    assert torch.equal(net.get_params(0).cpu(), theta.float())
+    # fields back to zero on the lattice (positions the unary kernel skips)
+    J = insts[1].J
+    net.set_couplings(1, J, None, 0.8)
+    zero = Instance(insts[1].n, insts[1].edges, J, np.zeros(insts[1].n), 0.8,
+                    insts[1].width_set, insts[1].order, insts[1].group_ptr, insts[1].hidden)
+    got = net.logz(flat, Bs).cpu().numpy()
+    assert np.abs(got[512:812] - _oracle_logz(zero, spins[1])).max() / zero.n <= TOL[prec]
+    with pytest.raises(Exception):
+        net.set_couplings(1, np.full(insts[1].n_edges, np.nan), None, 0.8)
+    with pytest.raises(Exception):
+        net.set_couplings(1, J, None, -1.0)
+    # refused values change nothing
+    got2 = net.logz(flat, Bs).cpu().numpy()
+    assert np.array_equal(got, got2)
 
 
 def test_batch_shapes_alternating_on_a_side_stream():
