@@ -9,7 +9,10 @@ the autoregressive masks switch off.  Each implementation applies the masks
 itself, so no mask pattern lives here.  Layout of the flat vector:
 W1 [H, n], b1 [H], W2 [n, H], b2 [n], W0 [n, n] (row-major, float32),
 with weights ~ U(-1/sqrt(fan), 1/sqrt(fan)) where fan is the full input
-count of the layer (n for W1, H + n for W2 and W0) and zero biases.
+count of the layer (n for W1, H + n for W2 and W0) and zero biases.  A
+network of depth D > 1 (and H > 0) continues with D - 1 hidden-to-hidden
+layers (W [H, H] with fan H, b [H] zero), drawn after the others, so the
+first part equals the depth-1 draw of the same seed.
 """
 
 from __future__ import annotations
@@ -27,11 +30,12 @@ def uniforms(B: int, nw: int, seed: int) -> np.ndarray:
     return rng.random((B, nw), dtype=np.float32)
 
 
-def made_param_count(nw: int, H: int) -> int:
-    return H * nw + H + nw * H + nw + nw * nw
+def made_param_count(nw: int, H: int, depth: int = 1) -> int:
+    extra = (depth - 1) * (H * H + H) if H > 0 else 0
+    return H * nw + H + nw * H + nw + nw * nw + extra
 
 
-def made_init(nw: int, H: int, seed: int) -> np.ndarray:
+def made_init(nw: int, H: int, seed: int, depth: int = 1) -> np.ndarray:
     """Flat float32 parameter vector (layout in the module docstring)."""
     rng = np.random.default_rng(seed)
     parts = []
@@ -45,8 +49,12 @@ def made_init(nw: int, H: int, seed: int) -> np.ndarray:
         a2 = 1.0 / np.sqrt(max(nw, 1))
     parts.append(np.zeros(nw))
     parts.append(rng.uniform(-a2, a2, (nw, nw)).ravel())
+    for _ in range(depth - 1 if H > 0 else 0):
+        ah = 1.0 / np.sqrt(H)
+        parts.append(rng.uniform(-ah, ah, (H, H)).ravel())
+        parts.append(np.zeros(H))
     out = np.concatenate(parts).astype(np.float32)
-    assert out.shape[0] == made_param_count(nw, H)
+    assert out.shape[0] == made_param_count(nw, H, depth)
     return out
 
 
