@@ -78,6 +78,12 @@ typedef struct {
   int32_t n_groups;           /* 0 => one vertex per elimination step */
   const int32_t *group_ptr;   /* [n_groups+1] CSR over `order`, or NULL */
   int32_t hidden;             /* hidden width H of q (0: Eq. 7 exactly) */
+  /* hidden layers of q (0 or 1: one; 2..4: D - 1 more tanh layers of width
+   * H after the first, a unit seeing the units below of no larger degree;
+   * their parameters follow W0, see tnvan_param_count).  Ignored when
+   * H = 0.  Nets with a deeper instance run every instance through the
+   * general sampler and REINFORCE kernels and need |W| <= 256, H <= 256. */
+  int32_t depth;
 } tnvan_instance;
 
 typedef struct {
@@ -221,7 +227,8 @@ void tnvan_free_network(tnvan_net *net);
 const char *tnvan_last_error(void);
 
 /* Number of float32 parameters of q for instance i (flat layout
- * W1 [H,n], b1 [H], W2 [n,H], b2 [n], W0 [n,n], n = |W|, row-major). */
+ * W1 [H,n], b1 [H], W2 [n,H], b2 [n], W0 [n,n], n = |W|, row-major; for
+ * depth D > 1 followed by (W^l [H,H], b^l [H]) for l = 2..D). */
 tnvan_status tnvan_param_count(const tnvan_net *net, int32_t inst, int64_t *count);
 
 /* Copy the parameters of instance i from / to device memory (float32 in

@@ -54,7 +54,7 @@ class CInstance(C.Structure):
                 ("n_width", C.c_int32), ("width_set", C.c_void_p),
                 ("n_order", C.c_int32), ("order", C.c_void_p),
                 ("n_groups", C.c_int32), ("group_ptr", C.c_void_p),
-                ("hidden", C.c_int32)]
+                ("hidden", C.c_int32), ("depth", C.c_int32)]
 
 
 class COptions(C.Structure):
@@ -163,6 +163,7 @@ def make_cinstance(inst, keep: list) -> CInstance:
     c.n_groups = 0 if gp is None else int(gp.shape[0] - 1)
     c.group_ptr = None if gp is None else gp.ctypes.data
     c.hidden = int(getattr(inst, "hidden", 0) or 0)
+    c.depth = int(getattr(inst, "depth", 1) or 1)
     return c
 
 

@@ -199,6 +199,8 @@ struct tnvan_net {
   // one-layer sampler (every instance H = 0, the general path): W0's
   // columns, n_q^2 floats per instance
   bool h0 = false;
+  // some instance has a deeper network: the deep sampler and rows kernels
+  bool deep = false;
   int h0_nmax = 0;
   DBuf w0t, d_w0t_off, w_sig;
   // matrix-core sampler
@@ -228,7 +230,7 @@ struct tnvan_net {
   // the instances as built (host copies): tnvan_set_couplings recompiles
   // them with new couplings, fields and inverse temperatures
   struct SrcInst {
-    int32_t n_spins = 0, n_edges = 0, hidden = 0;
+    int32_t n_spins = 0, n_edges = 0, hidden = 0, depth = 0;
     std::vector<int32_t> ei, ej, W, order, gp;
     std::vector<double> J, h;
     double beta = 0.0;
@@ -471,6 +473,7 @@ tnvan_instance src_view(const tnvan_net::SrcInst &c) {
   v.n_groups = c.gp.empty() ? 0 : (int32_t)c.gp.size() - 1;
   v.group_ptr = c.gp.empty() ? nullptr : c.gp.data();
   v.hidden = c.hidden;
+  v.depth = c.depth;
   return v;
 }
 
@@ -991,6 +994,18 @@ tnvan_status run_sample(tnvan_net *net, const float *uniforms, int8_t *spins, vo
   a.mi = net->d_mi.as<MadeInst>();
   a.params = net->params.as<float>();
   a.uniforms = uniforms;
+  if (net->deep) {
+    // deeper networks: a wave per sample, every instance
+    a.spins = spins;
+    a.logq = static_cast<real *>(logq);
+    a.seed = net->seed;
+    a.step_ctr = net->step_ctr.as<int32_t>();
+    int64_t maxB = 0;
+    for (int q = 0; q < net->n_inst; ++q) maxB = std::max(maxB, net->nkey[q]);
+    ProfScope ps(net, TNVAN_KERNEL_SAMPLE, st);
+    HIPCHK(launch_sample_deep<real>(a, net->n_inst, maxB, st));
+    return TNVAN_OK;
+  }
   if (net->h0) {
     // the current parameters' columns of W0, then a wave per sample
     a.spins = spins;
@@ -1131,8 +1146,10 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     float *g = net->grad.as<float>() + m.param_off;
     // REINFORCE backward through q (Eq. 10): per-sample rows, then batch sums
     const int n = m.n, H = m.H;
-    HIPCHK(net->w_hid.ensure(std::max<int64_t>(1, m.B * H) * sizeof(real)));
-    HIPCHK(net->w_da.ensure(std::max<int64_t>(1, m.B * H) * sizeof(real)));
+    // hidden layers run (deeper networks hold every layer in a row)
+    const int D = (net->deep && n >= 2 && H > 0) ? m.D : 1;
+    HIPCHK(net->w_hid.ensure(std::max<int64_t>(1, m.B * D * H) * sizeof(real)));
+    HIPCHK(net->w_da.ensure(std::max<int64_t>(1, m.B * D * H) * sizeof(real)));
     HIPCHK(net->w_dlogit.ensure(std::max<int64_t>(1, m.B * n) * sizeof(real)));
     HIPCHK(net->w_sf.ensure(std::max<int64_t>(1, m.B * n) * sizeof(real)));
     RowArgs<real> r{};
@@ -1146,7 +1163,13 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     r.da = net->w_da.as<real>();
     r.dlogit = net->w_dlogit.as<real>();
     r.sf = net->w_sf.as<real>();
-    if (net->h0) {
+    if (net->deep) {
+      // rows of at most 4096 / H samples and about 48 KB of LDS per round
+      const size_t per = sizeof(real) * (2 * (size_t)n + (size_t)D * H + H);
+      const int rb = (int)std::max<int64_t>(1, std::min<int64_t>({16, 4096 / std::max(1, H),
+                                                                  (int64_t)(49152 / per)}));
+      HIPCHK(launch_rows_deep<real>(r, rb, st));
+    } else if (net->h0) {
       // the conditionals the sampler stored for these spins and parameters
       r.sig = net->w_sig.as<real>() + m.spin_off;
       HIPCHK(launch_rows_h0<real>(r, st));
@@ -1155,15 +1178,27 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     }
     // batch slices of at least 64 rows, at most 64 slices
     const int ks = (int)std::max<int64_t>(1, std::min<int64_t>(64, m.B / 64));
-    const int64_t maxmn = std::max<int64_t>({(int64_t)n * H, (int64_t)n * n, (int64_t)H});
+    const int64_t maxmn = std::max<int64_t>({(int64_t)n * H, (int64_t)n * n, (int64_t)H * H,
+                                             (int64_t)H});
     HIPCHK(net->w_part.ensure(std::max<int64_t>(1, maxmn * ks) * sizeof(real)));
     float *gW1 = g, *gb1 = g + (int64_t)H * n, *gW2 = gb1 + H, *gb2 = gW2 + (int64_t)n * H,
           *gW0 = gb2 + n;
     real *part = net->w_part.as<real>();
     if (H > 0) {
-      HIPCHK(launch_atb<real>(r.dlogit, n, r.hid, H, m.B, n, H, part, ks, gW2, H, 1, n, st));
-      HIPCHK(launch_atb<real>(r.da, H, r.sf, n, m.B, H, n, part, ks, gW1, n, 3, n, st));
-      HIPCHK(launch_colsum<real>(r.da, H, m.B, H, part, ks, gb1, st));
+      // rows of D H: layer l at column (l - 1) H; the logits read layer D
+      const int DH = D * H;
+      HIPCHK(launch_atb<real>(r.dlogit, n, r.hid + (int64_t)(D - 1) * H, DH, m.B, n, H, part, ks,
+                              gW2, H, 1, n, st));
+      HIPCHK(launch_atb<real>(r.da, DH, r.sf, n, m.B, H, n, part, ks, gW1, n, 3, n, st));
+      HIPCHK(launch_colsum<real>(r.da, DH, m.B, H, part, ks, gb1, st));
+      // deeper layers l = 2..D after W0: W^l [H, H] (da^l against h^{l-1}), b^l
+      float *gl = gW0 + (int64_t)n * n;
+      for (int l = 2; l <= D; ++l, gl += (int64_t)H * H + H) {
+        HIPCHK(launch_atb<real>(r.da + (int64_t)(l - 1) * H, DH, r.hid + (int64_t)(l - 2) * H, DH,
+                                m.B, H, H, part, ks, gl, H, 4, n, st));
+        HIPCHK(launch_colsum<real>(r.da + (int64_t)(l - 1) * H, DH, m.B, H, part, ks,
+                                   gl + (int64_t)H * H, st));
+      }
     }
     HIPCHK(launch_atb<real>(r.dlogit, n, r.sf, n, m.B, n, n, part, ks, gW0, n, 2, n, st));
     HIPCHK(launch_colsum<real>(r.dlogit, n, m.B, n, part, ks, gb2, st));
@@ -1422,6 +1457,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
     c.n_spins = in.n_spins;
     c.n_edges = in.n_edges;
     c.hidden = in.hidden;
+    c.depth = in.depth;
     c.beta = in.beta;
     c.ei.assign(in.edge_i, in.edge_i + in.n_edges);
     c.ej.assign(in.edge_j, in.edge_j + in.n_edges);
@@ -1441,16 +1477,28 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
     MadeInst m{};
     m.n = net->P.insts[q].nw;
     m.H = net->P.hidden[q];
+    m.D = net->P.depth[q];
     int L = 8;
     while (L < 64 && (m.H > 16 * L || m.n > 32 * L)) L <<= 1;
     if (m.H > 16 * L || m.n > 32 * L) { delete net; return set_err(TNVAN_E_INVALID, "instance %d: network too wide", q); }
     m.L = L;
     m.param_off = poff;
-    const int64_t pc = (int64_t)m.H * m.n + m.H + (int64_t)m.n * m.H + m.n + (int64_t)m.n * m.n;
+    const int64_t pc = (int64_t)m.H * m.n + m.H + (int64_t)m.n * m.H + m.n + (int64_t)m.n * m.n +
+                       (int64_t)(m.D - 1) * ((int64_t)m.H * m.H + m.H);
+    if (m.D > 1 && m.n >= 2) net->deep = true;
     net->param_count.push_back(pc);
     poff += pc;
     net->mi.push_back(m);
   }
+  // deeper networks: every instance runs the general deep sampler and rows
+  // kernels, whose per-lane tables hold |W| <= 256 and H <= 256
+  if (net->deep)
+    for (int q = 0; q < n_inst; ++q)
+      if (net->mi[q].n > kDeepMaxN || net->mi[q].H > kDeepMaxH) {
+        delete net;
+        return set_err(TNVAN_E_INVALID, "instance %d: a net with a deeper network needs "
+                       "|W| <= %d and H <= %d", q, kDeepMaxN, kDeepMaxH);
+      }
   // one lane count for every instance keeps the sampler a single launch
   int Lmax = 8;
   for (auto &m : net->mi) Lmax = std::max(Lmax, (int)m.L);
@@ -1460,7 +1508,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   // units per degree (FP32 / BF16 precisions)
   {
     int nmax = 1;
-    bool fits = net->precision != TNVAN_FP64;
+    bool fits = net->precision != TNVAN_FP64 && !net->deep;
     for (auto &m : net->mi) {
       nmax = std::max(nmax, (int)m.n);
       if (m.n > 64 || (m.n >= 2 && m.H > 15 * (m.n - 1))) fits = false;
@@ -1468,7 +1516,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
     net->mpt = nmax <= 16 ? 1 : nmax <= 32 ? 2 : 4;
     net->msample = fits;
     // one-layer nets outside the matrix-core sampler: a wave per sample
-    bool h0 = !fits && nmax <= kH0MaxN;
+    bool h0 = !fits && nmax <= kH0MaxN && !net->deep;
     std::vector<int64_t> w0off;
     int64_t wo = 0;
     for (auto &m : net->mi) {
@@ -1498,7 +1546,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
     int dev = 0, maxlds = 65536;
     hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    bool gfit = net->precision != TNVAN_FP64;
+    bool gfit = net->precision != TNVAN_FP64 && !net->deep;
     for (auto &m : net->mi) {
       net->mg_hmax = std::max(net->mg_hmax, (int)m.H);
       if (m.n > 64 || m.H > 256 || m.n % 4 || m.H % 4) gfit = false;

@@ -362,6 +362,7 @@ tnvan_status compile_instance(const tnvan_instance &in, int max_width,
     return TNVAN_E_INVALID;
   }
   if (in.hidden < 0 || in.hidden > 65536) { fail(msg, "hidden width %ld out of range", in.hidden); return TNVAN_E_INVALID; }
+  if (in.depth < 0 || in.depth > 4) { fail(msg, "depth %ld out of range (0..4)", in.depth); return TNVAN_E_INVALID; }
   if (max_width <= 0 || max_width > kMaxW) max_width = kMaxW;
 
   std::vector<int32_t> pos(n, -1), widx(n, -1);
@@ -675,6 +676,7 @@ tnvan_status compile_instance(const tnvan_instance &in, int max_width,
   }
   P.insts.push_back(D);
   P.hidden.push_back(in.hidden);
+  P.depth.push_back(in.hidden > 0 && in.depth > 1 ? in.depth : 1);
   P.flops_fwd.push_back(flops);
   return TNVAN_OK;
 }

@@ -33,6 +33,7 @@ struct HostProgram {
   std::vector<double> hW;           // h on W indices (for E_1)
   std::vector<int32_t> vr, wv;      // R position -> vertex, W index -> vertex
   std::vector<int32_t> hidden;      // per instance
+  std::vector<int32_t> depth;       // per instance: hidden layers (1 when H = 0)
   std::vector<int64_t> flops_fwd;   // per instance, per sample
   std::vector<int32_t> hw_off;      // per instance offset into hW
   std::vector<int32_t> fld_wr;      // W-R edge (local index) of each fld entry

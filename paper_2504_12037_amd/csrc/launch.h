@@ -99,7 +99,7 @@ hipError_t launch_vjp_reduce(const VjpArgs &a, const real *partial, int n_inst, 
 struct MadeInst {
   int32_t n, H;             // |W|, hidden width
   int32_t L;                // lanes per sample in the sampler
-  int32_t pad;
+  int32_t D;                // hidden layers (1 when H = 0)
   int64_t param_off;        // offset of the instance's parameters
   int64_t pack_off;         // offset of its matrix-core sampler tables
   int64_t sample_off;       // first global sample
@@ -139,6 +139,14 @@ template <typename real>
 hipError_t launch_sample_h0(const SampleArgs<real> &a, int n_inst, int64_t max_B, int max_n,
                             hipStream_t st);
 size_t made_param_bytes(int n, int H);
+
+// Deeper networks (some instance with D > 1 hidden layers): one wave per
+// sample for every instance, a lane owning hidden units lane + 64 kk and
+// positions lane + 64 jj; the completed tanh values of each layer in LDS.
+constexpr int kDeepMaxN = 256, kDeepMaxH = 256, kDeepMaxD = 4;
+template <typename real>
+hipError_t launch_sample_deep(const SampleArgs<real> &a, int n_inst, int64_t max_B,
+                              hipStream_t st);
 
 // Matrix-core sampler (FP32): one wave per 16 samples of one instance.
 // Needs n <= 64 and at most 15 hidden units per degree (H <= 15 (n - 1)).
@@ -205,6 +213,10 @@ struct RowArgs {
 };
 template <typename real>
 hipError_t launch_rows(const RowArgs<real> &a, hipStream_t st);
+// deeper networks: hid and da hold every layer, [B, D * H] (layer-major
+// inside a row); rb samples per block round
+template <typename real>
+hipError_t launch_rows_deep(const RowArgs<real> &a, int rb, hipStream_t st);
 // one-layer nets: the rows from the conditionals the sampler stored
 template <typename real>
 hipError_t launch_rows_h0(const RowArgs<real> &a, hipStream_t st);

@@ -21,6 +21,12 @@ namespace {
 
 __device__ inline int degree(int k, int n) { return 1 + (k % (n - 1)); }
 
+// parameters of an instance: W1, b1, W2, b2, W0, then D - 1 deeper layers
+__device__ inline int64_t made_pc(const MadeInst &m) {
+  return (int64_t)m.H * m.n + m.H + (int64_t)m.n * m.H + m.n + (int64_t)m.n * m.n +
+         (int64_t)(m.D - 1) * ((int64_t)m.H * m.H + m.H);
+}
+
 template <typename real> __device__ inline real rexp(real x);
 template <> __device__ inline float rexp<float>(float x) { return expf(x); }
 template <> __device__ inline double rexp<double>(double x) { return exp(x); }
@@ -219,6 +225,241 @@ __global__ __launch_bounds__(256) void sample_kernel(SampleArgs<real> a) {
       }
     }
     if (live && l == 0) a.logq[mi.sample_off + b] = lq;
+  }
+}
+
+// Deeper networks (D > 1): layer l >= 2 has a^l_k' = b^l_k' + sum over
+// units k of layer l - 1 with m(k) <= m(k') of W^l[k', k] h^{l-1}_k; the
+// logits read layer D.  Its parameters follow W0: (W^l [H, H], b^l [H]).
+__device__ inline const float *deep_layer(const float *p, int n, int H, int l) {
+  // W^l of layer l = 2..D (its bias follows it)
+  return p + (int64_t)H * n + H + (int64_t)n * H + n + (int64_t)n * n +
+         (int64_t)(l - 2) * ((int64_t)H * H + H);
+}
+
+// One wave per sample (four per block, one instance per block row).  A unit
+// of layer 1 with degree m is complete once position m - 1 is drawn; a unit
+// of layer l then gets the newly completed units of layer l - 1 (those of
+// degree m: k = m - 1 + t (n - 1)) and is complete when its own degree is
+// reached.  Lane l owns units l + 64 kk of every layer (pre-activations in
+// registers) and positions l + 64 jj (spins in registers); completed tanh
+// values go to LDS, read by the wave after a barrier.
+constexpr int kDeepKK = kDeepMaxH / 64, kDeepJJ = kDeepMaxN / 64;
+template <typename real>
+__global__ __launch_bounds__(256) void sample_deep_kernel(SampleArgs<real> a) {
+  __shared__ real hs[4][kDeepMaxD][kDeepMaxH];
+  const int q = blockIdx.y, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const MadeInst mi = a.mi[q];
+  if ((int64_t)blockIdx.x * 4 >= mi.B) return;   // uniform over the block
+  const int64_t b = (int64_t)blockIdx.x * 4 + wv;
+  const bool live = b < mi.B;
+  const int64_t bs = live ? b : 0;
+  const int n = mi.n, H = n >= 2 ? mi.H : 0, D = H > 0 ? mi.D : 1;
+  const float *P = a.params + mi.param_off;
+  const MadeView w = made_view(P, n, mi.H);
+  const uint32_t step = a.step_ctr ? (uint32_t)a.step_ctr[q] : 0u;
+  real acc[kDeepMaxD][kDeepKK], sv[kDeepJJ];
+  int dg[kDeepKK];
+#pragma unroll
+  for (int kk = 0; kk < kDeepKK; ++kk) {
+    const int k = lane + 64 * kk;
+    dg[kk] = k < H ? degree(k, n) : 0;
+#pragma unroll
+    for (int l = 0; l < kDeepMaxD; ++l) {
+      const float *bl = l == 0 ? w.b1 : deep_layer(P, n, mi.H, l + 1) + (int64_t)mi.H * mi.H;
+      acc[l][kk] = (k < H && l < D) ? (real)bl[k] : (real)0;
+    }
+  }
+#pragma unroll
+  for (int jj = 0; jj < kDeepJJ; ++jj) sv[jj] = 0;
+  const float *u = a.uniforms ? a.uniforms + mi.spin_off + bs * n : nullptr;
+  int8_t *so = a.spins + mi.spin_off + bs * n;
+  uint32_t pw[4] = {0, 0, 0, 0};
+  real lq = 0;
+  for (int i = 0; i < n; ++i) {
+    // logit_i from the last layer's completed units and the earlier spins
+    real part = 0;
+#pragma unroll
+    for (int kk = 0; kk < kDeepKK; ++kk) {
+      const int k = lane + 64 * kk;
+      if (k < H && dg[kk] <= i) part += (real)w.W2[(int64_t)i * mi.H + k] * hs[wv][D - 1][k];
+    }
+#pragma unroll
+    for (int jj = 0; jj < kDeepJJ; ++jj) {
+      const int j = lane + 64 * jj;
+      if (j < i) part += (real)w.W0[(int64_t)i * n + j] * sv[jj];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+    const real logit = part + (real)w.b2[i];
+    float ui;
+    if (u) {
+      ui = live ? u[i] : 0.5f;
+    } else {
+      if ((i & 3) == 0) {
+        pw[0] = (uint32_t)(i >> 2); pw[1] = (uint32_t)bs; pw[2] = step; pw[3] = (uint32_t)q;
+        philox4x32_10(pw, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+      }
+      ui = (float)(pw[i & 3] >> 8) * 5.9604644775390625e-08f;
+    }
+    const real p = sigmoid<real>(logit);
+    const real si = ((real)ui < p) ? (real)1 : (real)-1;
+    lq += log_sigmoid<real>(si * logit);
+#pragma unroll
+    for (int jj = 0; jj < kDeepJJ; ++jj)
+      if (lane + 64 * jj == i) sv[jj] = si;
+    if (lane == 0 && live) so[i] = (int8_t)(si > 0 ? 1 : -1);
+    // layer 1: the new spin, and the units it completes
+#pragma unroll
+    for (int kk = 0; kk < kDeepKK; ++kk) {
+      const int k = lane + 64 * kk;
+      if (k < H && dg[kk] >= i + 1) {
+        acc[0][kk] += (real)w.W1[(int64_t)k * n + i] * si;
+        if (dg[kk] == i + 1) hs[wv][0][k] = rtanh<real>(acc[0][kk]);
+      }
+    }
+    // deeper layers: the units of degree i + 1 just completed below
+    for (int l = 1; l < D; ++l) {
+      __syncthreads();
+      const float *Wl = deep_layer(P, n, mi.H, l + 1);
+#pragma unroll
+      for (int kk = 0; kk < kDeepKK; ++kk) {
+        const int k2 = lane + 64 * kk;
+        if (k2 < H && dg[kk] >= i + 1) {
+          if (i + 1 <= n - 1)
+            for (int k = i; k < H; k += n - 1)
+              acc[l][kk] += (real)Wl[(int64_t)k2 * mi.H + k] * hs[wv][l - 1][k];
+          if (dg[kk] == i + 1) hs[wv][l][k2] = rtanh<real>(acc[l][kk]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (live && lane == 0) a.logq[mi.sample_off + b] = lq;
+}
+
+constexpr int kDeepRows = 4096;                // rb H of one block round
+constexpr int kDeepND = kDeepRows / 256;       // per-thread entries of one layer's dh
+
+// Rows of the REINFORCE backward for deeper networks: per sample every
+// layer's h^l, the logits, dlogit = w ((1+s)/2 - sigmoid), and back through
+// the layers da^l = (dh^l) (1 - (h^l)^2) with dh^D = dlogit . W2m and
+// dh^{l-1} = da^l . W^l m.  Rows of rb samples per block round, in LDS.
+template <typename real>
+__global__ __launch_bounds__(256) void rows_deep_kernel(RowArgs<real> a, int rb) {
+  extern __shared__ __align__(16) char smem[];
+  const MadeInst mi = a.mi;
+  const int n = mi.n, Hs = mi.H, H = n >= 2 ? mi.H : 0, D = H > 0 ? mi.D : 1;
+  const int DH = D * Hs;
+  const float *P = a.params + mi.param_off;
+  const MadeView w = made_view(P, n, Hs);
+  real *ss = reinterpret_cast<real *>(smem);   // [rb][n]
+  real *hh = ss + (size_t)rb * n;               // [rb][D][H]
+  real *dl = hh + (size_t)rb * DH;              // [rb][n]
+  real *d0 = dl + (size_t)rb * n;               // [rb][H]: dh of the current layer
+  const double Fq = a.stats[0];
+  const double invB = 1.0 / (double)mi.B;
+  const int64_t c0 = (int64_t)blockIdx.x * a.chunk;
+  const int64_t c1 = (c0 + a.chunk) < mi.B ? (c0 + a.chunk) : mi.B;
+  for (int64_t r0 = c0; r0 < c1; r0 += rb) {
+    const int nr = (int)((c1 - r0) < rb ? (c1 - r0) : rb);
+    for (int i = threadIdx.x; i < rb * n; i += blockDim.x)
+      ss[i] = i / n < nr ? (real)a.spins[r0 * n + i] : (real)0;
+    __syncthreads();
+    // forward through the layers
+    for (int i = threadIdx.x; i < rb * Hs; i += blockDim.x) {
+      const int r = i / Hs, k = i % Hs;
+      real acc = 0;
+      if (k < H) {
+        acc = (real)w.b1[k];
+        const int m = degree(k, n);
+        for (int j = 0; j < m; ++j) acc += (real)w.W1[(int64_t)k * n + j] * ss[r * n + j];
+        acc = rtanh<real>(acc);
+      }
+      hh[(size_t)r * DH + k] = acc;
+    }
+    __syncthreads();
+    for (int l = 2; l <= D; ++l) {
+      const float *Wl = deep_layer(P, n, Hs, l), *bl = Wl + (int64_t)Hs * Hs;
+      for (int i = threadIdx.x; i < rb * Hs; i += blockDim.x) {
+        const int r = i / Hs, k2 = i % Hs;
+        real acc = 0;
+        if (k2 < H) {
+          acc = (real)bl[k2];
+          const int m2 = degree(k2, n);
+          const real *hp = hh + (size_t)r * DH + (size_t)(l - 2) * Hs;
+          for (int k = 0; k < H; ++k)
+            if (degree(k, n) <= m2) acc += (real)Wl[(int64_t)k2 * Hs + k] * hp[k];
+          acc = rtanh<real>(acc);
+        }
+        hh[(size_t)r * DH + (size_t)(l - 1) * Hs + k2] = acc;
+      }
+      __syncthreads();
+    }
+    // logits and dlogit
+    for (int i = threadIdx.x; i < rb * n; i += blockDim.x) {
+      const int r = i / n, ii = i % n;
+      const real *hD = hh + (size_t)r * DH + (size_t)(D - 1) * Hs;
+      real z = (real)w.b2[ii];
+      for (int k = 0; k < H; ++k)
+        if (degree(k, n) <= ii) z += (real)w.W2[(int64_t)ii * Hs + k] * hD[k];
+      for (int j = 0; j < ii; ++j) z += (real)w.W0[(int64_t)ii * n + j] * ss[r * n + j];
+      const real sv = ss[i];
+      const real wt = r < nr ? (real)((a.f[mi.sample_off + r0 + r] - Fq) * invB) : (real)0;
+      const real d = wt * (((real)1 + sv) * (real)0.5 - sigmoid<real>(z));
+      dl[i] = d;
+      if (r < nr) {
+        a.dlogit[(r0 + r) * n + ii] = d;
+        a.sf[(r0 + r) * n + ii] = sv;
+      }
+    }
+    __syncthreads();
+    // back through the layers: dh^D from the logits, then W^l down
+    for (int i = threadIdx.x; i < rb * Hs; i += blockDim.x) {
+      const int r = i / Hs, k = i % Hs;
+      real acc = 0;
+      if (k < H) {
+        const int m = degree(k, n);
+        for (int ii = m; ii < n; ++ii) acc += dl[r * n + ii] * (real)w.W2[(int64_t)ii * Hs + k];
+      }
+      d0[i] = acc;
+    }
+    __syncthreads();
+    for (int l = D; l >= 1; --l) {
+      // da^l = dh^l (1 - h^2), written out with h^l
+      for (int i = threadIdx.x; i < rb * Hs; i += blockDim.x) {
+        const int r = i / Hs, k = i % Hs;
+        const real hk = hh[(size_t)r * DH + (size_t)(l - 1) * Hs + k];
+        const real da = d0[i] * ((real)1 - hk * hk);
+        d0[i] = da;
+        if (r < nr) {
+          a.hid[(r0 + r) * DH + (int64_t)(l - 1) * Hs + k] = hk;
+          a.da[(r0 + r) * DH + (int64_t)(l - 1) * Hs + k] = da;
+        }
+      }
+      __syncthreads();
+      if (l == 1) break;
+      // dh^{l-1}[k] = sum over k2 with m(k2) >= m(k) of da^l[k2] W^l[k2, k],
+      // kept per thread until every thread has read d0
+      const float *Wl = deep_layer(P, n, Hs, l);
+      // (rb H <= kDeepRows: at most kDeepND entries per thread)
+      real nd[kDeepND];
+      int c = 0;
+      for (int i = threadIdx.x; i < rb * Hs && c < kDeepND; i += blockDim.x, ++c) {
+        const int r = i / Hs, k = i % Hs;
+        real acc = 0;
+        if (k < H) {
+          const int m = degree(k, n);
+          for (int k2 = 0; k2 < H; ++k2)
+            if (degree(k2, n) >= m) acc += d0[r * Hs + k2] * (real)Wl[(int64_t)k2 * Hs + k];
+        }
+        nd[c] = acc;
+      }
+      __syncthreads();
+      c = 0;
+      for (int i = threadIdx.x; i < rb * Hs && c < kDeepND; i += blockDim.x, ++c) d0[i] = nd[c];
+      __syncthreads();
+    }
   }
 }
 
@@ -511,7 +752,8 @@ __global__ __launch_bounds__(256) void atb_kernel(const real *X, int ldx, const 
 
 // out[m*ldo + n] = mask(m, n) * sum_ks part[ks][m][n]
 // mask kinds: 0 none, 1 W2 (n > deg(k)... (row i, col k): i+1 > deg(k)),
-//             2 W0 (col j < row i), 3 W1 (row k, col j): j+1 <= deg(k)
+//             2 W0 (col j < row i), 3 W1 (row k, col j): j+1 <= deg(k),
+//             4 deeper layers (row k', col k): deg(k) <= deg(k')
 template <typename real>
 __global__ void atb_finish(const real *part, int ksplit, int M, int N, float *out,
                            int ldo, int mask_kind, int nW) {
@@ -525,6 +767,7 @@ __global__ void atb_finish(const real *part, int ksplit, int M, int N, float *ou
     if (mask_kind == 1) keep = nW >= 2 && (m + 1) > degree(nn, nW);
     else if (mask_kind == 2) keep = nn < m;
     else if (mask_kind == 3) keep = nW >= 2 && (nn + 1) <= degree(m, nW);
+    else if (mask_kind == 4) keep = nW >= 2 && degree(nn, nW) <= degree(m, nW);
     out[(int64_t)m * ldo + nn] = keep ? (float)acc : 0.0f;
   }
 }
@@ -788,7 +1031,7 @@ __global__ __launch_bounds__(256) void adam_step_kernel(OptArgs a) {
   const MadeInst mi = a.mi[q];
   // an instance without samples this step keeps its parameters and moments
   if (mi.B <= 0) return;
-  const int64_t pc = (int64_t)mi.H * mi.n + mi.H + (int64_t)mi.n * mi.H + mi.n + (int64_t)mi.n * mi.n;
+  const int64_t pc = made_pc(mi);
   float *P = a.params + mi.param_off, *M = a.m + mi.param_off, *V = a.v + mi.param_off;
   const float *G = a.grad + mi.param_off;
   const double t = (double)a.step_ctr[q];
@@ -2038,9 +2281,6 @@ __global__ __launch_bounds__(64 * kMg3W, 8 / kMg3W) void mgrad3_kernel(MGradArgs
 // FP64, sixteen loads in flight at a time; the quarters are added in order,
 // then the parameter's thread stores the gradient, applies Adam and updates
 // the packed tables (as adam_step_kernel).
-__device__ inline int64_t made_pc(const MadeInst &m) {
-  return (int64_t)m.H * m.n + m.H + (int64_t)m.n * m.H + m.n + (int64_t)m.n * m.n;
-}
 constexpr int kGaRows = 16;   // row loads in flight per thread
 __global__ __launch_bounds__(256) void grad_adam_kernel(MGradArgs g, OptArgs o) {
   __shared__ double sh[4][64];
@@ -2243,6 +2483,30 @@ hipError_t launch_rows(const RowArgs<real> &a, hipStream_t st) {
 }
 
 template <typename real>
+hipError_t launch_rows_deep(const RowArgs<real> &a, int rb, hipStream_t st) {
+  if (a.mi.B <= 0) return hipSuccess;
+  if (rb < 1 || (int64_t)rb * a.mi.H > kDeepRows || a.mi.D > kDeepMaxD) return hipErrorInvalidValue;
+  const int D = (a.mi.n >= 2 && a.mi.H > 0) ? a.mi.D : 1;
+  const size_t lds = sizeof(real) * (size_t)rb * (2 * a.mi.n + (size_t)D * a.mi.H + a.mi.H);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(rows_deep_kernel<real>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int64_t blocks = (a.mi.B + a.chunk - 1) / a.chunk;
+  hipLaunchKernelGGL(rows_deep_kernel<real>, dim3((unsigned)blocks), dim3(256), lds, st, a, rb);
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_sample_deep(const SampleArgs<real> &a, int n_inst, int64_t max_B,
+                              hipStream_t st) {
+  if (n_inst <= 0 || max_B <= 0) return hipSuccess;
+  const int64_t bx = (max_B + 3) / 4;
+  if (bx > 0x7fffffff || n_inst > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sample_deep_kernel<real>, dim3((unsigned)bx, n_inst), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename real>
 hipError_t launch_atb(const real *X, int ldx, const real *Y, int ldy, int64_t B, int M,
                       int N, real *part, int ksplit, float *out, int ldo, int mask_kind,
                       int nW, hipStream_t st) {
@@ -2323,6 +2587,10 @@ hipError_t launch_obs_w(const ObsArgs &a, int n_inst, hipStream_t st) {
 
 template hipError_t launch_sample<float>(const SampleArgs<float> &, int, size_t, hipStream_t);
 template hipError_t launch_sample<double>(const SampleArgs<double> &, int, size_t, hipStream_t);
+template hipError_t launch_sample_deep<float>(const SampleArgs<float> &, int, int64_t, hipStream_t);
+template hipError_t launch_sample_deep<double>(const SampleArgs<double> &, int, int64_t, hipStream_t);
+template hipError_t launch_rows_deep<float>(const RowArgs<float> &, int, hipStream_t);
+template hipError_t launch_rows_deep<double>(const RowArgs<double> &, int, hipStream_t);
 template hipError_t launch_sample_h0<float>(const SampleArgs<float> &, int, int64_t, int, hipStream_t);
 template hipError_t launch_sample_h0<double>(const SampleArgs<double> &, int, int64_t, int, hipStream_t);
 template hipError_t launch_rows<float>(const RowArgs<float> &, hipStream_t);

@@ -41,6 +41,7 @@ class Instance:
     hidden: int = 0              # hidden width of the masked-dense network
     name: str = ""
     meta: dict = field(default_factory=dict)
+    depth: int = 1               # hidden layers of the masked-dense network
 
     @property
     def n_edges(self) -> int:
@@ -54,7 +55,7 @@ class Instance:
         return Instance(self.n, self.edges, self.J, self.h, float(beta),
                         self.width_set, self.order, self.group_ptr,
                         self.hidden, f"{self.name.split('@')[0]}@b{beta:g}",
-                        dict(self.meta))
+                        dict(self.meta), self.depth)
 
     def groups(self) -> List[np.ndarray]:
         """The elimination groups as lists of vertices (singletons if no CSR)."""
