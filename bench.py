@@ -424,6 +424,40 @@ def main():
     t_obs = event_time(obs, 5, st)
     ess_o = [float(v) for v in ess_o.cpu().numpy()]
 
+    # magnetisation moments and susceptibility of p from the same samples:
+    # the remainder's conditional mean and variance by the second-order
+    # Taylor contraction, then the importance-weighted moments
+    sus = lambda: net.susceptibility(sp_o, lq_o, counts)
+    out_sus = sus().cpu().numpy()
+    t_sus = event_time(sus, 5, st)
+    mom = lambda: net.remainder_moments(sp_o, counts)
+    _, mean_m, var_m = mom()
+    torch.cuda.synchronize()
+    t_mom = event_time(mom, 5, st)
+    keep["moments"] = (sp_o.cpu().numpy().reshape(nI * B, nw), mean_m.cpu().numpy(),
+                       var_m.cpu().numpy())
+
+    # deeper masked networks: the training step of the step's lattices with
+    # H = 64 at depth 1, 2 and 3 (depth 1 on the one-layer kernels, the others
+    # on the deep sampler and rows kernels)
+    deep = {}
+    for D in (1, 2, 3):
+        insts_d = [S.c2_lattice(b, 64) for b in BETAS]
+        for i_d in insts_d:
+            i_d.depth = D
+        nd = Net(insts_d, precision=args.precision, seed=5,
+                 flags=Net.FLAG_SPLIT_BF16 if split else 0)
+        for k in range(nI):
+            nd.set_params(k, torch.from_numpy(S.made_init(nw, 64, 7 + k, depth=D)))
+        std = torch.empty(nI, 4, dtype=torch.float64, device="cuda")
+        fd = lambda: nd.free_energy_step(counts, 1e-3, stats=std)
+        fd()
+        fd()
+        t_d = event_time(fd, 5, st)
+        deep[str(D)] = {"ms_per_step": 1e3 * t_d, "samples_per_s": nI * B / t_d,
+                        "params_per_instance": nd.param_count(0)}
+        del nd
+
     # the width-set planner (host only, Sec. 2 dynamic slicing) on the
     # paper's graph sizes: a 40x40 lattice and an n = 1000, d = 3 random
     # regular graph at w_u = 20 with the tree kept, an n = 300, d = 4 random
@@ -455,6 +489,33 @@ def main():
     t40 = (time.perf_counter() - t0) / 1000
     F40 = [float(v) / inst40.n for v in st40.cpu().numpy()[0, :2]]
     del net40
+
+    # the paper's n = 1000, d = 3 random regular graph with a batch of 10000
+    # at w_u = 20 (Sec. 4, Fig. 3(b)): W and the order from the planner
+    # (|W| near the paper's 139 at that bound), message scopes up to 20 on
+    # the wide single-spin steps; logZ and forward + adjoint on this path
+    e1k = SI.random_regular_edges(1000, 3, np.random.default_rng(9))
+    W1k, o1k, w1k, _ = plan_width_set(1000, e1k, 20)
+    inst1k = S.Instance(1000, e1k.astype(np.int32),
+                        np.random.default_rng(1).choice([-1.0, 1.0], len(e1k)),
+                        np.random.default_rng(2).normal(0.0, np.sqrt(0.1), 1000), 0.5,
+                        W1k.astype(np.int32), o1k.astype(np.int32), None, 0, "rrg1000_wu20")
+    p1k = "fp64" if args.precision == "fp64" else "fp32"
+    net1k = Net([inst1k], precision=p1k, max_width=20)
+    B1k = 10000
+    sp1k_np = S.uniform_spins(B1k, inst1k.n_width, 105)
+    sp1k = torch.from_numpy(sp1k_np).cuda().reshape(-1)
+    lz1k = torch.empty(B1k, dtype=torch.float64, device="cuda")
+    net1k.logz(sp1k, B1k, out=lz1k)
+    torch.cuda.synchronize()
+    t_l1k = event_time(lambda: net1k.logz(sp1k, B1k, out=lz1k), 1, st)
+    t_fa1k, lzf1k, _ = fwd_adj(net1k, sp1k, [B1k], 1, st)
+    keep["rrg1000"] = (inst1k, sp1k_np[:2], lzf1k[:2])
+    rrg1k = {"workload": "random 3-regular n=1000, +-J, h ~ N(0,0.1), beta 0.5, w_u = 20 "
+                         f"(|W| = {inst1k.n_width}, message scope {w1k}), 10000 samples, {p1k}",
+             "logz_s": t_l1k, "fwd_adj_s": t_fa1k, "logz_samples_per_s": B1k / t_l1k,
+             "fwd_adj_samples_per_s": B1k / t_fa1k}
+    del net1k
 
     # the dominant kernel's live timing (none on paths without it, e.g. FP64)
     roofline = roofline_line(ktime, nI, split, args.checkpoint_every)
@@ -529,12 +590,22 @@ def main():
             "observables": {"workload": "the step's network and batch (samples of q)",
                             "s": t_obs, "samples_per_s": nI * B / t_obs,
                             "effective_sample_size": ess_o},
+            "susceptibility": {"workload": "the step's network and batch (samples of q)",
+                               "s": t_sus, "samples_per_s": nI * B / t_sus,
+                               "remainder_moments_s": t_mom,
+                               "m_per_spin": [float(v) for v in out_sus[:, 0]],
+                               "chi": [float(v) for v in out_sus[:, 2]],
+                               "effective_sample_size": [float(v) for v in out_sus[:, 3]]},
+            "deep_made": {"workload": "the step's 16x16 lattices, MADE H=64 at depth 1/2/3, "
+                                      "training step (sample, logZ, F_q, REINFORCE, Adam)",
+                          "depth": deep},
             "planner": plans,
             "lattice40_ferro_tc": {"workload": "40x40 OBC ferromagnet at beta_c, W = columns "
                                                "7,14,21,28,35, one masked layer, batch 1000, "
                                                "1000 steps, lr 0.01",
                                    "ms_per_step": 1e3 * t40, "F_q_per_spin": F40[0],
                                    "stderr_per_spin": F40[1]},
+            "rrg1000_wu20": rrg1k,
             "kernel_avg_us": {kname(k, split, args.checkpoint_every): 1e6 * t / n
                               for k, (t, n) in ktime.items()},
         },
@@ -637,6 +708,24 @@ def oracle_checks(bd, keep, insts, c3, c4, c5, B5):
         d = bd["c4"]["paths"][pname]
         d["max_abs_dlogZ_per_N_vs_oracle"] = float(np.abs(lz - want4).max() / c4.n)
         d["adjoint_max_err_over_max_entry_vs_oracle"] = vjp_err(c4, sp4, adj)
+    # magnetisation moments: 64 samples of every instance of the step's
+    # batch against the oracle's count-resolved elimination, relative to
+    # the raw second moment of M_R
+    from oracle import magnetisation as MG
+    sp_m, mean_m, var_m = keep["moments"]
+    em = 0.0
+    for k, inst in enumerate(insts):
+        idx = k * B + np.arange(0, B, B // 64)
+        mo, vo = MG.remainder_magnetisation(inst, sp_m[idx])
+        s2 = vo + mo * mo + 1.0
+        em = max(em, float(np.max(np.abs(mean_m[idx] - mo) / np.sqrt(s2))),
+                 float(np.max(np.abs(var_m[idx] - vo) / s2)))
+    bd["susceptibility"]["moments_max_err_over_second_moment_vs_oracle_64_per_instance"] = em
+    # the n = 1000 graph at w_u = 20: two samples by the oracle's elimination
+    inst1k, sp1k, lz1k = keep["rrg1000"]
+    want1k = OI.logz_r_elimination(inst1k, sp1k, chunk=1)
+    bd["rrg1000_wu20"]["max_abs_dlogZ_per_N_vs_oracle_2_samples"] = float(
+        np.abs(lz1k - want1k).max() / inst1k.n)
     # C5, 16 samples of every instance
     off = np.concatenate([[0], np.cumsum(B5)])
     want5 = [OI.logz_r_elimination(inst, keep["c5_spins"][k][:16]) for k, inst in enumerate(c5)]

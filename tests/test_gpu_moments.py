@@ -149,3 +149,29 @@ def test_susceptibility_matches_the_oracle_estimator(prec):
                               [Bs[0], 0]).cpu().numpy()
     np.testing.assert_allclose(out2[0], out[0], rtol=1e-12, atol=0)
     np.testing.assert_array_equal(out2[1], np.zeros(4))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_remainder_moments_at_full_size(prec):
+    # the benchmark's sizes: the 16x16 lattices at three temperatures with
+    # 8192 samples each, and the N = 256 random regular graph with 4096
+    # samples (one call); sampled outputs against the oracle
+    insts = [S.c2_lattice(b) for b in (0.5, 1.0, 2.0)] + [S.c4_rrg()]
+    Bs = [8192, 8192, 8192, 4096]
+    spins = [S.uniform_spins(b, i.n_width, 700 + k) for k, (b, i) in enumerate(zip(Bs, insts))]
+    print(f"\n[moments full size] prec={prec}", flush=True)
+    net = _net(insts, prec)
+    lz, mean, var = net.remainder_moments(_dev(np.concatenate([s.reshape(-1) for s in spins])),
+                                          Bs)
+    lz, mean, var = lz.cpu().numpy(), mean.cpu().numpy(), var.cpu().numpy()
+    off = 0
+    for k, (inst, b, s) in enumerate(zip(insts, Bs, spins)):
+        idx = np.arange(3, b, b // (8 if k == 3 else 32))
+        m_o, v_o = MG.remainder_magnetisation(inst, s[idx])
+        s2 = v_o + m_o * m_o + 1.0
+        em = (np.abs(mean[off + idx] - m_o) / np.sqrt(s2)).max()
+        ev = (np.abs(var[off + idx] - v_o) / s2).max()
+        el = np.abs(lz[off + idx] - OI.logz_r_elimination(inst, s[idx])).max() / inst.n
+        print(f"  {inst.name}: mean err {em:.2e} var err {ev:.2e} logz err/N {el:.2e}", flush=True)
+        assert em <= REL[prec] and ev <= REL[prec] and el <= TOL_LZ[prec]
+        off += b
