@@ -54,6 +54,11 @@ __host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~(size_t)15
 // row stride (floats) of the adjoint's LDS transposes: a multiple of 16
 // plus 16 or 32, so that the four row groups of a read land in different banks
 __host__ __device__ constexpr int ldt_of(int tiles) { return 16 * tiles + ((tiles & 1) ? 32 : 16); }
+// row stride (BF16 values) of the split adjoint's transpose of R's hi and lo
+// parts: 20 words, so that the four row groups of a read start 16 banks apart
+constexpr int kLdtH = 40;
+static_assert(2 * 16 * kLdtH * 2 <= 16 * ldt_of(2) * 4, "split R fits the FP32 transpose buffer");
+static_assert(16 * 2 <= kLdtH, "a row holds the states of two tiles");
 
 struct RL {
   size_t sp, ex, ga, rs, seg, end;
@@ -77,6 +82,7 @@ __host__ __device__ inline RL rlayout(const ChainLim &L, bool bwd, int sg) {
 }
 
 // d[t][r] = prod_j phi_j(bit j of x) for x = 16 t + 4 lg + r < K, else 0
+// (K is wave-uniform: a full group, K = 16 CT, takes no masking)
 template <int CT, int GR>
 __device__ inline void make_diag(const float (&p0)[GR], const float (&p1)[GR], int K, int lg,
                                  float (&d)[CT][4]) {
@@ -89,7 +95,14 @@ __device__ inline void make_diag(const float (&p0)[GR], const float (&p1)[GR], i
   for (int t = 0; t < CT; ++t) {
     const float ft = ph(4, t & 1) * ph(5, t & 2);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) d[t][r] = (16 * t + 4 * lg + r < K) ? fr[r] * ft : 0.f;
+    for (int r = 0; r < 4; ++r) d[t][r] = fr[r] * ft;
+  }
+  if (K < 16 * CT) {
+#pragma unroll
+    for (int t = 0; t < CT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (16 * t + 4 * lg + r >= K) d[t][r] = 0.f;
   }
 }
 
@@ -413,8 +426,6 @@ __global__ __launch_bounds__(256) void rchain_fwd_kernel(ChainArgs a) {
   fwd_chain<kM, CT, SG>(a, tk, cd, lane);
 }
 
-// spin sign of bit j of the state index x
-__device__ inline float sgn(int x, int j) { return ((x >> j) & 1) ? -1.f : 1.f; }
 
 template <int CT, bool kS, bool kK>
 __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstDesc &D,
@@ -433,6 +444,7 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
   int *ex = reinterpret_cast<int *>(base + L.ex);
   float *ga = reinterpret_cast<float *>(base + L.ga);
   float *rs = reinterpret_cast<float *>(base + L.rs);
+  __bf16 *rsb = reinterpret_cast<__bf16 *>(base + L.rs);   // split R (split products)
   const int64_t left = tk.Bq - tk.b0;
   const int nvalid = (int)(left < CW ? left : CW);
   const SpinBits sp = load_bits(a.spins + a.inst_spin_off[tk.q] + (tk.b0 + (ls < nvalid ? ls : 0)) * D.nw,
@@ -616,6 +628,18 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
       for (int c = 0; c < NC; ++c) {
         bf8 rh, rl;
         split_chunk<CT>(R, c, rh, rl);
+        // the split R also goes to LDS (hi in rows 0-15, lo in rows 16-31,
+        // row = sample) for the H product below, which reads it transposed:
+        // R is split once per step
+        typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+        if (2 * c < CT) {
+          *reinterpret_cast<bf4 *>(rsb + ls * kLdtH + 32 * c + 4 * lg) = rh.lo;
+          *reinterpret_cast<bf4 *>(rsb + (16 + ls) * kLdtH + 32 * c + 4 * lg) = rl.lo;
+        }
+        if (2 * c + 1 < CT) {
+          *reinterpret_cast<bf4 *>(rsb + ls * kLdtH + 32 * c + 16 + 4 * lg) = rh.hi;
+          *reinterpret_cast<bf4 *>(rsb + (16 + ls) * kLdtH + 32 * c + 16 + 4 * lg) = rl.hi;
+        }
 #pragma unroll
         for (int xt = 0; xt < CT; ++xt) lam[xt] = mfma_bf(as_bf8(cur.qh[xt][c]), rh, lam[xt]);
 #pragma unroll
@@ -633,20 +657,46 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
             lam[xt] = __builtin_amdgcn_mfma_f32_16x16x4f32(cur.tq[xt][ot][r], R[ot][r], lam[xt], 0, 0, 0);
     }
     // W-R correlations: per-sample magnetisation of a group spin times the
-    // neighbouring width-set spin, weighted and summed over the samples
+    // neighbouring width-set spin, weighted and summed over the samples.
+    // Bit j of this lane's state 16 t + 4 lg + r is bit j of r (j < 2), of
+    // lg (j = 2, 3) or of t (j >= 4): a branch on the wave-uniform j turns
+    // the signs into constants, or into the lane's own sign
+    if (st.n_wri > 0) {
+      float pa[CT][4], pr[4], pt[CT];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (k < st.n_wri) {
-        const int j = st.wri[k] & 0xff, wi = st.wri[k] >> 8;
-        float m = 0.f;
+      for (int xt = 0; xt < CT; ++xt)
 #pragma unroll
-        for (int xt = 0; xt < CT; ++xt)
+        for (int r = 0; r < 4; ++r) pa[xt][r] = As[xt][r] * lam[xt][r];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) m += sgn(16 * xt + 4 * lg + r, j) * As[xt][r] * lam[xt][r];
-        m = rows4_sum(m) * gs;
-        const float v = row16_sum(m * sp.sigma(wi));
-        if (lane == 0) prow[D.nr + st.wre[k]] = v;
+      for (int r = 0; r < 4; ++r) {
+        pr[r] = pa[0][r];
+#pragma unroll
+        for (int xt = 1; xt < CT; ++xt) pr[r] += pa[xt][r];
       }
+#pragma unroll
+      for (int xt = 0; xt < CT; ++xt) pt[xt] = (pa[xt][0] + pa[xt][1]) + (pa[xt][2] + pa[xt][3]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (k < st.n_wri) {
+          const int j = __builtin_amdgcn_readfirstlane(st.wri[k] & 0xff), wi = st.wri[k] >> 8;
+          float m;
+          if (j == 0) {
+            m = (pr[0] - pr[1]) + (pr[2] - pr[3]);
+          } else if (j == 1) {
+            m = (pr[0] + pr[1]) - (pr[2] + pr[3]);
+          } else if (j < 4) {
+            const float tot = (pr[0] + pr[1]) + (pr[2] + pr[3]);
+            m = ((lg >> (j - 2)) & 1) ? -tot : tot;
+          } else {
+            m = 0.f;
+#pragma unroll
+            for (int xt = 0; xt < CT; ++xt) m += ((xt >> (j - 4)) & 1) ? -pt[xt] : pt[xt];
+          }
+          m = rows4_sum(m) * gs;
+          const float v = row16_sum(m * sp.sigma(wi));
+          if (lane == 0) prow[D.nr + st.wre[k]] = v;
+        }
+    }
     // R of the previous step (unused after the first step)
     float Rn[CT][4];
     {
@@ -663,10 +713,12 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
     for (int xt = 0; xt < CT; ++xt)
       *reinterpret_cast<f4 *>(ga + ls * LDT + 16 * xt + 4 * lg) =
           f4{gs * As[xt][0], gs * As[xt][1], gs * As[xt][2], gs * As[xt][3]};
+    if constexpr (!kS) {
 #pragma unroll
-    for (int ot = 0; ot < CT; ++ot)
-      *reinterpret_cast<f4 *>(rs + ls * LDT + 16 * ot + 4 * lg) =
-          f4{R[ot][0], R[ot][1], R[ot][2], R[ot][3]};
+      for (int ot = 0; ot < CT; ++ot)
+        *reinterpret_cast<f4 *>(rs + ls * LDT + 16 * ot + 4 * lg) =
+            f4{R[ot][0], R[ot][1], R[ot][2], R[ot][3]};
+    }
     wsync();
     // per output tile: H (samples contracted), G = H o T, Q'^T = G^T S_x
     f4 qt[CT];
@@ -683,8 +735,8 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
           const __bf16 h = (__bf16)va, l = (__bf16)(va - (float)h);
           ah1[xt][j] = h; ah1[xt][4 + j] = l;
           ah2[xt][j] = h; ah2[xt][4 + j] = (__bf16)0.f;
-          const float vr = rs[(4 * lg + j) * LDT + 16 * xt + ls];
-          const __bf16 rh = (__bf16)vr, rl = (__bf16)(vr - (float)rh);
+          const __bf16 rh = rsb[(4 * lg + j) * kLdtH + 16 * xt + ls];
+          const __bf16 rl = rsb[(16 + 4 * lg + j) * kLdtH + 16 * xt + ls];
           rb1[xt][j] = rh; rb1[xt][4 + j] = rh;
           rb2[xt][j] = rl; rb2[xt][4 + j] = (__bf16)0.f;
         }
