@@ -213,9 +213,12 @@ def main():
 
     torch.cuda.set_device(0)
     st = torch.cuda.current_stream()
-    insts = [S.c2_lattice(b, HIDDEN) for b in BETAS]
+    # the workload file of the step (configs/c2.json)
+    from synthetic import config as SC
+    insts, counts = SC.instances("c2")
+    assert counts == [B] * len(BETAS) and [i.beta for i in insts] == list(BETAS)
+    assert all(i.hidden == HIDDEN for i in insts)
     nI = len(insts)
-    counts = [B] * nI
     nw = insts[0].n_width
     iters = max(5, args.steps)
     keep = {}          # GPU results the oracle leg checks

@@ -127,6 +127,12 @@ typedef struct {
  * the step's work has run, and the flags are cleared for the next call.
  * Without the flag the step does not wait and reports nothing. */
 #define TNVAN_FLAG_CHECK_FINITE 16
+/* roctx ranges around the phases of every call (tnvan/sample, tnvan/logz,
+ * tnvan/boundary, tnvan/steps, tnvan/adjoint, tnvan/step,
+ * tnvan/free_energy, tnvan/reinforce, tnvan/adam), for traces taken with
+ * rocprofv3 --marker-trace; host-side ranges around the launches, nothing
+ * waits.  Without the flag no roctx call is made. */
+#define TNVAN_FLAG_MARKERS 32
 
 /* Launch shapes of a net (tnvan_get_tuning, tnvan_set_tuning,
  * tnvan_autotune).  They change how the work is tiled, not what is computed:

@@ -97,6 +97,7 @@ class Net:
     FLAG_GRAPH = 4
     FLAG_SPLIT_BF16 = 8
     FLAG_CHECK_FINITE = 16
+    FLAG_MARKERS = 32
 
     def profile_only(self, kernels):
         """Time only these kernels (names or ids of KERNELS) from now on."""
@@ -134,7 +135,11 @@ class Net:
     def autotune(self, spins: torch.Tensor, grad: torch.Tensor, n_samples,
                  cache_path: str = None) -> dict:
         """tnvan_autotune on this batch: times the candidate launch shapes,
-        applies the fastest and returns it (JSON cache at cache_path)."""
+        applies the fastest and returns it (JSON cache at cache_path, or at
+        $TNVAN_AUTOTUNE_CACHE when that is set and cache_path is None)."""
+        import os
+        if cache_path is None:
+            cache_path = os.environ.get("TNVAN_AUTOTUNE_CACHE") or None
         arr, counts = self._counts(n_samples)
         spins = spins.to(device="cuda").contiguous()
         grad = grad.to(device="cuda", dtype=torch.float64).contiguous()

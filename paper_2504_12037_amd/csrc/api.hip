@@ -15,6 +15,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/tnvan.h"
 #include "compile.h"
 #include "launch.h"
@@ -188,6 +190,7 @@ struct tnvan_net {
   } step_graph;
   // kernel timing (TNVAN_FLAG_PROFILE): event pairs recorded since the last read
   bool profile = false;
+  bool markers = false;       // TNVAN_FLAG_MARKERS: roctx phase ranges
   uint32_t prof_mask = ~0u;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_used[TNVAN_KERNEL_COUNT], prof_pool;
   int u_chunks = 0;
@@ -267,6 +270,18 @@ tnvan_status quiesce(tnvan_net *net) {
                                                             net->call_streams.end() - 1);
   return TNVAN_OK;
 }
+
+// A roctx range around one phase of a call (sample, boundary, steps,
+// adjoint, free energy, REINFORCE, Adam), under TNVAN_FLAG_MARKERS only.
+struct Phase {
+  bool on;
+  Phase(const tnvan_net *n, const char *name, bool when = true) : on(n->markers && when) {
+    if (on) roctxRangePushA(name);
+  }
+  ~Phase() {
+    if (on) roctxRangePop();
+  }
+};
 
 // Events around one launch of a profiled kernel (no-op unless profiling).
 struct ProfScope {
@@ -754,6 +769,7 @@ ContractArgs<real> contract_args(tnvan_net *net, TileCache &tc, int S) {
 
 template <typename real>
 tnvan_status run_logz(tnvan_net *net, const int8_t *spins, double *logz, hipStream_t st) {
+  Phase ph0(net, "tnvan/logz");
   tnvan_status s = ensure_tiles(net, net->tc_fwd, net->S_fwd, false);
   if (s) return s;
   auto a = contract_args<real>(net, net->tc_fwd, net->S_fwd);
@@ -778,9 +794,13 @@ tnvan_status run_logz(tnvan_net *net, const int8_t *spins, double *logz, hipStre
     ChainArgs c = chain_args(net, false);
     c.spins = spins;
     if (net->rfwd) {
-      HIPCHK(launch_unary(c, net->chain_list.as<int32_t>(), net->n_chain_insts, net->u_chunks,
-                          net->u_maxB, net->f_off.as<int64_t>(), net->Ubuf.as<float>(),
-                          net->fabp.as<double>(), st));
+      {
+        Phase ph(net, "tnvan/boundary");
+        HIPCHK(launch_unary(c, net->chain_list.as<int32_t>(), net->n_chain_insts, net->u_chunks,
+                            net->u_maxB, net->f_off.as<int64_t>(), net->Ubuf.as<float>(),
+                            net->fabp.as<double>(), st));
+      }
+      Phase ph(net, "tnvan/steps");
       if (persistent(net)) {
         c.pq = net->pq.as<int32_t>() + 4;
         for (int gi = 0; gi < 3; ++gi) { c.pq_lo[gi] = net->rg_lo[gi]; c.pq_n[gi] = net->rg_n[gi]; }
@@ -826,6 +846,7 @@ template <typename real>
 tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *grad,
                           double *dh, double *dJ, double *dbeta, hipStream_t st,
                           double *logz = nullptr) {
+  Phase ph0(net, "tnvan/adjoint");
   tnvan_status s = ensure_tiles(net, net->tc_bwd, net->S_bwd, true);
   if (s) return s;
   TileCache &tc = net->tc_bwd;
@@ -856,9 +877,12 @@ tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *gra
     c.partial = reinterpret_cast<float *>(net->partial.p);
     c.inst_partial_off = tc.partial_off.as<int64_t>();
     if (net->rbwd) {
-      HIPCHK(launch_unary(c, net->chain_list.as<int32_t>(), net->n_chain_insts, net->u_chunks,
-                          net->u_maxB, net->f_off.as<int64_t>(), net->Ubuf.as<float>(),
-                          net->fabp.as<double>(), st));
+      {
+        Phase ph(net, "tnvan/boundary");
+        HIPCHK(launch_unary(c, net->chain_list.as<int32_t>(), net->n_chain_insts, net->u_chunks,
+                            net->u_maxB, net->f_off.as<int64_t>(), net->Ubuf.as<float>(),
+                            net->fabp.as<double>(), st));
+      }
       if (persistent(net)) {
         c.pq = net->pq.as<int32_t>() + 6;
         for (int gi = 0; gi < 3; ++gi) { c.pq_lo[gi] = net->brg_lo[gi]; c.pq_n[gi] = gi < 2 ? net->brg_n[gi] : 0; }
@@ -958,6 +982,7 @@ tnvan_status ensure_sample_blocks(tnvan_net *net) {
 template <typename real>
 tnvan_status run_sample(tnvan_net *net, const float *uniforms, int8_t *spins, void *logq,
                         hipStream_t st) {
+  Phase ph0(net, "tnvan/sample");
   tnvan_status s = ensure_sample_blocks(net);
   if (s) return s;
   if ((net->msample || net->mgrad) && sizeof(real) == 4) {
@@ -1047,6 +1072,7 @@ struct StepAdjoint {
 template <typename real>
 tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out,
                       hipStream_t st, const StepAdjoint *adj = nullptr) {
+  Phase ph0(net, "tnvan/step");
   const int64_t B = net->B_total;
   HIPCHK(net->w_spins.ensure(std::max<int64_t>(1, net->spin_total)));
   HIPCHK(net->w_logz.ensure(std::max<int64_t>(1, B) * 8));
@@ -1096,7 +1122,10 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
   f.finish = !fused;
   f.step_ctr = net->step_ctr.as<int32_t>();
   f.nonfinite = net->nonfinite.as<int32_t>();
-  HIPCHK(launch_free<real>(f, net->n_inst, st));
+  {
+    Phase ph(net, "tnvan/free_energy");
+    HIPCHK(launch_free<real>(f, net->n_inst, st));
+  }
   // Adam on every instance (one launch, after the REINFORCE gradient)
   OptArgs o{};
   o.mi = net->d_mi.as<MadeInst>();
@@ -1133,13 +1162,17 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     g.pack = net->mpack.as<float>();
     g.grad = net->grad.as<float>();
     {
+      Phase ph(net, "tnvan/reinforce");
       ProfScope ps(net, TNVAN_KERNEL_MADE_GRAD, st);
       HIPCHK(launch_mgrad(g, net->mpt, st));
     }
     int64_t max_pc = 1;
     for (auto pc : net->param_count) max_pc = std::max(max_pc, pc);
+    Phase ph(net, "tnvan/adam");
     HIPCHK(launch_grad_adam(g, o, max_pc, st));
   }
+  {
+  Phase ph_rf(net, "tnvan/reinforce", !fused);
   for (int q = 0; q < net->n_inst && !fused; ++q) {
     const MadeInst &m = net->mi[q];
     if (m.B <= 0) continue;
@@ -1203,9 +1236,11 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     HIPCHK(launch_atb<real>(r.dlogit, n, r.sf, n, m.B, n, n, part, ks, gW0, n, 2, n, st));
     HIPCHK(launch_colsum<real>(r.dlogit, n, m.B, n, part, ks, gb2, st));
   }
+  }
   if (!fused) {
     int64_t max_pc = 1;
     for (auto pc : net->param_count) max_pc = std::max(max_pc, pc);
+    Phase ph(net, "tnvan/adam");
     HIPCHK(launch_adam_step(o, net->n_inst, max_pc, st));
   }
   if (adj && !adj_logz) return run_backward<real>(net, spins, adj->grad, adj->dh, adj->dJ, adj->dbeta, st);
@@ -1431,6 +1466,7 @@ tnvan_status tnvan_build_network(const tnvan_instance *inst, int32_t n_inst,
   net->precision = opt->precision;
   net->seed = opt->seed;
   net->profile = (opt->flags & TNVAN_FLAG_PROFILE) != 0;
+  net->markers = (opt->flags & TNVAN_FLAG_MARKERS) != 0;
   net->use_graph = (opt->flags & TNVAN_FLAG_GRAPH) != 0;
   net->split = (opt->flags & TNVAN_FLAG_SPLIT_BF16) != 0 && net->precision == TNVAN_FP32;
   net->check_finite = (opt->flags & TNVAN_FLAG_CHECK_FINITE) != 0;

@@ -30,6 +30,7 @@ from .planner import (  # noqa: F401
     order_width,
     greedy_width_set,
 )
+from . import config  # noqa: F401
 from .draws import (  # noqa: F401
     uniform_spins,
     uniforms,
