@@ -103,6 +103,8 @@ def parse():
                    help="run one plain device copy of MIB MiB first (counter calibration)")
     p.add_argument("--checkpoint-every", type=int, default=0, metavar="K",
                    help="adjoint checkpoint interval of the step's net (0: the default, 1)")
+    p.add_argument("--markers", action="store_true",
+                   help="roctx phase ranges on the step's net (for rocprofv3 --marker-trace)")
     p.add_argument("--quick", action="store_true",
                    help="the timed step and its roofline line only (no breakdown, no "
                         "CPU baseline); for counter runs")
@@ -241,7 +243,8 @@ def main():
     # error this leaves against the oracle), unless --fp32-products
     split = args.precision == "fp32" and not args.fp32_products
     net = Net(insts, precision=args.precision, seed=2024,
-              flags=Net.FLAG_PROFILE | (Net.FLAG_SPLIT_BF16 if split else 0),
+              flags=Net.FLAG_PROFILE | (Net.FLAG_SPLIT_BF16 if split else 0) |
+              (Net.FLAG_MARKERS if args.markers else 0),
               checkpoint_every=args.checkpoint_every)
     net.profile_only(["chain_bwd_2"])
     for k in range(nI):
