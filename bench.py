@@ -80,7 +80,7 @@ KERNEL_FLOPS = {
 }
 KERNEL_NAMES = {
     "chain_fwd_2": "rchain_fwd_kernel<{mode}, 2, 2>", "chain_fwd_1": "rchain_fwd_kernel<{mode}, 1, 2>",
-    "chain_bwd_2": "rchain_bwd_kernel<2, {split}, {kk}>", "chain_bwd_1": "rchain_bwd_kernel<1, {split}, {kk}>",
+    "chain_bwd_2": "rchain_bwd_kernel<2, {split}, {kk}>", "chain_bwd_1": "rchain_meet_kernel<{split}>",
     "made_grad": "mgrad_kernel<2, 16>", "sample": "msample_kernel<2, false>",
 }
 PEAK_FP32 = 157.3e12       # MI355X FP32 (vector and 16x16x4 matrix), published

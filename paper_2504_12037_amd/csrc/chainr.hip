@@ -61,10 +61,12 @@ static_assert(2 * 16 * kLdtH * 2 <= 16 * ldt_of(2) * 4, "split R fits the FP32 t
 static_assert(16 * 2 <= kLdtH, "a row holds the states of two tiles");
 
 struct RL {
-  size_t sp, ex, ga, rs, seg, end;
+  size_t sp, ex, ga, rs, seg, fx, xa, xb, end;
 };
 __host__ __device__ inline int rk_of(const ChainLim &L) { return L.rk > 1 ? L.rk : 1; }
-__host__ __device__ inline RL rlayout(const ChainLim &L, bool bwd, int sg) {
+// LDS of one wave.  meet: also the split adjoint's exponents of the
+// backward vectors and the two vectors exchanged at the meeting step
+__host__ __device__ inline RL rlayout(const ChainLim &L, bool bwd, int sg, bool meet = false) {
   RL r{};
   size_t o = 0;
   r.sp = o;
@@ -76,9 +78,21 @@ __host__ __device__ inline RL rlayout(const ChainLim &L, bool bwd, int sg) {
     r.rs = o; o = al16(o + (size_t)CW * ldt * 4);
     // states A_t of one checkpoint segment replayed in the reverse walk
     r.seg = o; o = al16(o + (size_t)(rk_of(L) - 1) * kRegBwdTiles * 64 * 16);
+    if (meet) {
+      r.fx = o; o = al16(o + (size_t)L.max_steps * CW * 4);
+      r.xa = o; o = al16(o + (size_t)kRegBwdTiles * 64 * 16);
+      r.xb = o; o = al16(o + (size_t)kRegBwdTiles * 64 * 16);
+    }
   }
   r.end = al16(o);
   return r;
+}
+// rows of 64 lanes x 16 bytes per adjoint task in the checkpoint buffer:
+// the states kept at the checkpoint interval, or one per step (the split
+// adjoint of one-tile chains keeps every step's vector)
+__host__ __device__ inline int64_t ck_rows(const ChainLim &L) {
+  const int64_t kept = (int64_t)((L.max_steps + rk_of(L) - 1) / rk_of(L)) * kRegBwdTiles;
+  return kept > L.max_steps ? kept : (int64_t)L.max_steps;
 }
 
 // d[t][r] = prod_j phi_j(bit j of x) for x = 16 t + 4 lg + r < K, else 0
@@ -452,8 +466,7 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
   const float gs = ls < nvalid ? (float)a.grad[a.inst_sample_off[tk.q] + tk.b0 + ls] : 0.f;
   float *prow = a.partial + a.inst_partial_off[tk.q] + (tk.b0 / CW) * (int64_t)D.n_partial;
   const int T = cd.n_steps;
-  const int nslots = (a.lim.max_steps + kk - 1) / kk;
-  f4 *ck = reinterpret_cast<f4 *>(a.ckpt) + (int64_t)task_id * nslots * kRegBwdTiles * 64 + lane;
+  f4 *ck = reinterpret_cast<f4 *>(a.ckpt) + (int64_t)task_id * ck_rows(a.lim) * 64 + lane;
   f4 *seg = reinterpret_cast<f4 *>(base + L.seg) + lane;
   const float *ub = phi_base(a, tk.q, tk.Bq, tk.b0 + ls);
 
@@ -821,6 +834,604 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
   }
 }
 
+// ---------------------------------------------------------------------------
+// Split adjoint of one-tile chains.  The backward vectors need not wait for
+// the forward pass: beta_{T-1} is the unit vector of the closing entry and
+// beta_{t-1} = d_t * (T_t beta_t), each rescaled by a power of two of its
+// own, 2^-f_{t-1}.  With out_t = T_t^T A_t the step outputs of the forward
+// pass, R_t = d ln Z / d out_t = K_t beta_t for a per-sample scalar K_t:
+// out_t . R_t = 1 at every step fixes K at the meeting step m - 1
+// (m = ceil(T/2)), and the two recursions give K_t = K_{t-1} 2^(e_{t-1} -
+// f_{t-1}).  Role A runs the forward pass of steps < m (checkpoints and
+// exponents as in the one-wave walk); role B runs the backward vectors of
+// steps >= m and keeps them in the checkpoint slots of those steps.  After
+// the meeting, A continues the forward pass through steps >= m and takes
+// their gradient terms with R_t = K_t beta_t, while B walks steps < m from
+// R_{m-1} = K_{m-1} beta_{m-1} as the one-wave walk does.  Each wave's path
+// is about half the chain's.  Two waves of a workgroup take the two roles of
+// a chain, with one barrier between the phases; the persistent kernel runs
+// the four phases in turn on one wave (the same arithmetic, so the same
+// results bit for bit).
+
+// Lambda operands of one step: FP32 tq, or split-BF16 qh / ql
+template <int CT, bool kS> struct LamOps {
+  static constexpr int NC = (CT + 1) / 2;
+  f4 tq[kS ? 1 : CT][kS ? 1 : CT];
+  u4v qh[kS ? CT : 1][NC], ql[kS ? CT : 1][NC];
+  __device__ void load(const ChainArgs &a, const ChainStep &s, int lane) {
+    if constexpr (kS) {
+      const u4v *q3 = reinterpret_cast<const u4v *>(a.Ts3 + s.s3_off) + lane + 2 * CT * NC * 64;
+#pragma unroll
+      for (int i = 0; i < CT; ++i)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          qh[i][c] = q3[(i * NC + c) * 64];
+          ql[i][c] = q3[((CT + i) * NC + c) * 64];
+        }
+    } else {
+      load_t<CT>(a.Tq + s.tq_off, lane, tq);
+    }
+  }
+};
+
+// Lambda = T R in R-layout over the group's states; with kW (split
+// products) the split R also goes to LDS, sample-major, for the H product
+template <int CT, bool kS, bool kW>
+__device__ inline void lam_mm(const LamOps<CT, kS> &o, const float (&R)[CT][4], __bf16 *rsb, int ls,
+                              int lg, f4 (&lam)[CT]) {
+  constexpr int NC = (CT + 1) / 2;
+#pragma unroll
+  for (int xt = 0; xt < CT; ++xt) lam[xt] = f4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (kS) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      bf8 rh, rl;
+      split_chunk<CT>(R, c, rh, rl);
+      if constexpr (kW) {
+        typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+        if (2 * c < CT) {
+          *reinterpret_cast<bf4 *>(rsb + ls * kLdtH + 32 * c + 4 * lg) = rh.lo;
+          *reinterpret_cast<bf4 *>(rsb + (16 + ls) * kLdtH + 32 * c + 4 * lg) = rl.lo;
+        }
+        if (2 * c + 1 < CT) {
+          *reinterpret_cast<bf4 *>(rsb + ls * kLdtH + 32 * c + 16 + 4 * lg) = rh.hi;
+          *reinterpret_cast<bf4 *>(rsb + (16 + ls) * kLdtH + 32 * c + 16 + 4 * lg) = rl.hi;
+        }
+      }
+#pragma unroll
+      for (int xt = 0; xt < CT; ++xt) lam[xt] = mfma_bf(as_bf8(o.qh[xt][c]), rh, lam[xt]);
+#pragma unroll
+      for (int xt = 0; xt < CT; ++xt) lam[xt] = mfma_bf(as_bf8(o.qh[xt][c]), rl, lam[xt]);
+#pragma unroll
+      for (int xt = 0; xt < CT; ++xt) lam[xt] = mfma_bf(as_bf8(o.ql[xt][c]), rh, lam[xt]);
+    }
+  } else {
+#pragma unroll
+    for (int ot = 0; ot < CT; ++ot)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int xt = 0; xt < CT; ++xt)
+          lam[xt] = __builtin_amdgcn_mfma_f32_16x16x4f32(o.tq[xt][ot][r], R[ot][r], lam[xt], 0, 0, 0);
+  }
+}
+
+// the other operands of a step's gradient terms: T (for G = H o T), the S_x
+// and S_o tables and the columns this lane's correlations go to
+template <int CT, bool kS> struct GradOps {
+  static constexpr int NC = (CT + 1) / 2;
+  f4 tr[CT][CT], sx[kS ? 1 : CT], so[kS ? 1 : CT];
+  u4v sxb[NC], sob[NC];
+  i4v dq;
+  __device__ void load(const ChainArgs &a, const ChainStep &st, int lane) {
+    load_t<CT>(a.Tr + st.tr_off, lane, tr);
+    if constexpr (kS) {
+      const u4v *q3 = reinterpret_cast<const u4v *>(a.Ts3 + st.s3_off) + lane + 4 * CT * NC * 64;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        sxb[c] = q3[c * 64];
+        sob[c] = q3[(NC + c) * 64];
+      }
+    } else {
+      const f4 *sxo = reinterpret_cast<const f4 *>(a.Tsx + st.sx_off) + lane;
+#pragma unroll
+      for (int i = 0; i < CT; ++i) {
+        sx[i] = sxo[i * 64];
+        so[i] = sxo[(CT + i) * 64];
+      }
+    }
+    dq = reinterpret_cast<const i4v *>(a.Tdq + st.dq_off)[lane];
+  }
+};
+
+// The gradient terms of step st from A_t, R_t and Lambda_t: the W-R
+// correlations from p_t = A_t * Lambda_t, then H = sum_s g A R^T, G = H o T
+// and Q = S_o^T G^T S_x (the same products as the one-wave walk), stored to
+// the sample group's row of partial sums
+template <int CT, bool kS>
+__device__ inline void grad_terms(const ChainArgs &a, const InstDesc &D, const ChainStep &st,
+                                  const GradOps<CT, kS> &go, const float (&As)[CT][4],
+                                  const float (&R)[CT][4], const f4 (&lam)[CT], float gs,
+                                  const SpinBits &sp, float *prow, float *ga, float *rs,
+                                  const __bf16 *rsb, int lane) {
+  constexpr int LDT = ldt_of(CT);
+  const int ls = lane & 15, lg = lane >> 4;
+  if (st.n_wri > 0) {
+    float pa[CT][4], pr[4], pt[CT];
+#pragma unroll
+    for (int xt = 0; xt < CT; ++xt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) pa[xt][r] = As[xt][r] * lam[xt][r];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      pr[r] = pa[0][r];
+#pragma unroll
+      for (int xt = 1; xt < CT; ++xt) pr[r] += pa[xt][r];
+    }
+#pragma unroll
+    for (int xt = 0; xt < CT; ++xt) pt[xt] = (pa[xt][0] + pa[xt][1]) + (pa[xt][2] + pa[xt][3]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (k < st.n_wri) {
+        const int j = __builtin_amdgcn_readfirstlane(st.wri[k] & 0xff), wi = st.wri[k] >> 8;
+        float m;
+        if (j == 0) {
+          m = (pr[0] - pr[1]) + (pr[2] - pr[3]);
+        } else if (j == 1) {
+          m = (pr[0] + pr[1]) - (pr[2] + pr[3]);
+        } else if (j < 4) {
+          const float tot = (pr[0] + pr[1]) + (pr[2] + pr[3]);
+          m = ((lg >> (j - 2)) & 1) ? -tot : tot;
+        } else {
+          m = 0.f;
+#pragma unroll
+          for (int xt = 0; xt < CT; ++xt) m += ((xt >> (j - 4)) & 1) ? -pt[xt] : pt[xt];
+        }
+        m = rows4_sum(m) * gs;
+        const float v = row16_sum(m * sp.sigma(wi));
+        if (lane == 0) prow[D.nr + st.wre[k]] = v;
+      }
+  }
+#pragma unroll
+  for (int xt = 0; xt < CT; ++xt)
+    *reinterpret_cast<f4 *>(ga + ls * LDT + 16 * xt + 4 * lg) =
+        f4{gs * As[xt][0], gs * As[xt][1], gs * As[xt][2], gs * As[xt][3]};
+  if constexpr (!kS) {
+#pragma unroll
+    for (int ot = 0; ot < CT; ++ot)
+      *reinterpret_cast<f4 *>(rs + ls * LDT + 16 * ot + 4 * lg) = f4{R[ot][0], R[ot][1], R[ot][2], R[ot][3]};
+  }
+  wsync();
+  f4 qt[CT];
+  if constexpr (kS) {
+    bf8 ah1[CT], ah2[CT], rb1[CT], rb2[CT];
+#pragma unroll
+    for (int xt = 0; xt < CT; ++xt)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float va = ga[(4 * lg + j) * LDT + 16 * xt + ls];
+        const __bf16 h = (__bf16)va, l = (__bf16)(va - (float)h);
+        ah1[xt][j] = h; ah1[xt][4 + j] = l;
+        ah2[xt][j] = h; ah2[xt][4 + j] = (__bf16)0.f;
+        const __bf16 rh = rsb[(4 * lg + j) * kLdtH + 16 * xt + ls];
+        const __bf16 rl = rsb[(16 + 4 * lg + j) * kLdtH + 16 * xt + ls];
+        rb1[xt][j] = rh; rb1[xt][4 + j] = rh;
+        rb2[xt][j] = rl; rb2[xt][4 + j] = (__bf16)0.f;
+      }
+#pragma unroll
+    for (int ot = 0; ot < CT; ++ot) {
+      f4 hg[CT];
+#pragma unroll
+      for (int xt = 0; xt < CT; ++xt) hg[xt] = mfma_bf(ah1[xt], rb1[ot], f4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+      for (int xt = 0; xt < CT; ++xt) hg[xt] = mfma_bf(ah2[xt], rb2[ot], hg[xt]);
+      float gv[CT][4];
+#pragma unroll
+      for (int xt = 0; xt < CT; ++xt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gv[xt][r] = hg[xt][r] * go.tr[ot][xt][r];
+      bf8 gh, gl;
+      split_chunk<CT>(gv, 0, gh, gl);
+      qt[ot] = mfma_bf(gh, as_bf8(go.sxb[0]), f4{0.f, 0.f, 0.f, 0.f});
+      qt[ot] = mfma_bf(gl, as_bf8(go.sxb[0]), qt[ot]);
+    }
+  } else {
+#pragma unroll
+    for (int ot = 0; ot < CT; ++ot) {
+      f4 hg[CT];
+#pragma unroll
+      for (int xt = 0; xt < CT; ++xt) {
+        hg[xt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kc = 0; kc < 4; ++kc)
+          hg[xt] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+              ga[(4 * kc + lg) * LDT + 16 * xt + ls], rs[(4 * kc + lg) * LDT + 16 * ot + ls],
+              hg[xt], 0, 0, 0);
+      }
+      qt[ot] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int xt = 0; xt < CT; ++xt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          qt[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(hg[xt][r] * go.tr[ot][xt][r], go.sx[xt][r],
+                                                        qt[ot], 0, 0, 0);
+    }
+  }
+  wsync();
+  f4 qq = f4{0.f, 0.f, 0.f, 0.f};
+  if constexpr (kS) {
+    float qv[CT][4];
+#pragma unroll
+    for (int ot = 0; ot < CT; ++ot)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) qv[ot][r] = qt[ot][r];
+    bf8 qh, ql;
+    split_chunk<CT>(qv, 0, qh, ql);
+    qq = mfma_bf(as_bf8(go.sob[0]), qh, qq);
+    qq = mfma_bf(as_bf8(go.sob[0]), ql, qq);
+  } else {
+#pragma unroll
+    for (int ot = 0; ot < CT; ++ot)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        qq = __builtin_amdgcn_mfma_f32_16x16x4f32(go.so[ot][r], qt[ot][r], qq, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (go.dq[r] >= 0) prow[go.dq[r]] = qq[r];
+}
+
+// one chain task of the split adjoint, common to both roles
+struct MeetTask {
+  Task tk;
+  InstDesc D;
+  const ChainStep *cs;
+  int T, m;
+  f4 *ck;            // the task's checkpoint rows, this lane
+  const float *ub;   // the sample's unary factors
+  float gs;          // g of the lane's sample (0 past the batch)
+  SpinBits sp;
+  float *prow;
+};
+__device__ inline MeetTask meet_task(const ChainArgs &a, int task_id, int lane) {
+  MeetTask M;
+  const int ls = lane & 15;
+  M.tk = task_at(a, task_id);
+  M.D = a.inst[M.tk.q];
+  const ChainInst C = a.cinst[M.tk.q];
+  const ChainDesc cd = a.chains[C.chain_off + M.tk.c];
+  M.cs = a.csteps + cd.cs_off;
+  M.T = cd.n_steps;
+  M.m = (M.T + 1) / 2;
+  M.ck = reinterpret_cast<f4 *>(a.ckpt) + (int64_t)task_id * ck_rows(a.lim) * 64 + lane;
+  M.ub = phi_base(a, M.tk.q, M.tk.Bq, M.tk.b0 + ls);
+  const int64_t left = M.tk.Bq - M.tk.b0;
+  const int nvalid = (int)(left < CW ? left : CW);
+  M.sp = load_bits(a.spins + a.inst_spin_off[M.tk.q] + (M.tk.b0 + (ls < nvalid ? ls : 0)) * M.D.nw,
+                   M.D.nw, ls < nvalid);
+  M.gs = ls < nvalid ? (float)a.grad[a.inst_sample_off[M.tk.q] + M.tk.b0 + ls] : 0.f;
+  M.prow = a.partial + a.inst_partial_off[M.tk.q] + (M.tk.b0 / CW) * (int64_t)M.D.n_partial;
+  return M;
+}
+
+// what a role carries from its first phase to its second
+template <int CT> struct MeetState {
+  float v[CT][4];    // A: the forward state A_m; B: beta_{m-1}
+  int esum, elast;   // A: exponent sum of steps < m, e_{m-1}
+  float raw;         // A: the closing value when m = T
+};
+
+// role A, steps 0 .. m-1 of the forward pass: checkpoints A_t in slots
+// t < m, exponents e_t in LDS, out_{m-1} to the exchange slot xa
+template <int CT, bool kS>
+__device__ inline void meet_fwd1(const ChainArgs &a, const MeetTask &M, int *ex, f4 *xa, int lane,
+                                 MeetState<CT> &S) {
+  constexpr int GR = GroupMax<CT>::v;
+  constexpr int kM = kS ? 2 : 0;
+  const int ls = lane & 15, lg = lane >> 4;
+  const ChainStep *cs = M.cs;
+  const int T = M.T, m = M.m;
+  {
+    float u[GR];
+    load_phi<GR>(M.ub, M.tk.Bq, cs[0].gpos, cs[0].g, u);
+    diag_from_phi<CT, GR>(u, cs[0].g, lg, S.v);
+  }
+  S.esum = 0;
+  S.elast = 0;
+  S.raw = 1.f;
+  auto fstep = [&](int t, const ChainStep &nx, const FwdOps<kM, CT> &oc, const float (&uc)[GR],
+                   ChainStep &nn, FwdOps<kM, CT> &on, float (&un)[GR]) -> bool {
+#pragma unroll
+    for (int i = 0; i < CT; ++i) M.ck[(t * CT + i) * 64] = f4{S.v[i][0], S.v[i][1], S.v[i][2], S.v[i][3]};
+    nn = step_at(cs, t + 2 < T ? t + 2 : T - 1);
+    on.load(a, nx, lane);
+    load_phi<GR>(M.ub, M.tk.Bq, nn.gpos, nn.g, un);
+    f4 acc[CT];
+    oc.mm(S.v, acc);
+    if (t == m - 1) {
+#pragma unroll
+      for (int i = 0; i < CT; ++i) xa[i * 64] = acc[i];
+    }
+    if (t == T - 1) {
+      S.raw = __shfl(acc[0][0], ls, 64);
+      return true;
+    }
+    float d[CT][4];
+    diag_from_phi<CT, GR>(uc, nx.g, lg, d);
+    const int e = rescale_next<CT>(acc, d, S.v);
+    S.esum += e;
+    S.elast = e;
+    if (lg == 0) ex[t * CW + ls] = e;
+    return t == m - 1;
+  };
+  ChainStep nA = step_at(cs, T > 1 ? 1 : 0), nB;
+  FwdOps<kM, CT> oA, oB;
+  float uA[GR], uB[GR];
+  oA.load(a, cs[0], lane);
+  load_phi<GR>(M.ub, M.tk.Bq, nA.gpos, nA.g, uA);
+  for (int t = 0;; t += 2) {
+    if (fstep(t, nA, oA, uA, nB, oB, uB)) break;
+    if (fstep(t + 1, nB, oB, uB, nA, oA, uA)) break;
+  }
+}
+
+// role B, the backward vectors of steps T-1 .. m: beta_t to the checkpoint
+// slot t, f_{t-1} to LDS, beta_{m-1} kept and written to the exchange slot
+template <int CT, bool kS>
+__device__ inline void meet_bwd1(const ChainArgs &a, const MeetTask &M, int *fx, f4 *xb, int lane,
+                                 MeetState<CT> &S) {
+  constexpr int GR = GroupMax<CT>::v;
+  const int ls = lane & 15, lg = lane >> 4;
+  const ChainStep *cs = M.cs;
+  const int T = M.T, m = M.m;
+#pragma unroll
+  for (int i = 0; i < CT; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) S.v[i][r] = 0.f;
+  if (lg == 0) S.v[0][0] = 1.f;
+  struct Pre {
+    LamOps<CT, kS> o;
+    float u[GR];
+  };
+  auto pre = [&](const ChainStep &s, Pre &p) {
+    p.o.load(a, s, lane);
+    load_phi<GR>(M.ub, M.tk.Bq, s.gpos, s.g, p.u);
+  };
+  auto bstep = [&](int t, const ChainStep &st, const Pre &cur, ChainStep &sn, Pre &nxt) {
+#pragma unroll
+    for (int i = 0; i < CT; ++i) M.ck[(t * CT + i) * 64] = f4{S.v[i][0], S.v[i][1], S.v[i][2], S.v[i][3]};
+    sn = step_at(cs, t - 1 > m ? t - 1 : m);
+    pre(sn, nxt);
+    f4 lam[CT];
+    lam_mm<CT, kS, false>(cur.o, S.v, nullptr, ls, lg, lam);
+    float d[CT][4];
+    diag_from_phi<CT, GR>(cur.u, st.g, lg, d);
+    float mx = 0.f;
+#pragma unroll
+    for (int xt = 0; xt < CT; ++xt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        lam[xt][r] *= d[xt][r];
+        mx = fmaxf(mx, lam[xt][r]);
+      }
+    const int f = expo32(rows4_max(mx));
+    const float sc = pow2neg(f);
+#pragma unroll
+    for (int xt = 0; xt < CT; ++xt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) S.v[xt][r] = lam[xt][r] * sc;
+    if (lg == 0) fx[(t - 1) * CW + ls] = f;
+  };
+  if (T - 1 >= m) {
+    ChainStep sA = step_at(cs, T - 1), sB;
+    Pre pA, pB;
+    pre(sA, pA);
+    for (int t = T - 1;; t -= 2) {
+      bstep(t, sA, pA, sB, pB);
+      if (t - 1 < m) break;
+      bstep(t - 1, sB, pB, sA, pA);
+      if (t - 2 < m) break;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < CT; ++i) xb[i * 64] = f4{S.v[i][0], S.v[i][1], S.v[i][2], S.v[i][3]};
+}
+
+// K_{m-1} = 1 / (out_{m-1} . beta_{m-1}) from the two exchange slots (the
+// same sum in the same order on both roles)
+template <int CT>
+__device__ inline float meet_k(const f4 *xa, const f4 *xb) {
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < CT; ++i) {
+    const f4 p = xa[i * 64], q = xb[i * 64];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) s += p[r] * q[r];
+  }
+  s = rows4_sum(s);
+  return s > 0.f ? 1.f / s : 0.f;
+}
+
+// role A after the meeting: steps m .. T-1 of the forward pass with their
+// gradient terms (R_t = K_t beta_t), then the chain's log partial
+template <int CT, bool kS>
+__device__ inline void meet_fwd2(const ChainArgs &a, const MeetTask &M, const int *fx, float K,
+                                 float *ga, float *rs, __bf16 *rsb, int lane, MeetState<CT> &S) {
+  constexpr int GR = GroupMax<CT>::v;
+  constexpr int kM = kS ? 2 : 0;
+  const int ls = lane & 15, lg = lane >> 4;
+  const ChainStep *cs = M.cs;
+  const int T = M.T, m = M.m;
+  if (m < T) {
+    K = ldexpf(K, S.elast - fx[(m - 1) * CW + ls]);
+    struct Pre {
+      FwdOps<kM, CT> f;
+      LamOps<CT, kS> o;
+      f4 b[CT];
+      float u[GR];   // unary factors of step t + 1's group
+    };
+    auto pre = [&](int t, const ChainStep &s, const ChainStep &s1, Pre &p) {
+      p.f.load(a, s, lane);
+      p.o.load(a, s, lane);
+#pragma unroll
+      for (int i = 0; i < CT; ++i) p.b[i] = M.ck[(t * CT + i) * 64];
+      load_phi<GR>(M.ub, M.tk.Bq, s1.gpos, s1.g, p.u);
+    };
+    // step t with its descriptor st, that of step t + 1 (s1) and step t's
+    // operands cur; loads step t + 1's operands into nxt
+    auto fstep = [&](int t, const ChainStep &st, const ChainStep &s1, const Pre &cur, ChainStep &sn1,
+                     Pre &nxt) -> bool {
+      const bool last = t == T - 1;
+      GradOps<CT, kS> go;
+      go.load(a, st, lane);
+      sn1 = step_at(cs, t + 2 < T ? t + 2 : T - 1);
+      pre(last ? t : t + 1, s1, sn1, nxt);
+      f4 acc[CT];
+      cur.f.mm(S.v, acc);
+      float R[CT][4];
+#pragma unroll
+      for (int i = 0; i < CT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) R[i][r] = K * cur.b[i][r];
+      f4 lam[CT];
+      lam_mm<CT, kS, true>(cur.o, R, rsb, ls, lg, lam);
+      grad_terms<CT, kS>(a, M.D, st, go, S.v, R, lam, M.gs, M.sp, M.prow, ga, rs, rsb, lane);
+      if (last) {
+        S.raw = __shfl(acc[0][0], ls, 64);
+        return true;
+      }
+      float d[CT][4];
+      diag_from_phi<CT, GR>(cur.u, s1.g, lg, d);
+      const int e = rescale_next<CT>(acc, d, S.v);
+      S.esum += e;
+      K = ldexpf(K, e - fx[t * CW + ls]);
+      return false;
+    };
+    ChainStep sA = step_at(cs, m), sA1 = step_at(cs, m + 1 < T ? m + 1 : T - 1), sB, sB1;
+    Pre pA, pB;
+    pre(m, sA, sA1, pA);
+    for (int t = m;; t += 2) {
+      if (fstep(t, sA, sA1, pA, sB1, pB)) break;
+      sB = sA1;
+      if (fstep(t + 1, sB, sB1, pB, sA1, pA)) break;
+      sA = sB1;
+    }
+  }
+  if (lg == 0 && M.tk.b0 + ls < M.tk.Bq)
+    a.cpart[a.cpart_off[M.tk.q] + (int64_t)M.tk.c * M.tk.Bq + M.tk.b0 + ls] =
+        (double)S.esum * 0.69314718055994530942 + log((double)S.raw);
+}
+
+// role B after the meeting: the walk of steps m-1 .. 0 from
+// R_{m-1} = K beta_{m-1}, with A's checkpoints and exponents
+template <int CT, bool kS>
+__device__ inline void meet_bwd2(const ChainArgs &a, const MeetTask &M, const int *ex, float K,
+                                 float *ga, float *rs, __bf16 *rsb, int lane, MeetState<CT> &S) {
+  constexpr int GR = GroupMax<CT>::v;
+  const int ls = lane & 15, lg = lane >> 4;
+  const ChainStep *cs = M.cs;
+  float R[CT][4];
+#pragma unroll
+  for (int i = 0; i < CT; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) R[i][r] = K * S.v[i][r];
+  struct Pre {
+    f4 a[CT];
+    LamOps<CT, kS> o;
+    float u[GR];
+  };
+  auto pre = [&](int t, const ChainStep &s, Pre &p) {
+#pragma unroll
+    for (int i = 0; i < CT; ++i) p.a[i] = M.ck[(t * CT + i) * 64];
+    p.o.load(a, s, lane);
+    load_phi<GR>(M.ub, M.tk.Bq, s.gpos, s.g, p.u);
+  };
+  auto walk = [&](int t, const ChainStep &st, const Pre &cur, ChainStep &sn, Pre &nxt) {
+    GradOps<CT, kS> go;
+    go.load(a, st, lane);
+    sn = step_at(cs, t > 0 ? t - 1 : 0);
+    pre(t > 0 ? t - 1 : 0, sn, nxt);
+    float As[CT][4];
+#pragma unroll
+    for (int i = 0; i < CT; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) As[i][r] = cur.a[i][r];
+    f4 lam[CT];
+    lam_mm<CT, kS, true>(cur.o, R, rsb, ls, lg, lam);
+    grad_terms<CT, kS>(a, M.D, st, go, As, R, lam, M.gs, M.sp, M.prow, ga, rs, rsb, lane);
+    float d[CT][4];
+    diag_from_phi<CT, GR>(cur.u, st.g, lg, d);
+    const float sc = pow2neg(ex[(t > 0 ? t - 1 : 0) * CW + ls]);
+#pragma unroll
+    for (int xt = 0; xt < CT; ++xt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) R[xt][r] = d[xt][r] * lam[xt][r] * sc;
+  };
+  const int m = M.m;
+  ChainStep sA = step_at(cs, m - 1), sB;
+  Pre pA, pB;
+  pre(m - 1, sA, pA);
+  for (int t = m - 1; t >= 0; t -= 2) {
+    walk(t, sA, pA, sB, pB);
+    if (t == 0) break;
+    walk(t - 1, sB, pB, sA, pA);
+  }
+}
+
+template <int CT, bool kS>
+__device__ inline void meet_phase(const ChainArgs &a, const MeetTask &M, int role, int phase,
+                                  const RL &L, char *bA, char *bB, int lane, MeetState<CT> &S) {
+  int *ex = reinterpret_cast<int *>(bA + L.ex);
+  int *fx = reinterpret_cast<int *>(bB + L.fx);
+  f4 *xa = reinterpret_cast<f4 *>(bA + L.xa) + lane;
+  f4 *xb = reinterpret_cast<f4 *>(bB + L.xb) + lane;
+  char *own = role == 0 ? bA : bB;
+  float *ga = reinterpret_cast<float *>(own + L.ga);
+  float *rs = reinterpret_cast<float *>(own + L.rs);
+  __bf16 *rsb = reinterpret_cast<__bf16 *>(own + L.rs);
+  if (phase == 0) {
+    if (role == 0) meet_fwd1<CT, kS>(a, M, ex, xa, lane, S);
+    else meet_bwd1<CT, kS>(a, M, fx, xb, lane, S);
+  } else {
+    const float K = meet_k<CT>(xa, xb);
+    if (role == 0) {
+      meet_fwd2<CT, kS>(a, M, fx, K, ga, rs, rsb, lane, S);
+    } else {
+      // beta_{m-1} from its exchange slot (the value role B left there)
+#pragma unroll
+      for (int i = 0; i < CT; ++i) {
+        const f4 v = xb[i * 64];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) S.v[i][r] = v[r];
+      }
+      meet_bwd2<CT, kS>(a, M, ex, K, ga, rs, rsb, lane, S);
+    }
+  }
+}
+
+// the split adjoint of one-tile chains: two waves per task, roles A (even
+// wave) and B (odd wave), one barrier between the phases (every wave of the
+// workgroup reaches it, with a task or not)
+template <bool kS>
+__global__ __launch_bounds__(256, 3) void rchain_meet_kernel(ChainArgs a) {
+  extern __shared__ __align__(16) char smem[];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const int pair = wave >> 1, role = wave & 1;
+  const int task = a.task_base + blockIdx.x * 2 + pair;
+  const bool has = task < a.task_base + a.n_tasks;
+  const RL L = rlayout(a.lim, true, 1, true);
+  char *bA = smem + (size_t)(2 * pair) * L.end, *bB = bA + L.end;
+  MeetTask M;
+  MeetState<1> S;
+  if (has) {
+    M = meet_task(a, task, lane);
+    meet_phase<1, kS>(a, M, role, 0, L, bA, bB, lane, S);
+  }
+  __syncthreads();
+  if (has) meet_phase<1, kS>(a, M, role, 1, L, bA, bB, lane, S);
+}
+
 template <int CT, bool kS, bool kK>
 __global__ __launch_bounds__(256, 3) void rchain_bwd_kernel(ChainArgs a) {
   extern __shared__ __align__(16) char smem[];
@@ -859,16 +1470,36 @@ __global__ __launch_bounds__(256, 3) void rchain_bwd_pq_kernel(ChainArgs a) {
   extern __shared__ __align__(16) char smem[];
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
-  const RL L = rlayout(a.lim, true, 1);
+  const RL L = rlayout(a.lim, true, 1, true);
   char *base = smem + (size_t)wave * L.end;
   int task = 0, gi = 0;
   while (pq_task(a, lane, task, gi)) {
-    const Task tk = task_at(a, task);
-    const InstDesc D = a.inst[tk.q];
-    const ChainInst C = a.cinst[tk.q];
-    const ChainDesc cd = a.chains[C.chain_off + tk.c];
-    if (gi == 0) bwd_chain<1, kS, kK>(a, tk, D, cd, base, L, lane, task);
-    else bwd_chain<2, kS, kK>(a, tk, D, cd, base, L, lane, task);
+    if (gi == 0) {
+      // the split adjoint's four phases in turn on this wave
+      // (role B's state between its phases is beta_{m-1}, which its
+      // exchange slot holds)
+      const MeetTask M = meet_task(a, task, lane);
+      MeetState<1> SA;
+      meet_phase<1, kS>(a, M, 0, 0, L, base, base, lane, SA);
+      wsync();
+      {
+        MeetState<1> SB;
+        meet_phase<1, kS>(a, M, 1, 0, L, base, base, lane, SB);
+      }
+      wsync();
+      meet_phase<1, kS>(a, M, 0, 1, L, base, base, lane, SA);
+      wsync();
+      {
+        MeetState<1> SB;
+        meet_phase<1, kS>(a, M, 1, 1, L, base, base, lane, SB);
+      }
+    } else {
+      const Task tk = task_at(a, task);
+      const InstDesc D = a.inst[tk.q];
+      const ChainInst C = a.cinst[tk.q];
+      const ChainDesc cd = a.chains[C.chain_off + tk.c];
+      bwd_chain<2, kS, kK>(a, tk, D, cd, base, L, lane, task);
+    }
     wsync();
   }
   pq_exit(a, lane);
@@ -876,7 +1507,7 @@ __global__ __launch_bounds__(256, 3) void rchain_bwd_pq_kernel(ChainArgs a) {
 
 }  // namespace
 
-size_t rchain_wave_lds(const ChainLim &L, bool bwd, int sg) { return rlayout(L, bwd, sg).end; }
+size_t rchain_wave_lds(const ChainLim &L, bool bwd, int sg) { return rlayout(L, bwd, sg, bwd).end; }
 
 hipError_t launch_rchain_pq(const ChainArgs &a, bool bwd, hipStream_t st) {
   const int total = a.pq_n[0] + a.pq_n[1] + a.pq_n[2];
@@ -895,7 +1526,7 @@ hipError_t launch_rchain_pq(const ChainArgs &a, bool bwd, hipStream_t st) {
     else if (m == 1) k = sg >= 2 ? rchain_fwd_pq_kernel<1, 2> : rchain_fwd_pq_kernel<1, 1>;
     else k = sg >= 2 ? rchain_fwd_pq_kernel<2, 2> : rchain_fwd_pq_kernel<2, 1>;
   }
-  const size_t lds = (size_t)kWaves * rlayout(a.lim, bwd, sg).end;
+  const size_t lds = (size_t)kWaves * rlayout(a.lim, bwd, sg, bwd).end;
   hipError_t e;
   if (lds > 65536 && (e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
                                               hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -912,9 +1543,7 @@ hipError_t launch_rchain_pq(const ChainArgs &a, bool bwd, hipStream_t st) {
   return hipGetLastError();
 }
 
-int64_t rchain_ckpt_floats(const ChainLim &L) {
-  return (int64_t)((L.max_steps + rk_of(L) - 1) / rk_of(L)) * kRegBwdTiles * 64 * 4;
-}
+int64_t rchain_ckpt_floats(const ChainLim &L) { return ck_rows(L) * 64 * 4; }
 
 // one launch per chain width: tasks [task_base, task_base + n_tasks) all
 // belong to chains of a.ntm tiles
@@ -924,12 +1553,22 @@ hipError_t launch_rchain(const ChainArgs &a, bool bwd, hipStream_t st) {
   void (*k)(ChainArgs) = nullptr;
   const int ct = a.ntm;
   const bool sp = a.split != 0 && !a.bf16;
+  if (bwd && ct == 1) {
+    // one-tile chains: the split adjoint, two waves per task (every step's
+    // vector kept, whatever the checkpoint interval)
+    k = sp ? rchain_meet_kernel<true> : rchain_meet_kernel<false>;
+    const size_t lds = (size_t)kWaves * rlayout(a.lim, true, 1, true).end;
+    if (lds > 65536) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k, dim3((a.n_tasks + 1) / 2), dim3(64 * kWaves), lds, st, a);
+    return hipGetLastError();
+  }
   if (bwd) {
     const bool kk = rk_of(a.lim) > 1;
-    if (ct == 1)
-      k = sp ? (kk ? rchain_bwd_kernel<1, true, true> : rchain_bwd_kernel<1, true, false>)
-             : (kk ? rchain_bwd_kernel<1, false, true> : rchain_bwd_kernel<1, false, false>);
-    else if (ct == 2)
+    if (ct == 2)
       k = sp ? (kk ? rchain_bwd_kernel<2, true, true> : rchain_bwd_kernel<2, true, false>)
              : (kk ? rchain_bwd_kernel<2, false, true> : rchain_bwd_kernel<2, false, false>);
   } else if (a.bf16) {
