@@ -161,6 +161,10 @@ struct tnvan_net {
   // susceptibility's per-sample moments and effective sample sizes
   DBuf w_jar, w_jexp, d_jar_off, d_jexp_off, w_mmean, w_mvar, w_oess;
   std::vector<int64_t> mkey;
+  // moments on the chain kernels: per (chain, sample) mean and variance,
+  // and the per-instance flags that send the general kernel past them
+  DBuf w_mpart, d_mskip;
+  bool mskip_set = false;
   DBuf garena, partial, w_logz, w_logq, w_spins, w_f, w_fpart, w_hid, w_da, w_dlogit, w_sf,
       w_part, d_hw_off, d_sum_off;
   int max_partial = 0, max_out = 1;
@@ -1347,7 +1351,51 @@ tnvan_status run_moments(tnvan_net *net, const int8_t *spins, double *logz, doub
     HIPCHK(net->w_jexp.ensure((size_t)std::max<int64_t>(1, et) * sizeof(int32_t)));
     net->mkey = net->nkey;
   }
+  // instances whose program is a set of 1-2 tile chains take the jets on
+  // the register-resident chain kernels (FP32 products; the adjoint's task
+  // list), the others the general kernel
+  const bool chains = sizeof(real) == 4 && net->rbwd &&
+                      std::count(net->use_chain.begin(), net->use_chain.end(), 1) > 0;
+  if (chains) {
+    if (tnvan_status s = ensure_chain_tasks(net)) return s;
+    if (!net->mskip_set) {
+      std::vector<int32_t> fl(net->use_chain.begin(), net->use_chain.end());
+      if (tnvan_status s = quiesce(net)) return s;
+      HIPCHK(upload(net->d_mskip, fl));
+      net->mskip_set = true;
+    }
+    int64_t mtot = 0;
+    for (int q = 0; q < net->n_inst; ++q)
+      if (net->use_chain[q]) mtot += (int64_t)net->P.cinst[q].n_chains * net->nkey[q];
+    HIPCHK(net->w_mpart.ensure((size_t)std::max<int64_t>(1, 2 * mtot) * sizeof(double)));
+    ChainArgs c = chain_args(net, true);
+    c.spins = spins;
+    c.mpart = net->w_mpart.as<double>();
+    c.mtot = mtot;
+    HIPCHK(launch_unary(c, net->chain_list.as<int32_t>(), net->n_chain_insts, net->u_chunks,
+                        net->u_maxB, net->f_off.as<int64_t>(), net->Ubuf.as<float>(),
+                        net->fabp.as<double>(), st));
+    for (int gi = 0; gi < 2; ++gi) {
+      c.task_base = net->brg_lo[gi];
+      c.n_tasks = net->brg_n[gi];
+      c.ntm = 1 << gi;
+      HIPCHK(launch_rchain_moments(c, st));
+    }
+    if (logz)
+      HIPCHK(launch_chain_sum(net->inst.as<InstDesc>(), net->cinst.as<ChainInst>(),
+                              net->chain_list.as<int32_t>(), net->n_chain_insts,
+                              net->d_B.as<int64_t>(), net->d_sample_off.as<int64_t>(),
+                              net->cpart_off.as<int64_t>(), net->cpart.as<double>(),
+                              net->f_off.as<int64_t>(), net->fabp.as<double>(), logz, st));
+    HIPCHK(launch_chain_mom_sum(net->cinst.as<ChainInst>(), net->chain_list.as<int32_t>(),
+                                net->n_chain_insts, net->d_B.as<int64_t>(),
+                                net->d_sample_off.as<int64_t>(), net->cpart_off.as<int64_t>(),
+                                net->w_mpart.as<double>(), mtot, mean, var, st));
+    if (std::count(net->use_chain.begin(), net->use_chain.end(), 1) == net->n_inst)
+      return TNVAN_OK;
+  }
   MomentArgs<real> a{};
+  a.skip = chains ? net->d_mskip.as<int32_t>() : nullptr;
   a.inst = net->inst.as<InstDesc>();
   a.steps = net->steps.as<StepDesc>();
   a.inputs = net->inputs.as<InputDesc>();
@@ -1753,7 +1801,7 @@ void tnvan_free_network(tnvan_net *net) {
                  &net->tickets, &net->nonfinite, &net->pq, &net->col_out, &net->pcoef_out, &net->w_xspins, &net->w_xlogz, &net->w_xpart, &net->ww_e, &net->d_wv, &net->w_og,
                  &net->w_ostats, &net->w_odb, &net->fabp, &net->u_off,
                  &net->w_jar, &net->w_jexp, &net->d_jar_off, &net->d_jexp_off, &net->w_mmean,
-                 &net->w_mvar, &net->w_oess,
+                 &net->w_mvar, &net->w_oess, &net->w_mpart, &net->d_mskip,
                  &net->f_off,
                  &net->mpack, &net->mtask_inst, &net->mtask_start, &net->mg_task_inst,
                  &net->mg_task_start, &net->mg_first, &net->mg_count,

@@ -835,6 +835,146 @@ __device__ inline void bwd_chain(const ChainArgs &a, const Task &tk, const InstD
 }
 
 // ---------------------------------------------------------------------------
+// Magnetisation moments of the remainder on a chain: the Taylor jets in
+// eta = beta H of the general moments kernel, in the chain's register
+// layout.  Each state carries the coefficients (c0, c1, c2) of its message;
+// the transfer tables act on each coefficient alike (FP32 products), and a
+// group's diagonal brings the jet d (1, m, m^2 / 2) of its states'
+// magnetisation m.  The rescale is the forward pass's: the power of two of
+// the largest c0, applied to all three coefficients.  The closing entry z
+// gives the chain's log partial, <M> = z1 / z0 and Var(M) = 2 z2 / z0 -
+// (z1 / z0)^2 per sample (the chains of an instance are independent given
+// s_W, so their means and variances add).
+
+// magnetisation of state 16 t + 4 lg + r of a group of g spins (bit set:
+// spin -1); states past the group have d = 0
+__device__ inline float state_mag(int g, int t, int lg, int r) {
+  return (float)(g - 2 * (__builtin_popcount(r) + __builtin_popcount(lg) + __builtin_popcount(t)));
+}
+
+// x_k = jet product of the step output (a0, a1, a2), rescaled by the power
+// of two of its largest c0, with the diagonal jet of the next group;
+// returns that exponent
+template <int CT>
+__device__ inline int jet_next(const f4 (&a0)[CT], const f4 (&a1)[CT], const f4 (&a2)[CT],
+                               const float (&d)[CT][4], int g, int lg, float (&x0)[CT][4],
+                               float (&x1)[CT][4], float (&x2)[CT][4]) {
+  float mx = 0.f;
+#pragma unroll
+  for (int t = 0; t < CT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) mx = fmaxf(mx, a0[t][r]);
+  const int e = expo32(rows4_max(mx));
+  const float sc = pow2neg(e);
+#pragma unroll
+  for (int t = 0; t < CT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float D = d[t][r] * sc, mg = state_mag(g, t, lg, r);
+      x0[t][r] = a0[t][r] * D;
+      x1[t][r] = (a1[t][r] + mg * a0[t][r]) * D;
+      x2[t][r] = (a2[t][r] + mg * a1[t][r] + 0.5f * mg * mg * a0[t][r]) * D;
+    }
+  return e;
+}
+
+template <int CT>
+__device__ inline void mom_chain(const ChainArgs &a, const Task &tk, const ChainDesc &cd, int lane) {
+  constexpr int GR = GroupMax<CT>::v;
+  const int ls = lane & 15, lg = lane >> 4;
+  const ChainStep *cs = a.csteps + cd.cs_off;
+  const int T = cd.n_steps;
+  const float *ub = phi_base(a, tk.q, tk.Bq, tk.b0 + ls);
+  float x0[CT][4], x1[CT][4], x2[CT][4];
+  {
+    float u[GR], d[CT][4];
+    load_phi<GR>(ub, tk.Bq, cs[0].gpos, cs[0].g, u);
+    diag_from_phi<CT, GR>(u, cs[0].g, lg, d);
+#pragma unroll
+    for (int t = 0; t < CT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float mg = state_mag(cs[0].g, t, lg, r);
+        x0[t][r] = d[t][r];
+        x1[t][r] = d[t][r] * mg;
+        x2[t][r] = d[t][r] * (0.5f * mg * mg);
+      }
+  }
+  int esum = 0;
+  float z0 = 1.f, z1 = 0.f, z2 = 0.f;
+  // step t with the descriptor nx of step t + 1, the operands of step t and
+  // the unary factors uc of step t + 1's group; loads step t + 1's operands
+  // and step t + 2's unary factors into the other register set
+  auto fstep = [&](int t, const ChainStep &nx, const FwdOps<0, CT> &oc, const float (&uc)[GR],
+                   ChainStep &nn, FwdOps<0, CT> &on, float (&un)[GR]) -> bool {
+    nn = step_at(cs, t + 2 < T ? t + 2 : T - 1);
+    on.load(a, nx, lane);
+    load_phi<GR>(ub, tk.Bq, nn.gpos, nn.g, un);
+    f4 a0[CT], a1[CT], a2[CT];
+    oc.mm(x0, a0);
+    oc.mm(x1, a1);
+    oc.mm(x2, a2);
+    if (t == T - 1) {
+      z0 = __shfl(a0[0][0], ls, 64);
+      z1 = __shfl(a1[0][0], ls, 64);
+      z2 = __shfl(a2[0][0], ls, 64);
+      return true;
+    }
+    float d[CT][4];
+    diag_from_phi<CT, GR>(uc, nx.g, lg, d);
+    esum += jet_next<CT>(a0, a1, a2, d, nx.g, lg, x0, x1, x2);
+    return false;
+  };
+  ChainStep nA = step_at(cs, T > 1 ? 1 : 0), nB;
+  FwdOps<0, CT> oA, oB;
+  float uA[GR], uB[GR];
+  oA.load(a, cs[0], lane);
+  load_phi<GR>(ub, tk.Bq, nA.gpos, nA.g, uA);
+  for (int t = 0;; t += 2) {
+    if (fstep(t, nA, oA, uA, nB, oB, uB)) break;
+    if (fstep(t + 1, nB, oB, uB, nA, oA, uA)) break;
+  }
+  if (lg == 0 && tk.b0 + ls < tk.Bq) {
+    const int64_t i = a.cpart_off[tk.q] + (int64_t)tk.c * tk.Bq + tk.b0 + ls;
+    const double r1 = (double)z1 / (double)z0, r2 = (double)z2 / (double)z0;
+    a.cpart[i] = (double)esum * 0.69314718055994530942 + log((double)z0);
+    a.mpart[i] = r1;
+    a.mpart[a.mtot + i] = 2.0 * r2 - r1 * r1;
+  }
+}
+
+template <int CT>
+__global__ __launch_bounds__(256) void rchain_mom_kernel(ChainArgs a) {
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const Task tk = wave_task(a, wave);
+  if (tk.q < 0) return;
+  const ChainInst C = a.cinst[tk.q];
+  const ChainDesc cd = a.chains[C.chain_off + tk.c];
+  mom_chain<CT>(a, tk, cd, lane);
+}
+
+__global__ void chain_mom_sum_kernel(const ChainInst *cinst, const int32_t *cis,
+                                     const int64_t *inst_B, const int64_t *inst_sample_off,
+                                     const int64_t *cpart_off, const double *mpart, int64_t mtot,
+                                     double *mean, double *var) {
+  const int q = cis[blockIdx.y];
+  const int64_t B = inst_B[q];
+  const int nc = cinst[q].n_chains;
+  for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < B;
+       b += (int64_t)gridDim.x * blockDim.x) {
+    double m = 0.0, v = 0.0;
+    for (int c = 0; c < nc; ++c) {
+      const int64_t i = cpart_off[q] + (int64_t)c * B + b;
+      m += mpart[i];
+      v += mpart[mtot + i];
+    }
+    mean[inst_sample_off[q] + b] = m;
+    var[inst_sample_off[q] + b] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Split adjoint of one-tile chains.  The backward vectors need not wait for
 // the forward pass: beta_{T-1} is the unit vector of the closing entry and
 // beta_{t-1} = d_t * (T_t beta_t), each rescaled by a power of two of its
@@ -1544,6 +1684,25 @@ hipError_t launch_rchain_pq(const ChainArgs &a, bool bwd, hipStream_t st) {
 }
 
 int64_t rchain_ckpt_floats(const ChainLim &L) { return ck_rows(L) * 64 * 4; }
+
+hipError_t launch_rchain_moments(const ChainArgs &a, hipStream_t st) {
+  if (a.n_tasks <= 0) return hipSuccess;
+  void (*k)(ChainArgs) = a.ntm == 1 ? rchain_mom_kernel<1> : a.ntm == 2 ? rchain_mom_kernel<2> : nullptr;
+  if (!k) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k, dim3((a.n_tasks + kWaves - 1) / kWaves), dim3(64 * kWaves), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_chain_mom_sum(const ChainInst *cinst, const int32_t *chain_insts,
+                                int n_chain_insts, const int64_t *inst_B,
+                                const int64_t *inst_sample_off, const int64_t *cpart_off,
+                                const double *mpart, int64_t mtot, double *mean, double *var,
+                                hipStream_t st) {
+  if (n_chain_insts <= 0) return hipSuccess;
+  hipLaunchKernelGGL(chain_mom_sum_kernel, dim3(32, n_chain_insts), dim3(256), 0, st, cinst,
+                     chain_insts, inst_B, inst_sample_off, cpart_off, mpart, mtot, mean, var);
+  return hipGetLastError();
+}
 
 // one launch per chain width: tasks [task_base, task_base + n_tasks) all
 // belong to chains of a.ntm tiles

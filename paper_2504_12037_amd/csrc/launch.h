@@ -298,6 +298,7 @@ struct MomentArgs {
   const int64_t *jar_off, *jexp_off;
   double *logz;               // out [sum B] or null
   double *mean, *var;         // out [sum B]
+  const int32_t *skip;        // per instance: 1 where the chain kernels wrote it, or null
 };
 template <typename real>
 hipError_t launch_moments(const MomentArgs<real> &a, int n_inst, int64_t max_B, hipStream_t st);
@@ -438,6 +439,11 @@ struct ChainArgs {
   // 4 tiles), taken widest first
   int32_t *pq;
   int32_t pq_lo[3], pq_n[3];
+  // magnetisation moments launch: per chain and sample, the remainder's
+  // conditional mean of M at the chain-partial index and its variance at
+  // mtot plus that index
+  double *mpart;
+  int64_t mtot;
 };
 // U and the per-sample sums of beta |f| over each run of kUnaryChunk
 // positions (fabp[f_off[q] + chunk * B + b]) of the instances in cis.
@@ -458,6 +464,17 @@ constexpr int kRegBwdTiles = 2;
 size_t rchain_wave_lds(const ChainLim &L, bool bwd, int sg);
 int64_t rchain_ckpt_floats(const ChainLim &L);   // per adjoint task
 hipError_t launch_rchain(const ChainArgs &a, bool bwd, hipStream_t st);
+// Magnetisation moments on the register-resident chains (the adjoint's task
+// list: 16 samples per wave, chains of a.ntm <= 2 tiles): cpart and mpart
+// of every task's chain and samples
+hipError_t launch_rchain_moments(const ChainArgs &a, hipStream_t st);
+// per sample of the chain instances: mean and var, the sums over the
+// instance's chains of mpart (chain order)
+hipError_t launch_chain_mom_sum(const ChainInst *cinst, const int32_t *chain_insts,
+                                int n_chain_insts, const int64_t *inst_B,
+                                const int64_t *inst_sample_off, const int64_t *cpart_off,
+                                const double *mpart, int64_t mtot, double *mean, double *var,
+                                hipStream_t st);
 // every width of a.pq_lo / a.pq_n in one persistent launch
 hipError_t launch_rchain_pq(const ChainArgs &a, bool bwd, hipStream_t st);
 // logz[b] = log_const + sum over chains of the per-chain partials

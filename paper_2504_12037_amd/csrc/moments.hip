@@ -16,10 +16,12 @@
 // the parts (independent given s_W).  The same per-step power-of-two
 // rescale as the forward kernels applies to all three coefficients.
 //
-// Every instance runs its general step program (dense grouped steps and
+// An instance runs its general step program here (dense grouped steps and
 // single-spin steps with full tables; not the wide steps), one thread per
 // sample, the jets in device memory as [entry][coefficient][sample] so that
-// neighbouring threads touch neighbouring words.
+// neighbouring threads touch neighbouring words; instances whose program is
+// a set of narrow chains run the same jets on the register-resident chain
+// kernels instead (chainr.hip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -59,6 +61,7 @@ __device__ inline int expo_of(real v) {
 template <typename real>
 __global__ __launch_bounds__(256) void moments_kernel(MomentArgs<real> a) {
   const int q = blockIdx.y;
+  if (a.skip && a.skip[q]) return;
   const int64_t B = a.inst_B[q];
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;

@@ -86,6 +86,39 @@ def test_remainder_moments_against_the_oracle(prec):
         off += b
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_remainder_moments_on_the_chain_kernels(prec):
+    # lattice strips only (one- and two-tile chains, fields and couplings of
+    # both signs): the jets run on the register-resident chain kernels; the
+    # same bounds against the oracle, and a random regular graph beside them
+    # on the general kernel in a second net
+    names = ["c1", "lat8_field", "lat8_b2", "lat6_ferro"]
+    insts = [CASES[k]() for k in names] + [S.lattice_column_split(
+        S.lattice_2d(10, seed=21, beta=1.3, h_var=0.3), [4, 7])]
+    names.append("lat10_two_strips")
+    for extra in (False, True):
+        cur = insts + ([CASES["rrg20"]()] if extra else [])
+        nm = names + (["rrg20"] if extra else [])
+        Bs = [70, 33, 129, 16, 47, 21][:len(cur)]
+        spins = [S.uniform_spins(b, i.n_width, 500 + k) for k, (b, i) in enumerate(zip(Bs, cur))]
+        print(f"\n[moments on chains] prec={prec} with a general instance: {extra}", flush=True)
+        net = _net(cur, prec)
+        lz, mean, var = net.remainder_moments(
+            _dev(np.concatenate([s.reshape(-1) for s in spins])), Bs)
+        torch.cuda.synchronize()
+        lz, mean, var = lz.cpu().numpy(), mean.cpu().numpy(), var.cpu().numpy()
+        off = 0
+        for name, inst, b, s in zip(nm, cur, Bs, spins):
+            (m_o, v_o), lz_o = _oracle(inst, s)
+            s2 = v_o + m_o * m_o + 1.0
+            em = (np.abs(mean[off:off + b] - m_o) / np.sqrt(s2)).max()
+            ev = (np.abs(var[off:off + b] - v_o) / s2).max()
+            el = np.abs(lz[off:off + b] - lz_o).max() / inst.n
+            print(f"  {name}: mean err {em:.2e} var err {ev:.2e} logz err/N {el:.2e}", flush=True)
+            assert em <= REL[prec] and ev <= REL[prec] and el <= TOL_LZ[prec], name
+            off += b
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_susceptibility_exact_under_full_enumeration(prec):
     # every width-set configuration once with a uniform q: the estimate is
