@@ -1203,8 +1203,11 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     if (net->deep) {
       // rows of at most 4096 / H samples and about 48 KB of LDS per round
       const size_t per = sizeof(real) * (2 * (size_t)n + (size_t)D * H + H);
-      const int rb = (int)std::max<int64_t>(1, std::min<int64_t>({16, 4096 / std::max(1, H),
+      // (8 rows per block and one round each: every sample's rows are
+      // independent, and the block count fills the CUs)
+      const int rb = (int)std::max<int64_t>(1, std::min<int64_t>({8, 4096 / std::max(1, H),
                                                                   (int64_t)(49152 / per)}));
+      r.chunk = rb;
       HIPCHK(launch_rows_deep<real>(r, rb, st));
     } else if (net->h0) {
       // the conditionals the sampler stored for these spins and parameters

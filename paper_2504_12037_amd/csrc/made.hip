@@ -243,7 +243,8 @@ __device__ inline const float *deep_layer(const float *p, int n, int H, int l) {
 // degree m: k = m - 1 + t (n - 1)) and is complete when its own degree is
 // reached.  Lane l owns units l + 64 kk of every layer (pre-activations in
 // registers) and positions l + 64 jj (spins in registers); completed tanh
-// values go to LDS, read by the wave after a barrier.
+// values go to the wave's own slice of LDS, read by the wave after a wave
+// barrier (the four waves of a block never wait for each other).
 constexpr int kDeepKK = kDeepMaxH / 64, kDeepJJ = kDeepMaxN / 64;
 template <typename real>
 __global__ __launch_bounds__(256) void sample_deep_kernel(SampleArgs<real> a) {
@@ -289,8 +290,13 @@ __global__ __launch_bounds__(256) void sample_deep_kernel(SampleArgs<real> a) {
       const int j = lane + 64 * jj;
       if (j < i) part += (real)w.W0[(int64_t)i * n + j] * sv[jj];
     }
+    // the wave's sum in registers (row sums, then the four rows) in FP32
+    if constexpr (sizeof(real) == 4) {
+      part = rows4_sum(row16_sum(part));
+    } else {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+      for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+    }
     const real logit = part + (real)w.b2[i];
     float ui;
     if (u) {
@@ -318,9 +324,11 @@ __global__ __launch_bounds__(256) void sample_deep_kernel(SampleArgs<real> a) {
         if (dg[kk] == i + 1) hs[wv][0][k] = rtanh<real>(acc[0][kk]);
       }
     }
-    // deeper layers: the units of degree i + 1 just completed below
+    // deeper layers: the units of degree i + 1 just completed below (each
+    // wave reads only its own sample's slice of LDS, in order: a wave
+    // barrier keeps the writes before the reads)
     for (int l = 1; l < D; ++l) {
-      __syncthreads();
+      wsync();
       const float *Wl = deep_layer(P, n, mi.H, l + 1);
 #pragma unroll
       for (int kk = 0; kk < kDeepKK; ++kk) {
@@ -333,7 +341,7 @@ __global__ __launch_bounds__(256) void sample_deep_kernel(SampleArgs<real> a) {
         }
       }
     }
-    __syncthreads();
+    wsync();
   }
   if (live && lane == 0) a.logq[mi.sample_off + b] = lq;
 }
@@ -761,8 +769,17 @@ __global__ void atb_finish(const real *part, int ksplit, int M, int N, float *ou
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int m = (int)(idx / N), nn = (int)(idx % N);
+    // loads in batches of 8 (independent), additions in slice order
     double acc = 0;
-    for (int k = 0; k < ksplit; ++k) acc += (double)part[(int64_t)k * tot + idx];
+    int k = 0;
+    for (; k + 8 <= ksplit; k += 8) {
+      real v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = part[(int64_t)(k + j) * tot + idx];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc += (double)v[j];
+    }
+    for (; k < ksplit; ++k) acc += (double)part[(int64_t)k * tot + idx];
     bool keep = true;
     if (mask_kind == 1) keep = nW >= 2 && (m + 1) > degree(nn, nW);
     else if (mask_kind == 2) keep = nn < m;
@@ -799,8 +816,17 @@ template <typename real>
 __global__ void colsum_finish(const real *part, int ksplit, int M, float *out) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= M) return;
+  // loads in batches of 8 (independent), additions in slice order
   double acc = 0;
-  for (int k = 0; k < ksplit; ++k) acc += (double)part[(int64_t)k * M + m];
+  int k = 0;
+  for (; k + 8 <= ksplit; k += 8) {
+    real v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = part[(int64_t)(k + j) * M + m];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc += (double)v[j];
+  }
+  for (; k < ksplit; ++k) acc += (double)part[(int64_t)k * M + m];
   out[m] = (float)acc;
 }
 
