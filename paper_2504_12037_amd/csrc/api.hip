@@ -165,6 +165,11 @@ struct tnvan_net {
   // and the per-instance flags that send the general kernel past them
   DBuf w_mpart, d_mskip;
   bool mskip_set = false;
+  // jobs of the REINFORCE backward's batch sums (ensure_batch_sums) and
+  // their key: batch shape, row-buffer addresses, precision
+  DBuf bs_atb, bs_col, bs_alo, bs_aflo, bs_clo, bs_cflo;
+  std::vector<int64_t> bkey;
+  int32_t bs_counts[6] = {0, 0, 0, 0, 0, 0};
   DBuf garena, partial, w_logz, w_logq, w_spins, w_f, w_fpart, w_hid, w_da, w_dlogit, w_sf,
       w_part, d_hw_off, d_sum_off;
   int max_partial = 0, max_out = 1;
@@ -1073,6 +1078,104 @@ struct StepAdjoint {
   double *dh = nullptr, *dJ = nullptr, *dbeta = nullptr;
 };
 
+// The batch sums of the REINFORCE backward as jobs (one per instance and
+// matrix, each with its own slices of the partial sums), laid out once per
+// batch shape and row-buffer addresses
+template <typename real>
+tnvan_status ensure_batch_sums(tnvan_net *net, const std::vector<int64_t> &hoff,
+                               const std::vector<int64_t> &doff, BatchSums<real> *out) {
+  std::vector<int64_t> key(net->nkey);
+  for (const void *p : {net->w_hid.p, net->w_da.p, net->w_dlogit.p, net->w_sf.p, net->grad.p})
+    key.push_back((int64_t)reinterpret_cast<uintptr_t>(p));
+  key.push_back((int64_t)sizeof(real));
+  if (key != net->bkey) {
+    std::vector<AtbJob<real>> aj;
+    std::vector<ColJob<real>> cj;
+    std::vector<int32_t> alo{0}, aflo{0}, clo{0}, cflo{0};
+    int64_t ptot = 0;
+    auto atb = [&](const real *X, int ldx, const real *Y, int ldy, int64_t B, int M, int N,
+                   int ks, float *o, int ldo, int mask, int nW) {
+      if (M <= 0 || N <= 0) return;
+      AtbJob<real> j{X, Y, o, ptot, B, ldx, ldy, M, N, ks, ldo, mask, nW};
+      ptot += (int64_t)ks * M * N;
+      int32_t b = 0, f = 0;
+      batch_sum_blocks(M, N, ks, &b, &f);
+      aj.push_back(j);
+      alo.push_back(alo.back() + b);
+      aflo.push_back(aflo.back() + f);
+    };
+    auto col = [&](const real *X, int ldx, int64_t B, int M, int ks, float *o) {
+      if (M <= 0) return;
+      ColJob<real> j{X, o, ptot, B, ldx, M, ks, 0};
+      ptot += (int64_t)ks * M;
+      int32_t b = 0, f = 0;
+      batch_col_blocks(M, ks, &b, &f);
+      cj.push_back(j);
+      clo.push_back(clo.back() + b);
+      cflo.push_back(cflo.back() + f);
+    };
+    for (int q = 0; q < net->n_inst; ++q) {
+      const MadeInst &m = net->mi[q];
+      if (m.B <= 0) continue;
+      const int n = m.n, H = m.H;
+      const int D = (net->deep && n >= 2 && H > 0) ? m.D : 1;
+      const real *hid = net->w_hid.as<real>() + hoff[q], *da = net->w_da.as<real>() + hoff[q];
+      const real *dl = net->w_dlogit.as<real>() + doff[q], *sf = net->w_sf.as<real>() + doff[q];
+      // batch slices of at least 64 rows, at most 64 slices
+      const int ks = (int)std::max<int64_t>(1, std::min<int64_t>(64, m.B / 64));
+      float *g = net->grad.as<float>() + m.param_off;
+      float *gW1 = g, *gb1 = g + (int64_t)H * n, *gW2 = gb1 + H, *gb2 = gW2 + (int64_t)n * H,
+            *gW0 = gb2 + n;
+      if (H > 0) {
+        // rows of D H: layer l at column (l - 1) H; the logits read layer D
+        const int DH = D * H;
+        atb(dl, n, hid + (int64_t)(D - 1) * H, DH, m.B, n, H, ks, gW2, H, 1, n);
+        atb(da, DH, sf, n, m.B, H, n, ks, gW1, n, 3, n);
+        col(da, DH, m.B, H, ks, gb1);
+        // deeper layers l = 2..D after W0: W^l [H, H] (da^l against h^{l-1}), b^l
+        float *gl = gW0 + (int64_t)n * n;
+        for (int l = 2; l <= D; ++l, gl += (int64_t)H * H + H) {
+          atb(da + (int64_t)(l - 1) * H, DH, hid + (int64_t)(l - 2) * H, DH, m.B, H, H, ks, gl, H,
+              4, n);
+          col(da + (int64_t)(l - 1) * H, DH, m.B, H, ks, gl + (int64_t)H * H);
+        }
+      }
+      atb(dl, n, sf, n, m.B, n, n, ks, gW0, n, 2, n);
+      col(dl, n, m.B, n, ks, gb2);
+    }
+    if (tnvan_status s = quiesce(net)) return s;
+    HIPCHK(upload(net->bs_atb, aj));
+    HIPCHK(upload(net->bs_col, cj));
+    HIPCHK(upload(net->bs_alo, alo));
+    HIPCHK(upload(net->bs_aflo, aflo));
+    HIPCHK(upload(net->bs_clo, clo));
+    HIPCHK(upload(net->bs_cflo, cflo));
+    HIPCHK(net->w_part.ensure((size_t)std::max<int64_t>(1, ptot) * sizeof(real)));
+    net->bs_counts[0] = (int)aj.size();
+    net->bs_counts[1] = (int)cj.size();
+    net->bs_counts[2] = alo.back();
+    net->bs_counts[3] = aflo.back();
+    net->bs_counts[4] = clo.back();
+    net->bs_counts[5] = cflo.back();
+    net->bkey = key;
+  }
+  BatchSums<real> &a = *out;
+  a.atb = net->bs_atb.as<AtbJob<real>>();
+  a.atb_lo = net->bs_alo.as<int32_t>();
+  a.atb_flo = net->bs_aflo.as<int32_t>();
+  a.n_atb = net->bs_counts[0];
+  a.col = net->bs_col.as<ColJob<real>>();
+  a.col_lo = net->bs_clo.as<int32_t>();
+  a.col_flo = net->bs_cflo.as<int32_t>();
+  a.n_col = net->bs_counts[1];
+  a.atb_blocks = net->bs_counts[2];
+  a.atb_fblocks = net->bs_counts[3];
+  a.col_blocks = net->bs_counts[4];
+  a.col_fblocks = net->bs_counts[5];
+  a.part = net->w_part.as<real>();
+  return TNVAN_OK;
+}
+
 template <typename real>
 tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out,
                       hipStream_t st, const StepAdjoint *adj = nullptr) {
@@ -1177,71 +1280,62 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
   }
   {
   Phase ph_rf(net, "tnvan/reinforce", !fused);
-  for (int q = 0; q < net->n_inst && !fused; ++q) {
-    const MadeInst &m = net->mi[q];
-    if (m.B <= 0) continue;
-    float *g = net->grad.as<float>() + m.param_off;
-    // REINFORCE backward through q (Eq. 10): per-sample rows, then batch sums
-    const int n = m.n, H = m.H;
-    // hidden layers run (deeper networks hold every layer in a row)
-    const int D = (net->deep && n >= 2 && H > 0) ? m.D : 1;
-    HIPCHK(net->w_hid.ensure(std::max<int64_t>(1, m.B * D * H) * sizeof(real)));
-    HIPCHK(net->w_da.ensure(std::max<int64_t>(1, m.B * D * H) * sizeof(real)));
-    HIPCHK(net->w_dlogit.ensure(std::max<int64_t>(1, m.B * n) * sizeof(real)));
-    HIPCHK(net->w_sf.ensure(std::max<int64_t>(1, m.B * n) * sizeof(real)));
-    RowArgs<real> r{};
-    r.mi = m;
-    r.params = net->params.as<float>();
-    r.spins = spins + m.spin_off;
-    r.f = net->w_f.as<double>();
-    r.stats = stats + 4 * q;
-    r.chunk = std::max<int64_t>(16, ((m.B + 255) / 256 + 15) / 16 * 16);
-    r.hid = net->w_hid.as<real>();
-    r.da = net->w_da.as<real>();
-    r.dlogit = net->w_dlogit.as<real>();
-    r.sf = net->w_sf.as<real>();
-    if (net->deep) {
-      // rows of at most 4096 / H samples and about 48 KB of LDS per round
-      const size_t per = sizeof(real) * (2 * (size_t)n + (size_t)D * H + H);
-      // (8 rows per block and one round each: every sample's rows are
-      // independent, and the block count fills the CUs)
-      const int rb = (int)std::max<int64_t>(1, std::min<int64_t>({8, 4096 / std::max(1, H),
-                                                                  (int64_t)(49152 / per)}));
-      r.chunk = rb;
-      HIPCHK(launch_rows_deep<real>(r, rb, st));
-    } else if (net->h0) {
-      // the conditionals the sampler stored for these spins and parameters
-      r.sig = net->w_sig.as<real>() + m.spin_off;
-      HIPCHK(launch_rows_h0<real>(r, st));
-    } else {
-      HIPCHK(launch_rows<real>(r, st));
+  if (!fused) {
+    // REINFORCE backward through q (Eq. 10): per-sample rows of every
+    // instance into its own slice of the row buffers, then the batch sums of
+    // every instance and matrix in one launch per kind
+    std::vector<int64_t> hoff(net->n_inst, 0), doff(net->n_inst, 0);
+    int64_t htot = 0, dtot = 0;
+    for (int q = 0; q < net->n_inst; ++q) {
+      const MadeInst &m = net->mi[q];
+      const int D = (net->deep && m.n >= 2 && m.H > 0) ? m.D : 1;
+      hoff[q] = htot;
+      doff[q] = dtot;
+      if (m.B <= 0) continue;
+      htot += m.B * D * m.H;
+      dtot += m.B * m.n;
     }
-    // batch slices of at least 64 rows, at most 64 slices
-    const int ks = (int)std::max<int64_t>(1, std::min<int64_t>(64, m.B / 64));
-    const int64_t maxmn = std::max<int64_t>({(int64_t)n * H, (int64_t)n * n, (int64_t)H * H,
-                                             (int64_t)H});
-    HIPCHK(net->w_part.ensure(std::max<int64_t>(1, maxmn * ks) * sizeof(real)));
-    float *gW1 = g, *gb1 = g + (int64_t)H * n, *gW2 = gb1 + H, *gb2 = gW2 + (int64_t)n * H,
-          *gW0 = gb2 + n;
-    real *part = net->w_part.as<real>();
-    if (H > 0) {
-      // rows of D H: layer l at column (l - 1) H; the logits read layer D
-      const int DH = D * H;
-      HIPCHK(launch_atb<real>(r.dlogit, n, r.hid + (int64_t)(D - 1) * H, DH, m.B, n, H, part, ks,
-                              gW2, H, 1, n, st));
-      HIPCHK(launch_atb<real>(r.da, DH, r.sf, n, m.B, H, n, part, ks, gW1, n, 3, n, st));
-      HIPCHK(launch_colsum<real>(r.da, DH, m.B, H, part, ks, gb1, st));
-      // deeper layers l = 2..D after W0: W^l [H, H] (da^l against h^{l-1}), b^l
-      float *gl = gW0 + (int64_t)n * n;
-      for (int l = 2; l <= D; ++l, gl += (int64_t)H * H + H) {
-        HIPCHK(launch_atb<real>(r.da + (int64_t)(l - 1) * H, DH, r.hid + (int64_t)(l - 2) * H, DH,
-                                m.B, H, H, part, ks, gl, H, 4, n, st));
-        HIPCHK(launch_colsum<real>(r.da + (int64_t)(l - 1) * H, DH, m.B, H, part, ks,
-                                   gl + (int64_t)H * H, st));
+    HIPCHK(net->w_hid.ensure(std::max<int64_t>(1, htot) * sizeof(real)));
+    HIPCHK(net->w_da.ensure(std::max<int64_t>(1, htot) * sizeof(real)));
+    HIPCHK(net->w_dlogit.ensure(std::max<int64_t>(1, dtot) * sizeof(real)));
+    HIPCHK(net->w_sf.ensure(std::max<int64_t>(1, dtot) * sizeof(real)));
+    for (int q = 0; q < net->n_inst; ++q) {
+      const MadeInst &m = net->mi[q];
+      if (m.B <= 0) continue;
+      const int n = m.n, H = m.H;
+      // hidden layers run (deeper networks hold every layer in a row)
+      const int D = (net->deep && n >= 2 && H > 0) ? m.D : 1;
+      RowArgs<real> r{};
+      r.mi = m;
+      r.params = net->params.as<float>();
+      r.spins = spins + m.spin_off;
+      r.f = net->w_f.as<double>();
+      r.stats = stats + 4 * q;
+      r.chunk = std::max<int64_t>(16, ((m.B + 255) / 256 + 15) / 16 * 16);
+      r.hid = net->w_hid.as<real>() + hoff[q];
+      r.da = net->w_da.as<real>() + hoff[q];
+      r.dlogit = net->w_dlogit.as<real>() + doff[q];
+      r.sf = net->w_sf.as<real>() + doff[q];
+      if (net->deep) {
+        // rows of at most 4096 / H samples and about 48 KB of LDS per round
+        const size_t per = sizeof(real) * (2 * (size_t)n + (size_t)D * H + H);
+        // (8 rows per block and one round each: every sample's rows are
+        // independent, and the block count fills the CUs)
+        const int rb = (int)std::max<int64_t>(1, std::min<int64_t>({8, 4096 / std::max(1, H),
+                                                                    (int64_t)(49152 / per)}));
+        r.chunk = rb;
+        HIPCHK(launch_rows_deep<real>(r, rb, st));
+      } else if (net->h0) {
+        // the conditionals the sampler stored for these spins and parameters
+        r.sig = net->w_sig.as<real>() + m.spin_off;
+        HIPCHK(launch_rows_h0<real>(r, st));
+      } else {
+        HIPCHK(launch_rows<real>(r, st));
       }
     }
-    HIPCHK(launch_atb<real>(r.dlogit, n, r.sf, n, m.B, n, n, part, ks, gW0, n, 2, n, st));
-    HIPCHK(launch_colsum<real>(r.dlogit, n, m.B, n, part, ks, gb2, st));
+    BatchSums<real> bs{};
+    if (tnvan_status s2 = ensure_batch_sums<real>(net, hoff, doff, &bs)) return s2;
+    HIPCHK(launch_batch_sums<real>(bs, st));
   }
   }
   if (!fused) {
@@ -1805,6 +1899,8 @@ void tnvan_free_network(tnvan_net *net) {
                  &net->w_ostats, &net->w_odb, &net->fabp, &net->u_off,
                  &net->w_jar, &net->w_jexp, &net->d_jar_off, &net->d_jexp_off, &net->w_mmean,
                  &net->w_mvar, &net->w_oess, &net->w_mpart, &net->d_mskip,
+                 &net->bs_atb, &net->bs_col, &net->bs_alo, &net->bs_aflo, &net->bs_clo,
+                 &net->bs_cflo,
                  &net->f_off,
                  &net->mpack, &net->mtask_inst, &net->mtask_start, &net->mg_task_inst,
                  &net->mg_task_start, &net->mg_first, &net->mg_count,

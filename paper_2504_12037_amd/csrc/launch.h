@@ -229,6 +229,41 @@ hipError_t launch_atb(const real *X, int ldx, const real *Y, int ldy, int64_t B,
 template <typename real>
 hipError_t launch_colsum(const real *X, int ldx, int64_t B, int M, real *part,
                          int ksplit, float *out, hipStream_t st);
+// The batch sums of a whole REINFORCE backward, every instance and matrix in
+// one launch per kind: job j of launch_atb's arguments (part at part_off) or
+// of launch_colsum's; blo / clo: the jobs' first blocks of each kernel
+// (prefix sums, one more entry than jobs).  The same arithmetic per output
+// as the one-job launchers.
+template <typename real>
+struct AtbJob {
+  const real *X, *Y;
+  float *out;
+  int64_t part_off, B;
+  int32_t ldx, ldy, M, N, ks, ldo, mask, nW;
+};
+template <typename real>
+struct ColJob {
+  const real *X;
+  float *out;
+  int64_t part_off, B;
+  int32_t ldx, M, ks, pad;
+};
+template <typename real>
+struct BatchSums {
+  const AtbJob<real> *atb;
+  const int32_t *atb_lo, *atb_flo;   // atb blocks, finish blocks
+  int32_t n_atb;
+  const ColJob<real> *col;
+  const int32_t *col_lo, *col_flo;
+  int32_t n_col;
+  int32_t atb_blocks, atb_fblocks, col_blocks, col_fblocks;
+  real *part;
+};
+template <typename real>
+hipError_t launch_batch_sums(const BatchSums<real> &a, hipStream_t st);
+// blocks of one job: (atb, atb finish, colsum, colsum finish)
+void batch_sum_blocks(int M, int N, int ks, int32_t *atb, int32_t *fin);
+void batch_col_blocks(int M, int ks, int32_t *col, int32_t *fin);
 
 // Free energy statistics of every instance of the batch.
 template <typename real>

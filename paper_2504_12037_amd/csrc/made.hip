@@ -723,12 +723,11 @@ __global__ __launch_bounds__(256) void rows_h0_kernel(RowArgs<real> a) {
 // part[ks][m][n] = sum over batch rows of slice ks of X[b, m] * Y[b, n]
 constexpr int TM = 32, TN = 32, TK = 32;
 template <typename real>
-__global__ __launch_bounds__(256) void atb_kernel(const real *X, int ldx, const real *Y,
-                                                  int ldy, int64_t B, int M, int N,
-                                                  real *part, int ksplit) {
+__device__ inline void atb_block(const real *X, int ldx, const real *Y, int ldy, int64_t B, int M,
+                                 int N, real *part, int ksplit, int bx, int by, int ks) {
   __shared__ real xs[TK][TM + 1];
   __shared__ real ys[TK][TN + 1];
-  const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN, ks = blockIdx.z;
+  const int m0 = bx * TM, n0 = by * TN;
   const int64_t chunk = (B + ksplit - 1) / ksplit;
   const int64_t bb0 = (int64_t)ks * chunk;
   const int64_t bb1 = (bb0 + chunk) < B ? (bb0 + chunk) : B;
@@ -758,43 +757,56 @@ __global__ __launch_bounds__(256) void atb_kernel(const real *X, int ldx, const 
     }
 }
 
+template <typename real>
+__global__ __launch_bounds__(256) void atb_kernel(const real *X, int ldx, const real *Y,
+                                                  int ldy, int64_t B, int M, int N,
+                                                  real *part, int ksplit) {
+  atb_block<real>(X, ldx, Y, ldy, B, M, N, part, ksplit, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // out[m*ldo + n] = mask(m, n) * sum_ks part[ks][m][n]
 // mask kinds: 0 none, 1 W2 (n > deg(k)... (row i, col k): i+1 > deg(k)),
 //             2 W0 (col j < row i), 3 W1 (row k, col j): j+1 <= deg(k),
 //             4 deeper layers (row k', col k): deg(k) <= deg(k')
+// one output idx of the batch sum C = X^T Y: the slices in order, then the
+// mask of its matrix
+template <typename real>
+__device__ inline void atb_finish_one(const real *part, int ksplit, int M, int N, float *out,
+                                      int ldo, int mask_kind, int nW, int64_t idx) {
+  const int64_t tot = (int64_t)M * N;
+  const int m = (int)(idx / N), nn = (int)(idx % N);
+  // loads in batches of 8 (independent), additions in slice order
+  double acc = 0;
+  int k = 0;
+  for (; k + 8 <= ksplit; k += 8) {
+    real v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = part[(int64_t)(k + j) * tot + idx];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc += (double)v[j];
+  }
+  for (; k < ksplit; ++k) acc += (double)part[(int64_t)k * tot + idx];
+  bool keep = true;
+  if (mask_kind == 1) keep = nW >= 2 && (m + 1) > degree(nn, nW);
+  else if (mask_kind == 2) keep = nn < m;
+  else if (mask_kind == 3) keep = nW >= 2 && (nn + 1) <= degree(m, nW);
+  else if (mask_kind == 4) keep = nW >= 2 && degree(nn, nW) <= degree(m, nW);
+  out[(int64_t)m * ldo + nn] = keep ? (float)acc : 0.0f;
+}
+
 template <typename real>
 __global__ void atb_finish(const real *part, int ksplit, int M, int N, float *out,
                            int ldo, int mask_kind, int nW) {
   const int64_t tot = (int64_t)M * N;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int m = (int)(idx / N), nn = (int)(idx % N);
-    // loads in batches of 8 (independent), additions in slice order
-    double acc = 0;
-    int k = 0;
-    for (; k + 8 <= ksplit; k += 8) {
-      real v[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = part[(int64_t)(k + j) * tot + idx];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) acc += (double)v[j];
-    }
-    for (; k < ksplit; ++k) acc += (double)part[(int64_t)k * tot + idx];
-    bool keep = true;
-    if (mask_kind == 1) keep = nW >= 2 && (m + 1) > degree(nn, nW);
-    else if (mask_kind == 2) keep = nn < m;
-    else if (mask_kind == 3) keep = nW >= 2 && (nn + 1) <= degree(m, nW);
-    else if (mask_kind == 4) keep = nW >= 2 && degree(nn, nW) <= degree(m, nW);
-    out[(int64_t)m * ldo + nn] = keep ? (float)acc : 0.0f;
-  }
+       idx += (int64_t)gridDim.x * blockDim.x)
+    atb_finish_one<real>(part, ksplit, M, N, out, ldo, mask_kind, nW, idx);
 }
 
+// column m of batch slice ks
 template <typename real>
-__global__ void colsum_kernel(const real *X, int ldx, int64_t B, int M, real *part,
-                              int ksplit) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  const int ks = blockIdx.y;
-  if (m >= M) return;
+__device__ inline void colsum_one(const real *X, int ldx, int64_t B, int M, real *part,
+                                  int ksplit, int m, int ks) {
   const int64_t chunk = (B + ksplit - 1) / ksplit;
   const int64_t b0 = (int64_t)ks * chunk;
   const int64_t b1 = (b0 + chunk) < B ? (b0 + chunk) : B;
@@ -813,9 +825,15 @@ __global__ void colsum_kernel(const real *X, int ldx, int64_t B, int M, real *pa
 }
 
 template <typename real>
-__global__ void colsum_finish(const real *part, int ksplit, int M, float *out) {
+__global__ void colsum_kernel(const real *X, int ldx, int64_t B, int M, real *part,
+                              int ksplit) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= M) return;
+  colsum_one<real>(X, ldx, B, M, part, ksplit, m, blockIdx.y);
+}
+
+template <typename real>
+__device__ inline void colsum_finish_one(const real *part, int ksplit, int M, float *out, int m) {
   // loads in batches of 8 (independent), additions in slice order
   double acc = 0;
   int k = 0;
@@ -828,6 +846,58 @@ __global__ void colsum_finish(const real *part, int ksplit, int M, float *out) {
   }
   for (; k < ksplit; ++k) acc += (double)part[(int64_t)k * M + m];
   out[m] = (float)acc;
+}
+
+template <typename real>
+__global__ void colsum_finish(const real *part, int ksplit, int M, float *out) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  colsum_finish_one<real>(part, ksplit, M, out, m);
+}
+
+// The batched form: block b belongs to the last job whose first block is
+// at most b (a search over the prefix sums); inside its job it is the block
+// of the same index in the one-job launch's grid.
+__device__ inline int job_of(const int32_t *lo, int nj, int b) {
+  int a = 0, z = nj - 1;
+  while (a < z) {
+    const int mid = (a + z + 1) >> 1;
+    if (lo[mid] <= b) a = mid;
+    else z = mid - 1;
+  }
+  return a;
+}
+template <typename real>
+__global__ __launch_bounds__(256) void batch_atb_kernel(BatchSums<real> a) {
+  const int b = blockIdx.x, j = job_of(a.atb_lo, a.n_atb, b);
+  const AtbJob<real> J = a.atb[j];
+  const int t = b - a.atb_lo[j];
+  const int tm = (J.M + TM - 1) / TM, tn = (J.N + TN - 1) / TN;
+  atb_block<real>(J.X, J.ldx, J.Y, J.ldy, J.B, J.M, J.N, a.part + J.part_off, J.ks, t % tm,
+                  (t / tm) % tn, t / (tm * tn));
+}
+template <typename real>
+__global__ __launch_bounds__(256) void batch_atb_finish(BatchSums<real> a) {
+  const int b = blockIdx.x, j = job_of(a.atb_flo, a.n_atb, b);
+  const AtbJob<real> J = a.atb[j];
+  const int64_t idx = (int64_t)(b - a.atb_flo[j]) * blockDim.x + threadIdx.x;
+  if (idx < (int64_t)J.M * J.N)
+    atb_finish_one<real>(a.part + J.part_off, J.ks, J.M, J.N, J.out, J.ldo, J.mask, J.nW, idx);
+}
+template <typename real>
+__global__ __launch_bounds__(256) void batch_col_kernel(BatchSums<real> a) {
+  const int b = blockIdx.x, j = job_of(a.col_lo, a.n_col, b);
+  const ColJob<real> J = a.col[j];
+  const int t = b - a.col_lo[j], cm = (J.M + 255) / 256;
+  const int m = (t % cm) * 256 + threadIdx.x;
+  if (m < J.M) colsum_one<real>(J.X, J.ldx, J.B, J.M, a.part + J.part_off, J.ks, m, t / cm);
+}
+template <typename real>
+__global__ __launch_bounds__(256) void batch_col_finish(BatchSums<real> a) {
+  const int b = blockIdx.x, j = job_of(a.col_flo, a.n_col, b);
+  const ColJob<real> J = a.col[j];
+  const int m = (b - a.col_flo[j]) * 256 + threadIdx.x;
+  if (m < J.M) colsum_finish_one<real>(a.part + J.part_off, J.ks, J.M, J.out, m);
 }
 
 // f_b = E_1 - logZ_R / beta + ln q / beta (FP64, Eqs. 4 and 9) per sample and
@@ -2559,6 +2629,28 @@ hipError_t launch_colsum(const real *X, int ldx, int64_t B, int M, real *part, i
   return hipGetLastError();
 }
 
+void batch_sum_blocks(int M, int N, int ks, int32_t *atb, int32_t *fin) {
+  *atb = ((M + TM - 1) / TM) * ((N + TN - 1) / TN) * ks;
+  *fin = (int32_t)(((int64_t)M * N + 255) / 256);
+}
+void batch_col_blocks(int M, int ks, int32_t *col, int32_t *fin) {
+  *col = ((M + 255) / 256) * ks;
+  *fin = (M + 255) / 256;
+}
+
+template <typename real>
+hipError_t launch_batch_sums(const BatchSums<real> &a, hipStream_t st) {
+  if (a.n_atb > 0 && a.atb_blocks > 0) {
+    hipLaunchKernelGGL(batch_atb_kernel<real>, dim3(a.atb_blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(batch_atb_finish<real>, dim3(a.atb_fblocks), dim3(256), 0, st, a);
+  }
+  if (a.n_col > 0 && a.col_blocks > 0) {
+    hipLaunchKernelGGL(batch_col_kernel<real>, dim3(a.col_blocks), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(batch_col_finish<real>, dim3(a.col_fblocks), dim3(256), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
 template <typename real>
 hipError_t launch_free(const FreeArgs<real> &a, int n_inst, hipStream_t st) {
   if (n_inst <= 0) return hipSuccess;
@@ -2626,6 +2718,8 @@ template hipError_t launch_rows_h0<double>(const RowArgs<double> &, hipStream_t)
 template hipError_t launch_atb<float>(const float *, int, const float *, int, int64_t, int, int, float *, int, float *, int, int, int, hipStream_t);
 template hipError_t launch_atb<double>(const double *, int, const double *, int, int64_t, int, int, double *, int, float *, int, int, int, hipStream_t);
 template hipError_t launch_colsum<float>(const float *, int, int64_t, int, float *, int, float *, hipStream_t);
+template hipError_t launch_batch_sums<float>(const BatchSums<float> &, hipStream_t);
+template hipError_t launch_batch_sums<double>(const BatchSums<double> &, hipStream_t);
 template hipError_t launch_colsum<double>(const double *, int, int64_t, int, double *, int, float *, hipStream_t);
 template hipError_t launch_free<float>(const FreeArgs<float> &, int, hipStream_t);
 template hipError_t launch_free<double>(const FreeArgs<double> &, int, hipStream_t);
