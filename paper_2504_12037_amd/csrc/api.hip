@@ -844,7 +844,15 @@ tnvan_status run_logz(tnvan_net *net, const int8_t *spins, double *logz, hipStre
 // runs the register-resident chain kernels (their adjoint forward pass is the
 // forward kernel's arithmetic, so logz is the same as tnvan_logz_batch's)
 bool logz_with_adjoint(const tnvan_net *net) {
-  if (net->precision != TNVAN_FP32 || !net->rfwd || !net->rbwd) return false;
+  if (net->precision != TNVAN_FP32) return false;
+  // chain instances on the register-resident kernels, whose adjoint runs the
+  // forward kernel's arithmetic first; the general kernel's adjoint sweeps
+  // forward the same way as its forward pass
+  for (int q = 0; q < net->n_inst; ++q)
+    if (net->use_chain[q] && (!net->rfwd || !net->rbwd)) return false;
+  return true;
+}
+bool all_chains(const tnvan_net *net) {
   for (int q = 0; q < net->n_inst; ++q)
     if (!net->use_chain[q]) return false;
   return true;
@@ -875,6 +883,7 @@ tnvan_status run_backward(tnvan_net *net, const int8_t *spins, const double *gra
     a.arena_per_block = cap > 0;
   }
   a.pq = net->pq.as<int32_t>() + 2;
+  a.logz = logz;
   HIPCHK(launch_contract<real>(a, tc.n_tiles, net->lds_bwd, true, net->glob_bwd, st,
                                persistent(net) || cap > 0, cap));
   if (std::count(net->use_chain.begin(), net->use_chain.end(), 1)) {
@@ -1192,8 +1201,12 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
   // net allows it (one contraction instead of two), else it follows the step
   // (the free-energy kernel then sums the chain partials itself)
   const bool adj_logz = adj && logz_with_adjoint(net);
+  // (chain-only nets leave logZ as chain partials, which the free-energy
+  // kernel sums itself; with general instances the adjoint writes it out)
+  const bool cpart_logz = adj_logz && all_chains(net);
   if (adj_logz)
-    s = run_backward<real>(net, spins, adj->grad, adj->dh, adj->dJ, adj->dbeta, st);
+    s = run_backward<real>(net, spins, adj->grad, adj->dh, adj->dJ, adj->dbeta, st,
+                           cpart_logz ? nullptr : net->w_logz.as<double>());
   else
     s = run_logz<real>(net, spins, net->w_logz.as<double>(), st);
   if (s) return s;
@@ -1206,7 +1219,7 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
   f.hw_off = net->d_hw_off.as<int32_t>();
   f.spins = spins;
   f.logz = net->w_logz.as<double>();
-  if (adj_logz) {
+  if (cpart_logz) {
     f.cinst = net->cinst.as<ChainInst>();
     f.cpart_off = net->cpart_off.as<int64_t>();
     f.cpart = net->cpart.as<double>();

@@ -397,20 +397,23 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
     __syncthreads();
   }
 
-  if (!kBwd) {
+  // ln Z_R per sample: the forward kernel's result, and the adjoint's too
+  // when it is asked for (its forward sweep is the same arithmetic)
+  if (!kBwd || a.logz) {
     for (int s = tid; s < nb; s += kThreads) {
       double acc = D.log_const;
       for (int p = 0; p < D.nr; ++p) acc += (double)fab[p * S + s];
       int64_t esum = 0;
       for (int t = 0; t < D.n_steps; ++t) {
         const StepDesc sd = steps[t];
-        if (sd.w == 0) acc += log((double)arena[sd.off_fwd * S + s]);
+        if (sd.w == 0) acc += log((double)arena[(int64_t)(kBwd ? sd.off_all : sd.off_fwd) * S + s]);
         else esum += FB::expo(mx[t * S + s]);
       }
       acc += (double)esum * 0.69314718055994530942;
       a.logz[a.inst_sample_off[q] + b0 + s] = acc;
     }
-    return;
+    if (!kBwd) return;
+    __syncthreads();
   }
 
   // ------------------------------------------------------------ reverse
