@@ -844,7 +844,9 @@ tnvan_status run_logz(tnvan_net *net, const int8_t *spins, double *logz, hipStre
 // runs the register-resident chain kernels (their adjoint forward pass is the
 // forward kernel's arithmetic, so logz is the same as tnvan_logz_batch's)
 bool logz_with_adjoint(const tnvan_net *net) {
-  if (net->precision != TNVAN_FP32) return false;
+  // (BF16 nets: their forward rounds the step products to BF16, their
+  // adjoint does not, so logZ keeps its own pass)
+  if (net->precision == TNVAN_BF16) return false;
   // chain instances on the register-resident kernels, whose adjoint runs the
   // forward kernel's arithmetic first; the general kernel's adjoint sweeps
   // forward the same way as its forward pass
@@ -2344,7 +2346,10 @@ tnvan_status tnvan_logz_and_backward(tnvan_net *net, const int64_t *n_samples,
     return set_err(TNVAN_E_INVALID, "spins, grad_logz and logz are required");
   if (tnvan_status s = check_device({spins, grad, logz, dh, dJ, dbeta})) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (logz_with_adjoint(net)) return run_backward<float>(net, spins, grad, dh, dJ, dbeta, st, logz);
+  if (logz_with_adjoint(net))
+    return net->precision == TNVAN_FP64
+               ? run_backward<double>(net, spins, grad, dh, dJ, dbeta, st, logz)
+               : run_backward<float>(net, spins, grad, dh, dJ, dbeta, st, logz);
   if (net->precision == TNVAN_FP64) {
     if (tnvan_status s = run_logz<double>(net, spins, logz, st)) return s;
     return run_backward<double>(net, spins, grad, dh, dJ, dbeta, st);
