@@ -170,6 +170,11 @@ struct tnvan_net {
   DBuf bs_atb, bs_col, bs_alo, bs_aflo, bs_clo, bs_cflo;
   std::vector<int64_t> bkey;
   int32_t bs_counts[6] = {0, 0, 0, 0, 0, 0};
+  // jobs of the batched REINFORCE rows of one-layer nets, one launch per
+  // class of LDS need (kRowClasses): jobs, first blocks, counts, LDS bytes
+  DBuf rw_jobs[4], rw_lo[4];
+  int32_t rw_njobs[4] = {0, 0, 0, 0}, rw_blocks[4] = {0, 0, 0, 0};
+  size_t rw_lds[4] = {0, 0, 0, 0};
   DBuf garena, partial, w_logz, w_logq, w_spins, w_f, w_fpart, w_hid, w_da, w_dlogit, w_sf,
       w_part, d_hw_off, d_sum_off;
   int max_partial = 0, max_out = 1;
@@ -1154,7 +1159,46 @@ tnvan_status ensure_batch_sums(tnvan_net *net, const std::vector<int64_t> &hoff,
       atb(dl, n, sf, n, m.B, n, n, ks, gW0, n, 2, n);
       col(dl, n, m.B, n, ks, gb2);
     }
+    // one-layer nets: the per-sample rows, jobs in classes of LDS need
+    // (staged parameters <= 40 KB, <= 80 KB, <= the device's block limit,
+    // parameters read from global memory), one launch per class
+    std::vector<RowJob> rj[4];
+    std::vector<int32_t> rlo[4] = {{0}, {0}, {0}, {0}};
+    size_t rlds[4] = {0, 0, 0, 0};
+    if (!net->deep && !net->h0) {
+      int dev = 0, maxlds = 65536;
+      hipGetDevice(&dev);
+      (void)hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+      const size_t lim[3] = {40 * 1024, 80 * 1024, (size_t)maxlds};
+      for (int q = 0; q < net->n_inst; ++q) {
+        const MadeInst &m = net->mi[q];
+        if (m.B <= 0) continue;
+        const size_t need = rows_lds_bytes(m.n, m.H, sizeof(real), true);
+        int c = 0;
+        while (c < 3 && need > lim[c]) ++c;
+        const size_t lds = rows_lds_bytes(m.n, m.H, sizeof(real), c < 3);
+        // samples per block: one round of 16 for small parameter sets, up
+        // to four rounds per staging of the larger ones, and at most 256
+        // blocks per instance
+        const int64_t wb = (int64_t)(need - rows_lds_bytes(m.n, m.H, sizeof(real), false));
+        int64_t chunk = 16 * std::min<int64_t>(4, std::max<int64_t>(1, (wb + 32767) / 32768));
+        chunk = std::max<int64_t>(chunk, ((m.B + 255) / 256 + 15) / 16 * 16);
+        const int64_t blocks = (m.B + chunk - 1) / chunk;
+        if (rlo[c].back() + blocks > 0x7fffffff)
+          return set_err(TNVAN_E_INVALID, "instance %d: %lld rows blocks", q, (long long)blocks);
+        rj[c].push_back(RowJob{q, (int32_t)chunk, hoff[q], doff[q]});
+        rlo[c].push_back(rlo[c].back() + (int32_t)blocks);
+        rlds[c] = std::max(rlds[c], lds);
+      }
+    }
     if (tnvan_status s = quiesce(net)) return s;
+    for (int c = 0; c < 4; ++c) {
+      HIPCHK(upload(net->rw_jobs[c], rj[c]));
+      HIPCHK(upload(net->rw_lo[c], rlo[c]));
+      net->rw_njobs[c] = (int32_t)rj[c].size();
+      net->rw_blocks[c] = rlo[c].back();
+      net->rw_lds[c] = rlds[c];
+    }
     HIPCHK(upload(net->bs_atb, aj));
     HIPCHK(upload(net->bs_col, cj));
     HIPCHK(upload(net->bs_alo, alo));
@@ -1314,9 +1358,11 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
     HIPCHK(net->w_da.ensure(std::max<int64_t>(1, htot) * sizeof(real)));
     HIPCHK(net->w_dlogit.ensure(std::max<int64_t>(1, dtot) * sizeof(real)));
     HIPCHK(net->w_sf.ensure(std::max<int64_t>(1, dtot) * sizeof(real)));
+    BatchSums<real> bs{};
+    if (tnvan_status s2 = ensure_batch_sums<real>(net, hoff, doff, &bs)) return s2;
     for (int q = 0; q < net->n_inst; ++q) {
       const MadeInst &m = net->mi[q];
-      if (m.B <= 0) continue;
+      if (m.B <= 0 || !(net->deep || net->h0)) continue;
       const int n = m.n, H = m.H;
       // hidden layers run (deeper networks hold every layer in a row)
       const int D = (net->deep && n >= 2 && H > 0) ? m.D : 1;
@@ -1344,12 +1390,29 @@ tnvan_status run_step(tnvan_net *net, float lr, double *stats, int8_t *spins_out
         // the conditionals the sampler stored for these spins and parameters
         r.sig = net->w_sig.as<real>() + m.spin_off;
         HIPCHK(launch_rows_h0<real>(r, st));
-      } else {
-        HIPCHK(launch_rows<real>(r, st));
       }
     }
-    BatchSums<real> bs{};
-    if (tnvan_status s2 = ensure_batch_sums<real>(net, hoff, doff, &bs)) return s2;
+    if (!net->deep && !net->h0) {
+      RowBatch<real> rb{};
+      rb.mi = net->d_mi.as<MadeInst>();
+      rb.params = net->params.as<float>();
+      rb.spins = spins;
+      rb.f = net->w_f.as<double>();
+      rb.stats = stats;
+      rb.hid = net->w_hid.as<real>();
+      rb.da = net->w_da.as<real>();
+      rb.dlogit = net->w_dlogit.as<real>();
+      rb.sf = net->w_sf.as<real>();
+      // more waves per block where the LDS need leaves fewer blocks per CU
+      const int threads[4] = {256, 512, 1024, 1024};
+      for (int c = 0; c < 4; ++c) {
+        rb.jobs = net->rw_jobs[c].as<RowJob>();
+        rb.lo = net->rw_lo[c].as<int32_t>();
+        rb.n_jobs = net->rw_njobs[c];
+        rb.blocks = net->rw_blocks[c];
+        HIPCHK(launch_rows_batch<real>(rb, c < 3, net->rw_lds[c], threads[c], st));
+      }
+    }
     HIPCHK(launch_batch_sums<real>(bs, st));
   }
   }
@@ -1921,6 +1984,10 @@ void tnvan_free_network(tnvan_net *net) {
                  &net->mg_task_start, &net->mg_first, &net->mg_count,
                  &net->cpart_off, &net->chain_list, &net->cpart};
   for (DBuf *b : all) b->release();
+  for (int c = 0; c < 4; ++c) {
+    net->rw_jobs[c].release();
+    net->rw_lo[c].release();
+  }
   TileCache *tcs[] = {&net->tc_fwd, &net->tc_bwd};
   for (TileCache *tc : tcs) {
     tc->tile_inst.release(); tc->tile_start.release(); tc->first_tile.release();

@@ -211,8 +211,31 @@ struct RowArgs {
   real *sf;                // [B, n] spins as real
   const real *sig;         // one-layer nets: the sampler's conditionals [B, n]
 };
+// The rows of every instance in one launch: job j is one instance with its
+// chunk (samples per block) and its slices of the row buffers, and owns the
+// blocks [lo[j], lo[j + 1]).  `staged`: parameters staged in LDS; `threads`
+// per block, a multiple of 64 up to 1024.
+struct RowJob {
+  int32_t q, chunk;
+  int64_t hoff, doff;      // offsets into hid / da and into dlogit / sf
+};
 template <typename real>
-hipError_t launch_rows(const RowArgs<real> &a, hipStream_t st);
+struct RowBatch {
+  const MadeInst *mi;      // device, per instance
+  const float *params;
+  const int8_t *spins;     // every instance's spins (instance q at mi[q].spin_off)
+  const double *f;         // f_b per sample (global index)
+  const double *stats;     // [n_inst][4], F_q at [4 q]
+  const RowJob *jobs;
+  const int32_t *lo;       // [n_jobs + 1]
+  int32_t n_jobs, blocks;
+  real *hid, *da, *dlogit, *sf;
+};
+template <typename real>
+hipError_t launch_rows_batch(const RowBatch<real> &a, bool staged, size_t lds_bytes,
+                             int threads, hipStream_t st);
+// LDS bytes of one block of the batched rows for an (n, H) instance
+size_t rows_lds_bytes(int n, int H, size_t real_bytes, bool staged);
 // deeper networks: hid and da hold every layer, [B, D * H] (layer-major
 // inside a row); rb samples per block round
 template <typename real>

@@ -629,13 +629,29 @@ __global__ __launch_bounds__(256) void sample_h0_kernel(SampleArgs<real> a) {
 }
 
 // Per-sample rows of the log-prob pass and the REINFORCE backward:
+// The batched form: block b belongs to the last job whose first block is
+// at most b (a search over the prefix sums); inside its job it is the block
+// of the same index in the one-job launch's grid.
+__device__ inline int job_of(const int32_t *lo, int nj, int b) {
+  int a = 0, z = nj - 1;
+  while (a < z) {
+    const int mid = (a + z + 1) >> 1;
+    if (lo[mid] <= b) a = mid;
+    else z = mid - 1;
+  }
+  return a;
+}
+
 // a, tanh(a), logits, dlogit = w ((1+s)/2 - sigmoid(logit)) with the weight
-// w_b = (f_b - F_q) / B, and da = (dlogit . W2m) (1 - tanh^2).  A block walks
-// a chunk of samples in rounds of RB, with the parameters staged in LDS.
+// w_b = (f_b - F_q) / B, and da = (dlogit . W2m) (1 - tanh^2).  Block `blk`
+// of an instance walks its chunk of samples in rounds of RB, with the
+// parameters staged in LDS (kLDS).  Items run sample-fastest: the RB samples
+// of a round share each weight (one LDS or cache line per 16 lanes), and the
+// per-sample rows in LDS are padded by one entry against bank conflicts.
+// Every sum runs in ascending index order.
 constexpr int RB = 16;
 template <typename real, bool kLDS>
-__global__ __launch_bounds__(256) void rows_kernel(RowArgs<real> a) {
-  extern __shared__ __align__(16) char smem[];
+__device__ inline void rows_block(const RowArgs<real> &a, int64_t blk, char *smem) {
   const MadeInst mi = a.mi;
   const int n = mi.n, H = (n >= 2) ? mi.H : 0, Hs = mi.H;
   MadeView w = made_view(a.params + mi.param_off, n, Hs);
@@ -644,43 +660,49 @@ __global__ __launch_bounds__(256) void rows_kernel(RowArgs<real> a) {
     w = made_stage(w, n, Hs, reinterpret_cast<float *>(smem), false);
     woff = (made_stage_bytes(n, Hs) + 15) & ~(size_t)15;
   }
-  real *ss = reinterpret_cast<real *>(smem + woff);  // [RB][n]
-  real *hh = ss + RB * n;                            // [RB][H]
-  real *dl = hh + RB * Hs;                           // [RB][n]
+  const int ln = n + 1, lh = Hs + 1;
+  real *ss = reinterpret_cast<real *>(smem + woff);  // [RB][n + 1]
+  real *hh = ss + RB * ln;                           // [RB][H + 1]
+  real *dl = hh + RB * lh;                           // [RB][n + 1]
   const double Fq = a.stats[0];
   const double invB = 1.0 / (double)mi.B;
-  const int64_t c0 = (int64_t)blockIdx.x * a.chunk;
+  const int64_t c0 = blk * a.chunk;
   const int64_t c1 = (c0 + a.chunk) < mi.B ? (c0 + a.chunk) : mi.B;
   for (int64_t r0 = c0; r0 < c1; r0 += RB) {
     const int nr = (int)((c1 - r0) < RB ? (c1 - r0) : RB);
     const int8_t *sp = a.spins + r0 * n;
     for (int i = threadIdx.x; i < RB * n; i += blockDim.x) {
-      const int r = i / n;
-      ss[i] = r < nr ? (real)sp[i] : (real)0;
+      const int r = i / n, j = i - r * n;
+      ss[r * ln + j] = r < nr ? (real)sp[i] : (real)0;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < RB * Hs; i += blockDim.x) {
-      const int r = i / Hs, k = i % Hs;
+      const int k = i / RB, r = i - k * RB;
       real acc = 0;
       if (k < H) {
         acc = (real)w.b1[k];
         const int m = degree(k, n);
-        for (int j = 0; j < m; ++j) acc += (real)w.W1[(int64_t)k * w.ld1 + j] * ss[r * n + j];
+        for (int j = 0; j < m; ++j) acc += (real)w.W1[(int64_t)k * w.ld1 + j] * ss[r * ln + j];
         acc = rtanh<real>(acc);
       }
-      hh[i] = acc;
+      hh[r * lh + k] = acc;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < RB * n; i += blockDim.x) {
-      const int r = i / n, ii = i % n;
+      const int ii = i / RB, r = i - ii * RB;
       real z = (real)w.b2[ii];
-      for (int k = 0; k < H; ++k)
-        if (degree(k, n) <= ii) z += (real)w.W2[(int64_t)ii * w.ld2 + k] * hh[r * Hs + k];
-      for (int j = 0; j < ii; ++j) z += (real)w.W0[(int64_t)ii * w.ld0 + j] * ss[r * n + j];
-      const real s = ss[i];
+      // the units k with degree(k, n) = 1 + k mod (n - 1) <= ii: in every
+      // run of n - 1 units, the first ii
+      for (int base = 0; base < H; base += n - 1) {
+        const int e = ii < H - base ? ii : H - base;
+        for (int t = 0; t < e; ++t)
+          z += (real)w.W2[(int64_t)ii * w.ld2 + base + t] * hh[r * lh + base + t];
+      }
+      for (int j = 0; j < ii; ++j) z += (real)w.W0[(int64_t)ii * w.ld0 + j] * ss[r * ln + j];
+      const real s = ss[r * ln + ii];
       const real wt = r < nr ? (real)((a.f[mi.sample_off + r0 + r] - Fq) * invB) : (real)0;
       const real d = wt * (((real)1 + s) * (real)0.5 - sigmoid<real>(z));
-      dl[i] = d;
+      dl[r * ln + ii] = d;
       if (r < nr) {
         a.dlogit[(r0 + r) * n + ii] = d;
         a.sf[(r0 + r) * n + ii] = s;
@@ -688,13 +710,14 @@ __global__ __launch_bounds__(256) void rows_kernel(RowArgs<real> a) {
     }
     __syncthreads();
     for (int i = threadIdx.x; i < RB * Hs; i += blockDim.x) {
-      const int r = i / Hs, k = i % Hs;
+      const int k = i / RB, r = i - k * RB;
       if (r < nr) {
         real acc = 0;
-        const real hk = hh[i];
+        const real hk = hh[r * lh + k];
         if (k < H) {
           const int m = degree(k, n);
-          for (int ii = m; ii < n; ++ii) acc += dl[r * n + ii] * (real)w.W2[(int64_t)ii * w.ld2 + k];
+          for (int ii = m; ii < n; ++ii)
+            acc += dl[r * ln + ii] * (real)w.W2[(int64_t)ii * w.ld2 + k];
         }
         a.hid[(r0 + r) * Hs + k] = hk;
         a.da[(r0 + r) * Hs + k] = acc * ((real)1 - hk * hk);
@@ -702,6 +725,28 @@ __global__ __launch_bounds__(256) void rows_kernel(RowArgs<real> a) {
     }
     __syncthreads();
   }
+}
+
+// Every instance's rows in one launch: the block finds its job (a search
+// over the jobs' first blocks) and runs that instance's block of the same
+// index.
+template <typename real, bool kLDS>
+__global__ __launch_bounds__(1024) void rows_batch_kernel(RowBatch<real> b) {
+  extern __shared__ __align__(16) char smem[];
+  const int j = job_of(b.lo, b.n_jobs, blockIdx.x);
+  const RowJob J = b.jobs[j];
+  RowArgs<real> a{};
+  a.mi = b.mi[J.q];
+  a.params = b.params;
+  a.spins = b.spins + a.mi.spin_off;
+  a.f = b.f;
+  a.stats = b.stats + 4 * (int64_t)J.q;
+  a.chunk = J.chunk;
+  a.hid = b.hid + J.hoff;
+  a.da = b.da + J.hoff;
+  a.dlogit = b.dlogit + J.doff;
+  a.sf = b.sf + J.doff;
+  rows_block<real, kLDS>(a, (int64_t)blockIdx.x - b.lo[j], smem);
 }
 
 // The rows of the REINFORCE backward for one-layer nets: dlogit = w_b
@@ -855,18 +900,6 @@ __global__ void colsum_finish(const real *part, int ksplit, int M, float *out) {
   colsum_finish_one<real>(part, ksplit, M, out, m);
 }
 
-// The batched form: block b belongs to the last job whose first block is
-// at most b (a search over the prefix sums); inside its job it is the block
-// of the same index in the one-job launch's grid.
-__device__ inline int job_of(const int32_t *lo, int nj, int b) {
-  int a = 0, z = nj - 1;
-  while (a < z) {
-    const int mid = (a + z + 1) >> 1;
-    if (lo[mid] <= b) a = mid;
-    else z = mid - 1;
-  }
-  return a;
-}
 template <typename real>
 __global__ __launch_bounds__(256) void batch_atb_kernel(BatchSums<real> a) {
   const int b = blockIdx.x, j = job_of(a.atb_lo, a.n_atb, b);
@@ -2560,21 +2593,27 @@ hipError_t launch_rows_h0(const RowArgs<real> &a, hipStream_t st) {
   return hipGetLastError();
 }
 
+size_t rows_lds_bytes(int n, int H, size_t real_bytes, bool staged) {
+  const size_t rows = real_bytes * (size_t)RB * (2 * ((size_t)n + 1) + H + 1);
+  return rows + (staged ? (made_param_bytes(n, H) + 15) & ~(size_t)15 : 0);
+}
+
 template <typename real>
-hipError_t launch_rows(const RowArgs<real> &a, hipStream_t st) {
-  if (a.mi.B <= 0) return hipSuccess;
-  const int64_t blocks = (a.mi.B + a.chunk - 1) / a.chunk;
-  const size_t rows = sizeof(real) * (size_t)RB * (2 * a.mi.n + a.mi.H);
-  const size_t wb = (made_param_bytes(a.mi.n, a.mi.H) + 15) & ~(size_t)15;
-  if (wb + rows <= kStageMax) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(rows_kernel<real, true>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(wb + rows));
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((rows_kernel<real, true>), dim3(blocks), dim3(256), wb + rows, st, a);
-  } else {
-    hipLaunchKernelGGL((rows_kernel<real, false>), dim3(blocks), dim3(256), rows, st, a);
-  }
+hipError_t launch_rows_batch(const RowBatch<real> &a, bool staged, size_t lds_bytes,
+                             int threads, hipStream_t st) {
+  if (a.n_jobs <= 0 || a.blocks <= 0) return hipSuccess;
+  if (threads < 64 || threads > 1024 || threads % 64) return hipErrorInvalidValue;
+  const void *k = staged ? reinterpret_cast<const void *>(rows_batch_kernel<real, true>)
+                         : reinterpret_cast<const void *>(rows_batch_kernel<real, false>);
+  hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds_bytes);
+  if (e != hipSuccess) return e;
+  if (staged)
+    hipLaunchKernelGGL((rows_batch_kernel<real, true>), dim3(a.blocks), dim3(threads), lds_bytes,
+                       st, a);
+  else
+    hipLaunchKernelGGL((rows_batch_kernel<real, false>), dim3(a.blocks), dim3(threads), lds_bytes,
+                       st, a);
   return hipGetLastError();
 }
 
@@ -2711,8 +2750,10 @@ template hipError_t launch_rows_deep<float>(const RowArgs<float> &, int, hipStre
 template hipError_t launch_rows_deep<double>(const RowArgs<double> &, int, hipStream_t);
 template hipError_t launch_sample_h0<float>(const SampleArgs<float> &, int, int64_t, int, hipStream_t);
 template hipError_t launch_sample_h0<double>(const SampleArgs<double> &, int, int64_t, int, hipStream_t);
-template hipError_t launch_rows<float>(const RowArgs<float> &, hipStream_t);
-template hipError_t launch_rows<double>(const RowArgs<double> &, hipStream_t);
+template hipError_t launch_rows_batch<float>(const RowBatch<float> &, bool, size_t, int,
+                                             hipStream_t);
+template hipError_t launch_rows_batch<double>(const RowBatch<double> &, bool, size_t, int,
+                                              hipStream_t);
 template hipError_t launch_rows_h0<float>(const RowArgs<float> &, hipStream_t);
 template hipError_t launch_rows_h0<double>(const RowArgs<double> &, hipStream_t);
 template hipError_t launch_atb<float>(const float *, int, const float *, int, int64_t, int, int, float *, int, float *, int, int, int, hipStream_t);
