@@ -329,7 +329,9 @@ struct ProfScope {
 // Samples per tile S of the general-step kernel (a power of two <= 64).
 // Default rule: the largest S whose tile, arena included, fits the LDS
 // budget (80 KB, two workgroups per CU); below 4 the arena moves to global
-// memory and S is the largest <= 16 that fits.  A requested S (tuning) is
+// memory and S is the largest <= 8 that fits (more, smaller workgroups hide
+// the arena's latency better: the 64-instance batch's adjoint step took
+// 15.7 ms at 8, 19.1 ms at 16).  A requested S (tuning) is
 // taken with the arena in LDS when it fits the whole LDS, else in global
 // memory; false when even that does not fit.
 bool choose_tiles(tnvan_net *net, bool bwd, int req = 0) {
@@ -371,7 +373,7 @@ bool choose_tiles(tnvan_net *net, bool bwd, int req = 0) {
     if (S < 4) {
       glob = true;
       for (S = 64; S >= 1; S >>= 1)
-        if (worst_of(S, true) <= budget && S <= 16) break;
+        if (worst_of(S, true) <= budget && S <= 8) break;
       if (S < 1) S = 1;
     }
   }
@@ -988,8 +990,14 @@ tnvan_status ensure_sample_blocks(tnvan_net *net) {
   const int spb = 256 / net->mi[0].L;
   int64_t groups = 0;
   for (int q = 0; q < net->n_inst; ++q) groups += (net->nkey[q] + spb - 1) / spb;
-  // a few rounds per block so that each block stages its parameters once
-  net->sample_reps = (int)std::max<int64_t>(1, (groups + 511) / 512);
+  // a few rounds per block so that each block stages its parameters once;
+  // parameters too large to stage are read from global memory, and then
+  // more, shorter blocks keep more waves in flight (the sampler is bound by
+  // the latency of its position-by-position chain)
+  size_t stage = 0;
+  for (auto &m : net->mi) stage = std::max(stage, made_param_bytes(m.n, m.H));
+  const int64_t target = stage <= made_stage_max() ? 512 : 8192;
+  net->sample_reps = (int)std::max<int64_t>(1, (groups + target - 1) / target);
   const int64_t per_block = (int64_t)spb * net->sample_reps;
   for (int q = 0; q < net->n_inst; ++q) {
     for (int64_t b = 0; b < net->nkey[q]; b += per_block) {

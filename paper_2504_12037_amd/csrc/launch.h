@@ -139,6 +139,8 @@ template <typename real>
 hipError_t launch_sample_h0(const SampleArgs<real> &a, int n_inst, int64_t max_B, int max_n,
                             hipStream_t st);
 size_t made_param_bytes(int n, int H);
+// the largest parameter set the general sampler stages in LDS
+size_t made_stage_max();
 
 // Deeper networks (some instance with D > 1 hidden layers): one wave per
 // sample for every instance, a lane owning hidden units lane + 64 kk and

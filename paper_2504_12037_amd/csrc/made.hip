@@ -2477,6 +2477,7 @@ void (*pick_mgrad(int ht))(MGradArgs) {
 constexpr size_t kStageMax = 96 * 1024;
 
 size_t made_param_bytes(int n, int H) { return made_stage_bytes(n, H); }
+size_t made_stage_max() { return kStageMax; }
 
 int64_t made_pack_floats(int n, int npt, int H) { return mpack_floats(n, npt, H); }
 int64_t made_w2t_offset(int n, int npt) { return msample_floats(n, npt); }
