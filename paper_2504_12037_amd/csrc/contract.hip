@@ -63,6 +63,18 @@ template <> struct FBits<double> {
   }
 };
 
+// A load of a table the kernel only reads, at a workgroup-uniform address:
+// through the constant address space it becomes a scalar load (one per
+// wave, into scalar registers), and what is derived from it stays scalar
+// (loop bounds, offsets, branches).  The tables are written only between
+// launches.
+template <typename T>
+__device__ inline T uload(const T *p) {
+  T v;
+  __builtin_memcpy(&v, (const __attribute__((address_space(4))) T *)p, sizeof(T));
+  return v;
+}
+
 struct Layout {
   size_t mx, phi, fab, gs, M, C, red, res, pb, arena, scr, end;
 };
@@ -131,8 +143,8 @@ __device__ inline FastIn<real> fast_inputs(const ContractArgs<real> &a, const St
 #pragma unroll
   for (int k = 0; k < kFastIn; ++k) {
     if (k < sd.n_in) {
-      const InputDesc id = a.inputs[sd.in_off + k];
-      const StepDesc ps = steps[id.step];
+      const InputDesc id = uload(a.inputs + sd.in_off + k);
+      const StepDesc ps = uload(steps + id.step);
       f.ioff[k] = kBwd ? ps.off_all : ps.off_fwd;
       f.xs[k] = 1 << id.xbit;
       f.gb[k] = a.gtab + id.gb_off;
@@ -204,8 +216,8 @@ __device__ inline WideIn<real> wide_inputs(const ContractArgs<real> &a, const St
 #pragma unroll
   for (int k = 0; k < kWideIn; ++k) {
     if (k < sd.n_in) {
-      const InputDesc id = a.inputs[sd.in_off + k];
-      const StepDesc ps = steps[id.step];
+      const InputDesc id = uload(a.inputs + sd.in_off + k);
+      const StepDesc ps = uload(steps + id.step);
       f.ioff[k] = kBwd ? ps.off_all : ps.off_fwd;
       f.xs[k] = 1 << id.xbit;
       f.lo[k] = a.gtab2 + id.gb_off;
@@ -221,8 +233,8 @@ __device__ inline WideIn<real> wide_inputs(const ContractArgs<real> &a, const St
 #pragma unroll
   for (int e = 0; e < kWideEdges; ++e) {
     if (e < sd.n_edge) {
-      f.eb[e] = a.edges[sd.edge_off + e].bv;
-      f.es[e] = a.esmall[sd.edge_off + e];
+      f.eb[e] = uload(a.edges + sd.edge_off + e).bv;
+      f.es[e] = uload(a.esmall + sd.edge_off + e);
     } else {
       f.eb[e] = 0;
       f.es[e] = (real)1;
@@ -265,11 +277,11 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
   using FB = FBits<real>;
   using U = typename FB::U;
   const int tid = threadIdx.x;
-  const int q = a.tile_inst[tile];
-  const InstDesc D = a.inst[q];
+  const int q = uload(a.tile_inst + tile);
+  const InstDesc D = uload(a.inst + q);
   const int S = a.S, logS = a.logS;
-  const int64_t b0 = a.tile_start[tile];
-  const int64_t Bq = a.inst_B[q];
+  const int64_t b0 = uload(a.tile_start + tile);
+  const int64_t Bq = uload(a.inst_B + q);
   const int nb = (int)((Bq - b0) < S ? (Bq - b0) : S);
   const int sme = tid & (S - 1);
   const Layout Lo = make_layout(D, S, kBwd, kGlobal, (int)sizeof(real));
@@ -288,7 +300,7 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
     scr = reinterpret_cast<real *>(smem + Lo.scr);
   }
   const StepDesc *steps = a.steps + D.step_off;
-  const int8_t *spq = a.spins + a.inst_spin_off[q];
+  const int8_t *spq = a.spins + uload(a.inst_spin_off + q);
   const real beta = (real)D.beta;
 
   for (int i = tid; i < D.n_steps * S; i += kThreads) mx[i] = 0;
@@ -313,7 +325,7 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
 
   // ------------------------------------------------------------ forward
   for (int t = 0; t < D.n_steps; ++t) {
-    const StepDesc sd = steps[t];
+    const StepDesc sd = uload(steps + t);
     const int w = sd.w, g = sd.g;
     const int off = kBwd ? sd.off_all : sd.off_fwd;
     const real *Tt = a.T + (sd.t_off >= 0 ? sd.t_off : 0);
@@ -322,8 +334,8 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
       int inoff = 0;
       real insc = 1;
       if (sd.n_in) {
-        const InputDesc id = a.inputs[sd.in_off];
-        const StepDesc ps = steps[id.step];
+        const InputDesc id = uload(a.inputs + sd.in_off);
+        const StepDesc ps = uload(steps + id.step);
         inoff = kBwd ? ps.off_all : ps.off_fwd;
         insc = FB::scale(FB::expo(mx[id.step * S + sme]));
       }
@@ -405,7 +417,7 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
       for (int p = 0; p < D.nr; ++p) acc += (double)fab[p * S + s];
       int64_t esum = 0;
       for (int t = 0; t < D.n_steps; ++t) {
-        const StepDesc sd = steps[t];
+        const StepDesc sd = uload(steps + t);
         if (sd.w == 0) acc += log((double)arena[(int64_t)(kBwd ? sd.off_all : sd.off_fwd) * S + s]);
         else esum += FB::expo(mx[t * S + s]);
       }
@@ -430,7 +442,7 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
   const int lane = tid & 63, wave = tid >> 6;
 
   for (int t = D.n_steps - 1; t >= 0; --t) {
-    const StepDesc sd = steps[t];
+    const StepDesc sd = uload(steps + t);
     const int w = sd.w, g = sd.g;
     const int off = sd.off_all;
     const real *Tt = a.T + (sd.t_off >= 0 ? sd.t_off : 0);
@@ -446,8 +458,8 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
       int inoff = 0;
       real insc = 1;
       if (sd.n_in) {
-        const InputDesc id = a.inputs[sd.in_off];
-        inoff = steps[id.step].off_all;
+        const InputDesc id = uload(a.inputs + sd.in_off);
+        inoff = uload(steps + id.step).off_all;
         insc = FB::scale(FB::expo(mx[id.step * S + sme]));
       }
       real *sA = scr;                 // [x][S]
@@ -571,8 +583,8 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
       __syncthreads();
       // rho of every input: marginal of its scope over its scaled value
       for (int k = 0; k < sd.n_in; ++k) {
-        const InputDesc id = a.inputs[sd.in_off + k];
-        const StepDesc ps = steps[id.step];
+        const InputDesc id = uload(a.inputs + sd.in_off + k);
+        const StepDesc ps = uload(steps + id.step);
         const real sc = FB::scale(FB::expo(mx[id.step * S + sme]));
         const int omask = id.omask;
         const int freem = ((1 << w) - 1) & ~omask;
@@ -643,7 +655,7 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
         for (int r = 0; r < kRed; ++r) {
           v[r] = 0;
           const int k = c0 + r;
-          ob[r] = (k == 0 || k >= K) ? -1 : a.edges[sd.edge_off + k - 1].bv;
+          ob[r] = (k == 0 || k >= K) ? -1 : uload(a.edges + sd.edge_off + k - 1).bv;
         }
         for (int i = tid; i < (S << w); i += kThreads) {
           const int o = i >> logS;
@@ -719,7 +731,7 @@ __global__ __launch_bounds__(kThreads) void contract_pq_kernel(ContractArgs<real
     __syncthreads();   // every thread has read `next` and left the last tile
     if (threadIdx.x == 0) next = atomicAdd(a.pq, 1);
     __syncthreads();
-    const int tile = next;
+    const int tile = __builtin_amdgcn_readfirstlane(next);   // the same in every lane
     if (tile >= n_tiles) break;
     contract_tile<real, kGlobal, kBwd, kWide>(a, tile, smem);
   }
