@@ -76,7 +76,7 @@ __device__ inline T uload(const T *p) {
 }
 
 struct Layout {
-  size_t mx, phi, fab, gs, M, C, red, res, pb, arena, scr, end;
+  size_t mx, phi, fab, gs, M, C, red, pb, arena, scr, end;
 };
 
 __host__ __device__ inline size_t al8(size_t x) { return (x + 7) & ~(size_t)7; }
@@ -94,7 +94,6 @@ __host__ __device__ inline Layout make_layout(const InstDesc &D, int S, bool bwd
     L.M = o;   o = al8(o + (size_t)D.nr * S * rs);
     L.C = o;   o = al8(o + (size_t)D.n_rr * rs);
     L.red = o; o = al8(o + (size_t)kWaves * kRed * S * rs);
-    L.res = o; o = al8(o + (size_t)kRed * S * rs);
     L.pb = o;  o = al8(o + (size_t)D.pbuf * rs);
   }
   if (!global_arena) {
@@ -433,7 +432,6 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
   real *Mg = reinterpret_cast<real *>(smem + Lo.M);
   real *Cw = reinterpret_cast<real *>(smem + Lo.C);
   real *red = reinterpret_cast<real *>(smem + Lo.red);
-  real *res = reinterpret_cast<real *>(smem + Lo.res);
   real *pb = reinterpret_cast<real *>(smem + Lo.pb);
   for (int s = tid; s < S; s += kThreads)
     gs[s] = s < nb ? (real)a.grad[a.inst_sample_off[q] + b0 + s] : (real)0;
@@ -672,24 +670,25 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
           for (int r = 0; r < kRed; ++r) red[(wave * kRed + r) * S + lane] = v[r];
         }
         __syncthreads();
-        for (int i = tid; i < kRed * S; i += kThreads) {
+        // value r of sample s: the waves' parts added in wave order, read
+        // where it is used (no second pass through LDS)
+        auto wsum = [&](int i) {
           real sum = 0;
           for (int wv = 0; wv < kWaves; ++wv) sum += red[(wv * kRed) * S + i];
-          res[i] = sum;
-        }
-        __syncthreads();
+          return sum;
+        };
         for (int r = tid; r < kRed; r += kThreads) {
           const int k = c0 + r;
           if (k == 0) {
             // handled below (per sample)
           } else if (k < K) {
             real acc = 0;
-            for (int s = 0; s < S; ++s) acc += gs[s] * res[r * S + s];
+            for (int s = 0; s < S; ++s) acc += gs[s] * wsum(r * S + s);
             Cw[a.edges[sd.edge_off + k - 1].rr] = acc;
           }
         }
         if (c0 == 0)
-          for (int s = tid; s < S; s += kThreads) Mg[sd.gpos * S + s] = res[s];
+          for (int s = tid; s < S; s += kThreads) Mg[sd.gpos * S + s] = wsum(s);
         __syncthreads();
       }
     }
