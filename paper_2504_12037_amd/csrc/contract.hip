@@ -37,6 +37,7 @@ constexpr int kThreads = 256;
 constexpr int kLogThreads = 8;
 constexpr int kWaves = kThreads / 64;
 constexpr int kRed = 4;         // values per column reduction pass
+constexpr int kJoint = 2;       // output entries per thread and pass of a single-spin step
 
 template <typename real> struct FBits;
 template <> struct FBits<float> {
@@ -177,15 +178,28 @@ template <typename real, int NI>
 __device__ inline real fast_fwd(const FastIn<real> &f, const real *Tt, int w, real ph0, real ph1,
                                 real *arena, int off, int S, int logS, int sme, int tid) {
   real lmax = 0;
-  for (int i = tid; i < (S << w); i += kThreads) {
-    const int o = i >> logS;
-    real p0 = Tt[o] * ph0, p1 = Tt[(1 << w) | o] * ph1;
-    fast_pair<real, NI>(f, arena, S, sme, o, p0, p1);
-    real acc = 0;
-    acc += p0;
-    acc += p1;
-    arena[(off + o) * S + sme] = acc;
-    lmax = acc > lmax ? acc : lmax;
+  // kJoint entries per pass: every entry's loads before any store
+  const int n = S << w;
+  for (int i = tid; i < n; i += kJoint * kThreads) {
+    real p0[kJoint], p1[kJoint];
+    int ov[kJoint];
+#pragma unroll
+    for (int u = 0; u < kJoint; ++u) {
+      const int iu = i + u * kThreads;
+      ov[u] = (iu < n ? iu : i) >> logS;
+      p0[u] = Tt[ov[u]] * ph0;
+      p1[u] = Tt[(1 << w) | ov[u]] * ph1;
+      fast_pair<real, NI>(f, arena, S, sme, ov[u], p0[u], p1[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kJoint; ++u) {
+      if (i + u * kThreads >= n) break;
+      real acc = 0;
+      acc += p0[u];
+      acc += p1[u];
+      arena[(off + ov[u]) * S + sme] = acc;
+      lmax = acc > lmax ? acc : lmax;
+    }
   }
   return lmax;
 }
@@ -547,13 +561,26 @@ __device__ inline void contract_tile(const ContractArgs<real> &a, const int tile
         const real ph0 = phi[(2 * sd.gpos) * S + sme], ph1 = phi[(2 * sd.gpos + 1) * S + sme];
         auto joint = [&](auto ni) {
           constexpr int NI = decltype(ni)::value;
-          for (int i = tid; i < (S << w); i += kThreads) {
-            const int o = i >> logS;
-            const real r = rfac(o);
-            real p0 = r * Tt[o] * ph0, p1 = r * Tt[(1 << w) | o] * ph1;
-            fast_pair<real, NI>(f, arena, S, sme, o, p0, p1);
-            scr[(o * 2) * S + sme] = p0;
-            scr[(o * 2 + 1) * S + sme] = p1;
+          // kJoint entries per pass: every entry's loads before any store
+          const int n = S << w;
+          for (int i = tid; i < n; i += kJoint * kThreads) {
+            real p0[kJoint], p1[kJoint];
+            int ov[kJoint];
+#pragma unroll
+            for (int u = 0; u < kJoint; ++u) {
+              const int iu = i + u * kThreads;
+              ov[u] = (iu < n ? iu : i) >> logS;
+              const real r = rfac(ov[u]);
+              p0[u] = r * Tt[ov[u]] * ph0;
+              p1[u] = r * Tt[(1 << w) | ov[u]] * ph1;
+              fast_pair<real, NI>(f, arena, S, sme, ov[u], p0[u], p1[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < kJoint; ++u) {
+              if (i + u * kThreads >= n) break;
+              scr[(ov[u] * 2) * S + sme] = p0[u];
+              scr[(ov[u] * 2 + 1) * S + sme] = p1[u];
+            }
           }
         };
         switch (sd.n_in) {
