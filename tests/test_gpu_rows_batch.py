@@ -2,7 +2,10 @@
 (parameters staged in LDS up to 40 KB, up to 80 KB, up to the block limit,
 and read from global memory above it) through the C ABI: one training step
 on a net with an instance in each class and uneven batches whose last block
-is partial, gradient of Eq. (10) against the FP64 oracle per instance."""
+is partial, gradient of Eq. (10) against the FP64 oracle per instance.  The
+same step's spins pin the general sampler with its parameters read from
+global memory (one round of samples per block) against the oracle's Eq. (8)
+given the Philox uniforms."""
 
 import numpy as np
 import pytest
@@ -11,6 +14,7 @@ import synthetic as S
 from oracle import ising as OI
 from oracle import made as OM
 from oracle import objective as OO
+from oracle import philox as OP
 from synthetic.instances import Instance
 
 torch = pytest.importorskip("torch")
@@ -56,8 +60,17 @@ def test_rows_of_every_lds_class_against_the_oracle(prec):
         sp = sp_all[off:off + b * n].reshape(b, n)
         off += b * n
         th64 = thetas[k].astype(np.float64)
-        # the rows take the spins the sampler drew (its parity is tested
-        # on its own)
+        # the sampler: the oracle's draws from the same uniforms, with the
+        # GPU's spin forced only where the conditional is within 1e-6 of
+        # the uniform (FP32 against FP64 rounding)
+        u = OP.sampler_uniforms(seed, 0, k, b, n)
+        s_o, _, pr = OM.sample(th64, u, n, H)
+        tie = np.abs(pr - u) < 1e-6
+        if tie.any():
+            force = np.zeros((b, n), np.int8)
+            force[tie] = sp[tie]
+            s_o, _, pr = OM.sample(th64, u, n, H, force=force)
+        assert np.array_equal(s_o, sp), (inst.name, np.argwhere(s_o != sp)[:5])
         lq = OM.logq(th64, sp, n, H)
         lz = OI.logz_r_elimination(inst, sp)
         f, _ = OO.free_energy_terms(inst, sp, lq, lz)
