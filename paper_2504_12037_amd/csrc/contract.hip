@@ -28,6 +28,7 @@
 #include <type_traits>
 
 #include "launch.h"
+#include "uload.h"
 
 namespace tnvan {
 
@@ -63,18 +64,6 @@ template <> struct FBits<double> {
     return __longlong_as_double((long long)((unsigned long long)(1023 - e) << 52));
   }
 };
-
-// A load of a table the kernel only reads, at a workgroup-uniform address:
-// through the constant address space it becomes a scalar load (one per
-// wave, into scalar registers), and what is derived from it stays scalar
-// (loop bounds, offsets, branches).  The tables are written only between
-// launches.
-template <typename T>
-__device__ inline T uload(const T *p) {
-  T v;
-  __builtin_memcpy(&v, (const __attribute__((address_space(4))) T *)p, sizeof(T));
-  return v;
-}
 
 struct Layout {
   size_t mx, phi, fab, gs, M, C, red, pb, arena, scr, end;

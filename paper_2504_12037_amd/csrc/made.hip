@@ -13,6 +13,7 @@
 #include <algorithm>
 
 #include "launch.h"
+#include "uload.h"
 #include "wave.h"
 
 namespace tnvan {
@@ -146,8 +147,8 @@ __device__ inline MadeView made_stage(const MadeView g, int n, int H, float *s, 
 template <typename real, bool kLDS>
 __global__ __launch_bounds__(256) void sample_kernel(SampleArgs<real> a) {
   extern __shared__ __align__(16) char smem[];
-  const int q = a.blk_inst[blockIdx.x];
-  const MadeInst mi = a.mi[q];
+  const int q = uload(a.blk_inst + blockIdx.x);
+  const MadeInst mi = uload(a.mi + q);
   const int L = mi.L;
   const int grp = threadIdx.x / L, l = threadIdx.x % L;
   const int n = mi.n, Hs = mi.H, H = (n >= 2) ? mi.H : 0;
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(256) void sample_kernel(SampleArgs<real> a) {
     dg[kk] = k < H ? degree(k, n) : 0;
   }
   for (int rep = 0; rep < a.reps; ++rep) {
-    const int64_t b = a.blk_start[blockIdx.x] + (int64_t)rep * a.spb + grp;
+    const int64_t b = uload(a.blk_start + blockIdx.x) + (int64_t)rep * a.spb + grp;
     const bool live = grp < a.spb && b < mi.B;
     real av[KH], hv[KH], sv[KN];
 #pragma unroll
@@ -636,7 +637,7 @@ __device__ inline int job_of(const int32_t *lo, int nj, int b) {
   int a = 0, z = nj - 1;
   while (a < z) {
     const int mid = (a + z + 1) >> 1;
-    if (lo[mid] <= b) a = mid;
+    if (uload(lo + mid) <= b) a = mid;
     else z = mid - 1;
   }
   return a;
@@ -734,9 +735,9 @@ template <typename real, bool kLDS>
 __global__ __launch_bounds__(1024) void rows_batch_kernel(RowBatch<real> b) {
   extern __shared__ __align__(16) char smem[];
   const int j = job_of(b.lo, b.n_jobs, blockIdx.x);
-  const RowJob J = b.jobs[j];
+  const RowJob J = uload(b.jobs + j);
   RowArgs<real> a{};
-  a.mi = b.mi[J.q];
+  a.mi = uload(b.mi + J.q);
   a.params = b.params;
   a.spins = b.spins + a.mi.spin_off;
   a.f = b.f;
@@ -746,7 +747,7 @@ __global__ __launch_bounds__(1024) void rows_batch_kernel(RowBatch<real> b) {
   a.da = b.da + J.hoff;
   a.dlogit = b.dlogit + J.doff;
   a.sf = b.sf + J.doff;
-  rows_block<real, kLDS>(a, (int64_t)blockIdx.x - b.lo[j], smem);
+  rows_block<real, kLDS>(a, (int64_t)blockIdx.x - uload(b.lo + j), smem);
 }
 
 // The rows of the REINFORCE backward for one-layer nets: dlogit = w_b
@@ -903,8 +904,8 @@ __global__ void colsum_finish(const real *part, int ksplit, int M, float *out) {
 template <typename real>
 __global__ __launch_bounds__(256) void batch_atb_kernel(BatchSums<real> a) {
   const int b = blockIdx.x, j = job_of(a.atb_lo, a.n_atb, b);
-  const AtbJob<real> J = a.atb[j];
-  const int t = b - a.atb_lo[j];
+  const AtbJob<real> J = uload(a.atb + j);
+  const int t = b - uload(a.atb_lo + j);
   const int tm = (J.M + TM - 1) / TM, tn = (J.N + TN - 1) / TN;
   atb_block<real>(J.X, J.ldx, J.Y, J.ldy, J.B, J.M, J.N, a.part + J.part_off, J.ks, t % tm,
                   (t / tm) % tn, t / (tm * tn));
@@ -912,24 +913,24 @@ __global__ __launch_bounds__(256) void batch_atb_kernel(BatchSums<real> a) {
 template <typename real>
 __global__ __launch_bounds__(256) void batch_atb_finish(BatchSums<real> a) {
   const int b = blockIdx.x, j = job_of(a.atb_flo, a.n_atb, b);
-  const AtbJob<real> J = a.atb[j];
-  const int64_t idx = (int64_t)(b - a.atb_flo[j]) * blockDim.x + threadIdx.x;
+  const AtbJob<real> J = uload(a.atb + j);
+  const int64_t idx = (int64_t)(b - uload(a.atb_flo + j)) * blockDim.x + threadIdx.x;
   if (idx < (int64_t)J.M * J.N)
     atb_finish_one<real>(a.part + J.part_off, J.ks, J.M, J.N, J.out, J.ldo, J.mask, J.nW, idx);
 }
 template <typename real>
 __global__ __launch_bounds__(256) void batch_col_kernel(BatchSums<real> a) {
   const int b = blockIdx.x, j = job_of(a.col_lo, a.n_col, b);
-  const ColJob<real> J = a.col[j];
-  const int t = b - a.col_lo[j], cm = (J.M + 255) / 256;
+  const ColJob<real> J = uload(a.col + j);
+  const int t = b - uload(a.col_lo + j), cm = (J.M + 255) / 256;
   const int m = (t % cm) * 256 + threadIdx.x;
   if (m < J.M) colsum_one<real>(J.X, J.ldx, J.B, J.M, a.part + J.part_off, J.ks, m, t / cm);
 }
 template <typename real>
 __global__ __launch_bounds__(256) void batch_col_finish(BatchSums<real> a) {
   const int b = blockIdx.x, j = job_of(a.col_flo, a.n_col, b);
-  const ColJob<real> J = a.col[j];
-  const int m = (b - a.col_flo[j]) * 256 + threadIdx.x;
+  const ColJob<real> J = uload(a.col + j);
+  const int m = (b - uload(a.col_flo + j)) * 256 + threadIdx.x;
   if (m < J.M) colsum_finish_one<real>(a.part + J.part_off, J.ks, J.M, J.out, m);
 }
 
