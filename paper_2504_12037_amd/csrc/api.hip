@@ -171,7 +171,8 @@ struct tnvan_net {
   std::vector<int64_t> bkey;
   int32_t bs_counts[6] = {0, 0, 0, 0, 0, 0};
   // jobs of the batched REINFORCE rows of one-layer nets, one launch per
-  // class of LDS need (kRowClasses): jobs, first blocks, counts, LDS bytes
+  // class of LDS need (ensure_batch_sums): jobs, first blocks, counts, LDS
+  // bytes
   DBuf rw_jobs[4], rw_lo[4];
   int32_t rw_njobs[4] = {0, 0, 0, 0}, rw_blocks[4] = {0, 0, 0, 0};
   size_t rw_lds[4] = {0, 0, 0, 0};
@@ -1185,6 +1186,10 @@ tnvan_status ensure_batch_sums(tnvan_net *net, const std::vector<int64_t> &hoff,
         int c = 0;
         while (c < 3 && need > lim[c]) ++c;
         const size_t lds = rows_lds_bytes(m.n, m.H, sizeof(real), c < 3);
+        if (lds > (size_t)maxlds)
+          return set_err(TNVAN_E_INVALID, "instance %d: the REINFORCE rows of |W| = %d, H = %d "
+                         "need %zu bytes of LDS per block, above the device's %d", q, m.n, m.H,
+                         lds, maxlds);
         // samples per block: one round of 16 for small parameter sets, up
         // to four rounds per staging of the larger ones, and at most 256
         // blocks per instance

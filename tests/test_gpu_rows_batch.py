@@ -84,3 +84,15 @@ def test_rows_of_every_lds_class_against_the_oracle(prec):
         M1, M2, M0 = OM.masks(n, H)
         mask = OM.pack(M1, np.ones(H), M2, np.ones(n), M0)
         assert np.all(g_gpu[mask == 0] == 0), inst.name
+
+
+def test_rows_beyond_the_lds_limit_are_refused():
+    # FP64 rows of |W| = 700 with H = 16 need 16 x (2 x 701 + 17) x 8 bytes
+    # of LDS per block (about 182 KB), above the block limit: the step is
+    # refused before any rows launch, with the sizes in the message
+    from paper_2504_12037_amd import Net
+    from paper_2504_12037_amd._lib import TnvanError
+    net = Net([_path(700, 16, 5)], precision="fp64", seed=3)
+    print("\n[rows batch] |W| = 700 FP64, expecting a refusal", flush=True)
+    with pytest.raises(TnvanError, match="LDS"):
+        net.free_energy_step([64], 1e-3)
