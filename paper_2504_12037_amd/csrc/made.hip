@@ -353,70 +353,84 @@ constexpr int kDeepND = kDeepRows / 256;       // per-thread entries of one laye
 // Rows of the REINFORCE backward for deeper networks: per sample every
 // layer's h^l, the logits, dlogit = w ((1+s)/2 - sigmoid), and back through
 // the layers da^l = (dh^l) (1 - (h^l)^2) with dh^D = dlogit . W2m and
-// dh^{l-1} = da^l . W^l m.  Rows of rb samples per block round, in LDS.
+// dh^{l-1} = da^l . W^l m.  Rows of rb samples per block round, in LDS with
+// rows padded by one entry.  Items run sample-fastest, so the rb samples of
+// a round share each weight read; the masked sums walk the units of each
+// run of |W| - 1 (degree 1 + t for the t-th unit of a run) without a
+// per-unit test, in ascending order as every sum here.
 template <typename real>
 __global__ __launch_bounds__(256) void rows_deep_kernel(RowArgs<real> a, int rb) {
   extern __shared__ __align__(16) char smem[];
   const MadeInst mi = a.mi;
   const int n = mi.n, Hs = mi.H, H = n >= 2 ? mi.H : 0, D = H > 0 ? mi.D : 1;
   const int DH = D * Hs;
+  const int ln = n + 1, lh = DH + 1, ld = Hs + 1;
   const float *P = a.params + mi.param_off;
   const MadeView w = made_view(P, n, Hs);
-  real *ss = reinterpret_cast<real *>(smem);   // [rb][n]
-  real *hh = ss + (size_t)rb * n;               // [rb][D][H]
-  real *dl = hh + (size_t)rb * DH;              // [rb][n]
-  real *d0 = dl + (size_t)rb * n;               // [rb][H]: dh of the current layer
+  real *ss = reinterpret_cast<real *>(smem);   // [rb][n + 1]
+  real *hh = ss + (size_t)rb * ln;              // [rb][D H + 1]
+  real *dl = hh + (size_t)rb * lh;              // [rb][n + 1]
+  real *d0 = dl + (size_t)rb * ln;              // [rb][H + 1]: dh of the current layer
   const double Fq = a.stats[0];
   const double invB = 1.0 / (double)mi.B;
   const int64_t c0 = (int64_t)blockIdx.x * a.chunk;
   const int64_t c1 = (c0 + a.chunk) < mi.B ? (c0 + a.chunk) : mi.B;
   for (int64_t r0 = c0; r0 < c1; r0 += rb) {
     const int nr = (int)((c1 - r0) < rb ? (c1 - r0) : rb);
-    for (int i = threadIdx.x; i < rb * n; i += blockDim.x)
-      ss[i] = i / n < nr ? (real)a.spins[r0 * n + i] : (real)0;
+    for (int i = threadIdx.x; i < rb * n; i += blockDim.x) {
+      const int r = i / n, j = i - r * n;
+      ss[r * ln + j] = r < nr ? (real)a.spins[r0 * n + i] : (real)0;
+    }
     __syncthreads();
     // forward through the layers
     for (int i = threadIdx.x; i < rb * Hs; i += blockDim.x) {
-      const int r = i / Hs, k = i % Hs;
+      const int k = i / rb, r = i - k * rb;
       real acc = 0;
       if (k < H) {
         acc = (real)w.b1[k];
         const int m = degree(k, n);
-        for (int j = 0; j < m; ++j) acc += (real)w.W1[(int64_t)k * n + j] * ss[r * n + j];
+        for (int j = 0; j < m; ++j) acc += (real)w.W1[(int64_t)k * n + j] * ss[r * ln + j];
         acc = rtanh<real>(acc);
       }
-      hh[(size_t)r * DH + k] = acc;
+      hh[(size_t)r * lh + k] = acc;
     }
     __syncthreads();
     for (int l = 2; l <= D; ++l) {
       const float *Wl = deep_layer(P, n, Hs, l), *bl = Wl + (int64_t)Hs * Hs;
       for (int i = threadIdx.x; i < rb * Hs; i += blockDim.x) {
-        const int r = i / Hs, k2 = i % Hs;
+        const int k2 = i / rb, r = i - k2 * rb;
         real acc = 0;
         if (k2 < H) {
           acc = (real)bl[k2];
           const int m2 = degree(k2, n);
-          const real *hp = hh + (size_t)r * DH + (size_t)(l - 2) * Hs;
-          for (int k = 0; k < H; ++k)
-            if (degree(k, n) <= m2) acc += (real)Wl[(int64_t)k2 * Hs + k] * hp[k];
+          const real *hp = hh + (size_t)r * lh + (size_t)(l - 2) * Hs;
+          // units k with degree(k, n) <= m2
+          for (int base = 0; base < H; base += n - 1) {
+            const int e = m2 < H - base ? m2 : H - base;
+            for (int t = 0; t < e; ++t)
+              acc += (real)Wl[(int64_t)k2 * Hs + base + t] * hp[base + t];
+          }
           acc = rtanh<real>(acc);
         }
-        hh[(size_t)r * DH + (size_t)(l - 1) * Hs + k2] = acc;
+        hh[(size_t)r * lh + (size_t)(l - 1) * Hs + k2] = acc;
       }
       __syncthreads();
     }
     // logits and dlogit
     for (int i = threadIdx.x; i < rb * n; i += blockDim.x) {
-      const int r = i / n, ii = i % n;
-      const real *hD = hh + (size_t)r * DH + (size_t)(D - 1) * Hs;
+      const int ii = i / rb, r = i - ii * rb;
+      const real *hD = hh + (size_t)r * lh + (size_t)(D - 1) * Hs;
       real z = (real)w.b2[ii];
-      for (int k = 0; k < H; ++k)
-        if (degree(k, n) <= ii) z += (real)w.W2[(int64_t)ii * Hs + k] * hD[k];
-      for (int j = 0; j < ii; ++j) z += (real)w.W0[(int64_t)ii * n + j] * ss[r * n + j];
-      const real sv = ss[i];
+      // units k with degree(k, n) <= ii
+      for (int base = 0; base < H; base += n - 1) {
+        const int e = ii < H - base ? ii : H - base;
+        for (int t = 0; t < e; ++t) z += (real)w.W2[(int64_t)ii * Hs + base + t] * hD[base + t];
+      }
+      for (int j = 0; j < ii; ++j) z += (real)w.W0[(int64_t)ii * n + j] * ss[r * ln + j];
+      const real sv = ss[r * ln + ii];
       const real wt = r < nr ? (real)((a.f[mi.sample_off + r0 + r] - Fq) * invB) : (real)0;
       const real d = wt * (((real)1 + sv) * (real)0.5 - sigmoid<real>(z));
-      dl[i] = d;
+      dl[r * ln + ii] = d;
       if (r < nr) {
         a.dlogit[(r0 + r) * n + ii] = d;
         a.sf[(r0 + r) * n + ii] = sv;
@@ -425,22 +439,22 @@ __global__ __launch_bounds__(256) void rows_deep_kernel(RowArgs<real> a, int rb)
     __syncthreads();
     // back through the layers: dh^D from the logits, then W^l down
     for (int i = threadIdx.x; i < rb * Hs; i += blockDim.x) {
-      const int r = i / Hs, k = i % Hs;
+      const int k = i / rb, r = i - k * rb;
       real acc = 0;
       if (k < H) {
         const int m = degree(k, n);
-        for (int ii = m; ii < n; ++ii) acc += dl[r * n + ii] * (real)w.W2[(int64_t)ii * Hs + k];
+        for (int ii = m; ii < n; ++ii) acc += dl[r * ln + ii] * (real)w.W2[(int64_t)ii * Hs + k];
       }
-      d0[i] = acc;
+      d0[r * ld + k] = acc;
     }
     __syncthreads();
     for (int l = D; l >= 1; --l) {
       // da^l = dh^l (1 - h^2), written out with h^l
       for (int i = threadIdx.x; i < rb * Hs; i += blockDim.x) {
-        const int r = i / Hs, k = i % Hs;
-        const real hk = hh[(size_t)r * DH + (size_t)(l - 1) * Hs + k];
-        const real da = d0[i] * ((real)1 - hk * hk);
-        d0[i] = da;
+        const int k = i / rb, r = i - k * rb;
+        const real hk = hh[(size_t)r * lh + (size_t)(l - 1) * Hs + k];
+        const real da = d0[r * ld + k] * ((real)1 - hk * hk);
+        d0[r * ld + k] = da;
         if (r < nr) {
           a.hid[(r0 + r) * DH + (int64_t)(l - 1) * Hs + k] = hk;
           a.da[(r0 + r) * DH + (int64_t)(l - 1) * Hs + k] = da;
@@ -455,18 +469,25 @@ __global__ __launch_bounds__(256) void rows_deep_kernel(RowArgs<real> a, int rb)
       real nd[kDeepND];
       int c = 0;
       for (int i = threadIdx.x; i < rb * Hs && c < kDeepND; i += blockDim.x, ++c) {
-        const int r = i / Hs, k = i % Hs;
+        const int k = i / rb, r = i - k * rb;
         real acc = 0;
         if (k < H) {
           const int m = degree(k, n);
-          for (int k2 = 0; k2 < H; ++k2)
-            if (degree(k2, n) >= m) acc += d0[r * Hs + k2] * (real)Wl[(int64_t)k2 * Hs + k];
+          // units k2 with degree(k2, n) = 1 + t >= m: t from m - 1 in each run
+          for (int base = 0; base < H; base += n - 1) {
+            const int e = (n - 1) < H - base ? (n - 1) : H - base;
+            for (int t = m - 1; t < e; ++t)
+              acc += d0[r * ld + base + t] * (real)Wl[(int64_t)(base + t) * Hs + k];
+          }
         }
         nd[c] = acc;
       }
       __syncthreads();
       c = 0;
-      for (int i = threadIdx.x; i < rb * Hs && c < kDeepND; i += blockDim.x, ++c) d0[i] = nd[c];
+      for (int i = threadIdx.x; i < rb * Hs && c < kDeepND; i += blockDim.x, ++c) {
+        const int k = i / rb, r = i - k * rb;
+        d0[r * ld + k] = nd[c];
+      }
       __syncthreads();
     }
   }
@@ -2624,7 +2645,8 @@ hipError_t launch_rows_deep(const RowArgs<real> &a, int rb, hipStream_t st) {
   if (a.mi.B <= 0) return hipSuccess;
   if (rb < 1 || (int64_t)rb * a.mi.H > kDeepRows || a.mi.D > kDeepMaxD) return hipErrorInvalidValue;
   const int D = (a.mi.n >= 2 && a.mi.H > 0) ? a.mi.D : 1;
-  const size_t lds = sizeof(real) * (size_t)rb * (2 * a.mi.n + (size_t)D * a.mi.H + a.mi.H);
+  const size_t lds =
+      sizeof(real) * (size_t)rb * (2 * ((size_t)a.mi.n + 1) + (size_t)D * a.mi.H + a.mi.H + 2);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(rows_deep_kernel<real>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
