@@ -329,10 +329,13 @@ struct ProfScope {
 
 // Samples per tile S of the general-step kernel (a power of two <= 64).
 // Default rule: the largest S whose tile, arena included, fits the LDS
-// budget (80 KB, two workgroups per CU); below 4 the arena moves to global
-// memory and S is the largest <= 8 that fits (more, smaller workgroups hide
+// budget (80 KB, two workgroups per CU).  Below 4 samples for the adjoint,
+// or 8 for the forward pass, the arena moves to global memory, with S the
+// largest that fits up to 8 for the adjoint (more, smaller workgroups hide
 // the arena's latency better: the 64-instance batch's adjoint step took
-// 15.7 ms at 8, 19.1 ms at 16).  A requested S (tuning) is
+// 15.7 ms at 8, 19.1 ms at 16) and up to 16 (FP32) or 8 (FP64) for the
+// forward pass (its logZ took 2.4 ms at 16 in device memory against 4.8 ms
+// at 4 in LDS).  A requested S (tuning) is
 // taken with the arena in LDS when it fits the whole LDS, else in global
 // memory; false when even that does not fit.
 bool choose_tiles(tnvan_net *net, bool bwd, int req = 0) {
@@ -371,10 +374,12 @@ bool choose_tiles(tnvan_net *net, bool bwd, int req = 0) {
   } else {
     for (; S >= 1; S >>= 1)
       if (worst_of(S, false) <= budget) break;
-    if (S < 4) {
+    const int min_lds = bwd ? 4 : 8;
+    const int max_glob = bwd ? 8 : (net->rs() == 4 ? 16 : 8);
+    if (S < min_lds) {
       glob = true;
       for (S = 64; S >= 1; S >>= 1)
-        if (worst_of(S, true) <= budget && S <= 8) break;
+        if (worst_of(S, true) <= budget && S <= max_glob) break;
       if (S < 1) S = 1;
     }
   }
