@@ -246,19 +246,14 @@ hipError_t launch_rows_deep(const RowArgs<real> &a, int rb, hipStream_t st);
 template <typename real>
 hipError_t launch_rows_h0(const RowArgs<real> &a, hipStream_t st);
 
-// C[M, N] (+)= X^T Y over the batch; X [B, ldx] column offset, Y likewise.
-template <typename real>
-hipError_t launch_atb(const real *X, int ldx, const real *Y, int ldy, int64_t B,
-                      int M, int N, real *part, int ksplit, float *out,
-                      int ldo, int mask_kind, int nW, hipStream_t st);
-template <typename real>
-hipError_t launch_colsum(const real *X, int ldx, int64_t B, int M, real *part,
-                         int ksplit, float *out, hipStream_t st);
 // The batch sums of a whole REINFORCE backward, every instance and matrix in
-// one launch per kind: job j of launch_atb's arguments (part at part_off) or
-// of launch_colsum's; blo / clo: the jobs' first blocks of each kernel
-// (prefix sums, one more entry than jobs).  The same arithmetic per output
-// as the one-job launchers.
+// one launch per kind.  An AtbJob is out[M, N] = mask * X^T Y over the batch
+// (X [B, ldx] and Y [B, ldy] at their column offsets), summed in ks batch
+// slices whose partial sums sit at part + part_off, then added in slice
+// order; a ColJob is the column sums of X the same way.  Mask kinds: 0 none,
+// 1 W2, 2 W0, 3 W1, 4 the deeper layers (the autoregressive masks of Eq. 7).
+// The lo / flo arrays: the jobs' first blocks in each kernel (prefix sums,
+// one more entry than jobs).
 template <typename real>
 struct AtbJob {
   const real *X, *Y;

@@ -824,13 +824,6 @@ __device__ inline void atb_block(const real *X, int ldx, const real *Y, int ldy,
     }
 }
 
-template <typename real>
-__global__ __launch_bounds__(256) void atb_kernel(const real *X, int ldx, const real *Y,
-                                                  int ldy, int64_t B, int M, int N,
-                                                  real *part, int ksplit) {
-  atb_block<real>(X, ldx, Y, ldy, B, M, N, part, ksplit, blockIdx.x, blockIdx.y, blockIdx.z);
-}
-
 // out[m*ldo + n] = mask(m, n) * sum_ks part[ks][m][n]
 // mask kinds: 0 none, 1 W2 (n > deg(k)... (row i, col k): i+1 > deg(k)),
 //             2 W0 (col j < row i), 3 W1 (row k, col j): j+1 <= deg(k),
@@ -861,15 +854,6 @@ __device__ inline void atb_finish_one(const real *part, int ksplit, int M, int N
   out[(int64_t)m * ldo + nn] = keep ? (float)acc : 0.0f;
 }
 
-template <typename real>
-__global__ void atb_finish(const real *part, int ksplit, int M, int N, float *out,
-                           int ldo, int mask_kind, int nW) {
-  const int64_t tot = (int64_t)M * N;
-  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot;
-       idx += (int64_t)gridDim.x * blockDim.x)
-    atb_finish_one<real>(part, ksplit, M, N, out, ldo, mask_kind, nW, idx);
-}
-
 // column m of batch slice ks
 template <typename real>
 __device__ inline void colsum_one(const real *X, int ldx, int64_t B, int M, real *part,
@@ -892,14 +876,6 @@ __device__ inline void colsum_one(const real *X, int ldx, int64_t B, int M, real
 }
 
 template <typename real>
-__global__ void colsum_kernel(const real *X, int ldx, int64_t B, int M, real *part,
-                              int ksplit) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= M) return;
-  colsum_one<real>(X, ldx, B, M, part, ksplit, m, blockIdx.y);
-}
-
-template <typename real>
 __device__ inline void colsum_finish_one(const real *part, int ksplit, int M, float *out, int m) {
   // loads in batches of 8 (independent), additions in slice order
   double acc = 0;
@@ -913,13 +889,6 @@ __device__ inline void colsum_finish_one(const real *part, int ksplit, int M, fl
   }
   for (; k < ksplit; ++k) acc += (double)part[(int64_t)k * M + m];
   out[m] = (float)acc;
-}
-
-template <typename real>
-__global__ void colsum_finish(const real *part, int ksplit, int M, float *out) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= M) return;
-  colsum_finish_one<real>(part, ksplit, M, out, m);
 }
 
 template <typename real>
@@ -2665,33 +2634,6 @@ hipError_t launch_sample_deep(const SampleArgs<real> &a, int n_inst, int64_t max
   return hipGetLastError();
 }
 
-template <typename real>
-hipError_t launch_atb(const real *X, int ldx, const real *Y, int ldy, int64_t B, int M,
-                      int N, real *part, int ksplit, float *out, int ldo, int mask_kind,
-                      int nW, hipStream_t st) {
-  if (M <= 0 || N <= 0) return hipSuccess;
-  dim3 grid((M + TM - 1) / TM, (N + TN - 1) / TN, ksplit);
-  hipLaunchKernelGGL(atb_kernel<real>, grid, dim3(256), 0, st, X, ldx, Y, ldy, B, M, N,
-                     part, ksplit);
-  int64_t tot = (int64_t)M * N;
-  int blocks = (int)((tot + 255) / 256);
-  if (blocks > 2048) blocks = 2048;
-  hipLaunchKernelGGL(atb_finish<real>, dim3(blocks), dim3(256), 0, st, part, ksplit, M, N,
-                     out, ldo, mask_kind, nW);
-  return hipGetLastError();
-}
-
-template <typename real>
-hipError_t launch_colsum(const real *X, int ldx, int64_t B, int M, real *part, int ksplit,
-                         float *out, hipStream_t st) {
-  if (M <= 0) return hipSuccess;
-  dim3 grid((M + 255) / 256, ksplit);
-  hipLaunchKernelGGL(colsum_kernel<real>, grid, dim3(256), 0, st, X, ldx, B, M, part, ksplit);
-  hipLaunchKernelGGL(colsum_finish<real>, dim3((M + 255) / 256), dim3(256), 0, st, part,
-                     ksplit, M, out);
-  return hipGetLastError();
-}
-
 void batch_sum_blocks(int M, int N, int ks, int32_t *atb, int32_t *fin) {
   *atb = ((M + TM - 1) / TM) * ((N + TN - 1) / TN) * ks;
   *fin = (int32_t)(((int64_t)M * N + 255) / 256);
@@ -2780,12 +2722,8 @@ template hipError_t launch_rows_batch<double>(const RowBatch<double> &, bool, si
                                               hipStream_t);
 template hipError_t launch_rows_h0<float>(const RowArgs<float> &, hipStream_t);
 template hipError_t launch_rows_h0<double>(const RowArgs<double> &, hipStream_t);
-template hipError_t launch_atb<float>(const float *, int, const float *, int, int64_t, int, int, float *, int, float *, int, int, int, hipStream_t);
-template hipError_t launch_atb<double>(const double *, int, const double *, int, int64_t, int, int, double *, int, float *, int, int, int, hipStream_t);
-template hipError_t launch_colsum<float>(const float *, int, int64_t, int, float *, int, float *, hipStream_t);
 template hipError_t launch_batch_sums<float>(const BatchSums<float> &, hipStream_t);
 template hipError_t launch_batch_sums<double>(const BatchSums<double> &, hipStream_t);
-template hipError_t launch_colsum<double>(const double *, int, int64_t, int, double *, int, float *, hipStream_t);
 template hipError_t launch_free<float>(const FreeArgs<float> &, int, hipStream_t);
 template hipError_t launch_free<double>(const FreeArgs<double> &, int, hipStream_t);
 
