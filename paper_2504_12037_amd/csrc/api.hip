@@ -1067,7 +1067,11 @@ tnvan_status run_sample(tnvan_net *net, const float *uniforms, int8_t *spins, vo
     int64_t maxB = 0;
     for (int q = 0; q < net->n_inst; ++q) maxB = std::max(maxB, net->nkey[q]);
     ProfScope ps(net, TNVAN_KERNEL_SAMPLE, st);
-    HIPCHK(launch_sample_deep<real>(a, net->n_inst, maxB, st));
+    // small networks: 16 lanes per sample
+    bool small = true;
+    for (auto &m : net->mi)
+      if (m.n > kDeep16MaxN || m.H > kDeep16MaxH) small = false;
+    HIPCHK(launch_sample_deep<real>(a, net->n_inst, maxB, small, st));
     return TNVAN_OK;
   }
   if (net->h0) {

@@ -145,9 +145,12 @@ size_t made_stage_max();
 // Deeper networks (some instance with D > 1 hidden layers): one wave per
 // sample for every instance, a lane owning hidden units lane + 64 kk and
 // positions lane + 64 jj; the completed tanh values of each layer in LDS.
+// small (every instance |W| <= kDeep16MaxN and H <= kDeep16MaxH): 16 lanes
+// per sample instead, four samples per wave.
 constexpr int kDeepMaxN = 256, kDeepMaxH = 256, kDeepMaxD = 4;
+constexpr int kDeep16MaxN = 128, kDeep16MaxH = 64;
 template <typename real>
-hipError_t launch_sample_deep(const SampleArgs<real> &a, int n_inst, int64_t max_B,
+hipError_t launch_sample_deep(const SampleArgs<real> &a, int n_inst, int64_t max_B, bool small,
                               hipStream_t st);
 
 // Matrix-core sampler (FP32): one wave per 16 samples of one instance.

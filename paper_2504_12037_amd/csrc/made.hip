@@ -347,6 +347,112 @@ __global__ __launch_bounds__(256) void sample_deep_kernel(SampleArgs<real> a) {
   if (live && lane == 0) a.logq[mi.sample_off + b] = lq;
 }
 
+// The same sampler for small deeper networks (every instance |W| <= 128 and
+// H <= 64): 16 lanes per sample, four samples per wave and sixteen per
+// block, so that four times as many independent position chains are in
+// flight.  Lane c of a sample owns units c + 16 kk and positions c + 16 jj;
+// the logit is the 16-lane row sum.  Each sample's completed tanh values go
+// to its own slice of LDS, read by its own lanes after a wave barrier.
+constexpr int kD16KK = kDeep16MaxH / 16, kD16JJ = kDeep16MaxN / 16;
+template <typename real>
+__global__ __launch_bounds__(256) void sample_deep16_kernel(SampleArgs<real> a) {
+  __shared__ real hs[16][kDeepMaxD][kDeep16MaxH];
+  const int q = blockIdx.y, lane = threadIdx.x & 63, c = lane & 15;
+  const int slot = threadIdx.x >> 4;   // the block's sample 0..15
+  const MadeInst mi = uload(a.mi + q);
+  if ((int64_t)blockIdx.x * 16 >= mi.B) return;   // uniform over the block
+  const int64_t b = (int64_t)blockIdx.x * 16 + slot;
+  const bool live = b < mi.B;
+  const int64_t bs = live ? b : 0;
+  const int n = mi.n, H = n >= 2 ? mi.H : 0, D = H > 0 ? mi.D : 1;
+  const float *P = a.params + mi.param_off;
+  const MadeView w = made_view(P, n, mi.H);
+  const uint32_t step = a.step_ctr ? (uint32_t)a.step_ctr[q] : 0u;
+  real acc[kDeepMaxD][kD16KK], sv[kD16JJ];
+  int dg[kD16KK];
+#pragma unroll
+  for (int kk = 0; kk < kD16KK; ++kk) {
+    const int k = c + 16 * kk;
+    dg[kk] = k < H ? degree(k, n) : 0;
+#pragma unroll
+    for (int l = 0; l < kDeepMaxD; ++l) {
+      const float *bl = l == 0 ? w.b1 : deep_layer(P, n, mi.H, l + 1) + (int64_t)mi.H * mi.H;
+      acc[l][kk] = (k < H && l < D) ? (real)bl[k] : (real)0;
+    }
+  }
+#pragma unroll
+  for (int jj = 0; jj < kD16JJ; ++jj) sv[jj] = 0;
+  const float *u = a.uniforms ? a.uniforms + mi.spin_off + bs * n : nullptr;
+  int8_t *so = a.spins + mi.spin_off + bs * n;
+  uint32_t pw[4] = {0, 0, 0, 0};
+  real lq = 0;
+  for (int i = 0; i < n; ++i) {
+    // logit_i from the last layer's completed units and the earlier spins
+    real part = 0;
+#pragma unroll
+    for (int kk = 0; kk < kD16KK; ++kk) {
+      const int k = c + 16 * kk;
+      if (k < H && dg[kk] <= i) part += (real)w.W2[(int64_t)i * mi.H + k] * hs[slot][D - 1][k];
+    }
+#pragma unroll
+    for (int jj = 0; jj < kD16JJ; ++jj) {
+      const int j = c + 16 * jj;
+      if (j < i) part += (real)w.W0[(int64_t)i * n + j] * sv[jj];
+    }
+    // the sample's sum over its 16 lanes
+    if constexpr (sizeof(real) == 4) {
+      part = row16_sum(part);
+    } else {
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) part += __shfl_xor(part, off, 16);
+    }
+    const real logit = part + (real)w.b2[i];
+    float ui;
+    if (u) {
+      ui = live ? u[i] : 0.5f;
+    } else {
+      if ((i & 3) == 0) {
+        pw[0] = (uint32_t)(i >> 2); pw[1] = (uint32_t)bs; pw[2] = step; pw[3] = (uint32_t)q;
+        philox4x32_10(pw, (uint32_t)a.seed, (uint32_t)(a.seed >> 32));
+      }
+      ui = (float)(pw[i & 3] >> 8) * 5.9604644775390625e-08f;
+    }
+    const real p = sigmoid<real>(logit);
+    const real si = ((real)ui < p) ? (real)1 : (real)-1;
+    lq += log_sigmoid<real>(si * logit);
+#pragma unroll
+    for (int jj = 0; jj < kD16JJ; ++jj)
+      if (c + 16 * jj == i) sv[jj] = si;
+    if (c == 0 && live) so[i] = (int8_t)(si > 0 ? 1 : -1);
+    // layer 1: the new spin, and the units it completes
+#pragma unroll
+    for (int kk = 0; kk < kD16KK; ++kk) {
+      const int k = c + 16 * kk;
+      if (k < H && dg[kk] >= i + 1) {
+        acc[0][kk] += (real)w.W1[(int64_t)k * n + i] * si;
+        if (dg[kk] == i + 1) hs[slot][0][k] = rtanh<real>(acc[0][kk]);
+      }
+    }
+    // deeper layers: the units of degree i + 1 just completed below
+    for (int l = 1; l < D; ++l) {
+      wsync();
+      const float *Wl = deep_layer(P, n, mi.H, l + 1);
+#pragma unroll
+      for (int kk = 0; kk < kD16KK; ++kk) {
+        const int k2 = c + 16 * kk;
+        if (k2 < H && dg[kk] >= i + 1) {
+          if (i + 1 <= n - 1)
+            for (int k = i; k < H; k += n - 1)
+              acc[l][kk] += (real)Wl[(int64_t)k2 * mi.H + k] * hs[slot][l - 1][k];
+          if (dg[kk] == i + 1) hs[slot][l][k2] = rtanh<real>(acc[l][kk]);
+        }
+      }
+    }
+    wsync();
+  }
+  if (live && c == 0) a.logq[mi.sample_off + b] = lq;
+}
+
 constexpr int kDeepRows = 4096;                // rb H of one block round
 constexpr int kDeepND = kDeepRows / 256;       // per-thread entries of one layer's dh
 
@@ -2625,9 +2731,16 @@ hipError_t launch_rows_deep(const RowArgs<real> &a, int rb, hipStream_t st) {
 }
 
 template <typename real>
-hipError_t launch_sample_deep(const SampleArgs<real> &a, int n_inst, int64_t max_B,
+hipError_t launch_sample_deep(const SampleArgs<real> &a, int n_inst, int64_t max_B, bool small,
                               hipStream_t st) {
   if (n_inst <= 0 || max_B <= 0) return hipSuccess;
+  if (small) {
+    const int64_t bx = (max_B + 15) / 16;
+    if (bx > 0x7fffffff || n_inst > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(sample_deep16_kernel<real>, dim3((unsigned)bx, n_inst), dim3(256), 0, st,
+                       a);
+    return hipGetLastError();
+  }
   const int64_t bx = (max_B + 3) / 4;
   if (bx > 0x7fffffff || n_inst > 65535) return hipErrorInvalidValue;
   hipLaunchKernelGGL(sample_deep_kernel<real>, dim3((unsigned)bx, n_inst), dim3(256), 0, st, a);
@@ -2710,8 +2823,10 @@ hipError_t launch_obs_w(const ObsArgs &a, int n_inst, hipStream_t st) {
 
 template hipError_t launch_sample<float>(const SampleArgs<float> &, int, size_t, hipStream_t);
 template hipError_t launch_sample<double>(const SampleArgs<double> &, int, size_t, hipStream_t);
-template hipError_t launch_sample_deep<float>(const SampleArgs<float> &, int, int64_t, hipStream_t);
-template hipError_t launch_sample_deep<double>(const SampleArgs<double> &, int, int64_t, hipStream_t);
+template hipError_t launch_sample_deep<float>(const SampleArgs<float> &, int, int64_t, bool,
+                                              hipStream_t);
+template hipError_t launch_sample_deep<double>(const SampleArgs<double> &, int, int64_t, bool,
+                                               hipStream_t);
 template hipError_t launch_rows_deep<float>(const RowArgs<float> &, int, hipStream_t);
 template hipError_t launch_rows_deep<double>(const RowArgs<double> &, int, hipStream_t);
 template hipError_t launch_sample_h0<float>(const SampleArgs<float> &, int, int64_t, int, hipStream_t);

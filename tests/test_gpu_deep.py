@@ -78,9 +78,20 @@ def test_parameter_count_and_refusals():
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_deep_sampler_parity_given_uniforms(prec):
-    insts = _mixed()
-    Bs = [301, 257, 64, 130]
-    print(f"\n[deep sample] prec={prec}", flush=True)
+    # every instance |W| <= 128 and H <= 64: 16 lanes per sample
+    _sampler_parity(_mixed(), [301, 257, 64, 130], prec)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_deep_sampler_parity_one_wave_per_sample(prec):
+    # an instance with H above 64: a wave per sample for the whole net
+    insts = [_deep(S.lattice_column_split(S.lattice_2d(8, seed=1), [5]), 80, 2),
+             _deep(S.c1_small_lattice(), 16, 3)]
+    _sampler_parity(insts, [129, 64], prec)
+
+
+def _sampler_parity(insts, Bs, prec):
+    print(f"\n[deep sample] prec={prec} H={[i.hidden for i in insts]}", flush=True)
     net = _net(insts, prec)
     thetas, us = [], []
     for k, inst in enumerate(insts):
@@ -104,9 +115,11 @@ def test_deep_sampler_parity_given_uniforms(prec):
         lo += Bs[k]
 
 
-def test_deep_sampler_philox_stream():
-    inst = _deep(S.lattice_column_split(S.lattice_2d(8, seed=1), [5]), 24, 3)
-    n, H, D, B = inst.n_width, 24, 3, 500
+@pytest.mark.parametrize("H", [24, 80])
+def test_deep_sampler_philox_stream(H):
+    # H = 24: 16 lanes per sample; H = 80: a wave per sample
+    inst = _deep(S.lattice_column_split(S.lattice_2d(8, seed=1), [5]), H, 3)
+    n, D, B = inst.n_width, 3, 500
     theta = _theta(n, H, D, 4, 0.3)
     net = _net([inst], "fp32", seed=0x1234_5678_9ABC)
     net.set_params(0, torch.from_numpy(theta))
